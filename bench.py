@@ -1,0 +1,181 @@
+"""Benchmark of the (P|ab) hot path on one MI355X.
+
+Workload (one step): the per-class batches -- 1e5 shell triplets for each
+class (L_P, l_a, l_b) in {(0,0,0), (2,1,1), (4,2,2), (6,3,3), (6,4,4)} and each
+contraction degree K_a = K_b in {1, 3, 6} (K_P = 1), fresh centres per
+triplet in a 20 bohr cube, exponents log-uniform in [0.05, 100], raw blocks
+written to HBM.  value = contracted output integrals per second over the whole
+step, inputs resident in HBM.  Also reported: per-batch integrals/s and the
+DF-J wall time of the 8-atom and 120-atom systems.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "3-center integrals/s (FP64) per L class; DF-J and J-gradient ms vs plain"
+PEAK_FP64 = 78.6e12       # FLOP/s: 256 CUs x 2.4 GHz x 128 FP64 FLOP/clk/CU
+PEAK_HBM = 8.0e12         # B/s
+# algorithmic FP64 FLOP per triplet of the per-class batches (operation-count
+# model of the HGPA scheme: Boys, VRR1, contraction, CVRR2, transform, HRR)
+MODEL_FLOP = {
+    ((0, 0, 0), 1): 66, ((0, 0, 0), 3): 562, ((0, 0, 0), 6): 2236,
+    ((2, 1, 1), 1): 756, ((2, 1, 1), 3): 3400, ((2, 1, 1), 6): 12300,
+    ((4, 2, 2), 1): 8400, ((4, 2, 2), 3): 25000, ((4, 2, 2), 6): 82000,
+    ((6, 3, 3), 1): 53000, ((6, 3, 3), 3): 131000, ((6, 3, 3), 6): 393000,
+    ((6, 4, 4), 1): 131000, ((6, 4, 4), 3): 298000, ((6, 4, 4), 6): 863000,
+}
+
+
+def parse():
+    p = argparse.ArgumentParser()
+    p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--steps", type=int, default=3)
+    p.add_argument("--warmup", type=int, default=1)
+    p.add_argument("--ntrip", type=int, default=100000)
+    p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--no-dfj", action="store_true")
+    return p.parse_args()
+
+
+def cpu_baseline(batches, budget_s=20.0):
+    """The oracle on a bounded sample of every batch (same triplets), scaled to
+    integrals/s of the whole per-class workload."""
+    import oracle
+    nthreads = os.cpu_count() or 1
+    total_t, total_int = 0.0, 0
+    per = budget_s / len(batches)
+    desc = []
+    for (cls, K), cb in batches.items():
+        n = 8
+        while True:
+            t0 = time.perf_counter()
+            oracle.eval_batch(cb.xyz, cb.aux, cb.orb, cb.trip[:n], nthreads=nthreads)
+            dt = time.perf_counter() - t0
+            if dt > per / 4 or n >= 4096:
+                break
+            n *= 4
+        # time per integral of this batch, weighted by its share of the workload
+        total_t += dt / (n * cb.block) * cb.nint
+        total_int += cb.nint
+        desc.append(f"{cls}K{K}:{n}")
+    return {"value": total_int / total_t, "unit": "integrals/s", "cores": nthreads,
+            "kind": "oracle",
+            "sample": "first n triplets of each of the 15 per-class batches (" + ", ".join(desc) +
+                      "), time scaled to 1e5 triplets per batch"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (asked for {args.gpus}); the per-GPU share of a "
+              "sharded run is the single-GPU workload", file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    from paper_2210_03192_amd import df3c, inputs
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    df3c.init()
+
+    batches, gpu = {}, {}
+    maxout = 0
+    for cls in inputs.PER_CLASS_CLASSES:
+        for K in inputs.PER_CLASS_K:
+            cb = inputs.class_batch(*cls, K, args.ntrip)
+            batches[(cls, K)] = cb
+            gpu[(cls, K)] = dict(
+                xyz=torch.as_tensor(cb.xyz, device=dev),
+                aux=df3c.DeviceBasis.from_basis(cb.aux, dev),
+                orb=df3c.DeviceBasis.from_basis(cb.orb, dev),
+                trip=torch.as_tensor(cb.trip, device=dev),
+                off=torch.as_tensor(cb.out_off, device=dev))
+            maxout = max(maxout, cb.nint)
+    out = torch.empty(maxout, dtype=torch.float64, device=dev)
+    ws = torch.empty(df3c.eval_batch_workspace(args.ntrip), dtype=torch.uint8, device=dev)
+    stream = torch.cuda.current_stream()
+
+    def step(times=None):
+        for key, g in gpu.items():
+            if times is not None:
+                e0 = torch.cuda.Event(enable_timing=True)
+                e1 = torch.cuda.Event(enable_timing=True)
+                e0.record(stream)
+            df3c.eval_batch(g["xyz"], g["aux"], g["orb"], g["trip"], g["off"], out, ws=ws,
+                            stream=stream)
+            if times is not None:
+                e1.record(stream)
+                times.setdefault(key, []).append((e0, e1))
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    times = {}
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step(times)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_step = wall / args.steps * 1e3
+    nint = sum(cb.nint for cb in batches.values())
+    per_class = {}
+    dom_key, dom_ms = None, 0.0
+    for key, ev in times.items():
+        ms = float(np.mean([a.elapsed_time(b) for a, b in ev]))
+        cb = batches[key]
+        per_class[f"P{key[0][0]}a{key[0][1]}b{key[0][2]}_K{key[1]}"] = {
+            "ms": ms, "integrals_per_s": cb.nint / (ms * 1e-3),
+            "model_tflops": MODEL_FLOP[key] * cb.ntrip / (ms * 1e-3) / 1e12}
+        if ms > dom_ms:
+            dom_key, dom_ms = key, ms
+    cbd = batches[dom_key]
+    flop = MODEL_FLOP[dom_key] * cbd.ntrip
+    ach = flop / (dom_ms * 1e-3)
+    roof = {"bound": "alu", "achieved": ach / 1e12, "peak": PEAK_FP64 / 1e12, "unit": "TFLOP/s",
+            "frac": ach / PEAK_FP64, "traffic": None,
+            "kernel": f"k_store<{dom_key[0][0]},{dom_key[0][1]},{dom_key[0][2]}> K={dom_key[1]}",
+            "hbm_write_GBps": cbd.nint * 8 / (dom_ms * 1e-3) / 1e9}
+
+    extra = {}
+    if not args.no_dfj:
+        for name, sysf in (("plain_8atoms", inputs.plain_dfj_system),
+                           ("water_120atoms", inputs.dfj_120_system)):
+            s = sysf()
+            d = torch.as_tensor(inputs.fitting_coefficients(s.aux.nbf, 1), device=dev)
+            xyz = torch.as_tensor(s.xyz, device=dev)
+            aux = df3c.DeviceBasis.from_basis(s.aux, dev)
+            orb = df3c.DeviceBasis.from_basis(s.orb, dev)
+            J = torch.empty((s.orb.nbf, s.orb.nbf), dtype=torch.float64, device=dev)
+            wsj = torch.empty(df3c.coulomb_J_workspace(aux, orb), dtype=torch.uint8, device=dev)
+            df3c.coulomb_J(xyz, aux, orb, d, J=J, ws=wsj)
+            torch.cuda.synchronize()
+            reps = 3
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                df3c.coulomb_J(xyz, aux, orb, d, J=J, ws=wsj)
+            torch.cuda.synchronize()
+            extra[f"dfj_ms_{name}"] = (time.perf_counter() - t0) / reps * 1e3
+
+    rec = {"metric": METRIC, "value": nint / (ms_step * 1e-3), "unit": "integrals/s",
+           "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_step,
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+           "data": "synthetic",
+           "config": {"workload": "per-class batches: 1e5 triplets x (L_P,l_a,l_b) in "
+                                  "{(0,0,0),(2,1,1),(4,2,2),(6,3,3),(6,4,4)} x K_a=K_b in {1,3,6}",
+                      "ntrip_per_batch": args.ntrip, "integrals_per_step": nint},
+           "roofline": roof, "per_class": per_class, **extra}
+    if not args.no_cpu_baseline:
+        rec["cpu_baseline"] = cpu_baseline(batches)
+    print(json.dumps(rec), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,115 @@
+/*
+ * df3c.h -- C ABI of libdf3c: 3-center 2-electron Coulomb integrals (P|ab) and
+ * the density-fitted Coulomb matrix on AMD MI355X (gfx950), FP64 throughout.
+ *
+ * The operations are those of Asadchev & Valeev, "Memory-Efficient Recursive
+ * Evaluation of 3-Center Gaussian Integrals":
+ *   - integrals over contracted Gaussian shells (Appendix "Notation"): orbital
+ *     shells a, b are Cartesian, the auxiliary (ket) shell P is a real
+ *     solid-harmonic shell (Section 2.2, first design assumption);
+ *   - evaluated by the HGPA scheme of Section 2.5.1: Boys function (2.5.2),
+ *     2-quantal VRR1 (2.5.3), early-contracted n-quantal CVRR2 (2.5.4), ket
+ *     transform, n-quantal HRR (2.5.5);
+ *   - digested into J_ab = sum_P (ab|P) d_P, the DF-J build of Sections 3 and 4
+ *     (Table "dfj"), and its nuclear gradient.
+ *
+ * Conventions
+ *   - Units: bohr, atomic units.  All arithmetic is IEEE FP64.
+ *   - Cartesian order inside a shell of l quanta: for i = 0..l, for j = 0..i:
+ *     (l-i, i-j, j), i.e. xx, xy, xz, yy, yz, zz.
+ *   - Solid harmonics ordered m = -l..+l, leading monomial positive, scaled so
+ *     that a solid-harmonic member of a contracted shell has unit norm when the
+ *     shell's x^l Cartesian member has unit norm.
+ *   - Contraction coefficients passed in already include all normalisation.
+ *   - A block (P|ab) is stored row-major [p][i][j] (P slowest, b fastest).
+ *   - AO order: shell order, then component order; aux functions likewise.
+ *
+ * Memory: every pointer marked DEVICE must point to device memory of the
+ * current HIP device; HOST pointers to host memory.  The caller owns every
+ * buffer, including the workspace; the library never allocates device memory
+ * in these entry points (it keeps one read-only Boys table per device, set up
+ * by df3c_init).  All device work is enqueued on `stream`.
+ *
+ * Errors: every function returns DF3C_OK (0) or a negative status; no C++
+ * exception crosses the ABI.  After an error the outputs are unspecified.
+ * Arguments are validated on the host before any device work is enqueued.
+ */
+#ifndef DF3C_H
+#define DF3C_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define DF3C_OK 0
+#define DF3C_E_ARG (-1)          /* null pointer, bad size, index out of range */
+#define DF3C_E_UNSUPPORTED (-2)  /* angular momentum or option beyond the build */
+#define DF3C_E_WORKSPACE (-3)    /* workspace missing or too small */
+#define DF3C_E_HIP (-4)          /* a HIP runtime call failed */
+
+/* Limits of this build. */
+#define DF3C_LMAX_ORB 4  /* orbital shells: s..g */
+#define DF3C_LMAX_AUX 6  /* auxiliary shells: s..i */
+
+/* flags */
+#define DF3C_FLAG_NONE 0u
+
+/* A basis: nshell shells.  l_host is a HOST array; the other arrays are DEVICE
+ * arrays.  exps/coefs are indexed by prim_off[s] .. prim_off[s] + nprim[s]-1. */
+typedef struct {
+  int32_t nshell;
+  const int32_t *l_host;   /* HOST   [nshell] angular momentum */
+  const int32_t *l;        /* DEVICE [nshell] angular momentum (same values) */
+  const int32_t *nprim;    /* DEVICE [nshell] contraction degree K >= 1 */
+  const int64_t *prim_off; /* DEVICE [nshell] offset into exps / coefs */
+  const int32_t *atom;     /* DEVICE [nshell] index of the shell's centre in xyz */
+  const double *exps;      /* DEVICE primitive exponents (> 0) */
+  const double *coefs;     /* DEVICE contraction coefficients (normalised) */
+  int32_t pure;            /* aux: 1 solid-harmonic (0 allowed only for l <= 1);
+                              orbital: must be 0 (Cartesian) */
+} df3c_shells;
+
+/* Load-time set-up for the current device (Boys table upload).  Called
+ * implicitly by the entry points; call it explicitly before capturing a HIP
+ * graph.  Returns DF3C_E_HIP on failure. */
+int df3c_init(void);
+
+/* Bytes of workspace df3c_eval_batch needs for ntrip triplets. */
+size_t df3c_eval_batch_workspace(int64_t ntrip);
+
+/* (P|ab) blocks for a batch of shell triplets (Section 2.5.1; the batch may mix
+ * classes and is unordered, Section 3).
+ *   xyz      DEVICE [natom][3] centres
+ *   aux, orb bases of P and of a, b (orb->pure must be 0)
+ *   trip     DEVICE [ntrip][3] = (P, a, b) shell indices
+ *   out_off  DEVICE [ntrip] offset (in doubles) of each block in out
+ *   out      DEVICE output; block t is npure(l_P) x ncart(l_a) x ncart(l_b)
+ *            (ncart(l_P) for a Cartesian aux basis) at out + out_off[t]
+ *   ws       DEVICE workspace of at least df3c_eval_batch_workspace(ntrip) bytes
+ * Shell indices in trip are checked on the device; the call synchronises
+ * `stream` once to plan the per-class launches. */
+int df3c_eval_batch(const double *xyz, const df3c_shells *aux, const df3c_shells *orb,
+                    int64_t ntrip, const int32_t *trip, const int64_t *out_off, double *out,
+                    void *ws, size_t ws_bytes, uint32_t flags, void *stream);
+
+/* Bytes of workspace df3c_coulomb_J needs. */
+size_t df3c_coulomb_J_workspace(const df3c_shells *aux, const df3c_shells *orb);
+
+/* J_ab = sum_P (ab|P) d_P over all orbital shell pairs (DF-J, Section 3).
+ *   d   DEVICE [naux] fitting coefficients, aux function order
+ *   J   DEVICE [nao][nao] output, overwritten, both triangles written
+ *   ws  DEVICE workspace of at least df3c_coulomb_J_workspace bytes */
+int df3c_coulomb_J(const double *xyz, const df3c_shells *aux, const df3c_shells *orb,
+                   const double *d, double *J, void *ws, size_t ws_bytes, uint32_t flags,
+                   void *stream);
+
+/* Readable name of a status code (static string). */
+const char *df3c_status_string(int status);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

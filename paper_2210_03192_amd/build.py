@@ -1,0 +1,65 @@
+"""Build libdf3c.so (HIP for gfx950) in-tree.
+
+Steps: generate the index tables (csrc/gen_tables.py), compile every .hip
+translation unit with hipcc for gfx950 in parallel, link a shared library next
+to this file.
+"""
+import concurrent.futures as cf
+import os
+import subprocess
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+CSRC = os.path.join(HERE, "csrc")
+OBJ = os.path.join(HERE, "_build")
+LIB = os.path.join(HERE, "libdf3c.so")
+ARCH = "gfx950"
+
+HIPCC_FLAGS = [
+    "-O3", f"--offload-arch={ARCH}", "-std=c++20", "-fPIC",
+    # no packed FP32 instructions in the device code
+    "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    "-Wno-unused-command-line-argument",
+]
+
+
+def _sources():
+    return sorted(f for f in os.listdir(CSRC) if f.endswith(".hip"))
+
+
+def _compile(src, verbose):
+    obj = os.path.join(OBJ, src.replace(".hip", ".o"))
+    cmd = ["hipcc", *HIPCC_FLAGS, "-I", CSRC, "-c", os.path.join(CSRC, src), "-o", obj]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    msgs = "\n".join(l for l in (r.stdout + r.stderr).splitlines()
+                     if "packed-fp32-ops" not in l and l.strip())
+    if r.returncode != 0:
+        raise RuntimeError(f"hipcc failed for {src}:\n{msgs}")
+    return obj, msgs
+
+
+def build(verbose: bool = False, jobs: int = 0) -> str:
+    subprocess.run([sys.executable, os.path.join(CSRC, "gen_tables.py"),
+                    os.path.join(CSRC, "gen")], check=True)
+    os.makedirs(OBJ, exist_ok=True)
+    srcs = _sources()
+    jobs = jobs or min(len(srcs), max(1, (os.cpu_count() or 4)))
+    objs = []
+    with cf.ThreadPoolExecutor(jobs) as ex:
+        for obj, msgs in ex.map(lambda s: _compile(s, verbose), srcs):
+            objs.append(obj)
+            if msgs and verbose:
+                print(msgs, flush=True)
+    tmp = LIB + ".tmp"
+    cmd = ["hipcc", f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.run(cmd, check=True)
+    os.replace(tmp, LIB)
+    return LIB
+
+
+if __name__ == "__main__":
+    build(verbose=True)

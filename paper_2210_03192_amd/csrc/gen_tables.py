@@ -1,0 +1,326 @@
+"""Generate the index tables of the gfx950 kernels as C++ headers.
+
+Section 3 of the paper builds its kernels from compile-time metadata (orbital
+lists, recurrence index maps).  Evaluating the larger maps in the C++ constant
+evaluator is slow, so this script computes them once at build time and writes
+them as literal arrays (gen/tables_lp<L>.hpp, gen/tables_common.hpp).
+
+Conventions (must match tables.hpp):
+  * Cartesian order inside a shell of l quanta: for i = 0..l, for j = 0..i:
+    (l-i, i-j, j);  offT(j) = number of Cartesians of all levels below j.
+  * A geometry (LP, EA, EB) computes (e0|P) for e in levels EA..EB.
+    pi_k(e', n): k = 0..LP, n of level LP-k, e' of levels emin(k)..emax(k) with
+    emin(k) = max(0, EA-k), emax(k) = EB-k; entry r = pi_off(k) + idx(n) nek(k)
+    + (offT(|e'|) - offT(emin(k))) + idx(e').
+  * n-q CVRR2 (Eq. cVRR2 applied |c| times):
+        (e0|c) = sum_{u <= min(e,c)} prod_i C(c_i,u_i) e_i!/(e_i-u_i)! pi_{|u|}(e-u, c-u)
+  * real solid harmonics: Re/Im (x+iy)^|m| times the associated-Legendre
+    polynomial in (z, r^2) from (l-m) P_{l,m} = (2l-1) z P_{l-1,m}
+    - (l+m-1) r^2 P_{l-2,m}, P_{m,m} = 1; rows m = -l..l scaled to unit norm
+    under the Cartesian overlap of a shell whose x^l member has unit norm.
+  * n-q HRR: (a b|P) = sum_{i <= b} prod_x C(b_x,i_x) AB_x^{b_x-i_x} (a+i 0|P).
+"""
+import math
+import os
+import sys
+from fractions import Fraction
+
+LMAX_AUX = 6
+LMAX_ORB = 4
+
+
+def ncart(l):
+    return (l + 1) * (l + 2) // 2 if l >= 0 else 0
+
+
+def offT(j):
+    return j * (j + 1) * (j + 2) // 6 if j > 0 else 0
+
+
+def carts(l):
+    return [(l - i, i - j, j) for i in range(l + 1) for j in range(i + 1)]
+
+
+def cidx(q):
+    i = q[1] + q[2]
+    return i * (i + 1) // 2 + q[2]
+
+
+def rdir(e):
+    return 0 if e[0] > 0 else (1 if e[1] > 0 else 2)
+
+
+# ----------------------------------------------------------------- geometry
+class Geo:
+    def __init__(self, LP, EA, EB):
+        self.LP, self.EA, self.EB = LP, EA, EB
+
+    def emin(self, k):
+        return max(0, self.EA - k)
+
+    def emax(self, k):
+        return self.EB - k
+
+    def nek(self, k):
+        return offT(self.emax(k) + 1) - offT(self.emin(k)) if self.emax(k) >= self.emin(k) else 0
+
+    def pi_off(self, k):
+        return sum(ncart(self.LP - q) * self.nek(q) for q in range(k))
+
+    def sw_off(self, k):
+        return sum(ncart(self.LP - q) for q in range(k))
+
+    @property
+    def NPI(self):
+        return self.pi_off(self.LP + 1)
+
+    def pi_index(self, k, ep, n):
+        return (self.pi_off(k) + cidx(n) * self.nek(k) + offT(sum(ep)) - offT(self.emin(k))
+                + cidx(ep))
+
+
+def pimap(g):
+    sw, v = [], []
+    for k in range(g.LP + 1):
+        for n in range(ncart(g.LP - k)):
+            for e in range(g.nek(k)):
+                sw.append(g.sw_off(k) + n)
+                v.append(offT(g.emin(k)) + e)
+    assert len(sw) == g.NPI
+    return sw, v
+
+
+def combine(g):
+    start, pi, w = [], [], []
+    for e in range(g.EA, g.EB + 1):
+        for E in carts(e):
+            for C in carts(g.LP):
+                start.append(len(pi))
+                for ux in range(min(E[0], C[0]) + 1):
+                    for uy in range(min(E[1], C[1]) + 1):
+                        for uz in range(min(E[2], C[2]) + 1):
+                            u = (ux, uy, uz)
+                            wt = 1
+                            for i in range(3):
+                                wt *= math.comb(C[i], u[i]) * math.perm(E[i], u[i])
+                            ep = tuple(E[i] - u[i] for i in range(3))
+                            nn = tuple(C[i] - u[i] for i in range(3))
+                            pi.append(g.pi_index(sum(u), ep, nn))
+                            w.append(wt)
+    start.append(len(pi))
+    assert max(w) < 2**31
+    return start, pi, w
+
+
+# ----------------------------------------------------------- solid harmonics
+def pmul(p, q):
+    r = {}
+    for a, x in p.items():
+        for b, y in q.items():
+            k = (a[0] + b[0], a[1] + b[1], a[2] + b[2])
+            r[k] = r.get(k, 0) + x * y
+    return {k: v for k, v in r.items() if v != 0}
+
+
+def padd(p, s, q, t):
+    r = {}
+    for k, v in p.items():
+        r[k] = r.get(k, 0) + s * v
+    for k, v in q.items():
+        r[k] = r.get(k, 0) + t * v
+    return {k: v for k, v in r.items() if v != 0}
+
+
+def dfact(n):
+    r = 1
+    while n > 1:
+        r *= n
+        n -= 2
+    return r
+
+
+def solid(l):
+    one, X, Y, Z = {(0, 0, 0): 1}, {(1, 0, 0): 1}, {(0, 1, 0): 1}, {(0, 0, 1): 1}
+    R2 = {(2, 0, 0): 1, (0, 2, 0): 1, (0, 0, 2): 1}
+    rows = {}
+    for am in range(l + 1):
+        A, B = one, {}
+        for _ in range(am):
+            A, B = padd(pmul(X, A), 1, pmul(Y, B), -1), padd(pmul(Y, A), 1, pmul(X, B), 1)
+        pm2, pm1 = {}, one
+        for ll in range(am + 1, l + 1):
+            nx = padd(pmul(Z, pm1), Fraction(2 * ll - 1, ll - am), pmul(R2, pm2),
+                      -Fraction(ll + am - 1, ll - am))
+            pm2, pm1 = pm1, nx
+        for sgn in (1, -1):
+            if am == 0 and sgn < 0:
+                continue
+            S = pmul(pm1, A if sgn > 0 else B)
+            row = [Fraction(S.get(q, 0)) for q in carts(l)]
+            nrm = Fraction(0)
+            qs = carts(l)
+            for i, a in enumerate(qs):
+                for j, b in enumerate(qs):
+                    s = [a[t] + b[t] for t in range(3)]
+                    if any(v % 2 for v in s):
+                        continue
+                    ov = Fraction(dfact(s[0] - 1) * dfact(s[1] - 1) * dfact(s[2] - 1), dfact(2 * l - 1))
+                    nrm += row[i] * row[j] * ov
+            f = 1.0 / math.sqrt(nrm)
+            rows[sgn * am] = [float(v) * f if v != 0 else 0.0 for v in row]
+    return [rows[m] for m in range(-l, l + 1)]
+
+
+# ----------------------------------------------------------------------- HRR
+def hrr(LA, LB):
+    hc_start, hc_pow, hc_binom = [], [], []
+    n = 0
+    for q in carts(LB):
+        hc_start.append(n)
+        for ix in range(q[0] + 1):
+            for iy in range(q[1] + 1):
+                for iz in range(q[2] + 1):
+                    hc_pow += [q[0] - ix, q[1] - iy, q[2] - iz, 0]
+                    hc_binom.append(math.comb(q[0], ix) * math.comb(q[1], iy) * math.comb(q[2], iz))
+                    n += 1
+    hc_start.append(n)
+    e = []
+    for A in carts(LA):
+        for q in carts(LB):
+            for ix in range(q[0] + 1):
+                for iy in range(q[1] + 1):
+                    for iz in range(q[2] + 1):
+                        E = (A[0] + ix, A[1] + iy, A[2] + iz)
+                        e.append(offT(sum(E)) - offT(LA) + cidx(E))
+    return hc_start, hc_pow, hc_binom, e
+
+
+# ---------------------------------------------------------------------- VRR1
+def vstages(L):
+    if L == 0:
+        return []
+    if L % 2:
+        return [(1, False)] + [(1 + 2 * s, True) for s in range(1, (L - 1) // 2 + 1)]
+    return [(2 + 2 * s, True) for s in range(L // 2)]
+
+
+def vtab(L):
+    items = []
+
+    def one_q(o, c, m):
+        e = carts(o)[c]
+        i = rdir(e)
+        e1 = list(e)
+        e1[i] -= 1
+        e2 = list(e)
+        e2[i] -= 2
+        return (0, c, m, i, 0, cidx(e1), cidx(e2) if e[i] >= 2 else -1, e[i] - 1, -1, 0)
+
+    for j, twoq in vstages(L):
+        if twoq:
+            for c in range(ncart(j - 1)):
+                for m in range(L - j + 2):
+                    items.append(one_q(j - 1, c, m))
+            for c in range(ncart(j)):
+                for m in range(L - j + 1):
+                    e = carts(j)[c]
+                    i = rdir(e)
+                    x = list(e)
+                    x[i] -= 1
+                    ip = rdir(x)
+                    x1, x2, y = list(x), list(x), list(e)
+                    x1[ip] -= 1
+                    x2[ip] -= 2
+                    y[i] -= 2
+                    items.append((1, c, m, i, ip, cidx(x1), cidx(x2) if x[ip] >= 2 else -1,
+                                  x[ip] - 1, cidx(y) if e[i] >= 2 else -1, e[i] - 1))
+        else:
+            for c in range(ncart(j)):
+                for m in range(L - j + 1):
+                    items.append(one_q(j, c, m))
+    return items
+
+
+# -------------------------------------------------------------------- output
+def arr(ctype, name, vals):
+    if not vals:
+        vals = [0]
+    body = ",".join(str(v) for v in vals)
+    return f"  static constexpr {ctype} {name}[{len(vals)}] = {{{body}}};\n"
+
+
+def geometries():
+    """(LP, EA, EB) of every class: plain (EA = la, EB = la + lb)."""
+    out = set()
+    for LP in range(LMAX_AUX + 1):
+        for la in range(LMAX_ORB + 1):
+            for lb in range(la + 1):
+                out.add((LP, la, la + lb))
+    return sorted(out)
+
+
+def write(outdir):
+    os.makedirs(outdir, exist_ok=True)
+    geos = geometries()
+    for LP in range(LMAX_AUX + 1):
+        s = ["// generated by gen_tables.py -- do not edit\n#pragma once\n#include <cstdint>\n",
+             "namespace df3c {\n"]
+        for (lp, EA, EB) in geos:
+            if lp != LP:
+                continue
+            g = Geo(LP, EA, EB)
+            sw, v = pimap(g)
+            st, pi, w = combine(g)
+            s.append(f"template <> struct GenTab<{LP}, {EA}, {EB}> {{\n")
+            s.append(f"  static constexpr int NPI = {g.NPI};\n")
+            s.append(f"  static constexpr int NTGT = {len(st) - 1};\n")
+            s.append(arr("int16_t", "pi_sw", sw))
+            s.append(arr("int16_t", "pi_v", v))
+            s.append(arr("int32_t", "cb_start", st))
+            s.append(arr("int16_t", "cb_pi", pi))
+            s.append(arr("int32_t", "cb_w", w))
+            s.append("};\n")
+        s.append("}  // namespace df3c\n")
+        with open(os.path.join(outdir, f"tables_lp{LP}.hpp"), "w") as f:
+            f.write("".join(s))
+    s = ["// generated by gen_tables.py -- do not edit\n#pragma once\n#include <cstdint>\n",
+         "namespace df3c {\n"]
+    for l in range(LMAX_AUX + 1):
+        rows = solid(l)
+        start, col, val = [], [], []
+        for r in rows:
+            start.append(len(col))
+            for c, x in enumerate(r):
+                if x != 0.0:
+                    col.append(c)
+                    val.append(repr(x))
+        start.append(len(col))
+        s.append(f"template <> struct GenSolid<{l}> {{\n")
+        s.append(arr("int16_t", "start", start))
+        s.append(arr("int16_t", "col", col))
+        s.append(arr("double", "val", val))
+        s.append(arr("double", "dense", [repr(x) for r in rows for x in r]))
+        s.append("};\n")
+    for la in range(LMAX_ORB + 1):
+        for lb in range(LMAX_ORB + 1):
+            hs, hp, hb, e = hrr(la, lb)
+            s.append(f"template <> struct GenHrr<{la}, {lb}> {{\n")
+            s.append(f"  static constexpr int NHC = {hs[-1]};\n")
+            s.append(arr("int16_t", "hc_start", hs))
+            s.append(arr("int8_t", "hc_pow", hp))
+            s.append(arr("int16_t", "hc_binom", hb))
+            s.append(arr("int16_t", "e", e))
+            s.append("};\n")
+    for L in range(2 * LMAX_ORB + 2):
+        items = vtab(L)
+        s.append(f"template <> struct GenV<{L}> {{\n")
+        s.append(f"  static constexpr int N = {len(items)};\n")
+        s.append(arr("VI", "it", ["{" + ",".join(str(x) for x in t) + "}" for t in items]))
+        s.append("};\n")
+    s.append("}  // namespace df3c\n")
+    with open(os.path.join(outdir, "tables_common.hpp"), "w") as f:
+        f.write("".join(s))
+
+
+if __name__ == "__main__":
+    write(sys.argv[1] if len(sys.argv) > 1 else os.path.join(os.path.dirname(__file__), "gen"))

@@ -1,0 +1,4 @@
+// Kernels of all classes with an auxiliary shell of l = 2 (one translation
+// unit per l so the build parallelises).
+#include "registry.hpp"
+DF3C_REGISTER_LP(2, register_lp2)

@@ -1,0 +1,4 @@
+// Kernels of all classes with an auxiliary shell of l = 3 (one translation
+// unit per l so the build parallelises).
+#include "registry.hpp"
+DF3C_REGISTER_LP(3, register_lp3)

@@ -1,0 +1,103 @@
+// Per-class launch configuration and the launcher table shared by the
+// instantiation units and the runtime.
+#pragma once
+#include "kernels.hpp"
+
+namespace df3c {
+
+struct ClassInfo {
+  int ts = 0;         // lanes per team
+  int tpw = 0;        // teams per wavefront (= workgroup)
+  int lds = 0;        // dynamic LDS bytes per workgroup
+  hipError_t (*store)(const StoreArgs &, int, hipStream_t) = nullptr;
+  hipError_t (*jfn)(const JArgs &, int, hipStream_t) = nullptr;
+};
+
+// Team size and primitive chunk per class: small classes run one triplet per
+// lane (or per few lanes), large ones one triplet per wavefront.
+template <int LP, int LA, int LB>
+struct Cfg {
+  using G = Geo<LP, LA, LA + LB>;
+  static constexpr int work = G::NPI + G::NE * G::NCP + G::NPURE * G::NE +
+                              G::NPURE * ncart(LA) * ncart(LB);
+  static constexpr int TS0 = work >= 1024 ? 64 : work >= 256 ? 16 : work >= 48 ? 4 : 1;
+  static constexpr int PCH0 = TS0 >= 16 ? 4 : TS0 == 4 ? 2 : 1;
+  // keep the workgroup's LDS within the 160 KiB of a CU
+  static constexpr int lds_of(int ts, int pch) {
+    return (64 / ts) * (imax(pch * (PS_N + G::NV1 + G::NSW), G::NE * G::NCP) +
+                        imax(G::NPI, G::NPURE * G::NE) + GenHrr<LA, LB>::NHC) * 8;
+  }
+  static constexpr int TS = lds_of(TS0, PCH0) <= 160 * 1024 ? TS0
+                            : lds_of(imin(64, TS0 * 4), PCH0) <= 160 * 1024 ? imin(64, TS0 * 4)
+                                                                           : 64;
+  static constexpr int PCH = lds_of(TS, PCH0) <= 160 * 1024 ? PCH0 : 1;
+  static constexpr int LDS = (64 / TS) * Foot<LP, LA, LB, PCH>::TOTAL * 8;
+  static_assert(LDS <= 160 * 1024, "class does not fit the LDS of a CU");
+};
+
+template <int LP, int LA, int LB>
+hipError_t launch_store(const StoreArgs &a, int grid, hipStream_t s) {
+  using C = Cfg<LP, LA, LB>;
+  auto kern = k_store<LP, LA, LB, C::TS, C::PCH>;
+  static const hipError_t attr = hipFuncSetAttribute(
+      reinterpret_cast<const void *>(kern), hipFuncAttributeMaxDynamicSharedMemorySize, C::LDS);
+  if (attr != hipSuccess) return attr;
+  hipLaunchKernelGGL(kern, dim3(grid), dim3(64), C::LDS, s, a);
+  return hipGetLastError();
+}
+
+template <int LP, int LA, int LB>
+hipError_t launch_J(const JArgs &a, int grid, hipStream_t s) {
+  using C = Cfg<LP, LA, LB>;
+  auto kern = k_J<LP, LA, LB, C::TS, C::PCH>;
+  static const hipError_t attr = hipFuncSetAttribute(
+      reinterpret_cast<const void *>(kern), hipFuncAttributeMaxDynamicSharedMemorySize, C::LDS);
+  if (attr != hipSuccess) return attr;
+  hipLaunchKernelGGL(kern, dim3(grid), dim3(64), C::LDS, s, a);
+  return hipGetLastError();
+}
+
+template <int LP, int LA, int LB>
+ClassInfo class_info() {
+  using C = Cfg<LP, LA, LB>;
+  ClassInfo c;
+  c.ts = C::TS;
+  c.tpw = 64 / C::TS;
+  c.lds = C::LDS;
+  c.store = &launch_store<LP, LA, LB>;
+  c.jfn = &launch_J<LP, LA, LB>;
+  return c;
+}
+
+constexpr int NLP = 7, NLA = 5;  // LP <= 6, la, lb <= 4
+// filled by inst_lp<LP>.hip
+void register_lp0(ClassInfo (&t)[NLA][NLA]);
+void register_lp1(ClassInfo (&t)[NLA][NLA]);
+void register_lp2(ClassInfo (&t)[NLA][NLA]);
+void register_lp3(ClassInfo (&t)[NLA][NLA]);
+void register_lp4(ClassInfo (&t)[NLA][NLA]);
+void register_lp5(ClassInfo (&t)[NLA][NLA]);
+void register_lp6(ClassInfo (&t)[NLA][NLA]);
+
+}  // namespace df3c
+
+#define DF3C_REGISTER_LP(LPV, FN)                                   \
+  namespace df3c {                                                  \
+  void FN(ClassInfo (&t)[NLA][NLA]) {                               \
+    t[0][0] = class_info<LPV, 0, 0>();                              \
+    t[1][0] = class_info<LPV, 1, 0>();                              \
+    t[1][1] = class_info<LPV, 1, 1>();                              \
+    t[2][0] = class_info<LPV, 2, 0>();                              \
+    t[2][1] = class_info<LPV, 2, 1>();                              \
+    t[2][2] = class_info<LPV, 2, 2>();                              \
+    t[3][0] = class_info<LPV, 3, 0>();                              \
+    t[3][1] = class_info<LPV, 3, 1>();                              \
+    t[3][2] = class_info<LPV, 3, 2>();                              \
+    t[3][3] = class_info<LPV, 3, 3>();                              \
+    t[4][0] = class_info<LPV, 4, 0>();                              \
+    t[4][1] = class_info<LPV, 4, 1>();                              \
+    t[4][2] = class_info<LPV, 4, 2>();                              \
+    t[4][3] = class_info<LPV, 4, 3>();                              \
+    t[4][4] = class_info<LPV, 4, 4>();                              \
+  }                                                                 \
+  }

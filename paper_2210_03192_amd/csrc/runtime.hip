@@ -1,0 +1,394 @@
+// Host runtime of libdf3c: argument validation, class binning, planning and
+// launches behind the C ABI of include/df3c.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <mutex>
+#include <vector>
+
+#include "../../include/df3c.h"
+#include "registry.hpp"
+
+namespace df3c {
+namespace {
+
+constexpr int NCLS = NLP * NLA * NLA;  // class id = (LP * 5 + la) * 5 + lb
+constexpr int MAX_DEV = 64;
+
+struct DevState {
+  bool ready = false;
+  double *boys = nullptr;
+  int ncu = 0;
+};
+DevState g_dev[MAX_DEV];
+std::mutex g_mu;
+ClassInfo g_cls[NLP][NLA][NLA];
+bool g_cls_ready = false;
+int *g_pinned = nullptr;  // host readback buffer
+
+// Boys table: F_m(i * DT) for m < BOYS_MTAB, by the series
+//   F_m(T) = exp(-T) sum_k (2T)^k / ((2m+1)(2m+3)...(2m+2k+1))
+// summed in long double (all terms positive, T <= 36).
+void boys_table_host(std::vector<double> &tab) {
+  tab.assign(size_t(BOYS_NGRID) * BOYS_MTAB, 0.0);
+  for (int i = 0; i < BOYS_NGRID; ++i) {
+    const long double T = (long double)i * BOYS_DT;
+    for (int m = 0; m < BOYS_MTAB; ++m) {
+      long double term = 1.0L / (2 * m + 1), sum = term;
+      for (int k = 1; k < 4000; ++k) {
+        term *= 2 * T / (2 * m + 2 * k + 1);
+        sum += term;
+        if (term < sum * 1e-24L) break;
+      }
+      tab[size_t(i) * BOYS_MTAB + m] = (double)(expl(-T) * sum);
+    }
+  }
+}
+
+void register_all() {
+  if (g_cls_ready) return;
+  ClassInfo (*t)[NLA][NLA] = g_cls;
+  register_lp0(t[0]);
+  register_lp1(t[1]);
+  register_lp2(t[2]);
+  register_lp3(t[3]);
+  register_lp4(t[4]);
+  register_lp5(t[5]);
+  register_lp6(t[6]);
+  g_cls_ready = true;
+}
+
+int init_device(DevState **out) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= MAX_DEV) return DF3C_E_HIP;
+  std::lock_guard<std::mutex> lk(g_mu);
+  register_all();
+  DevState &s = g_dev[dev];
+  if (!s.ready) {
+    std::vector<double> tab;
+    boys_table_host(tab);
+    if (hipMalloc(&s.boys, tab.size() * sizeof(double)) != hipSuccess) return DF3C_E_HIP;
+    if (hipMemcpy(s.boys, tab.data(), tab.size() * sizeof(double), hipMemcpyHostToDevice) !=
+        hipSuccess)
+      return DF3C_E_HIP;
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return DF3C_E_HIP;
+    s.ncu = prop.multiProcessorCount;
+    if (!g_pinned && hipHostMalloc((void **)&g_pinned, sizeof(int) * (NCLS + 8)) != hipSuccess)
+      return DF3C_E_HIP;
+    s.ready = true;
+  }
+  *out = &s;
+  return DF3C_OK;
+}
+
+ShellsDev dev_shells(const df3c_shells *b) {
+  return ShellsDev{b->nprim, b->prim_off, b->atom, b->exps, b->coefs};
+}
+
+bool shells_ok(const df3c_shells *b) {
+  return b && b->nshell >= 0 && (b->nshell == 0 || (b->l && b->nprim && b->prim_off && b->atom &&
+                                                    b->exps && b->coefs));
+}
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+// ------------------------------------------------------------ small kernels
+__global__ void k_fill_i32(int *p, int n, int v) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = v;
+}
+__global__ void k_zero_f64(double *p, int64_t n) {
+  for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < n;
+       i += int64_t(gridDim.x) * blockDim.x)
+    p[i] = 0.0;
+}
+
+// class of every triplet; hist[NCLS] counts, err[0] flags bad input
+__global__ void k_classify(const int32_t *trip, int64_t ntrip, const int32_t *laux, int32_t naux,
+                           const int32_t *lorb, int32_t norb, uint8_t *cls, int *hist, int *err) {
+  for (int64_t t = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; t < ntrip;
+       t += int64_t(gridDim.x) * blockDim.x) {
+    const int P = trip[3 * t], a = trip[3 * t + 1], b = trip[3 * t + 2];
+    if (P < 0 || P >= naux || a < 0 || a >= norb || b < 0 || b >= norb) {
+      atomicOr(err, 1);
+      cls[t] = 255;
+      continue;
+    }
+    const int lp = laux[P], la = lorb[a], lb = lorb[b];
+    if (lp < 0 || lp > DF3C_LMAX_AUX || la < 0 || la > DF3C_LMAX_ORB || lb < 0 ||
+        lb > DF3C_LMAX_ORB) {
+      atomicOr(err, 2);
+      cls[t] = 255;
+      continue;
+    }
+    const int hi = la >= lb ? la : lb, lo = la >= lb ? lb : la;
+    const int c = (lp * NLA + hi) * NLA + lo;
+    cls[t] = uint8_t(c);
+    atomicAdd(&hist[c], 1);
+  }
+}
+
+// exclusive scan of hist into cursor (one thread; NCLS is small)
+__global__ void k_scan(const int *hist, int *cursor) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    int s = 0;
+    for (int c = 0; c < NCLS; ++c) {
+      cursor[c] = s;
+      s += hist[c];
+    }
+  }
+}
+
+// HRR direction.  Eq. hrr moves quanta from the centre on which VRR1 built
+// them (A) to the other one (B) with powers of AB; the transfer is well
+// conditioned when the Gaussian product centre P lies near A, i.e. when A's
+// exponents dominate.  For equal l the triplet is oriented so that the shell
+// with the larger (max exponent x min exponent) carries the VRR1 quanta; for
+// unequal l the quanta always go to the lower-l shell (fewest transfers).
+__device__ __forceinline__ double shell_tightness(const ShellsDev &b, int s) {
+  const int K = b.nprim[s];
+  const double *e = b.exps + b.prim_off[s];
+  double lo = e[0], hi = e[0];
+  for (int i = 1; i < K; ++i) {
+    lo = fmin(lo, e[i]);
+    hi = fmax(hi, e[i]);
+  }
+  return lo * hi;
+}
+
+__global__ void k_scatter(const int32_t *trip, int64_t ntrip, const int32_t *lorb, ShellsDev orb,
+                          const uint8_t *cls, int *cursor, uint32_t *bucket) {
+  for (int64_t t = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; t < ntrip;
+       t += int64_t(gridDim.x) * blockDim.x) {
+    const int c = cls[t];
+    if (c == 255) continue;
+    const int a = trip[3 * t + 1], b = trip[3 * t + 2];
+    const int la = lorb[a], lb = lorb[b];
+    const bool swp = la < lb || (la == lb && shell_tightness(orb, b) > shell_tightness(orb, a));
+    const uint32_t code = uint32_t(t) | (swp ? 0x80000000u : 0u);
+    bucket[atomicAdd(&cursor[c], 1)] = code;
+  }
+}
+
+int grid_for(int64_t items, int tpw, int ncu) {
+  const int64_t need = (items + tpw - 1) / tpw;
+  const int64_t cap = int64_t(ncu) * 64;
+  return int(std::max<int64_t>(1, std::min(need, cap)));
+}
+
+}  // namespace
+}  // namespace df3c
+
+using namespace df3c;
+
+extern "C" {
+
+int df3c_init(void) {
+  DevState *s = nullptr;
+  return init_device(&s);
+}
+
+const char *df3c_status_string(int status) {
+  switch (status) {
+    case DF3C_OK: return "ok";
+    case DF3C_E_ARG: return "invalid argument";
+    case DF3C_E_UNSUPPORTED: return "unsupported angular momentum or option";
+    case DF3C_E_WORKSPACE: return "workspace missing or too small";
+    case DF3C_E_HIP: return "HIP runtime error";
+    default: return "unknown status";
+  }
+}
+
+size_t df3c_eval_batch_workspace(int64_t ntrip) {
+  if (ntrip < 0) ntrip = 0;
+  return align256(sizeof(int) * (2 * NCLS + 8)) + align256(size_t(ntrip)) +
+         align256(sizeof(uint32_t) * size_t(ntrip));
+}
+
+int df3c_eval_batch(const double *xyz, const df3c_shells *aux, const df3c_shells *orb,
+                    int64_t ntrip, const int32_t *trip, const int64_t *out_off, double *out,
+                    void *ws, size_t ws_bytes, uint32_t flags, void *stream) {
+  (void)flags;
+  if (ntrip < 0 || ntrip > 0x7fffffff) return DF3C_E_ARG;
+  if (ntrip == 0) return DF3C_OK;
+  if (!xyz || !shells_ok(aux) || !shells_ok(orb) || !trip || !out_off || !out) return DF3C_E_ARG;
+  if (orb->pure != 0 || (aux->pure != 0 && aux->pure != 1)) return DF3C_E_UNSUPPORTED;
+  if (!ws || ws_bytes < df3c_eval_batch_workspace(ntrip)) return DF3C_E_WORKSPACE;
+  DevState *ds = nullptr;
+  int rc = init_device(&ds);
+  if (rc) return rc;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  char *w = static_cast<char *>(ws);
+  int *hist = reinterpret_cast<int *>(w);
+  int *cursor = hist + NCLS;
+  int *err = cursor + NCLS;
+  w += align256(sizeof(int) * (2 * NCLS + 8));
+  uint8_t *cls = reinterpret_cast<uint8_t *>(w);
+  w += align256(size_t(ntrip));
+  uint32_t *bucket = reinterpret_cast<uint32_t *>(w);
+
+  const int g = int(std::min<int64_t>((ntrip + 255) / 256, 4096));
+  hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(256), 0, s, hist, 2 * NCLS + 8, 0);
+  hipLaunchKernelGGL(k_classify, dim3(g), dim3(256), 0, s, trip, ntrip, aux->l, aux->nshell,
+                     orb->l, orb->nshell, cls, hist, err);
+  hipLaunchKernelGGL(k_scan, dim3(1), dim3(64), 0, s, hist, cursor);
+  hipLaunchKernelGGL(k_scatter, dim3(g), dim3(256), 0, s, trip, ntrip, orb->l, dev_shells(orb),
+                     cls, cursor, bucket);
+  if (hipMemcpyAsync(g_pinned, hist, sizeof(int) * NCLS, hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipMemcpyAsync(g_pinned + NCLS, err, sizeof(int), hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess)
+    return DF3C_E_HIP;
+  if (g_pinned[NCLS] & 1) return DF3C_E_ARG;
+  if (g_pinned[NCLS] & 2) return DF3C_E_UNSUPPORTED;
+  int counts[NCLS];
+  std::memcpy(counts, g_pinned, sizeof(counts));
+  if (aux->pure == 0)
+    for (int c = 0; c < NCLS; ++c)
+      if (counts[c] && c / (NLA * NLA) > 1) return DF3C_E_UNSUPPORTED;
+
+  StoreArgs a{};
+  a.boys = ds->boys;
+  a.xyz = xyz;
+  a.aux = dev_shells(aux);
+  a.orb = dev_shells(orb);
+  a.trip = trip;
+  a.out_off = out_off;
+  a.out = out;
+  a.pure = aux->pure;
+  int64_t off = 0;
+  for (int c = 0; c < NCLS; ++c) {
+    if (!counts[c]) continue;
+    const int lp = c / (NLA * NLA), la = (c / NLA) % NLA, lb = c % NLA;
+    const ClassInfo &ci = g_cls[lp][la][lb];
+    a.bucket = bucket + off;
+    a.count = counts[c];
+    if (ci.store(a, grid_for(counts[c], ci.tpw, ds->ncu), s) != hipSuccess) return DF3C_E_HIP;
+    off += counts[c];
+  }
+  return DF3C_OK;
+}
+
+// ------------------------------------------------------------------- DF-J
+namespace {
+struct JPlan {
+  std::vector<int32_t> orb_sorted, aux_sorted;     // shells grouped by l
+  int32_t orb_start[DF3C_LMAX_ORB + 2] = {}, aux_start[DF3C_LMAX_AUX + 2] = {};
+  std::vector<int64_t> ao_off, aux_off;
+  int64_t nao = 0, naux = 0;
+};
+
+int make_plan(const df3c_shells *aux, const df3c_shells *orb, JPlan &p) {
+  if (!aux->l_host || !orb->l_host) return DF3C_E_ARG;
+  std::vector<int32_t> cnt_o(DF3C_LMAX_ORB + 1, 0), cnt_a(DF3C_LMAX_AUX + 1, 0);
+  p.ao_off.assign(orb->nshell + 1, 0);
+  p.aux_off.assign(aux->nshell + 1, 0);
+  for (int s = 0; s < orb->nshell; ++s) {
+    const int l = orb->l_host[s];
+    if (l < 0 || l > DF3C_LMAX_ORB) return DF3C_E_UNSUPPORTED;
+    cnt_o[l]++;
+    p.ao_off[s + 1] = p.ao_off[s] + (l + 1) * (l + 2) / 2;
+  }
+  for (int s = 0; s < aux->nshell; ++s) {
+    const int l = aux->l_host[s];
+    if (l < 0 || l > DF3C_LMAX_AUX) return DF3C_E_UNSUPPORTED;
+    if (!aux->pure && l > 1) return DF3C_E_UNSUPPORTED;
+    cnt_a[l]++;
+    p.aux_off[s + 1] = p.aux_off[s] + (aux->pure ? 2 * l + 1 : (l + 1) * (l + 2) / 2);
+  }
+  p.nao = p.ao_off[orb->nshell];
+  p.naux = p.aux_off[aux->nshell];
+  for (int l = 0; l <= DF3C_LMAX_ORB; ++l) p.orb_start[l + 1] = p.orb_start[l] + cnt_o[l];
+  for (int l = 0; l <= DF3C_LMAX_AUX; ++l) p.aux_start[l + 1] = p.aux_start[l] + cnt_a[l];
+  p.orb_sorted.resize(orb->nshell);
+  p.aux_sorted.resize(aux->nshell);
+  std::vector<int32_t> fo(p.orb_start, p.orb_start + DF3C_LMAX_ORB + 1),
+      fa(p.aux_start, p.aux_start + DF3C_LMAX_AUX + 1);
+  for (int s = 0; s < orb->nshell; ++s) p.orb_sorted[fo[orb->l_host[s]]++] = s;
+  for (int s = 0; s < aux->nshell; ++s) p.aux_sorted[fa[aux->l_host[s]]++] = s;
+  return DF3C_OK;
+}
+
+size_t jplan_bytes(int64_t norb, int64_t naux) {
+  return align256(sizeof(int32_t) * norb) + align256(sizeof(int32_t) * naux) +
+         align256(sizeof(int64_t) * (norb + 1)) + align256(sizeof(int64_t) * (naux + 1));
+}
+}  // namespace
+
+size_t df3c_coulomb_J_workspace(const df3c_shells *aux, const df3c_shells *orb) {
+  if (!aux || !orb) return 0;
+  return jplan_bytes(orb->nshell, aux->nshell);
+}
+
+int df3c_coulomb_J(const double *xyz, const df3c_shells *aux, const df3c_shells *orb,
+                   const double *d, double *J, void *ws, size_t ws_bytes, uint32_t flags,
+                   void *stream) {
+  (void)flags;
+  if (!xyz || !shells_ok(aux) || !shells_ok(orb) || !d || !J) return DF3C_E_ARG;
+  if (orb->pure != 0 || (aux->pure != 0 && aux->pure != 1)) return DF3C_E_UNSUPPORTED;
+  if (!ws || ws_bytes < df3c_coulomb_J_workspace(aux, orb)) return DF3C_E_WORKSPACE;
+  DevState *ds = nullptr;
+  int rc = init_device(&ds);
+  if (rc) return rc;
+  JPlan p;
+  rc = make_plan(aux, orb, p);
+  if (rc) return rc;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  char *w = static_cast<char *>(ws);
+  int32_t *orb_sorted = reinterpret_cast<int32_t *>(w);
+  w += align256(sizeof(int32_t) * orb->nshell);
+  int32_t *aux_sorted = reinterpret_cast<int32_t *>(w);
+  w += align256(sizeof(int32_t) * aux->nshell);
+  int64_t *ao_off = reinterpret_cast<int64_t *>(w);
+  w += align256(sizeof(int64_t) * (orb->nshell + 1));
+  int64_t *aux_off = reinterpret_cast<int64_t *>(w);
+  if (hipMemcpyAsync(orb_sorted, p.orb_sorted.data(), sizeof(int32_t) * orb->nshell,
+                     hipMemcpyHostToDevice, s) != hipSuccess ||
+      hipMemcpyAsync(aux_sorted, p.aux_sorted.data(), sizeof(int32_t) * aux->nshell,
+                     hipMemcpyHostToDevice, s) != hipSuccess ||
+      hipMemcpyAsync(ao_off, p.ao_off.data(), sizeof(int64_t) * (orb->nshell + 1),
+                     hipMemcpyHostToDevice, s) != hipSuccess ||
+      hipMemcpyAsync(aux_off, p.aux_off.data(), sizeof(int64_t) * (aux->nshell + 1),
+                     hipMemcpyHostToDevice, s) != hipSuccess)
+    return DF3C_E_HIP;
+  // the host vectors must outlive the asynchronous copies
+  if (hipStreamSynchronize(s) != hipSuccess) return DF3C_E_HIP;
+  const int64_t nJ = p.nao * p.nao;
+  hipLaunchKernelGGL(k_zero_f64, dim3(int(std::min<int64_t>((nJ + 255) / 256, 4096))), dim3(256),
+                     0, s, J, nJ);
+  JArgs a{};
+  a.boys = ds->boys;
+  a.xyz = xyz;
+  a.aux = dev_shells(aux);
+  a.orb = dev_shells(orb);
+  a.ao_off = ao_off;
+  a.aux_off = aux_off;
+  a.d = d;
+  a.J = J;
+  a.nao = p.nao;
+  a.pure = aux->pure;
+  for (int lp = 0; lp <= DF3C_LMAX_AUX; ++lp) {
+    const int np = p.aux_start[lp + 1] - p.aux_start[lp];
+    if (!np) continue;
+    a.psh = aux_sorted + p.aux_start[lp];
+    a.np = np;
+    for (int la = 0; la <= DF3C_LMAX_ORB; ++la)
+      for (int lb = 0; lb <= la; ++lb) {
+        const int na = p.orb_start[la + 1] - p.orb_start[la];
+        const int nb = p.orb_start[lb + 1] - p.orb_start[lb];
+        if (!na || !nb) continue;
+        a.ash = orb_sorted + p.orb_start[la];
+        a.bsh = orb_sorted + p.orb_start[lb];
+        a.na = na;
+        a.nb = nb;
+        a.same = (la == lb);
+        a.npair = (la == lb) ? int64_t(na) * (na + 1) / 2 : int64_t(na) * nb;
+        const ClassInfo &ci = g_cls[lp][la][lb];
+        if (ci.jfn(a, grid_for(a.npair, ci.tpw, ds->ncu), s) != hipSuccess) return DF3C_E_HIP;
+      }
+  }
+  return DF3C_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,150 @@
+"""Python binding of libdf3c (ctypes).  Argument marshalling only: every step
+of the integral path runs in the library's HIP kernels; PyTorch provides the
+device memory and the stream.  There is no CPU fallback: without the built
+library (or without a GPU) these functions raise.
+"""
+import ctypes
+import os
+from dataclasses import dataclass
+from typing import Optional
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libdf3c.so")
+_lib = None
+
+DF3C_OK = 0
+
+
+class DF3CError(RuntimeError):
+    pass
+
+
+class _Shells(ctypes.Structure):
+    _fields_ = [
+        ("nshell", ctypes.c_int32),
+        ("l_host", ctypes.c_void_p),
+        ("l", ctypes.c_void_p),
+        ("nprim", ctypes.c_void_p),
+        ("prim_off", ctypes.c_void_p),
+        ("atom", ctypes.c_void_p),
+        ("exps", ctypes.c_void_p),
+        ("coefs", ctypes.c_void_p),
+        ("pure", ctypes.c_int32),
+    ]
+
+
+def lib():
+    """The loaded libdf3c (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise DF3CError(f"{LIB_PATH} is missing: build it with paper_2210_03192_amd/build.py")
+        L = ctypes.CDLL(LIB_PATH)
+        P, I64, U32, SZ = ctypes.c_void_p, ctypes.c_int64, ctypes.c_uint32, ctypes.c_size_t
+        L.df3c_init.argtypes = []
+        L.df3c_status_string.restype = ctypes.c_char_p
+        L.df3c_status_string.argtypes = [ctypes.c_int]
+        L.df3c_eval_batch_workspace.restype = SZ
+        L.df3c_eval_batch_workspace.argtypes = [I64]
+        L.df3c_eval_batch.argtypes = [P, P, P, I64, P, P, P, P, SZ, U32, P]
+        L.df3c_coulomb_J_workspace.restype = SZ
+        L.df3c_coulomb_J_workspace.argtypes = [P, P]
+        L.df3c_coulomb_J.argtypes = [P, P, P, P, P, P, SZ, U32, P]
+        _lib = L
+    return _lib
+
+
+def _check(rc, what):
+    if rc != DF3C_OK:
+        raise DF3CError(f"{what}: {lib().df3c_status_string(rc).decode()} (status {rc})")
+
+
+def _stream(stream=None):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None and t.numel() else ctypes.c_void_p(0)
+
+
+@dataclass
+class DeviceBasis:
+    """A basis resident on the GPU (arrays of paper_2210_03192_amd.inputs.Basis)."""
+    l_host: np.ndarray
+    l: torch.Tensor
+    nprim: torch.Tensor
+    prim_off: torch.Tensor
+    atom: torch.Tensor
+    exps: torch.Tensor
+    coefs: torch.Tensor
+    pure: int
+
+    @classmethod
+    def from_basis(cls, b, device="cuda"):
+        l_host = np.ascontiguousarray(b.l, np.int32)
+        t = lambda a, dt: torch.as_tensor(np.ascontiguousarray(a), dtype=dt, device=device)
+        return cls(l_host, t(b.l, torch.int32), t(b.nprim, torch.int32),
+                   t(b.prim_off, torch.int64), t(b.atom, torch.int32),
+                   t(b.exps, torch.float64), t(b.coefs, torch.float64), int(b.pure))
+
+    @property
+    def nshell(self):
+        return int(self.l_host.shape[0])
+
+    def struct(self):
+        return _Shells(self.nshell, self.l_host.ctypes.data, self.l.data_ptr(),
+                       self.nprim.data_ptr(), self.prim_off.data_ptr(), self.atom.data_ptr(),
+                       self.exps.data_ptr(), self.coefs.data_ptr(), self.pure)
+
+    def offsets(self):
+        n = np.array([2 * l + 1 if self.pure else (l + 1) * (l + 2) // 2 for l in self.l_host],
+                     np.int64)
+        return np.concatenate([[0], np.cumsum(n)]).astype(np.int64)
+
+
+def init():
+    _check(lib().df3c_init(), "df3c_init")
+
+
+def eval_batch_workspace(ntrip: int) -> int:
+    return int(lib().df3c_eval_batch_workspace(int(ntrip)))
+
+
+def eval_batch(xyz: torch.Tensor, aux: DeviceBasis, orb: DeviceBasis, trip: torch.Tensor,
+               out_off: torch.Tensor, out: torch.Tensor, ws: Optional[torch.Tensor] = None,
+               flags: int = 0, stream=None) -> torch.Tensor:
+    """(P|ab) blocks of trip[t] = (P, a, b) written to out[out_off[t]:]."""
+    ntrip = int(trip.shape[0])
+    need = eval_batch_workspace(ntrip)
+    if ws is None or ws.numel() < need:
+        ws = torch.empty(max(need, 1), dtype=torch.uint8, device=xyz.device)
+    sa, so = aux.struct(), orb.struct()
+    _check(lib().df3c_eval_batch(_ptr(xyz), ctypes.byref(sa), ctypes.byref(so), ntrip, _ptr(trip),
+                                 _ptr(out_off), _ptr(out), _ptr(ws), ws.numel(), flags,
+                                 _stream(stream)), "df3c_eval_batch")
+    return out
+
+
+def coulomb_J_workspace(aux: DeviceBasis, orb: DeviceBasis) -> int:
+    sa, so = aux.struct(), orb.struct()
+    return int(lib().df3c_coulomb_J_workspace(ctypes.byref(sa), ctypes.byref(so)))
+
+
+def coulomb_J(xyz: torch.Tensor, aux: DeviceBasis, orb: DeviceBasis, d: torch.Tensor,
+              J: Optional[torch.Tensor] = None, ws: Optional[torch.Tensor] = None,
+              flags: int = 0, stream=None) -> torch.Tensor:
+    """J_ab = sum_P (ab|P) d_P (both triangles)."""
+    nao = int(orb.offsets()[-1])
+    if J is None:
+        J = torch.empty((nao, nao), dtype=torch.float64, device=xyz.device)
+    need = coulomb_J_workspace(aux, orb)
+    if ws is None or ws.numel() < need:
+        ws = torch.empty(max(need, 1), dtype=torch.uint8, device=xyz.device)
+    sa, so = aux.struct(), orb.struct()
+    _check(lib().df3c_coulomb_J(_ptr(xyz), ctypes.byref(sa), ctypes.byref(so), _ptr(d), _ptr(J),
+                                _ptr(ws), ws.numel(), flags, _stream(stream)), "df3c_coulomb_J")
+    return J

@@ -1,0 +1,62 @@
+"""Host-side checks of libdf3c that need no GPU: the library loads, exports every
+entry point declared in include/df3c.h, and rejects bad arguments before any
+device work."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "df3c.h")
+
+
+def _declared():
+    txt = open(HEADER).read()
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?[A-Za-z_0-9]+\s*\*?\s*(df3c_[A-Za-z_0-9]+)\s*\(",
+                                 txt, re.M)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_2210_03192_amd import df3c
+    if not os.path.exists(df3c.LIB_PATH):
+        pytest.fail("libdf3c.so is not built (run paper_2210_03192_amd/build.py)")
+    return df3c.lib()
+
+
+def test_header_declares_entry_points():
+    names = _declared()
+    for n in ("df3c_eval_batch", "df3c_coulomb_J", "df3c_init", "df3c_status_string"):
+        assert n in names
+
+
+def test_exports_every_declared_symbol(lib):
+    for n in _declared():
+        assert hasattr(lib, n), n
+
+
+def test_status_strings(lib):
+    for code in (0, -1, -2, -3, -4):
+        assert lib.df3c_status_string(code)
+    assert lib.df3c_status_string(-99) == b"unknown status"
+
+
+def test_eval_batch_rejects_null_arguments(lib):
+    # validation happens before any HIP call, so this runs without a GPU
+    rc = lib.df3c_eval_batch(None, None, None, 5, None, None, None, None, 0, 0, None)
+    assert rc == -1
+    rc = lib.df3c_eval_batch(None, None, None, -1, None, None, None, None, 0, 0, None)
+    assert rc == -1
+    assert lib.df3c_eval_batch(None, None, None, 0, None, None, None, None, 0, 0, None) == 0
+
+
+def test_coulomb_J_rejects_null_arguments(lib):
+    assert lib.df3c_coulomb_J(None, None, None, None, None, None, 0, 0, None) == -1
+
+
+def test_workspace_sizes(lib):
+    a = lib.df3c_eval_batch_workspace(0)
+    b = lib.df3c_eval_batch_workspace(100000)
+    assert 0 < a < b
