@@ -91,15 +91,19 @@ def pimap(g):
 
 
 def combine(g):
+    """Terms with u != 0, targets in [c][e''] order (the u = 0 term is the
+    prerequisite block pi_0 itself, which the kernels use as the target array)."""
     start, pi, w = [], [], []
-    for e in range(g.EA, g.EB + 1):
-        for E in carts(e):
-            for C in carts(g.LP):
+    for C in carts(g.LP):
+        for e in range(g.EA, g.EB + 1):
+            for E in carts(e):
                 start.append(len(pi))
                 for ux in range(min(E[0], C[0]) + 1):
                     for uy in range(min(E[1], C[1]) + 1):
                         for uz in range(min(E[2], C[2]) + 1):
                             u = (ux, uy, uz)
+                            if u == (0, 0, 0):
+                                continue
                             wt = 1
                             for i in range(3):
                                 wt *= math.comb(C[i], u[i]) * math.perm(E[i], u[i])
@@ -108,7 +112,7 @@ def combine(g):
                             pi.append(g.pi_index(sum(u), ep, nn))
                             w.append(wt)
     start.append(len(pi))
-    assert max(w) < 2**31
+    assert max(w, default=0) < 2**31
     return start, pi, w
 
 

@@ -3,11 +3,17 @@
 // Per contracted triplet (Section 2.5.1):
 //   setup + Boys -> [00|0]^(m)      per primitive triplet (Section 2.5.2)
 //   VRR1 2-quantal -> [e0|0]^(LP)   per primitive triplet (Section 2.5.3)
-//   pi_k(e', n)    += sW x [e'0|0]  early contraction of the CVRR2 prerequisites
-//   (e0|c)          = n-q CVRR2      once per triplet (Section 2.5.4)
-//   (e0|P)          = solid-harmonic transform of the ket
-//   (ab|P)          = n-q HRR        once per triplet (Section 2.5.5)
-//   digestion: store the block, or accumulate J_ab += sum_P (ab|P) d_P.
+//   pi_k(e', n)    += sW x [e'0|0]  early contraction of the CVRR2 prerequisites,
+//                                   accumulated in registers across primitives
+//   (e0|c)          = n-q CVRR2      once per triplet, in place on pi_0 (Section 2.5.4)
+//   (e0|P)          = solid-harmonic transform, constant coefficients
+//   (ab|P)          = n-q HRR, factorised per Cartesian axis, in registers (Section 2.5.5)
+//   digestion: store the block (staged through LDS for coalesced writes), or
+//   accumulate J_ab += sum_P (ab|P) d_P.
+//
+// A team of TS lanes owns one triplet; TS <= 64 packs 64/TS teams in a
+// single-wave workgroup, TS = 128 / 256 spreads one triplet over 2 / 4 waves
+// of a workgroup.  Team synchronisation is a workgroup barrier.
 #pragma once
 #include "device.hpp"
 
@@ -44,49 +50,94 @@ struct JArgs {
   int32_t pure;
 };
 
-
-// LDS footprint (doubles) of one team
+// LDS layout of one team (in doubles).  Regions are reused once dead:
+//   PI   [0, NPI)                 pi; its block k = 0 is the target (e0|c) ([c][e''])
+//   PRIM [NPI, NPI + PCH*REC)     primitive records of the current chunk
+//   EM   (e0|P) [m][e'']          in the dead tail of pi, else in PRIM, else extra
+//   STG  output staging          in the dead pi_0 / PRIM area not used by EM, else extra
 template <int LP, int LA, int LB, int PCH>
-struct Foot {
+struct Layout {
   using G = Geo<LP, LA, LA + LB>;
-  static constexpr int REC = PS_N + G::NV1 + G::NSW;      // per primitive record
-  static constexpr int PRIM = PCH * REC;
-  static constexpr int EC = G::NE * G::NCP;
-  static constexpr int EM = G::NPURE * G::NE;
-  static constexpr int NHC = GenHrr<LA, LB>::NHC;
-  static constexpr int R0 = imax(PRIM, EC);               // prim records, then (e0|c)
-  static constexpr int R1 = imax(G::NPI, EM);             // pi, then (e0|P)
-  static constexpr int TOTAL = R0 + R1 + NHC;
+  static constexpr int REC = PS_N + G::NV1 + G::NSW;
+  static constexpr int NEC = G::NCP * G::NE;
+  static constexpr int NEM = G::NPURE * G::NE;
+  static constexpr int NOUT = G::NPURE * ncart(LA) * ncart(LB);
+  static constexpr int PI = 0;
+  static constexpr int PRIM = G::NPI;
+  static constexpr int PRIM_END = PRIM + PCH * REC;
+  // EM: after pi_0 if the tail of pi is large enough, else in the PRIM area
+  static constexpr bool EM_IN_PI = NEM <= G::NPI - NEC;
+  static constexpr bool EM_IN_PRIM = !EM_IN_PI && NEM <= PCH * REC;
+  static constexpr int EM = EM_IN_PI ? NEC : EM_IN_PRIM ? PRIM : PRIM_END;
+  static constexpr int EM_END = EM + NEM;
+  static constexpr int END0 = imax(PRIM_END, EM_END);
+  // STG must not overlap EM (read during the HRR)
+  static constexpr int STG = (EM >= NOUT) ? 0 : (EM_IN_PI && NOUT <= PCH * REC) ? PRIM : END0;
+  static constexpr int TOTAL = imax(END0, STG + NOUT);
+};
+
+// Team size and primitive chunk per class: small classes run one triplet per
+// lane (or per few lanes), large ones one triplet per one to four wavefronts.
+template <int LP, int LA, int LB>
+struct Cfg {
+  using G = Geo<LP, LA, LA + LB>;
+  static constexpr int work = G::NPI + G::NE * G::NCP + G::NPURE * G::NE +
+                              G::NPURE * ncart(LA) * ncart(LB);
+  static constexpr int TS = work >= 6000 ? 256 : work >= 2500 ? 128 : work >= 1024 ? 64
+                            : work >= 256 ? 16 : work >= 48 ? 4 : 1;
+  static constexpr int PCH = TS >= 16 ? 4 : TS == 4 ? 2 : 1;
+  static constexpr int BLK = TS > 64 ? TS : 64;
+  static constexpr int LDS = (BLK / TS) * Layout<LP, LA, LB, PCH>::TOTAL * 8;
+  static_assert(LDS <= 160 * 1024, "class does not fit the LDS of a CU");
 };
 
 // ---------------------------------------------------------------------------
-// The per-triplet pipeline up to (e0|P) in LDS.  The team's LDS slice S holds
-// [R0: primitive records / (e0|c)] [R1: pi / (e0|P)] [HC].
-// A, B, C: centres; shell data of a (l = LA), b (l = LB), P (l = LP).
+// Per-lane slots of the prerequisite array pi: slot q of lane tid holds entry
+// r = tid + q TS, packed as (sW index << 16) | (VRR1 target index).
+// ---------------------------------------------------------------------------
+template <class G>
+__device__ __forceinline__ int pi_slot(int r) {
+  int code = -1;
+  static_for<G::LP + 1>([&](auto kc) {
+    constexpr int k = decltype(kc)::value;
+    if constexpr (G::nek(k) > 0) {
+      constexpr int o0 = G::pi_off(k), o1 = G::pi_off(k + 1), ne = G::nek(k);
+      if (r >= o0 && r < o1) {
+        const int n = (r - o0) / ne, e = r - o0 - n * ne;
+        code = ((G::sw_off(k) + n) << 16) | (offT(G::emin(k)) + e);
+      }
+    }
+  });
+  return code;
+}
+
+// ---------------------------------------------------------------------------
+// The per-triplet pipeline up to (e0|P) in LDS (region EM of the layout).
 // ---------------------------------------------------------------------------
 template <int LP, int LA, int LB, int TS, int PCH>
-__device__ __forceinline__ void triplet_to_e0P(const double *btab, double *S, int tid, int npmax,
-                                               const double *A,
+__device__ __forceinline__ void triplet_to_e0P(const double *btab, double *S, int tid,
+                                               const int *slot, int npmax, const double *A,
                                                const double *B, const double *C, int Ka,
                                                const double *ea, const double *ca, int Kb,
                                                const double *eb, const double *cb, int Kc,
                                                const double *ec, const double *cc, int pure) {
   using G = Geo<LP, LA, LA + LB>;
-  using F = Foot<LP, LA, LB, PCH>;
-  constexpr int L = G::L;
-  constexpr int REC = F::REC;
-  double *prims = S;
-  double *PI = S + F::R0;
-  double *EC = S;
-  double *EM = S + F::R0;
+  using LY = Layout<LP, LA, LB, PCH>;
   using TB = GenTab<LP, G::EA, G::EB>;
   static_assert(TB::NPI == G::NPI && TB::NTGT == G::NE * G::NCP, "generated tables out of date");
+  constexpr int L = G::L;
+  constexpr int REC = LY::REC;
+  constexpr int NQ = (G::NPI + TS - 1) / TS;
+  double *PI = S + LY::PI;
+  double *prims = S + LY::PRIM;
 
   const double ABx = A[0] - B[0], ABy = A[1] - B[1], ABz = A[2] - B[2];
   const double AB2 = ABx * ABx + ABy * ABy + ABz * ABz;
   const int K = Ka * Kb * Kc;
 
-  for (int r = tid; r < G::NPI; r += TS) PI[r] = 0.0;
+  double acc[NQ];
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) acc[q] = 0.0;
 
   for (int p0 = 0; p0 < npmax; p0 += PCH) {
     const int npc = imax(0, imin(PCH, K - p0));
@@ -147,55 +198,186 @@ __device__ __forceinline__ void triplet_to_e0P(const double *btab, double *S, in
     team_sync();
     // ---- VRR1, 2-quantal stages in place
     vrr1<G, TS, PCH, REC>(prims, npc, tid);
-    // ---- early contraction of the CVRR2 prerequisites
-    for (int r = tid; r < G::NPI; r += TS) {
-      const int isw = TB::pi_sw[r], iv = TB::pi_v[r];
-      double acc = PI[r];
-      for (int pp = 0; pp < npc; ++pp) {
-        const double *R = prims + pp * REC + PS_N;
-        acc += R[G::NV1 + isw] * R[iv];
+    // ---- early contraction of the CVRR2 prerequisites (register accumulators)
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+      const int code = slot[q];
+      if (code >= 0) {
+        const int isw = G::NV1 + (code >> 16), iv = code & 0xffff;
+        double a = acc[q];
+        for (int pp = 0; pp < npc; ++pp) {
+          const double *R = prims + pp * REC + PS_N;
+          a += R[isw] * R[iv];
+        }
+        acc[q] = a;
       }
-      PI[r] = acc;
     }
     team_sync();
   }
-  // ---- n-quantal CVRR2: (e0|c) = sum_u w pi_{|u|}(e-u, c-u)
+#pragma unroll
+  for (int q = 0; q < NQ; ++q)
+    if (slot[q] >= 0) PI[tid + q * TS] = acc[q];
+  team_sync();
+  // ---- n-quantal CVRR2 in place on pi_0: (e0|c) += sum_{u != 0} w pi_{|u|}(e-u, c-u)
   for (int t = tid; t < TB::NTGT; t += TS) {
-    double acc = 0.0;
-    for (int q = TB::cb_start[t]; q < TB::cb_start[t + 1]; ++q)
-      acc += double(TB::cb_w[q]) * PI[TB::cb_pi[q]];
-    EC[t] = acc;
+    const int q0 = TB::cb_start[t], q1 = TB::cb_start[t + 1];
+    if (q1 > q0) {
+      double a = PI[t];
+      for (int q = q0; q < q1; ++q) a += double(TB::cb_w[q]) * PI[TB::cb_pi[q]];
+      PI[t] = a;
+    }
   }
   team_sync();
-  // ---- ket to solid harmonics (or keep Cartesian for LP <= 1)
+  // ---- ket to solid harmonics: lanes over e'', constant coefficients
   if (pure) {
-    using sh = GenSolid<LP>;
-    for (int t = tid; t < G::NPURE * G::NE; t += TS) {
-      const int m = t / G::NE, e = t - m * G::NE;
-      double acc = 0.0;
-      for (int q = sh::start[m]; q < sh::start[m + 1]; ++q) acc += sh::val[q] * EC[e * G::NCP + sh::col[q]];
-      EM[t] = acc;
+    double *EM = S + LY::EM;
+    using SH = GenSolid<LP>;
+    for (int e = tid; e < G::NE; e += TS) {
+      double ecv[G::NCP];
+#pragma unroll
+      for (int c = 0; c < G::NCP; ++c) ecv[c] = PI[c * G::NE + e];
+      static_for<G::NPURE>([&](auto mc) {
+        constexpr int m = decltype(mc)::value;
+        double v = 0.0;
+        static_for<G::NCP>([&](auto cc_) {
+          constexpr int c = decltype(cc_)::value;
+          constexpr double t = SH::dense[m * G::NCP + c];
+          if constexpr (t != 0.0) v += t * ecv[c];
+        });
+        EM[m * G::NE + e] = v;
+      });
     }
-  } else {
-    for (int t = tid; t < G::NCP * G::NE; t += TS) {
-      const int m = t / G::NE, e = t - m * G::NE;
-      EM[t] = EC[e * G::NCP + m];
-    }
+  } else if constexpr (LY::EM != 0) {
+    // Cartesian ket (LP <= 1): (e0|c) is already the result; move it to EM
+    double *EM = S + LY::EM;
+    for (int t = tid; t < G::NCP * G::NE; t += TS) EM[t] = PI[t];
   }
   team_sync();
 }
 
-// HRR coefficients prod_x C(b_x, i_x) AB_x^{b_x - i_x} for all (b, i)
+// ---------------------------------------------------------------------------
+// n-quantal HRR for one (ket component m, bra component a):
+//   (a b|m) = sum_{i <= b} prod_x C(b_x, i_x) AB_x^{b_x - i_x} (a+i 0|m),
+// evaluated axis by axis (z, then y, then x) in registers.  out[b] for all
+// Cartesian b of l = LB.
+// ---------------------------------------------------------------------------
 template <int LA, int LB>
-__device__ __forceinline__ void hrr_coefs(double *HC, int tid, int TS, const double *A,
-                                          const double *B) {
-  using h = GenHrr<LA, LB>;
-  const double AB[3] = {A[0] - B[0], A[1] - B[1], A[2] - B[2]};
-  for (int n = tid; n < h::NHC; n += TS) {
-    double v = double(h::hc_binom[n]);
-    for (int x = 0; x < 3; ++x)
-      for (int k = 0; k < h::hc_pow[4 * n + x]; ++k) v *= AB[x];
-    HC[n] = v;
+__device__ __forceinline__ void hrr_nq(const double *EMm, int a, const double *pwx,
+                                       const double *pwy, const double *pwz, double *out) {
+  constexpr int NI = offT(LB + 1);  // all Cartesians i with |i| <= LB
+  // components of a (y, z suffice for the index)
+  int ay = 0, az = 0;
+  static_for<ncart(LA)>([&](auto ac) {
+    constexpr int c = decltype(ac)::value;
+    constexpr C3 q = cart(LA, c);
+    if (a == c) {
+      ay = q[1];
+      az = q[2];
+    }
+  });
+  double X[NI];
+  // X[i] = (a+i 0|m); e'' index of a + i relative to level LA
+  static_for<LB + 1>([&](auto lc) {
+    constexpr int li = decltype(lc)::value;
+    static_for<ncart(li)>([&](auto ic) {
+      constexpr int c = decltype(ic)::value;
+      constexpr C3 i = cart(li, c);
+      const int s = ay + az + i[1] + i[2];
+      const int idx = offT(LA + li) - offT(LA) + (s * (s + 1)) / 2 + az + i[2];
+      X[offT(li) + c] = EMm[idx];
+    });
+  });
+  // z: Z(ix, iy, bz) = sum_{iz <= bz} C(bz, iz) ABz^{bz-iz} X(ix, iy, iz)
+  double Z[NI];
+  static_for<LB + 1>([&](auto xc) {
+    constexpr int ix = decltype(xc)::value;
+    static_for<LB + 1 - ix>([&](auto yc) {
+      constexpr int iy = decltype(yc)::value;
+      static_for<LB + 1 - ix - iy>([&](auto zc) {
+        constexpr int bz = decltype(zc)::value;
+        double v = 0.0;
+        static_for<bz + 1>([&](auto kc) {
+          constexpr int iz = decltype(kc)::value;
+          constexpr double bn = double(binom(bz, iz));
+          v += (bn * pwz[bz - iz]) * X[offT(ix + iy + iz) + cidx(ix, iy, iz)];
+        });
+        Z[offT(ix + iy + bz) + cidx(ix, iy, bz)] = v;
+      });
+    });
+  });
+  // y: Y(ix, by, bz) = sum_{iy <= by} C(by, iy) ABy^{by-iy} Z(ix, iy, bz)
+  double Y[NI];
+  static_for<LB + 1>([&](auto xc) {
+    constexpr int ix = decltype(xc)::value;
+    static_for<LB + 1 - ix>([&](auto yc) {
+      constexpr int by = decltype(yc)::value;
+      static_for<LB + 1 - ix - by>([&](auto zc) {
+        constexpr int bz = decltype(zc)::value;
+        double v = 0.0;
+        static_for<by + 1>([&](auto kc) {
+          constexpr int iy = decltype(kc)::value;
+          constexpr double bn = double(binom(by, iy));
+          v += (bn * pwy[by - iy]) * Z[offT(ix + iy + bz) + cidx(ix, iy, bz)];
+        });
+        Y[offT(ix + by + bz) + cidx(ix, by, bz)] = v;
+      });
+    });
+  });
+  // x: out(b) = sum_{ix <= bx} C(bx, ix) ABx^{bx-ix} Y(ix, by, bz), |b| = LB
+  static_for<ncart(LB)>([&](auto bc) {
+    constexpr int b = decltype(bc)::value;
+    constexpr C3 q = cart(LB, b);
+    double v = 0.0;
+    static_for<q[0] + 1>([&](auto kc) {
+      constexpr int ix = decltype(kc)::value;
+      constexpr double bn = double(binom(q[0], ix));
+      v += (bn * pwx[q[0] - ix]) * Y[offT(ix + q[1] + q[2]) + cidx(ix, q[1], q[2])];
+    });
+    out[b] = v;
+  });
+}
+
+// HRR of the whole block into the staging area STG: [m][a][b] (or [m][b][a]
+// when the triplet's a and b were swapped to orient the transfer).
+template <int LP, int LA, int LB, int TS, int PCH>
+__device__ __forceinline__ void hrr_block(double *S, int tid, const double *A, const double *B,
+                                          int np_out, bool swp) {
+  using G = Geo<LP, LA, LA + LB>;
+  using LY = Layout<LP, LA, LB, PCH>;
+  constexpr int NA = ncart(LA), NB = ncart(LB);
+  const double *EM = S + LY::EM;
+  double *STG = S + LY::STG;
+  double pwx[LB + 1], pwy[LB + 1], pwz[LB + 1];
+  pwx[0] = pwy[0] = pwz[0] = 1.0;
+#pragma unroll
+  for (int k = 1; k <= LB; ++k) {
+    pwx[k] = pwx[k - 1] * (A[0] - B[0]);
+    pwy[k] = pwy[k - 1] * (A[1] - B[1]);
+    pwz[k] = pwz[k - 1] * (A[2] - B[2]);
+  }
+  for (int it = tid; it < np_out * NA; it += TS) {
+    const int m = it / NA, a = it - m * NA;
+    double o[NB];
+    hrr_nq<LA, LB>(EM + m * G::NE, a, pwx, pwy, pwz, o);
+    if (!swp) {
+#pragma unroll
+      for (int b = 0; b < NB; ++b) STG[(m * NA + a) * NB + b] = o[b];
+    } else {
+#pragma unroll
+      for (int b = 0; b < NB; ++b) STG[(m * NB + b) * NA + a] = o[b];
+    }
+  }
+}
+
+// per-lane contraction slots, decoded once per launch
+template <int LP, int LA, int LB, int TS>
+__device__ __forceinline__ void make_slots(int *slot, int tid) {
+  using G = Geo<LP, LA, LA + LB>;
+  constexpr int NQ = (G::NPI + TS - 1) / TS;
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) {
+    const int r = tid + q * TS;
+    slot[q] = r < G::NPI ? pi_slot<G>(r) : -1;
   }
 }
 
@@ -203,20 +385,21 @@ __device__ __forceinline__ void hrr_coefs(double *HC, int tid, int TS, const dou
 // store digestion: one triplet per team, blocks written to out + out_off[t]
 // ---------------------------------------------------------------------------
 template <int LP, int LA, int LB, int TS, int PCH>
-__global__ void __launch_bounds__(64) k_store(StoreArgs a) {
+__global__ void __launch_bounds__(TS > 64 ? TS : 64) k_store(StoreArgs a) {
   using G = Geo<LP, LA, LA + LB>;
-  using F = Foot<LP, LA, LB, PCH>;
-  constexpr int TPW = 64 / TS;
+  using LY = Layout<LP, LA, LB, PCH>;
+  constexpr int BLK = TS > 64 ? TS : 64;
+  constexpr int TPB = BLK / TS;
   constexpr int NA = ncart(LA), NB = ncart(LB);
+  constexpr int NQ = (G::NPI + TS - 1) / TS;
   extern __shared__ double smem[];
   const int team = threadIdx.x / TS, tid = threadIdx.x % TS;
-  double *S = smem + team * F::TOTAL;
-  double *HC = S + F::R0 + F::R1;
-  double *EM = S + F::R0;
-  using h = GenHrr<LA, LB>;
+  double *S = smem + team * LY::TOTAL;
   const int np_out = a.pure ? npure(LP) : ncart(LP);
+  int slot[NQ];
+  make_slots<LP, LA, LB, TS>(slot, tid);
 
-  for (int64_t base = int64_t(blockIdx.x) * TPW; base < a.count; base += int64_t(gridDim.x) * TPW) {
+  for (int64_t base = int64_t(blockIdx.x) * TPB; base < a.count; base += int64_t(gridDim.x) * TPB) {
     const int64_t item = base + team;
     const bool valid = item < a.count;
     uint32_t code = valid ? a.bucket[item] : 0u;
@@ -231,7 +414,7 @@ __global__ void __launch_bounds__(64) k_store(StoreArgs a) {
     const int sa = swp ? s2 : s1, sb = swp ? s1 : s2;
     const int Ka = valid ? a.orb.nprim[sa] : 0, Kb = valid ? a.orb.nprim[sb] : 0;
     const int Kc = valid ? a.aux.nprim[sP] : 0;
-    const int npmax = wave_max(Ka * Kb * Kc);
+    const int npmax = TS >= 64 ? Ka * Kb * Kc : wave_max(Ka * Kb * Kc);
     const int64_t oa = valid ? a.orb.prim_off[sa] : 0, ob = valid ? a.orb.prim_off[sb] : 0,
                   oc = valid ? a.aux.prim_off[sP] : 0;
     double Ar[3] = {0, 0, 0}, Br[3] = {0, 0, 0}, Cr[3] = {0, 0, 0};
@@ -243,23 +426,17 @@ __global__ void __launch_bounds__(64) k_store(StoreArgs a) {
         Cr[x] = a.xyz[3 * ic + x];
       }
     }
-    triplet_to_e0P<LP, LA, LB, TS, PCH>(a.boys, S, tid, npmax, Ar, Br, Cr, Ka, a.orb.exps + oa,
-                                        a.orb.coefs + oa, Kb, a.orb.exps + ob, a.orb.coefs + ob,
-                                        Kc, a.aux.exps + oc, a.aux.coefs + oc, a.pure);
-    hrr_coefs<LA, LB>(HC, tid, TS, Ar, Br);
+    triplet_to_e0P<LP, LA, LB, TS, PCH>(a.boys, S, tid, slot, npmax, Ar, Br, Cr, Ka,
+                                        a.orb.exps + oa, a.orb.coefs + oa, Kb, a.orb.exps + ob,
+                                        a.orb.coefs + ob, Kc, a.aux.exps + oc, a.aux.coefs + oc,
+                                        a.pure);
+    hrr_block<LP, LA, LB, TS, PCH>(S, tid, Ar, Br, np_out, swp);
     team_sync();
     if (valid) {
       double *out = a.out + a.out_off[t];
+      const double *STG = S + LY::STG;
       const int nout = np_out * NA * NB;
-      for (int o = tid; o < nout; o += TS) {
-        const int m = o / (NA * NB), ab = o - m * (NA * NB);
-        const int ia = ab / NB, ib = ab - ia * NB;
-        double acc = 0.0;
-        const int16_t *ep = &h::e[ia * h::NHC];
-        for (int n = h::hc_start[ib]; n < h::hc_start[ib + 1]; ++n) acc += HC[n] * EM[m * G::NE + ep[n]];
-        const int dst = swp ? (m * NB + ib) * NA + ia : o;
-        out[dst] = acc;
-      }
+      for (int o = tid; o < nout; o += TS) out[o] = STG[o];
     }
     team_sync();
   }
@@ -272,22 +449,23 @@ __global__ void __launch_bounds__(64) k_store(StoreArgs a) {
 // team, so no atomics are needed; launches of different LP run in stream order.
 // ---------------------------------------------------------------------------
 template <int LP, int LA, int LB, int TS, int PCH>
-__global__ void __launch_bounds__(64) k_J(JArgs a) {
+__global__ void __launch_bounds__(TS > 64 ? TS : 64) k_J(JArgs a) {
   using G = Geo<LP, LA, LA + LB>;
-  using F = Foot<LP, LA, LB, PCH>;
-  constexpr int TPW = 64 / TS;
+  using LY = Layout<LP, LA, LB, PCH>;
+  constexpr int BLK = TS > 64 ? TS : 64;
+  constexpr int TPB = BLK / TS;
   constexpr int NA = ncart(LA), NB = ncart(LB);
   constexpr int NAB = NA * NB;
   constexpr int NACC = (NAB + TS - 1) / TS;
+  constexpr int NQ = (G::NPI + TS - 1) / TS;
   extern __shared__ double smem[];
   const int team = threadIdx.x / TS, tid = threadIdx.x % TS;
-  double *S = smem + team * F::TOTAL;
-  double *HC = S + F::R0 + F::R1;
-  double *EM = S + F::R0;
-  using h = GenHrr<LA, LB>;
+  double *S = smem + team * LY::TOTAL;
   const int np_out = a.pure ? npure(LP) : ncart(LP);
+  int slot[NQ];
+  make_slots<LP, LA, LB, TS>(slot, tid);
 
-  for (int64_t base = int64_t(blockIdx.x) * TPW; base < a.npair; base += int64_t(gridDim.x) * TPW) {
+  for (int64_t base = int64_t(blockIdx.x) * TPB; base < a.npair; base += int64_t(gridDim.x) * TPB) {
     const int64_t q = base + team;
     const bool valid = q < a.npair;
     int sa = 0, sb = 0;
@@ -337,31 +515,27 @@ __global__ void __launch_bounds__(64) k_J(JArgs a) {
     double acc[NACC];
 #pragma unroll
     for (int k = 0; k < NACC; ++k) acc[k] = 0.0;
-    hrr_coefs<LA, LB>(HC, tid, TS, Ar, Br);
     for (int ip = 0; ip < a.np; ++ip) {
       const int sP = a.psh[ip];
       const int Kc = a.aux.nprim[sP];
-      const int npmax = wave_max(Ka * Kb * Kc);
+      const int npmax = TS >= 64 ? Ka * Kb * Kc : wave_max(Ka * Kb * Kc);
       const int64_t oc = a.aux.prim_off[sP];
       const int ic = a.aux.atom[sP];
       const double Cr[3] = {a.xyz[3 * ic], a.xyz[3 * ic + 1], a.xyz[3 * ic + 2]};
-      triplet_to_e0P<LP, LA, LB, TS, PCH>(a.boys, S, tid, npmax, Ar, Br, Cr, Ka, a.orb.exps + oa,
-                                          a.orb.coefs + oa, Kb, a.orb.exps + ob,
-                                          a.orb.coefs + ob, Kc, a.aux.exps + oc,
-                                          a.aux.coefs + oc, a.pure);
+      triplet_to_e0P<LP, LA, LB, TS, PCH>(a.boys, S, tid, slot, npmax, Ar, Br, Cr, Ka,
+                                          a.orb.exps + oa, a.orb.coefs + oa, Kb,
+                                          a.orb.exps + ob, a.orb.coefs + ob, Kc,
+                                          a.aux.exps + oc, a.aux.coefs + oc, a.pure);
+      hrr_block<LP, LA, LB, TS, PCH>(S, tid, Ar, Br, np_out, false);
+      team_sync();
+      const double *STG = S + LY::STG;
       const double *dP = a.d + a.aux_off[sP];
 #pragma unroll
       for (int k = 0; k < NACC; ++k) {
         const int ab = tid + k * TS;
         if (ab < NAB) {
-          const int ia = ab / NB, ib = ab - ia * NB;
-          const int16_t *ep = &h::e[ia * h::NHC];
           double s = acc[k];
-          for (int m = 0; m < np_out; ++m) {
-            double v = 0.0;
-            for (int n = h::hc_start[ib]; n < h::hc_start[ib + 1]; ++n) v += HC[n] * EM[m * G::NE + ep[n]];
-            s += v * dP[m];
-          }
+          for (int m = 0; m < np_out; ++m) s += STG[m * NAB + ab] * dP[m];
           acc[k] = s;
         }
       }

@@ -7,32 +7,10 @@ namespace df3c {
 
 struct ClassInfo {
   int ts = 0;         // lanes per team
-  int tpw = 0;        // teams per wavefront (= workgroup)
+  int tpw = 0;        // teams per workgroup
   int lds = 0;        // dynamic LDS bytes per workgroup
   hipError_t (*store)(const StoreArgs &, int, hipStream_t) = nullptr;
   hipError_t (*jfn)(const JArgs &, int, hipStream_t) = nullptr;
-};
-
-// Team size and primitive chunk per class: small classes run one triplet per
-// lane (or per few lanes), large ones one triplet per wavefront.
-template <int LP, int LA, int LB>
-struct Cfg {
-  using G = Geo<LP, LA, LA + LB>;
-  static constexpr int work = G::NPI + G::NE * G::NCP + G::NPURE * G::NE +
-                              G::NPURE * ncart(LA) * ncart(LB);
-  static constexpr int TS0 = work >= 1024 ? 64 : work >= 256 ? 16 : work >= 48 ? 4 : 1;
-  static constexpr int PCH0 = TS0 >= 16 ? 4 : TS0 == 4 ? 2 : 1;
-  // keep the workgroup's LDS within the 160 KiB of a CU
-  static constexpr int lds_of(int ts, int pch) {
-    return (64 / ts) * (imax(pch * (PS_N + G::NV1 + G::NSW), G::NE * G::NCP) +
-                        imax(G::NPI, G::NPURE * G::NE) + GenHrr<LA, LB>::NHC) * 8;
-  }
-  static constexpr int TS = lds_of(TS0, PCH0) <= 160 * 1024 ? TS0
-                            : lds_of(imin(64, TS0 * 4), PCH0) <= 160 * 1024 ? imin(64, TS0 * 4)
-                                                                           : 64;
-  static constexpr int PCH = lds_of(TS, PCH0) <= 160 * 1024 ? PCH0 : 1;
-  static constexpr int LDS = (64 / TS) * Foot<LP, LA, LB, PCH>::TOTAL * 8;
-  static_assert(LDS <= 160 * 1024, "class does not fit the LDS of a CU");
 };
 
 template <int LP, int LA, int LB>
@@ -42,7 +20,7 @@ hipError_t launch_store(const StoreArgs &a, int grid, hipStream_t s) {
   static const hipError_t attr = hipFuncSetAttribute(
       reinterpret_cast<const void *>(kern), hipFuncAttributeMaxDynamicSharedMemorySize, C::LDS);
   if (attr != hipSuccess) return attr;
-  hipLaunchKernelGGL(kern, dim3(grid), dim3(64), C::LDS, s, a);
+  hipLaunchKernelGGL(kern, dim3(grid), dim3(C::BLK), C::LDS, s, a);
   return hipGetLastError();
 }
 
@@ -53,7 +31,7 @@ hipError_t launch_J(const JArgs &a, int grid, hipStream_t s) {
   static const hipError_t attr = hipFuncSetAttribute(
       reinterpret_cast<const void *>(kern), hipFuncAttributeMaxDynamicSharedMemorySize, C::LDS);
   if (attr != hipSuccess) return attr;
-  hipLaunchKernelGGL(kern, dim3(grid), dim3(64), C::LDS, s, a);
+  hipLaunchKernelGGL(kern, dim3(grid), dim3(C::BLK), C::LDS, s, a);
   return hipGetLastError();
 }
 
@@ -62,7 +40,7 @@ ClassInfo class_info() {
   using C = Cfg<LP, LA, LB>;
   ClassInfo c;
   c.ts = C::TS;
-  c.tpw = 64 / C::TS;
+  c.tpw = C::BLK / C::TS;
   c.lds = C::LDS;
   c.store = &launch_store<LP, LA, LB>;
   c.jfn = &launch_J<LP, LA, LB>;

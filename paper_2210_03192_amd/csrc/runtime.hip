@@ -105,9 +105,13 @@ __global__ void k_zero_f64(double *p, int64_t n) {
     p[i] = 0.0;
 }
 
-// class of every triplet; hist[NCLS] counts, err[0] flags bad input
+// class of every triplet; hist[NCLS] counts (aggregated per workgroup in LDS),
+// err[0] flags bad input
 __global__ void k_classify(const int32_t *trip, int64_t ntrip, const int32_t *laux, int32_t naux,
                            const int32_t *lorb, int32_t norb, uint8_t *cls, int *hist, int *err) {
+  __shared__ int h[NCLS];
+  for (int i = threadIdx.x; i < NCLS; i += blockDim.x) h[i] = 0;
+  __syncthreads();
   for (int64_t t = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; t < ntrip;
        t += int64_t(gridDim.x) * blockDim.x) {
     const int P = trip[3 * t], a = trip[3 * t + 1], b = trip[3 * t + 2];
@@ -126,8 +130,11 @@ __global__ void k_classify(const int32_t *trip, int64_t ntrip, const int32_t *la
     const int hi = la >= lb ? la : lb, lo = la >= lb ? lb : la;
     const int c = (lp * NLA + hi) * NLA + lo;
     cls[t] = uint8_t(c);
-    atomicAdd(&hist[c], 1);
+    atomicAdd(&h[c], 1);
   }
+  __syncthreads();
+  for (int i = threadIdx.x; i < NCLS; i += blockDim.x)
+    if (h[i]) atomicAdd(&hist[i], h[i]);
 }
 
 // exclusive scan of hist into cursor (one thread; NCLS is small)
@@ -160,15 +167,31 @@ __device__ __forceinline__ double shell_tightness(const ShellsDev &b, int s) {
 
 __global__ void k_scatter(const int32_t *trip, int64_t ntrip, const int32_t *lorb, ShellsDev orb,
                           const uint8_t *cls, int *cursor, uint32_t *bucket) {
-  for (int64_t t = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; t < ntrip;
-       t += int64_t(gridDim.x) * blockDim.x) {
-    const int c = cls[t];
-    if (c == 255) continue;
-    const int a = trip[3 * t + 1], b = trip[3 * t + 2];
-    const int la = lorb[a], lb = lorb[b];
-    const bool swp = la < lb || (la == lb && shell_tightness(orb, b) > shell_tightness(orb, a));
-    const uint32_t code = uint32_t(t) | (swp ? 0x80000000u : 0u);
-    bucket[atomicAdd(&cursor[c], 1)] = code;
+  // per round of blockDim.x triplets: rank inside the workgroup from LDS
+  // atomics, one global reservation per class and workgroup
+  __shared__ int h[NCLS], base[NCLS];
+  for (int64_t t0 = blockIdx.x * int64_t(blockDim.x); t0 < ntrip;
+       t0 += int64_t(gridDim.x) * blockDim.x) {
+    for (int i = threadIdx.x; i < NCLS; i += blockDim.x) h[i] = 0;
+    __syncthreads();
+    const int64_t t = t0 + threadIdx.x;
+    const int c = t < ntrip ? cls[t] : 255;
+    int rank = 0;
+    uint32_t code = 0;
+    if (c != 255) {
+      const int a = trip[3 * t + 1], b = trip[3 * t + 2];
+      const int la = lorb[a], lb = lorb[b];
+      const bool swp =
+          la < lb || (la == lb && shell_tightness(orb, b) > shell_tightness(orb, a));
+      code = uint32_t(t) | (swp ? 0x80000000u : 0u);
+      rank = atomicAdd(&h[c], 1);
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < NCLS; i += blockDim.x)
+      if (h[i]) base[i] = atomicAdd(&cursor[i], h[i]);
+    __syncthreads();
+    if (c != 255) bucket[base[c] + rank] = code;
+    __syncthreads();
   }
 }
 
