@@ -53,6 +53,8 @@ extern "C" {
 /* Limits of this build. */
 #define DF3C_LMAX_ORB 4  /* orbital shells: s..g */
 #define DF3C_LMAX_AUX 6  /* auxiliary shells: s..i */
+#define DF3C_LMAX_GRAD_ORB 3  /* orbital shells in df3c_coulomb_J_grad: s..f */
+#define DF3C_KMAX 64          /* primitives per shell */
 
 /* flags */
 #define DF3C_FLAG_NONE 0u
@@ -83,7 +85,9 @@ size_t df3c_eval_batch_workspace(int64_t ntrip);
 /* (P|ab) blocks for a batch of shell triplets (Section 2.5.1; the batch may mix
  * classes and is unordered, Section 3).
  *   xyz      DEVICE [natom][3] centres
- *   aux, orb bases of P and of a, b (orb->pure must be 0)
+ *   aux, orb bases of P and of a, b (orb->pure must be 0); every shell's atom
+ *            index must lie in [0, natom) and 1 <= nprim <= DF3C_KMAX
+ *            (checked on the device; DF3C_E_ARG otherwise)
  *   trip     DEVICE [ntrip][3] = (P, a, b) shell indices
  *   out_off  DEVICE [ntrip] offset (in doubles) of each block in out
  *   out      DEVICE output; block t is npure(l_P) x ncart(l_a) x ncart(l_b)
@@ -91,7 +95,8 @@ size_t df3c_eval_batch_workspace(int64_t ntrip);
  *   ws       DEVICE workspace of at least df3c_eval_batch_workspace(ntrip) bytes
  * Shell indices in trip are checked on the device; the call synchronises
  * `stream` once to plan the per-class launches. */
-int df3c_eval_batch(const double *xyz, const df3c_shells *aux, const df3c_shells *orb,
+int df3c_eval_batch(const double *xyz, int32_t natom, const df3c_shells *aux,
+                    const df3c_shells *orb,
                     int64_t ntrip, const int32_t *trip, const int64_t *out_off, double *out,
                     void *ws, size_t ws_bytes, uint32_t flags, void *stream);
 
@@ -99,12 +104,33 @@ int df3c_eval_batch(const double *xyz, const df3c_shells *aux, const df3c_shells
 size_t df3c_coulomb_J_workspace(const df3c_shells *aux, const df3c_shells *orb);
 
 /* J_ab = sum_P (ab|P) d_P over all orbital shell pairs (DF-J, Section 3).
+ *   xyz, natom, aux, orb as for df3c_eval_batch
  *   d   DEVICE [naux] fitting coefficients, aux function order
  *   J   DEVICE [nao][nao] output, overwritten, both triangles written
  *   ws  DEVICE workspace of at least df3c_coulomb_J_workspace bytes */
-int df3c_coulomb_J(const double *xyz, const df3c_shells *aux, const df3c_shells *orb,
-                   const double *d, double *J, void *ws, size_t ws_bytes, uint32_t flags,
-                   void *stream);
+int df3c_coulomb_J(const double *xyz, int32_t natom, const df3c_shells *aux,
+                   const df3c_shells *orb, const double *d, double *J, void *ws, size_t ws_bytes,
+                   uint32_t flags, void *stream);
+
+/* Bytes of workspace df3c_coulomb_J_grad needs (depends on the current device's
+ * CU count). */
+size_t df3c_coulomb_J_grad_workspace(const df3c_shells *aux, const df3c_shells *orb,
+                                     int32_t natom);
+
+/* Nuclear gradient of L = sum_ab G_ab J_ab with J from df3c_coulomb_J, d and G
+ * held fixed (the backward of the DF-J build; not in the paper).  Derivative
+ * integrals come from raising and lowering the bra angular momentum,
+ * d/dA (ab|P) = (a+1 b|P)^{2 zeta_a} - a (a-1 b|P) and likewise for B; the aux
+ * centre follows from translational invariance.  Integrals are recomputed.
+ *   xyz, natom, aux, orb, d as for df3c_coulomb_J
+ *   G      DEVICE [nao][nao] = dL/dJ (need not be symmetric)
+ *   grad   DEVICE [natom][3] output, overwritten
+ * Orbital shells up to DF3C_LMAX_GRAD_ORB.  The result is bitwise reproducible
+ * (fixed-order reductions).  Returns DF3C_E_UNSUPPORTED when natom is too large
+ * for the per-team LDS accumulators (about 1500 atoms). */
+int df3c_coulomb_J_grad(const double *xyz, int32_t natom, const df3c_shells *aux,
+                        const df3c_shells *orb, const double *d, const double *G, double *grad,
+                        void *ws, size_t ws_bytes, uint32_t flags, void *stream);
 
 /* Readable name of a status code (static string). */
 const char *df3c_status_string(int status);

@@ -27,8 +27,23 @@ def _sources():
     return sorted(f for f in os.listdir(CSRC) if f.endswith(".hip"))
 
 
-def _compile(src, verbose):
+def _newest_header():
+    paths = [os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith(".hpp")]
+    gen = os.path.join(CSRC, "gen")
+    if os.path.isdir(gen):
+        paths += [os.path.join(gen, f) for f in os.listdir(gen) if f.endswith(".hpp")]
+    return max(os.path.getmtime(p) for p in paths)
+
+
+def _compile(src, verbose, force=True):
     obj = os.path.join(OBJ, src.replace(".hip", ".o"))
+    if not force and os.path.exists(obj):
+        t = os.path.getmtime(obj)
+        deps = [_newest_header()]
+        if src == "runtime.hip":
+            deps.append(os.path.getmtime(os.path.join(HERE, "..", "include", "df3c.h")))
+        if t > os.path.getmtime(os.path.join(CSRC, src)) and t > max(deps):
+            return obj, ""
     cmd = ["hipcc", *HIPCC_FLAGS, "-I", CSRC, "-c", os.path.join(CSRC, src), "-o", obj]
     if verbose:
         print(" ".join(cmd), flush=True)
@@ -40,7 +55,8 @@ def _compile(src, verbose):
     return obj, msgs
 
 
-def build(verbose: bool = False, jobs: int = 0) -> str:
+def build(verbose: bool = False, jobs: int = 0, force: bool = True) -> str:
+    """Compile and link; force=False reuses objects newer than their sources."""
     subprocess.run([sys.executable, os.path.join(CSRC, "gen_tables.py"),
                     os.path.join(CSRC, "gen")], check=True)
     os.makedirs(OBJ, exist_ok=True)
@@ -48,7 +64,7 @@ def build(verbose: bool = False, jobs: int = 0) -> str:
     jobs = jobs or min(len(srcs), max(1, (os.cpu_count() or 4)))
     objs = []
     with cf.ThreadPoolExecutor(jobs) as ex:
-        for obj, msgs in ex.map(lambda s: _compile(s, verbose), srcs):
+        for obj, msgs in ex.map(lambda s: _compile(s, verbose, force), srcs):
             objs.append(obj)
             if msgs and verbose:
                 print(msgs, flush=True)
@@ -62,4 +78,4 @@ def build(verbose: bool = False, jobs: int = 0) -> str:
 
 
 if __name__ == "__main__":
-    build(verbose=True)
+    build(verbose=True, force="--incremental" not in sys.argv)

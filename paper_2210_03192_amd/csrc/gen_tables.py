@@ -253,12 +253,24 @@ def arr(ctype, name, vals):
     return f"  static constexpr {ctype} {name}[{len(vals)}] = {{{body}}};\n"
 
 
+def _write_if_changed(path, text):
+    """Keep the timestamp of unchanged headers so incremental builds stay valid."""
+    if os.path.exists(path):
+        with open(path) as f:
+            if f.read() == text:
+                return
+    with open(path, "w") as f:
+        f.write(text)
+
+
 def geometries():
-    """(LP, EA, EB) of every class: plain (EA = la, EB = la + lb)."""
+    """(LP, EA, EB) = (L_P, l_a, l_a + l_b) of every (l_a, l_b) pair up to the
+    orbital limit, in both orders: the forward classes use l_a >= l_b, the
+    derivative classes also need the raised / lowered pairs."""
     out = set()
     for LP in range(LMAX_AUX + 1):
         for la in range(LMAX_ORB + 1):
-            for lb in range(la + 1):
+            for lb in range(LMAX_ORB + 1):
                 out.add((LP, la, la + lb))
     return sorted(out)
 
@@ -285,8 +297,7 @@ def write(outdir):
             s.append(arr("int32_t", "cb_w", w))
             s.append("};\n")
         s.append("}  // namespace df3c\n")
-        with open(os.path.join(outdir, f"tables_lp{LP}.hpp"), "w") as f:
-            f.write("".join(s))
+        _write_if_changed(os.path.join(outdir, f"tables_lp{LP}.hpp"), "".join(s))
     s = ["// generated by gen_tables.py -- do not edit\n#pragma once\n#include <cstdint>\n",
          "namespace df3c {\n"]
     for l in range(LMAX_AUX + 1):
@@ -322,8 +333,7 @@ def write(outdir):
         s.append(arr("VI", "it", ["{" + ",".join(str(x) for x in t) + "}" for t in items]))
         s.append("};\n")
     s.append("}  // namespace df3c\n")
-    with open(os.path.join(outdir, "tables_common.hpp"), "w") as f:
-        f.write("".join(s))
+    _write_if_changed(os.path.join(outdir, "tables_common.hpp"), "".join(s))
 
 
 if __name__ == "__main__":

@@ -1,0 +1,4 @@
+// Backward (J-gradient) kernels of all classes with an auxiliary shell of
+// l = 6 (one translation unit per l so the build parallelises).
+#include "registry.hpp"
+DF3C_REGISTER_GRAD_LP(6, register_grad_lp6)

@@ -114,7 +114,10 @@ __device__ __forceinline__ int pi_slot(int r) {
 // ---------------------------------------------------------------------------
 // The per-triplet pipeline up to (e0|P) in LDS (region EM of the layout).
 // ---------------------------------------------------------------------------
-template <int LP, int LA, int LB, int TS, int PCH>
+// WM selects the contraction weights: 0 -> c_a c_b c_c, 1 -> 2 zeta_a c_a c_b c_c,
+// 2 -> 2 zeta_b c_a c_b c_c (the raised bra of the derivative integrals).  slot is
+// the per-lane prerequisite map of make_slots, or nullptr to decode it inline.
+template <int LP, int LA, int LB, int TS, int PCH, int WM = 0>
 __device__ __forceinline__ void triplet_to_e0P(const double *btab, double *S, int tid,
                                                const int *slot, int npmax, const double *A,
                                                const double *B, const double *C, int Ka,
@@ -155,8 +158,10 @@ __device__ __forceinline__ void triplet_to_e0P(const double *btab, double *S, in
       const double rho = g * zc / gz;
       const double T = rho * (PCx * PCx + PCy * PCy + PCz * PCz);
       // 2 pi^{5/2} / ((g+zc)^{1/2} g zc) exp(-za zb/g AB^2) x contraction coefficients
-      const double pre = 34.98683665524972497 / (sqrt(gz) * g * zc) * exp(-za * zb * ig * AB2) *
-                         (ca[ia] * cb[ib] * cc[ic]);
+      double pre = 34.98683665524972497 / (sqrt(gz) * g * zc) * exp(-za * zb * ig * AB2) *
+                   (ca[ia] * cb[ib] * cc[ic]);
+      if constexpr (WM == 1) pre *= 2.0 * za;
+      if constexpr (WM == 2) pre *= 2.0 * zb;
       double Fm[L + 1];
       boys<LP, L + 1>(btab, T, Fm);
       double *R = prims + pp * REC;
@@ -201,7 +206,8 @@ __device__ __forceinline__ void triplet_to_e0P(const double *btab, double *S, in
     // ---- early contraction of the CVRR2 prerequisites (register accumulators)
 #pragma unroll
     for (int q = 0; q < NQ; ++q) {
-      const int code = slot[q];
+      const int r = tid + q * TS;
+      const int code = slot ? slot[q] : (r < G::NPI ? pi_slot<G>(r) : -1);
       if (code >= 0) {
         const int isw = G::NV1 + (code >> 16), iv = code & 0xffff;
         double a = acc[q];
@@ -216,7 +222,7 @@ __device__ __forceinline__ void triplet_to_e0P(const double *btab, double *S, in
   }
 #pragma unroll
   for (int q = 0; q < NQ; ++q)
-    if (slot[q] >= 0) PI[tid + q * TS] = acc[q];
+    if (tid + q * TS < G::NPI) PI[tid + q * TS] = acc[q];
   team_sync();
   // ---- n-quantal CVRR2 in place on pi_0: (e0|c) += sum_{u != 0} w pi_{|u|}(e-u, c-u)
   for (int t = tid; t < TB::NTGT; t += TS) {

@@ -1,7 +1,7 @@
 // Per-class launch configuration and the launcher table shared by the
 // instantiation units and the runtime.
 #pragma once
-#include "kernels.hpp"
+#include "grad.hpp"
 
 namespace df3c {
 
@@ -11,6 +11,12 @@ struct ClassInfo {
   int lds = 0;        // dynamic LDS bytes per workgroup
   hipError_t (*store)(const StoreArgs &, int, hipStream_t) = nullptr;
   hipError_t (*jfn)(const JArgs &, int, hipStream_t) = nullptr;
+};
+
+struct GradInfo {
+  int tpb = 0;        // teams per workgroup
+  int team = 0;       // LDS doubles per team before the per-atom array
+  hipError_t (*gfn)(const GradArgs &, int, int, hipStream_t) = nullptr;  // (args, grid, lds)
 };
 
 template <int LP, int LA, int LB>
@@ -36,6 +42,27 @@ hipError_t launch_J(const JArgs &a, int grid, hipStream_t s) {
 }
 
 template <int LP, int LA, int LB>
+hipError_t launch_grad(const GradArgs &a, int grid, int lds, hipStream_t s) {
+  using C = GradCfg<LP, LA, LB>;
+  auto kern = k_grad<LP, LA, LB, C::TS, C::PCH>;
+  static const hipError_t attr = hipFuncSetAttribute(
+      reinterpret_cast<const void *>(kern), hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+  if (attr != hipSuccess) return attr;
+  hipLaunchKernelGGL(kern, dim3(grid), dim3(C::BLK), lds, s, a);
+  return hipGetLastError();
+}
+
+template <int LP, int LA, int LB>
+GradInfo grad_info() {
+  using C = GradCfg<LP, LA, LB>;
+  GradInfo g;
+  g.tpb = C::TPB;
+  g.team = C::TEAM;
+  g.gfn = &launch_grad<LP, LA, LB>;
+  return g;
+}
+
+template <int LP, int LA, int LB>
 ClassInfo class_info() {
   using C = Cfg<LP, LA, LB>;
   ClassInfo c;
@@ -48,6 +75,7 @@ ClassInfo class_info() {
 }
 
 constexpr int NLP = 7, NLA = 5;  // LP <= 6, la, lb <= 4
+constexpr int NLG = 4;           // gradient: la, lb <= 3
 // filled by inst_lp<LP>.hip
 void register_lp0(ClassInfo (&t)[NLA][NLA]);
 void register_lp1(ClassInfo (&t)[NLA][NLA]);
@@ -56,6 +84,13 @@ void register_lp3(ClassInfo (&t)[NLA][NLA]);
 void register_lp4(ClassInfo (&t)[NLA][NLA]);
 void register_lp5(ClassInfo (&t)[NLA][NLA]);
 void register_lp6(ClassInfo (&t)[NLA][NLA]);
+void register_grad_lp0(GradInfo (&t)[NLG][NLG]);
+void register_grad_lp1(GradInfo (&t)[NLG][NLG]);
+void register_grad_lp2(GradInfo (&t)[NLG][NLG]);
+void register_grad_lp3(GradInfo (&t)[NLG][NLG]);
+void register_grad_lp4(GradInfo (&t)[NLG][NLG]);
+void register_grad_lp5(GradInfo (&t)[NLG][NLG]);
+void register_grad_lp6(GradInfo (&t)[NLG][NLG]);
 
 }  // namespace df3c
 
@@ -77,5 +112,21 @@ void register_lp6(ClassInfo (&t)[NLA][NLA]);
     t[4][2] = class_info<LPV, 4, 2>();                              \
     t[4][3] = class_info<LPV, 4, 3>();                              \
     t[4][4] = class_info<LPV, 4, 4>();                              \
+  }                                                                 \
+  }
+
+#define DF3C_REGISTER_GRAD_LP(LPV, FN)                              \
+  namespace df3c {                                                  \
+  void FN(GradInfo (&t)[NLG][NLG]) {                                \
+    t[0][0] = grad_info<LPV, 0, 0>();                               \
+    t[1][0] = grad_info<LPV, 1, 0>();                               \
+    t[1][1] = grad_info<LPV, 1, 1>();                               \
+    t[2][0] = grad_info<LPV, 2, 0>();                               \
+    t[2][1] = grad_info<LPV, 2, 1>();                               \
+    t[2][2] = grad_info<LPV, 2, 2>();                               \
+    t[3][0] = grad_info<LPV, 3, 0>();                               \
+    t[3][1] = grad_info<LPV, 3, 1>();                               \
+    t[3][2] = grad_info<LPV, 3, 2>();                               \
+    t[3][3] = grad_info<LPV, 3, 3>();                               \
   }                                                                 \
   }

@@ -25,6 +25,7 @@ struct DevState {
 DevState g_dev[MAX_DEV];
 std::mutex g_mu;
 ClassInfo g_cls[NLP][NLA][NLA];
+GradInfo g_grad[NLP][NLG][NLG];
 bool g_cls_ready = false;
 int *g_pinned = nullptr;  // host readback buffer
 
@@ -57,6 +58,13 @@ void register_all() {
   register_lp4(t[4]);
   register_lp5(t[5]);
   register_lp6(t[6]);
+  register_grad_lp0(g_grad[0]);
+  register_grad_lp1(g_grad[1]);
+  register_grad_lp2(g_grad[2]);
+  register_grad_lp3(g_grad[3]);
+  register_grad_lp4(g_grad[4]);
+  register_grad_lp5(g_grad[5]);
+  register_grad_lp6(g_grad[6]);
   g_cls_ready = true;
 }
 
@@ -103,6 +111,22 @@ __global__ void k_zero_f64(double *p, int64_t n) {
   for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < n;
        i += int64_t(gridDim.x) * blockDim.x)
     p[i] = 0.0;
+}
+
+// shell descriptors: contraction degree and centre index in range
+__global__ void k_check_shells(const int32_t *nprim, const int64_t *prim_off, const int32_t *atom,
+                               int32_t n, int32_t natom, int *err) {
+  for (int s = blockIdx.x * blockDim.x + threadIdx.x; s < n; s += gridDim.x * blockDim.x)
+    if (nprim[s] < 1 || nprim[s] > DF3C_KMAX || prim_off[s] < 0 || atom[s] < 0 ||
+        atom[s] >= natom)
+      atomicOr(err, 4);
+}
+
+void check_shells(const df3c_shells *b, int natom, int *err, hipStream_t s) {
+  if (b->nshell <= 0) return;
+  const int g = std::min((b->nshell + 255) / 256, 1024);
+  hipLaunchKernelGGL(k_check_shells, dim3(g), dim3(256), 0, s, b->nprim, b->prim_off, b->atom,
+                     b->nshell, natom, err);
 }
 
 // class of every triplet; hist[NCLS] counts (aggregated per workgroup in LDS),
@@ -195,6 +219,15 @@ __global__ void k_scatter(const int32_t *trip, int64_t ntrip, const int32_t *lor
   }
 }
 
+// grad[x] = sum over team partials, in a fixed order (bitwise reproducible)
+__global__ void k_reduce_partial(const double *partial, int nslot, int n, double *grad) {
+  for (int x = blockIdx.x * blockDim.x + threadIdx.x; x < n; x += gridDim.x * blockDim.x) {
+    double s = 0.0;
+    for (int k = 0; k < nslot; ++k) s += partial[int64_t(k) * n + x];
+    grad[x] = s;
+  }
+}
+
 int grid_for(int64_t items, int tpw, int ncu) {
   const int64_t need = (items + tpw - 1) / tpw;
   const int64_t cap = int64_t(ncu) * 64;
@@ -230,13 +263,15 @@ size_t df3c_eval_batch_workspace(int64_t ntrip) {
          align256(sizeof(uint32_t) * size_t(ntrip));
 }
 
-int df3c_eval_batch(const double *xyz, const df3c_shells *aux, const df3c_shells *orb,
-                    int64_t ntrip, const int32_t *trip, const int64_t *out_off, double *out,
-                    void *ws, size_t ws_bytes, uint32_t flags, void *stream) {
+int df3c_eval_batch(const double *xyz, int32_t natom, const df3c_shells *aux,
+                    const df3c_shells *orb, int64_t ntrip, const int32_t *trip,
+                    const int64_t *out_off, double *out, void *ws, size_t ws_bytes, uint32_t flags,
+                    void *stream) {
   (void)flags;
   if (ntrip < 0 || ntrip > 0x7fffffff) return DF3C_E_ARG;
   if (ntrip == 0) return DF3C_OK;
-  if (!xyz || !shells_ok(aux) || !shells_ok(orb) || !trip || !out_off || !out) return DF3C_E_ARG;
+  if (!xyz || natom <= 0 || !shells_ok(aux) || !shells_ok(orb) || !trip || !out_off || !out)
+    return DF3C_E_ARG;
   if (orb->pure != 0 || (aux->pure != 0 && aux->pure != 1)) return DF3C_E_UNSUPPORTED;
   if (!ws || ws_bytes < df3c_eval_batch_workspace(ntrip)) return DF3C_E_WORKSPACE;
   DevState *ds = nullptr;
@@ -254,17 +289,20 @@ int df3c_eval_batch(const double *xyz, const df3c_shells *aux, const df3c_shells
 
   const int g = int(std::min<int64_t>((ntrip + 255) / 256, 4096));
   hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(256), 0, s, hist, 2 * NCLS + 8, 0);
+  check_shells(aux, natom, err, s);
+  check_shells(orb, natom, err, s);
   hipLaunchKernelGGL(k_classify, dim3(g), dim3(256), 0, s, trip, ntrip, aux->l, aux->nshell,
                      orb->l, orb->nshell, cls, hist, err);
-  hipLaunchKernelGGL(k_scan, dim3(1), dim3(64), 0, s, hist, cursor);
-  hipLaunchKernelGGL(k_scatter, dim3(g), dim3(256), 0, s, trip, ntrip, orb->l, dev_shells(orb),
-                     cls, cursor, bucket);
   if (hipMemcpyAsync(g_pinned, hist, sizeof(int) * NCLS, hipMemcpyDeviceToHost, s) != hipSuccess ||
       hipMemcpyAsync(g_pinned + NCLS, err, sizeof(int), hipMemcpyDeviceToHost, s) != hipSuccess ||
       hipStreamSynchronize(s) != hipSuccess)
     return DF3C_E_HIP;
-  if (g_pinned[NCLS] & 1) return DF3C_E_ARG;
+  // nothing that dereferences shell data runs before the descriptors are checked
+  if (g_pinned[NCLS] & 5) return DF3C_E_ARG;
   if (g_pinned[NCLS] & 2) return DF3C_E_UNSUPPORTED;
+  hipLaunchKernelGGL(k_scan, dim3(1), dim3(64), 0, s, hist, cursor);
+  hipLaunchKernelGGL(k_scatter, dim3(g), dim3(256), 0, s, trip, ntrip, orb->l, dev_shells(orb),
+                     cls, cursor, bucket);
   int counts[NCLS];
   std::memcpy(counts, g_pinned, sizeof(counts));
   if (aux->pure == 0)
@@ -334,7 +372,7 @@ int make_plan(const df3c_shells *aux, const df3c_shells *orb, JPlan &p) {
 }
 
 size_t jplan_bytes(int64_t norb, int64_t naux) {
-  return align256(sizeof(int32_t) * norb) + align256(sizeof(int32_t) * naux) +
+  return align256(sizeof(int) * 8) + align256(sizeof(int32_t) * norb) + align256(sizeof(int32_t) * naux) +
          align256(sizeof(int64_t) * (norb + 1)) + align256(sizeof(int64_t) * (naux + 1));
 }
 }  // namespace
@@ -344,11 +382,11 @@ size_t df3c_coulomb_J_workspace(const df3c_shells *aux, const df3c_shells *orb) 
   return jplan_bytes(orb->nshell, aux->nshell);
 }
 
-int df3c_coulomb_J(const double *xyz, const df3c_shells *aux, const df3c_shells *orb,
-                   const double *d, double *J, void *ws, size_t ws_bytes, uint32_t flags,
-                   void *stream) {
+int df3c_coulomb_J(const double *xyz, int32_t natom, const df3c_shells *aux,
+                   const df3c_shells *orb, const double *d, double *J, void *ws, size_t ws_bytes,
+                   uint32_t flags, void *stream) {
   (void)flags;
-  if (!xyz || !shells_ok(aux) || !shells_ok(orb) || !d || !J) return DF3C_E_ARG;
+  if (!xyz || natom <= 0 || !shells_ok(aux) || !shells_ok(orb) || !d || !J) return DF3C_E_ARG;
   if (orb->pure != 0 || (aux->pure != 0 && aux->pure != 1)) return DF3C_E_UNSUPPORTED;
   if (!ws || ws_bytes < df3c_coulomb_J_workspace(aux, orb)) return DF3C_E_WORKSPACE;
   DevState *ds = nullptr;
@@ -359,6 +397,8 @@ int df3c_coulomb_J(const double *xyz, const df3c_shells *aux, const df3c_shells 
   if (rc) return rc;
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   char *w = static_cast<char *>(ws);
+  int *err = reinterpret_cast<int *>(w);
+  w += align256(sizeof(int) * 8);
   int32_t *orb_sorted = reinterpret_cast<int32_t *>(w);
   w += align256(sizeof(int32_t) * orb->nshell);
   int32_t *aux_sorted = reinterpret_cast<int32_t *>(w);
@@ -375,8 +415,14 @@ int df3c_coulomb_J(const double *xyz, const df3c_shells *aux, const df3c_shells 
       hipMemcpyAsync(aux_off, p.aux_off.data(), sizeof(int64_t) * (aux->nshell + 1),
                      hipMemcpyHostToDevice, s) != hipSuccess)
     return DF3C_E_HIP;
+  hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, s, err, 1, 0);
+  check_shells(aux, natom, err, s);
+  check_shells(orb, natom, err, s);
+  if (hipMemcpyAsync(g_pinned, err, sizeof(int), hipMemcpyDeviceToHost, s) != hipSuccess)
+    return DF3C_E_HIP;
   // the host vectors must outlive the asynchronous copies
   if (hipStreamSynchronize(s) != hipSuccess) return DF3C_E_HIP;
+  if (g_pinned[0]) return DF3C_E_ARG;
   const int64_t nJ = p.nao * p.nao;
   hipLaunchKernelGGL(k_zero_f64, dim3(int(std::min<int64_t>((nJ + 255) / 256, 4096))), dim3(256),
                      0, s, J, nJ);
@@ -411,6 +457,121 @@ int df3c_coulomb_J(const double *xyz, const df3c_shells *aux, const df3c_shells 
         if (ci.jfn(a, grid_for(a.npair, ci.tpw, ds->ncu), s) != hipSuccess) return DF3C_E_HIP;
       }
   }
+  return DF3C_OK;
+}
+
+
+// ----------------------------------------------------------------- J gradient
+namespace {
+constexpr int GRAD_GRID_PER_CU = 4;     // workgroups per CU of every gradient launch
+constexpr int GRAD_MAX_TPB = 4;         // teams per workgroup of the gradient kernels
+int grad_slots(int ncu) { return ncu * GRAD_GRID_PER_CU * GRAD_MAX_TPB; }
+}  // namespace
+
+size_t df3c_coulomb_J_grad_workspace(const df3c_shells *aux, const df3c_shells *orb,
+                                     int32_t natom) {
+  if (!aux || !orb || natom < 0) return 0;
+  int dev = 0, ncu = 256;
+  if (hipGetDevice(&dev) == hipSuccess) {
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, dev) == hipSuccess) ncu = prop.multiProcessorCount;
+  }
+  return jplan_bytes(orb->nshell, aux->nshell) +
+         align256(sizeof(double) * size_t(grad_slots(ncu)) * 3 * size_t(natom));
+}
+
+int df3c_coulomb_J_grad(const double *xyz, int32_t natom, const df3c_shells *aux,
+                        const df3c_shells *orb, const double *d, const double *G, double *grad,
+                        void *ws, size_t ws_bytes, uint32_t flags, void *stream) {
+  (void)flags;
+  if (!xyz || natom <= 0 || !shells_ok(aux) || !shells_ok(orb) || !d || !G || !grad)
+    return DF3C_E_ARG;
+  if (orb->pure != 0 || (aux->pure != 0 && aux->pure != 1)) return DF3C_E_UNSUPPORTED;
+  DevState *ds = nullptr;
+  int rc = init_device(&ds);
+  if (rc) return rc;
+  const int nslot = grad_slots(ds->ncu);
+  const size_t need = jplan_bytes(orb->nshell, aux->nshell) +
+                      align256(sizeof(double) * size_t(nslot) * 3 * size_t(natom));
+  if (!ws || ws_bytes < need) return DF3C_E_WORKSPACE;
+  JPlan p;
+  rc = make_plan(aux, orb, p);
+  if (rc) return rc;
+  for (int l = DF3C_LMAX_GRAD_ORB + 1; l <= DF3C_LMAX_ORB; ++l)
+    if (p.orb_start[l + 1] > p.orb_start[l]) return DF3C_E_UNSUPPORTED;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  char *w = static_cast<char *>(ws);
+  int *err = reinterpret_cast<int *>(w);
+  w += align256(sizeof(int) * 8);
+  int32_t *orb_sorted = reinterpret_cast<int32_t *>(w);
+  w += align256(sizeof(int32_t) * orb->nshell);
+  int32_t *aux_sorted = reinterpret_cast<int32_t *>(w);
+  w += align256(sizeof(int32_t) * aux->nshell);
+  int64_t *ao_off = reinterpret_cast<int64_t *>(w);
+  w += align256(sizeof(int64_t) * (orb->nshell + 1));
+  int64_t *aux_off = reinterpret_cast<int64_t *>(w);
+  w += align256(sizeof(int64_t) * (aux->nshell + 1));
+  double *partial = reinterpret_cast<double *>(w);
+  if (hipMemcpyAsync(orb_sorted, p.orb_sorted.data(), sizeof(int32_t) * orb->nshell,
+                     hipMemcpyHostToDevice, s) != hipSuccess ||
+      hipMemcpyAsync(aux_sorted, p.aux_sorted.data(), sizeof(int32_t) * aux->nshell,
+                     hipMemcpyHostToDevice, s) != hipSuccess ||
+      hipMemcpyAsync(ao_off, p.ao_off.data(), sizeof(int64_t) * (orb->nshell + 1),
+                     hipMemcpyHostToDevice, s) != hipSuccess ||
+      hipMemcpyAsync(aux_off, p.aux_off.data(), sizeof(int64_t) * (aux->nshell + 1),
+                     hipMemcpyHostToDevice, s) != hipSuccess)
+    return DF3C_E_HIP;
+  hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, s, err, 1, 0);
+  check_shells(aux, natom, err, s);
+  check_shells(orb, natom, err, s);
+  if (hipMemcpyAsync(g_pinned, err, sizeof(int), hipMemcpyDeviceToHost, s) != hipSuccess)
+    return DF3C_E_HIP;
+  if (hipStreamSynchronize(s) != hipSuccess) return DF3C_E_HIP;
+  if (g_pinned[0]) return DF3C_E_ARG;
+  const int64_t npart = int64_t(nslot) * 3 * natom;
+  hipLaunchKernelGGL(k_zero_f64, dim3(int(std::min<int64_t>((npart + 255) / 256, 4096))),
+                     dim3(256), 0, s, partial, npart);
+  GradArgs a{};
+  a.boys = ds->boys;
+  a.xyz = xyz;
+  a.aux = dev_shells(aux);
+  a.orb = dev_shells(orb);
+  a.ao_off = ao_off;
+  a.aux_off = aux_off;
+  a.d = d;
+  a.G = G;
+  a.nao = p.nao;
+  a.pure = aux->pure;
+  a.natom = natom;
+  a.partial = partial;
+  const int grid_cap = ds->ncu * GRAD_GRID_PER_CU;
+  for (int lp = 0; lp <= DF3C_LMAX_AUX; ++lp) {
+    const int np = p.aux_start[lp + 1] - p.aux_start[lp];
+    if (!np) continue;
+    a.psh = aux_sorted + p.aux_start[lp];
+    a.np = np;
+    for (int la = 0; la <= DF3C_LMAX_GRAD_ORB; ++la)
+      for (int lb = 0; lb <= la; ++lb) {
+        const int na = p.orb_start[la + 1] - p.orb_start[la];
+        const int nb = p.orb_start[lb + 1] - p.orb_start[lb];
+        if (!na || !nb) continue;
+        a.ash = orb_sorted + p.orb_start[la];
+        a.bsh = orb_sorted + p.orb_start[lb];
+        a.na = na;
+        a.nb = nb;
+        a.same = (la == lb);
+        a.npair = (la == lb) ? int64_t(na) * (na + 1) / 2 : int64_t(na) * nb;
+        const GradInfo &gi = g_grad[lp][la][lb];
+        const int lds = gi.tpb * (gi.team + 3 * natom) * 8;
+        if (lds > 160 * 1024) return DF3C_E_UNSUPPORTED;
+        const int grid = int(std::max<int64_t>(1, std::min<int64_t>((a.npair + gi.tpb - 1) / gi.tpb,
+                                                                     grid_cap)));
+        if (gi.gfn(a, grid, lds, s) != hipSuccess) return DF3C_E_HIP;
+      }
+  }
+  const int n = 3 * natom;
+  hipLaunchKernelGGL(k_reduce_partial, dim3((n + 255) / 256), dim3(256), 0, s, partial, nslot, n,
+                     grad);
   return DF3C_OK;
 }
 

@@ -49,10 +49,14 @@ def lib():
         L.df3c_status_string.argtypes = [ctypes.c_int]
         L.df3c_eval_batch_workspace.restype = SZ
         L.df3c_eval_batch_workspace.argtypes = [I64]
-        L.df3c_eval_batch.argtypes = [P, P, P, I64, P, P, P, P, SZ, U32, P]
+        I32 = ctypes.c_int32
+        L.df3c_eval_batch.argtypes = [P, I32, P, P, I64, P, P, P, P, SZ, U32, P]
         L.df3c_coulomb_J_workspace.restype = SZ
         L.df3c_coulomb_J_workspace.argtypes = [P, P]
-        L.df3c_coulomb_J.argtypes = [P, P, P, P, P, P, SZ, U32, P]
+        L.df3c_coulomb_J.argtypes = [P, I32, P, P, P, P, P, SZ, U32, P]
+        L.df3c_coulomb_J_grad_workspace.restype = SZ
+        L.df3c_coulomb_J_grad_workspace.argtypes = [P, P, I32]
+        L.df3c_coulomb_J_grad.argtypes = [P, I32, P, P, P, P, P, P, SZ, U32, P]
         _lib = L
     return _lib
 
@@ -123,7 +127,8 @@ def eval_batch(xyz: torch.Tensor, aux: DeviceBasis, orb: DeviceBasis, trip: torc
     if ws is None or ws.numel() < need:
         ws = torch.empty(max(need, 1), dtype=torch.uint8, device=xyz.device)
     sa, so = aux.struct(), orb.struct()
-    _check(lib().df3c_eval_batch(_ptr(xyz), ctypes.byref(sa), ctypes.byref(so), ntrip, _ptr(trip),
+    _check(lib().df3c_eval_batch(_ptr(xyz), int(xyz.shape[0]), ctypes.byref(sa), ctypes.byref(so),
+                                 ntrip, _ptr(trip),
                                  _ptr(out_off), _ptr(out), _ptr(ws), ws.numel(), flags,
                                  _stream(stream)), "df3c_eval_batch")
     return out
@@ -145,6 +150,54 @@ def coulomb_J(xyz: torch.Tensor, aux: DeviceBasis, orb: DeviceBasis, d: torch.Te
     if ws is None or ws.numel() < need:
         ws = torch.empty(max(need, 1), dtype=torch.uint8, device=xyz.device)
     sa, so = aux.struct(), orb.struct()
-    _check(lib().df3c_coulomb_J(_ptr(xyz), ctypes.byref(sa), ctypes.byref(so), _ptr(d), _ptr(J),
-                                _ptr(ws), ws.numel(), flags, _stream(stream)), "df3c_coulomb_J")
+    _check(lib().df3c_coulomb_J(_ptr(xyz), int(xyz.shape[0]), ctypes.byref(sa), ctypes.byref(so),
+                                _ptr(d), _ptr(J), _ptr(ws), ws.numel(), flags, _stream(stream)),
+           "df3c_coulomb_J")
     return J
+
+
+def coulomb_J_grad_workspace(aux: DeviceBasis, orb: DeviceBasis, natom: int) -> int:
+    sa, so = aux.struct(), orb.struct()
+    return int(lib().df3c_coulomb_J_grad_workspace(ctypes.byref(sa), ctypes.byref(so), int(natom)))
+
+
+def coulomb_J_grad(xyz: torch.Tensor, aux: DeviceBasis, orb: DeviceBasis, d: torch.Tensor,
+                   G: torch.Tensor, grad: Optional[torch.Tensor] = None,
+                   ws: Optional[torch.Tensor] = None, flags: int = 0, stream=None) -> torch.Tensor:
+    """dL/dxyz for L = sum_ab G_ab J_ab (d and G fixed)."""
+    natom = int(xyz.shape[0])
+    if grad is None:
+        grad = torch.empty((natom, 3), dtype=torch.float64, device=xyz.device)
+    need = coulomb_J_grad_workspace(aux, orb, natom)
+    if ws is None or ws.numel() < need:
+        ws = torch.empty(max(need, 1), dtype=torch.uint8, device=xyz.device)
+    G = G.contiguous()
+    sa, so = aux.struct(), orb.struct()
+    _check(lib().df3c_coulomb_J_grad(_ptr(xyz), natom, ctypes.byref(sa), ctypes.byref(so), _ptr(d),
+                                     _ptr(G), _ptr(grad), _ptr(ws), ws.numel(), flags,
+                                     _stream(stream)), "df3c_coulomb_J_grad")
+    return grad
+
+
+class CoulombJ(torch.autograd.Function):
+    """J(xyz) = sum_P (ab|P) d_P as a differentiable function of the atomic
+    positions.  backward(G) runs the library's gradient kernel with G = dL/dJ;
+    the gradient with respect to d is not provided (returned as None)."""
+
+    @staticmethod
+    def forward(ctx, xyz, d, aux, orb):
+        ctx.save_for_backward(xyz, d)
+        ctx.aux, ctx.orb = aux, orb
+        return coulomb_J(xyz.detach().contiguous(), aux, orb, d.detach().contiguous())
+
+    @staticmethod
+    def backward(ctx, gJ):
+        xyz, d = ctx.saved_tensors
+        g = coulomb_J_grad(xyz.detach().contiguous(), ctx.aux, ctx.orb, d.detach().contiguous(),
+                           gJ.detach().to(torch.float64).contiguous())
+        return g, None, None, None
+
+
+def J(xyz: torch.Tensor, d: torch.Tensor, aux: DeviceBasis, orb: DeviceBasis) -> torch.Tensor:
+    """Differentiable DF-J build (see CoulombJ)."""
+    return CoulombJ.apply(xyz, d, aux, orb)

@@ -28,7 +28,8 @@ def lib():
 
 def test_header_declares_entry_points():
     names = _declared()
-    for n in ("df3c_eval_batch", "df3c_coulomb_J", "df3c_init", "df3c_status_string"):
+    for n in ("df3c_eval_batch", "df3c_coulomb_J", "df3c_coulomb_J_grad", "df3c_init",
+              "df3c_status_string"):
         assert n in names
 
 
@@ -45,15 +46,16 @@ def test_status_strings(lib):
 
 def test_eval_batch_rejects_null_arguments(lib):
     # validation happens before any HIP call, so this runs without a GPU
-    rc = lib.df3c_eval_batch(None, None, None, 5, None, None, None, None, 0, 0, None)
+    rc = lib.df3c_eval_batch(None, 1, None, None, 5, None, None, None, None, 0, 0, None)
     assert rc == -1
-    rc = lib.df3c_eval_batch(None, None, None, -1, None, None, None, None, 0, 0, None)
+    rc = lib.df3c_eval_batch(None, 1, None, None, -1, None, None, None, None, 0, 0, None)
     assert rc == -1
-    assert lib.df3c_eval_batch(None, None, None, 0, None, None, None, None, 0, 0, None) == 0
+    assert lib.df3c_eval_batch(None, 1, None, None, 0, None, None, None, None, 0, 0, None) == 0
 
 
 def test_coulomb_J_rejects_null_arguments(lib):
-    assert lib.df3c_coulomb_J(None, None, None, None, None, None, 0, 0, None) == -1
+    assert lib.df3c_coulomb_J(None, 1, None, None, None, None, None, 0, 0, None) == -1
+    assert lib.df3c_coulomb_J_grad(None, 1, None, None, None, None, None, None, 0, 0, None) == -1
 
 
 def test_workspace_sizes(lib):
