@@ -43,6 +43,7 @@ def parse():
     p.add_argument("--ntrip", type=int, default=100000)
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-dfj", action="store_true")
+    p.add_argument("--batched-nmol", type=int, default=64)
     return p.parse_args()
 
 
@@ -71,6 +72,73 @@ def cpu_baseline(batches, budget_s=20.0):
             "kind": "oracle",
             "sample": "first n triplets of each of the 15 per-class batches (" + ", ".join(desc) +
                       "), time scaled to 1e5 triplets per batch"}
+
+
+def _time_ms(torch, fn, reps, stream=None):
+    fn()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / reps * 1e3
+
+
+def dfj_legs(args, df3c, inputs, torch, dev):
+    """DF-J wall times (device-resident inputs): single molecules, the batched
+    uneven water clusters (per-class launches vs the tuned persistent queue in a
+    HIP graph), and the J gradient."""
+    out = {}
+    for name, sysf in (("plain_8atoms", inputs.plain_dfj_system),
+                       ("water_120atoms", inputs.dfj_120_system)):
+        s = sysf()
+        d = torch.as_tensor(inputs.fitting_coefficients(s.aux.nbf, 1), device=dev)
+        xyz = torch.as_tensor(s.xyz, device=dev)
+        aux = df3c.DeviceBasis.from_basis(s.aux, dev)
+        orb = df3c.DeviceBasis.from_basis(s.orb, dev)
+        J = torch.empty((s.orb.nbf, s.orb.nbf), dtype=torch.float64, device=dev)
+        wsj = torch.empty(df3c.coulomb_J_workspace(aux, orb), dtype=torch.uint8, device=dev)
+        out[f"dfj_ms_{name}"] = _time_ms(torch, lambda: df3c.coulomb_J(xyz, aux, orb, d, J=J,
+                                                                        ws=wsj), 3)
+    # J gradient, 60 atoms
+    s = inputs.grad_60_system()
+    d = torch.as_tensor(inputs.fitting_coefficients(s.aux.nbf, 5), device=dev)
+    G = torch.as_tensor(inputs.symmetric_density(s.orb.nbf, 6), device=dev)
+    xyz = torch.as_tensor(s.xyz, device=dev)
+    aux = df3c.DeviceBasis.from_basis(s.aux, dev)
+    orb = df3c.DeviceBasis.from_basis(s.orb, dev)
+    out["dfj_ms_water_60atoms"] = _time_ms(torch, lambda: df3c.coulomb_J(xyz, aux, orb, d), 2)
+    out["grad_ms_water_60atoms"] = _time_ms(
+        torch, lambda: df3c.coulomb_J_grad(xyz, aux, orb, d, G), 1)
+    # batched uneven clusters
+    if args.batched_nmol > 0:
+        from paper_2210_03192_amd import autotune
+        b = inputs.concat_systems(inputs.batched_systems(args.batched_nmol))
+        db = torch.as_tensor(inputs.fitting_coefficients(b.aux.nbf, 7), device=dev)
+        xb = torch.as_tensor(b.xyz, device=dev)
+        ab = df3c.DeviceBasis.from_basis(b.aux, dev)
+        ob = df3c.DeviceBasis.from_basis(b.orb, dev)
+        st = torch.cuda.Stream()
+        ws = torch.empty(df3c.coulomb_J_batched_workspace(ab, ob, b.nmol), dtype=torch.uint8,
+                         device=dev)
+        off = b.orb.offsets()
+        nao = off[b.mol_orb[1:]] - off[b.mol_orb[:-1]]
+        Jb = torch.empty(int((nao * nao).sum()), dtype=torch.float64, device=dev)
+        tuned = autotune.load()
+
+        def run(flags, tune=None):
+            with torch.cuda.stream(st):
+                df3c.coulomb_J_batched(xb, ab, ob, b.mol_orb, b.mol_aux, db, J=Jb, tune=tune,
+                                       flags=flags, ws=ws, stream=st)
+        out["batched_nmol"] = b.nmol
+        out["batched_natoms"] = int(len(b.xyz))
+        out["batched_dfj_ms_per_class"] = _time_ms(torch, lambda: run(df3c.SCHED_PER_CLASS), 1)
+        out["batched_dfj_ms_persistent_graph"] = _time_ms(
+            torch, lambda: run(df3c.SCHED_PERSISTENT | df3c.GRAPH), 1)
+        if tuned is not None:
+            out["batched_dfj_ms_persistent_graph_tuned"] = _time_ms(
+                torch, lambda: run(df3c.SCHED_PERSISTENT | df3c.GRAPH, tuned), 1)
+    return out
 
 
 def main():
@@ -146,24 +214,7 @@ def main():
 
     extra = {}
     if not args.no_dfj:
-        for name, sysf in (("plain_8atoms", inputs.plain_dfj_system),
-                           ("water_120atoms", inputs.dfj_120_system)):
-            s = sysf()
-            d = torch.as_tensor(inputs.fitting_coefficients(s.aux.nbf, 1), device=dev)
-            xyz = torch.as_tensor(s.xyz, device=dev)
-            aux = df3c.DeviceBasis.from_basis(s.aux, dev)
-            orb = df3c.DeviceBasis.from_basis(s.orb, dev)
-            J = torch.empty((s.orb.nbf, s.orb.nbf), dtype=torch.float64, device=dev)
-            wsj = torch.empty(df3c.coulomb_J_workspace(aux, orb), dtype=torch.uint8, device=dev)
-            df3c.coulomb_J(xyz, aux, orb, d, J=J, ws=wsj)
-            torch.cuda.synchronize()
-            reps = 3
-            t0 = time.perf_counter()
-            for _ in range(reps):
-                df3c.coulomb_J(xyz, aux, orb, d, J=J, ws=wsj)
-            torch.cuda.synchronize()
-            extra[f"dfj_ms_{name}"] = (time.perf_counter() - t0) / reps * 1e3
-
+        extra.update(dfj_legs(args, df3c, inputs, torch, dev))
     rec = {"metric": METRIC, "value": nint / (ms_step * 1e-3), "unit": "integrals/s",
            "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_step,
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",

@@ -58,6 +58,11 @@ extern "C" {
 
 /* flags */
 #define DF3C_FLAG_NONE 0u
+#define DF3C_SCHED_PER_CLASS 0u  /* batched J: one launch per (molecule, class) */
+#define DF3C_SCHED_PERSISTENT 1u /* batched J: one persistent work-queue launch per class */
+#define DF3C_GRAPH 2u            /* batched J: capture the launches in a HIP graph on the
+                                    first call and replay it on calls with the same
+                                    arguments */
 
 /* A basis: nshell shells.  l_host is a HOST array; the other arrays are DEVICE
  * arrays.  exps/coefs are indexed by prim_off[s] .. prim_off[s] + nprim[s]-1. */
@@ -131,6 +136,43 @@ size_t df3c_coulomb_J_grad_workspace(const df3c_shells *aux, const df3c_shells *
 int df3c_coulomb_J_grad(const double *xyz, int32_t natom, const df3c_shells *aux,
                         const df3c_shells *orb, const double *d, const double *G, double *grad,
                         void *ws, size_t ws_bytes, uint32_t flags, void *stream);
+
+/* Per-class schedule parameters of the persistent batched J (written by the
+ * project's autotuner).  A table has DF3C_NCLASS entries indexed by
+ * (l_P * 5 + l_a) * 5 + l_b with l_a >= l_b. */
+typedef struct {
+  int32_t chunk;        /* consecutive shell pairs per team and queue grab, >= 1 */
+  int32_t grid_per_cu;  /* persistent workgroups per CU, >= 1 */
+  int32_t enabled;      /* 0 skips the class (lets the autotuner time one class) */
+  int32_t order;        /* launch order key, smaller first */
+} df3c_class_tune;
+#define DF3C_NCLASS 175
+
+/* Bytes of workspace df3c_coulomb_J_batched needs. */
+size_t df3c_coulomb_J_batched_workspace(const df3c_shells *aux, const df3c_shells *orb,
+                                        int32_t nmol);
+
+/* DF-J for nmol independent molecules in one call: the batched form of
+ * df3c_coulomb_J for uneven molecule sizes, L classes and contraction degrees.
+ *   mol_orb, mol_aux  HOST [nmol+1]: molecule m owns orbital shells
+ *                     [mol_orb[m], mol_orb[m+1]) and aux shells
+ *                     [mol_aux[m], mol_aux[m+1]); mol_*[0] = 0, mol_*[nmol] = nshell
+ *   d                 DEVICE, the molecules' fitting coefficients in aux order
+ *   J                 DEVICE output, molecule m's nao_m x nao_m matrix at offset
+ *                     sum_{m' < m} nao_m'^2 (both triangles)
+ *   tune              HOST [DF3C_NCLASS] schedule parameters, or NULL for defaults
+ *   flags             DF3C_SCHED_PER_CLASS or DF3C_SCHED_PERSISTENT, optionally
+ *                     | DF3C_GRAPH.  With DF3C_GRAPH the workspace must be left
+ *                     untouched between calls with the same arguments (the graph
+ *                     reads the plan stored in it), and `stream` must not be the
+ *                     legacy default stream (it cannot be captured).
+ * The persistent schedule runs one launch per class in which workgroups take
+ * shell pairs of all molecules from an atomic counter until the queue is empty. */
+int df3c_coulomb_J_batched(const double *xyz, int32_t natom, const df3c_shells *aux,
+                           const df3c_shells *orb, int32_t nmol, const int32_t *mol_orb,
+                           const int32_t *mol_aux, const double *d, double *J,
+                           const df3c_class_tune *tune, void *ws, size_t ws_bytes,
+                           uint32_t flags, void *stream);
 
 /* Readable name of a status code (static string). */
 const char *df3c_status_string(int status);

@@ -47,6 +47,7 @@ struct JArgs {
   double *J;                // [nao][nao]
   int64_t nao;
   int64_t npair;
+  int64_t ao_base;          // subtracted from ao_off (first AO of the molecule)
   int32_t pure;
 };
 
@@ -88,7 +89,8 @@ struct Cfg {
   static constexpr int PCH = TS >= 16 ? 4 : TS == 4 ? 2 : 1;
   static constexpr int BLK = TS > 64 ? TS : 64;
   static constexpr int LDS = (BLK / TS) * Layout<LP, LA, LB, PCH>::TOTAL * 8;
-  static_assert(LDS <= 160 * 1024, "class does not fit the LDS of a CU");
+  static constexpr int LDS_J = (BLK / TS) * (Layout<LP, LA, LB, PCH>::TOTAL + G::NE) * 8;
+  static_assert(LDS_J <= 160 * 1024, "class does not fit the LDS of a CU");
 };
 
 // ---------------------------------------------------------------------------
@@ -450,24 +452,135 @@ __global__ void __launch_bounds__(TS > 64 ? TS : 64) k_store(StoreArgs a) {
 
 // ---------------------------------------------------------------------------
 // J digestion: one orbital shell pair per team; the team loops over all aux
-// shells of l = LP and accumulates J_ab += sum_P (ab|P) d_P for its pair, then
-// adds the block (and its transpose) into J.  Each pair is owned by exactly one
-// team, so no atomics are needed; launches of different LP run in stream order.
+// shells of l = LP.  The HRR and the ket transform are linear in the ket, and
+// the HRR coefficients depend only on A - B, so d_P is contracted into (e0|P)
+// right after the transform and accumulated over all aux shells,
+//   X_e = sum_P sum_m d_Pm (e0|Pm),
+// and one single-component HRR per pair gives J_ab = (ab|X) -- the same sum as
+// sum_P (ab|P) d_P in another order (the contraction of the density with
+// intermediates that Section 4 names as the better J strategy).  The block and
+// its transpose are added into J; each pair is owned by exactly one team, so
+// no atomics are needed, and launches of different LP run in stream order.
 // ---------------------------------------------------------------------------
+template <int LP, int LA, int LB, int TS, int PCH>
+struct JLayout {
+  using G = Geo<LP, LA, LA + LB>;
+  static constexpr int XD = Layout<LP, LA, LB, PCH>::TOTAL;   // X_e for the final HRR
+  static constexpr int TOTAL = XD + G::NE;
+};
+
+template <int LP, int LA, int LB, int TS, int PCH>
+__device__ __forceinline__ void j_pair(const JArgs &a, double *S, int tid, const int *slot,
+                                       bool valid, int sa, int sb, int np_loop) {
+  using G = Geo<LP, LA, LA + LB>;
+  using LY = Layout<LP, LA, LB, PCH>;
+  using JL = JLayout<LP, LA, LB, TS, PCH>;
+  constexpr int NA = ncart(LA), NB = ncart(LB);
+  constexpr int NX = (G::NE + TS - 1) / TS;
+  const int np_out = a.pure ? npure(LP) : ncart(LP);
+  if (valid && LA == LB && sa != sb) {
+    // orient the pair for a well-conditioned HRR (see the runtime's k_scatter):
+    // VRR1 quanta on the shell with the larger (max exponent x min exponent);
+    // both J blocks are written below, so the orientation is free.
+    auto tight = [&](int sh) {
+      const double *e = a.orb.exps + a.orb.prim_off[sh];
+      double lo = e[0], hi = e[0];
+      for (int i = 1; i < a.orb.nprim[sh]; ++i) {
+        lo = fmin(lo, e[i]);
+        hi = fmax(hi, e[i]);
+      }
+      return lo * hi;
+    };
+    if (tight(sb) > tight(sa)) {
+      const int t = sa;
+      sa = sb;
+      sb = t;
+    }
+  }
+  const int Ka = valid ? a.orb.nprim[sa] : 0, Kb = valid ? a.orb.nprim[sb] : 0;
+  const int64_t oa = valid ? a.orb.prim_off[sa] : 0, ob = valid ? a.orb.prim_off[sb] : 0;
+  double Ar[3] = {0, 0, 0}, Br[3] = {0, 0, 0};
+  if (valid) {
+    const int ia = a.orb.atom[sa], ib = a.orb.atom[sb];
+    for (int x = 0; x < 3; ++x) {
+      Ar[x] = a.xyz[3 * ia + x];
+      Br[x] = a.xyz[3 * ib + x];
+    }
+  }
+  double X[NX];
+#pragma unroll
+  for (int k = 0; k < NX; ++k) X[k] = 0.0;
+  // np_loop is uniform over the workgroup (>= a.np); teams past their own
+  // a.np run the iteration without work so that every barrier is met
+  for (int ip = 0; ip < np_loop; ++ip) {
+    const bool active = valid && ip < a.np;
+    const int sP = active ? a.psh[ip] : 0;
+    const int Kc = active ? a.aux.nprim[sP] : 0;
+    const int npmax = TS >= 64 ? Ka * Kb * Kc : wave_max(Ka * Kb * Kc);
+    const int64_t oc = active ? a.aux.prim_off[sP] : 0;
+    double Cr[3] = {0, 0, 0};
+    if (active) {
+      const int ic = a.aux.atom[sP];
+      Cr[0] = a.xyz[3 * ic];
+      Cr[1] = a.xyz[3 * ic + 1];
+      Cr[2] = a.xyz[3 * ic + 2];
+    }
+    triplet_to_e0P<LP, LA, LB, TS, PCH>(a.boys, S, tid, slot, npmax, Ar, Br, Cr, Ka,
+                                        a.orb.exps + oa, a.orb.coefs + oa, Kb, a.orb.exps + ob,
+                                        a.orb.coefs + ob, Kc, a.aux.exps + oc, a.aux.coefs + oc,
+                                        a.pure);
+    const double *EM = S + LY::EM;
+    const double *dP = a.d + (active ? a.aux_off[sP] : 0);
+#pragma unroll
+    for (int k = 0; k < NX; ++k) {
+      const int e = tid + k * TS;
+      if (active && e < G::NE) {
+        double v = X[k];
+        for (int m = 0; m < np_out; ++m) v += dP[m] * EM[m * G::NE + e];
+        X[k] = v;
+      }
+    }
+    team_sync();
+  }
+  // one single-component HRR for the pair
+  double *XD = S + JL::XD;
+#pragma unroll
+  for (int k = 0; k < NX; ++k)
+    if (tid + k * TS < G::NE) XD[tid + k * TS] = X[k];
+  team_sync();
+  double pwx[LB + 1], pwy[LB + 1], pwz[LB + 1];
+  pwx[0] = pwy[0] = pwz[0] = 1.0;
+#pragma unroll
+  for (int k = 1; k <= LB; ++k) {
+    pwx[k] = pwx[k - 1] * (Ar[0] - Br[0]);
+    pwy[k] = pwy[k - 1] * (Ar[1] - Br[1]);
+    pwz[k] = pwz[k - 1] * (Ar[2] - Br[2]);
+  }
+  if (valid) {
+    const int64_t ra = a.ao_off[sa] - a.ao_base, rb = a.ao_off[sb] - a.ao_base;
+    for (int ia = tid; ia < NA; ia += TS) {
+      double o[NB];
+      hrr_nq<LA, LB>(XD, ia, pwx, pwy, pwz, o);
+#pragma unroll
+      for (int ib = 0; ib < NB; ++ib) {
+        a.J[(ra + ia) * a.nao + rb + ib] += o[ib];
+        if (sa != sb) a.J[(rb + ib) * a.nao + ra + ia] += o[ib];
+      }
+    }
+  }
+  team_sync();
+}
+
 template <int LP, int LA, int LB, int TS, int PCH>
 __global__ void __launch_bounds__(TS > 64 ? TS : 64) k_J(JArgs a) {
   using G = Geo<LP, LA, LA + LB>;
-  using LY = Layout<LP, LA, LB, PCH>;
+  using JL = JLayout<LP, LA, LB, TS, PCH>;
   constexpr int BLK = TS > 64 ? TS : 64;
   constexpr int TPB = BLK / TS;
-  constexpr int NA = ncart(LA), NB = ncart(LB);
-  constexpr int NAB = NA * NB;
-  constexpr int NACC = (NAB + TS - 1) / TS;
   constexpr int NQ = (G::NPI + TS - 1) / TS;
   extern __shared__ double smem[];
   const int team = threadIdx.x / TS, tid = threadIdx.x % TS;
-  double *S = smem + team * LY::TOTAL;
-  const int np_out = a.pure ? npure(LP) : ncart(LP);
+  double *S = smem + team * JL::TOTAL;
   int slot[NQ];
   make_slots<LP, LA, LB, TS>(slot, tid);
 
@@ -489,76 +602,7 @@ __global__ void __launch_bounds__(TS > 64 ? TS : 64) k_J(JArgs a) {
         sb = a.bsh[j];
       }
     }
-    if (valid && LA == LB && sa != sb) {
-      // orient the pair for a well-conditioned HRR (see the runtime's k_scatter):
-      // VRR1 quanta on the shell with the larger (max exponent x min exponent);
-      // both J blocks are written below, so the orientation is free.
-      auto tight = [&](int sh) {
-        const double *e = a.orb.exps + a.orb.prim_off[sh];
-        double lo = e[0], hi = e[0];
-        for (int i = 1; i < a.orb.nprim[sh]; ++i) {
-          lo = fmin(lo, e[i]);
-          hi = fmax(hi, e[i]);
-        }
-        return lo * hi;
-      };
-      if (tight(sb) > tight(sa)) {
-        const int t = sa;
-        sa = sb;
-        sb = t;
-      }
-    }
-    const int Ka = valid ? a.orb.nprim[sa] : 0, Kb = valid ? a.orb.nprim[sb] : 0;
-    const int64_t oa = valid ? a.orb.prim_off[sa] : 0, ob = valid ? a.orb.prim_off[sb] : 0;
-    double Ar[3] = {0, 0, 0}, Br[3] = {0, 0, 0};
-    if (valid) {
-      const int ia = a.orb.atom[sa], ib = a.orb.atom[sb];
-      for (int x = 0; x < 3; ++x) {
-        Ar[x] = a.xyz[3 * ia + x];
-        Br[x] = a.xyz[3 * ib + x];
-      }
-    }
-    double acc[NACC];
-#pragma unroll
-    for (int k = 0; k < NACC; ++k) acc[k] = 0.0;
-    for (int ip = 0; ip < a.np; ++ip) {
-      const int sP = a.psh[ip];
-      const int Kc = a.aux.nprim[sP];
-      const int npmax = TS >= 64 ? Ka * Kb * Kc : wave_max(Ka * Kb * Kc);
-      const int64_t oc = a.aux.prim_off[sP];
-      const int ic = a.aux.atom[sP];
-      const double Cr[3] = {a.xyz[3 * ic], a.xyz[3 * ic + 1], a.xyz[3 * ic + 2]};
-      triplet_to_e0P<LP, LA, LB, TS, PCH>(a.boys, S, tid, slot, npmax, Ar, Br, Cr, Ka,
-                                          a.orb.exps + oa, a.orb.coefs + oa, Kb,
-                                          a.orb.exps + ob, a.orb.coefs + ob, Kc,
-                                          a.aux.exps + oc, a.aux.coefs + oc, a.pure);
-      hrr_block<LP, LA, LB, TS, PCH>(S, tid, Ar, Br, np_out, false);
-      team_sync();
-      const double *STG = S + LY::STG;
-      const double *dP = a.d + a.aux_off[sP];
-#pragma unroll
-      for (int k = 0; k < NACC; ++k) {
-        const int ab = tid + k * TS;
-        if (ab < NAB) {
-          double s = acc[k];
-          for (int m = 0; m < np_out; ++m) s += STG[m * NAB + ab] * dP[m];
-          acc[k] = s;
-        }
-      }
-      team_sync();
-    }
-    if (valid) {
-      const int64_t ra = a.ao_off[sa], rb = a.ao_off[sb];
-#pragma unroll
-      for (int k = 0; k < NACC; ++k) {
-        const int ab = tid + k * TS;
-        if (ab < NAB) {
-          const int ia = ab / NB, ib = ab - ia * NB;
-          a.J[(ra + ia) * a.nao + rb + ib] += acc[k];
-          if (sa != sb) a.J[(rb + ib) * a.nao + ra + ia] += acc[k];
-        }
-      }
-    }
+    j_pair<LP, LA, LB, TS, PCH>(a, S, tid, slot, valid, sa, sb, a.np);
   }
 }
 

@@ -2,6 +2,7 @@
 // instantiation units and the runtime.
 #pragma once
 #include "grad.hpp"
+#include "queue.hpp"
 
 namespace df3c {
 
@@ -11,6 +12,7 @@ struct ClassInfo {
   int lds = 0;        // dynamic LDS bytes per workgroup
   hipError_t (*store)(const StoreArgs &, int, hipStream_t) = nullptr;
   hipError_t (*jfn)(const JArgs &, int, hipStream_t) = nullptr;
+  hipError_t (*jq)(const JQArgs &, int, hipStream_t) = nullptr;
 };
 
 struct GradInfo {
@@ -35,9 +37,20 @@ hipError_t launch_J(const JArgs &a, int grid, hipStream_t s) {
   using C = Cfg<LP, LA, LB>;
   auto kern = k_J<LP, LA, LB, C::TS, C::PCH>;
   static const hipError_t attr = hipFuncSetAttribute(
-      reinterpret_cast<const void *>(kern), hipFuncAttributeMaxDynamicSharedMemorySize, C::LDS);
+      reinterpret_cast<const void *>(kern), hipFuncAttributeMaxDynamicSharedMemorySize, C::LDS_J);
   if (attr != hipSuccess) return attr;
-  hipLaunchKernelGGL(kern, dim3(grid), dim3(C::BLK), C::LDS, s, a);
+  hipLaunchKernelGGL(kern, dim3(grid), dim3(C::BLK), C::LDS_J, s, a);
+  return hipGetLastError();
+}
+
+template <int LP, int LA, int LB>
+hipError_t launch_Jq(const JQArgs &a, int grid, hipStream_t s) {
+  using C = Cfg<LP, LA, LB>;
+  auto kern = k_Jq<LP, LA, LB, C::TS, C::PCH>;
+  static const hipError_t attr = hipFuncSetAttribute(
+      reinterpret_cast<const void *>(kern), hipFuncAttributeMaxDynamicSharedMemorySize, C::LDS_J);
+  if (attr != hipSuccess) return attr;
+  hipLaunchKernelGGL(kern, dim3(grid), dim3(C::BLK), C::LDS_J, s, a);
   return hipGetLastError();
 }
 
@@ -71,6 +84,7 @@ ClassInfo class_info() {
   c.lds = C::LDS;
   c.store = &launch_store<LP, LA, LB>;
   c.jfn = &launch_J<LP, LA, LB>;
+  c.jq = &launch_Jq<LP, LA, LB>;
   return c;
 }
 

@@ -3,9 +3,11 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstring>
 #include <mutex>
+#include <unordered_map>
 #include <vector>
 
 #include "../../include/df3c.h"
@@ -572,6 +574,304 @@ int df3c_coulomb_J_grad(const double *xyz, int32_t natom, const df3c_shells *aux
   const int n = 3 * natom;
   hipLaunchKernelGGL(k_reduce_partial, dim3((n + 255) / 256), dim3(256), 0, s, partial, nslot, n,
                      grad);
+  return DF3C_OK;
+}
+
+
+// --------------------------------------------------------------- batched DF-J
+namespace {
+struct BPlan {
+  std::vector<int32_t> orb_sorted, aux_sorted;  // per molecule, grouped by l
+  std::vector<int64_t> ao_off, aux_off;
+  std::vector<JSeg> seg;                         // all classes, class-major
+  int32_t cls_seg0[NCLS + 1] = {};               // segment range of every class
+  int64_t cls_items[NCLS] = {};
+  std::vector<int64_t> jbase, nao_m, ao_base;
+  int64_t jtotal = 0;
+};
+
+size_t bplan_bytes(int64_t norb, int64_t naux, int64_t nmol) {
+  return align256(sizeof(int) * 8) + align256(sizeof(int32_t) * norb) +
+         align256(sizeof(int32_t) * naux) + align256(sizeof(int64_t) * (norb + 1)) +
+         align256(sizeof(int64_t) * (naux + 1)) + align256(sizeof(JSeg) * nmol * NCLS) +
+         align256(sizeof(unsigned long long) * NCLS);
+}
+
+int make_bplan(const df3c_shells *aux, const df3c_shells *orb, int nmol, const int32_t *mo,
+               const int32_t *ma, BPlan &p) {
+  if (!aux->l_host || !orb->l_host || !mo || !ma || nmol <= 0) return DF3C_E_ARG;
+  if (mo[0] != 0 || ma[0] != 0 || mo[nmol] != orb->nshell || ma[nmol] != aux->nshell)
+    return DF3C_E_ARG;
+  for (int m = 0; m < nmol; ++m)
+    if (mo[m + 1] < mo[m] || ma[m + 1] < ma[m]) return DF3C_E_ARG;
+  p.ao_off.assign(orb->nshell + 1, 0);
+  p.aux_off.assign(aux->nshell + 1, 0);
+  for (int s = 0; s < orb->nshell; ++s) {
+    const int l = orb->l_host[s];
+    if (l < 0 || l > DF3C_LMAX_ORB) return DF3C_E_UNSUPPORTED;
+    p.ao_off[s + 1] = p.ao_off[s] + (l + 1) * (l + 2) / 2;
+  }
+  for (int s = 0; s < aux->nshell; ++s) {
+    const int l = aux->l_host[s];
+    if (l < 0 || l > DF3C_LMAX_AUX || (!aux->pure && l > 1)) return DF3C_E_UNSUPPORTED;
+    p.aux_off[s + 1] = p.aux_off[s] + (aux->pure ? 2 * l + 1 : (l + 1) * (l + 2) / 2);
+  }
+  // per molecule: shells grouped by l
+  std::vector<std::array<int32_t, DF3C_LMAX_ORB + 2>> ost(nmol);
+  std::vector<std::array<int32_t, DF3C_LMAX_AUX + 2>> ast(nmol);
+  p.orb_sorted.clear();
+  p.aux_sorted.clear();
+  p.jbase.resize(nmol);
+  p.nao_m.resize(nmol);
+  p.ao_base.resize(nmol);
+  int64_t jb = 0;
+  for (int m = 0; m < nmol; ++m) {
+    for (int l = 0; l <= DF3C_LMAX_ORB; ++l) {
+      ost[m][l] = int32_t(p.orb_sorted.size());
+      for (int s = mo[m]; s < mo[m + 1]; ++s)
+        if (orb->l_host[s] == l) p.orb_sorted.push_back(s);
+    }
+    ost[m][DF3C_LMAX_ORB + 1] = int32_t(p.orb_sorted.size());
+    for (int l = 0; l <= DF3C_LMAX_AUX; ++l) {
+      ast[m][l] = int32_t(p.aux_sorted.size());
+      for (int s = ma[m]; s < ma[m + 1]; ++s)
+        if (aux->l_host[s] == l) p.aux_sorted.push_back(s);
+    }
+    ast[m][DF3C_LMAX_AUX + 1] = int32_t(p.aux_sorted.size());
+    p.ao_base[m] = p.ao_off[mo[m]];
+    p.nao_m[m] = p.ao_off[mo[m + 1]] - p.ao_off[mo[m]];
+    p.jbase[m] = jb;
+    jb += p.nao_m[m] * p.nao_m[m];
+  }
+  p.jtotal = jb;
+  p.seg.clear();
+  for (int c = 0; c < NCLS; ++c) {
+    p.cls_seg0[c] = int32_t(p.seg.size());
+    const int lp = c / (NLA * NLA), la = (c / NLA) % NLA, lb = c % NLA;
+    int64_t items = 0;
+    if (lb <= la)
+      for (int m = 0; m < nmol; ++m) {
+        const int na = ost[m][la + 1] - ost[m][la], nb = ost[m][lb + 1] - ost[m][lb];
+        const int np = ast[m][lp + 1] - ast[m][lp];
+        if (!na || !nb || !np) continue;
+        JSeg g{};
+        g.item0 = items;
+        g.npair = (la == lb) ? int64_t(na) * (na + 1) / 2 : int64_t(na) * nb;
+        g.jbase = p.jbase[m];
+        g.nao = p.nao_m[m];
+        g.ao_base = p.ao_base[m];
+        g.ash = ost[m][la];
+        g.bsh = ost[m][lb];
+        g.psh = ast[m][lp];
+        g.na = na;
+        g.nb = nb;
+        g.np = np;
+        g.same = (la == lb);
+        g.pad = m;  // molecule index
+        items += g.npair;
+        p.seg.push_back(g);
+      }
+    p.cls_items[c] = items;
+  }
+  p.cls_seg0[NCLS] = int32_t(p.seg.size());
+  return DF3C_OK;
+}
+
+uint64_t fnv(uint64_t h, const void *data, size_t n) {
+  const unsigned char *b = static_cast<const unsigned char *>(data);
+  for (size_t i = 0; i < n; ++i) h = (h ^ b[i]) * 1099511628211ull;
+  return h;
+}
+
+struct GraphEntry {
+  hipGraphExec_t exec = nullptr;
+};
+std::unordered_map<uint64_t, GraphEntry> g_graphs;
+std::mutex g_graph_mu;
+
+df3c_class_tune default_tune(int c) {
+  df3c_class_tune t{};
+  t.chunk = 1;
+  t.grid_per_cu = 4;
+  t.enabled = 1;
+  t.order = -int(c / (NLA * NLA));  // high l_P first (the longest classes start early)
+  return t;
+}
+}  // namespace
+
+size_t df3c_coulomb_J_batched_workspace(const df3c_shells *aux, const df3c_shells *orb,
+                                        int32_t nmol) {
+  if (!aux || !orb || nmol <= 0) return 0;
+  return bplan_bytes(orb->nshell, aux->nshell, nmol);
+}
+
+int df3c_coulomb_J_batched(const double *xyz, int32_t natom, const df3c_shells *aux,
+                           const df3c_shells *orb, int32_t nmol, const int32_t *mol_orb,
+                           const int32_t *mol_aux, const double *d, double *J,
+                           const df3c_class_tune *tune, void *ws, size_t ws_bytes,
+                           uint32_t flags, void *stream) {
+  if (!xyz || natom <= 0 || !shells_ok(aux) || !shells_ok(orb) || !d || !J || nmol <= 0)
+    return DF3C_E_ARG;
+  if (orb->pure != 0 || (aux->pure != 0 && aux->pure != 1)) return DF3C_E_UNSUPPORTED;
+  if (flags & ~(DF3C_SCHED_PERSISTENT | DF3C_GRAPH)) return DF3C_E_ARG;
+  if (!ws || ws_bytes < bplan_bytes(orb->nshell, aux->nshell, nmol)) return DF3C_E_WORKSPACE;
+  DevState *ds = nullptr;
+  int rc = init_device(&ds);
+  if (rc) return rc;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  df3c_class_tune tt[NCLS];
+  for (int c = 0; c < NCLS; ++c) {
+    tt[c] = tune ? tune[c] : default_tune(c);
+    if (tt[c].chunk < 1 || tt[c].grid_per_cu < 1) return DF3C_E_ARG;
+  }
+
+  // graph cache key: every argument that the captured launches depend on
+  uint64_t key = 1469598103934665603ull;
+  int dev = 0;
+  hipGetDevice(&dev);
+  const void *ptrs[] = {xyz, aux->l, aux->nprim, aux->prim_off, aux->atom, aux->exps, aux->coefs,
+                        orb->l, orb->nprim, orb->prim_off, orb->atom, orb->exps, orb->coefs,
+                        d, J, ws};
+  key = fnv(key, ptrs, sizeof(ptrs));
+  const int64_t scal[] = {natom, aux->nshell, orb->nshell, aux->pure, nmol, int64_t(ws_bytes),
+                          int64_t(flags), dev};
+  key = fnv(key, scal, sizeof(scal));
+  key = fnv(key, aux->l_host, sizeof(int32_t) * aux->nshell);
+  key = fnv(key, orb->l_host, sizeof(int32_t) * orb->nshell);
+  key = fnv(key, mol_orb, sizeof(int32_t) * (nmol + 1));
+  key = fnv(key, mol_aux, sizeof(int32_t) * (nmol + 1));
+  key = fnv(key, tt, sizeof(tt));
+  if (flags & DF3C_GRAPH) {
+    std::lock_guard<std::mutex> lk(g_graph_mu);
+    auto it = g_graphs.find(key);
+    if (it != g_graphs.end())
+      return hipGraphLaunch(it->second.exec, s) == hipSuccess ? DF3C_OK : DF3C_E_HIP;
+  }
+
+  BPlan p;
+  rc = make_bplan(aux, orb, nmol, mol_orb, mol_aux, p);
+  if (rc) return rc;
+  char *w = static_cast<char *>(ws);
+  int *err = reinterpret_cast<int *>(w);
+  w += align256(sizeof(int) * 8);
+  int32_t *orb_sorted = reinterpret_cast<int32_t *>(w);
+  w += align256(sizeof(int32_t) * orb->nshell);
+  int32_t *aux_sorted = reinterpret_cast<int32_t *>(w);
+  w += align256(sizeof(int32_t) * aux->nshell);
+  int64_t *ao_off = reinterpret_cast<int64_t *>(w);
+  w += align256(sizeof(int64_t) * (orb->nshell + 1));
+  int64_t *aux_off = reinterpret_cast<int64_t *>(w);
+  w += align256(sizeof(int64_t) * (aux->nshell + 1));
+  JSeg *segd = reinterpret_cast<JSeg *>(w);
+  w += align256(sizeof(JSeg) * nmol * NCLS);
+  unsigned long long *ctr = reinterpret_cast<unsigned long long *>(w);
+  if ((!p.orb_sorted.empty() &&
+       hipMemcpyAsync(orb_sorted, p.orb_sorted.data(), sizeof(int32_t) * p.orb_sorted.size(),
+                      hipMemcpyHostToDevice, s) != hipSuccess) ||
+      (!p.aux_sorted.empty() &&
+       hipMemcpyAsync(aux_sorted, p.aux_sorted.data(), sizeof(int32_t) * p.aux_sorted.size(),
+                      hipMemcpyHostToDevice, s) != hipSuccess) ||
+      hipMemcpyAsync(ao_off, p.ao_off.data(), sizeof(int64_t) * p.ao_off.size(),
+                     hipMemcpyHostToDevice, s) != hipSuccess ||
+      hipMemcpyAsync(aux_off, p.aux_off.data(), sizeof(int64_t) * p.aux_off.size(),
+                     hipMemcpyHostToDevice, s) != hipSuccess ||
+      (!p.seg.empty() && hipMemcpyAsync(segd, p.seg.data(), sizeof(JSeg) * p.seg.size(),
+                                        hipMemcpyHostToDevice, s) != hipSuccess))
+    return DF3C_E_HIP;
+  hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, s, err, 1, 0);
+  check_shells(aux, natom, err, s);
+  check_shells(orb, natom, err, s);
+  if (hipMemcpyAsync(g_pinned, err, sizeof(int), hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess)
+    return DF3C_E_HIP;
+  if (g_pinned[0]) return DF3C_E_ARG;
+
+  // class launch order
+  std::vector<int> order;
+  for (int c = 0; c < NCLS; ++c)
+    if (p.cls_items[c] > 0 && tt[c].enabled) order.push_back(c);
+  std::stable_sort(order.begin(), order.end(),
+                   [&](int x, int y) { return tt[x].order < tt[y].order; });
+
+  JArgs base{};
+  base.boys = ds->boys;
+  base.xyz = xyz;
+  base.aux = dev_shells(aux);
+  base.orb = dev_shells(orb);
+  base.ao_off = ao_off;
+  base.aux_off = aux_off;
+  base.d = d;
+  base.pure = aux->pure;
+
+  auto enqueue = [&]() -> int {
+    hipLaunchKernelGGL(k_zero_f64, dim3(int(std::min<int64_t>((p.jtotal + 255) / 256, 4096))),
+                       dim3(256), 0, s, J, p.jtotal);
+    if (flags & DF3C_SCHED_PERSISTENT) {
+      hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(256), 0, s, reinterpret_cast<int *>(ctr),
+                         2 * NCLS, 0);
+      for (int c : order) {
+        const int lp = c / (NLA * NLA), la = (c / NLA) % NLA, lb = c % NLA;
+        JQArgs q{};
+        q.a = base;
+        q.orb_sorted = orb_sorted;
+        q.aux_sorted = aux_sorted;
+        q.Jall = J;
+        q.seg = segd + p.cls_seg0[c];
+        q.nseg = p.cls_seg0[c + 1] - p.cls_seg0[c];
+        q.chunk = tt[c].chunk;
+        q.total = p.cls_items[c];
+        q.counter = ctr + c;
+        const ClassInfo &ci = g_cls[lp][la][lb];
+        const int64_t need = (q.total + int64_t(ci.tpw) * q.chunk - 1) / (int64_t(ci.tpw) * q.chunk);
+        const int grid = int(std::max<int64_t>(
+            1, std::min<int64_t>(need, int64_t(ds->ncu) * tt[c].grid_per_cu)));
+        if (ci.jq(q, grid, s) != hipSuccess) return DF3C_E_HIP;
+      }
+    } else {
+      for (int m = 0; m < nmol; ++m)
+        for (int c : order) {
+          const int lp = c / (NLA * NLA), la = (c / NLA) % NLA, lb = c % NLA;
+          for (int g = p.cls_seg0[c]; g < p.cls_seg0[c + 1]; ++g) {
+            const JSeg &sg = p.seg[g];
+            if (sg.pad != m) continue;
+            JArgs a = base;
+            a.ash = orb_sorted + sg.ash;
+            a.bsh = orb_sorted + sg.bsh;
+            a.na = sg.na;
+            a.nb = sg.nb;
+            a.same = sg.same;
+            a.psh = aux_sorted + sg.psh;
+            a.np = sg.np;
+            a.J = J + sg.jbase;
+            a.nao = sg.nao;
+            a.ao_base = sg.ao_base;
+            a.npair = sg.npair;
+            const ClassInfo &ci = g_cls[lp][la][lb];
+            if (ci.jfn(a, grid_for(a.npair, ci.tpw, ds->ncu), s) != hipSuccess) return DF3C_E_HIP;
+          }
+        }
+    }
+    return DF3C_OK;
+  };
+
+  if (!(flags & DF3C_GRAPH)) return enqueue();
+  // first call with DF3C_GRAPH: run once eagerly (sets kernel attributes), then
+  // capture the same launches and keep the executable graph
+  rc = enqueue();
+  if (rc) return rc;
+  hipGraph_t graph = nullptr;
+  if (hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) != hipSuccess) return DF3C_E_HIP;
+  rc = enqueue();
+  if (hipStreamEndCapture(s, &graph) != hipSuccess || rc) {
+    if (graph) hipGraphDestroy(graph);
+    return rc ? rc : DF3C_E_HIP;
+  }
+  hipGraphExec_t exec = nullptr;
+  const hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  hipGraphDestroy(graph);
+  if (ie != hipSuccess) return DF3C_E_HIP;
+  std::lock_guard<std::mutex> lk(g_graph_mu);
+  g_graphs[key].exec = exec;
   return DF3C_OK;
 }
 

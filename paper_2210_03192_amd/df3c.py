@@ -16,6 +16,27 @@ LIB_PATH = os.path.join(_HERE, "libdf3c.so")
 _lib = None
 
 DF3C_OK = 0
+SCHED_PER_CLASS = 0
+SCHED_PERSISTENT = 1
+GRAPH = 2
+NCLASS = 175
+
+
+class ClassTune(ctypes.Structure):
+    """Per-class schedule parameters of the persistent batched J."""
+    _fields_ = [("chunk", ctypes.c_int32), ("grid_per_cu", ctypes.c_int32),
+                ("enabled", ctypes.c_int32), ("order", ctypes.c_int32)]
+
+
+def class_index(lp: int, la: int, lb: int) -> int:
+    return (lp * 5 + la) * 5 + lb
+
+
+def default_tune():
+    t = (ClassTune * NCLASS)()
+    for c in range(NCLASS):
+        t[c] = ClassTune(1, 4, 1, -(c // 25))
+    return t
 
 
 class DF3CError(RuntimeError):
@@ -57,6 +78,9 @@ def lib():
         L.df3c_coulomb_J_grad_workspace.restype = SZ
         L.df3c_coulomb_J_grad_workspace.argtypes = [P, P, I32]
         L.df3c_coulomb_J_grad.argtypes = [P, I32, P, P, P, P, P, P, SZ, U32, P]
+        L.df3c_coulomb_J_batched_workspace.restype = SZ
+        L.df3c_coulomb_J_batched_workspace.argtypes = [P, P, I32]
+        L.df3c_coulomb_J_batched.argtypes = [P, I32, P, P, I32, P, P, P, P, P, P, SZ, U32, P]
         _lib = L
     return _lib
 
@@ -201,3 +225,35 @@ class CoulombJ(torch.autograd.Function):
 def J(xyz: torch.Tensor, d: torch.Tensor, aux: DeviceBasis, orb: DeviceBasis) -> torch.Tensor:
     """Differentiable DF-J build (see CoulombJ)."""
     return CoulombJ.apply(xyz, d, aux, orb)
+
+
+def coulomb_J_batched_workspace(aux: DeviceBasis, orb: DeviceBasis, nmol: int) -> int:
+    sa, so = aux.struct(), orb.struct()
+    return int(lib().df3c_coulomb_J_batched_workspace(ctypes.byref(sa), ctypes.byref(so),
+                                                      int(nmol)))
+
+
+def coulomb_J_batched(xyz: torch.Tensor, aux: DeviceBasis, orb: DeviceBasis,
+                      mol_orb: np.ndarray, mol_aux: np.ndarray, d: torch.Tensor,
+                      J: Optional[torch.Tensor] = None, tune=None, flags: int = SCHED_PERSISTENT,
+                      ws: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+    """J of every molecule, concatenated (molecule m's nao_m x nao_m block at
+    offset sum_{m'<m} nao_m'^2).  mol_orb / mol_aux: shell ranges per molecule."""
+    mol_orb = np.ascontiguousarray(mol_orb, np.int32)
+    mol_aux = np.ascontiguousarray(mol_aux, np.int32)
+    nmol = len(mol_orb) - 1
+    off = orb.offsets()
+    nao = off[mol_orb[1:]] - off[mol_orb[:-1]]
+    if J is None:
+        J = torch.empty(int((nao * nao).sum()), dtype=torch.float64, device=xyz.device)
+    need = coulomb_J_batched_workspace(aux, orb, nmol)
+    if ws is None or ws.numel() < need:
+        ws = torch.empty(max(need, 1), dtype=torch.uint8, device=xyz.device)
+    sa, so = aux.struct(), orb.struct()
+    tp = ctypes.cast(tune, ctypes.c_void_p) if tune is not None else None
+    _check(lib().df3c_coulomb_J_batched(_ptr(xyz), int(xyz.shape[0]), ctypes.byref(sa),
+                                        ctypes.byref(so), nmol, mol_orb.ctypes.data,
+                                        mol_aux.ctypes.data, _ptr(d), _ptr(J), tp, _ptr(ws),
+                                        ws.numel(), flags, _stream(stream)),
+           "df3c_coulomb_J_batched")
+    return J

@@ -317,3 +317,44 @@ def fitting_coefficients(naux: int, seed: int) -> np.ndarray:
 def symmetric_density(nao: int, seed: int) -> np.ndarray:
     X = np.random.default_rng(seed).normal(size=(nao, nao))
     return (X + X.T) / 2
+
+
+@dataclass
+class Batch:
+    """Several molecules in one system: shells of molecule m are
+    orb[mol_orb[m]:mol_orb[m+1]] and aux[mol_aux[m]:mol_aux[m+1]]."""
+    xyz: np.ndarray
+    orb: Basis
+    aux: Basis
+    mol_orb: np.ndarray
+    mol_aux: np.ndarray
+    systems: List[System]
+
+    @property
+    def nmol(self) -> int:
+        return len(self.systems)
+
+
+def _concat_basis(parts: List[Basis], atom_off: List[int]) -> Basis:
+    prim = 0
+    l, nprim, off, atom, exps, coefs = [], [], [], [], [], []
+    for b, ao in zip(parts, atom_off):
+        l.append(b.l)
+        nprim.append(b.nprim)
+        off.append(b.prim_off + prim)
+        atom.append(b.atom + ao)
+        exps.append(b.exps)
+        coefs.append(b.coefs)
+        prim += len(b.exps)
+    return Basis(np.concatenate(l).astype(np.int32), np.concatenate(nprim).astype(np.int32),
+                 np.concatenate(off).astype(np.int64), np.concatenate(atom).astype(np.int32),
+                 np.concatenate(exps), np.concatenate(coefs), parts[0].pure)
+
+
+def concat_systems(systems: List[System]) -> Batch:
+    atom_off = list(np.cumsum([0] + [len(s.xyz) for s in systems[:-1]]))
+    orb = _concat_basis([s.orb for s in systems], atom_off)
+    aux = _concat_basis([s.aux for s in systems], atom_off)
+    mol_orb = np.concatenate([[0], np.cumsum([s.orb.nshell for s in systems])]).astype(np.int32)
+    mol_aux = np.concatenate([[0], np.cumsum([s.aux.nshell for s in systems])]).astype(np.int32)
+    return Batch(np.concatenate([s.xyz for s in systems]), orb, aux, mol_orb, mol_aux, systems)
