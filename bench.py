@@ -43,7 +43,10 @@ def parse():
     p.add_argument("--ntrip", type=int, default=100000)
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-dfj", action="store_true")
-    p.add_argument("--batched-nmol", type=int, default=64)
+    p.add_argument("--batched-nmol", type=int, default=16)
+    p.add_argument("--copy-calibration-mib", type=int, default=0,
+                   help="first run a plain device copy of this many MiB three times "
+                        "(the reference kernel for hardware byte counters)")
     return p.parse_args()
 
 
@@ -171,33 +174,50 @@ def main():
     ws = torch.empty(df3c.eval_batch_workspace(args.ntrip), dtype=torch.uint8, device=dev)
     stream = torch.cuda.current_stream()
 
-    def step(times=None):
-        for key, g in gpu.items():
-            if times is not None:
-                e0 = torch.cuda.Event(enable_timing=True)
-                e1 = torch.cuda.Event(enable_timing=True)
-                e0.record(stream)
+    if args.copy_calibration_mib > 0:
+        n = args.copy_calibration_mib * (1 << 20) // 8
+        src = torch.ones(n, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            torch.mul(src, 1.0, out=dst)
+        torch.cuda.synchronize()
+        del src, dst
+
+    keys = list(gpu)
+
+    def step():
+        for key in keys:
+            g = gpu[key]
             df3c.eval_batch(g["xyz"], g["aux"], g["orb"], g["trip"], g["off"], out, ws=ws,
                             stream=stream)
-            if times is not None:
-                e1.record(stream)
-                times.setdefault(key, []).append((e0, e1))
 
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
-    times = {}
+    # every eval_batch of a per-class batch launches exactly one class kernel; the
+    # library brackets it with HIP events on the launch stream
+    df3c.timing_read()
+    df3c.timing_enable(True)
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        step(times)
+        step()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    df3c.timing_enable(False)
+    rec_t = [r for r in df3c.timing_read() if r[0] == df3c.KERNEL_STORE]
+    if len(rec_t) != len(keys) * args.steps:
+        raise RuntimeError(f"expected {len(keys) * args.steps} timed launches, got {len(rec_t)}")
+    times = {key: [] for key in keys}
+    for i, (_, cls_id, ms) in enumerate(rec_t):
+        key = keys[i % len(keys)]
+        assert cls_id == df3c.class_index(*key[0])
+        times[key].append(ms)
     ms_step = wall / args.steps * 1e3
     nint = sum(cb.nint for cb in batches.values())
     per_class = {}
     dom_key, dom_ms = None, 0.0
     for key, ev in times.items():
-        ms = float(np.mean([a.elapsed_time(b) for a, b in ev]))
+        ms = float(np.mean(ev))
         cb = batches[key]
         per_class[f"P{key[0][0]}a{key[0][1]}b{key[0][2]}_K{key[1]}"] = {
             "ms": ms, "integrals_per_s": cb.nint / (ms * 1e-3),
@@ -210,6 +230,8 @@ def main():
     roof = {"bound": "alu", "achieved": ach / 1e12, "peak": PEAK_FP64 / 1e12, "unit": "TFLOP/s",
             "frac": ach / PEAK_FP64, "traffic": None,
             "kernel": f"k_store<{dom_key[0][0]},{dom_key[0][1]},{dom_key[0][2]}> K={dom_key[1]}",
+            "kernel_ms": dom_ms, "model_flop_per_triplet": MODEL_FLOP[dom_key],
+            "triplets_per_launch": cbd.ntrip,
             "hbm_write_GBps": cbd.nint * 8 / (dom_ms * 1e-3) / 1e9}
 
     extra = {}

@@ -174,6 +174,25 @@ int df3c_coulomb_J_batched(const double *xyz, int32_t natom, const df3c_shells *
                            const df3c_class_tune *tune, void *ws, size_t ws_bytes,
                            uint32_t flags, void *stream);
 
+/* ---------------------------------------------------------------- timing
+ * Launch timing for measurement.  While enabled, every class-kernel launch of
+ * the entry points above that is not being captured into a graph is bracketed
+ * by two HIP events recorded on the launch's stream (one record per launch:
+ * kind, class id (L_P * 5 + l_a) * 5 + l_b, duration).  Recording adds two
+ * event records per launch and nothing else.  Not thread-safe against calls
+ * that launch on other threads while df3c_timing_read runs. */
+#define DF3C_KERNEL_STORE 0  /* df3c_eval_batch block kernel */
+#define DF3C_KERNEL_J 1      /* DF-J pair kernel (single molecule, per-class batched) */
+#define DF3C_KERNEL_GRAD 2   /* J-gradient kernel */
+#define DF3C_KERNEL_JQ 3     /* persistent work-queue DF-J kernel */
+int df3c_timing_enable(int32_t on);
+
+/* Waits for the recorded launches, writes the first min(n, cap) of them to
+ * kind/cls/ms (HOST arrays of cap entries) and forgets all n of them.  Returns
+ * n (>= 0) or a negative status (DF3C_E_ARG for cap < 0 or a null array with
+ * cap > 0, DF3C_E_HIP). */
+int64_t df3c_timing_read(int32_t *kind, int32_t *cls, float *ms, int64_t cap);
+
 /* Readable name of a status code (static string). */
 const char *df3c_status_string(int status);
 

@@ -68,7 +68,7 @@ typedef double real;
 #define R_PI 3.141592653589793238462643383279502884
 #endif
 
-#define LMAX_ORB 6  /* orbital shells, including the +1 of the gradient */
+#define LMAX_ORB 9  /* orbital shells, including the +1 of the gradient */
 #define LMAX_AUX 8  /* auxiliary shells, including the +1 of the gradient */
 #define MMAX_BOYS 40
 

@@ -1,8 +1,8 @@
 // Device building blocks of the gfx950 (ab|P) pipeline.
 //
-// One "team" of TS lanes (TS divides 64) evaluates one contracted shell
-// triplet at a time; a workgroup is exactly one wavefront, so team-level
-// synchronisation is a workgroup barrier of a single wave.  Intermediates live
+// One "team" of TS lanes evaluates one contracted shell triplet at a time
+// (TS <= 64: several teams share one wavefront; TS = 128 / 256: a team spans
+// 2 / 4 wavefronts); team synchronisation is a workgroup barrier.  Intermediates live
 // in the team's LDS slice between stages; every stage is lane-parallel over the
 // items it produces (the paper's intra-shell-set parallelism, Section 2.2).
 #pragma once
@@ -96,20 +96,12 @@ __device__ __forceinline__ void vrr1(double *prims, int npc, int tid) {
   using S = VStages<L>;
   static_for<S::nstage>([&](auto sc) {
     constexpr int s = decltype(sc)::value;
-    constexpr int j = S::hi(s);
-    constexpr bool twoq = S::two_q(s);
     constexpr int NIT = S::nitems(s);
     constexpr int IOFF = S::items_off(s);
-    // input state: upper level hu, lower level hl (may be -1)
-    constexpr int hu = twoq ? j - 2 : j - 1;
-    constexpr int hl = hu - 1;
-    constexpr int wl = (hl >= 0) ? ncart(hl) * (L - hl) : 0;  // lower input size
-    constexpr int WIN_L = 0, WIN_U = wl;
-    // output placement
-    constexpr int WOUT_LO = 0;                                       // level j-1 (2-q)
-    constexpr int WOUT_HI = twoq ? ncart(j - 1) * (L - j + 1) : L;   // level j
     constexpr int MAXIT = (NIT * PCH + TS - 1) / TS;
     using V = GenV<L>;
+
+    static_assert(V::NT == G::NT && V::NW == G::NW, "generated VRR1 tables out of date");
 
     double res[MAXIT];
     int dst[MAXIT];
@@ -120,42 +112,24 @@ __device__ __forceinline__ void vrr1(double *prims, int npc, int tid) {
       dst[q] = -1;
       if (it < tot) {
         const int pp = it / NIT, x = it - pp * NIT;
-        double *P = prims + pp * REC;
-        const double *Tr = P + PS_N;
-        const double *W = Tr + G::NT;
-        const VI v = V::it[IOFF + x];
-        const int m = v.m;
-        // stored levels: value(level, comp, mm)
-        auto up = [&](int c, int mm) -> double {
-          return mm == 0 ? Tr[offT(hu) + c] : W[WIN_U + (mm - 1) * ncart(hu) + c];
-        };
-        auto lw = [&](int c, int mm) -> double {
-          return mm == 0 ? Tr[offT(hl) + c] : W[WIN_L + (mm - 1) * ncart(hl) + c];
-        };
+        const double *P = prims + pp * REC;
+        const double *T = P + PS_N;
+        const VO o = V::ofs[IOFF + x];
+        const int ip = (o.ax >> 2) & 3;
         const double i2g = P[PS_I2G], rg = P[PS_RG];
-        double val;
-        if (v.q == 0) {
-          const int i = v.i;
-          val = P[PS_PAX + i] * up(v.a1, m) - P[PS_RPX + i] * up(v.a1, m + 1);
-          if (v.a2 >= 0) val += double(v.f1) * i2g * (lw(v.a2, m) - rg * lw(v.a2, m + 1));
-        } else {
-          const int i = v.i, ip = v.ip;
-          // x = e - 1_i (level j-1) at m and m+1, built in registers from the
-          // stored levels j-2 (upper input) and j-3 (lower input)
-          double X0 = P[PS_PAX + ip] * up(v.a1, m) - P[PS_RPX + ip] * up(v.a1, m + 1);
-          double X1 = P[PS_PAX + ip] * up(v.a1, m + 1) - P[PS_RPX + ip] * up(v.a1, m + 2);
-          if (v.a2 >= 0) {
-            X0 += double(v.f1) * i2g * (lw(v.a2, m) - rg * lw(v.a2, m + 1));
-            X1 += double(v.f1) * i2g * (lw(v.a2, m + 1) - rg * lw(v.a2, m + 2));
-          }
-          val = P[PS_PAX + i] * X0 - P[PS_RPX + i] * X1;
-          if (v.y >= 0) val += double(v.f2) * i2g * (up(v.y, m) - rg * up(v.y, m + 1));
+        const double pa = P[PS_PAX + ip], rp = P[PS_RPX + ip];
+        const double c1 = double(o.f1) * i2g;
+        const double u1 = T[o.u1], l1 = T[o.l1];
+        double val = pa * T[o.u0] - rp * u1 + c1 * (T[o.l0] - rg * l1);
+        if (o.ax & 16) {
+          // 2-q: val is [x]^(m); [x]^(m+1), then the outer step along i
+          const int i = o.ax & 3;
+          const double x1 = pa * u1 - rp * T[o.u2] + c1 * (l1 - rg * T[o.l2]);
+          val = P[PS_PAX + i] * val - P[PS_RPX + i] * x1 +
+                double(o.f2) * i2g * (T[o.y0] - rg * T[o.y1]);
         }
         res[q] = val;
-        const int lvl = (v.q == 1 || !twoq) ? j : j - 1;
-        const int wout = (lvl == j) ? WOUT_HI : WOUT_LO;
-        dst[q] = pp * REC + PS_N +
-                 (m == 0 ? offT(lvl) + v.c : G::NT + wout + (m - 1) * ncart(lvl) + v.c);
+        dst[q] = pp * REC + PS_N + o.dst;
       }
     }
     team_sync();

@@ -175,6 +175,46 @@ def solid(l):
     return [rows[m] for m in range(-l, l + 1)]
 
 
+# ---------------------------------------------------------------- J engine
+def hterms(LP):
+    """H_u = sum_{c >= u, |c| = LP} d'_c C(c, u) W^{c-u} for every u with
+    |u| <= LP: per u (flat index offT(|u|) + idx(u)) the terms
+    (c index within level LP, flat index of the monomial c - u, C(c, u))."""
+    start, cidx_, mono, coef = [], [], [], []
+    for k in range(LP + 1):
+        for u in carts(k):
+            start.append(len(cidx_))
+            for ci, c in enumerate(carts(LP)):
+                if all(c[i] >= u[i] for i in range(3)):
+                    m = tuple(c[i] - u[i] for i in range(3))
+                    cidx_.append(ci)
+                    mono.append(offT(sum(m)) + cidx(m))
+                    coef.append(math.comb(c[0], u[0]) * math.comb(c[1], u[1]) * math.comb(c[2], u[2]))
+    start.append(len(cidx_))
+    return start, cidx_, mono, coef
+
+
+def xterms(LP, EA, EB):
+    """X_e += sum_{u <= e, |u| <= LP} e!/(e-u)! H_u V_{e-u}: per target e
+    (levels EA..EB) the terms (flat u, flat e - u, e!/(e-u)!)."""
+    start, uu, vv, coef = [], [], [], []
+    for lev in range(EA, EB + 1):
+        for e in carts(lev):
+            start.append(len(uu))
+            for ux in range(e[0] + 1):
+                for uy in range(e[1] + 1):
+                    for uz in range(e[2] + 1):
+                        if ux + uy + uz > LP:
+                            continue
+                        u = (ux, uy, uz)
+                        r = tuple(e[i] - u[i] for i in range(3))
+                        uu.append(offT(sum(u)) + cidx(u))
+                        vv.append(offT(sum(r)) + cidx(r))
+                        coef.append(math.perm(e[0], ux) * math.perm(e[1], uy) * math.perm(e[2], uz))
+    start.append(len(uu))
+    return start, uu, vv, coef
+
+
 # ----------------------------------------------------------------------- HRR
 def hrr(LA, LB):
     hc_start, hc_pow, hc_binom = [], [], []
@@ -245,6 +285,54 @@ def vtab(L):
     return items
 
 
+def vofs(L):
+    """Operand and destination offsets of every VRR1 item, relative to the T
+    region of a primitive record (the layout of device.hpp's vrr1): T holds the
+    m = 0 values of all levels at offT(level) + c; W (at NT) holds the higher m
+    of the two most recent levels, the lower one first.  Per item:
+    (u0, u1, u2, l0, l1, l2, y0, y1, dst, axes, f1, f2) with
+    axes = i | ip << 2 | q << 4 (for a 1-quantal item ip = i).  A missing operand
+    points at offset 0 and has a zero coefficient."""
+    NT = offT(L + 1)
+    items = vtab(L)
+    out, k = [], 0
+    for j, twoq in vstages(L):
+        hu = j - 2 if twoq else j - 1
+        hl = hu - 1
+        win_u = ncart(hl) * (L - hl) if hl >= 0 else 0
+        wout_hi = ncart(j - 1) * (L - j + 1) if twoq else L
+        n = ncart(j) * (L - j + 1) + (ncart(j - 1) * (L - j + 2) if twoq else 0)
+
+        def up(c, mm):
+            return offT(hu) + c if mm == 0 else NT + win_u + (mm - 1) * ncart(hu) + c
+
+        def lw(c, mm):
+            if c < 0:
+                return 0
+            return offT(hl) + c if mm == 0 else NT + (mm - 1) * ncart(hl) + c
+
+        for (q, c, m, i, ip, a1, a2, f1, y, f2) in items[k:k + n]:
+            lvl = j if (q == 1 or not twoq) else j - 1
+            wout = wout_hi if lvl == j else 0
+            dst = offT(lvl) + c if m == 0 else NT + wout + (m - 1) * ncart(lvl) + c
+            if q == 0:
+                assert (a2 >= 0) or f1 == 0
+                out.append((up(a1, m), up(a1, m + 1), 0, lw(a2, m), lw(a2, m + 1), 0, 0, 0, dst,
+                            i | (i << 2), f1, 0))
+            else:
+                assert (a2 >= 0 or f1 == 0) and (y >= 0 or f2 == 0)
+                yy = (up(y, m), up(y, m + 1)) if y >= 0 else (0, 0)
+                out.append((up(a1, m), up(a1, m + 1), up(a1, m + 2), lw(a2, m), lw(a2, m + 1),
+                            lw(a2, m + 2), yy[0], yy[1], dst, i | (ip << 2) | 16, f1, f2))
+        k += n
+    assert k == len(items)
+    nw = L
+    for j in range(1, L + 1):
+        nw = max(nw, (ncart(j - 1) * (L - j + 1)) + ncart(j) * (L - j))
+    assert all(0 <= x < NT + nw for t in out for x in t[:9])
+    return out, NT, nw
+
+
 # -------------------------------------------------------------------- output
 def arr(ctype, name, vals):
     if not vals:
@@ -295,6 +383,11 @@ def write(outdir):
             s.append(arr("int32_t", "cb_start", st))
             s.append(arr("int16_t", "cb_pi", pi))
             s.append(arr("int32_t", "cb_w", w))
+            xs, xu, xv, xc = xterms(LP, EA, EB)
+            s.append(arr("int16_t", "xt_start", xs))
+            s.append(arr("int16_t", "xt_u", xu))
+            s.append(arr("int16_t", "xt_v", xv))
+            s.append(arr("int32_t", "xt_c", xc))
             s.append("};\n")
         s.append("}  // namespace df3c\n")
         _write_if_changed(os.path.join(outdir, f"tables_lp{LP}.hpp"), "".join(s))
@@ -315,6 +408,11 @@ def write(outdir):
         s.append(arr("int16_t", "col", col))
         s.append(arr("double", "val", val))
         s.append(arr("double", "dense", [repr(x) for r in rows for x in r]))
+        hs, hc, hm, hk = hterms(l)
+        s.append(arr("int16_t", "ht_start", hs))
+        s.append(arr("int16_t", "ht_c", hc))
+        s.append(arr("int16_t", "ht_m", hm))
+        s.append(arr("int32_t", "ht_k", hk))
         s.append("};\n")
     for la in range(LMAX_ORB + 1):
         for lb in range(LMAX_ORB + 1):
@@ -330,7 +428,9 @@ def write(outdir):
         items = vtab(L)
         s.append(f"template <> struct GenV<{L}> {{\n")
         s.append(f"  static constexpr int N = {len(items)};\n")
-        s.append(arr("VI", "it", ["{" + ",".join(str(x) for x in t) + "}" for t in items]))
+        ofs, nt, nw = vofs(L)
+        s.append(f"  static constexpr int NT = {nt}, NW = {nw};\n")
+        s.append(arr("VO", "ofs", ["{" + ",".join(str(x) for x in t) + "}" for t in ofs]))
         s.append("};\n")
     s.append("}  // namespace df3c\n")
     _write_if_changed(os.path.join(outdir, "tables_common.hpp"), "".join(s))

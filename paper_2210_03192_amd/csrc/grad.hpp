@@ -76,6 +76,7 @@ struct GradCfg {
   static constexpr int BLK = TS > 64 ? TS : 64;
   static constexpr int TPB = BLK / TS;
   static constexpr int TEAM = GradLayout<LP, LA, LB, PCH>::TEAM;
+  static constexpr int WPE = TS >= 128 ? DF3C_MIN_WAVES_BIG : TS == 64 ? DF3C_MIN_WAVES_WAVE : 1;
   // dynamic LDS for natom atoms
   static constexpr int lds(int natom) { return TPB * (TEAM + 3 * natom) * 8; }
 };
@@ -136,7 +137,8 @@ __device__ __forceinline__ void grad_hrr(double *S, int tid, const double *pwx, 
 }
 
 template <int LP, int LA, int LB, int TS, int PCH>
-__global__ void __launch_bounds__(TS > 64 ? TS : 64) k_grad(GradArgs g) {
+__global__ void __launch_bounds__(TS > 64 ? TS : 64)
+    __attribute__((amdgpu_waves_per_eu(GradCfg<LP, LA, LB>::WPE))) k_grad(GradArgs g) {
   using GL = GradLayout<LP, LA, LB, PCH>;
   constexpr int BLK = TS > 64 ? TS : 64;
   constexpr int TPB = BLK / TS;

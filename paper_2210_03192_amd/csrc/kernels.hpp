@@ -79,6 +79,17 @@ struct Layout {
 
 // Team size and primitive chunk per class: small classes run one triplet per
 // lane (or per few lanes), large ones one triplet per one to four wavefronts.
+// Minimum waves per SIMD asked of the register allocator for teams of 2-4
+// waves and of one wave.  Two waves per SIMD let one team's barriers and LDS
+// latency overlap another's work; measured faster than one wave with more
+// registers even where it costs a few spills.
+#ifndef DF3C_MIN_WAVES_BIG
+#define DF3C_MIN_WAVES_BIG 2
+#endif
+#ifndef DF3C_MIN_WAVES_WAVE
+#define DF3C_MIN_WAVES_WAVE 2
+#endif
+
 template <int LP, int LA, int LB>
 struct Cfg {
   using G = Geo<LP, LA, LA + LB>;
@@ -90,6 +101,8 @@ struct Cfg {
   static constexpr int BLK = TS > 64 ? TS : 64;
   static constexpr int LDS = (BLK / TS) * Layout<LP, LA, LB, PCH>::TOTAL * 8;
   static constexpr int LDS_J = (BLK / TS) * (Layout<LP, LA, LB, PCH>::TOTAL + G::NE) * 8;
+  // minimum waves per SIMD requested from the register allocator
+  static constexpr int WPE = TS >= 128 ? DF3C_MIN_WAVES_BIG : TS == 64 ? DF3C_MIN_WAVES_WAVE : 1;
   static_assert(LDS_J <= 160 * 1024, "class does not fit the LDS of a CU");
 };
 
@@ -112,6 +125,40 @@ __device__ __forceinline__ int pi_slot(int r) {
   });
   return code;
 }
+
+// ---------------------------------------------------------------------------
+// Prerequisite contraction on the FP64 matrix cores.  For each k the block
+//   pi_k[n][e'] = sum_prim sW_k[n](prim) V[e'](prim),  V = [e'0|0]^(LP),
+// is an ncart(LP-k) x K times K x nek(k) product over the K primitives of the
+// triplet.  The output is cut into 16 x 16 tiles; each chunk of 4 primitives
+// adds one v_mfma_f64_16x16x4 per tile (lane l supplies A[l%16][l/16] and
+// B[l/16][l%16]; it holds D[4v + l/16][l%16], v < 4).  Tiles are dealt
+// round-robin to the waves of the team.
+// ---------------------------------------------------------------------------
+typedef double dbl4 __attribute__((ext_vector_type(4)));
+
+template <class G>
+struct PiTiles {
+  static constexpr int nr(int k) { return (ncart(G::LP - k) + 15) / 16; }
+  static constexpr int nc(int k) { return (G::nek(k) + 15) / 16; }
+  static constexpr int count() {
+    int n = 0;
+    for (int k = 0; k <= G::LP; ++k)
+      if (G::nek(k) > 0) n += nr(k) * nc(k);
+    return n;
+  }
+  static constexpr int N = count();
+  // tile t -> (k, first row, first column), tiles ordered by k, row, column
+  static constexpr int field(int t, int which) {
+    for (int k = 0; k <= G::LP; ++k) {
+      if (G::nek(k) == 0) continue;
+      const int n = nr(k) * nc(k);
+      if (t < n) return which == 0 ? k : which == 1 ? 16 * (t / nc(k)) : 16 * (t % nc(k));
+      t -= n;
+    }
+    return -1;
+  }
+};
 
 // ---------------------------------------------------------------------------
 // The per-triplet pipeline up to (e0|P) in LDS (region EM of the layout).
@@ -140,14 +187,29 @@ __device__ __forceinline__ void triplet_to_e0P(const double *btab, double *S, in
   const double AB2 = ABx * ABx + ABy * ABy + ABz * ABz;
   const int K = Ka * Kb * Kc;
 
-  double acc[NQ];
+  // matrix-core contraction for whole-wave teams (chunks of 4 primitives = the
+  // K extent of one MFMA); per-lane register slots otherwise
+  constexpr bool MF = (TS % 64 == 0) && PCH == 4;
+  using PT = PiTiles<G>;
+  constexpr int NWV = TS >= 64 ? TS / 64 : 1;
+  constexpr int NTW = MF ? (PT::N + NWV - 1) / NWV : 1;
+  constexpr int NQA = MF ? 1 : NQ;
+  const int wv = tid >> 6, pl = (tid & 63) >> 4, il = tid & 15;
+  dbl4 macc[NTW];
 #pragma unroll
-  for (int q = 0; q < NQ; ++q) acc[q] = 0.0;
+  for (int j = 0; j < NTW; ++j) macc[j] = dbl4{0.0, 0.0, 0.0, 0.0};
+  double acc[NQA];
+#pragma unroll
+  for (int q = 0; q < NQA; ++q) acc[q] = 0.0;
 
   for (int p0 = 0; p0 < npmax; p0 += PCH) {
     const int npc = imax(0, imin(PCH, K - p0));
+    // the lane index is re-read every chunk: lane-dependent addresses are then
+    // recomputed per chunk instead of being hoisted and kept live (spilled)
+    int lt = tid;
+    __asm__ volatile("" : "+v"(lt));
     // ---- setup, Boys, level 0 of VRR1 and the CVRR2 monomials sW
-    for (int pp = tid; pp < npc; pp += TS) {
+    for (int pp = lt; pp < npc; pp += TS) {
       const int p = p0 + pp;
       const int ic = p % Kc, rest = p / Kc;
       const int ib = rest % Kb, ia = rest / Kb;
@@ -204,27 +266,72 @@ __device__ __forceinline__ void triplet_to_e0P(const double *btab, double *S, in
     }
     team_sync();
     // ---- VRR1, 2-quantal stages in place
-    vrr1<G, TS, PCH, REC>(prims, npc, tid);
-    // ---- early contraction of the CVRR2 prerequisites (register accumulators)
-#pragma unroll
-    for (int q = 0; q < NQ; ++q) {
-      const int r = tid + q * TS;
-      const int code = slot ? slot[q] : (r < G::NPI ? pi_slot<G>(r) : -1);
-      if (code >= 0) {
-        const int isw = G::NV1 + (code >> 16), iv = code & 0xffff;
-        double a = acc[q];
-        for (int pp = 0; pp < npc; ++pp) {
-          const double *R = prims + pp * REC + PS_N;
-          a += R[isw] * R[iv];
+    vrr1<G, TS, PCH, REC>(prims, npc, lt);
+    // ---- early contraction of the CVRR2 prerequisites
+    if constexpr (MF) {
+      // lane (pl, il): primitive pl of the chunk, row / column il of a tile
+      const int wl = lt >> 6, pc = (lt & 63) >> 4, cl = lt & 15;
+      const double *Rl = prims + pc * REC + PS_N + cl;
+      const bool pv = pc < npc;
+      static_for<NWV>([&](auto wc) {
+        constexpr int W = decltype(wc)::value;
+        if (wl == W) {
+          static_for<NTW>([&](auto jc) {
+            constexpr int j = decltype(jc)::value;
+            constexpr int t = j * NWV + W;
+            if constexpr (t < PT::N) {
+              constexpr int k = PT::field(t, 0), r0 = PT::field(t, 1), c0 = PT::field(t, 2);
+              constexpr int nr = ncart(LP - k) - r0, nc = G::nek(k) - c0;
+              const double av = (pv && cl < nr) ? Rl[G::NV1 + G::sw_off(k) + r0] : 0.0;
+              const double bv = (pv && cl < nc) ? Rl[offT(G::emin(k)) + c0] : 0.0;
+              macc[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, macc[j], 0, 0, 0);
+            }
+          });
         }
-        acc[q] = a;
+      });
+    } else {
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) {
+        const int r = lt + q * TS;
+        const int code = slot ? slot[q] : (r < G::NPI ? pi_slot<G>(r) : -1);
+        if (code >= 0) {
+          const int isw = G::NV1 + (code >> 16), iv = code & 0xffff;
+          double a = acc[q];
+          for (int pp = 0; pp < npc; ++pp) {
+            const double *R = prims + pp * REC + PS_N;
+            a += R[isw] * R[iv];
+          }
+          acc[q] = a;
+        }
       }
     }
     team_sync();
   }
+  if constexpr (MF) {
+    static_for<NWV>([&](auto wc) {
+      constexpr int W = decltype(wc)::value;
+      if (wv == W) {
+        static_for<NTW>([&](auto jc) {
+          constexpr int j = decltype(jc)::value;
+          constexpr int t = j * NWV + W;
+          if constexpr (t < PT::N) {
+            constexpr int k = PT::field(t, 0), r0 = PT::field(t, 1), c0 = PT::field(t, 2);
+            constexpr int nr = ncart(LP - k) - r0, nc = G::nek(k) - c0;
+            constexpr int base = G::pi_off(k) + r0 * G::nek(k) + c0;
 #pragma unroll
-  for (int q = 0; q < NQ; ++q)
-    if (tid + q * TS < G::NPI) PI[tid + q * TS] = acc[q];
+            for (int v = 0; v < 4; ++v) {
+              const int r = 4 * v + pl;
+              if (r < nr && il < nc) PI[base + r * G::nek(k) + il] = macc[j][v];
+            }
+          }
+        });
+      }
+    });
+  } else {
+#pragma unroll
+    for (int q = 0; q < NQ; ++q)
+      if (tid + q * TS < G::NPI) PI[tid + q * TS] = acc[q];
+  }
   team_sync();
   // ---- n-quantal CVRR2 in place on pi_0: (e0|c) += sum_{u != 0} w pi_{|u|}(e-u, c-u)
   for (int t = tid; t < TB::NTGT; t += TS) {
@@ -393,7 +500,8 @@ __device__ __forceinline__ void make_slots(int *slot, int tid) {
 // store digestion: one triplet per team, blocks written to out + out_off[t]
 // ---------------------------------------------------------------------------
 template <int LP, int LA, int LB, int TS, int PCH>
-__global__ void __launch_bounds__(TS > 64 ? TS : 64) k_store(StoreArgs a) {
+__global__ void __launch_bounds__(TS > 64 ? TS : 64)
+    __attribute__((amdgpu_waves_per_eu(Cfg<LP, LA, LB>::WPE))) k_store(StoreArgs a) {
   using G = Geo<LP, LA, LA + LB>;
   using LY = Layout<LP, LA, LB, PCH>;
   constexpr int BLK = TS > 64 ? TS : 64;
@@ -572,7 +680,8 @@ __device__ __forceinline__ void j_pair(const JArgs &a, double *S, int tid, const
 }
 
 template <int LP, int LA, int LB, int TS, int PCH>
-__global__ void __launch_bounds__(TS > 64 ? TS : 64) k_J(JArgs a) {
+__global__ void __launch_bounds__(TS > 64 ? TS : 64)
+    __attribute__((amdgpu_waves_per_eu(Cfg<LP, LA, LB>::WPE))) k_J(JArgs a) {
   using G = Geo<LP, LA, LA + LB>;
   using JL = JLayout<LP, LA, LB, TS, PCH>;
   constexpr int BLK = TS > 64 ? TS : 64;

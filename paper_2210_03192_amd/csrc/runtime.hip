@@ -105,6 +105,47 @@ bool shells_ok(const df3c_shells *b) {
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
+// ------------------------------------------------------- launch timing
+// When enabled, every class-kernel launch outside graph capture is bracketed by
+// a pair of HIP events recorded on its stream; df3c_timing_read returns the
+// durations.  Events are pooled and reused across reads.
+struct TimedLaunch {
+  int kind, cls, dev;
+  hipEvent_t e0, e1;
+};
+bool g_timing = false;
+std::vector<TimedLaunch> g_tl;
+size_t g_tl_used = 0;
+
+template <class F>
+hipError_t timed(int kind, int cls, hipStream_t s, F &&launch) {
+  hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+  if (!g_timing || hipStreamIsCapturing(s, &cap) != hipSuccess ||
+      cap != hipStreamCaptureStatusNone)
+    return launch();
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  std::lock_guard<std::mutex> lk(g_mu);
+  if (g_tl_used == g_tl.size()) g_tl.push_back(TimedLaunch{0, 0, -1, nullptr, nullptr});
+  TimedLaunch &t = g_tl[g_tl_used];
+  if (t.dev != dev) {
+    if (t.e0) (void)hipEventDestroy(t.e0);
+    if (t.e1) (void)hipEventDestroy(t.e1);
+    t.e0 = t.e1 = nullptr;
+    if ((e = hipEventCreate(&t.e0)) != hipSuccess || (e = hipEventCreate(&t.e1)) != hipSuccess)
+      return e;
+    t.dev = dev;
+  }
+  t.kind = kind;
+  t.cls = cls;
+  if ((e = hipEventRecord(t.e0, s)) != hipSuccess) return e;
+  if ((e = launch()) != hipSuccess) return e;
+  if ((e = hipEventRecord(t.e1, s)) != hipSuccess) return e;
+  ++g_tl_used;
+  return hipSuccess;
+}
+
 // ------------------------------------------------------------ small kernels
 __global__ void k_fill_i32(int *p, int n, int v) {
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = v;
@@ -248,6 +289,36 @@ int df3c_init(void) {
   return init_device(&s);
 }
 
+int df3c_timing_enable(int32_t on) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  g_timing = on != 0;
+  return DF3C_OK;
+}
+
+int64_t df3c_timing_read(int32_t *kind, int32_t *cls, float *ms, int64_t cap) {
+  if (cap < 0 || (cap > 0 && (!kind || !cls || !ms))) return DF3C_E_ARG;
+  std::lock_guard<std::mutex> lk(g_mu);
+  const int64_t n = int64_t(g_tl_used);
+  int cur = 0;
+  if (hipGetDevice(&cur) != hipSuccess) return DF3C_E_HIP;
+  int rc = DF3C_OK;
+  for (int64_t i = 0; i < n && i < cap; ++i) {
+    const TimedLaunch &t = g_tl[size_t(i)];
+    if (t.dev != cur && hipSetDevice(t.dev) != hipSuccess) { rc = DF3C_E_HIP; break; }
+    float v = 0.f;
+    if (hipEventSynchronize(t.e1) != hipSuccess || hipEventElapsedTime(&v, t.e0, t.e1) != hipSuccess) {
+      rc = DF3C_E_HIP;
+      break;
+    }
+    kind[i] = t.kind;
+    cls[i] = t.cls;
+    ms[i] = v;
+  }
+  g_tl_used = 0;
+  if (hipSetDevice(cur) != hipSuccess) return DF3C_E_HIP;
+  return rc ? rc : n;
+}
+
 const char *df3c_status_string(int status) {
   switch (status) {
     case DF3C_OK: return "ok";
@@ -327,7 +398,9 @@ int df3c_eval_batch(const double *xyz, int32_t natom, const df3c_shells *aux,
     const ClassInfo &ci = g_cls[lp][la][lb];
     a.bucket = bucket + off;
     a.count = counts[c];
-    if (ci.store(a, grid_for(counts[c], ci.tpw, ds->ncu), s) != hipSuccess) return DF3C_E_HIP;
+    if (timed(DF3C_KERNEL_STORE, c, s,
+              [&] { return ci.store(a, grid_for(counts[c], ci.tpw, ds->ncu), s); }) != hipSuccess)
+      return DF3C_E_HIP;
     off += counts[c];
   }
   return DF3C_OK;
@@ -456,7 +529,10 @@ int df3c_coulomb_J(const double *xyz, int32_t natom, const df3c_shells *aux,
         a.same = (la == lb);
         a.npair = (la == lb) ? int64_t(na) * (na + 1) / 2 : int64_t(na) * nb;
         const ClassInfo &ci = g_cls[lp][la][lb];
-        if (ci.jfn(a, grid_for(a.npair, ci.tpw, ds->ncu), s) != hipSuccess) return DF3C_E_HIP;
+        const int c = (lp * NLA + la) * NLA + lb;
+        if (timed(DF3C_KERNEL_J, c, s,
+                  [&] { return ci.jfn(a, grid_for(a.npair, ci.tpw, ds->ncu), s); }) != hipSuccess)
+          return DF3C_E_HIP;
       }
   }
   return DF3C_OK;
@@ -568,7 +644,9 @@ int df3c_coulomb_J_grad(const double *xyz, int32_t natom, const df3c_shells *aux
         if (lds > 160 * 1024) return DF3C_E_UNSUPPORTED;
         const int grid = int(std::max<int64_t>(1, std::min<int64_t>((a.npair + gi.tpb - 1) / gi.tpb,
                                                                      grid_cap)));
-        if (gi.gfn(a, grid, lds, s) != hipSuccess) return DF3C_E_HIP;
+        if (timed(DF3C_KERNEL_GRAD, (lp * NLA + la) * NLA + lb, s,
+                  [&] { return gi.gfn(a, grid, lds, s); }) != hipSuccess)
+          return DF3C_E_HIP;
       }
   }
   const int n = 3 * natom;
@@ -825,7 +903,8 @@ int df3c_coulomb_J_batched(const double *xyz, int32_t natom, const df3c_shells *
         const int64_t need = (q.total + int64_t(ci.tpw) * q.chunk - 1) / (int64_t(ci.tpw) * q.chunk);
         const int grid = int(std::max<int64_t>(
             1, std::min<int64_t>(need, int64_t(ds->ncu) * tt[c].grid_per_cu)));
-        if (ci.jq(q, grid, s) != hipSuccess) return DF3C_E_HIP;
+        if (timed(DF3C_KERNEL_JQ, c, s, [&] { return ci.jq(q, grid, s); }) != hipSuccess)
+          return DF3C_E_HIP;
       }
     } else {
       for (int m = 0; m < nmol; ++m)
@@ -847,7 +926,10 @@ int df3c_coulomb_J_batched(const double *xyz, int32_t natom, const df3c_shells *
             a.ao_base = sg.ao_base;
             a.npair = sg.npair;
             const ClassInfo &ci = g_cls[lp][la][lb];
-            if (ci.jfn(a, grid_for(a.npair, ci.tpw, ds->ncu), s) != hipSuccess) return DF3C_E_HIP;
+            if (timed(DF3C_KERNEL_J, c, s, [&] {
+                  return ci.jfn(a, grid_for(a.npair, ci.tpw, ds->ncu), s);
+                }) != hipSuccess)
+              return DF3C_E_HIP;
           }
         }
     }

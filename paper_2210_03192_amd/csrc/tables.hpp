@@ -144,18 +144,21 @@ struct VStages {
 };
 
 
-// VRR1 stage item (decoded by device.hpp; the tables are generated)
-struct VI {
-  int8_t q;    // 0: 1-quantal from stored levels, 1: 2-quantal
-  int8_t c;    // output component
-  int8_t m;    // m - LP
-  int8_t i;    // direction of the outer step (2-q) / the step (1-q)
-  int8_t ip;   // direction of the inner step (2-q)
-  int8_t a1;   // 1-q: e-1_i in the upper input;  2-q: x-1_ip in the upper input
-  int8_t a2;   // 1-q: e-2_i in the lower input;  2-q: x-2_ip in the lower input (-1: none)
-  int8_t f1;   // 1-q: e_i - 1;  2-q: x_ip - 1
-  int8_t y;    // 2-q: e-2_i in the upper input (-1: none)
-  int8_t f2;   // 2-q: e_i - 1
+// VRR1 stage item: operand and destination offsets (doubles) relative to the
+// T region of a primitive record, and the coefficients of Eq. vrr1.
+//   1-quantal (q = 0), step along i:
+//     [e]^(m) = PA_i [e-1_i]^(m) - (rho/gamma) PC_i [e-1_i]^(m+1)
+//               + f1/(2 gamma) ([e-2_i]^(m) - (rho/gamma) [e-2_i]^(m+1))
+//   2-quantal (q = 1): the same step along ip gives [x]^(m), [x]^(m+1) of
+//     x = e - 1_i in registers, then one step along i (lower term via y = e-2_i).
+// A missing operand points at offset 0 and carries a zero coefficient.
+struct alignas(8) VO {
+  int16_t u0, u1, u2;  // upper input at m, m+1, m+2
+  int16_t l0, l1, l2;  // lower input at m, m+1, m+2
+  int16_t y0, y1;      // 2-q: e-2_i (upper input level) at m, m+1
+  int16_t dst;         // output
+  int16_t ax;          // i | ip << 2 | q << 4
+  int16_t f1, f2;      // integer coefficients (e_ip - 1 or e_i - 1; e_i - 1)
 };
 
 // Generated tables (gen_tables.py):
@@ -163,7 +166,7 @@ struct VI {
 //                        combine (cb_start, cb_pi, cb_w)
 //   GenSolid<l>:        solid-harmonic transform, CSR rows m = -l..l
 //   GenHrr<LA, LB>:     n-q HRR terms
-//   GenV<L>:            VRR1 stage items
+//   GenV<L>:            VRR1 stage items (operand offsets)
 template <int LP, int EA, int EB> struct GenTab;
 template <int l> struct GenSolid;
 template <int LA, int LB> struct GenHrr;

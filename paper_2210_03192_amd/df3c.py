@@ -12,7 +12,8 @@ import numpy as np
 import torch
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libdf3c.so")
+# DF3C_LIBRARY selects another build of the library (e.g. a tuning variant)
+LIB_PATH = os.environ.get("DF3C_LIBRARY") or os.path.join(_HERE, "libdf3c.so")
 _lib = None
 
 DF3C_OK = 0
@@ -81,6 +82,9 @@ def lib():
         L.df3c_coulomb_J_batched_workspace.restype = SZ
         L.df3c_coulomb_J_batched_workspace.argtypes = [P, P, I32]
         L.df3c_coulomb_J_batched.argtypes = [P, I32, P, P, I32, P, P, P, P, P, P, SZ, U32, P]
+        L.df3c_timing_enable.argtypes = [I32]
+        L.df3c_timing_read.restype = I64
+        L.df3c_timing_read.argtypes = [P, P, P, I64]
         _lib = L
     return _lib
 
@@ -257,3 +261,25 @@ def coulomb_J_batched(xyz: torch.Tensor, aux: DeviceBasis, orb: DeviceBasis,
                                         ws.numel(), flags, _stream(stream)),
            "df3c_coulomb_J_batched")
     return J
+
+
+KERNEL_STORE, KERNEL_J, KERNEL_GRAD, KERNEL_JQ = 0, 1, 2, 3
+
+
+def timing_enable(on: bool = True) -> None:
+    """Bracket every class-kernel launch with HIP events on its stream."""
+    _check(lib().df3c_timing_enable(1 if on else 0), "df3c_timing_enable")
+
+
+def timing_read(cap: int = 65536):
+    """Durations of the launches recorded since the last read, as a list of
+    (kind, class id, ms); waits for them and clears the record."""
+    kind = (ctypes.c_int32 * cap)()
+    cls = (ctypes.c_int32 * cap)()
+    ms = (ctypes.c_float * cap)()
+    n = lib().df3c_timing_read(kind, cls, ms, cap)
+    if n < 0:
+        _check(int(n), "df3c_timing_read")
+    if n > cap:
+        raise DF3CError(f"df3c_timing_read: {n} launches recorded, only {cap} could be read")
+    return [(int(kind[i]), int(cls[i]), float(ms[i])) for i in range(n)]
