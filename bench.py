@@ -34,6 +34,27 @@ MODEL_FLOP = {
     ((6, 4, 4), 1): 131000, ((6, 4, 4), 3): 298000, ((6, 4, 4), 6): 863000,
 }
 
+# HBM bytes per launch of the dominant kernel from the FETCH_SIZE / WRITE_SIZE
+# counter passes summarised under profiles/ (each scaled by the counter's
+# reading for a copy of known size).  A figure holds only for the kernel
+# sources it was measured with: SHA-256 over KERNEL_SOURCES, else traffic = null.
+KERNEL_SOURCES = [os.path.join("paper_2210_03192_amd", "csrc", f)
+                  for f in ("device.hpp", "tables.hpp", "kernels.hpp", "gen_tables.py",
+                            "inst_lp6.hip")]
+MEASURED_TRAFFIC = {
+    "k_store<6,4,4> K=6": (3.0924e9,
+                           "baa897396f8aaa740fb2036a88b5f1490badcf7ba2a7c0dd7dfc3e7caf5fced7"),
+}
+
+
+def kernel_sources_sha256():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
 
 def parse():
     p = argparse.ArgumentParser()
@@ -227,9 +248,13 @@ def main():
     cbd = batches[dom_key]
     flop = MODEL_FLOP[dom_key] * cbd.ntrip
     ach = flop / (dom_ms * 1e-3)
+    kname = f"k_store<{dom_key[0][0]},{dom_key[0][1]},{dom_key[0][2]}> K={dom_key[1]}"
+    traffic = None
+    if kname in MEASURED_TRAFFIC and MEASURED_TRAFFIC[kname][1] == kernel_sources_sha256():
+        traffic = MEASURED_TRAFFIC[kname][0]
     roof = {"bound": "alu", "achieved": ach / 1e12, "peak": PEAK_FP64 / 1e12, "unit": "TFLOP/s",
-            "frac": ach / PEAK_FP64, "traffic": None,
-            "kernel": f"k_store<{dom_key[0][0]},{dom_key[0][1]},{dom_key[0][2]}> K={dom_key[1]}",
+            "frac": ach / PEAK_FP64, "traffic": traffic, "traffic_unit": "B per launch",
+            "kernel": kname,
             "kernel_ms": dom_ms, "model_flop_per_triplet": MODEL_FLOP[dom_key],
             "triplets_per_launch": cbd.ntrip,
             "hbm_write_GBps": cbd.nint * 8 / (dom_ms * 1e-3) / 1e9}
