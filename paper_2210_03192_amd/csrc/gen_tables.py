@@ -176,43 +176,59 @@ def solid(l):
 
 
 # ---------------------------------------------------------------- J engine
-def hterms(LP):
-    """H_u = sum_{c >= u, |c| = LP} d'_c C(c, u) W^{c-u} for every u with
-    |u| <= LP: per u (flat index offT(|u|) + idx(u)) the terms
-    (c index within level LP, flat index of the monomial c - u, C(c, u))."""
-    start, cidx_, mono, coef = [], [], [], []
+# With d'_c = sum_m d_m T_mc (the Cartesian image of the fitting coefficients
+# of one aux shell) the d-contracted CVRR2 targets are
+#   X_e = sum_c d'_c (e0|c) = sum_prim sum_u e!/(e-u)! H_u V_{e-u},
+#   H_u = sum_{c >= u, |c| = LP} C(c, u) d'_c sW_{|u|}[c - u]
+# (the powers of rho/(2 gamma zeta_c) cancel against those of the prerequisite
+# monomials sW_k[n] = s^k (rho/zeta_c PC)^n, k + |n| = LP), and V = [e'0|0]^(LP).
+# The kernels accumulate M_{u,e'} = sum_prim H_u V_{e'} per k = |u| and combine
+# X_e = sum_u e!/(e-u)! M_{u,e-u} once per shell pair.
+def jh_terms(LP):
+    """Per u (flat index offT(|u|) + cidx(u), |u| <= LP): the terms
+    (c index within level LP, sW index sw_off(|u|) + cidx(c - u), C(c, u))."""
+    def sw_off(k):
+        return sum(ncart(LP - q) for q in range(k))
+    start, cc, sw, b = [], [], [], []
     for k in range(LP + 1):
         for u in carts(k):
-            start.append(len(cidx_))
+            start.append(len(cc))
             for ci, c in enumerate(carts(LP)):
                 if all(c[i] >= u[i] for i in range(3)):
-                    m = tuple(c[i] - u[i] for i in range(3))
-                    cidx_.append(ci)
-                    mono.append(offT(sum(m)) + cidx(m))
-                    coef.append(math.comb(c[0], u[0]) * math.comb(c[1], u[1]) * math.comb(c[2], u[2]))
-    start.append(len(cidx_))
-    return start, cidx_, mono, coef
+                    n = tuple(c[i] - u[i] for i in range(3))
+                    cc.append(ci)
+                    sw.append(sw_off(k) + cidx(n))
+                    b.append(math.comb(c[0], u[0]) * math.comb(c[1], u[1]) * math.comb(c[2], u[2]))
+    start.append(len(cc))
+    return start, cc, sw, b
 
 
-def xterms(LP, EA, EB):
-    """X_e += sum_{u <= e, |u| <= LP} e!/(e-u)! H_u V_{e-u}: per target e
-    (levels EA..EB) the terms (flat u, flat e - u, e!/(e-u)!)."""
-    start, uu, vv, coef = [], [], [], []
-    for lev in range(EA, EB + 1):
+def jm_off(g, k):
+    """Offset of block k of M (ncart(k) rows x nek(k) columns, row-major)."""
+    return sum(ncart(q) * g.nek(q) for q in range(k))
+
+
+def jx_terms(g):
+    """Per target e (levels EA..EB, flat order): the terms (index into M,
+    e!/(e-u)!) of X_e = sum_u e!/(e-u)! M_{u, e-u}."""
+    start, mi, co = [], [], []
+    for lev in range(g.EA, g.EB + 1):
         for e in carts(lev):
-            start.append(len(uu))
+            start.append(len(mi))
             for ux in range(e[0] + 1):
                 for uy in range(e[1] + 1):
                     for uz in range(e[2] + 1):
-                        if ux + uy + uz > LP:
+                        k = ux + uy + uz
+                        if k > g.LP:
                             continue
                         u = (ux, uy, uz)
-                        r = tuple(e[i] - u[i] for i in range(3))
-                        uu.append(offT(sum(u)) + cidx(u))
-                        vv.append(offT(sum(r)) + cidx(r))
-                        coef.append(math.perm(e[0], ux) * math.perm(e[1], uy) * math.perm(e[2], uz))
-    start.append(len(uu))
-    return start, uu, vv, coef
+                        r = (e[0] - ux, e[1] - uy, e[2] - uz)
+                        col = offT(sum(r)) + cidx(r) - offT(g.emin(k))
+                        assert 0 <= col < g.nek(k)
+                        mi.append(jm_off(g, k) + cidx(u) * g.nek(k) + col)
+                        co.append(math.perm(e[0], ux) * math.perm(e[1], uy) * math.perm(e[2], uz))
+    start.append(len(mi))
+    return start, mi, co
 
 
 # ----------------------------------------------------------------------- HRR
@@ -383,11 +399,11 @@ def write(outdir):
             s.append(arr("int32_t", "cb_start", st))
             s.append(arr("int16_t", "cb_pi", pi))
             s.append(arr("int32_t", "cb_w", w))
-            xs, xu, xv, xc = xterms(LP, EA, EB)
-            s.append(arr("int16_t", "xt_start", xs))
-            s.append(arr("int16_t", "xt_u", xu))
-            s.append(arr("int16_t", "xt_v", xv))
-            s.append(arr("int32_t", "xt_c", xc))
+            js, jm, jc = jx_terms(g)
+            s.append(f"  static constexpr int NM = {jm_off(g, LP + 1)};\n")
+            s.append(arr("int16_t", "jx_start", js))
+            s.append(arr("int16_t", "jx_m", jm))
+            s.append(arr("int32_t", "jx_c", jc))
             s.append("};\n")
         s.append("}  // namespace df3c\n")
         _write_if_changed(os.path.join(outdir, f"tables_lp{LP}.hpp"), "".join(s))
@@ -408,11 +424,11 @@ def write(outdir):
         s.append(arr("int16_t", "col", col))
         s.append(arr("double", "val", val))
         s.append(arr("double", "dense", [repr(x) for r in rows for x in r]))
-        hs, hc, hm, hk = hterms(l)
-        s.append(arr("int16_t", "ht_start", hs))
-        s.append(arr("int16_t", "ht_c", hc))
-        s.append(arr("int16_t", "ht_m", hm))
-        s.append(arr("int32_t", "ht_k", hk))
+        hs, hc, hw, hb = jh_terms(l)
+        s.append(arr("int16_t", "jh_start", hs))
+        s.append(arr("int8_t", "jh_c", hc))
+        s.append(arr("int16_t", "jh_sw", hw))
+        s.append(arr("int16_t", "jh_b", hb))
         s.append("};\n")
     for la in range(LMAX_ORB + 1):
         for lb in range(LMAX_ORB + 1):

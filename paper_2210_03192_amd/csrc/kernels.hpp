@@ -161,11 +161,83 @@ struct PiTiles {
 };
 
 // ---------------------------------------------------------------------------
+// Setup of one chunk of primitive triplets p0 .. p0+npc-1 (lanes over
+// primitives): the scalars of the record, Boys, level 0 of VRR1 at every m and
+// the CVRR2 monomials sW.  Record of primitive pp at prims + pp * REC:
+//   [PS_N scalars][T: NT][W: NW][sW: NSW]...
+// WM selects the contraction weights: 0 -> c_a c_b c_c, 1 -> 2 zeta_a c_a c_b c_c,
+// 2 -> 2 zeta_b c_a c_b c_c (the raised bra of the derivative integrals).
+// ---------------------------------------------------------------------------
+template <class G, int TS, int REC, int WM>
+__device__ __forceinline__ void setup_chunk(const double *btab, double *prims, int lt, int p0,
+                                            int npc, int Kb, int Kc, const double *A,
+                                            const double *B, const double *C, double AB2,
+                                            const double *ea, const double *ca,
+                                            const double *eb, const double *cb,
+                                            const double *ec, const double *cc) {
+  constexpr int LP = G::LP, L = G::L;
+  for (int pp = lt; pp < npc; pp += TS) {
+    const int p = p0 + pp;
+    const int ic = p % Kc, rest = p / Kc;
+    const int ib = rest % Kb, ia = rest / Kb;
+    const double za = ea[ia], zb = eb[ib], zc = ec[ic];
+    const double g = za + zb, ig = 1.0 / g;
+    const double Px = (za * A[0] + zb * B[0]) * ig, Py = (za * A[1] + zb * B[1]) * ig,
+                 Pz = (za * A[2] + zb * B[2]) * ig;
+    const double PCx = Px - C[0], PCy = Py - C[1], PCz = Pz - C[2];
+    const double gz = g + zc;
+    const double rho = g * zc / gz;
+    const double T = rho * (PCx * PCx + PCy * PCy + PCz * PCz);
+    // 2 pi^{5/2} / ((g+zc)^{1/2} g zc) exp(-za zb/g AB^2) x contraction coefficients
+    double pre = 34.98683665524972497 / (sqrt(gz) * g * zc) * exp(-za * zb * ig * AB2) *
+                 (ca[ia] * cb[ib] * cc[ic]);
+    if constexpr (WM == 1) pre *= 2.0 * za;
+    if constexpr (WM == 2) pre *= 2.0 * zb;
+    double Fm[L + 1];
+    boys<LP, L + 1>(btab, T, Fm);
+    double *R = prims + pp * REC;
+    R[PS_PAX] = Px - A[0];
+    R[PS_PAY] = Py - A[1];
+    R[PS_PAZ] = Pz - A[2];
+    const double rg = rho * ig;
+    R[PS_RPX] = rg * PCx;
+    R[PS_RPY] = rg * PCy;
+    R[PS_RPZ] = rg * PCz;
+    R[PS_I2G] = 0.5 * ig;
+    R[PS_RG] = rg;
+    double *Tr = R + PS_N;
+    double *W = Tr + G::NT;
+    Tr[0] = pre * Fm[0];
+#pragma unroll
+    for (int mm = 1; mm <= L; ++mm) W[mm - 1] = pre * Fm[mm];
+    // sW[k][n] = (rho/(2 g zc))^k (rho/zc PC)^n, k + |n| = LP   (Eq. a0cv2)
+    double *SW = Tr + G::NV1;
+    const double s = rho * ig * (0.5 / zc), rz = rho / zc;
+    double wx[LP + 1], wy[LP + 1], wz[LP + 1], sk[LP + 1];
+    wx[0] = wy[0] = wz[0] = sk[0] = 1.0;
+#pragma unroll
+    for (int q = 1; q <= LP; ++q) {
+      wx[q] = wx[q - 1] * (rz * PCx);
+      wy[q] = wy[q - 1] * (rz * PCy);
+      wz[q] = wz[q - 1] * (rz * PCz);
+      sk[q] = sk[q - 1] * s;
+    }
+    static_for<LP + 1>([&](auto kc) {
+      constexpr int k = decltype(kc)::value;
+      static_for<ncart(LP - k)>([&](auto nc) {
+        constexpr int n = decltype(nc)::value;
+        constexpr C3 q = cart(LP - k, n);
+        SW[G::sw_off(k) + n] = sk[k] * wx[q[0]] * wy[q[1]] * wz[q[2]];
+      });
+    });
+  }
+}
+
+// ---------------------------------------------------------------------------
 // The per-triplet pipeline up to (e0|P) in LDS (region EM of the layout).
 // ---------------------------------------------------------------------------
-// WM selects the contraction weights: 0 -> c_a c_b c_c, 1 -> 2 zeta_a c_a c_b c_c,
-// 2 -> 2 zeta_b c_a c_b c_c (the raised bra of the derivative integrals).  slot is
-// the per-lane prerequisite map of make_slots, or nullptr to decode it inline.
+// WM selects the contraction weights (see setup_chunk).  slot is the per-lane
+// prerequisite map of make_slots, or nullptr to decode it inline.
 template <int LP, int LA, int LB, int TS, int PCH, int WM = 0>
 __device__ __forceinline__ void triplet_to_e0P(const double *btab, double *S, int tid,
                                                const int *slot, int npmax, const double *A,
@@ -208,62 +280,8 @@ __device__ __forceinline__ void triplet_to_e0P(const double *btab, double *S, in
     // recomputed per chunk instead of being hoisted and kept live (spilled)
     int lt = tid;
     __asm__ volatile("" : "+v"(lt));
-    // ---- setup, Boys, level 0 of VRR1 and the CVRR2 monomials sW
-    for (int pp = lt; pp < npc; pp += TS) {
-      const int p = p0 + pp;
-      const int ic = p % Kc, rest = p / Kc;
-      const int ib = rest % Kb, ia = rest / Kb;
-      const double za = ea[ia], zb = eb[ib], zc = ec[ic];
-      const double g = za + zb, ig = 1.0 / g;
-      const double Px = (za * A[0] + zb * B[0]) * ig, Py = (za * A[1] + zb * B[1]) * ig,
-                   Pz = (za * A[2] + zb * B[2]) * ig;
-      const double PCx = Px - C[0], PCy = Py - C[1], PCz = Pz - C[2];
-      const double gz = g + zc;
-      const double rho = g * zc / gz;
-      const double T = rho * (PCx * PCx + PCy * PCy + PCz * PCz);
-      // 2 pi^{5/2} / ((g+zc)^{1/2} g zc) exp(-za zb/g AB^2) x contraction coefficients
-      double pre = 34.98683665524972497 / (sqrt(gz) * g * zc) * exp(-za * zb * ig * AB2) *
-                   (ca[ia] * cb[ib] * cc[ic]);
-      if constexpr (WM == 1) pre *= 2.0 * za;
-      if constexpr (WM == 2) pre *= 2.0 * zb;
-      double Fm[L + 1];
-      boys<LP, L + 1>(btab, T, Fm);
-      double *R = prims + pp * REC;
-      R[PS_PAX] = Px - A[0];
-      R[PS_PAY] = Py - A[1];
-      R[PS_PAZ] = Pz - A[2];
-      const double rg = rho * ig;
-      R[PS_RPX] = rg * PCx;
-      R[PS_RPY] = rg * PCy;
-      R[PS_RPZ] = rg * PCz;
-      R[PS_I2G] = 0.5 * ig;
-      R[PS_RG] = rg;
-      double *Tr = R + PS_N;
-      double *W = Tr + G::NT;
-      Tr[0] = pre * Fm[0];
-#pragma unroll
-      for (int mm = 1; mm <= L; ++mm) W[mm - 1] = pre * Fm[mm];
-      // sW[k][n] = (rho/(2 g zc))^k (rho/zc PC)^n, k + |n| = LP   (Eq. a0cv2)
-      double *SW = Tr + G::NV1;
-      const double s = rho * ig * (0.5 / zc), rz = rho / zc;
-      double wx[LP + 1], wy[LP + 1], wz[LP + 1], sk[LP + 1];
-      wx[0] = wy[0] = wz[0] = sk[0] = 1.0;
-#pragma unroll
-      for (int q = 1; q <= LP; ++q) {
-        wx[q] = wx[q - 1] * (rz * PCx);
-        wy[q] = wy[q - 1] * (rz * PCy);
-        wz[q] = wz[q - 1] * (rz * PCz);
-        sk[q] = sk[q - 1] * s;
-      }
-      static_for<LP + 1>([&](auto kc) {
-        constexpr int k = decltype(kc)::value;
-        static_for<ncart(LP - k)>([&](auto nc) {
-          constexpr int n = decltype(nc)::value;
-          constexpr C3 q = cart(LP - k, n);
-          SW[G::sw_off(k) + n] = sk[k] * wx[q[0]] * wy[q[1]] * wz[q[2]];
-        });
-      });
-    }
+    setup_chunk<G, TS, REC, WM>(btab, prims, lt, p0, npc, Kb, Kc, A, B, C, AB2, ea, ca, eb, cb, ec,
+                                cc);
     team_sync();
     // ---- VRR1, 2-quantal stages in place
     vrr1<G, TS, PCH, REC>(prims, npc, lt);
@@ -570,16 +588,262 @@ __global__ void __launch_bounds__(TS > 64 ? TS : 64)
 // its transpose are added into J; each pair is owned by exactly one team, so
 // no atomics are needed, and launches of different LP run in stream order.
 // ---------------------------------------------------------------------------
+// ---------------------------------------------------------------------------
+// J engine: the fitting coefficients are digested into the ket before the
+// CVRR2 combination.  For one aux shell with Cartesian image
+// d'_c = sum_m d_m T_mc of its coefficients,
+//   sum_c d'_c (e0|c) = sum_prim sum_u e!/(e-u)! H_u V_{e-u},
+//   H_u = sum_{c >= u, |c| = LP} C(c,u) d'_c sW_{|u|}[c-u],  V = [e'0|0]^(LP),
+// which is Eq. cVRR2 in n-quantal form applied to the prerequisites of
+// Eq. a0cv2 (the powers of rho/(2 gamma zeta_c) cancel between the two).  Per
+// shell pair the team accumulates M_{u,e'} = sum_{aux shells} sum_prim H_u V_{e'}
+// on the matrix cores (block k = |u|: ncart(k) rows, nek(k) columns, 16 x 16 x 4
+// tiles) and forms X_e = sum_u e!/(e-u)! M_{u,e-u} once; one HRR of X gives the
+// J block.  No per-triplet CVRR2 combination, ket transform or digestion remains.
+// ---------------------------------------------------------------------------
+template <class G>
+struct MTiles {
+  static constexpr int nr(int k) { return (ncart(k) + 15) / 16; }
+  static constexpr int nc(int k) { return (G::nek(k) + 15) / 16; }
+  static constexpr int count() {
+    int n = 0;
+    for (int k = 0; k <= G::LP; ++k)
+      if (G::nek(k) > 0) n += nr(k) * nc(k);
+    return n;
+  }
+  static constexpr int N = count();
+  static constexpr int field(int t, int which) {
+    for (int k = 0; k <= G::LP; ++k) {
+      if (G::nek(k) == 0) continue;
+      const int n = nr(k) * nc(k);
+      if (t < n) return which == 0 ? k : which == 1 ? 16 * (t / nc(k)) : 16 * (t % nc(k));
+      t -= n;
+    }
+    return -1;
+  }
+  static constexpr int moff(int k) {
+    int o = 0;
+    for (int q = 0; q < k; ++q) o += ncart(q) * G::nek(q);
+    return o;
+  }
+  static constexpr int NM = moff(G::LP + 1);
+};
+
+// LDS layout of one J-engine team (doubles):
+//   PRIM [0, PCH*REC)    records [PS_N][T][W][sW][H] of the current chunk
+//   DP   [.., +NCP)      d' of the current aux shell
+//   MJ   [0, NM)         M after the aux loop (over the dead PRIM / DP)
+//   XD   [.., +NE)       X_e for the HRR
+template <int LP, int LA, int LB, int PCH>
+struct JELayout {
+  using G = Geo<LP, LA, LA + LB>;
+  static constexpr int HU = PS_N + G::NV1 + G::NSW;
+  static constexpr int REC = HU + G::NSW;
+  static constexpr int DP = PCH * REC;
+  static constexpr int MJ = 0;
+  static constexpr int XD = imax(DP + G::NCP, MTiles<G>::NM);
+  static constexpr int TOTAL = XD + G::NE;
+};
+
+// classes whose J runs on the engine: whole-wave teams with chunks of 4
+template <int LP, int LA, int LB, int TS, int PCH>
+constexpr bool use_jengine() {
+  return TS % 64 == 0 && PCH == 4;
+}
+
+template <int LP, int LA, int LB, int TS, int PCH>
+__device__ __forceinline__ void jeng_pair(const JArgs &a, double *S, int tid, bool valid, int sa,
+                                          int sb, int np_loop) {
+  using G = Geo<LP, LA, LA + LB>;
+  using JE = JELayout<LP, LA, LB, PCH>;
+  using MT = MTiles<G>;
+  using SH = GenSolid<LP>;
+  using TB = GenTab<LP, G::EA, G::EB>;
+  static_assert(TB::NM == MT::NM, "generated J-engine tables out of date");
+  static_assert(TS % 64 == 0 && PCH == 4, "the J engine runs whole-wave teams");
+  constexpr int REC = JE::REC;
+  constexpr int NA = ncart(LA), NB = ncart(LB);
+  constexpr int NWV = TS / 64;
+  constexpr int NTW = (MT::N + NWV - 1) / NWV;
+  constexpr int NU = offT(imin(LP, G::EB) + 1);  // H_u with |u| <= min(LP, EB)
+  if (valid && LA == LB && sa != sb) {
+    // HRR orientation as in j_pair
+    auto tight = [&](int sh) {
+      const double *e = a.orb.exps + a.orb.prim_off[sh];
+      double lo = e[0], hi = e[0];
+      for (int i = 1; i < a.orb.nprim[sh]; ++i) {
+        lo = fmin(lo, e[i]);
+        hi = fmax(hi, e[i]);
+      }
+      return lo * hi;
+    };
+    if (tight(sb) > tight(sa)) {
+      const int t = sa;
+      sa = sb;
+      sb = t;
+    }
+  }
+  const int Ka = valid ? a.orb.nprim[sa] : 0, Kb = valid ? a.orb.nprim[sb] : 0;
+  const int64_t oa = valid ? a.orb.prim_off[sa] : 0, ob = valid ? a.orb.prim_off[sb] : 0;
+  double Ar[3] = {0, 0, 0}, Br[3] = {0, 0, 0};
+  if (valid) {
+    const int ia = a.orb.atom[sa], ib = a.orb.atom[sb];
+    for (int x = 0; x < 3; ++x) {
+      Ar[x] = a.xyz[3 * ia + x];
+      Br[x] = a.xyz[3 * ib + x];
+    }
+  }
+  const double ABx = Ar[0] - Br[0], ABy = Ar[1] - Br[1], ABz = Ar[2] - Br[2];
+  const double AB2 = ABx * ABx + ABy * ABy + ABz * ABz;
+  double *prims = S;
+  double *DP = S + JE::DP;
+  dbl4 macc[NTW];
+#pragma unroll
+  for (int j = 0; j < NTW; ++j) macc[j] = dbl4{0.0, 0.0, 0.0, 0.0};
+
+  for (int ip = 0; ip < np_loop; ++ip) {
+    const bool active = valid && ip < a.np;
+    const int sP = active ? a.psh[ip] : 0;
+    const int Kc = active ? a.aux.nprim[sP] : 0;
+    const int64_t oc = active ? a.aux.prim_off[sP] : 0;
+    double Cr[3] = {0, 0, 0};
+    if (active) {
+      const int ic = a.aux.atom[sP];
+      Cr[0] = a.xyz[3 * ic];
+      Cr[1] = a.xyz[3 * ic + 1];
+      Cr[2] = a.xyz[3 * ic + 2];
+    }
+    // d' of this shell (visible to the H step after the first barrier below)
+    const double *dP = a.d + (active ? a.aux_off[sP] : 0);
+    for (int c = tid; c < G::NCP; c += TS) {
+      double v = 0.0;
+      if (active) {
+        if (a.pure) {
+#pragma unroll
+          for (int m = 0; m < G::NPURE; ++m) v += dP[m] * SH::dense[m * G::NCP + c];
+        } else {
+          v = dP[c];
+        }
+      }
+      DP[c] = v;
+    }
+    const int K = Ka * Kb * Kc;  // uniform over the team
+    for (int p0 = 0; p0 < K; p0 += PCH) {
+      const int npc = imin(PCH, K - p0);
+      int lt = tid;
+      __asm__ volatile("" : "+v"(lt));
+      setup_chunk<G, TS, REC, 0>(a.boys, prims, lt, p0, npc, Kb, Kc, Ar, Br, Cr, AB2,
+                                 a.orb.exps + oa, a.orb.coefs + oa, a.orb.exps + ob,
+                                 a.orb.coefs + ob, a.aux.exps + oc, a.aux.coefs + oc);
+      team_sync();
+      vrr1<G, TS, PCH, REC>(prims, npc, lt);
+      // H_u of the chunk, u-major so the long sums (small |u|) spread over lanes
+      for (int it = lt; it < npc * NU; it += TS) {
+        const int u = it / npc, pp = it - u * npc;
+        const double *SWp = prims + pp * REC + PS_N + G::NV1;
+        double h = 0.0;
+        for (int q = SH::jh_start[u]; q < SH::jh_start[u + 1]; ++q)
+          h += double(SH::jh_b[q]) * DP[SH::jh_c[q]] * SWp[SH::jh_sw[q]];
+        prims[pp * REC + JE::HU + u] = h;
+      }
+      team_sync();
+      // M += H V on the matrix cores; lane (pc, cl): primitive pc, row / column cl
+      const int wl = lt >> 6, pc = (lt & 63) >> 4, cl = lt & 15;
+      const double *Rl = prims + pc * REC + cl;
+      const bool pv = pc < npc;
+      static_for<NWV>([&](auto wc) {
+        constexpr int W = decltype(wc)::value;
+        if (wl == W) {
+          static_for<NTW>([&](auto jc) {
+            constexpr int j = decltype(jc)::value;
+            constexpr int t = j * NWV + W;
+            if constexpr (t < MT::N) {
+              constexpr int k = MT::field(t, 0), r0 = MT::field(t, 1), c0 = MT::field(t, 2);
+              constexpr int nr = ncart(k) - r0, nc = G::nek(k) - c0;
+              const double av = (pv && cl < nr) ? Rl[JE::HU + offT(k) + r0] : 0.0;
+              const double bv = (pv && cl < nc) ? Rl[PS_N + offT(G::emin(k)) + c0] : 0.0;
+              macc[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, macc[j], 0, 0, 0);
+            }
+          });
+        }
+      });
+      team_sync();
+    }
+  }
+  // M to LDS, then X_e = sum_u e!/(e-u)! M_{u,e-u}
+  double *MJ = S + JE::MJ;
+  {
+    const int wl = tid >> 6, pc = (tid & 63) >> 4, cl = tid & 15;
+    static_for<NWV>([&](auto wc) {
+      constexpr int W = decltype(wc)::value;
+      if (wl == W) {
+        static_for<NTW>([&](auto jc) {
+          constexpr int j = decltype(jc)::value;
+          constexpr int t = j * NWV + W;
+          if constexpr (t < MT::N) {
+            constexpr int k = MT::field(t, 0), r0 = MT::field(t, 1), c0 = MT::field(t, 2);
+            constexpr int nr = ncart(k) - r0, nc = G::nek(k) - c0;
+            constexpr int base = MT::moff(k) + r0 * G::nek(k) + c0;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+              const int r = 4 * v + pc;
+              if (r < nr && cl < nc) MJ[base + r * G::nek(k) + cl] = macc[j][v];
+            }
+          }
+        });
+      }
+    });
+  }
+  team_sync();
+  double *XD = S + JE::XD;
+  for (int e = tid; e < G::NE; e += TS) {
+    double v = 0.0;
+    for (int q = TB::jx_start[e]; q < TB::jx_start[e + 1]; ++q)
+      v += double(TB::jx_c[q]) * MJ[TB::jx_m[q]];
+    XD[e] = v;
+  }
+  team_sync();
+  double pwx[LB + 1], pwy[LB + 1], pwz[LB + 1];
+  pwx[0] = pwy[0] = pwz[0] = 1.0;
+#pragma unroll
+  for (int k = 1; k <= LB; ++k) {
+    pwx[k] = pwx[k - 1] * ABx;
+    pwy[k] = pwy[k - 1] * ABy;
+    pwz[k] = pwz[k - 1] * ABz;
+  }
+  if (valid) {
+    const int64_t ra = a.ao_off[sa] - a.ao_base, rb = a.ao_off[sb] - a.ao_base;
+    for (int ia = tid; ia < NA; ia += TS) {
+      double o[NB];
+      hrr_nq<LA, LB>(XD, ia, pwx, pwy, pwz, o);
+#pragma unroll
+      for (int ib = 0; ib < NB; ++ib) {
+        a.J[(ra + ia) * a.nao + rb + ib] += o[ib];
+        if (sa != sb) a.J[(rb + ib) * a.nao + ra + ia] += o[ib];
+      }
+    }
+  }
+  team_sync();
+}
+
 template <int LP, int LA, int LB, int TS, int PCH>
 struct JLayout {
   using G = Geo<LP, LA, LA + LB>;
   static constexpr int XD = Layout<LP, LA, LB, PCH>::TOTAL;   // X_e for the final HRR
-  static constexpr int TOTAL = XD + G::NE;
+  // doubles per team: the engine's layout, or the per-triplet layout + X
+  static constexpr int TOTAL =
+      use_jengine<LP, LA, LB, TS, PCH>() ? JELayout<LP, LA, LB, PCH>::TOTAL : XD + G::NE;
+  static constexpr int BYTES_WG = ((TS > 64 ? TS : 64) / TS) * TOTAL * 8;
+  static_assert(BYTES_WG <= 160 * 1024, "J layout does not fit the LDS of a CU");
 };
 
 template <int LP, int LA, int LB, int TS, int PCH>
 __device__ __forceinline__ void j_pair(const JArgs &a, double *S, int tid, const int *slot,
                                        bool valid, int sa, int sb, int np_loop) {
+  if constexpr (use_jengine<LP, LA, LB, TS, PCH>()) {
+    jeng_pair<LP, LA, LB, TS, PCH>(a, S, tid, valid, sa, sb, np_loop);
+    return;
+  }
   using G = Geo<LP, LA, LA + LB>;
   using LY = Layout<LP, LA, LB, PCH>;
   using JL = JLayout<LP, LA, LB, TS, PCH>;

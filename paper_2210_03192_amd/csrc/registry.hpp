@@ -35,22 +35,24 @@ hipError_t launch_store(const StoreArgs &a, int grid, hipStream_t s) {
 template <int LP, int LA, int LB>
 hipError_t launch_J(const JArgs &a, int grid, hipStream_t s) {
   using C = Cfg<LP, LA, LB>;
+  constexpr int lds = JLayout<LP, LA, LB, C::TS, C::PCH>::BYTES_WG;
   auto kern = k_J<LP, LA, LB, C::TS, C::PCH>;
   static const hipError_t attr = hipFuncSetAttribute(
-      reinterpret_cast<const void *>(kern), hipFuncAttributeMaxDynamicSharedMemorySize, C::LDS_J);
+      reinterpret_cast<const void *>(kern), hipFuncAttributeMaxDynamicSharedMemorySize, lds);
   if (attr != hipSuccess) return attr;
-  hipLaunchKernelGGL(kern, dim3(grid), dim3(C::BLK), C::LDS_J, s, a);
+  hipLaunchKernelGGL(kern, dim3(grid), dim3(C::BLK), lds, s, a);
   return hipGetLastError();
 }
 
 template <int LP, int LA, int LB>
 hipError_t launch_Jq(const JQArgs &a, int grid, hipStream_t s) {
   using C = Cfg<LP, LA, LB>;
+  constexpr int lds = JLayout<LP, LA, LB, C::TS, C::PCH>::BYTES_WG;
   auto kern = k_Jq<LP, LA, LB, C::TS, C::PCH>;
   static const hipError_t attr = hipFuncSetAttribute(
-      reinterpret_cast<const void *>(kern), hipFuncAttributeMaxDynamicSharedMemorySize, C::LDS_J);
+      reinterpret_cast<const void *>(kern), hipFuncAttributeMaxDynamicSharedMemorySize, lds);
   if (attr != hipSuccess) return attr;
-  hipLaunchKernelGGL(kern, dim3(grid), dim3(C::BLK), C::LDS_J, s, a);
+  hipLaunchKernelGGL(kern, dim3(grid), dim3(C::BLK), lds, s, a);
   return hipGetLastError();
 }
 

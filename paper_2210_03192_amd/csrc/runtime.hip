@@ -806,7 +806,7 @@ int df3c_coulomb_J_batched(const double *xyz, int32_t natom, const df3c_shells *
   // graph cache key: every argument that the captured launches depend on
   uint64_t key = 1469598103934665603ull;
   int dev = 0;
-  hipGetDevice(&dev);
+  if (hipGetDevice(&dev) != hipSuccess) return DF3C_E_HIP;
   const void *ptrs[] = {xyz, aux->l, aux->nprim, aux->prim_off, aux->atom, aux->exps, aux->coefs,
                         orb->l, orb->nprim, orb->prim_off, orb->atom, orb->exps, orb->coefs,
                         d, J, ws};
@@ -945,12 +945,12 @@ int df3c_coulomb_J_batched(const double *xyz, int32_t natom, const df3c_shells *
   if (hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) != hipSuccess) return DF3C_E_HIP;
   rc = enqueue();
   if (hipStreamEndCapture(s, &graph) != hipSuccess || rc) {
-    if (graph) hipGraphDestroy(graph);
+    if (graph) (void)hipGraphDestroy(graph);
     return rc ? rc : DF3C_E_HIP;
   }
   hipGraphExec_t exec = nullptr;
   const hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
-  hipGraphDestroy(graph);
+  (void)hipGraphDestroy(graph);
   if (ie != hipSuccess) return DF3C_E_HIP;
   std::lock_guard<std::mutex> lk(g_graph_mu);
   g_graphs[key].exec = exec;
