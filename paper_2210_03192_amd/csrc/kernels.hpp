@@ -90,6 +90,25 @@ struct Layout {
 #define DF3C_MIN_WAVES_WAVE 2
 #endif
 
+// Small classes whose J runs on the register engine (jr_pair): VRR1 over all
+// m, the d-contracted ket and X fit the registers of one lane.
+template <int LP, int LA, int LB>
+struct JReg {
+  static constexpr int L = LA + LB, EA = LA, EB = LA + LB;
+  static constexpr int NE = offT(EB + 1) - offT(EA);
+  static constexpr int KU = imin(LP, EB);  // |u| of the H_u that can meet a target
+  static constexpr int NU = offT(KU + 1);
+  // VRR1 in registers: level l holds m = 0..L-l (relative to LP)
+  static constexpr int voff(int l) {
+    int o = 0;
+    for (int q = 0; q < l; ++q) o += ncart(q) * (L - q + 1);
+    return o;
+  }
+  static constexpr int NVR = voff(L + 1);
+  static constexpr int COST = ncart(LP) + NU + NE + NVR;
+  static constexpr bool OK = L <= 4 && COST <= 160;
+};
+
 template <int LP, int LA, int LB>
 struct Cfg {
   using G = Geo<LP, LA, LA + LB>;
@@ -103,6 +122,11 @@ struct Cfg {
   static constexpr int LDS_J = (BLK / TS) * (Layout<LP, LA, LB, PCH>::TOTAL + G::NE) * 8;
   // minimum waves per SIMD requested from the register allocator
   static constexpr int WPE = TS >= 128 ? DF3C_MIN_WAVES_BIG : TS == 64 ? DF3C_MIN_WAVES_WAVE : 1;
+  // J kernels: one lane per shell pair on the register engine, else as above
+  static constexpr bool JREG = TS < 64 && JReg<LP, LA, LB>::OK;
+  static constexpr int TSJ = JREG ? 1 : TS;
+  static constexpr int PCHJ = JREG ? 1 : PCH;
+  static constexpr int BLKJ = TSJ > 64 ? TSJ : 64;
   static_assert(LDS_J <= 160 * 1024, "class does not fit the LDS of a CU");
 };
 
@@ -589,6 +613,209 @@ __global__ void __launch_bounds__(TS > 64 ? TS : 64)
 // no atomics are needed, and launches of different LP run in stream order.
 // ---------------------------------------------------------------------------
 // ---------------------------------------------------------------------------
+// Register J engine for small classes: one lane owns one shell pair and runs
+// every aux shell and primitive triplet of it with all intermediates in
+// registers (compile-time indices, no LDS, no index tables).  Per primitive:
+// setup, Boys, VRR1 (Eq. vrr1, 1-quantal steps over all m), then the digested
+// ket of the J engine below with the sW monomials formed on the fly:
+//   H_u = s^{|u|} sum_{c >= u} C(c,u) d'_c W^{c-u},  W = rho/zeta_c PC,
+//   X_e += sum_u e!/(e-u)! H_u [e-u 0|0]^(LP);
+// one HRR of X per pair adds the J block (both triangles).
+// ---------------------------------------------------------------------------
+template <int LP, int LA, int LB>
+__device__ __forceinline__ void jr_pair(const JArgs &a, bool valid, int sa, int sb) {
+  using R = JReg<LP, LA, LB>;
+  using SH = GenSolid<LP>;
+  constexpr int L = R::L, NE = R::NE, NCP = ncart(LP), NA = ncart(LA), NB = ncart(LB);
+  if (!valid) return;
+  if (LA == LB && sa != sb) {
+    // HRR orientation as in j_pair
+    auto tight = [&](int sh) {
+      const double *e = a.orb.exps + a.orb.prim_off[sh];
+      double lo = e[0], hi = e[0];
+      for (int i = 1; i < a.orb.nprim[sh]; ++i) {
+        lo = fmin(lo, e[i]);
+        hi = fmax(hi, e[i]);
+      }
+      return lo * hi;
+    };
+    if (tight(sb) > tight(sa)) {
+      const int t = sa;
+      sa = sb;
+      sb = t;
+    }
+  }
+  const int Ka = a.orb.nprim[sa], Kb = a.orb.nprim[sb];
+  const double *ea = a.orb.exps + a.orb.prim_off[sa], *ca = a.orb.coefs + a.orb.prim_off[sa];
+  const double *eb = a.orb.exps + a.orb.prim_off[sb], *cb = a.orb.coefs + a.orb.prim_off[sb];
+  double A[3], B[3];
+  {
+    const int ia = a.orb.atom[sa], ib = a.orb.atom[sb];
+#pragma unroll
+    for (int x = 0; x < 3; ++x) {
+      A[x] = a.xyz[3 * ia + x];
+      B[x] = a.xyz[3 * ib + x];
+    }
+  }
+  const double AB2 = (A[0] - B[0]) * (A[0] - B[0]) + (A[1] - B[1]) * (A[1] - B[1]) +
+                     (A[2] - B[2]) * (A[2] - B[2]);
+  double X[NE];
+#pragma unroll
+  for (int e = 0; e < NE; ++e) X[e] = 0.0;
+
+  for (int ip = 0; ip < a.np; ++ip) {
+    const int sP = a.psh[ip];
+    const int Kc = a.aux.nprim[sP];
+    const double *ec = a.aux.exps + a.aux.prim_off[sP], *cc = a.aux.coefs + a.aux.prim_off[sP];
+    const int icn = a.aux.atom[sP];
+    const double C[3] = {a.xyz[3 * icn], a.xyz[3 * icn + 1], a.xyz[3 * icn + 2]};
+    const double *dP = a.d + a.aux_off[sP];
+    // d' = T^T d (pure) or d (Cartesian)
+    double dq[NCP];
+    if (a.pure) {
+      static_for<NCP>([&](auto cc_) {
+        constexpr int c = decltype(cc_)::value;
+        double v = 0.0;
+        static_for<npure(LP)>([&](auto mc) {
+          constexpr int m = decltype(mc)::value;
+          constexpr double t = SH::dense[m * NCP + c];
+          if constexpr (t != 0.0) v += t * dP[m];
+        });
+        dq[c] = v;
+      });
+    } else {
+#pragma unroll
+      for (int c = 0; c < NCP; ++c) dq[c] = dP[c];
+    }
+    for (int ia = 0; ia < Ka; ++ia)
+      for (int ib = 0; ib < Kb; ++ib) {
+        const double za = ea[ia], zb = eb[ib];
+        const double g = za + zb, ig = 1.0 / g;
+        const double P[3] = {(za * A[0] + zb * B[0]) * ig, (za * A[1] + zb * B[1]) * ig,
+                             (za * A[2] + zb * B[2]) * ig};
+        const double PA[3] = {P[0] - A[0], P[1] - A[1], P[2] - A[2]};
+        const double eab = exp(-za * zb * ig * AB2) * ca[ia] * cb[ib];
+        for (int ic = 0; ic < Kc; ++ic) {
+          const double zc = ec[ic];
+          const double PC[3] = {P[0] - C[0], P[1] - C[1], P[2] - C[2]};
+          const double gz = g + zc, rho = g * zc / gz, rg = rho * ig, i2g = 0.5 * ig;
+          const double T = rho * (PC[0] * PC[0] + PC[1] * PC[1] + PC[2] * PC[2]);
+          // 2 pi^{5/2} / ((g+zc)^{1/2} g zc) exp(-za zb/g AB^2) x contraction coefficients
+          const double pre = 34.98683665524972497 / (sqrt(gz) * g * zc) * eab * cc[ic];
+          const double RP[3] = {rg * PC[0], rg * PC[1], rg * PC[2]};
+          double Fm[L + 1];
+          boys<LP, L + 1>(a.boys, T, Fm);
+          // VRR1: vr[voff(l) + c (L-l+1) + m] = [e 0|0]^(LP+m), e = cart(l, c)
+          double vr[R::NVR];
+#pragma unroll
+          for (int m = 0; m <= L; ++m) vr[m] = pre * Fm[m];
+          static_for<L>([&](auto lc) {
+            constexpr int l = decltype(lc)::value + 1;
+            static_for<ncart(l)>([&](auto cc_) {
+              constexpr int c = decltype(cc_)::value;
+              constexpr C3 e = cart(l, c);
+              constexpr int i = rdir(e);
+              constexpr int c1 = cidx(e[0] - (i == 0), e[1] - (i == 1), e[2] - (i == 2));
+              constexpr int o1 = R::voff(l - 1) + c1 * (L - l + 2);
+              constexpr int o = R::voff(l) + c * (L - l + 1);
+              static_for<L - l + 1>([&](auto mc) {
+                constexpr int m = decltype(mc)::value;
+                double v = PA[i] * vr[o1 + m] - RP[i] * vr[o1 + m + 1];
+                if constexpr (e[i] >= 2) {
+                  constexpr int c2 = cidx(e[0] - 2 * (i == 0), e[1] - 2 * (i == 1),
+                                          e[2] - 2 * (i == 2));
+                  constexpr int o2 = R::voff(l - 2) + c2 * (L - l + 3);
+                  v += double(e[i] - 1) * i2g * (vr[o2 + m] - rg * vr[o2 + m + 1]);
+                }
+                vr[o + m] = v;
+              });
+            });
+          });
+          // H_u, |u| <= KU
+          const double s = rho * ig * (0.5 / zc), rz = rho / zc;
+          double wx[LP + 1], wy[LP + 1], wz[LP + 1], sk[R::KU + 1];
+          wx[0] = wy[0] = wz[0] = sk[0] = 1.0;
+#pragma unroll
+          for (int q = 1; q <= LP; ++q) {
+            wx[q] = wx[q - 1] * (rz * PC[0]);
+            wy[q] = wy[q - 1] * (rz * PC[1]);
+            wz[q] = wz[q - 1] * (rz * PC[2]);
+          }
+#pragma unroll
+          for (int q = 1; q <= R::KU; ++q) sk[q] = sk[q - 1] * s;
+          double H[R::NU];
+          static_for<R::KU + 1>([&](auto kc) {
+            constexpr int k = decltype(kc)::value;
+            static_for<ncart(k)>([&](auto uc) {
+              constexpr int ui = decltype(uc)::value;
+              constexpr C3 u = cart(k, ui);
+              double h = 0.0;
+              static_for<NCP>([&](auto cc_) {
+                constexpr int c = decltype(cc_)::value;
+                constexpr C3 q = cart(LP, c);
+                if constexpr (q[0] >= u[0] && q[1] >= u[1] && q[2] >= u[2]) {
+                  constexpr double bn =
+                      double(binom(q[0], u[0]) * binom(q[1], u[1]) * binom(q[2], u[2]));
+                  h += (bn * dq[c]) * (wx[q[0] - u[0]] * wy[q[1] - u[1]] * wz[q[2] - u[2]]);
+                }
+              });
+              H[offT(k) + ui] = sk[k] * h;
+            });
+          });
+          // X_e += sum_u e!/(e-u)! H_u V_{e-u}
+          static_for<L - LA + 1>([&](auto lc) {
+            constexpr int le = LA + decltype(lc)::value;
+            static_for<ncart(le)>([&](auto ec_) {
+              constexpr int ce = decltype(ec_)::value;
+              constexpr C3 e = cart(le, ce);
+              double v = X[offT(le) - offT(LA) + ce];
+              static_for<e[0] + 1>([&](auto xc) {
+                constexpr int ux = decltype(xc)::value;
+                static_for<e[1] + 1>([&](auto yc) {
+                  constexpr int uy = decltype(yc)::value;
+                  static_for<e[2] + 1>([&](auto zc_) {
+                    constexpr int uz = decltype(zc_)::value;
+                    constexpr int k = ux + uy + uz;
+                    if constexpr (k <= LP) {
+                      constexpr int lr = le - k;
+                      constexpr int cr = cidx(e[0] - ux, e[1] - uy, e[2] - uz);
+                      constexpr double f = double(falling(e[0], ux) * falling(e[1], uy) *
+                                                  falling(e[2], uz));
+                      v += (f * H[offT(k) + cidx(ux, uy, uz)]) *
+                           vr[R::voff(lr) + cr * (L - lr + 1)];
+                    }
+                  });
+                });
+              });
+              X[offT(le) - offT(LA) + ce] = v;
+            });
+          });
+        }
+      }
+  }
+  // one HRR of X, both J triangles
+  double pwx[LB + 1], pwy[LB + 1], pwz[LB + 1];
+  pwx[0] = pwy[0] = pwz[0] = 1.0;
+#pragma unroll
+  for (int k = 1; k <= LB; ++k) {
+    pwx[k] = pwx[k - 1] * (A[0] - B[0]);
+    pwy[k] = pwy[k - 1] * (A[1] - B[1]);
+    pwz[k] = pwz[k - 1] * (A[2] - B[2]);
+  }
+  const int64_t ra = a.ao_off[sa] - a.ao_base, rb = a.ao_off[sb] - a.ao_base;
+  static_for<NA>([&](auto ac) {
+    constexpr int ia = decltype(ac)::value;
+    double o[NB];
+    hrr_nq<LA, LB>(X, ia, pwx, pwy, pwz, o);
+#pragma unroll
+    for (int ib = 0; ib < NB; ++ib) {
+      a.J[(ra + ia) * a.nao + rb + ib] += o[ib];
+      if (sa != sb) a.J[(rb + ib) * a.nao + ra + ia] += o[ib];
+    }
+  });
+}
+
+// ---------------------------------------------------------------------------
 // J engine: the fitting coefficients are digested into the ket before the
 // CVRR2 combination.  For one aux shell with Cartesian image
 // d'_c = sum_m d_m T_mc of its coefficients,
@@ -831,8 +1058,10 @@ struct JLayout {
   using G = Geo<LP, LA, LA + LB>;
   static constexpr int XD = Layout<LP, LA, LB, PCH>::TOTAL;   // X_e for the final HRR
   // doubles per team: the engine's layout, or the per-triplet layout + X
-  static constexpr int TOTAL =
-      use_jengine<LP, LA, LB, TS, PCH>() ? JELayout<LP, LA, LB, PCH>::TOTAL : XD + G::NE;
+  static constexpr bool REG = TS == 1 && JReg<LP, LA, LB>::OK;
+  static constexpr int TOTAL = REG ? 0
+                               : use_jengine<LP, LA, LB, TS, PCH>() ? JELayout<LP, LA, LB, PCH>::TOTAL
+                                                                   : XD + G::NE;
   static constexpr int BYTES_WG = ((TS > 64 ? TS : 64) / TS) * TOTAL * 8;
   static_assert(BYTES_WG <= 160 * 1024, "J layout does not fit the LDS of a CU");
 };
@@ -840,7 +1069,10 @@ struct JLayout {
 template <int LP, int LA, int LB, int TS, int PCH>
 __device__ __forceinline__ void j_pair(const JArgs &a, double *S, int tid, const int *slot,
                                        bool valid, int sa, int sb, int np_loop) {
-  if constexpr (use_jengine<LP, LA, LB, TS, PCH>()) {
+  if constexpr (TS == 1 && JReg<LP, LA, LB>::OK) {
+    jr_pair<LP, LA, LB>(a, valid, sa, sb);
+    return;
+  } else if constexpr (use_jengine<LP, LA, LB, TS, PCH>()) {
     jeng_pair<LP, LA, LB, TS, PCH>(a, S, tid, valid, sa, sb, np_loop);
     return;
   }
@@ -950,12 +1182,13 @@ __global__ void __launch_bounds__(TS > 64 ? TS : 64)
   using JL = JLayout<LP, LA, LB, TS, PCH>;
   constexpr int BLK = TS > 64 ? TS : 64;
   constexpr int TPB = BLK / TS;
-  constexpr int NQ = (G::NPI + TS - 1) / TS;
+  constexpr bool REG = JLayout<LP, LA, LB, TS, PCH>::REG;
+  constexpr int NQ = REG ? 1 : (G::NPI + TS - 1) / TS;
   extern __shared__ double smem[];
   const int team = threadIdx.x / TS, tid = threadIdx.x % TS;
   double *S = smem + team * JL::TOTAL;
   int slot[NQ];
-  make_slots<LP, LA, LB, TS>(slot, tid);
+  if constexpr (!REG) make_slots<LP, LA, LB, TS>(slot, tid);
 
   for (int64_t base = int64_t(blockIdx.x) * TPB; base < a.npair; base += int64_t(gridDim.x) * TPB) {
     const int64_t q = base + team;

@@ -54,13 +54,14 @@ __global__ void __launch_bounds__(TS > 64 ? TS : 64)
   using JL = JLayout<LP, LA, LB, TS, PCH>;
   constexpr int BLK = TS > 64 ? TS : 64;
   constexpr int TPB = BLK / TS;
-  constexpr int NQ = (G::NPI + TS - 1) / TS;
+  constexpr bool REG = JLayout<LP, LA, LB, TS, PCH>::REG;
+  constexpr int NQ = REG ? 1 : (G::NPI + TS - 1) / TS;
   extern __shared__ double smem[];
   __shared__ unsigned long long s_base;
   const int team = threadIdx.x / TS, tid = threadIdx.x % TS;
   double *S = smem + team * JL::TOTAL;
   int slot[NQ];
-  make_slots<LP, LA, LB, TS>(slot, tid);
+  if constexpr (!REG) make_slots<LP, LA, LB, TS>(slot, tid);
 
   for (;;) {
     if (threadIdx.x == 0) s_base = atomicAdd(q.counter, (unsigned long long)(TPB * q.chunk));

@@ -8,7 +8,8 @@ namespace df3c {
 
 struct ClassInfo {
   int ts = 0;         // lanes per team
-  int tpw = 0;        // teams per workgroup
+  int tpw = 0;        // teams per workgroup (block kernels)
+  int tpwj = 0;       // teams per workgroup of the J kernels
   int lds = 0;        // dynamic LDS bytes per workgroup
   hipError_t (*store)(const StoreArgs &, int, hipStream_t) = nullptr;
   hipError_t (*jfn)(const JArgs &, int, hipStream_t) = nullptr;
@@ -35,24 +36,24 @@ hipError_t launch_store(const StoreArgs &a, int grid, hipStream_t s) {
 template <int LP, int LA, int LB>
 hipError_t launch_J(const JArgs &a, int grid, hipStream_t s) {
   using C = Cfg<LP, LA, LB>;
-  constexpr int lds = JLayout<LP, LA, LB, C::TS, C::PCH>::BYTES_WG;
-  auto kern = k_J<LP, LA, LB, C::TS, C::PCH>;
+  constexpr int lds = JLayout<LP, LA, LB, C::TSJ, C::PCHJ>::BYTES_WG;
+  auto kern = k_J<LP, LA, LB, C::TSJ, C::PCHJ>;
   static const hipError_t attr = hipFuncSetAttribute(
       reinterpret_cast<const void *>(kern), hipFuncAttributeMaxDynamicSharedMemorySize, lds);
   if (attr != hipSuccess) return attr;
-  hipLaunchKernelGGL(kern, dim3(grid), dim3(C::BLK), lds, s, a);
+  hipLaunchKernelGGL(kern, dim3(grid), dim3(C::BLKJ), lds, s, a);
   return hipGetLastError();
 }
 
 template <int LP, int LA, int LB>
 hipError_t launch_Jq(const JQArgs &a, int grid, hipStream_t s) {
   using C = Cfg<LP, LA, LB>;
-  constexpr int lds = JLayout<LP, LA, LB, C::TS, C::PCH>::BYTES_WG;
-  auto kern = k_Jq<LP, LA, LB, C::TS, C::PCH>;
+  constexpr int lds = JLayout<LP, LA, LB, C::TSJ, C::PCHJ>::BYTES_WG;
+  auto kern = k_Jq<LP, LA, LB, C::TSJ, C::PCHJ>;
   static const hipError_t attr = hipFuncSetAttribute(
       reinterpret_cast<const void *>(kern), hipFuncAttributeMaxDynamicSharedMemorySize, lds);
   if (attr != hipSuccess) return attr;
-  hipLaunchKernelGGL(kern, dim3(grid), dim3(C::BLK), lds, s, a);
+  hipLaunchKernelGGL(kern, dim3(grid), dim3(C::BLKJ), lds, s, a);
   return hipGetLastError();
 }
 
@@ -83,6 +84,7 @@ ClassInfo class_info() {
   ClassInfo c;
   c.ts = C::TS;
   c.tpw = C::BLK / C::TS;
+  c.tpwj = C::BLKJ / C::TSJ;
   c.lds = C::LDS;
   c.store = &launch_store<LP, LA, LB>;
   c.jfn = &launch_J<LP, LA, LB>;

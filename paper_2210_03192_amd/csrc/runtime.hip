@@ -531,7 +531,7 @@ int df3c_coulomb_J(const double *xyz, int32_t natom, const df3c_shells *aux,
         const ClassInfo &ci = g_cls[lp][la][lb];
         const int c = (lp * NLA + la) * NLA + lb;
         if (timed(DF3C_KERNEL_J, c, s,
-                  [&] { return ci.jfn(a, grid_for(a.npair, ci.tpw, ds->ncu), s); }) != hipSuccess)
+                  [&] { return ci.jfn(a, grid_for(a.npair, ci.tpwj, ds->ncu), s); }) != hipSuccess)
           return DF3C_E_HIP;
       }
   }
@@ -900,7 +900,7 @@ int df3c_coulomb_J_batched(const double *xyz, int32_t natom, const df3c_shells *
         q.total = p.cls_items[c];
         q.counter = ctr + c;
         const ClassInfo &ci = g_cls[lp][la][lb];
-        const int64_t need = (q.total + int64_t(ci.tpw) * q.chunk - 1) / (int64_t(ci.tpw) * q.chunk);
+        const int64_t need = (q.total + int64_t(ci.tpwj) * q.chunk - 1) / (int64_t(ci.tpwj) * q.chunk);
         const int grid = int(std::max<int64_t>(
             1, std::min<int64_t>(need, int64_t(ds->ncu) * tt[c].grid_per_cu)));
         if (timed(DF3C_KERNEL_JQ, c, s, [&] { return ci.jq(q, grid, s); }) != hipSuccess)
@@ -927,7 +927,7 @@ int df3c_coulomb_J_batched(const double *xyz, int32_t natom, const df3c_shells *
             a.npair = sg.npair;
             const ClassInfo &ci = g_cls[lp][la][lb];
             if (timed(DF3C_KERNEL_J, c, s, [&] {
-                  return ci.jfn(a, grid_for(a.npair, ci.tpw, ds->ncu), s);
+                  return ci.jfn(a, grid_for(a.npair, ci.tpwj, ds->ncu), s);
                 }) != hipSuccess)
               return DF3C_E_HIP;
           }
