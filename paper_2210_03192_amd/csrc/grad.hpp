@@ -321,4 +321,349 @@ __global__ void __launch_bounds__(TS > 64 ? TS : 64)
   for (int x = tid; x < 3 * g.natom; x += TS) part[x] += ACC[x];
 }
 
+// ---------------------------------------------------------------------------
+// Register gradient engine for small classes: one lane per shell pair, every
+// intermediate in registers (compile-time indices), one wavefront per
+// workgroup.  Per primitive triplet: setup, Boys, 1-quantal VRR1 up to
+// l_a + l_b + 1, the d-contracted ket digested as in the register J engine,
+//   Y_e = sum_u e!/(e-u)! H_u [e-u 0|0]^(LP),
+// accumulated with the weights of the shifted classes: Ya (2 zeta_a, targets of
+// (l_a+1, l_b)), Yb (2 zeta_b, targets of (l_a, l_b+1)) and Y0 (1, targets of
+// (l_a-1, l_b) and (l_a, l_b-1)).  Per aux shell the HRR of the shifted blocks
+// is contracted with G~ in registers:
+//   dA_x = sum_ab G~_ab [(a+1_x b|)^{2 zeta_a} - a_x (a-1_x b|)],
+//   dB_x = sum_ab G~_ab [(a b+1_x|)^{2 zeta_b} - b_x (a b-1_x|)],
+// dC = -(dA + dB) is summed over the wavefront (fixed butterfly order) and added
+// to the aux shell's atom; dA, dB of the pairs are added lane by lane at the
+// end, so the per-workgroup atom array is filled in a fixed order.
+// ---------------------------------------------------------------------------
+template <int LP, int LA, int LB>
+struct GReg {
+  static constexpr int L = LA + LB + 1;               // top VRR1 level
+  static constexpr int EL = LA > 0 ? LA - 1 : 0;      // lowest target level
+  static constexpr int NA = ncart(LA), NB = ncart(LB);
+  static constexpr int KU = imin(LP, L);
+  static constexpr int NU = offT(KU + 1);
+  // target ranges of the accumulators (levels, inclusive)
+  static constexpr int A0 = LA + 1, A1 = L;           // Ya
+  static constexpr int B0 = LA, B1 = L;               // Yb
+  static constexpr int Z0 = EL, Z1 = LA + LB - 1;     // Y0 (empty when LA = LB = 0)
+  static constexpr int ny(int lo, int hi) { return hi >= lo ? offT(hi + 1) - offT(lo) : 0; }
+  static constexpr int NYA = ny(A0, A1), NYB = ny(B0, B1), NY0 = ny(Z0, Z1);
+  static constexpr int voff(int l) {
+    int o = 0;
+    for (int q = 0; q < l; ++q) o += ncart(q) * (L - q + 1);
+    return o;
+  }
+  static constexpr int NVR = voff(L + 1);
+  static constexpr int COST = NYA + NYB + NY0 + ncart(LP) + NU + NVR / 2 + NA * NB;
+  static constexpr bool OK = L <= 4 && COST <= 170;
+};
+
+template <int LP, int LA, int LB>
+__global__ void __launch_bounds__(64) k_gradr(GradArgs g) {
+  using R = GReg<LP, LA, LB>;
+  using SH = GenSolid<LP>;
+  constexpr int L = R::L, NCP = ncart(LP), NA = R::NA, NB = R::NB;
+  extern __shared__ double smem[];
+  double *ACC = smem;  // [natom][3] of this workgroup
+  const int lane = threadIdx.x;
+  for (int x = lane; x < 3 * g.natom; x += 64) ACC[x] = 0.0;
+  __syncthreads();
+
+  for (int64_t base = int64_t(blockIdx.x) * 64; base < g.npair; base += int64_t(gridDim.x) * 64) {
+    const int64_t q = base + lane;
+    const bool valid = q < g.npair;
+    int sa = 0, sb = 0;
+    if (valid) {
+      if (g.same) {
+        int i = int((sqrt(8.0 * double(q) + 1.0) - 1.0) * 0.5);
+        while (int64_t(i) * (i + 1) / 2 > q) --i;
+        while (int64_t(i + 1) * (i + 2) / 2 <= q) ++i;
+        const int j = int(q - int64_t(i) * (i + 1) / 2);
+        sa = g.ash[i];
+        sb = g.ash[j];
+      } else {
+        const int i = int(q / g.nb), j = int(q - int64_t(i) * g.nb);
+        sa = g.ash[i];
+        sb = g.bsh[j];
+      }
+      if (LA == LB && sa != sb) {
+        // same orientation rule as the forward J kernels
+        auto tight = [&](int sh) {
+          const double *e = g.orb.exps + g.orb.prim_off[sh];
+          double lo = e[0], hi = e[0];
+          for (int i = 1; i < g.orb.nprim[sh]; ++i) {
+            lo = fmin(lo, e[i]);
+            hi = fmax(hi, e[i]);
+          }
+          return lo * hi;
+        };
+        if (tight(sb) > tight(sa)) {
+          const int t = sa;
+          sa = sb;
+          sb = t;
+        }
+      }
+    }
+    const int Ka = valid ? g.orb.nprim[sa] : 0, Kb = valid ? g.orb.nprim[sb] : 0;
+    const double *ea = g.orb.exps + (valid ? g.orb.prim_off[sa] : 0);
+    const double *ca = g.orb.coefs + (valid ? g.orb.prim_off[sa] : 0);
+    const double *eb = g.orb.exps + (valid ? g.orb.prim_off[sb] : 0);
+    const double *cb = g.orb.coefs + (valid ? g.orb.prim_off[sb] : 0);
+    const int atA = valid ? g.orb.atom[sa] : 0, atB = valid ? g.orb.atom[sb] : 0;
+    double A[3], B[3];
+#pragma unroll
+    for (int x = 0; x < 3; ++x) {
+      A[x] = g.xyz[3 * atA + x];
+      B[x] = g.xyz[3 * atB + x];
+    }
+    const double AB2 = (A[0] - B[0]) * (A[0] - B[0]) + (A[1] - B[1]) * (A[1] - B[1]) +
+                       (A[2] - B[2]) * (A[2] - B[2]);
+    // G~ of the pair (both J blocks of an off-diagonal pair)
+    double gt[NA * NB];
+    {
+      const int64_t ra = valid ? g.ao_off[sa] : 0, rb = valid ? g.ao_off[sb] : 0;
+#pragma unroll
+      for (int ia = 0; ia < NA; ++ia)
+#pragma unroll
+        for (int ib = 0; ib < NB; ++ib) {
+          double v = 0.0;
+          if (valid) {
+            v = g.G[(ra + ia) * g.nao + rb + ib];
+            if (sa != sb) v += g.G[(rb + ib) * g.nao + ra + ia];
+          }
+          gt[ia * NB + ib] = v;
+        }
+    }
+    double pwx[LB + 2], pwy[LB + 2], pwz[LB + 2];
+    pwx[0] = pwy[0] = pwz[0] = 1.0;
+#pragma unroll
+    for (int k = 1; k <= LB + 1; ++k) {
+      pwx[k] = pwx[k - 1] * (A[0] - B[0]);
+      pwy[k] = pwy[k - 1] * (A[1] - B[1]);
+      pwz[k] = pwz[k - 1] * (A[2] - B[2]);
+    }
+    double GA[3] = {0, 0, 0}, GB[3] = {0, 0, 0};
+
+    for (int ip = 0; ip < g.np; ++ip) {  // uniform over the wavefront
+      const int sP = g.psh[ip];
+      const int Kc = g.aux.nprim[sP];
+      const double *ec = g.aux.exps + g.aux.prim_off[sP];
+      const double *cc = g.aux.coefs + g.aux.prim_off[sP];
+      const int atC = g.aux.atom[sP];
+      const double C[3] = {g.xyz[3 * atC], g.xyz[3 * atC + 1], g.xyz[3 * atC + 2]};
+      const double *dP = g.d + g.aux_off[sP];
+      double dq[NCP];
+      if (g.pure) {
+        static_for<NCP>([&](auto cc_) {
+          constexpr int c = decltype(cc_)::value;
+          double v = 0.0;
+          static_for<npure(LP)>([&](auto mc) {
+            constexpr int m = decltype(mc)::value;
+            constexpr double t = SH::dense[m * NCP + c];
+            if constexpr (t != 0.0) v += t * dP[m];
+          });
+          dq[c] = v;
+        });
+      } else {
+#pragma unroll
+        for (int c = 0; c < NCP; ++c) dq[c] = dP[c];
+      }
+      double Ya[R::NYA > 0 ? R::NYA : 1], Yb[R::NYB > 0 ? R::NYB : 1],
+          Y0[R::NY0 > 0 ? R::NY0 : 1];
+#pragma unroll
+      for (int e = 0; e < R::NYA; ++e) Ya[e] = 0.0;
+#pragma unroll
+      for (int e = 0; e < R::NYB; ++e) Yb[e] = 0.0;
+#pragma unroll
+      for (int e = 0; e < R::NY0; ++e) Y0[e] = 0.0;
+      for (int ia = 0; ia < Ka; ++ia)
+        for (int ib = 0; ib < Kb; ++ib) {
+          const double za = ea[ia], zb = eb[ib];
+          const double gg = za + zb, ig = 1.0 / gg;
+          const double P[3] = {(za * A[0] + zb * B[0]) * ig, (za * A[1] + zb * B[1]) * ig,
+                               (za * A[2] + zb * B[2]) * ig};
+          const double PA[3] = {P[0] - A[0], P[1] - A[1], P[2] - A[2]};
+          const double eab = exp(-za * zb * ig * AB2) * ca[ia] * cb[ib];
+          for (int ic = 0; ic < Kc; ++ic) {
+            const double zc = ec[ic];
+            const double PC[3] = {P[0] - C[0], P[1] - C[1], P[2] - C[2]};
+            const double gz = gg + zc, rho = gg * zc / gz, rg = rho * ig, i2g = 0.5 * ig;
+            const double T = rho * (PC[0] * PC[0] + PC[1] * PC[1] + PC[2] * PC[2]);
+            const double pre = 34.98683665524972497 / (sqrt(gz) * gg * zc) * eab * cc[ic];
+            const double RP[3] = {rg * PC[0], rg * PC[1], rg * PC[2]};
+            double Fm[L + 1];
+            boys<LP, L + 1>(g.boys, T, Fm);
+            double vr[R::NVR];
+#pragma unroll
+            for (int m = 0; m <= L; ++m) vr[m] = pre * Fm[m];
+            static_for<L>([&](auto lc) {
+              constexpr int l = decltype(lc)::value + 1;
+              static_for<ncart(l)>([&](auto cc_) {
+                constexpr int c = decltype(cc_)::value;
+                constexpr C3 e = cart(l, c);
+                constexpr int i = rdir(e);
+                constexpr int c1 = cidx(e[0] - (i == 0), e[1] - (i == 1), e[2] - (i == 2));
+                constexpr int o1 = R::voff(l - 1) + c1 * (L - l + 2);
+                constexpr int o = R::voff(l) + c * (L - l + 1);
+                static_for<L - l + 1>([&](auto mc) {
+                  constexpr int m = decltype(mc)::value;
+                  double v = PA[i] * vr[o1 + m] - RP[i] * vr[o1 + m + 1];
+                  if constexpr (e[i] >= 2) {
+                    constexpr int c2 = cidx(e[0] - 2 * (i == 0), e[1] - 2 * (i == 1),
+                                            e[2] - 2 * (i == 2));
+                    constexpr int o2 = R::voff(l - 2) + c2 * (L - l + 3);
+                    v += double(e[i] - 1) * i2g * (vr[o2 + m] - rg * vr[o2 + m + 1]);
+                  }
+                  vr[o + m] = v;
+                });
+              });
+            });
+            const double s = rho * ig * (0.5 / zc), rz = rho / zc;
+            double wx[LP + 1], wy[LP + 1], wz[LP + 1], sk[R::KU + 1];
+            wx[0] = wy[0] = wz[0] = sk[0] = 1.0;
+#pragma unroll
+            for (int k = 1; k <= LP; ++k) {
+              wx[k] = wx[k - 1] * (rz * PC[0]);
+              wy[k] = wy[k - 1] * (rz * PC[1]);
+              wz[k] = wz[k - 1] * (rz * PC[2]);
+            }
+#pragma unroll
+            for (int k = 1; k <= R::KU; ++k) sk[k] = sk[k - 1] * s;
+            double H[R::NU];
+            static_for<R::KU + 1>([&](auto kc) {
+              constexpr int k = decltype(kc)::value;
+              static_for<ncart(k)>([&](auto uc) {
+                constexpr int ui = decltype(uc)::value;
+                constexpr C3 u = cart(k, ui);
+                double h = 0.0;
+                static_for<NCP>([&](auto cc_) {
+                  constexpr int c = decltype(cc_)::value;
+                  constexpr C3 qq = cart(LP, c);
+                  if constexpr (qq[0] >= u[0] && qq[1] >= u[1] && qq[2] >= u[2]) {
+                    constexpr double bn =
+                        double(binom(qq[0], u[0]) * binom(qq[1], u[1]) * binom(qq[2], u[2]));
+                    h += (bn * dq[c]) *
+                         (wx[qq[0] - u[0]] * wy[qq[1] - u[1]] * wz[qq[2] - u[2]]);
+                  }
+                });
+                H[offT(k) + ui] = sk[k] * h;
+              });
+            });
+            const double wA = 2.0 * za, wB = 2.0 * zb;
+            static_for<L - R::EL + 1>([&](auto lc) {
+              constexpr int le = R::EL + decltype(lc)::value;
+              static_for<ncart(le)>([&](auto ec_) {
+                constexpr int ce = decltype(ec_)::value;
+                constexpr C3 e = cart(le, ce);
+                double y = 0.0;
+                static_for<e[0] + 1>([&](auto xc) {
+                  constexpr int ux = decltype(xc)::value;
+                  static_for<e[1] + 1>([&](auto yc) {
+                    constexpr int uy = decltype(yc)::value;
+                    static_for<e[2] + 1>([&](auto zc_) {
+                      constexpr int uz = decltype(zc_)::value;
+                      constexpr int k = ux + uy + uz;
+                      if constexpr (k <= LP) {
+                        constexpr int lr = le - k;
+                        constexpr int cr = cidx(e[0] - ux, e[1] - uy, e[2] - uz);
+                        constexpr double f = double(falling(e[0], ux) * falling(e[1], uy) *
+                                                    falling(e[2], uz));
+                        y += (f * H[offT(k) + cidx(ux, uy, uz)]) *
+                             vr[R::voff(lr) + cr * (L - lr + 1)];
+                      }
+                    });
+                  });
+                });
+                if constexpr (le >= R::A0 && le <= R::A1) Ya[offT(le) - offT(R::A0) + ce] += wA * y;
+                if constexpr (le >= R::B0 && le <= R::B1) Yb[offT(le) - offT(R::B0) + ce] += wB * y;
+                if constexpr (le >= R::Z0 && le <= R::Z1) Y0[offT(le) - offT(R::Z0) + ce] += y;
+              });
+            });
+          }
+        }
+      // HRR of the shifted blocks contracted with G~:
+      //   (a' b'|) = sum_{i <= b'} C(b', i) AB^{b'-i} Y[a' + i]
+      double pA[3] = {0, 0, 0}, pB[3] = {0, 0, 0};
+      static_for<NA>([&](auto ac) {
+        constexpr int ai = decltype(ac)::value;
+        constexpr C3 av = cart(LA, ai);
+        static_for<NB>([&](auto bc) {
+          constexpr int bi = decltype(bc)::value;
+          constexpr C3 bv = cart(LB, bi);
+          const double gab = gt[ai * NB + bi];
+          static_for<3>([&](auto xc) {
+            constexpr int x = decltype(xc)::value;
+            // hrr(Y, lo, a', b'): block element of Y's class with bra a', b'
+            auto hrr = [&](auto &Y, auto loc, auto a3c, auto b3c) {
+              constexpr int lo = decltype(loc)::value;
+              constexpr int ax = decltype(a3c)::value / 100, ay = (decltype(a3c)::value / 10) % 10,
+                            az = decltype(a3c)::value % 10;
+              constexpr int bx = decltype(b3c)::value / 100, by = (decltype(b3c)::value / 10) % 10,
+                            bz = decltype(b3c)::value % 10;
+              double v = 0.0;
+              static_for<bx + 1>([&](auto ixc) {
+                constexpr int ix = decltype(ixc)::value;
+                static_for<by + 1>([&](auto iyc) {
+                  constexpr int iy = decltype(iyc)::value;
+                  static_for<bz + 1>([&](auto izc) {
+                    constexpr int iz = decltype(izc)::value;
+                    constexpr int lev = ax + ay + az + ix + iy + iz;
+                    constexpr int idx = offT(lev) - offT(lo) + cidx(ax + ix, ay + iy, az + iz);
+                    constexpr double bn = double(binom(bx, ix) * binom(by, iy) * binom(bz, iz));
+                    v += (bn * pwx[bx - ix] * pwy[by - iy] * pwz[bz - iz]) * Y[idx];
+                  });
+                });
+              });
+              return v;
+            };
+            constexpr int d100 = x == 0 ? 100 : x == 1 ? 10 : 1;
+            constexpr int ac3 = av[0] * 100 + av[1] * 10 + av[2];
+            constexpr int bc3 = bv[0] * 100 + bv[1] * 10 + bv[2];
+            double vA = hrr(Ya, std::integral_constant<int, R::A0>{},
+                            std::integral_constant<int, ac3 + d100>{},
+                            std::integral_constant<int, bc3>{});
+            if constexpr (av[x] > 0)
+              vA -= double(av[x]) * hrr(Y0, std::integral_constant<int, R::Z0>{},
+                                        std::integral_constant<int, ac3 - d100>{},
+                                        std::integral_constant<int, bc3>{});
+            double vB = hrr(Yb, std::integral_constant<int, R::B0>{},
+                            std::integral_constant<int, ac3>{},
+                            std::integral_constant<int, bc3 + d100>{});
+            if constexpr (bv[x] > 0)
+              vB -= double(bv[x]) * hrr(Y0, std::integral_constant<int, R::Z0>{},
+                                        std::integral_constant<int, ac3>{},
+                                        std::integral_constant<int, bc3 - d100>{});
+            pA[x] += gab * vA;
+            pB[x] += gab * vB;
+          });
+        });
+      });
+#pragma unroll
+      for (int x = 0; x < 3; ++x) {
+        GA[x] += pA[x];
+        GB[x] += pB[x];
+        double v = -(pA[x] + pB[x]);
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+        if (lane == 0) ACC[3 * atC + x] += v;
+      }
+    }
+    // dA, dB of the pairs, lane by lane
+    for (int j = 0; j < 64; ++j) {
+      if (lane == j && valid) {
+#pragma unroll
+        for (int x = 0; x < 3; ++x) {
+          ACC[3 * atA + x] += GA[x];
+          ACC[3 * atB + x] += GB[x];
+        }
+      }
+    }
+  }
+  __syncthreads();
+  double *part = g.partial + int64_t(blockIdx.x) * 3 * g.natom;
+  for (int x = lane; x < 3 * g.natom; x += 64) part[x] += ACC[x];
+}
+
 }  // namespace df3c

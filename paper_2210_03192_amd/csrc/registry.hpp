@@ -17,8 +17,9 @@ struct ClassInfo {
 };
 
 struct GradInfo {
-  int tpb = 0;        // teams per workgroup
+  int tpb = 0;        // per-atom LDS arrays (teams) per workgroup
   int team = 0;       // LDS doubles per team before the per-atom array
+  int ppw = 0;        // shell pairs per workgroup and grid step
   hipError_t (*gfn)(const GradArgs &, int, int, hipStream_t) = nullptr;  // (args, grid, lds)
 };
 
@@ -69,12 +70,30 @@ hipError_t launch_grad(const GradArgs &a, int grid, int lds, hipStream_t s) {
 }
 
 template <int LP, int LA, int LB>
+hipError_t launch_gradr(const GradArgs &a, int grid, int lds, hipStream_t s) {
+  auto kern = k_gradr<LP, LA, LB>;
+  static const hipError_t attr = hipFuncSetAttribute(
+      reinterpret_cast<const void *>(kern), hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+  if (attr != hipSuccess) return attr;
+  hipLaunchKernelGGL(kern, dim3(grid), dim3(64), lds, s, a);
+  return hipGetLastError();
+}
+
+template <int LP, int LA, int LB>
 GradInfo grad_info() {
   using C = GradCfg<LP, LA, LB>;
   GradInfo g;
-  g.tpb = C::TPB;
-  g.team = C::TEAM;
-  g.gfn = &launch_grad<LP, LA, LB>;
+  if constexpr (GReg<LP, LA, LB>::OK) {
+    g.tpb = 1;
+    g.team = 0;
+    g.ppw = 64;
+    g.gfn = &launch_gradr<LP, LA, LB>;
+  } else {
+    g.tpb = C::TPB;
+    g.team = C::TEAM;
+    g.ppw = C::TPB;
+    g.gfn = &launch_grad<LP, LA, LB>;
+  }
   return g;
 }
 

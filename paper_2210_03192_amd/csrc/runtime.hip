@@ -642,7 +642,7 @@ int df3c_coulomb_J_grad(const double *xyz, int32_t natom, const df3c_shells *aux
         const GradInfo &gi = g_grad[lp][la][lb];
         const int lds = gi.tpb * (gi.team + 3 * natom) * 8;
         if (lds > 160 * 1024) return DF3C_E_UNSUPPORTED;
-        const int grid = int(std::max<int64_t>(1, std::min<int64_t>((a.npair + gi.tpb - 1) / gi.tpb,
+        const int grid = int(std::max<int64_t>(1, std::min<int64_t>((a.npair + gi.ppw - 1) / gi.ppw,
                                                                      grid_cap)));
         if (timed(DF3C_KERNEL_GRAD, (lp * NLA + la) * NLA + lb, s,
                   [&] { return gi.gfn(a, grid, lds, s); }) != hipSuccess)
