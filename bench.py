@@ -64,7 +64,7 @@ def parse():
     p.add_argument("--ntrip", type=int, default=100000)
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-dfj", action="store_true")
-    p.add_argument("--batched-nmol", type=int, default=16)
+    p.add_argument("--batched-nmol", type=int, default=64)
     p.add_argument("--copy-calibration-mib", type=int, default=0,
                    help="first run a plain device copy of this many MiB three times "
                         "(the reference kernel for hardware byte counters)")

@@ -337,6 +337,13 @@ __global__ void __launch_bounds__(TS > 64 ? TS : 64)
 // to the aux shell's atom; dA, dB of the pairs are added lane by lane at the
 // end, so the per-workgroup atom array is filled in a fixed order.
 // ---------------------------------------------------------------------------
+#ifndef DF3C_GREG_LMAX
+#define DF3C_GREG_LMAX 4
+#endif
+#ifndef DF3C_GREG_COST
+#define DF3C_GREG_COST 170
+#endif
+
 template <int LP, int LA, int LB>
 struct GReg {
   static constexpr int L = LA + LB + 1;               // top VRR1 level
@@ -357,7 +364,7 @@ struct GReg {
   }
   static constexpr int NVR = voff(L + 1);
   static constexpr int COST = NYA + NYB + NY0 + ncart(LP) + NU + NVR / 2 + NA * NB;
-  static constexpr bool OK = L <= 4 && COST <= 170;
+  static constexpr bool OK = L <= DF3C_GREG_LMAX && COST <= DF3C_GREG_COST;
 };
 
 template <int LP, int LA, int LB>
