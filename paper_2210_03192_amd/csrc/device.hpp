@@ -114,22 +114,27 @@ __device__ __forceinline__ void vrr1(double *prims, int npc, int tid) {
         const int pp = it / NIT, x = it - pp * NIT;
         const double *P = prims + pp * REC;
         const double *T = P + PS_N;
-        const VO o = V::ofs[IOFF + x];
-        const int ip = (o.ax >> 2) & 3;
+        // the 32-byte item record in two 16-byte loads; all fields are >= 0
+        const uint4 *vp = reinterpret_cast<const uint4 *>(&V::ofs[IOFF + x]);
+        const uint4 w0 = vp[0], w1 = vp[1];
+        const int u0 = w0.x & 0xffff, u1o = w0.x >> 16, u2 = w0.y & 0xffff, l0 = w0.y >> 16;
+        const int l1o = w0.z & 0xffff, l2 = w0.z >> 16, y0 = w0.w & 0xffff, y1 = w0.w >> 16;
+        const int od = w1.x & 0xffff, ax = w1.x >> 16, f1 = w1.y & 0xffff, f2 = w1.y >> 16;
+        const int ip = (ax >> 2) & 3;
         const double i2g = P[PS_I2G], rg = P[PS_RG];
         const double pa = P[PS_PAX + ip], rp = P[PS_RPX + ip];
-        const double c1 = double(o.f1) * i2g;
-        const double u1 = T[o.u1], l1 = T[o.l1];
-        double val = pa * T[o.u0] - rp * u1 + c1 * (T[o.l0] - rg * l1);
-        if (o.ax & 16) {
+        const double c1 = double(f1) * i2g;
+        const double u1 = T[u1o], l1 = T[l1o];
+        double val = pa * T[u0] - rp * u1 + c1 * (T[l0] - rg * l1);
+        if (ax & 16) {
           // 2-q: val is [x]^(m); [x]^(m+1), then the outer step along i
-          const int i = o.ax & 3;
-          const double x1 = pa * u1 - rp * T[o.u2] + c1 * (l1 - rg * T[o.l2]);
+          const int i = ax & 3;
+          const double x1 = pa * u1 - rp * T[u2] + c1 * (l1 - rg * T[l2]);
           val = P[PS_PAX + i] * val - P[PS_RPX + i] * x1 +
-                double(o.f2) * i2g * (T[o.y0] - rg * T[o.y1]);
+                double(f2) * i2g * (T[y0] - rg * T[y1]);
         }
         res[q] = val;
-        dst[q] = pp * REC + PS_N + o.dst;
+        dst[q] = pp * REC + PS_N + od;
       }
     }
     team_sync();

@@ -397,13 +397,15 @@ def write(outdir):
             s.append(arr("int16_t", "pi_sw", sw))
             s.append(arr("int16_t", "pi_v", v))
             s.append(arr("int32_t", "cb_start", st))
-            s.append(arr("int16_t", "cb_pi", pi))
-            s.append(arr("int32_t", "cb_w", w))
+            # one word per term: weight << 16 | prerequisite index
+            assert max(pi, default=0) < 65536 and max(w, default=0) < 65536
+            s.append(arr("uint32_t", "cb_pw", [(ww << 16) | pp for pp, ww in zip(pi, w)]))
             js, jm, jc = jx_terms(g)
             s.append(f"  static constexpr int NM = {jm_off(g, LP + 1)};\n")
             s.append(arr("int16_t", "jx_start", js))
-            s.append(arr("int16_t", "jx_m", jm))
-            s.append(arr("int32_t", "jx_c", jc))
+            # one word per term: coefficient << 16 | index into M
+            assert max(jm, default=0) < 65536 and max(jc, default=0) < 65536
+            s.append(arr("uint32_t", "jx_mc", [(cc << 16) | mm for mm, cc in zip(jm, jc)]))
             s.append("};\n")
         s.append("}  // namespace df3c\n")
         _write_if_changed(os.path.join(outdir, f"tables_lp{LP}.hpp"), "".join(s))
@@ -426,9 +428,10 @@ def write(outdir):
         s.append(arr("double", "dense", [repr(x) for r in rows for x in r]))
         hs, hc, hw, hb = jh_terms(l)
         s.append(arr("int16_t", "jh_start", hs))
-        s.append(arr("int8_t", "jh_c", hc))
-        s.append(arr("int16_t", "jh_sw", hw))
-        s.append(arr("int16_t", "jh_b", hb))
+        # one word per term: binomial << 16 | sW index << 8 | c
+        assert max(hc, default=0) < 256 and max(hw, default=0) < 256 and max(hb, default=0) < 65536
+        s.append(arr("uint32_t", "jh_t", [(bb << 16) | (ww << 8) | cc
+                                          for cc, ww, bb in zip(hc, hw, hb)]))
         s.append("};\n")
     for la in range(LMAX_ORB + 1):
         for lb in range(LMAX_ORB + 1):
@@ -446,7 +449,7 @@ def write(outdir):
         s.append(f"  static constexpr int N = {len(items)};\n")
         ofs, nt, nw = vofs(L)
         s.append(f"  static constexpr int NT = {nt}, NW = {nw};\n")
-        s.append(arr("VO", "ofs", ["{" + ",".join(str(x) for x in t) + "}" for t in ofs]))
+        s.append(arr("VO", "ofs", ["{" + ",".join(str(x) for x in t) + ",0,0,0,0}" for t in ofs]))
         s.append("};\n")
     s.append("}  // namespace df3c\n")
     _write_if_changed(os.path.join(outdir, "tables_common.hpp"), "".join(s))

@@ -380,7 +380,12 @@ __device__ __forceinline__ void triplet_to_e0P(const double *btab, double *S, in
     const int q0 = TB::cb_start[t], q1 = TB::cb_start[t + 1];
     if (q1 > q0) {
       double a = PI[t];
-      for (int q = q0; q < q1; ++q) a += double(TB::cb_w[q]) * PI[TB::cb_pi[q]];
+      // independent table loads, batched so their latencies overlap
+#pragma unroll 8
+      for (int q = q0; q < q1; ++q) {
+        const uint32_t c = TB::cb_pw[q];
+        a += double(c >> 16) * PI[c & 0xffffu];
+      }
       PI[t] = a;
     }
   }
@@ -969,8 +974,11 @@ __device__ __forceinline__ void jeng_pair(const JArgs &a, double *S, int tid, bo
         const int u = it / npc, pp = it - u * npc;
         const double *SWp = prims + pp * REC + PS_N + G::NV1;
         double h = 0.0;
-        for (int q = SH::jh_start[u]; q < SH::jh_start[u + 1]; ++q)
-          h += double(SH::jh_b[q]) * DP[SH::jh_c[q]] * SWp[SH::jh_sw[q]];
+#pragma unroll 4
+        for (int q = SH::jh_start[u]; q < SH::jh_start[u + 1]; ++q) {
+          const uint32_t t = SH::jh_t[q];
+          h += double(t >> 16) * DP[t & 0xffu] * SWp[(t >> 8) & 0xffu];
+        }
         prims[pp * REC + JE::HU + u] = h;
       }
       team_sync();
@@ -1025,8 +1033,11 @@ __device__ __forceinline__ void jeng_pair(const JArgs &a, double *S, int tid, bo
   double *XD = S + JE::XD;
   for (int e = tid; e < G::NE; e += TS) {
     double v = 0.0;
-    for (int q = TB::jx_start[e]; q < TB::jx_start[e + 1]; ++q)
-      v += double(TB::jx_c[q]) * MJ[TB::jx_m[q]];
+#pragma unroll 8
+    for (int q = TB::jx_start[e]; q < TB::jx_start[e + 1]; ++q) {
+      const uint32_t t = TB::jx_mc[q];
+      v += double(t >> 16) * MJ[t & 0xffffu];
+    }
     XD[e] = v;
   }
   team_sync();

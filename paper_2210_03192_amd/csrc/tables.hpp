@@ -152,18 +152,19 @@ struct VStages {
 //   2-quantal (q = 1): the same step along ip gives [x]^(m), [x]^(m+1) of
 //     x = e - 1_i in registers, then one step along i (lower term via y = e-2_i).
 // A missing operand points at offset 0 and carries a zero coefficient.
-struct alignas(8) VO {
+struct alignas(16) VO {
   int16_t u0, u1, u2;  // upper input at m, m+1, m+2
   int16_t l0, l1, l2;  // lower input at m, m+1, m+2
   int16_t y0, y1;      // 2-q: e-2_i (upper input level) at m, m+1
   int16_t dst;         // output
   int16_t ax;          // i | ip << 2 | q << 4
   int16_t f1, f2;      // integer coefficients (e_ip - 1 or e_i - 1; e_i - 1)
+  int16_t pad[4];      // 32 bytes: two 16-byte loads per item
 };
 
 // Generated tables (gen_tables.py):
 //   GenTab<LP, EA, EB>: CVRR2 contraction map (pi_sw, pi_v) and n-q CVRR2
-//                        combine (cb_start, cb_pi, cb_w)
+//                        combine (cb_start, cb_pw)
 //   GenSolid<l>:        solid-harmonic transform, CSR rows m = -l..l
 //   GenHrr<LA, LB>:     n-q HRR terms
 //   GenV<L>:            VRR1 stage items (operand offsets)
