@@ -52,10 +52,11 @@ struct JArgs {
 };
 
 // LDS layout of one team (in doubles).  Regions are reused once dead:
-//   PI   [0, NPI)                 pi; its block k = 0 is the target (e0|c) ([c][e''])
-//   PRIM [NPI, NPI + PCH*REC)     primitive records of the current chunk
-//   EM   (e0|P) [m][e'']          in the dead tail of pi, else in PRIM, else extra
-//   STG  output staging          in the dead pi_0 / PRIM area not used by EM, else extra
+//   PRIM [0, PCH*REC)             primitive records of the current chunk (loop only)
+//   PI   [0, NPI)                 pi, written after the loop; its block k = 0 is
+//                                 the target (e0|c) ([c][e''])
+//   EM   (e0|P) [m][e'']          in the dead tail of pi, else after everything
+//   STG  output staging          at 0 (dead pi_0) when EM starts beyond it, else extra
 template <int LP, int LA, int LB, int PCH>
 struct Layout {
   using G = Geo<LP, LA, LA + LB>;
@@ -64,17 +65,21 @@ struct Layout {
   static constexpr int NEM = G::NPURE * G::NE;
   static constexpr int NOUT = G::NPURE * ncart(LA) * ncart(LB);
   static constexpr int PI = 0;
-  static constexpr int PRIM = G::NPI;
-  static constexpr int PRIM_END = PRIM + PCH * REC;
-  // EM: after pi_0 if the tail of pi is large enough, else in the PRIM area
+  // the primitive records live only during the primitive loop, pi is written
+  // to LDS only after it: the two share the start of the slice
+  static constexpr int PRIM = 0;
+  static constexpr int PRIM_END = PCH * REC;
+  static constexpr int END_LOOP = imax(G::NPI, PRIM_END);
+  // EM: after pi_0 if the tail of pi is large enough, else after everything
   static constexpr bool EM_IN_PI = NEM <= G::NPI - NEC;
-  static constexpr bool EM_IN_PRIM = !EM_IN_PI && NEM <= PCH * REC;
-  static constexpr int EM = EM_IN_PI ? NEC : EM_IN_PRIM ? PRIM : PRIM_END;
+  static constexpr int EM = EM_IN_PI ? NEC : END_LOOP;
   static constexpr int EM_END = EM + NEM;
-  static constexpr int END0 = imax(PRIM_END, EM_END);
-  // STG must not overlap EM (read during the HRR)
-  static constexpr int STG = (EM >= NOUT) ? 0 : (EM_IN_PI && NOUT <= PCH * REC) ? PRIM : END0;
-  static constexpr int TOTAL = imax(END0, STG + NOUT);
+  static constexpr int END0 = imax(END_LOOP, EM_END);
+  // STG (written by the HRR) must not overlap EM (read by the HRR)
+  static constexpr int STG = (EM >= NOUT) ? 0 : END0;
+  // odd number of doubles: the slices of the teams of one workgroup start on
+  // different LDS banks
+  static constexpr int TOTAL = imax(END0, STG + NOUT) | 1;
 };
 
 // Team size and primitive chunk per class: small classes run one triplet per
@@ -116,18 +121,21 @@ struct Cfg {
                               G::NPURE * ncart(LA) * ncart(LB);
   static constexpr int TS = work >= 6000 ? 256 : work >= 2500 ? 128 : work >= 1024 ? 64
                             : work >= 256 ? 16 : work >= 48 ? 4 : 1;
-  static constexpr int PCH = TS >= 16 ? 4 : TS == 4 ? 2 : 1;
+  // primitives per chunk: whole-wave teams take as many groups of 4 (the K
+  // extent of one MFMA) as fit in the pi region, up to 16
+  static constexpr int REC = PS_N + G::NV1 + G::NSW;
+  static constexpr int PCH = TS >= 64 ? 4 * imax(1, imin(4, G::NPI / (4 * REC)))
+                             : TS >= 16 ? 4 : TS == 4 ? 2 : 1;
   static constexpr int BLK = TS > 64 ? TS : 64;
   static constexpr int LDS = (BLK / TS) * Layout<LP, LA, LB, PCH>::TOTAL * 8;
-  static constexpr int LDS_J = (BLK / TS) * (Layout<LP, LA, LB, PCH>::TOTAL + G::NE) * 8;
   // minimum waves per SIMD requested from the register allocator
   static constexpr int WPE = TS >= 128 ? DF3C_MIN_WAVES_BIG : TS == 64 ? DF3C_MIN_WAVES_WAVE : 1;
   // J kernels: one lane per shell pair on the register engine, else as above
   static constexpr bool JREG = TS < 64 && JReg<LP, LA, LB>::OK;
   static constexpr int TSJ = JREG ? 1 : TS;
-  static constexpr int PCHJ = JREG ? 1 : PCH;
+  static constexpr int PCHJ = JREG ? 1 : TS >= 64 ? 4 : PCH;
   static constexpr int BLKJ = TSJ > 64 ? TSJ : 64;
-  static_assert(LDS_J <= 160 * 1024, "class does not fit the LDS of a CU");
+  static_assert(LDS <= 160 * 1024, "class does not fit the LDS of a CU");
 };
 
 // ---------------------------------------------------------------------------
@@ -285,7 +293,7 @@ __device__ __forceinline__ void triplet_to_e0P(const double *btab, double *S, in
 
   // matrix-core contraction for whole-wave teams (chunks of 4 primitives = the
   // K extent of one MFMA); per-lane register slots otherwise
-  constexpr bool MF = (TS % 64 == 0) && PCH == 4;
+  constexpr bool MF = (TS % 64 == 0) && PCH % 4 == 0;
   using PT = PiTiles<G>;
   constexpr int NWV = TS >= 64 ? TS / 64 : 1;
   constexpr int NTW = MF ? (PT::N + NWV - 1) / NWV : 1;
@@ -313,20 +321,27 @@ __device__ __forceinline__ void triplet_to_e0P(const double *btab, double *S, in
     if constexpr (MF) {
       // lane (pl, il): primitive pl of the chunk, row / column il of a tile
       const int wl = lt >> 6, pc = (lt & 63) >> 4, cl = lt & 15;
-      const double *Rl = prims + pc * REC + PS_N + cl;
-      const bool pv = pc < npc;
-      static_for<NWV>([&](auto wc) {
-        constexpr int W = decltype(wc)::value;
-        if (wl == W) {
-          static_for<NTW>([&](auto jc) {
-            constexpr int j = decltype(jc)::value;
-            constexpr int t = j * NWV + W;
-            if constexpr (t < PT::N) {
-              constexpr int k = PT::field(t, 0), r0 = PT::field(t, 1), c0 = PT::field(t, 2);
-              constexpr int nr = ncart(LP - k) - r0, nc = G::nek(k) - c0;
-              const double av = (pv && cl < nr) ? Rl[G::NV1 + G::sw_off(k) + r0] : 0.0;
-              const double bv = (pv && cl < nc) ? Rl[offT(G::emin(k)) + c0] : 0.0;
-              macc[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, macc[j], 0, 0, 0);
+      // groups of 4 primitives: the K extent of one MFMA (empty groups skipped,
+      // uniformly over the team)
+      static_for<PCH / 4>([&](auto gc) {
+        constexpr int gq = decltype(gc)::value;
+        if (4 * gq < npc) {
+          const double *Rl = prims + (4 * gq + pc) * REC + PS_N + cl;
+          const bool pv = 4 * gq + pc < npc;
+          static_for<NWV>([&](auto wc) {
+            constexpr int W = decltype(wc)::value;
+            if (wl == W) {
+              static_for<NTW>([&](auto jc) {
+                constexpr int j = decltype(jc)::value;
+                constexpr int t = j * NWV + W;
+                if constexpr (t < PT::N) {
+                  constexpr int k = PT::field(t, 0), r0 = PT::field(t, 1), c0 = PT::field(t, 2);
+                  constexpr int nr = ncart(LP - k) - r0, nc = G::nek(k) - c0;
+                  const double av = (pv && cl < nr) ? Rl[G::NV1 + G::sw_off(k) + r0] : 0.0;
+                  const double bv = (pv && cl < nc) ? Rl[offT(G::emin(k)) + c0] : 0.0;
+                  macc[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, macc[j], 0, 0, 0);
+                }
+              });
             }
           });
         }
@@ -1072,7 +1087,7 @@ struct JLayout {
   static constexpr bool REG = TS == 1 && JReg<LP, LA, LB>::OK;
   static constexpr int TOTAL = REG ? 0
                                : use_jengine<LP, LA, LB, TS, PCH>() ? JELayout<LP, LA, LB, PCH>::TOTAL
-                                                                   : XD + G::NE;
+                                                                   : (XD + G::NE) | 1;
   static constexpr int BYTES_WG = ((TS > 64 ? TS : 64) / TS) * TOTAL * 8;
   static_assert(BYTES_WG <= 160 * 1024, "J layout does not fit the LDS of a CU");
 };
