@@ -47,6 +47,59 @@ MEASURED_TRAFFIC = {
 }
 
 
+def class_model_flop(LP, la, lb, K):
+    """Operation-count model of one contracted triplet with K primitive triplets
+    (the scheme as implemented: per primitive setup ~40 FLOP, Boys ~20 FLOP per
+    m, 4 FMA per VRR1 item, one FMA per CVRR2 prerequisite; per triplet the
+    CVRR2 combination, the sparse ket transform and the HRR at one FMA per term).
+    Used for the DF-J and gradient legs; the per-class batches use MODEL_FLOP."""
+    prim, fixed = _class_model(LP, la, lb)
+    return prim * K + fixed
+
+
+_MODEL_CACHE = {}
+
+
+def _class_model(LP, la, lb):
+    key = (LP, la, lb)
+    if key not in _MODEL_CACHE:
+        sys.path.insert(0, os.path.join(ROOT, "paper_2210_03192_amd", "csrc"))
+        import gen_tables as gt
+        g = gt.Geo(LP, la, la + lb)
+        L = la + lb
+        nnz = sum(1 for r in gt.solid(LP) for x in r if x != 0.0)
+        ne = gt.offT(L + 1) - gt.offT(la)
+        prim = 40 + 20 * (L + 1) + 8 * len(gt.vtab(L)) + 2 * g.NPI
+        fixed = 2 * len(gt.combine(g)[1]) + 2 * nnz * ne + 2 * gt.hrr(la, lb)[0][-1] * (2 * LP + 1)
+        _MODEL_CACHE[key] = (prim, fixed)
+    return _MODEL_CACHE[key]
+
+
+def system_model_flop(aux, orb, grad=False):
+    """Model FLOP of DF-J over all (P, a >= b) triplets of a system (no
+    screening); grad=True sums the four shifted classes of the derivative
+    integrals instead."""
+    from collections import Counter
+    ko = Counter(zip(orb.l.tolist(), orb.nprim.tolist()))
+    kp = Counter(zip(aux.l.tolist(), aux.nprim.tolist()))
+    total = 0.0
+    items = sorted(ko.items())
+    for i, ((la, ka), na) in enumerate(items):
+        for (lb, kb), nb in items[:i + 1]:
+            npair = na * (na + 1) // 2 if (la, ka) == (lb, kb) else na * nb
+            hi, lo = (la, lb) if la >= lb else (lb, la)
+            for (lp, kc), npp in kp.items():
+                K = ka * kb * kc
+                if grad:
+                    shifted = [(hi + 1, lo), (hi, lo + 1), (hi - 1, lo), (hi, lo - 1)]
+                    f = sum(class_model_flop(lp, max(x, y), min(x, y), K)
+                            for x, y in shifted if min(x, y) >= 0)
+                else:
+                    f = class_model_flop(lp, hi, lo, K)
+                total += f * npair * npp
+    return total
+
+
 def kernel_sources_sha256():
     import hashlib
     h = hashlib.sha256()
@@ -124,6 +177,8 @@ def dfj_legs(args, df3c, inputs, torch, dev):
         wsj = torch.empty(df3c.coulomb_J_workspace(aux, orb), dtype=torch.uint8, device=dev)
         out[f"dfj_ms_{name}"] = _time_ms(torch, lambda: df3c.coulomb_J(xyz, aux, orb, d, J=J,
                                                                         ws=wsj), 3)
+        mf = system_model_flop(s.aux, s.orb)
+        out[f"dfj_model_frac_{name}"] = mf / (out[f"dfj_ms_{name}"] * 1e-3) / PEAK_FP64
     # J gradient, 60 atoms
     s = inputs.grad_60_system()
     d = torch.as_tensor(inputs.fitting_coefficients(s.aux.nbf, 5), device=dev)
@@ -134,6 +189,10 @@ def dfj_legs(args, df3c, inputs, torch, dev):
     out["dfj_ms_water_60atoms"] = _time_ms(torch, lambda: df3c.coulomb_J(xyz, aux, orb, d), 2)
     out["grad_ms_water_60atoms"] = _time_ms(
         torch, lambda: df3c.coulomb_J_grad(xyz, aux, orb, d, G), 1)
+    out["dfj_model_frac_water_60atoms"] = system_model_flop(s.aux, s.orb) / (
+        out["dfj_ms_water_60atoms"] * 1e-3) / PEAK_FP64
+    out["grad_model_frac_water_60atoms"] = system_model_flop(s.aux, s.orb, grad=True) / (
+        out["grad_ms_water_60atoms"] * 1e-3) / PEAK_FP64
     # batched uneven clusters
     if args.batched_nmol > 0:
         from paper_2210_03192_amd import autotune
