@@ -94,6 +94,10 @@ struct Layout {
 #ifndef DF3C_MIN_WAVES_WAVE
 #define DF3C_MIN_WAVES_WAVE 2
 #endif
+// J kernels of the register engine (one lane per shell pair)
+#ifndef DF3C_MIN_WAVES_JREG
+#define DF3C_MIN_WAVES_JREG 1
+#endif
 
 // Small classes whose J runs on the register engine (jr_pair): VRR1 over all
 // m, the d-contracted ket and X fit the registers of one lane.
@@ -135,6 +139,7 @@ struct Cfg {
   static constexpr int TSJ = JREG ? 1 : TS;
   static constexpr int PCHJ = JREG ? 1 : TS >= 64 ? 4 : PCH;
   static constexpr int BLKJ = TSJ > 64 ? TSJ : 64;
+  static constexpr int WPEJ = JREG ? DF3C_MIN_WAVES_JREG : WPE;
   static_assert(LDS <= 160 * 1024, "class does not fit the LDS of a CU");
 };
 
@@ -1203,7 +1208,7 @@ __device__ __forceinline__ void j_pair(const JArgs &a, double *S, int tid, const
 
 template <int LP, int LA, int LB, int TS, int PCH>
 __global__ void __launch_bounds__(TS > 64 ? TS : 64)
-    __attribute__((amdgpu_waves_per_eu(Cfg<LP, LA, LB>::WPE))) k_J(JArgs a) {
+    __attribute__((amdgpu_waves_per_eu(Cfg<LP, LA, LB>::WPEJ))) k_J(JArgs a) {
   using G = Geo<LP, LA, LA + LB>;
   using JL = JLayout<LP, LA, LB, TS, PCH>;
   constexpr int BLK = TS > 64 ? TS : 64;

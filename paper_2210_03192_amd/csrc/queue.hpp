@@ -49,7 +49,7 @@ __device__ __forceinline__ int find_seg(const JSeg *seg, int nseg, int64_t item)
 
 template <int LP, int LA, int LB, int TS, int PCH>
 __global__ void __launch_bounds__(TS > 64 ? TS : 64)
-    __attribute__((amdgpu_waves_per_eu(Cfg<LP, LA, LB>::WPE))) k_Jq(JQArgs q) {
+    __attribute__((amdgpu_waves_per_eu(Cfg<LP, LA, LB>::WPEJ))) k_Jq(JQArgs q) {
   using G = Geo<LP, LA, LA + LB>;
   using JL = JLayout<LP, LA, LB, TS, PCH>;
   constexpr int BLK = TS > 64 ? TS : 64;
