@@ -1,8 +1,9 @@
 """CPU oracle -- TEST INFRASTRUCTURE ONLY.
 
 A plain, slow McMurchie-Davidson implementation (oracle.c) of the 3-center
-Coulomb integrals (P|ab), of J_ab = sum_P (ab|P) d_P and of the nuclear gradient
-of L = sum_ab G_ab J_ab, wrapped with ctypes.  Only tests/, the smoke check and
+Coulomb integrals (P|ab), of J_ab = sum_P (ab|P) d_P, of its adjoint
+gamma_P = sum_ab (P|ab) D_ab and of the nuclear gradient of L = sum_ab G_ab J_ab,
+wrapped with ctypes.  Only tests/, the smoke check and
 the benchmark's CPU-baseline leg may import this package; the GPU library never
 does.
 
@@ -46,6 +47,7 @@ def _lib(precision="double"):
         lib.oracle_solid_transform.argtypes = [ctypes.c_int, P]
         lib.oracle_eval_batch.argtypes = [P, P, P, ctypes.c_int64, P, P, P, ctypes.c_int]
         lib.oracle_coulomb_J.argtypes = [P, P, P, P, P, ctypes.c_int]
+        lib.oracle_coulomb_gamma.argtypes = [P, P, P, P, P, ctypes.c_int]
         lib.oracle_coulomb_J_pairs.argtypes = [P, P, P, P, ctypes.c_int64, P, P, P,
                                                ctypes.c_int]
         lib.oracle_coulomb_J_grad.argtypes = [P, ctypes.c_int32, P, P, P, P, P, P,
@@ -132,6 +134,18 @@ def coulomb_J(xyz, aux, orb, d, nthreads=0, precision="double"):
     _check(_lib(precision).oracle_coulomb_J(_ptr(xyz), pa.ref, po.ref, _ptr(d), _ptr(J),
                                             int(nthreads)), "coulomb_J")
     return J
+
+
+def coulomb_gamma(xyz, aux, orb, D, nthreads=0, precision="double"):
+    """gamma_P = sum_{a,b} (P|ab) D_ab (D: nao x nao, any symmetry)."""
+    xyz = np.ascontiguousarray(xyz, np.float64)
+    D = np.ascontiguousarray(D, np.float64)
+    naux = int(sum(nfunc(int(l), aux.pure) for l in aux.l))
+    g = np.zeros(naux)
+    pa, po = _Pinned(aux), _Pinned(orb)
+    _check(_lib(precision).oracle_coulomb_gamma(_ptr(xyz), pa.ref, po.ref, _ptr(D), _ptr(g),
+                                                int(nthreads)), "coulomb_gamma")
+    return g
 
 
 def coulomb_J_pairs(xyz, aux, orb, d, pairs, nthreads=0, precision="double"):

@@ -70,6 +70,7 @@ typedef double real;
 
 #define LMAX_ORB 9  /* orbital shells, including the +1 of the gradient */
 #define LMAX_AUX 8  /* auxiliary shells, including the +1 of the gradient */
+#define GRAD_LMAX_ORB 4  /* orbital shells of the gradient (its work arrays are sized for it) */
 #define MMAX_BOYS 40
 
 static int ncart(int l) { return (l + 1) * (l + 2) / 2; }
@@ -400,7 +401,10 @@ static void set_threads(int nthreads) {
 #endif
 }
 
-#define BLK_MAX (45 * 28 * 28)
+/* largest Cartesian block [c][a][b]: aux l <= LMAX_AUX - 1, orbital l <= LMAX_ORB - 1 */
+#define NC_AUX ((LMAX_AUX) * (LMAX_AUX + 1) / 2)
+#define NC_ORB ((LMAX_ORB) * (LMAX_ORB + 1) / 2)
+#define BLK_MAX (NC_AUX * NC_ORB * NC_ORB)
 
 int oracle_eval_batch(const double *xyz, const oracle_basis *aux, const oracle_basis *orb,
                       int64_t ntrip, const int32_t *trip, const int64_t *out_off, double *out,
@@ -460,6 +464,52 @@ static void J_block(const double *xyz, const oracle_basis *aux, const oracle_bas
   }
 }
 
+/* gamma_P = sum_{a,b} (P|ab) D_ab over all ordered orbital shell pairs: the
+ * definition written out (the contraction of the right-hand side of the fitting
+ * equations, and dL/dd for L = sum_ab G_ab J_ab with D = G).  One loop
+ * iteration owns one aux shell. */
+int oracle_coulomb_gamma(const double *xyz, const oracle_basis *aux, const oracle_basis *orb,
+                         const double *D, double *gamma, int nthreads) {
+  if (check_basis(aux, LMAX_AUX - 1) || check_basis(orb, LMAX_ORB - 1) || orb->pure) return -1;
+  set_threads(nthreads);
+  int64_t *aoff = (int64_t *)malloc(sizeof(int64_t) * (aux->nshell + 1));
+  int64_t *ooff = (int64_t *)malloc(sizeof(int64_t) * (orb->nshell + 1));
+  offsets(aux, aoff);
+  offsets(orb, ooff);
+  int64_t nao = ooff[orb->nshell];
+#pragma omp parallel
+  {
+    md_work *w = (md_work *)malloc(sizeof(md_work));
+    real *cart = (real *)malloc(sizeof(real) * BLK_MAX);
+    real *pure = (real *)malloc(sizeof(real) * BLK_MAX);
+#pragma omp for schedule(dynamic, 1)
+    for (int sP = 0; sP < aux->nshell; ++sP) {
+      shell_view P = view(xyz, aux, sP);
+      int np = nfunc(aux, P.l);
+      real acc[2 * LMAX_AUX + 1 > 64 ? 2 * LMAX_AUX + 1 : 64];
+      for (int p = 0; p < np; ++p) acc[p] = 0;
+      for (int sa = 0; sa < orb->nshell; ++sa)
+        for (int sb = 0; sb < orb->nshell; ++sb) {
+          shell_view a = view(xyz, orb, sa), b = view(xyz, orb, sb);
+          int na = ncart(a.l), nb = ncart(b.l), nab = na * nb;
+          contracted_cart(&P, &a, &b, cart, w);
+          ket_to_pure(P.l, aux->pure, nab, cart, pure);
+          for (int p = 0; p < np; ++p)
+            for (int i = 0; i < na; ++i)
+              for (int j = 0; j < nb; ++j)
+                acc[p] += pure[p * nab + i * nb + j] * D[(ooff[sa] + i) * nao + ooff[sb] + j];
+        }
+      for (int p = 0; p < np; ++p) gamma[aoff[sP] + p] = (double)acc[p];
+    }
+    free(w);
+    free(cart);
+    free(pure);
+  }
+  free(aoff);
+  free(ooff);
+  return 0;
+}
+
 int oracle_coulomb_J(const double *xyz, const oracle_basis *aux, const oracle_basis *orb,
                      const double *d, double *J, int nthreads) {
   if (check_basis(aux, LMAX_AUX - 1) || check_basis(orb, LMAX_ORB - 1) || orb->pure) return -1;
@@ -475,7 +525,7 @@ int oracle_coulomb_J(const double *xyz, const oracle_basis *aux, const oracle_ba
     md_work *w = (md_work *)malloc(sizeof(md_work));
     real *cart = (real *)malloc(sizeof(real) * BLK_MAX);
     real *pure = (real *)malloc(sizeof(real) * BLK_MAX);
-    real Jblk[28 * 28];
+    real Jblk[NC_ORB * NC_ORB];
 #pragma omp for schedule(dynamic, 1)
     for (int64_t k = 0; k < npair; ++k) {
       /* k -> (sa >= sb) */
@@ -513,7 +563,7 @@ int oracle_coulomb_J_pairs(const double *xyz, const oracle_basis *aux, const ora
     md_work *w = (md_work *)malloc(sizeof(md_work));
     real *cart = (real *)malloc(sizeof(real) * BLK_MAX);
     real *pure = (real *)malloc(sizeof(real) * BLK_MAX);
-    real Jblk[28 * 28];
+    real Jblk[NC_ORB * NC_ORB];
 #pragma omp for schedule(dynamic, 1)
     for (int64_t k = 0; k < npair; ++k) {
       int sa = pairs[2 * k], sb = pairs[2 * k + 1];
@@ -610,7 +660,7 @@ static void contracted_deriv(const shell_view *P, const shell_view *a, const she
 int oracle_coulomb_J_grad(const double *xyz, int32_t natom, const oracle_basis *aux,
                           const oracle_basis *orb, const double *d, const double *G,
                           const uint8_t *atom_mask, double *grad, int nthreads) {
-  if (check_basis(aux, LMAX_AUX - 2) || check_basis(orb, LMAX_ORB - 2) || orb->pure ||
+  if (check_basis(aux, LMAX_AUX - 2) || check_basis(orb, GRAD_LMAX_ORB) || orb->pure ||
       natom < 0)
     return -1;
   set_threads(nthreads);

@@ -54,6 +54,12 @@ int oracle_coulomb_J(const double *xyz, const oracle_basis *aux,
                      const oracle_basis *orb, const double *d, double *J,
                      int nthreads);
 
+/* gamma[naux] = sum_{a,b} (P|ab) D_ab over all ordered orbital shell pairs;
+ * D is nao x nao row-major (not assumed symmetric). */
+int oracle_coulomb_gamma(const double *xyz, const oracle_basis *aux,
+                         const oracle_basis *orb, const double *D, double *gamma,
+                         int nthreads);
+
 /* J blocks for selected orbital shell pairs pairs[t] = (a, b):
  * out + out_off[t] receives the ncart(a) x ncart(b) block of J. */
 int oracle_coulomb_J_pairs(const double *xyz, const oracle_basis *aux,

@@ -262,6 +262,47 @@ def test_rotation_covariance_p():
     assert np.allclose(y, np.einsum("ci,aj,bk,ijk->cab", q, q, q, x), atol=1e-13)
 
 
+def test_gamma_bilinear_identity_with_J():
+    """sum_P gamma_P(D) d_P == sum_ab D_ab J_ab(d) for a non-symmetric D: gamma
+    digests over the orbital pairs, J over the aux shells, in separate loops."""
+    s = inputs.plain_dfj_system(seed=inputs.SEED_BASE + 71, natom=3)
+    rng = np.random.default_rng(71)
+    D = rng.normal(size=(s.orb.nbf, s.orb.nbf))
+    d = rng.normal(size=s.aux.nbf)
+    g = oracle.coulomb_gamma(s.xyz, s.aux, s.orb, D)
+    J = oracle.coulomb_J(s.xyz, s.aux, s.orb, d)
+    assert abs(g @ d - (D * J).sum()) <= 1e-12 * np.abs(g).max() * np.abs(d).sum()
+
+
+def test_gamma_equals_block_contraction():
+    """gamma against blocks of the batch entry point contracted with D by
+    numpy (an orbital g shell and a Cartesian index order that a transposed D
+    would break)."""
+    rng = np.random.default_rng(72)
+    xyz = rng.uniform(-1.5, 1.5, (2, 3))
+    from paper_2210_03192_amd.inputs import _Builder
+    ob, ab = _Builder(0), _Builder(1)
+    for a, ls in ((0, (0, 1, 4)), (1, (2, 3))):
+        for l in ls:
+            ob.add(l, a, rng.uniform(0.3, 3.0, 2), rng.uniform(0.2, 1.0, 2))
+    for a in (0, 1):
+        for l in (0, 2, 5):
+            ab.add(l, a, rng.uniform(0.2, 2.0, 1), [1.0])
+    orb, aux = ob.build(), ab.build()
+    D = rng.normal(size=(orb.nbf, orb.nbf))
+    g = oracle.coulomb_gamma(xyz, aux, orb, D)
+    trip = np.array([(P, a, b) for P in range(aux.nshell) for a in range(orb.nshell)
+                     for b in range(orb.nshell)], np.int32)
+    out, off = oracle.eval_batch(xyz, aux, orb, trip)
+    ao, po = orb.offsets(), aux.offsets()
+    ref = np.zeros(aux.nbf)
+    for (P, a, b), o in zip(trip, off):
+        nP, na, nb = aux.nfunc(P), orb.nfunc(a), orb.nfunc(b)
+        blk = out[o:o + nP * na * nb].reshape(nP, na, nb)
+        ref[po[P]:po[P + 1]] += np.einsum("pab,ab->p", blk, D[ao[a]:ao[a + 1], ao[b]:ao[b + 1]])
+    np.testing.assert_allclose(g, ref, rtol=1e-12, atol=1e-14 * np.abs(ref).max())
+
+
 def test_J_equals_block_contraction():
     s = inputs.plain_dfj_system()
     d = inputs.fitting_coefficients(s.aux.nbf, 7)
