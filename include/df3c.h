@@ -185,6 +185,7 @@ int df3c_coulomb_J_batched(const double *xyz, int32_t natom, const df3c_shells *
 #define DF3C_KERNEL_J 1      /* DF-J pair kernel (single molecule, per-class batched) */
 #define DF3C_KERNEL_GRAD 2   /* J-gradient kernel */
 #define DF3C_KERNEL_JQ 3     /* persistent work-queue DF-J kernel */
+#define DF3C_KERNEL_GAMMA 4  /* adjoint digestion (gamma) kernel */
 int df3c_timing_enable(int32_t on);
 
 /* Waits for the recorded launches, writes the first min(n, cap) of them to
@@ -192,6 +193,24 @@ int df3c_timing_enable(int32_t on);
  * n (>= 0) or a negative status (DF3C_E_ARG for cap < 0 or a null array with
  * cap > 0, DF3C_E_HIP). */
 int64_t df3c_timing_read(int32_t *kind, int32_t *cls, float *ms, int64_t cap);
+
+/* Bytes of workspace df3c_coulomb_gamma needs (the first call on a device
+ * initialises it, as df3c_init does; 0 on error). */
+size_t df3c_coulomb_gamma_workspace(const df3c_shells *aux, const df3c_shells *orb);
+
+/* Adjoint digestion: gamma_P = sum_{a,b} (P|ab) D_ab over all ordered orbital
+ * function pairs -- the right-hand side of the density-fitting equations
+ * (Section 3, the digestion of a 3-index batch) and dL/dd of L = sum G_ab J_ab
+ * with D = G.
+ *   D      DEVICE [nao][nao] row-major, any symmetry
+ *   gamma  DEVICE output [naux] in aux-shell order, then component order
+ *          (overwritten)
+ * Work items are (aux shell, chunk of shell pairs); every item writes its own
+ * partial sum and one fixed-order reduction per class adds them: bitwise
+ * reproducible.  DF3C_E_UNSUPPORTED for a Cartesian aux shell with l > 1. */
+int df3c_coulomb_gamma(const double *xyz, int32_t natom, const df3c_shells *aux,
+                       const df3c_shells *orb, const double *D, double *gamma, void *ws,
+                       size_t ws_bytes, uint32_t flags, void *stream);
 
 /* Readable name of a status code (static string). */
 const char *df3c_status_string(int status);

@@ -1,6 +1,7 @@
 // Per-class launch configuration and the launcher table shared by the
 // instantiation units and the runtime.
 #pragma once
+#include "gamma.hpp"
 #include "grad.hpp"
 #include "queue.hpp"
 
@@ -14,6 +15,9 @@ struct ClassInfo {
   hipError_t (*store)(const StoreArgs &, int, hipStream_t) = nullptr;
   hipError_t (*jfn)(const JArgs &, int, hipStream_t) = nullptr;
   hipError_t (*jq)(const JQArgs &, int, hipStream_t) = nullptr;
+  hipError_t (*gam)(const GamArgs &, int, hipStream_t) = nullptr;
+  int gam_reg = 0;    // gamma on the register engine (one lane per item)
+  int gam_ipw = 0;    // gamma items per workgroup and grid step
 };
 
 struct GradInfo {
@@ -55,6 +59,23 @@ hipError_t launch_Jq(const JQArgs &a, int grid, hipStream_t s) {
       reinterpret_cast<const void *>(kern), hipFuncAttributeMaxDynamicSharedMemorySize, lds);
   if (attr != hipSuccess) return attr;
   hipLaunchKernelGGL(kern, dim3(grid), dim3(C::BLKJ), lds, s, a);
+  return hipGetLastError();
+}
+
+template <int LP, int LA, int LB>
+hipError_t launch_gam(const GamArgs &a, int grid, hipStream_t s) {
+  using C = Cfg<LP, LA, LB>;
+  if constexpr (C::JREG) {
+    auto kr = k_gam_r<LP, LA, LB>;
+    hipLaunchKernelGGL(kr, dim3(grid), dim3(64), 0, s, a);
+  } else {
+    constexpr int lds = GamLayout<LP, LA, LB, C::TS, C::PCH>::BYTES_WG;
+    auto kern = k_gam_p<LP, LA, LB, C::TS, C::PCH>;
+    static const hipError_t attr = hipFuncSetAttribute(
+        reinterpret_cast<const void *>(kern), hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+    if (attr != hipSuccess) return attr;
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(C::BLK), lds, s, a);
+  }
   return hipGetLastError();
 }
 
@@ -108,6 +129,9 @@ ClassInfo class_info() {
   c.store = &launch_store<LP, LA, LB>;
   c.jfn = &launch_J<LP, LA, LB>;
   c.jq = &launch_Jq<LP, LA, LB>;
+  c.gam = &launch_gam<LP, LA, LB>;
+  c.gam_reg = C::JREG ? 1 : 0;
+  c.gam_ipw = C::JREG ? 64 : C::BLK / C::TS;
   return c;
 }
 

@@ -539,6 +539,125 @@ int df3c_coulomb_J(const double *xyz, int32_t natom, const df3c_shells *aux,
 }
 
 
+// ------------------------------------------------------------ adjoint gamma
+namespace {
+// gamma work items aimed at per class: 4 wavefronts of register items per CU
+int64_t gam_target(int ncu) { return int64_t(ncu) * 4 * 64; }
+
+// gamma[aux function] += sum over the chunks of the class's partials, in order
+__global__ void k_gam_reduce(const double *partial, int32_t np, int32_t nchunk, int32_t nout,
+                             const int32_t *psh, const int64_t *aux_off, double *gamma) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < np * nout; i += gridDim.x * blockDim.x) {
+    const int ip = i / nout, m = i - ip * nout;
+    double v = 0.0;
+    for (int c = 0; c < nchunk; ++c) v += partial[(int64_t(ip) * nchunk + c) * nout + m];
+    gamma[aux_off[psh[ip]] + m] += v;
+  }
+}
+}  // namespace
+
+size_t df3c_coulomb_gamma_workspace(const df3c_shells *aux, const df3c_shells *orb) {
+  if (!aux || !orb) return 0;
+  DevState *ds = nullptr;
+  if (init_device(&ds)) return 0;
+  const size_t items = size_t(gam_target(ds->ncu)) + size_t(aux->nshell);
+  return jplan_bytes(orb->nshell, aux->nshell) +
+         align256(sizeof(double) * items * size_t(2 * DF3C_LMAX_AUX + 1));
+}
+
+int df3c_coulomb_gamma(const double *xyz, int32_t natom, const df3c_shells *aux,
+                       const df3c_shells *orb, const double *D, double *gamma, void *ws,
+                       size_t ws_bytes, uint32_t flags, void *stream) {
+  (void)flags;
+  if (!xyz || natom <= 0 || !shells_ok(aux) || !shells_ok(orb) || !D || !gamma) return DF3C_E_ARG;
+  if (orb->pure != 0 || (aux->pure != 0 && aux->pure != 1)) return DF3C_E_UNSUPPORTED;
+  if (!ws || ws_bytes < df3c_coulomb_gamma_workspace(aux, orb)) return DF3C_E_WORKSPACE;
+  DevState *ds = nullptr;
+  int rc = init_device(&ds);
+  if (rc) return rc;
+  JPlan p;
+  rc = make_plan(aux, orb, p);
+  if (rc) return rc;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  char *w = static_cast<char *>(ws);
+  int *err = reinterpret_cast<int *>(w);
+  w += align256(sizeof(int) * 8);
+  int32_t *orb_sorted = reinterpret_cast<int32_t *>(w);
+  w += align256(sizeof(int32_t) * orb->nshell);
+  int32_t *aux_sorted = reinterpret_cast<int32_t *>(w);
+  w += align256(sizeof(int32_t) * aux->nshell);
+  int64_t *ao_off = reinterpret_cast<int64_t *>(w);
+  w += align256(sizeof(int64_t) * (orb->nshell + 1));
+  int64_t *aux_off = reinterpret_cast<int64_t *>(w);
+  w += align256(sizeof(int64_t) * (aux->nshell + 1));
+  double *partial = reinterpret_cast<double *>(w);
+  if (hipMemcpyAsync(orb_sorted, p.orb_sorted.data(), sizeof(int32_t) * orb->nshell,
+                     hipMemcpyHostToDevice, s) != hipSuccess ||
+      hipMemcpyAsync(aux_sorted, p.aux_sorted.data(), sizeof(int32_t) * aux->nshell,
+                     hipMemcpyHostToDevice, s) != hipSuccess ||
+      hipMemcpyAsync(ao_off, p.ao_off.data(), sizeof(int64_t) * (orb->nshell + 1),
+                     hipMemcpyHostToDevice, s) != hipSuccess ||
+      hipMemcpyAsync(aux_off, p.aux_off.data(), sizeof(int64_t) * (aux->nshell + 1),
+                     hipMemcpyHostToDevice, s) != hipSuccess)
+    return DF3C_E_HIP;
+  hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, s, err, 1, 0);
+  check_shells(aux, natom, err, s);
+  check_shells(orb, natom, err, s);
+  if (hipMemcpyAsync(g_pinned, err, sizeof(int), hipMemcpyDeviceToHost, s) != hipSuccess)
+    return DF3C_E_HIP;
+  if (hipStreamSynchronize(s) != hipSuccess) return DF3C_E_HIP;
+  if (g_pinned[0]) return DF3C_E_ARG;
+  hipLaunchKernelGGL(k_zero_f64, dim3(int(std::min<int64_t>((p.naux + 255) / 256, 4096))),
+                     dim3(256), 0, s, gamma, p.naux);
+  GamArgs a{};
+  a.boys = ds->boys;
+  a.xyz = xyz;
+  a.aux = dev_shells(aux);
+  a.orb = dev_shells(orb);
+  a.ao_off = ao_off;
+  a.D = D;
+  a.nao = p.nao;
+  a.pure = aux->pure;
+  a.partial = partial;
+  for (int lp = 0; lp <= DF3C_LMAX_AUX; ++lp) {
+    const int np = p.aux_start[lp + 1] - p.aux_start[lp];
+    if (!np) continue;
+    const int nout = aux->pure ? 2 * lp + 1 : (lp + 1) * (lp + 2) / 2;
+    a.psh = aux_sorted + p.aux_start[lp];
+    a.np = np;
+    for (int la = 0; la <= DF3C_LMAX_ORB; ++la)
+      for (int lb = 0; lb <= la; ++lb) {
+        const int na = p.orb_start[la + 1] - p.orb_start[la];
+        const int nb = p.orb_start[lb + 1] - p.orb_start[lb];
+        if (!na || !nb) continue;
+        a.ash = orb_sorted + p.orb_start[la];
+        a.bsh = orb_sorted + p.orb_start[lb];
+        a.na = na;
+        a.nb = nb;
+        a.same = (la == lb);
+        a.npair = (la == lb) ? int64_t(na) * (na + 1) / 2 : int64_t(na) * nb;
+        const ClassInfo &ci = g_cls[lp][la][lb];
+        // items = (aux shell, chunk of pairs); about gam_target of them per class
+        const int64_t target = ci.gam_reg ? gam_target(ds->ncu) : int64_t(ds->ncu) * 2 * ci.gam_ipw;
+        int64_t nchunk = std::min<int64_t>(a.npair, std::max<int64_t>(1, (target + np - 1) / np));
+        a.chunk = (a.npair + nchunk - 1) / nchunk;
+        nchunk = (a.npair + a.chunk - 1) / a.chunk;
+        a.nchunk = int32_t(nchunk);
+        const int64_t items = int64_t(np) * nchunk;
+        const int grid = int(std::max<int64_t>(
+            1, std::min<int64_t>((items + ci.gam_ipw - 1) / ci.gam_ipw,
+                                 int64_t(ds->ncu) * (ci.gam_reg ? 8 : 4))));
+        const int c = (lp * NLA + la) * NLA + lb;
+        if (timed(DF3C_KERNEL_GAMMA, c, s, [&] { return ci.gam(a, grid, s); }) != hipSuccess)
+          return DF3C_E_HIP;
+        const int nred = np * nout;
+        hipLaunchKernelGGL(k_gam_reduce, dim3((nred + 255) / 256), dim3(256), 0, s, partial, np,
+                           a.nchunk, nout, a.psh, aux_off, gamma);
+      }
+  }
+  return DF3C_OK;
+}
+
 // ----------------------------------------------------------------- J gradient
 namespace {
 constexpr int GRAD_GRID_PER_CU = 4;     // workgroups per CU of every gradient launch

@@ -82,6 +82,9 @@ def lib():
         L.df3c_coulomb_J_batched_workspace.restype = SZ
         L.df3c_coulomb_J_batched_workspace.argtypes = [P, P, I32]
         L.df3c_coulomb_J_batched.argtypes = [P, I32, P, P, I32, P, P, P, P, P, P, SZ, U32, P]
+        L.df3c_coulomb_gamma_workspace.restype = SZ
+        L.df3c_coulomb_gamma_workspace.argtypes = [P, P]
+        L.df3c_coulomb_gamma.argtypes = [P, I32, P, P, P, P, P, SZ, U32, P]
         L.df3c_timing_enable.argtypes = [I32]
         L.df3c_timing_read.restype = I64
         L.df3c_timing_read.argtypes = [P, P, P, I64]
@@ -207,10 +210,35 @@ def coulomb_J_grad(xyz: torch.Tensor, aux: DeviceBasis, orb: DeviceBasis, d: tor
     return grad
 
 
+def coulomb_gamma_workspace(aux: DeviceBasis, orb: DeviceBasis) -> int:
+    return int(lib().df3c_coulomb_gamma_workspace(ctypes.byref(aux.struct()),
+                                                  ctypes.byref(orb.struct())))
+
+
+def coulomb_gamma(xyz: torch.Tensor, aux: DeviceBasis, orb: DeviceBasis, D: torch.Tensor,
+                  gamma: Optional[torch.Tensor] = None, ws: Optional[torch.Tensor] = None,
+                  flags: int = 0, stream=None) -> torch.Tensor:
+    """gamma_P = sum_{a,b} (P|ab) D_ab (D: nao x nao, any symmetry)."""
+    naux = int(aux.offsets()[-1])
+    if gamma is None:
+        gamma = torch.empty(naux, dtype=torch.float64, device=xyz.device)
+    need = coulomb_gamma_workspace(aux, orb)
+    if need == 0:
+        raise DF3CError("df3c_coulomb_gamma_workspace failed")
+    if ws is None or ws.numel() < need:
+        ws = torch.empty(need, dtype=torch.uint8, device=xyz.device)
+    sa, so = aux.struct(), orb.struct()
+    _check(lib().df3c_coulomb_gamma(_ptr(xyz), int(xyz.shape[0]), ctypes.byref(sa),
+                                    ctypes.byref(so), _ptr(D), _ptr(gamma), _ptr(ws), ws.numel(),
+                                    flags, _stream(stream)), "df3c_coulomb_gamma")
+    return gamma
+
+
 class CoulombJ(torch.autograd.Function):
-    """J(xyz) = sum_P (ab|P) d_P as a differentiable function of the atomic
-    positions.  backward(G) runs the library's gradient kernel with G = dL/dJ;
-    the gradient with respect to d is not provided (returned as None)."""
+    """J(xyz, d) = sum_P (ab|P) d_P as a differentiable function of the atomic
+    positions and of the fitting coefficients.  backward(G), G = dL/dJ, runs the
+    library's gradient kernel for dL/dxyz and the adjoint digestion
+    gamma(G) = sum_ab (P|ab) G_ab for dL/dd."""
 
     @staticmethod
     def forward(ctx, xyz, d, aux, orb):
@@ -221,9 +249,14 @@ class CoulombJ(torch.autograd.Function):
     @staticmethod
     def backward(ctx, gJ):
         xyz, d = ctx.saved_tensors
-        g = coulomb_J_grad(xyz.detach().contiguous(), ctx.aux, ctx.orb, d.detach().contiguous(),
-                           gJ.detach().to(torch.float64).contiguous())
-        return g, None, None, None
+        G = gJ.detach().to(torch.float64).contiguous()
+        gx = gd = None
+        if ctx.needs_input_grad[0]:
+            gx = coulomb_J_grad(xyz.detach().contiguous(), ctx.aux, ctx.orb,
+                                d.detach().contiguous(), G)
+        if ctx.needs_input_grad[1]:
+            gd = coulomb_gamma(xyz.detach().contiguous(), ctx.aux, ctx.orb, G)
+        return gx, gd, None, None
 
 
 def J(xyz: torch.Tensor, d: torch.Tensor, aux: DeviceBasis, orb: DeviceBasis) -> torch.Tensor:
