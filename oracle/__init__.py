@@ -48,6 +48,7 @@ def _lib(precision="double"):
         lib.oracle_eval_batch.argtypes = [P, P, P, ctypes.c_int64, P, P, P, ctypes.c_int]
         lib.oracle_coulomb_J.argtypes = [P, P, P, P, P, ctypes.c_int]
         lib.oracle_coulomb_gamma.argtypes = [P, P, P, P, P, ctypes.c_int]
+        lib.oracle_coulomb_metric.argtypes = [P, P, P, ctypes.c_int]
         lib.oracle_coulomb_J_pairs.argtypes = [P, P, P, P, ctypes.c_int64, P, P, P,
                                                ctypes.c_int]
         lib.oracle_coulomb_J_grad.argtypes = [P, ctypes.c_int32, P, P, P, P, P, P,
@@ -146,6 +147,17 @@ def coulomb_gamma(xyz, aux, orb, D, nthreads=0, precision="double"):
     _check(_lib(precision).oracle_coulomb_gamma(_ptr(xyz), pa.ref, po.ref, _ptr(D), _ptr(g),
                                                 int(nthreads)), "coulomb_gamma")
     return g
+
+
+def coulomb_metric(xyz, aux, nthreads=0, precision="double"):
+    """V[P][Q] = (P|Q) over the aux basis."""
+    xyz = np.ascontiguousarray(xyz, np.float64)
+    naux = int(sum(nfunc(int(l), aux.pure) for l in aux.l))
+    V = np.zeros((naux, naux))
+    pa = _Pinned(aux)
+    _check(_lib(precision).oracle_coulomb_metric(_ptr(xyz), pa.ref, _ptr(V), int(nthreads)),
+           "coulomb_metric")
+    return V
 
 
 def coulomb_J_pairs(xyz, aux, orb, d, pairs, nthreads=0, precision="double"):

@@ -510,6 +510,58 @@ int oracle_coulomb_gamma(const double *xyz, const oracle_basis *aux, const oracl
   return 0;
 }
 
+/* V[P][Q] = (P|Q), the two-centre Coulomb integrals of the aux basis: the
+ * three-centre integral with Q as the bra shell and a unit s function
+ * (exponent 0, coefficient 1) as its partner, the bra then taken to the same
+ * (pure or Cartesian) functions as the ket. */
+int oracle_coulomb_metric(const double *xyz, const oracle_basis *aux, double *V, int nthreads) {
+  /* Q is the bra: aux l <= LMAX_AUX - 1 is within the orbital range */
+  if (check_basis(aux, LMAX_AUX - 1)) return -1;
+  set_threads(nthreads);
+  int64_t *aoff = (int64_t *)malloc(sizeof(int64_t) * (aux->nshell + 1));
+  offsets(aux, aoff);
+  int64_t naux = aoff[aux->nshell];
+  static const double zero_exp = 0.0, unit_coef = 1.0;
+#pragma omp parallel
+  {
+    md_work *w = (md_work *)malloc(sizeof(md_work));
+    real *cart = (real *)malloc(sizeof(real) * BLK_MAX);
+    real *pure = (real *)malloc(sizeof(real) * BLK_MAX);
+    real Tq[(2 * LMAX_AUX + 1) * 45];
+#pragma omp for schedule(dynamic, 1)
+    for (int sP = 0; sP < aux->nshell; ++sP) {
+      shell_view P = view(xyz, aux, sP);
+      int npP = nfunc(aux, P.l);
+      for (int sQ = 0; sQ < aux->nshell; ++sQ) {
+        shell_view Q = view(xyz, aux, sQ);
+        shell_view one = Q;
+        one.l = 0;
+        one.K = 1;
+        one.e = &zero_exp;
+        one.c = &unit_coef;
+        int nq = ncart(Q.l), npQ = nfunc(aux, Q.l);
+        contracted_cart(&P, &Q, &one, cart, w);       /* [c][q] */
+        ket_to_pure(P.l, aux->pure, nq, cart, pure);  /* [p][q] */
+        if (aux->pure) solid_transform_real(Q.l, Tq);
+        for (int p = 0; p < npP; ++p)
+          for (int q = 0; q < npQ; ++q) {
+            real v = 0;
+            if (aux->pure)
+              for (int c = 0; c < nq; ++c) v += Tq[q * nq + c] * pure[p * nq + c];
+            else
+              v = pure[p * nq + q];
+            V[(aoff[sP] + p) * naux + aoff[sQ] + q] = (double)v;
+          }
+      }
+    }
+    free(w);
+    free(cart);
+    free(pure);
+  }
+  free(aoff);
+  return 0;
+}
+
 int oracle_coulomb_J(const double *xyz, const oracle_basis *aux, const oracle_basis *orb,
                      const double *d, double *J, int nthreads) {
   if (check_basis(aux, LMAX_AUX - 1) || check_basis(orb, LMAX_ORB - 1) || orb->pure) return -1;

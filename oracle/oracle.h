@@ -60,6 +60,10 @@ int oracle_coulomb_gamma(const double *xyz, const oracle_basis *aux,
                          const oracle_basis *orb, const double *D, double *gamma,
                          int nthreads);
 
+/* V[naux][naux] = (P|Q), the two-centre Coulomb integrals of the aux basis
+ * (pure or Cartesian as the basis says). */
+int oracle_coulomb_metric(const double *xyz, const oracle_basis *aux, double *V, int nthreads);
+
 /* J blocks for selected orbital shell pairs pairs[t] = (a, b):
  * out + out_off[t] receives the ncart(a) x ncart(b) block of J. */
 int oracle_coulomb_J_pairs(const double *xyz, const oracle_basis *aux,

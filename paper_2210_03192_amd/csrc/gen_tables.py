@@ -370,12 +370,16 @@ def _write_if_changed(path, text):
 def geometries():
     """(LP, EA, EB) = (L_P, l_a, l_a + l_b) of every (l_a, l_b) pair up to the
     orbital limit, in both orders: the forward classes use l_a >= l_b, the
-    derivative classes also need the raised / lowered pairs."""
+    derivative classes also need the raised / lowered pairs; and (L_P, l_Q, l_Q)
+    of the two-centre metric up to the aux limit."""
     out = set()
     for LP in range(LMAX_AUX + 1):
         for la in range(LMAX_ORB + 1):
             for lb in range(LMAX_ORB + 1):
                 out.add((LP, la, la + lb))
+        # two-centre metric (P|Q): Q as a bra of l_Q with an s partner
+        for lq in range(LMAX_AUX + 1):
+            out.add((LP, lq, lq))
     return sorted(out)
 
 

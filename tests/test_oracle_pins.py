@@ -303,6 +303,61 @@ def test_gamma_equals_block_contraction():
     np.testing.assert_allclose(g, ref, rtol=1e-12, atol=1e-14 * np.abs(ref).max())
 
 
+def _ss_closed(za, zb, R2):
+    """Unnormalised (s_a|s_b) and F_1 of the two-centre integral."""
+    from scipy.special import erf
+    rho = za * zb / (za + zb)
+    T = rho * R2
+    F0 = 0.5 * math.sqrt(math.pi / T) * erf(math.sqrt(T))
+    F1 = (F0 - math.exp(-T)) / (2 * T)
+    pre = 2 * math.pi ** 2.5 / (za * zb * math.sqrt(za + zb))
+    return pre * F0, pre, rho, F1
+
+
+def test_metric_closed_forms():
+    """(s|s) from F_0 by erf, (p_x|s) = 1/(2 zeta_p) d/dP_x (s|s) with
+    dF_0/dT = -F_1 (Cartesian aux so the p components are x, y, z)."""
+    from paper_2210_03192_amd.inputs import _Builder
+    xyz = np.array([[0.0, 0.0, 0.0], [0.3, -0.7, 1.1]])
+    za, zb = 0.8, 1.7
+    b = _Builder(0)
+    b.add(1, 0, [za], [1.0])
+    b.add(0, 1, [zb], [1.0])
+    aux = b.build()
+    V = oracle.coulomb_metric(xyz, aux)
+    cp, cs = aux.coefs
+    R = xyz[0] - xyz[1]
+    ss, pre, rho, F1 = _ss_closed(za, zb, R @ R)
+    for x in range(3):
+        px_s = cp * cs / (2 * za) * pre * (-F1) * 2 * rho * R[x]
+        assert abs(V[x, 3] - px_s) <= 1e-13 * abs(V).max()
+        assert abs(V[3, x] - px_s) <= 1e-13 * abs(V).max()
+    b = _Builder(1)
+    b.add(0, 0, [za], [1.0])
+    b.add(0, 1, [zb], [1.0])
+    aux = b.build()
+    V = oracle.coulomb_metric(xyz, aux)
+    c0, c1 = aux.coefs
+    assert abs(V[0, 1] - c0 * c1 * ss) <= 1e-14 * abs(V[0, 1])
+    # one centre: F_0(0) = 1
+    assert abs(V[0, 0] - c0 * c0 * 2 * math.pi ** 2.5 / (za * za * math.sqrt(2 * za))) <= \
+        1e-14 * V[0, 0]
+
+
+def test_metric_symmetric_positive_definite():
+    s = inputs.plain_dfj_system(seed=inputs.SEED_BASE + 91, natom=2)
+    from paper_2210_03192_amd.inputs import _Builder
+    rng = np.random.default_rng(91)
+    b = _Builder(1)
+    for a in range(2):
+        for l in range(7):
+            b.add(l, a, rng.uniform(0.3, 3.0, 1), [1.0])
+    aux = b.build()
+    V = oracle.coulomb_metric(s.xyz, aux)
+    assert np.abs(V - V.T).max() <= 1e-13 * np.abs(V).max()
+    assert np.linalg.eigvalsh(0.5 * (V + V.T)).min() > 0
+
+
 def test_J_equals_block_contraction():
     s = inputs.plain_dfj_system()
     d = inputs.fitting_coefficients(s.aux.nbf, 7)
