@@ -194,6 +194,19 @@ int df3c_timing_enable(int32_t on);
  * cap > 0, DF3C_E_HIP). */
 int64_t df3c_timing_read(int32_t *kind, int32_t *cls, float *ms, int64_t cap);
 
+/* Bytes of workspace df3c_coulomb_metric needs. */
+size_t df3c_coulomb_metric_workspace(const df3c_shells *aux);
+
+/* Two-centre Coulomb metric V[P][Q] = (P|Q) of the auxiliary basis, the matrix
+ * of the density-fitting equations V d = gamma (Section 3's DF-J builder takes
+ * d as given).  Evaluated as the three-centre class (L_P, l_Q, 0) with a unit
+ * s function of exponent 0 as Q's partner.
+ *   V  DEVICE output [naux][naux] row-major, both triangles (symmetric)
+ * aux->l_host is read.  DF3C_E_UNSUPPORTED for l > DF3C_LMAX_AUX or a
+ * Cartesian aux shell with l > 1. */
+int df3c_coulomb_metric(const double *xyz, int32_t natom, const df3c_shells *aux, double *V,
+                        void *ws, size_t ws_bytes, uint32_t flags, void *stream);
+
 /* Bytes of workspace df3c_coulomb_gamma needs (the first call on a device
  * initialises it, as df3c_init does; 0 on error). */
 size_t df3c_coulomb_gamma_workspace(const df3c_shells *aux, const df3c_shells *orb);

@@ -3,6 +3,7 @@
 #pragma once
 #include "gamma.hpp"
 #include "grad.hpp"
+#include "metric.hpp"
 #include "queue.hpp"
 
 namespace df3c {
@@ -18,6 +19,11 @@ struct ClassInfo {
   hipError_t (*gam)(const GamArgs &, int, hipStream_t) = nullptr;
   int gam_reg = 0;    // gamma on the register engine (one lane per item)
   int gam_ipw = 0;    // gamma items per workgroup and grid step
+};
+
+struct MetricInfo {
+  int ppw = 0;        // shell pairs per workgroup and grid step
+  hipError_t (*fn)(const MetArgs &, int, hipStream_t) = nullptr;
 };
 
 struct GradInfo {
@@ -79,6 +85,27 @@ hipError_t launch_gam(const GamArgs &a, int grid, hipStream_t s) {
   return hipGetLastError();
 }
 
+template <int LP, int LQ>
+hipError_t launch_metric(const MetArgs &a, int grid, hipStream_t s) {
+  using C = Cfg<LP, LQ, 0>;
+  constexpr int lds = C::LDS;
+  auto kern = k_metric<LP, LQ, C::TS, C::PCH>;
+  static const hipError_t attr = hipFuncSetAttribute(
+      reinterpret_cast<const void *>(kern), hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+  if (attr != hipSuccess) return attr;
+  hipLaunchKernelGGL(kern, dim3(grid), dim3(C::BLK), lds, s, a);
+  return hipGetLastError();
+}
+
+// metric classes (LP, LQ <= LP) of one LP
+template <int LP, int LQ = 0>
+void fill_metric(MetricInfo (&t)[7]) {
+  using C = Cfg<LP, LQ, 0>;
+  t[LQ].ppw = C::BLK / C::TS;
+  t[LQ].fn = &launch_metric<LP, LQ>;
+  if constexpr (LQ < LP) fill_metric<LP, LQ + 1>(t);
+}
+
 template <int LP, int LA, int LB>
 hipError_t launch_grad(const GradArgs &a, int grid, int lds, hipStream_t s) {
   using C = GradCfg<LP, LA, LB>;
@@ -138,6 +165,13 @@ ClassInfo class_info() {
 constexpr int NLP = 7, NLA = 5;  // LP <= 6, la, lb <= 4
 constexpr int NLG = 4;           // gradient: la, lb <= 3
 // filled by inst_lp<LP>.hip
+void register_metric_lp0(MetricInfo (&t)[7]);
+void register_metric_lp1(MetricInfo (&t)[7]);
+void register_metric_lp2(MetricInfo (&t)[7]);
+void register_metric_lp3(MetricInfo (&t)[7]);
+void register_metric_lp4(MetricInfo (&t)[7]);
+void register_metric_lp5(MetricInfo (&t)[7]);
+void register_metric_lp6(MetricInfo (&t)[7]);
 void register_lp0(ClassInfo (&t)[NLA][NLA]);
 void register_lp1(ClassInfo (&t)[NLA][NLA]);
 void register_lp2(ClassInfo (&t)[NLA][NLA]);

@@ -28,6 +28,7 @@ DevState g_dev[MAX_DEV];
 std::mutex g_mu;
 ClassInfo g_cls[NLP][NLA][NLA];
 GradInfo g_grad[NLP][NLG][NLG];
+MetricInfo g_metric[NLP][NLP];
 bool g_cls_ready = false;
 int *g_pinned = nullptr;  // host readback buffer
 
@@ -60,6 +61,13 @@ void register_all() {
   register_lp4(t[4]);
   register_lp5(t[5]);
   register_lp6(t[6]);
+  register_metric_lp0(g_metric[0]);
+  register_metric_lp1(g_metric[1]);
+  register_metric_lp2(g_metric[2]);
+  register_metric_lp3(g_metric[3]);
+  register_metric_lp4(g_metric[4]);
+  register_metric_lp5(g_metric[5]);
+  register_metric_lp6(g_metric[6]);
   register_grad_lp0(g_grad[0]);
   register_grad_lp1(g_grad[1]);
   register_grad_lp2(g_grad[2]);
@@ -538,6 +546,76 @@ int df3c_coulomb_J(const double *xyz, int32_t natom, const df3c_shells *aux,
   return DF3C_OK;
 }
 
+
+// ---------------------------------------------------------- two-centre metric
+size_t df3c_coulomb_metric_workspace(const df3c_shells *aux) {
+  if (!aux) return 0;
+  return align256(sizeof(int) * 8) + align256(sizeof(int32_t) * aux->nshell) +
+         align256(sizeof(int64_t) * (aux->nshell + 1));
+}
+
+int df3c_coulomb_metric(const double *xyz, int32_t natom, const df3c_shells *aux, double *V,
+                        void *ws, size_t ws_bytes, uint32_t flags, void *stream) {
+  (void)flags;
+  if (!xyz || natom <= 0 || !shells_ok(aux) || !V || !aux->l_host) return DF3C_E_ARG;
+  if (aux->pure != 0 && aux->pure != 1) return DF3C_E_UNSUPPORTED;
+  if (!ws || ws_bytes < df3c_coulomb_metric_workspace(aux)) return DF3C_E_WORKSPACE;
+  DevState *ds = nullptr;
+  int rc = init_device(&ds);
+  if (rc) return rc;
+  // shells grouped by l, function offsets
+  std::vector<int32_t> cnt(DF3C_LMAX_AUX + 2, 0), sorted(aux->nshell);
+  std::vector<int64_t> off(aux->nshell + 1, 0);
+  for (int s = 0; s < aux->nshell; ++s) {
+    const int l = aux->l_host[s];
+    if (l < 0 || l > DF3C_LMAX_AUX || (!aux->pure && l > 1)) return DF3C_E_UNSUPPORTED;
+    cnt[l + 1]++;
+    off[s + 1] = off[s] + (aux->pure ? 2 * l + 1 : (l + 1) * (l + 2) / 2);
+  }
+  for (int l = 0; l <= DF3C_LMAX_AUX; ++l) cnt[l + 1] += cnt[l];
+  std::vector<int32_t> fill(cnt.begin(), cnt.end() - 1);
+  for (int s = 0; s < aux->nshell; ++s) sorted[fill[aux->l_host[s]]++] = s;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  char *w = static_cast<char *>(ws);
+  int *err = reinterpret_cast<int *>(w);
+  w += align256(sizeof(int) * 8);
+  int32_t *sorted_d = reinterpret_cast<int32_t *>(w);
+  w += align256(sizeof(int32_t) * aux->nshell);
+  int64_t *off_d = reinterpret_cast<int64_t *>(w);
+  if (hipMemcpyAsync(sorted_d, sorted.data(), sizeof(int32_t) * aux->nshell,
+                     hipMemcpyHostToDevice, s) != hipSuccess ||
+      hipMemcpyAsync(off_d, off.data(), sizeof(int64_t) * (aux->nshell + 1), hipMemcpyHostToDevice,
+                     s) != hipSuccess)
+    return DF3C_E_HIP;
+  hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, s, err, 1, 0);
+  check_shells(aux, natom, err, s);
+  if (hipMemcpyAsync(g_pinned, err, sizeof(int), hipMemcpyDeviceToHost, s) != hipSuccess)
+    return DF3C_E_HIP;
+  if (hipStreamSynchronize(s) != hipSuccess) return DF3C_E_HIP;
+  if (g_pinned[0]) return DF3C_E_ARG;
+  MetArgs a{};
+  a.boys = ds->boys;
+  a.xyz = xyz;
+  a.aux = dev_shells(aux);
+  a.aux_off = off_d;
+  a.naux = off[aux->nshell];
+  a.pure = aux->pure;
+  a.V = V;
+  for (int lp = 0; lp <= DF3C_LMAX_AUX; ++lp)
+    for (int lq = 0; lq <= lp; ++lq) {
+      const int np = cnt[lp + 1] - cnt[lp], nq = cnt[lq + 1] - cnt[lq];
+      if (!np || !nq) continue;
+      a.psh = sorted_d + cnt[lp];
+      a.qsh = sorted_d + cnt[lq];
+      a.np = np;
+      a.nq = nq;
+      a.same = (lp == lq);
+      a.npair = (lp == lq) ? int64_t(np) * (np + 1) / 2 : int64_t(np) * nq;
+      const MetricInfo &mi = g_metric[lp][lq];
+      if (mi.fn(a, grid_for(a.npair, mi.ppw, ds->ncu), s) != hipSuccess) return DF3C_E_HIP;
+    }
+  return DF3C_OK;
+}
 
 // ------------------------------------------------------------ adjoint gamma
 namespace {

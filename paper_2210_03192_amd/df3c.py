@@ -82,6 +82,9 @@ def lib():
         L.df3c_coulomb_J_batched_workspace.restype = SZ
         L.df3c_coulomb_J_batched_workspace.argtypes = [P, P, I32]
         L.df3c_coulomb_J_batched.argtypes = [P, I32, P, P, I32, P, P, P, P, P, P, SZ, U32, P]
+        L.df3c_coulomb_metric_workspace.restype = SZ
+        L.df3c_coulomb_metric_workspace.argtypes = [P]
+        L.df3c_coulomb_metric.argtypes = [P, I32, P, P, P, SZ, U32, P]
         L.df3c_coulomb_gamma_workspace.restype = SZ
         L.df3c_coulomb_gamma_workspace.argtypes = [P, P]
         L.df3c_coulomb_gamma.argtypes = [P, I32, P, P, P, P, P, SZ, U32, P]
@@ -208,6 +211,22 @@ def coulomb_J_grad(xyz: torch.Tensor, aux: DeviceBasis, orb: DeviceBasis, d: tor
                                      _ptr(G), _ptr(grad), _ptr(ws), ws.numel(), flags,
                                      _stream(stream)), "df3c_coulomb_J_grad")
     return grad
+
+
+def coulomb_metric(xyz: torch.Tensor, aux: DeviceBasis, V: Optional[torch.Tensor] = None,
+                   ws: Optional[torch.Tensor] = None, flags: int = 0, stream=None) -> torch.Tensor:
+    """V[P][Q] = (P|Q), the two-centre metric of the aux basis."""
+    naux = int(aux.offsets()[-1])
+    if V is None:
+        V = torch.empty((naux, naux), dtype=torch.float64, device=xyz.device)
+    sa = aux.struct()
+    need = int(lib().df3c_coulomb_metric_workspace(ctypes.byref(sa)))
+    if ws is None or ws.numel() < need:
+        ws = torch.empty(max(need, 1), dtype=torch.uint8, device=xyz.device)
+    _check(lib().df3c_coulomb_metric(_ptr(xyz), int(xyz.shape[0]), ctypes.byref(sa), _ptr(V),
+                                     _ptr(ws), ws.numel(), flags, _stream(stream)),
+           "df3c_coulomb_metric")
+    return V
 
 
 def coulomb_gamma_workspace(aux: DeviceBasis, orb: DeviceBasis) -> int:
