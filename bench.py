@@ -179,6 +179,19 @@ def dfj_legs(args, df3c, inputs, torch, dev):
                                                                         ws=wsj), 3)
         mf = system_model_flop(s.aux, s.orb)
         out[f"dfj_model_frac_{name}"] = mf / (out[f"dfj_ms_{name}"] * 1e-3) / PEAK_FP64
+        if name == "water_120atoms":
+            # the fitting legs: gamma = (P|ab) D and the metric (P|Q)
+            D = torch.as_tensor(inputs.symmetric_density(s.orb.nbf, 2), device=dev)
+            gam = torch.empty(s.aux.nbf, dtype=torch.float64, device=dev)
+            wsg = torch.empty(df3c.coulomb_gamma_workspace(aux, orb), dtype=torch.uint8,
+                              device=dev)
+            out["gamma_ms_water_120atoms"] = _time_ms(
+                torch, lambda: df3c.coulomb_gamma(xyz, aux, orb, D, gamma=gam, ws=wsg), 2)
+            out["gamma_model_frac_water_120atoms"] = mf / (
+                out["gamma_ms_water_120atoms"] * 1e-3) / PEAK_FP64
+            Vm = torch.empty((s.aux.nbf, s.aux.nbf), dtype=torch.float64, device=dev)
+            out["metric_ms_water_120atoms"] = _time_ms(
+                torch, lambda: df3c.coulomb_metric(xyz, aux, V=Vm), 3)
     # J gradient, 60 atoms
     s = inputs.grad_60_system()
     d = torch.as_tensor(inputs.fitting_coefficients(s.aux.nbf, 5), device=dev)
