@@ -77,6 +77,12 @@ typedef struct {
   const double *coefs;     /* DEVICE contraction coefficients (normalised) */
   int32_t pure;            /* aux: 1 solid-harmonic (0 allowed only for l <= 1);
                               orbital: must be 0 (Cartesian) */
+  const int32_t *nprim_host; /* HOST [nshell] copy of nprim, or NULL.  Optional: when
+                              given, the orbital shells of each l are processed in
+                              order of decreasing contraction degree, so that the
+                              shell pairs that share a wavefront have equal primitive
+                              loops; the results do not depend on it beyond rounding
+                              (the orientation of pairs of equally tight shells) */
 } df3c_shells;
 
 /* Load-time set-up for the current device (Boys table upload).  Called

@@ -423,6 +423,16 @@ struct JPlan {
   int64_t nao = 0, naux = 0;
 };
 
+// Orbital shells of one l in order of decreasing contraction degree (stable):
+// the kernels give one lane or one team to a shell pair and loop over its
+// primitive pairs, so pairs that share a wavefront should have equal Ka Kb.
+void sort_by_contraction(const df3c_shells *orb, int32_t *first, int32_t *last) {
+  if (!orb->nprim_host) return;
+  std::stable_sort(first, last, [orb](int32_t x, int32_t y) {
+    return orb->nprim_host[x] > orb->nprim_host[y];
+  });
+}
+
 int make_plan(const df3c_shells *aux, const df3c_shells *orb, JPlan &p) {
   if (!aux->l_host || !orb->l_host) return DF3C_E_ARG;
   std::vector<int32_t> cnt_o(DF3C_LMAX_ORB + 1, 0), cnt_a(DF3C_LMAX_AUX + 1, 0);
@@ -451,6 +461,8 @@ int make_plan(const df3c_shells *aux, const df3c_shells *orb, JPlan &p) {
       fa(p.aux_start, p.aux_start + DF3C_LMAX_AUX + 1);
   for (int s = 0; s < orb->nshell; ++s) p.orb_sorted[fo[orb->l_host[s]]++] = s;
   for (int s = 0; s < aux->nshell; ++s) p.aux_sorted[fa[aux->l_host[s]]++] = s;
+  for (int l = 0; l <= DF3C_LMAX_ORB; ++l)
+    sort_by_contraction(orb, p.orb_sorted.data() + p.orb_start[l], p.orb_sorted.data() + p.orb_start[l + 1]);
   return DF3C_OK;
 }
 
@@ -905,6 +917,7 @@ int make_bplan(const df3c_shells *aux, const df3c_shells *orb, int nmol, const i
       ost[m][l] = int32_t(p.orb_sorted.size());
       for (int s = mo[m]; s < mo[m + 1]; ++s)
         if (orb->l_host[s] == l) p.orb_sorted.push_back(s);
+      sort_by_contraction(orb, p.orb_sorted.data() + ost[m][l], p.orb_sorted.data() + p.orb_sorted.size());
     }
     ost[m][DF3C_LMAX_ORB + 1] = int32_t(p.orb_sorted.size());
     for (int l = 0; l <= DF3C_LMAX_AUX; ++l) {

@@ -55,6 +55,7 @@ class _Shells(ctypes.Structure):
         ("exps", ctypes.c_void_p),
         ("coefs", ctypes.c_void_p),
         ("pure", ctypes.c_int32),
+        ("nprim_host", ctypes.c_void_p),
     ]
 
 
@@ -120,6 +121,7 @@ class DeviceBasis:
     exps: torch.Tensor
     coefs: torch.Tensor
     pure: int
+    nprim_host: Optional[np.ndarray] = None   # host copy of nprim (orders pairs)
 
     @classmethod
     def from_basis(cls, b, device="cuda"):
@@ -127,7 +129,8 @@ class DeviceBasis:
         t = lambda a, dt: torch.as_tensor(np.ascontiguousarray(a), dtype=dt, device=device)
         return cls(l_host, t(b.l, torch.int32), t(b.nprim, torch.int32),
                    t(b.prim_off, torch.int64), t(b.atom, torch.int32),
-                   t(b.exps, torch.float64), t(b.coefs, torch.float64), int(b.pure))
+                   t(b.exps, torch.float64), t(b.coefs, torch.float64), int(b.pure),
+                   np.ascontiguousarray(b.nprim, np.int32))
 
     @property
     def nshell(self):
@@ -136,7 +139,8 @@ class DeviceBasis:
     def struct(self):
         return _Shells(self.nshell, self.l_host.ctypes.data, self.l.data_ptr(),
                        self.nprim.data_ptr(), self.prim_off.data_ptr(), self.atom.data_ptr(),
-                       self.exps.data_ptr(), self.coefs.data_ptr(), self.pure)
+                       self.exps.data_ptr(), self.coefs.data_ptr(), self.pure,
+                       None if self.nprim_host is None else self.nprim_host.ctypes.data)
 
     def offsets(self):
         n = np.array([2 * l + 1 if self.pure else (l + 1) * (l + 2) // 2 for l in self.l_host],
