@@ -49,6 +49,8 @@ struct JArgs {
   int64_t npair;
   int64_t ao_base;          // subtracted from ao_off (first AO of the molecule)
   int32_t pure;
+  int32_t nsub;             // register engine: lanes per shell pair (power of two,
+                            // 1..16), which split the aux shells between them
 };
 
 // LDS layout of one team (in doubles).  Regions are reused once dead:
@@ -648,7 +650,7 @@ __global__ void __launch_bounds__(TS > 64 ? TS : 64)
 // one HRR of X per pair adds the J block (both triangles).
 // ---------------------------------------------------------------------------
 template <int LP, int LA, int LB>
-__device__ __forceinline__ void jr_pair(const JArgs &a, bool valid, int sa, int sb) {
+__device__ __forceinline__ void jr_pair(const JArgs &a, bool valid, int sa, int sb, int sub) {
   using R = JReg<LP, LA, LB>;
   using SH = GenSolid<LP>;
   constexpr int L = R::L, NE = R::NE, NCP = ncart(LP), NA = ncart(LA), NB = ncart(LB);
@@ -688,7 +690,9 @@ __device__ __forceinline__ void jr_pair(const JArgs &a, bool valid, int sa, int 
 #pragma unroll
   for (int e = 0; e < NE; ++e) X[e] = 0.0;
 
-  for (int ip = 0; ip < a.np; ++ip) {
+  // the nsub lanes of the pair take every nsub-th aux shell
+  const int nsub = a.nsub;
+  for (int ip = sub; ip < a.np; ip += nsub) {
     const int sP = a.psh[ip];
     const int Kc = a.aux.nprim[sP];
     const double *ec = a.aux.exps + a.aux.prim_off[sP], *cc = a.aux.coefs + a.aux.prim_off[sP];
@@ -818,6 +822,13 @@ __device__ __forceinline__ void jr_pair(const JArgs &a, bool valid, int sa, int 
         }
       }
   }
+  // sum the partial X of the pair's lanes p + k 64/nsub by a butterfly: every
+  // lane ends with the same bits, (x0 + x1) + (x2 + x3) for nsub = 4
+  for (int m = 64 / nsub; m < 64; m <<= 1) {
+#pragma unroll
+    for (int e = 0; e < NE; ++e) X[e] += __shfl_xor(X[e], m);
+  }
+  if (sub != 0) return;
   // one HRR of X, both J triangles
   double pwx[LB + 1], pwy[LB + 1], pwz[LB + 1];
   pwx[0] = pwy[0] = pwz[0] = 1.0;
@@ -1099,9 +1110,9 @@ struct JLayout {
 
 template <int LP, int LA, int LB, int TS, int PCH>
 __device__ __forceinline__ void j_pair(const JArgs &a, double *S, int tid, const int *slot,
-                                       bool valid, int sa, int sb, int np_loop) {
+                                       bool valid, int sa, int sb, int np_loop, int sub) {
   if constexpr (TS == 1 && JReg<LP, LA, LB>::OK) {
-    jr_pair<LP, LA, LB>(a, valid, sa, sb);
+    jr_pair<LP, LA, LB>(a, valid, sa, sb, sub);
     return;
   } else if constexpr (use_jengine<LP, LA, LB, TS, PCH>()) {
     jeng_pair<LP, LA, LB, TS, PCH>(a, S, tid, valid, sa, sb, np_loop);
@@ -1216,12 +1227,16 @@ __global__ void __launch_bounds__(TS > 64 ? TS : 64)
   constexpr bool REG = JLayout<LP, LA, LB, TS, PCH>::REG;
   constexpr int NQ = REG ? 1 : (G::NPI + TS - 1) / TS;
   extern __shared__ double smem[];
-  const int team = threadIdx.x / TS, tid = threadIdx.x % TS;
-  double *S = smem + team * JL::TOTAL;
+  // register engine: lane = sub (64 / nsub) + team, nsub lanes per pair
+  const int tpb = REG ? TPB / a.nsub : TPB;
+  const int team = REG ? int(threadIdx.x) % tpb : int(threadIdx.x) / TS;
+  const int sub = REG ? int(threadIdx.x) / tpb : 0;
+  const int tid = threadIdx.x % TS;
+  double *S = smem + (REG ? 0 : team * JL::TOTAL);
   int slot[NQ];
   if constexpr (!REG) make_slots<LP, LA, LB, TS>(slot, tid);
 
-  for (int64_t base = int64_t(blockIdx.x) * TPB; base < a.npair; base += int64_t(gridDim.x) * TPB) {
+  for (int64_t base = int64_t(blockIdx.x) * tpb; base < a.npair; base += int64_t(gridDim.x) * tpb) {
     const int64_t q = base + team;
     const bool valid = q < a.npair;
     int sa = 0, sb = 0;
@@ -1239,7 +1254,7 @@ __global__ void __launch_bounds__(TS > 64 ? TS : 64)
         sb = a.bsh[j];
       }
     }
-    j_pair<LP, LA, LB, TS, PCH>(a, S, tid, slot, valid, sa, sb, a.np);
+    j_pair<LP, LA, LB, TS, PCH>(a, S, tid, slot, valid, sa, sb, a.np, sub);
   }
 }
 

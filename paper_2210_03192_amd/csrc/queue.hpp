@@ -58,13 +58,17 @@ __global__ void __launch_bounds__(TS > 64 ? TS : 64)
   constexpr int NQ = REG ? 1 : (G::NPI + TS - 1) / TS;
   extern __shared__ double smem[];
   __shared__ unsigned long long s_base;
-  const int team = threadIdx.x / TS, tid = threadIdx.x % TS;
-  double *S = smem + team * JL::TOTAL;
+  // register engine: lane = sub (64 / nsub) + team, nsub lanes per item
+  const int tpb = REG ? TPB / q.a.nsub : TPB;
+  const int team = REG ? int(threadIdx.x) % tpb : int(threadIdx.x) / TS;
+  const int sub = REG ? int(threadIdx.x) / tpb : 0;
+  const int tid = threadIdx.x % TS;
+  double *S = smem + (REG ? 0 : team * JL::TOTAL);
   int slot[NQ];
   if constexpr (!REG) make_slots<LP, LA, LB, TS>(slot, tid);
 
   for (;;) {
-    if (threadIdx.x == 0) s_base = atomicAdd(q.counter, (unsigned long long)(TPB * q.chunk));
+    if (threadIdx.x == 0) s_base = atomicAdd(q.counter, (unsigned long long)(tpb * q.chunk));
     __syncthreads();
     const int64_t base = int64_t(s_base);
     __syncthreads();
@@ -98,7 +102,7 @@ __global__ void __launch_bounds__(TS > 64 ? TS : 64)
       a.np = np;
       // the aux loop runs to the workgroup's largest np; shorter teams idle
       const int np_loop = TS >= 64 ? np : wave_max(np);
-      j_pair<LP, LA, LB, TS, PCH>(a, S, tid, slot, valid, sa, sb, np_loop);
+      j_pair<LP, LA, LB, TS, PCH>(a, S, tid, slot, valid, sa, sb, np_loop, sub);
     }
   }
 }

@@ -12,6 +12,7 @@ struct ClassInfo {
   int ts = 0;         // lanes per team
   int tpw = 0;        // teams per workgroup (block kernels)
   int tpwj = 0;       // teams per workgroup of the J kernels
+  int jreg = 0;       // J on the register engine (one lane, or nsub lanes, per pair)
   int lds = 0;        // dynamic LDS bytes per workgroup
   hipError_t (*store)(const StoreArgs &, int, hipStream_t) = nullptr;
   hipError_t (*jfn)(const JArgs &, int, hipStream_t) = nullptr;
@@ -152,6 +153,7 @@ ClassInfo class_info() {
   c.ts = C::TS;
   c.tpw = C::BLK / C::TS;
   c.tpwj = C::BLKJ / C::TSJ;
+  c.jreg = C::JREG ? 1 : 0;
   c.lds = C::LDS;
   c.store = &launch_store<LP, LA, LB>;
   c.jfn = &launch_J<LP, LA, LB>;

@@ -279,6 +279,19 @@ __global__ void k_reduce_partial(const double *partial, int nslot, int n, double
   }
 }
 
+// Lanes per shell pair of the register J engine.  It gives one lane to a pair
+// and runs every aux shell of the class in that lane, so a class of few pairs
+// leaves the SIMDs close to idle; the aux shells are then split between nsub
+// lanes of a pair (a power of two <= 16, no more than the aux shells) until
+// about four waves per SIMD are resident.
+int reg_split(const ClassInfo &ci, int64_t items, int np, int ncu) {
+  if (!ci.jreg) return 1;
+  const int64_t target = int64_t(ncu) * 4 * 4 * 64;
+  int n = 1;
+  while (n < 16 && 2 * n <= np && items * n < target) n *= 2;
+  return n;
+}
+
 int grid_for(int64_t items, int tpw, int ncu) {
   const int64_t need = (items + tpw - 1) / tpw;
   const int64_t cap = int64_t(ncu) * 64;
@@ -550,8 +563,10 @@ int df3c_coulomb_J(const double *xyz, int32_t natom, const df3c_shells *aux,
         a.npair = (la == lb) ? int64_t(na) * (na + 1) / 2 : int64_t(na) * nb;
         const ClassInfo &ci = g_cls[lp][la][lb];
         const int c = (lp * NLA + la) * NLA + lb;
-        if (timed(DF3C_KERNEL_J, c, s,
-                  [&] { return ci.jfn(a, grid_for(a.npair, ci.tpwj, ds->ncu), s); }) != hipSuccess)
+        a.nsub = reg_split(ci, a.npair, a.np, ds->ncu);
+        if (timed(DF3C_KERNEL_J, c, s, [&] {
+              return ci.jfn(a, grid_for(a.npair, ci.tpwj / a.nsub, ds->ncu), s);
+            }) != hipSuccess)
           return DF3C_E_HIP;
       }
   }
@@ -1090,6 +1105,14 @@ int df3c_coulomb_J_batched(const double *xyz, int32_t natom, const df3c_shells *
   base.aux_off = aux_off;
   base.d = d;
   base.pure = aux->pure;
+  // lanes per pair of the register engine: one value per class from the
+  // batch's totals, so that both schedules sum in the same order
+  auto class_nsub = [&](int c) {
+    const int lp = c / (NLA * NLA), la = (c / NLA) % NLA, lb = c % NLA;
+    int np_max = 0;
+    for (int g = p.cls_seg0[c]; g < p.cls_seg0[c + 1]; ++g) np_max = std::max(np_max, p.seg[g].np);
+    return reg_split(g_cls[lp][la][lb], p.cls_items[c], np_max, ds->ncu);
+  };
 
   auto enqueue = [&]() -> int {
     hipLaunchKernelGGL(k_zero_f64, dim3(int(std::min<int64_t>((p.jtotal + 255) / 256, 4096))),
@@ -1110,7 +1133,9 @@ int df3c_coulomb_J_batched(const double *xyz, int32_t natom, const df3c_shells *
         q.total = p.cls_items[c];
         q.counter = ctr + c;
         const ClassInfo &ci = g_cls[lp][la][lb];
-        const int64_t need = (q.total + int64_t(ci.tpwj) * q.chunk - 1) / (int64_t(ci.tpwj) * q.chunk);
+        q.a.nsub = class_nsub(c);
+        const int64_t tpw = ci.tpwj / q.a.nsub;
+        const int64_t need = (q.total + tpw * q.chunk - 1) / (tpw * q.chunk);
         const int grid = int(std::max<int64_t>(
             1, std::min<int64_t>(need, int64_t(ds->ncu) * tt[c].grid_per_cu)));
         if (timed(DF3C_KERNEL_JQ, c, s, [&] { return ci.jq(q, grid, s); }) != hipSuccess)
@@ -1136,8 +1161,9 @@ int df3c_coulomb_J_batched(const double *xyz, int32_t natom, const df3c_shells *
             a.ao_base = sg.ao_base;
             a.npair = sg.npair;
             const ClassInfo &ci = g_cls[lp][la][lb];
+            a.nsub = class_nsub(c);
             if (timed(DF3C_KERNEL_J, c, s, [&] {
-                  return ci.jfn(a, grid_for(a.npair, ci.tpwj, ds->ncu), s);
+                  return ci.jfn(a, grid_for(a.npair, ci.tpwj / a.nsub, ds->ncu), s);
                 }) != hipSuccess)
               return DF3C_E_HIP;
           }
