@@ -200,23 +200,22 @@ struct PiTiles {
 };
 
 // ---------------------------------------------------------------------------
-// Setup of one chunk of primitive triplets p0 .. p0+npc-1 (lanes over
-// primitives): the scalars of the record, Boys, level 0 of VRR1 at every m and
-// the CVRR2 monomials sW.  Record of primitive pp at prims + pp * REC:
+// Setup of primitive triplet p of a shell triplet (p = (ia Kb + ib) Kc + ic)
+// into its record R: the scalars, Boys, level 0 of VRR1 at every m and the
+// CVRR2 monomials sW.  setup_chunk runs it for p0 .. p0+npc-1 (lanes over
+// primitives), record of primitive pp at prims + pp * REC:
 //   [PS_N scalars][T: NT][W: NW][sW: NSW]...
 // WM selects the contraction weights: 0 -> c_a c_b c_c, 1 -> 2 zeta_a c_a c_b c_c,
 // 2 -> 2 zeta_b c_a c_b c_c (the raised bra of the derivative integrals).
 // ---------------------------------------------------------------------------
-template <class G, int TS, int REC, int WM>
-__device__ __forceinline__ void setup_chunk(const double *btab, double *prims, int lt, int p0,
-                                            int npc, int Kb, int Kc, const double *A,
-                                            const double *B, const double *C, double AB2,
-                                            const double *ea, const double *ca,
-                                            const double *eb, const double *cb,
-                                            const double *ec, const double *cc) {
+template <class G, int WM>
+__device__ __forceinline__ void setup_prim(const double *btab, double *R, int p, int Kb, int Kc,
+                                           const double *A, const double *B, const double *C,
+                                           double AB2, const double *ea, const double *ca,
+                                           const double *eb, const double *cb,
+                                           const double *ec, const double *cc) {
   constexpr int LP = G::LP, L = G::L;
-  for (int pp = lt; pp < npc; pp += TS) {
-    const int p = p0 + pp;
+  {
     const int ic = p % Kc, rest = p / Kc;
     const int ib = rest % Kb, ia = rest / Kb;
     const double za = ea[ia], zb = eb[ib], zc = ec[ic];
@@ -234,7 +233,6 @@ __device__ __forceinline__ void setup_chunk(const double *btab, double *prims, i
     if constexpr (WM == 2) pre *= 2.0 * zb;
     double Fm[L + 1];
     boys<LP, L + 1>(btab, T, Fm);
-    double *R = prims + pp * REC;
     R[PS_PAX] = Px - A[0];
     R[PS_PAY] = Py - A[1];
     R[PS_PAZ] = Pz - A[2];
@@ -270,6 +268,18 @@ __device__ __forceinline__ void setup_chunk(const double *btab, double *prims, i
       });
     });
   }
+}
+
+template <class G, int TS, int REC, int WM>
+__device__ __forceinline__ void setup_chunk(const double *btab, double *prims, int lt, int p0,
+                                            int npc, int Kb, int Kc, const double *A,
+                                            const double *B, const double *C, double AB2,
+                                            const double *ea, const double *ca,
+                                            const double *eb, const double *cb,
+                                            const double *ec, const double *cc) {
+  for (int pp = lt; pp < npc; pp += TS)
+    setup_prim<G, WM>(btab, prims + pp * REC, p0 + pp, Kb, Kc, A, B, C, AB2, ea, ca, eb, cb, ec,
+                      cc);
 }
 
 // ---------------------------------------------------------------------------
@@ -894,7 +904,7 @@ struct MTiles {
 
 // LDS layout of one J-engine team (doubles):
 //   PRIM [0, PCH*REC)    records [PS_N][T][W][sW][H] of the current chunk
-//   DP   [.., +NCP)      d' of the current aux shell
+//   DP   [.., +PCH*NCP)  d' of the aux shell of each primitive of the chunk
 //   MJ   [0, NM)         M after the aux loop (over the dead PRIM / DP)
 //   XD   [.., +NE)       X_e for the HRR
 template <int LP, int LA, int LB, int PCH>
@@ -904,7 +914,7 @@ struct JELayout {
   static constexpr int REC = HU + G::NSW;
   static constexpr int DP = PCH * REC;
   static constexpr int MJ = 0;
-  static constexpr int XD = imax(DP + G::NCP, MTiles<G>::NM);
+  static constexpr int XD = imax(DP + PCH * G::NCP, MTiles<G>::NM);
   static constexpr int TOTAL = XD + G::NE;
 };
 
@@ -963,78 +973,106 @@ __device__ __forceinline__ void jeng_pair(const JArgs &a, double *S, int tid, bo
   dbl4 macc[NTW];
 #pragma unroll
   for (int j = 0; j < NTW; ++j) macc[j] = dbl4{0.0, 0.0, 0.0, 0.0};
-
-  for (int ip = 0; ip < np_loop; ++ip) {
-    const bool active = valid && ip < a.np;
-    const int sP = active ? a.psh[ip] : 0;
-    const int Kc = active ? a.aux.nprim[sP] : 0;
-    const int64_t oc = active ? a.aux.prim_off[sP] : 0;
-    double Cr[3] = {0, 0, 0};
-    if (active) {
-      const int ic = a.aux.atom[sP];
-      Cr[0] = a.xyz[3 * ic];
-      Cr[1] = a.xyz[3 * ic + 1];
-      Cr[2] = a.xyz[3 * ic + 2];
-    }
-    // d' of this shell (visible to the H step after the first barrier below)
-    const double *dP = a.d + (active ? a.aux_off[sP] : 0);
-    for (int c = tid; c < G::NCP; c += TS) {
-      double v = 0.0;
-      if (active) {
-        if (a.pure) {
+  const int Kab = Ka * Kb;
+  // The pair's primitive triplets over all its aux shells, (aux shell, p) in
+  // order, are cut into chunks of PCH: M sums over aux shells as well, so a
+  // chunk may mix shells and every chunk but the last is full.  The cursor
+  // (cip, cp) is uniform over the team.
+  auto shell_prims = [&](int ip) { return (valid && ip < a.np) ? Kab * a.aux.nprim[a.psh[ip]] : 0; };
+  int cip = 0, cp = 0, cK = shell_prims(0);
+  while (cip < np_loop && cK == 0) cK = shell_prims(++cip);
+  while (cip < np_loop) {
+    // slots of this chunk: aux shell position and primitive in the shell
+    int sl_ip[PCH], sl_p[PCH];
+    int npc = 0;
 #pragma unroll
-          for (int m = 0; m < G::NPURE; ++m) v += dP[m] * SH::dense[m * G::NCP + c];
-        } else {
-          v = dP[c];
+    for (int pp = 0; pp < PCH; ++pp) {
+      sl_ip[pp] = cip;
+      sl_p[pp] = cp;
+      if (cip < np_loop) {
+        npc = pp + 1;
+        if (++cp == cK) {
+          cp = 0;
+          cK = shell_prims(++cip);
+          while (cip < np_loop && cK == 0) cK = shell_prims(++cip);
         }
       }
-      DP[c] = v;
     }
-    const int K = Ka * Kb * Kc;  // uniform over the team
-    for (int p0 = 0; p0 < K; p0 += PCH) {
-      const int npc = imin(PCH, K - p0);
-      int lt = tid;
-      __asm__ volatile("" : "+v"(lt));
-      setup_chunk<G, TS, REC, 0>(a.boys, prims, lt, p0, npc, Kb, Kc, Ar, Br, Cr, AB2,
-                                 a.orb.exps + oa, a.orb.coefs + oa, a.orb.exps + ob,
-                                 a.orb.coefs + ob, a.aux.exps + oc, a.aux.coefs + oc);
-      team_sync();
-      vrr1<G, TS, PCH, REC>(prims, npc, lt);
-      // H_u of the chunk, u-major so the long sums (small |u|) spread over lanes
-      for (int it = lt; it < npc * NU; it += TS) {
-        const int u = it / npc, pp = it - u * npc;
-        const double *SWp = prims + pp * REC + PS_N + G::NV1;
-        double h = 0.0;
+    int lt = tid;
+    __asm__ volatile("" : "+v"(lt));
+    // d' of the aux shell of every slot
+    for (int it = lt; it < npc * G::NCP; it += TS) {
+      const int pp = it / G::NCP, c = it - pp * G::NCP;
+      int ip = sl_ip[0];
+#pragma unroll
+      for (int q = 1; q < PCH; ++q)
+        if (pp == q) ip = sl_ip[q];
+      const double *dP = a.d + a.aux_off[a.psh[ip]];
+      double v;
+      if (a.pure) {
+        v = 0.0;
+#pragma unroll
+        for (int m = 0; m < G::NPURE; ++m) v += dP[m] * SH::dense[m * G::NCP + c];
+      } else {
+        v = dP[c];
+      }
+      DP[pp * G::NCP + c] = v;
+    }
+    // one lane per slot: record setup (primitive of its own aux shell)
+    if (lt < npc) {
+      int ip = sl_ip[0], p = sl_p[0];
+#pragma unroll
+      for (int q = 1; q < PCH; ++q)
+        if (lt == q) {
+          ip = sl_ip[q];
+          p = sl_p[q];
+        }
+      const int sP = a.psh[ip];
+      const int Kc = a.aux.nprim[sP];
+      const int64_t oc = a.aux.prim_off[sP];
+      const int ic = a.aux.atom[sP];
+      const double Cr[3] = {a.xyz[3 * ic], a.xyz[3 * ic + 1], a.xyz[3 * ic + 2]};
+      setup_prim<G, 0>(a.boys, prims + lt * REC, p, Kb, Kc, Ar, Br, Cr, AB2, a.orb.exps + oa,
+                       a.orb.coefs + oa, a.orb.exps + ob, a.orb.coefs + ob, a.aux.exps + oc,
+                       a.aux.coefs + oc);
+    }
+    team_sync();
+    vrr1<G, TS, PCH, REC>(prims, npc, lt);
+    // H_u of the chunk, u-major so the long sums (small |u|) spread over lanes
+    for (int it = lt; it < npc * NU; it += TS) {
+      const int u = it / npc, pp = it - u * npc;
+      const double *SWp = prims + pp * REC + PS_N + G::NV1;
+      const double *DPp = DP + pp * G::NCP;
+      double h = 0.0;
 #pragma unroll 4
-        for (int q = SH::jh_start[u]; q < SH::jh_start[u + 1]; ++q) {
-          const uint32_t t = SH::jh_t[q];
-          h += double(t >> 16) * DP[t & 0xffu] * SWp[(t >> 8) & 0xffu];
-        }
-        prims[pp * REC + JE::HU + u] = h;
+      for (int q = SH::jh_start[u]; q < SH::jh_start[u + 1]; ++q) {
+        const uint32_t t = SH::jh_t[q];
+        h += double(t >> 16) * DPp[t & 0xffu] * SWp[(t >> 8) & 0xffu];
       }
-      team_sync();
-      // M += H V on the matrix cores; lane (pc, cl): primitive pc, row / column cl
-      const int wl = lt >> 6, pc = (lt & 63) >> 4, cl = lt & 15;
-      const double *Rl = prims + pc * REC + cl;
-      const bool pv = pc < npc;
-      static_for<NWV>([&](auto wc) {
-        constexpr int W = decltype(wc)::value;
-        if (wl == W) {
-          static_for<NTW>([&](auto jc) {
-            constexpr int j = decltype(jc)::value;
-            constexpr int t = j * NWV + W;
-            if constexpr (t < MT::N) {
-              constexpr int k = MT::field(t, 0), r0 = MT::field(t, 1), c0 = MT::field(t, 2);
-              constexpr int nr = ncart(k) - r0, nc = G::nek(k) - c0;
-              const double av = (pv && cl < nr) ? Rl[JE::HU + offT(k) + r0] : 0.0;
-              const double bv = (pv && cl < nc) ? Rl[PS_N + offT(G::emin(k)) + c0] : 0.0;
-              macc[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, macc[j], 0, 0, 0);
-            }
-          });
-        }
-      });
-      team_sync();
+      prims[pp * REC + JE::HU + u] = h;
     }
+    team_sync();
+    // M += H V on the matrix cores; lane (pc, cl): primitive pc, row / column cl
+    const int wl = lt >> 6, pc = (lt & 63) >> 4, cl = lt & 15;
+    const double *Rl = prims + pc * REC + cl;
+    const bool pv = pc < npc;
+    static_for<NWV>([&](auto wc) {
+      constexpr int W = decltype(wc)::value;
+      if (wl == W) {
+        static_for<NTW>([&](auto jc) {
+          constexpr int j = decltype(jc)::value;
+          constexpr int t = j * NWV + W;
+          if constexpr (t < MT::N) {
+            constexpr int k = MT::field(t, 0), r0 = MT::field(t, 1), c0 = MT::field(t, 2);
+            constexpr int nr = ncart(k) - r0, nc = G::nek(k) - c0;
+            const double av = (pv && cl < nr) ? Rl[JE::HU + offT(k) + r0] : 0.0;
+            const double bv = (pv && cl < nc) ? Rl[PS_N + offT(G::emin(k)) + c0] : 0.0;
+            macc[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, macc[j], 0, 0, 0);
+          }
+        });
+      }
+    });
+    team_sync();
   }
   // M to LDS, then X_e = sum_u e!/(e-u)! M_{u,e-u}
   double *MJ = S + JE::MJ;
