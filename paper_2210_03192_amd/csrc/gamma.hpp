@@ -49,27 +49,6 @@ __device__ __forceinline__ void gam_pair(const GamArgs &g, int64_t q, int &sa, i
   }
 }
 
-// HRR orientation of equal-l pairs, as in the forward kernels
-template <int LA, int LB>
-__device__ __forceinline__ void gam_orient(const ShellsDev &orb, int &sa, int &sb) {
-  if (LA == LB && sa != sb) {
-    auto tight = [&](int sh) {
-      const double *e = orb.exps + orb.prim_off[sh];
-      double lo = e[0], hi = e[0];
-      for (int i = 1; i < orb.nprim[sh]; ++i) {
-        lo = fmin(lo, e[i]);
-        hi = fmax(hi, e[i]);
-      }
-      return lo * hi;
-    };
-    if (tight(sb) > tight(sa)) {
-      const int t = sa;
-      sa = sb;
-      sb = t;
-    }
-  }
-}
-
 // ---------------------------------------------------------------------------
 // Register engine (classes of the register J engine): one lane per item.
 // ---------------------------------------------------------------------------
@@ -96,7 +75,7 @@ __global__ void __launch_bounds__(64) k_gam_r(GamArgs g) {
     for (int64_t q = q0; q < q1; ++q) {
       int sa, sb;
       gam_pair(g, q, sa, sb);
-      gam_orient<LA, LB>(g.orb, sa, sb);
+      orient_pair<LA, LB>(g.orb, sa, sb);
       const int Ka = g.orb.nprim[sa], Kb = g.orb.nprim[sb];
       const double *ea = g.orb.exps + g.orb.prim_off[sa], *ca = g.orb.coefs + g.orb.prim_off[sa];
       const double *eb = g.orb.exps + g.orb.prim_off[sb], *cb = g.orb.coefs + g.orb.prim_off[sb];
@@ -330,7 +309,7 @@ __global__ void __launch_bounds__(TS > 64 ? TS : 64)
       int sa = 0, sb = 0;
       if (valid) {
         gam_pair(g, q, sa, sb);
-        gam_orient<LA, LB>(g.orb, sa, sb);
+        orient_pair<LA, LB>(g.orb, sa, sb);
       }
       const int Ka = valid ? g.orb.nprim[sa] : 0, Kb = valid ? g.orb.nprim[sb] : 0;
       const int Kc = valid ? g.aux.nprim[sP] : 0;

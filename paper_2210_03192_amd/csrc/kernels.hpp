@@ -136,12 +136,14 @@ struct Cfg {
   static constexpr int LDS = (BLK / TS) * Layout<LP, LA, LB, PCH>::TOTAL * 8;
   // minimum waves per SIMD requested from the register allocator
   static constexpr int WPE = TS >= 128 ? DF3C_MIN_WAVES_BIG : TS == 64 ? DF3C_MIN_WAVES_WAVE : 1;
-  // J kernels: one lane per shell pair on the register engine, else as above
+  // J kernels: one lane per shell pair on the register engine, else the J
+  // engine with whole-wave teams (at least one wave per shell pair)
   static constexpr bool JREG = TS < 64 && JReg<LP, LA, LB>::OK;
-  static constexpr int TSJ = JREG ? 1 : TS;
-  static constexpr int PCHJ = JREG ? 1 : TS >= 64 ? 4 : PCH;
+  static constexpr int TSJ = JREG ? 1 : TS >= 64 ? TS : 64;
+  static constexpr int PCHJ = JREG ? 1 : 4;
   static constexpr int BLKJ = TSJ > 64 ? TSJ : 64;
-  static constexpr int WPEJ = JREG ? DF3C_MIN_WAVES_JREG : WPE;
+  static constexpr int WPEJ = JREG ? DF3C_MIN_WAVES_JREG : TSJ >= 128 ? DF3C_MIN_WAVES_BIG
+                                                                    : DF3C_MIN_WAVES_WAVE;
   static_assert(LDS <= 160 * 1024, "class does not fit the LDS of a CU");
 };
 
@@ -638,8 +640,34 @@ __global__ void __launch_bounds__(TS > 64 ? TS : 64)
 }
 
 // ---------------------------------------------------------------------------
-// J digestion: one orbital shell pair per team; the team loops over all aux
-// shells of l = LP.  The HRR and the ket transform are linear in the ket, and
+// HRR orientation of a pair of equal l: the VRR1 quanta go to the shell with
+// the larger (max exponent x min exponent), for which the Gaussian product
+// centre P lies closest to its own centre and the HRR transfers are best
+// conditioned.  The J kernels write both J blocks of a pair, so the choice is
+// free; the batched (P|ab) path makes the same choice.
+// ---------------------------------------------------------------------------
+template <int LA, int LB>
+__device__ __forceinline__ void orient_pair(const ShellsDev &orb, int &sa, int &sb) {
+  if (LA != LB || sa == sb) return;
+  auto tight = [&](int sh) {
+    const double *e = orb.exps + orb.prim_off[sh];
+    double lo = e[0], hi = e[0];
+    for (int i = 1; i < orb.nprim[sh]; ++i) {
+      lo = fmin(lo, e[i]);
+      hi = fmax(hi, e[i]);
+    }
+    return lo * hi;
+  };
+  if (tight(sb) > tight(sa)) {
+    const int t = sa;
+    sa = sb;
+    sb = t;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// J digestion: one orbital shell pair per team (per lane group on the register
+// engine); the team loops over all aux shells of l = LP.  The HRR and the ket transform are linear in the ket, and
 // the HRR coefficients depend only on A - B, so d_P is contracted into (e0|P)
 // right after the transform and accumulated over all aux shells,
 //   X_e = sum_P sum_m d_Pm (e0|Pm),
@@ -665,23 +693,7 @@ __device__ __forceinline__ void jr_pair(const JArgs &a, bool valid, int sa, int 
   using SH = GenSolid<LP>;
   constexpr int L = R::L, NE = R::NE, NCP = ncart(LP), NA = ncart(LA), NB = ncart(LB);
   if (!valid) return;
-  if (LA == LB && sa != sb) {
-    // HRR orientation as in j_pair
-    auto tight = [&](int sh) {
-      const double *e = a.orb.exps + a.orb.prim_off[sh];
-      double lo = e[0], hi = e[0];
-      for (int i = 1; i < a.orb.nprim[sh]; ++i) {
-        lo = fmin(lo, e[i]);
-        hi = fmax(hi, e[i]);
-      }
-      return lo * hi;
-    };
-    if (tight(sb) > tight(sa)) {
-      const int t = sa;
-      sa = sb;
-      sb = t;
-    }
-  }
+  orient_pair<LA, LB>(a.orb, sa, sb);
   const int Ka = a.orb.nprim[sa], Kb = a.orb.nprim[sb];
   const double *ea = a.orb.exps + a.orb.prim_off[sa], *ca = a.orb.coefs + a.orb.prim_off[sa];
   const double *eb = a.orb.exps + a.orb.prim_off[sb], *cb = a.orb.coefs + a.orb.prim_off[sb];
@@ -939,23 +951,7 @@ __device__ __forceinline__ void jeng_pair(const JArgs &a, double *S, int tid, bo
   constexpr int NWV = TS / 64;
   constexpr int NTW = (MT::N + NWV - 1) / NWV;
   constexpr int NU = offT(imin(LP, G::EB) + 1);  // H_u with |u| <= min(LP, EB)
-  if (valid && LA == LB && sa != sb) {
-    // HRR orientation as in j_pair
-    auto tight = [&](int sh) {
-      const double *e = a.orb.exps + a.orb.prim_off[sh];
-      double lo = e[0], hi = e[0];
-      for (int i = 1; i < a.orb.nprim[sh]; ++i) {
-        lo = fmin(lo, e[i]);
-        hi = fmax(hi, e[i]);
-      }
-      return lo * hi;
-    };
-    if (tight(sb) > tight(sa)) {
-      const int t = sa;
-      sa = sb;
-      sb = t;
-    }
-  }
+  if (valid) orient_pair<LA, LB>(a.orb, sa, sb);
   const int Ka = valid ? a.orb.nprim[sa] : 0, Kb = valid ? a.orb.nprim[sb] : 0;
   const int64_t oa = valid ? a.orb.prim_off[sa] : 0, ob = valid ? a.orb.prim_off[sb] : 0;
   double Ar[3] = {0, 0, 0}, Br[3] = {0, 0, 0};
@@ -1135,135 +1131,31 @@ __device__ __forceinline__ void jeng_pair(const JArgs &a, double *S, int tid, bo
 
 template <int LP, int LA, int LB, int TS, int PCH>
 struct JLayout {
-  using G = Geo<LP, LA, LA + LB>;
-  static constexpr int XD = Layout<LP, LA, LB, PCH>::TOTAL;   // X_e for the final HRR
-  // doubles per team: the engine's layout, or the per-triplet layout + X
+  // the register engine keeps everything in registers; the J engine runs
+  // whole-wave teams with chunks of 4 primitive triplets
   static constexpr bool REG = TS == 1 && JReg<LP, LA, LB>::OK;
-  static constexpr int TOTAL = REG ? 0
-                               : use_jengine<LP, LA, LB, TS, PCH>() ? JELayout<LP, LA, LB, PCH>::TOTAL
-                                                                   : (XD + G::NE) | 1;
+  static_assert(REG || use_jengine<LP, LA, LB, TS, PCH>(), "J runs on one of the two engines");
+  static constexpr int TOTAL = REG ? 0 : JELayout<LP, LA, LB, PCH>::TOTAL;
   static constexpr int BYTES_WG = ((TS > 64 ? TS : 64) / TS) * TOTAL * 8;
   static_assert(BYTES_WG <= 160 * 1024, "J layout does not fit the LDS of a CU");
 };
 
 template <int LP, int LA, int LB, int TS, int PCH>
-__device__ __forceinline__ void j_pair(const JArgs &a, double *S, int tid, const int *slot,
-                                       bool valid, int sa, int sb, int np_loop, int sub) {
-  if constexpr (TS == 1 && JReg<LP, LA, LB>::OK) {
+__device__ __forceinline__ void j_pair(const JArgs &a, double *S, int tid, bool valid, int sa,
+                                       int sb, int np_loop, int sub) {
+  if constexpr (JLayout<LP, LA, LB, TS, PCH>::REG)
     jr_pair<LP, LA, LB>(a, valid, sa, sb, sub);
-    return;
-  } else if constexpr (use_jengine<LP, LA, LB, TS, PCH>()) {
+  else
     jeng_pair<LP, LA, LB, TS, PCH>(a, S, tid, valid, sa, sb, np_loop);
-    return;
-  }
-  using G = Geo<LP, LA, LA + LB>;
-  using LY = Layout<LP, LA, LB, PCH>;
-  using JL = JLayout<LP, LA, LB, TS, PCH>;
-  constexpr int NA = ncart(LA), NB = ncart(LB);
-  constexpr int NX = (G::NE + TS - 1) / TS;
-  const int np_out = a.pure ? npure(LP) : ncart(LP);
-  if (valid && LA == LB && sa != sb) {
-    // orient the pair for a well-conditioned HRR (see the runtime's k_scatter):
-    // VRR1 quanta on the shell with the larger (max exponent x min exponent);
-    // both J blocks are written below, so the orientation is free.
-    auto tight = [&](int sh) {
-      const double *e = a.orb.exps + a.orb.prim_off[sh];
-      double lo = e[0], hi = e[0];
-      for (int i = 1; i < a.orb.nprim[sh]; ++i) {
-        lo = fmin(lo, e[i]);
-        hi = fmax(hi, e[i]);
-      }
-      return lo * hi;
-    };
-    if (tight(sb) > tight(sa)) {
-      const int t = sa;
-      sa = sb;
-      sb = t;
-    }
-  }
-  const int Ka = valid ? a.orb.nprim[sa] : 0, Kb = valid ? a.orb.nprim[sb] : 0;
-  const int64_t oa = valid ? a.orb.prim_off[sa] : 0, ob = valid ? a.orb.prim_off[sb] : 0;
-  double Ar[3] = {0, 0, 0}, Br[3] = {0, 0, 0};
-  if (valid) {
-    const int ia = a.orb.atom[sa], ib = a.orb.atom[sb];
-    for (int x = 0; x < 3; ++x) {
-      Ar[x] = a.xyz[3 * ia + x];
-      Br[x] = a.xyz[3 * ib + x];
-    }
-  }
-  double X[NX];
-#pragma unroll
-  for (int k = 0; k < NX; ++k) X[k] = 0.0;
-  // np_loop is uniform over the workgroup (>= a.np); teams past their own
-  // a.np run the iteration without work so that every barrier is met
-  for (int ip = 0; ip < np_loop; ++ip) {
-    const bool active = valid && ip < a.np;
-    const int sP = active ? a.psh[ip] : 0;
-    const int Kc = active ? a.aux.nprim[sP] : 0;
-    const int npmax = TS >= 64 ? Ka * Kb * Kc : wave_max(Ka * Kb * Kc);
-    const int64_t oc = active ? a.aux.prim_off[sP] : 0;
-    double Cr[3] = {0, 0, 0};
-    if (active) {
-      const int ic = a.aux.atom[sP];
-      Cr[0] = a.xyz[3 * ic];
-      Cr[1] = a.xyz[3 * ic + 1];
-      Cr[2] = a.xyz[3 * ic + 2];
-    }
-    triplet_to_e0P<LP, LA, LB, TS, PCH>(a.boys, S, tid, slot, npmax, Ar, Br, Cr, Ka,
-                                        a.orb.exps + oa, a.orb.coefs + oa, Kb, a.orb.exps + ob,
-                                        a.orb.coefs + ob, Kc, a.aux.exps + oc, a.aux.coefs + oc,
-                                        a.pure);
-    const double *EM = S + LY::EM;
-    const double *dP = a.d + (active ? a.aux_off[sP] : 0);
-#pragma unroll
-    for (int k = 0; k < NX; ++k) {
-      const int e = tid + k * TS;
-      if (active && e < G::NE) {
-        double v = X[k];
-        for (int m = 0; m < np_out; ++m) v += dP[m] * EM[m * G::NE + e];
-        X[k] = v;
-      }
-    }
-    team_sync();
-  }
-  // one single-component HRR for the pair
-  double *XD = S + JL::XD;
-#pragma unroll
-  for (int k = 0; k < NX; ++k)
-    if (tid + k * TS < G::NE) XD[tid + k * TS] = X[k];
-  team_sync();
-  double pwx[LB + 1], pwy[LB + 1], pwz[LB + 1];
-  pwx[0] = pwy[0] = pwz[0] = 1.0;
-#pragma unroll
-  for (int k = 1; k <= LB; ++k) {
-    pwx[k] = pwx[k - 1] * (Ar[0] - Br[0]);
-    pwy[k] = pwy[k - 1] * (Ar[1] - Br[1]);
-    pwz[k] = pwz[k - 1] * (Ar[2] - Br[2]);
-  }
-  if (valid) {
-    const int64_t ra = a.ao_off[sa] - a.ao_base, rb = a.ao_off[sb] - a.ao_base;
-    for (int ia = tid; ia < NA; ia += TS) {
-      double o[NB];
-      hrr_nq<LA, LB>(XD, ia, pwx, pwy, pwz, o);
-#pragma unroll
-      for (int ib = 0; ib < NB; ++ib) {
-        a.J[(ra + ia) * a.nao + rb + ib] += o[ib];
-        if (sa != sb) a.J[(rb + ib) * a.nao + ra + ia] += o[ib];
-      }
-    }
-  }
-  team_sync();
 }
 
 template <int LP, int LA, int LB, int TS, int PCH>
 __global__ void __launch_bounds__(TS > 64 ? TS : 64)
     __attribute__((amdgpu_waves_per_eu(Cfg<LP, LA, LB>::WPEJ))) k_J(JArgs a) {
-  using G = Geo<LP, LA, LA + LB>;
   using JL = JLayout<LP, LA, LB, TS, PCH>;
   constexpr int BLK = TS > 64 ? TS : 64;
   constexpr int TPB = BLK / TS;
-  constexpr bool REG = JLayout<LP, LA, LB, TS, PCH>::REG;
-  constexpr int NQ = REG ? 1 : (G::NPI + TS - 1) / TS;
+  constexpr bool REG = JL::REG;
   extern __shared__ double smem[];
   // register engine: lane = sub (64 / nsub) + team, nsub lanes per pair
   const int tpb = REG ? TPB / a.nsub : TPB;
@@ -1271,8 +1163,6 @@ __global__ void __launch_bounds__(TS > 64 ? TS : 64)
   const int sub = REG ? int(threadIdx.x) / tpb : 0;
   const int tid = threadIdx.x % TS;
   double *S = smem + (REG ? 0 : team * JL::TOTAL);
-  int slot[NQ];
-  if constexpr (!REG) make_slots<LP, LA, LB, TS>(slot, tid);
 
   for (int64_t base = int64_t(blockIdx.x) * tpb; base < a.npair; base += int64_t(gridDim.x) * tpb) {
     const int64_t q = base + team;
@@ -1292,7 +1182,7 @@ __global__ void __launch_bounds__(TS > 64 ? TS : 64)
         sb = a.bsh[j];
       }
     }
-    j_pair<LP, LA, LB, TS, PCH>(a, S, tid, slot, valid, sa, sb, a.np, sub);
+    j_pair<LP, LA, LB, TS, PCH>(a, S, tid, valid, sa, sb, a.np, sub);
   }
 }
 

@@ -50,12 +50,10 @@ __device__ __forceinline__ int find_seg(const JSeg *seg, int nseg, int64_t item)
 template <int LP, int LA, int LB, int TS, int PCH>
 __global__ void __launch_bounds__(TS > 64 ? TS : 64)
     __attribute__((amdgpu_waves_per_eu(Cfg<LP, LA, LB>::WPEJ))) k_Jq(JQArgs q) {
-  using G = Geo<LP, LA, LA + LB>;
   using JL = JLayout<LP, LA, LB, TS, PCH>;
   constexpr int BLK = TS > 64 ? TS : 64;
   constexpr int TPB = BLK / TS;
-  constexpr bool REG = JLayout<LP, LA, LB, TS, PCH>::REG;
-  constexpr int NQ = REG ? 1 : (G::NPI + TS - 1) / TS;
+  constexpr bool REG = JL::REG;
   extern __shared__ double smem[];
   __shared__ unsigned long long s_base;
   // register engine: lane = sub (64 / nsub) + team, nsub lanes per item
@@ -64,8 +62,6 @@ __global__ void __launch_bounds__(TS > 64 ? TS : 64)
   const int sub = REG ? int(threadIdx.x) / tpb : 0;
   const int tid = threadIdx.x % TS;
   double *S = smem + (REG ? 0 : team * JL::TOTAL);
-  int slot[NQ];
-  if constexpr (!REG) make_slots<LP, LA, LB, TS>(slot, tid);
 
   for (;;) {
     if (threadIdx.x == 0) s_base = atomicAdd(q.counter, (unsigned long long)(tpb * q.chunk));
@@ -102,7 +98,7 @@ __global__ void __launch_bounds__(TS > 64 ? TS : 64)
       a.np = np;
       // the aux loop runs to the workgroup's largest np; shorter teams idle
       const int np_loop = TS >= 64 ? np : wave_max(np);
-      j_pair<LP, LA, LB, TS, PCH>(a, S, tid, slot, valid, sa, sb, np_loop, sub);
+      j_pair<LP, LA, LB, TS, PCH>(a, S, tid, valid, sa, sb, np_loop, sub);
     }
   }
 }
