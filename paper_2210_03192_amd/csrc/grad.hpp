@@ -12,7 +12,7 @@
 // single-component HRR gives the shifted blocks that are contracted with G.
 // Integrals are recomputed, never stored.
 //
-// Owner computes: one team per orbital shell pair, looping over the aux shells
+// Owner computes: one team per orbital shell pair and subset of the aux shells
 // of l = LP.  Per-atom contributions are accumulated per team in LDS in a fixed
 // order and added to a per-(workgroup, team) partial array in global memory;
 // a final kernel sums the partials in a fixed order, so the gradient is
@@ -36,8 +36,17 @@ struct GradArgs {
   int64_t nao, npair;
   int32_t pure;
   int32_t natom;
+  int32_t nsplit;           // aux shells of a pair split into nsplit interleaved subsets
   double *partial;          // [gridDim.x * teams per block][natom][3], accumulated
 };
+
+// Work items of the gradient kernels: blocks of tpb consecutive shell pairs
+// times nsplit subsets of the aux shells (subset k: aux shells k, k + nsplit,
+// ...); every team of a workgroup takes the same subset, so the aux loop is
+// uniform over the workgroup.  Block b -> subset b / nblk, pairs of block b % nblk.
+__device__ __forceinline__ int64_t grad_blocks(const GradArgs &g, int tpb) {
+  return (g.npair + tpb - 1) / tpb * g.nsplit;
+}
 
 template <int LP, int LA, int LB, int PCH>
 struct GradLayout {
@@ -154,8 +163,10 @@ __global__ void __launch_bounds__(TS > 64 ? TS : 64)
   for (int x = tid; x < 3 * g.natom; x += TS) ACC[x] = 0.0;
   team_sync();
 
-  for (int64_t base = int64_t(blockIdx.x) * TPB; base < g.npair; base += int64_t(gridDim.x) * TPB) {
-    const int64_t q = base + team;
+  const int64_t nblk = (g.npair + TPB - 1) / TPB;
+  for (int64_t blk = blockIdx.x; blk < grad_blocks(g, TPB); blk += gridDim.x) {
+    const int sub = int(blk / nblk);
+    const int64_t q = (blk - sub * nblk) * TPB + team;
     const bool valid = q < g.npair;
     int sa = 0, sb = 0;
     if (valid) {
@@ -172,23 +183,7 @@ __global__ void __launch_bounds__(TS > 64 ? TS : 64)
         sb = g.bsh[j];
       }
     }
-    if (valid && LA == LB && sa != sb) {
-      // same orientation rule as the forward J kernel (well-conditioned HRR)
-      auto tight = [&](int sh) {
-        const double *e = g.orb.exps + g.orb.prim_off[sh];
-        double lo = e[0], hi = e[0];
-        for (int i = 1; i < g.orb.nprim[sh]; ++i) {
-          lo = fmin(lo, e[i]);
-          hi = fmax(hi, e[i]);
-        }
-        return lo * hi;
-      };
-      if (tight(sb) > tight(sa)) {
-        const int t = sa;
-        sa = sb;
-        sb = t;
-      }
-    }
+    if (valid) orient_pair<LA, LB>(g.orb, sa, sb);
     const int Ka = valid ? g.orb.nprim[sa] : 0, Kb = valid ? g.orb.nprim[sb] : 0;
     const int64_t oa = valid ? g.orb.prim_off[sa] : 0, ob = valid ? g.orb.prim_off[sb] : 0;
     const int atA = valid ? g.orb.atom[sa] : 0, atB = valid ? g.orb.atom[sb] : 0;
@@ -220,7 +215,7 @@ __global__ void __launch_bounds__(TS > 64 ? TS : 64)
       pwz[k] = pwz[k - 1] * (Ar[2] - Br[2]);
     }
     double GA[3] = {0, 0, 0}, GB[3] = {0, 0, 0};
-    for (int ip = 0; ip < g.np; ++ip) {
+    for (int ip = sub; ip < g.np; ip += g.nsplit) {
       const int sP = g.psh[ip];
       const int Kc = g.aux.nprim[sP];
       const int npmax = TS >= 64 ? Ka * Kb * Kc : wave_max(Ka * Kb * Kc);
@@ -378,8 +373,10 @@ __global__ void __launch_bounds__(64) k_gradr(GradArgs g) {
   for (int x = lane; x < 3 * g.natom; x += 64) ACC[x] = 0.0;
   __syncthreads();
 
-  for (int64_t base = int64_t(blockIdx.x) * 64; base < g.npair; base += int64_t(gridDim.x) * 64) {
-    const int64_t q = base + lane;
+  const int64_t nblk = (g.npair + 63) / 64;
+  for (int64_t blk = blockIdx.x; blk < grad_blocks(g, 64); blk += gridDim.x) {
+    const int sub = int(blk / nblk);
+    const int64_t q = (blk - sub * nblk) * 64 + lane;
     const bool valid = q < g.npair;
     int sa = 0, sb = 0;
     if (valid) {
@@ -395,23 +392,7 @@ __global__ void __launch_bounds__(64) k_gradr(GradArgs g) {
         sa = g.ash[i];
         sb = g.bsh[j];
       }
-      if (LA == LB && sa != sb) {
-        // same orientation rule as the forward J kernels
-        auto tight = [&](int sh) {
-          const double *e = g.orb.exps + g.orb.prim_off[sh];
-          double lo = e[0], hi = e[0];
-          for (int i = 1; i < g.orb.nprim[sh]; ++i) {
-            lo = fmin(lo, e[i]);
-            hi = fmax(hi, e[i]);
-          }
-          return lo * hi;
-        };
-        if (tight(sb) > tight(sa)) {
-          const int t = sa;
-          sa = sb;
-          sb = t;
-        }
-      }
+      orient_pair<LA, LB>(g.orb, sa, sb);
     }
     const int Ka = valid ? g.orb.nprim[sa] : 0, Kb = valid ? g.orb.nprim[sb] : 0;
     const double *ea = g.orb.exps + (valid ? g.orb.prim_off[sa] : 0);
@@ -453,7 +434,7 @@ __global__ void __launch_bounds__(64) k_gradr(GradArgs g) {
     }
     double GA[3] = {0, 0, 0}, GB[3] = {0, 0, 0};
 
-    for (int ip = 0; ip < g.np; ++ip) {  // uniform over the wavefront
+    for (int ip = sub; ip < g.np; ip += g.nsplit) {  // uniform over the wavefront
       const int sP = g.psh[ip];
       const int Kc = g.aux.nprim[sP];
       const double *ec = g.aux.exps + g.aux.prim_off[sP];

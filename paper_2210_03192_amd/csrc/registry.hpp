@@ -31,6 +31,7 @@ struct GradInfo {
   int tpb = 0;        // per-atom LDS arrays (teams) per workgroup
   int team = 0;       // LDS doubles per team before the per-atom array
   int ppw = 0;        // shell pairs per workgroup and grid step
+  int wpb = 0;        // wavefronts per workgroup
   hipError_t (*gfn)(const GradArgs &, int, int, hipStream_t) = nullptr;  // (args, grid, lds)
 };
 
@@ -136,11 +137,13 @@ GradInfo grad_info() {
     g.tpb = 1;
     g.team = 0;
     g.ppw = 64;
+    g.wpb = 1;
     g.gfn = &launch_gradr<LP, LA, LB>;
   } else {
     g.tpb = C::TPB;
     g.team = C::TEAM;
     g.ppw = C::TPB;
+    g.wpb = C::BLK / 64;
     g.gfn = &launch_grad<LP, LA, LB>;
   }
   return g;

@@ -765,9 +765,21 @@ int df3c_coulomb_gamma(const double *xyz, int32_t natom, const df3c_shells *aux,
 
 // ----------------------------------------------------------------- J gradient
 namespace {
-constexpr int GRAD_GRID_PER_CU = 4;     // workgroups per CU of every gradient launch
+constexpr int GRAD_GRID_PER_CU = 16;    // workgroups per CU of every gradient launch
 constexpr int GRAD_MAX_TPB = 4;         // teams per workgroup of the gradient kernels
 int grad_slots(int ncu) { return ncu * GRAD_GRID_PER_CU * GRAD_MAX_TPB; }
+
+// Aux-shell subsets per shell pair of a gradient class: a class of few pairs
+// (or few pairs per wavefront) is split into pairs x subsets work items until
+// about four waves per SIMD are available (at most 16 subsets, no more than
+// the aux shells).
+int grad_split(const GradInfo &gi, int64_t npair, int np, int ncu) {
+  const int64_t target = int64_t(ncu) * 16;
+  auto waves = [&](int k) { return (npair + gi.ppw - 1) / gi.ppw * k * gi.wpb; };
+  int n = 1;
+  while (n < 16 && 2 * n <= np && waves(n) < target) n *= 2;
+  return n;
+}
 }  // namespace
 
 size_t df3c_coulomb_J_grad_workspace(const df3c_shells *aux, const df3c_shells *orb,
@@ -866,8 +878,9 @@ int df3c_coulomb_J_grad(const double *xyz, int32_t natom, const df3c_shells *aux
         const GradInfo &gi = g_grad[lp][la][lb];
         const int lds = gi.tpb * (gi.team + 3 * natom) * 8;
         if (lds > 160 * 1024) return DF3C_E_UNSUPPORTED;
-        const int grid = int(std::max<int64_t>(1, std::min<int64_t>((a.npair + gi.ppw - 1) / gi.ppw,
-                                                                     grid_cap)));
+        a.nsplit = grad_split(gi, a.npair, np, ds->ncu);
+        const int64_t blocks = (a.npair + gi.ppw - 1) / gi.ppw * a.nsplit;
+        const int grid = int(std::max<int64_t>(1, std::min<int64_t>(blocks, grid_cap)));
         if (timed(DF3C_KERNEL_GRAD, (lp * NLA + la) * NLA + lb, s,
                   [&] { return gi.gfn(a, grid, lds, s); }) != hipSuccess)
           return DF3C_E_HIP;
