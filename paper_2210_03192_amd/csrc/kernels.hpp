@@ -138,7 +138,7 @@ struct Cfg {
   static constexpr int WPE = TS >= 128 ? DF3C_MIN_WAVES_BIG : TS == 64 ? DF3C_MIN_WAVES_WAVE : 1;
   // J kernels: one lane per shell pair on the register engine, else the J
   // engine with whole-wave teams (at least one wave per shell pair)
-  static constexpr bool JREG = TS < 64 && JReg<LP, LA, LB>::OK;
+  static constexpr bool JREG = JReg<LP, LA, LB>::OK;
   static constexpr int TSJ = JREG ? 1 : TS >= 64 ? TS : 64;
   static constexpr int PCHJ = JREG ? 1 : 4;
   static constexpr int BLKJ = TSJ > 64 ? TSJ : 64;
