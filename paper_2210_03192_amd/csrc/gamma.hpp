@@ -8,9 +8,10 @@
 //   G_u = sum_{e >= u} w_e e!/(e-u)! [e-u 0|0]^(LP),
 //   y_c += sum_{u <= c} C(c,u) sW_{|u|}[c-u] G_u,      gamma_m = sum_c T_mc y_c.
 //
-// Work item = (aux shell, chunk of consecutive shell pairs of the class); each
-// item writes its own partial gamma of the aux shell, and one reduction per
-// class adds the partials in chunk order: no atomics, bitwise reproducible.
+// Work items write partial gammas that one reduction per class adds in a fixed
+// order (no atomics, bitwise reproducible): on the register engine an item is
+// (range of shell pairs, subset of the aux shells), on the per-triplet
+// pipeline (aux shell, chunk of consecutive shell pairs).
 #pragma once
 #include "kernels.hpp"
 
@@ -30,7 +31,14 @@ struct GamArgs {
   int32_t pure;
   int32_t nchunk;             // chunks of pairs per aux shell
   int64_t chunk;              // pairs per chunk
-  double *partial;            // [np * nchunk][np_out]
+  // register engine: items (pair range r, aux subset s); subset s holds the
+  // aux shells s, s + nsplit, ... (at most nps of them), range r the pairs
+  // [r prange, (r + 1) prange)
+  int32_t nsplit, nps;
+  int64_t prange;
+  int64_t nrange;
+  double *partial;            // per-triplet pipeline: [np * nchunk][np_out];
+                              // register engine: [nrange][nsplit][nps][np_out]
 };
 
 // pair q of the class -> (sa, sb)
@@ -50,33 +58,36 @@ __device__ __forceinline__ void gam_pair(const GamArgs &g, int64_t q, int &sa, i
 }
 
 // ---------------------------------------------------------------------------
-// Register engine (classes of the register J engine): one lane per item.
+// Register engine (classes of the register J engine): one lane per shell pair.
+// A workgroup is one wavefront and one item (pair range, aux subset).  Per
+// round of 64 pairs each lane transposes the HRR onto its D~ once (w_e); per
+// aux shell of the subset it forms y over the pair's primitive triplets, the
+// ket transform, and the wavefront sums the 64 pairs by a fixed butterfly.
+// Lane 0 accumulates the sums per aux shell in LDS, and the item writes them
+// as its partial; a reduction adds the ranges in order.
 // ---------------------------------------------------------------------------
 template <int LP, int LA, int LB>
 __global__ void __launch_bounds__(64) k_gam_r(GamArgs g) {
   using R = JReg<LP, LA, LB>;
   using SH = GenSolid<LP>;
   constexpr int L = R::L, NE = R::NE, NCP = ncart(LP), NA = ncart(LA), NB = ncart(LB);
-  const int64_t items = int64_t(g.np) * g.nchunk;
-  for (int64_t item = int64_t(blockIdx.x) * 64 + threadIdx.x; item < items;
-       item += int64_t(gridDim.x) * 64) {
-    const int ip = int(item / g.nchunk);
-    const int64_t ch = item - int64_t(ip) * g.nchunk;
-    const int sP = g.psh[ip];
-    const int Kc = g.aux.nprim[sP];
-    const double *ec = g.aux.exps + g.aux.prim_off[sP], *cc = g.aux.coefs + g.aux.prim_off[sP];
-    const int icn = g.aux.atom[sP];
-    const double C[3] = {g.xyz[3 * icn], g.xyz[3 * icn + 1], g.xyz[3 * icn + 2]};
-    const int64_t q0 = ch * g.chunk, q1 = q0 + g.chunk < g.npair ? q0 + g.chunk : g.npair;
-    double y[NCP];
-#pragma unroll
-    for (int c = 0; c < NCP; ++c) y[c] = 0.0;
-
-    for (int64_t q = q0; q < q1; ++q) {
-      int sa, sb;
-      gam_pair(g, q, sa, sb);
-      orient_pair<LA, LB>(g.orb, sa, sb);
-      const int Ka = g.orb.nprim[sa], Kb = g.orb.nprim[sb];
+  extern __shared__ double acc[];  // [nps][np_out]
+  const int lane = threadIdx.x;
+  const int nout = g.pure ? npure(LP) : NCP;
+  for (int64_t item = blockIdx.x; item < g.nrange * g.nsplit; item += gridDim.x) {
+    const int64_t r = item / g.nsplit;
+    const int sub = int(item - r * g.nsplit);
+    for (int x = lane; x < g.nps * nout; x += 64) acc[x] = 0.0;
+    const int64_t qend = (r + 1) * g.prange < g.npair ? (r + 1) * g.prange : g.npair;
+    for (int64_t q0 = r * g.prange; q0 < qend; q0 += 64) {
+      const int64_t q = q0 + lane;
+      const bool valid = q < qend;
+      int sa = 0, sb = 0;
+      if (valid) {
+        gam_pair(g, q, sa, sb);
+        orient_pair<LA, LB>(g.orb, sa, sb);
+      }
+      const int Ka = valid ? g.orb.nprim[sa] : 0, Kb = valid ? g.orb.nprim[sb] : 0;
       const double *ea = g.orb.exps + g.orb.prim_off[sa], *ca = g.orb.coefs + g.orb.prim_off[sa];
       const double *eb = g.orb.exps + g.orb.prim_off[sb], *cb = g.orb.coefs + g.orb.prim_off[sb];
       double A[3], B[3];
@@ -110,8 +121,8 @@ __global__ void __launch_bounds__(64) k_gam_r(GamArgs g) {
           static_for<NB>([&](auto bc) {
             constexpr int bi = decltype(bc)::value;
             constexpr C3 bv = cart(LB, bi);
-            double dt = g.D[(ra + ai) * g.nao + rb + bi];
-            if (sa != sb) dt += g.D[(rb + bi) * g.nao + ra + ai];
+            double dt = valid ? g.D[(ra + ai) * g.nao + rb + bi] : 0.0;
+            if (valid && sa != sb) dt += g.D[(rb + bi) * g.nao + ra + ai];
             static_for<bv[0] + 1>([&](auto xc) {
               constexpr int ix = decltype(xc)::value;
               static_for<bv[1] + 1>([&](auto yc) {
@@ -128,127 +139,148 @@ __global__ void __launch_bounds__(64) k_gam_r(GamArgs g) {
           });
         });
       }
-      for (int ia = 0; ia < Ka; ++ia)
-        for (int ib = 0; ib < Kb; ++ib) {
-          const double za = ea[ia], zb = eb[ib];
-          const double gg = za + zb, ig = 1.0 / gg;
-          const double P[3] = {(za * A[0] + zb * B[0]) * ig, (za * A[1] + zb * B[1]) * ig,
-                               (za * A[2] + zb * B[2]) * ig};
-          const double PA[3] = {P[0] - A[0], P[1] - A[1], P[2] - A[2]};
-          const double eab = exp(-za * zb * ig * AB2) * ca[ia] * cb[ib];
-          for (int ic = 0; ic < Kc; ++ic) {
-            const double zc = ec[ic];
-            const double PC[3] = {P[0] - C[0], P[1] - C[1], P[2] - C[2]};
-            const double gz = gg + zc, rho = gg * zc / gz, rg = rho * ig, i2g = 0.5 * ig;
-            const double T = rho * (PC[0] * PC[0] + PC[1] * PC[1] + PC[2] * PC[2]);
-            const double pre = 34.98683665524972497 / (sqrt(gz) * gg * zc) * eab * cc[ic];
-            const double RP[3] = {rg * PC[0], rg * PC[1], rg * PC[2]};
-            double Fm[L + 1];
-            boys<LP, L + 1>(g.boys, T, Fm);
-            double vr[R::NVR];
+      for (int ks = 0, ip = sub; ip < g.np; ++ks, ip += g.nsplit) {  // uniform over the wave
+        const int sP = g.psh[ip];
+        const int Kc = g.aux.nprim[sP];
+        const double *ec = g.aux.exps + g.aux.prim_off[sP], *cc = g.aux.coefs + g.aux.prim_off[sP];
+        const int icn = g.aux.atom[sP];
+        const double C[3] = {g.xyz[3 * icn], g.xyz[3 * icn + 1], g.xyz[3 * icn + 2]};
+        double y[NCP];
 #pragma unroll
-            for (int m = 0; m <= L; ++m) vr[m] = pre * Fm[m];
-            static_for<L>([&](auto lc) {
-              constexpr int l = decltype(lc)::value + 1;
-              static_for<ncart(l)>([&](auto cc_) {
-                constexpr int c = decltype(cc_)::value;
-                constexpr C3 e = cart(l, c);
-                constexpr int i = rdir(e);
-                constexpr int c1 = cidx(e[0] - (i == 0), e[1] - (i == 1), e[2] - (i == 2));
-                constexpr int o1 = R::voff(l - 1) + c1 * (L - l + 2);
-                constexpr int o = R::voff(l) + c * (L - l + 1);
-                static_for<L - l + 1>([&](auto mc) {
-                  constexpr int m = decltype(mc)::value;
-                  double v = PA[i] * vr[o1 + m] - RP[i] * vr[o1 + m + 1];
-                  if constexpr (e[i] >= 2) {
-                    constexpr int c2 = cidx(e[0] - 2 * (i == 0), e[1] - 2 * (i == 1),
-                                            e[2] - 2 * (i == 2));
-                    constexpr int o2 = R::voff(l - 2) + c2 * (L - l + 3);
-                    v += double(e[i] - 1) * i2g * (vr[o2 + m] - rg * vr[o2 + m + 1]);
-                  }
-                  vr[o + m] = v;
+        for (int c = 0; c < NCP; ++c) y[c] = 0.0;
+        for (int ia = 0; ia < Ka; ++ia)
+          for (int ib = 0; ib < Kb; ++ib) {
+            const double za = ea[ia], zb = eb[ib];
+            const double gg = za + zb, ig = 1.0 / gg;
+            const double P[3] = {(za * A[0] + zb * B[0]) * ig, (za * A[1] + zb * B[1]) * ig,
+                                 (za * A[2] + zb * B[2]) * ig};
+            const double PA[3] = {P[0] - A[0], P[1] - A[1], P[2] - A[2]};
+            const double eab = exp(-za * zb * ig * AB2) * ca[ia] * cb[ib];
+            for (int ic = 0; ic < Kc; ++ic) {
+              const double zc = ec[ic];
+              const double PC[3] = {P[0] - C[0], P[1] - C[1], P[2] - C[2]};
+              const double gz = gg + zc, rho = gg * zc / gz, rg = rho * ig, i2g = 0.5 * ig;
+              const double T = rho * (PC[0] * PC[0] + PC[1] * PC[1] + PC[2] * PC[2]);
+              const double pre = 34.98683665524972497 / (sqrt(gz) * gg * zc) * eab * cc[ic];
+              const double RP[3] = {rg * PC[0], rg * PC[1], rg * PC[2]};
+              double Fm[L + 1];
+              boys<LP, L + 1>(g.boys, T, Fm);
+              double vr[R::NVR];
+#pragma unroll
+              for (int m = 0; m <= L; ++m) vr[m] = pre * Fm[m];
+              static_for<L>([&](auto lc) {
+                constexpr int l = decltype(lc)::value + 1;
+                static_for<ncart(l)>([&](auto cc_) {
+                  constexpr int c = decltype(cc_)::value;
+                  constexpr C3 e = cart(l, c);
+                  constexpr int i = rdir(e);
+                  constexpr int c1 = cidx(e[0] - (i == 0), e[1] - (i == 1), e[2] - (i == 2));
+                  constexpr int o1 = R::voff(l - 1) + c1 * (L - l + 2);
+                  constexpr int o = R::voff(l) + c * (L - l + 1);
+                  static_for<L - l + 1>([&](auto mc) {
+                    constexpr int m = decltype(mc)::value;
+                    double v = PA[i] * vr[o1 + m] - RP[i] * vr[o1 + m + 1];
+                    if constexpr (e[i] >= 2) {
+                      constexpr int c2 = cidx(e[0] - 2 * (i == 0), e[1] - 2 * (i == 1),
+                                              e[2] - 2 * (i == 2));
+                      constexpr int o2 = R::voff(l - 2) + c2 * (L - l + 3);
+                      v += double(e[i] - 1) * i2g * (vr[o2 + m] - rg * vr[o2 + m + 1]);
+                    }
+                    vr[o + m] = v;
+                  });
                 });
               });
-            });
-            // G_u = sum_{e >= u} w_e e!/(e-u)! V_{e-u}
-            double Gu[R::NU];
+              // G_u = sum_{e >= u} w_e e!/(e-u)! V_{e-u}
+              double Gu[R::NU];
 #pragma unroll
-            for (int u = 0; u < R::NU; ++u) Gu[u] = 0.0;
-            static_for<L - LA + 1>([&](auto lc) {
-              constexpr int le = LA + decltype(lc)::value;
-              static_for<ncart(le)>([&](auto ec_) {
-                constexpr int ce = decltype(ec_)::value;
-                constexpr C3 e = cart(le, ce);
-                const double we = w[offT(le) - offT(LA) + ce];
-                static_for<e[0] + 1>([&](auto xc) {
-                  constexpr int ux = decltype(xc)::value;
-                  static_for<e[1] + 1>([&](auto yc) {
-                    constexpr int uy = decltype(yc)::value;
-                    static_for<e[2] + 1>([&](auto zc_) {
-                      constexpr int uz = decltype(zc_)::value;
-                      constexpr int k = ux + uy + uz;
-                      if constexpr (k <= LP) {
-                        constexpr int lr = le - k;
-                        constexpr int cr = cidx(e[0] - ux, e[1] - uy, e[2] - uz);
-                        constexpr double f = double(falling(e[0], ux) * falling(e[1], uy) *
-                                                    falling(e[2], uz));
-                        Gu[offT(k) + cidx(ux, uy, uz)] +=
-                            (f * we) * vr[R::voff(lr) + cr * (L - lr + 1)];
-                      }
+              for (int u = 0; u < R::NU; ++u) Gu[u] = 0.0;
+              static_for<L - LA + 1>([&](auto lc) {
+                constexpr int le = LA + decltype(lc)::value;
+                static_for<ncart(le)>([&](auto ec_) {
+                  constexpr int ce = decltype(ec_)::value;
+                  constexpr C3 e = cart(le, ce);
+                  const double we = w[offT(le) - offT(LA) + ce];
+                  static_for<e[0] + 1>([&](auto xc) {
+                    constexpr int ux = decltype(xc)::value;
+                    static_for<e[1] + 1>([&](auto yc) {
+                      constexpr int uy = decltype(yc)::value;
+                      static_for<e[2] + 1>([&](auto zc_) {
+                        constexpr int uz = decltype(zc_)::value;
+                        constexpr int k = ux + uy + uz;
+                        if constexpr (k <= LP) {
+                          constexpr int lr = le - k;
+                          constexpr int cr = cidx(e[0] - ux, e[1] - uy, e[2] - uz);
+                          constexpr double f = double(falling(e[0], ux) * falling(e[1], uy) *
+                                                      falling(e[2], uz));
+                          Gu[offT(k) + cidx(ux, uy, uz)] +=
+                              (f * we) * vr[R::voff(lr) + cr * (L - lr + 1)];
+                        }
+                      });
                     });
                   });
                 });
               });
-            });
-            // y_c += sum_{u <= c} C(c,u) s^{|u|} W^{c-u} G_u
-            const double s = rho * ig * (0.5 / zc), rz = rho / zc;
-            double wx[LP + 1], wy[LP + 1], wz[LP + 1], sk[R::KU + 1];
-            wx[0] = wy[0] = wz[0] = sk[0] = 1.0;
+              // y_c += sum_{u <= c} C(c,u) s^{|u|} W^{c-u} G_u
+              const double s = rho * ig * (0.5 / zc), rz = rho / zc;
+              double wx[LP + 1], wy[LP + 1], wz[LP + 1], sk[R::KU + 1];
+              wx[0] = wy[0] = wz[0] = sk[0] = 1.0;
 #pragma unroll
-            for (int k = 1; k <= LP; ++k) {
-              wx[k] = wx[k - 1] * (rz * PC[0]);
-              wy[k] = wy[k - 1] * (rz * PC[1]);
-              wz[k] = wz[k - 1] * (rz * PC[2]);
-            }
+              for (int k = 1; k <= LP; ++k) {
+                wx[k] = wx[k - 1] * (rz * PC[0]);
+                wy[k] = wy[k - 1] * (rz * PC[1]);
+                wz[k] = wz[k - 1] * (rz * PC[2]);
+              }
 #pragma unroll
-            for (int k = 1; k <= R::KU; ++k) sk[k] = sk[k - 1] * s;
-            static_for<R::KU + 1>([&](auto kc) {
-              constexpr int k = decltype(kc)::value;
-              static_for<ncart(k)>([&](auto uc) {
-                constexpr int ui = decltype(uc)::value;
-                constexpr C3 u = cart(k, ui);
-                const double gk = sk[k] * Gu[offT(k) + ui];
-                static_for<NCP>([&](auto cc_) {
-                  constexpr int c = decltype(cc_)::value;
-                  constexpr C3 qq = cart(LP, c);
-                  if constexpr (qq[0] >= u[0] && qq[1] >= u[1] && qq[2] >= u[2]) {
-                    constexpr double bn =
-                        double(binom(qq[0], u[0]) * binom(qq[1], u[1]) * binom(qq[2], u[2]));
-                    y[c] += (bn * gk) * (wx[qq[0] - u[0]] * wy[qq[1] - u[1]] * wz[qq[2] - u[2]]);
-                  }
+              for (int k = 1; k <= R::KU; ++k) sk[k] = sk[k - 1] * s;
+              static_for<R::KU + 1>([&](auto kc) {
+                constexpr int k = decltype(kc)::value;
+                static_for<ncart(k)>([&](auto uc) {
+                  constexpr int ui = decltype(uc)::value;
+                  constexpr C3 u = cart(k, ui);
+                  const double gk = sk[k] * Gu[offT(k) + ui];
+                  static_for<NCP>([&](auto cc_) {
+                    constexpr int c = decltype(cc_)::value;
+                    constexpr C3 qq = cart(LP, c);
+                    if constexpr (qq[0] >= u[0] && qq[1] >= u[1] && qq[2] >= u[2]) {
+                      constexpr double bn =
+                          double(binom(qq[0], u[0]) * binom(qq[1], u[1]) * binom(qq[2], u[2]));
+                      y[c] += (bn * gk) * (wx[qq[0] - u[0]] * wy[qq[1] - u[1]] * wz[qq[2] - u[2]]);
+                    }
+                  });
                 });
               });
+            }
+          }
+        // ket transform, sum over the wavefront's pairs, accumulate for the shell
+        double o[NCP];
+        if (g.pure) {
+          static_for<npure(LP)>([&](auto mc) {
+            constexpr int m = decltype(mc)::value;
+            double v = 0.0;
+            static_for<NCP>([&](auto cc_) {
+              constexpr int c = decltype(cc_)::value;
+              constexpr double t = SH::dense[m * NCP + c];
+              if constexpr (t != 0.0) v += t * y[c];
             });
+            o[m] = v;
+          });
+        } else {
+#pragma unroll
+          for (int c = 0; c < NCP; ++c) o[c] = y[c];
+        }
+#pragma unroll
+        for (int m = 0; m < NCP; ++m) {
+          if (m < nout) {
+            double v = o[m];
+#pragma unroll
+            for (int sh = 32; sh > 0; sh >>= 1) v += __shfl_xor(v, sh, 64);
+            if (lane == 0) acc[ks * nout + m] += v;
           }
         }
+      }
     }
-    // ket transform once per item, partial of this (aux shell, chunk)
-    double *out = g.partial + item * (g.pure ? npure(LP) : NCP);
-    if (g.pure) {
-      static_for<npure(LP)>([&](auto mc) {
-        constexpr int m = decltype(mc)::value;
-        double v = 0.0;
-        static_for<NCP>([&](auto cc_) {
-          constexpr int c = decltype(cc_)::value;
-          constexpr double t = SH::dense[m * NCP + c];
-          if constexpr (t != 0.0) v += t * y[c];
-        });
-        out[m] = v;
-      });
-    } else {
-#pragma unroll
-      for (int c = 0; c < NCP; ++c) out[c] = y[c];
-    }
+    double *out = g.partial + item * g.nps * nout;
+    for (int x = lane; x < g.nps * nout; x += 64) out[x] = acc[x];
   }
 }
 

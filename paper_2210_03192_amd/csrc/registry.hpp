@@ -75,7 +75,8 @@ hipError_t launch_gam(const GamArgs &a, int grid, hipStream_t s) {
   using C = Cfg<LP, LA, LB>;
   if constexpr (C::JREG) {
     auto kr = k_gam_r<LP, LA, LB>;
-    hipLaunchKernelGGL(kr, dim3(grid), dim3(64), 0, s, a);
+    const int lds = a.nps * (a.pure ? 2 * LP + 1 : (LP + 1) * (LP + 2) / 2) * 8;
+    hipLaunchKernelGGL(kr, dim3(grid), dim3(64), lds, s, a);
   } else {
     constexpr int lds = GamLayout<LP, LA, LB, C::TS, C::PCH>::BYTES_WG;
     auto kern = k_gam_p<LP, LA, LB, C::TS, C::PCH>;

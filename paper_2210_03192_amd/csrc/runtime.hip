@@ -649,6 +649,42 @@ namespace {
 // gamma work items aimed at per class: 4 wavefronts of register items per CU
 int64_t gam_target(int ncu) { return int64_t(ncu) * 4 * 64; }
 
+// Items of the register gamma engine for a class of npair shell pairs and np
+// aux shells with nout functions each: nsplit aux subsets (about 8 aux shells
+// per subset, so that a pair's set-up serves several shells; at most 4096
+// LDS doubles per item) times nrange ranges of pairs, about four wavefronts
+// per SIMD in all.
+struct GamRegPlan {
+  int32_t nsplit, nps;
+  int64_t prange, nrange;
+  size_t partial_doubles(int nout) const { return size_t(nrange) * nsplit * nps * nout; }
+};
+GamRegPlan gam_reg_plan(int64_t npair, int np, int nout, int ncu) {
+  GamRegPlan g;
+  const int64_t target = int64_t(ncu) * 16;
+  const int lo = int((int64_t(np) * nout + 4095) / 4096);
+  g.nsplit = std::max(lo, std::min(std::max(1, np / 8), 64));
+  g.nps = (np + g.nsplit - 1) / g.nsplit;
+  const int64_t rounds = (npair + 63) / 64;
+  const int64_t want = std::max<int64_t>(1, std::min<int64_t>(rounds, target / g.nsplit));
+  g.prange = (rounds + want - 1) / want * 64;
+  g.nrange = (npair + g.prange - 1) / g.prange;
+  return g;
+}
+
+// register engine: gamma[aux function] += sum over the pair ranges, in order
+__global__ void k_gam_reduce_r(const double *partial, int32_t np, int32_t nsplit, int32_t nps,
+                               int64_t nrange, int32_t nout, const int32_t *psh,
+                               const int64_t *aux_off, double *gamma) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < np * nout; i += gridDim.x * blockDim.x) {
+    const int ip = i / nout, m = i - ip * nout;
+    const int sub = ip % nsplit, k = ip / nsplit;
+    double v = 0.0;
+    for (int64_t r = 0; r < nrange; ++r) v += partial[((r * nsplit + sub) * nps + k) * nout + m];
+    gamma[aux_off[psh[ip]] + m] += v;
+  }
+}
+
 // gamma[aux function] += sum over the chunks of the class's partials, in order
 __global__ void k_gam_reduce(const double *partial, int32_t np, int32_t nchunk, int32_t nout,
                              const int32_t *psh, const int64_t *aux_off, double *gamma) {
@@ -662,12 +698,27 @@ __global__ void k_gam_reduce(const double *partial, int32_t np, int32_t nchunk, 
 }  // namespace
 
 size_t df3c_coulomb_gamma_workspace(const df3c_shells *aux, const df3c_shells *orb) {
-  if (!aux || !orb) return 0;
+  if (!aux || !orb || !aux->l_host || !orb->l_host) return 0;
   DevState *ds = nullptr;
   if (init_device(&ds)) return 0;
+  // per-triplet pipeline: (aux shell, chunk) items; register engine: the plan
+  // of every class it runs
   const size_t items = size_t(gam_target(ds->ncu)) + size_t(aux->nshell);
-  return jplan_bytes(orb->nshell, aux->nshell) +
-         align256(sizeof(double) * items * size_t(2 * DF3C_LMAX_AUX + 1));
+  size_t part = items * size_t(2 * DF3C_LMAX_AUX + 1);
+  int64_t no[DF3C_LMAX_ORB + 1] = {}, na[DF3C_LMAX_AUX + 1] = {};
+  for (int s = 0; s < orb->nshell; ++s)
+    if (orb->l_host[s] >= 0 && orb->l_host[s] <= DF3C_LMAX_ORB) ++no[orb->l_host[s]];
+  for (int s = 0; s < aux->nshell; ++s)
+    if (aux->l_host[s] >= 0 && aux->l_host[s] <= DF3C_LMAX_AUX) ++na[aux->l_host[s]];
+  for (int lp = 0; lp <= DF3C_LMAX_AUX; ++lp)
+    for (int la = 0; la <= DF3C_LMAX_ORB; ++la)
+      for (int lb = 0; lb <= la; ++lb) {
+        if (!na[lp] || !no[la] || !no[lb] || !g_cls[lp][la][lb].gam_reg) continue;
+        const int64_t npair = la == lb ? no[la] * (no[la] + 1) / 2 : no[la] * no[lb];
+        const int nout = aux->pure ? 2 * lp + 1 : (lp + 1) * (lp + 2) / 2;
+        part = std::max(part, gam_reg_plan(npair, int(na[lp]), nout, ds->ncu).partial_doubles(nout));
+      }
+  return jplan_bytes(orb->nshell, aux->nshell) + align256(sizeof(double) * part);
 }
 
 int df3c_coulomb_gamma(const double *xyz, int32_t natom, const df3c_shells *aux,
@@ -742,17 +793,30 @@ int df3c_coulomb_gamma(const double *xyz, int32_t natom, const df3c_shells *aux,
         a.same = (la == lb);
         a.npair = (la == lb) ? int64_t(na) * (na + 1) / 2 : int64_t(na) * nb;
         const ClassInfo &ci = g_cls[lp][la][lb];
+        const int c = (lp * NLA + la) * NLA + lb;
+        if (ci.gam_reg) {
+          const GamRegPlan gp = gam_reg_plan(a.npair, np, nout, ds->ncu);
+          a.nsplit = gp.nsplit;
+          a.nps = gp.nps;
+          a.prange = gp.prange;
+          a.nrange = gp.nrange;
+          const int grid = int(gp.nrange * gp.nsplit);
+          if (timed(DF3C_KERNEL_GAMMA, c, s, [&] { return ci.gam(a, grid, s); }) != hipSuccess)
+            return DF3C_E_HIP;
+          const int nred = np * nout;
+          hipLaunchKernelGGL(k_gam_reduce_r, dim3((nred + 255) / 256), dim3(256), 0, s, partial, np,
+                             gp.nsplit, gp.nps, gp.nrange, nout, a.psh, aux_off, gamma);
+          continue;
+        }
         // items = (aux shell, chunk of pairs); about gam_target of them per class
-        const int64_t target = ci.gam_reg ? gam_target(ds->ncu) : int64_t(ds->ncu) * 2 * ci.gam_ipw;
+        const int64_t target = int64_t(ds->ncu) * 2 * ci.gam_ipw;
         int64_t nchunk = std::min<int64_t>(a.npair, std::max<int64_t>(1, (target + np - 1) / np));
         a.chunk = (a.npair + nchunk - 1) / nchunk;
         nchunk = (a.npair + a.chunk - 1) / a.chunk;
         a.nchunk = int32_t(nchunk);
         const int64_t items = int64_t(np) * nchunk;
         const int grid = int(std::max<int64_t>(
-            1, std::min<int64_t>((items + ci.gam_ipw - 1) / ci.gam_ipw,
-                                 int64_t(ds->ncu) * (ci.gam_reg ? 8 : 4))));
-        const int c = (lp * NLA + la) * NLA + lb;
+            1, std::min<int64_t>((items + ci.gam_ipw - 1) / ci.gam_ipw, int64_t(ds->ncu) * 4)));
         if (timed(DF3C_KERNEL_GAMMA, c, s, [&] { return ci.gam(a, grid, s); }) != hipSuccess)
           return DF3C_E_HIP;
         const int nred = np * nout;
