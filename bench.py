@@ -42,8 +42,8 @@ KERNEL_SOURCES = [os.path.join("paper_2210_03192_amd", "csrc", f)
                   for f in ("device.hpp", "tables.hpp", "kernels.hpp", "gen_tables.py",
                             "inst_lp6.hip")]
 MEASURED_TRAFFIC = {
-    "k_store<6,4,4> K=6": (3.0469e9,
-                           "ffdbaa448c5fdc7aac58ec74351833742d5c6251426b6a2f032ddab238c21d7c"),
+    "k_store<6,4,4> K=6": (3.0434e9,
+                           "5bcd0c9478c97fb1ec22a35c7b4415659fb17be031c7ab99d851cdeac780e3d4"),
 }
 
 
