@@ -27,6 +27,7 @@ from fractions import Fraction
 
 LMAX_AUX = 6
 LMAX_ORB = 4
+LMAX_GRAD_ORB = 3
 
 
 def ncart(l):
@@ -231,6 +232,37 @@ def jx_terms(g):
     return start, mi, co
 
 
+def gy_terms(LP, EA, EB):
+    """Per target e (levels EA..EB, flat order): the terms (e!/(e-u)!, H_u
+    index offT(|u|) + cidx(u), VRR1 index offT(|e-u|) + cidx(e-u)) of the
+    per-primitive digested ket Y_e = sum_u e!/(e-u)! H_u [e-u 0|0]^(LP),
+    |u| <= LP (the derivative engine)."""
+    start, co, hu, vi = [], [], [], []
+    for lev in range(EA, EB + 1):
+        for e in carts(lev):
+            start.append(len(co))
+            for ux in range(e[0] + 1):
+                for uy in range(e[1] + 1):
+                    for uz in range(e[2] + 1):
+                        k = ux + uy + uz
+                        if k > LP:
+                            continue
+                        r = (e[0] - ux, e[1] - uy, e[2] - uz)
+                        co.append(math.perm(e[0], ux) * math.perm(e[1], uy) * math.perm(e[2], uz))
+                        hu.append(offT(k) + cidx((ux, uy, uz)))
+                        vi.append(offT(sum(r)) + cidx(r))
+    start.append(len(co))
+    return start, co, hu, vi
+
+
+def grad_geometries():
+    """(LP, EA, EB) = (L_P, max(l_a - 1, 0), l_a + l_b + 1) of the gradient
+    classes (l_a >= l_b, up to the gradient's orbital limit)."""
+    return sorted({(LP, max(la - 1, 0), la + lb + 1)
+                   for LP in range(LMAX_AUX + 1)
+                   for la in range(LMAX_GRAD_ORB + 1) for lb in range(la + 1)})
+
+
 # ----------------------------------------------------------------------- HRR
 def hrr(LA, LB):
     hc_start, hc_pow, hc_binom = [], [], []
@@ -410,6 +442,16 @@ def write(outdir):
             # one word per term: coefficient << 16 | index into M
             assert max(jm, default=0) < 65536 and max(jc, default=0) < 65536
             s.append(arr("uint32_t", "jx_mc", [(cc << 16) | mm for mm, cc in zip(jm, jc)]))
+            s.append("};\n")
+        for (lp, EA, EB) in grad_geometries():
+            if lp != LP:
+                continue
+            ys, yc, yh, yv = gy_terms(LP, EA, EB)
+            s.append(f"template <> struct GenY<{LP}, {EA}, {EB}> {{\n")
+            s.append(arr("int16_t", "y_start", ys))
+            # one word per term: coefficient << 16 | H_u index << 8 | VRR1 index
+            assert max(yh) < 256 and max(yv) < 256 and max(yc) < 65536
+            s.append(arr("uint32_t", "y_t", [(c << 16) | (h << 8) | v for c, h, v in zip(yc, yh, yv)]))
             s.append("};\n")
         s.append("}  // namespace df3c\n")
         _write_if_changed(os.path.join(outdir, f"tables_lp{LP}.hpp"), "".join(s))

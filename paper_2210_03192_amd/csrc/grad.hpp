@@ -655,3 +655,288 @@ __global__ void __launch_bounds__(64) k_gradr(GradArgs g) {
 }
 
 }  // namespace df3c
+
+namespace df3c {
+
+// ---------------------------------------------------------------------------
+// Gradient engine (classes beyond the register engine): one wavefront per
+// work item (shell pair, subset of the aux shells).  The HRRs of the four
+// shifted classes are transposed onto G~ once per pair, giving twelve weight
+// vectors over the targets e (shift s = A+, B+, A-, B-, direction x):
+//   omega^{A+,x}_e = sum_ab G~_ab sum_i [a + 1_x + i = e] C(b,i) AB^{b-i}
+//   omega^{B+,x}_e = sum_ab G~_ab sum_i [a + i = e] C(b+1_x,i) AB^{b+1_x-i}
+//   omega^{A-,x}_e = sum_ab G~_ab a_x sum_i [a - 1_x + i = e] C(b,i) AB^{b-i}
+//   omega^{B-,x}_e = sum_ab G~_ab b_x sum_i [a + i = e] C(b-1_x,i) AB^{b-1_x-i}
+// (the HRR (ab|X) = sum_i C(b,i) AB^{b-i} X_{a+i} of every shifted block).
+// Per primitive triplet, with the digested ket
+//   Y_e = sum_u e!/(e-u)! H_u [e-u 0|0]^(LP),   e = max(l_a-1,0) .. l_a+l_b+1,
+// the derivative integrals contracted with G~ and d are dot products,
+//   dA_x = 2 zeta_a omega^{A+,x}.Y - omega^{A-,x}.Y,
+//   dB_x = 2 zeta_b omega^{B+,x}.Y - omega^{B-,x}.Y,   dC_x = -(dA_x + dB_x),
+// with dC on the primitive's own aux centre.  No per-aux-shell HRR remains, so
+// chunks of primitive triplets span the aux shells of the subset (as in the
+// J engine); the three lanes of the directions add the chunk's contributions
+// in primitive order, so the atom arrays are filled in a fixed order.
+// ---------------------------------------------------------------------------
+template <int LP, int LA, int LB>
+struct GEng {
+  static constexpr int EA = LA > 0 ? LA - 1 : 0, EB = LA + LB + 1;
+  using G = Geo<LP, EA, EB>;
+  static constexpr int NA = ncart(LA), NB = ncart(LB), NCP = ncart(LP);
+  static constexpr int NY = offT(EB + 1) - offT(EA);
+  static constexpr int NU = offT(imin(LP, EB) + 1);   // H_u with |u| <= min(LP, EB)
+  static constexpr int HU = PS_N + G::NV1 + G::NSW;    // record: scalars, VRR1, sW, H
+  static constexpr int REC = HU + G::NSW;
+  static constexpr int PCH = REC <= 200 ? 16 : 8;
+  // LDS regions of the team (doubles)
+  static constexpr int DP = PCH * REC;                 // d' per slot [PCH][NCP]
+  static constexpr int ZW = DP + PCH * NCP;            // per slot: 2 zeta_a, 2 zeta_b, aux atom
+  static constexpr int Y = ZW + 3 * PCH;               // [PCH][NY]
+  static constexpr int T = Y + PCH * NY;               // dot products [PCH][12]
+  static constexpr int OM = T + 12 * PCH;              // omega [12][NY]
+  static constexpr int GT = OM + 12 * NY;              // G~ of the pair [NA][NB]
+  static constexpr int PW = GT + NA * NB;              // AB powers [3][LB + 2]
+  static constexpr int TEAM = PW + 3 * (LB + 2);       // doubles before the atom array
+  // first and one-past-last flat target index of shift s (relative to level EA)
+  static constexpr int lo(int s) {
+    return offT(imax(s == 0 ? LA + 1 : s == 2 ? LA - 1 : LA, EA)) - offT(EA);
+  }
+  static constexpr int hi(int s) {
+    const int top = s == 0 ? LA + 1 + LB : s == 1 ? LA + LB + 1 : s == 2 ? LA - 1 + LB : LA + LB - 1;
+    return top < EA ? 0 : offT(top + 1) - offT(EA);
+  }
+};
+
+// omega^{s,x}_e (j = 3 s + x; e given by its flat index relative to level EA)
+template <int LA, int LB, int EA>
+__device__ __forceinline__ double grad_omega(int j, int ef, const double *GT, const double *PW) {
+  int lev = EA;
+  while (offT(lev + 1) - offT(EA) <= ef) ++lev;
+  const C3 e = cart(lev, ef - (offT(lev) - offT(EA)));
+  const int s = j / 3, x = j - 3 * s;
+  const int las = s == 0 ? LA + 1 : s == 2 ? LA - 1 : LA;
+  const int k = lev - las;  // |i|
+  if (k < 0) return 0.0;
+  const int dbx = x == 0, dby = x == 1, dbz = x == 2;
+  double v = 0.0;
+  for (int bi = 0; bi < ncart(LB); ++bi) {
+    const C3 b = cart(LB, bi);
+    const int bx = b[0], by = b[1], bz = b[2];
+    const int bxs = x == 0 ? bx : x == 1 ? by : bz;
+    if (s == 3 && bxs == 0) continue;
+    const int sg = s == 1 ? 1 : s == 3 ? -1 : 0;
+    const int b0 = bx + sg * dbx, b1 = by + sg * dby, b2 = bz + sg * dbz;
+    if (k > b0 + b1 + b2) continue;
+    const double cb = s == 3 ? double(bxs) : 1.0;
+    for (int ic = 0; ic < ncart(k); ++ic) {
+      const C3 i = cart(k, ic);
+      if (i[0] > b0 || i[1] > b1 || i[2] > b2) continue;
+      const int sa = s == 0 ? -1 : s == 2 ? 1 : 0;
+      const int a0 = e[0] - i[0] + sa * dbx, a1 = e[1] - i[1] + sa * dby, a2 = e[2] - i[2] + sa * dbz;
+      if (a0 < 0 || a1 < 0 || a2 < 0) continue;
+      const double ca = s == 2 ? double(x == 0 ? a0 : x == 1 ? a1 : a2) : 1.0;
+      const double bn = double(binom(b0, i[0]) * binom(b1, i[1]) * binom(b2, i[2]));
+      v += ca * cb * bn * GT[cidx(a0, a1, a2) * ncart(LB) + bi] * PW[b0 - i[0]] *
+           PW[(LB + 2) + b1 - i[1]] * PW[2 * (LB + 2) + b2 - i[2]];
+    }
+  }
+  return v;
+}
+
+template <int LP, int LA, int LB>
+__global__ void __launch_bounds__(64)
+    __attribute__((amdgpu_waves_per_eu(DF3C_MIN_WAVES_WAVE))) k_grade(GradArgs g) {
+  using E = GEng<LP, LA, LB>;
+  using G = typename E::G;
+  using SH = GenSolid<LP>;
+  using TY = GenY<LP, E::EA, E::EB>;
+  constexpr int TS = 64, PCH = E::PCH, REC = E::REC, NY = E::NY, NU = E::NU;
+  constexpr int NA = E::NA, NB = E::NB, NCP = E::NCP;
+  extern __shared__ double smem[];
+  double *S = smem;
+  double *ACC = S + E::TEAM;
+  double *prims = S, *DP = S + E::DP, *ZW = S + E::ZW, *Yv = S + E::Y, *Tv = S + E::T;
+  double *OM = S + E::OM, *GT = S + E::GT, *PW = S + E::PW;
+  const int tid = threadIdx.x;
+  for (int x = tid; x < 3 * g.natom; x += TS) ACC[x] = 0.0;
+  team_sync();
+
+  const int64_t nblk = g.npair;  // one pair per block
+  for (int64_t blk = blockIdx.x; blk < nblk * g.nsplit; blk += gridDim.x) {
+    const int sub = int(blk / nblk);
+    const int64_t q = blk - sub * nblk;
+    int sa, sb;
+    if (g.same) {
+      int i = int((sqrt(8.0 * double(q) + 1.0) - 1.0) * 0.5);
+      while (int64_t(i) * (i + 1) / 2 > q) --i;
+      while (int64_t(i + 1) * (i + 2) / 2 <= q) ++i;
+      const int j = int(q - int64_t(i) * (i + 1) / 2);
+      sa = g.ash[i];
+      sb = g.ash[j];
+    } else {
+      const int i = int(q / g.nb), j = int(q - int64_t(i) * g.nb);
+      sa = g.ash[i];
+      sb = g.bsh[j];
+    }
+    orient_pair<LA, LB>(g.orb, sa, sb);
+    const int Ka = g.orb.nprim[sa], Kb = g.orb.nprim[sb];
+    const int64_t oa = g.orb.prim_off[sa], ob = g.orb.prim_off[sb];
+    const int atA = g.orb.atom[sa], atB = g.orb.atom[sb];
+    double Ar[3], Br[3];
+    for (int x = 0; x < 3; ++x) {
+      Ar[x] = g.xyz[3 * atA + x];
+      Br[x] = g.xyz[3 * atB + x];
+    }
+    const double AB2 = (Ar[0] - Br[0]) * (Ar[0] - Br[0]) + (Ar[1] - Br[1]) * (Ar[1] - Br[1]) +
+                       (Ar[2] - Br[2]) * (Ar[2] - Br[2]);
+    // G~ (both J blocks of an off-diagonal pair) and the powers of A - B
+    {
+      const int64_t ra = g.ao_off[sa], rb = g.ao_off[sb];
+      for (int ab = tid; ab < NA * NB; ab += TS) {
+        const int ia = ab / NB, ib = ab - ia * NB;
+        double v = g.G[(ra + ia) * g.nao + rb + ib];
+        if (sa != sb) v += g.G[(rb + ib) * g.nao + ra + ia];
+        GT[ab] = v;
+      }
+      if (tid < 3) {
+        const double d = Ar[tid] - Br[tid];
+        double p = 1.0;
+        for (int n = 0; n < LB + 2; ++n) {
+          PW[tid * (LB + 2) + n] = p;
+          p *= d;
+        }
+      }
+    }
+    team_sync();
+    for (int it = tid; it < 12 * NY; it += TS)
+      OM[it] = grad_omega<LA, LB, E::EA>(it / NY, it - (it / NY) * NY, GT, PW);
+    team_sync();
+
+    double GA = 0.0, GB = 0.0;  // lanes 0..2: direction x = tid
+    const int Kab = Ka * Kb;
+    // the pair's primitive triplets over the aux shells of its subset, in
+    // (aux shell, p) order, cut into chunks of PCH; the cursor is uniform
+    auto shell_prims = [&](int ip) { return ip < g.np ? Kab * g.aux.nprim[g.psh[ip]] : 0; };
+    int cip = sub, cp = 0, cK = shell_prims(sub);
+    while (cip < g.np && cK == 0) cK = shell_prims(cip += g.nsplit);
+    while (cip < g.np) {
+      int sl_ip[PCH], sl_p[PCH];
+      int npc = 0;
+#pragma unroll
+      for (int pp = 0; pp < PCH; ++pp) {
+        sl_ip[pp] = cip;
+        sl_p[pp] = cp;
+        if (cip < g.np) {
+          npc = pp + 1;
+          if (++cp == cK) {
+            cp = 0;
+            cK = shell_prims(cip += g.nsplit);
+            while (cip < g.np && cK == 0) cK = shell_prims(cip += g.nsplit);
+          }
+        }
+      }
+      int lt = tid;
+      __asm__ volatile("" : "+v"(lt));
+      // d' of the aux shell of every slot
+      for (int it = lt; it < npc * NCP; it += TS) {
+        const int pp = it / NCP, c = it - pp * NCP;
+        int ip = sl_ip[0];
+#pragma unroll
+        for (int qq = 1; qq < PCH; ++qq)
+          if (pp == qq) ip = sl_ip[qq];
+        const double *dP = g.d + g.aux_off[g.psh[ip]];
+        double v;
+        if (g.pure) {
+          v = 0.0;
+#pragma unroll
+          for (int m = 0; m < G::NPURE; ++m) v += dP[m] * SH::dense[m * NCP + c];
+        } else {
+          v = dP[c];
+        }
+        DP[pp * NCP + c] = v;
+      }
+      // one lane per slot: record set-up, 2 zeta_a, 2 zeta_b and the aux atom
+      if (lt < npc) {
+        int ip = sl_ip[0], p = sl_p[0];
+#pragma unroll
+        for (int qq = 1; qq < PCH; ++qq)
+          if (lt == qq) {
+            ip = sl_ip[qq];
+            p = sl_p[qq];
+          }
+        const int sP = g.psh[ip];
+        const int Kc = g.aux.nprim[sP];
+        const int64_t oc = g.aux.prim_off[sP];
+        const int atC = g.aux.atom[sP];
+        const double Cr[3] = {g.xyz[3 * atC], g.xyz[3 * atC + 1], g.xyz[3 * atC + 2]};
+        setup_prim<G, 0>(g.boys, prims + lt * REC, p, Kb, Kc, Ar, Br, Cr, AB2, g.orb.exps + oa,
+                         g.orb.coefs + oa, g.orb.exps + ob, g.orb.coefs + ob, g.aux.exps + oc,
+                         g.aux.coefs + oc);
+        const int rest = p / Kc;
+        ZW[lt * 3] = 2.0 * g.orb.exps[oa + rest / Kb];
+        ZW[lt * 3 + 1] = 2.0 * g.orb.exps[ob + rest % Kb];
+        ZW[lt * 3 + 2] = double(atC);
+      }
+      team_sync();
+      vrr1<G, TS, PCH, REC>(prims, npc, lt);
+      // H_u of the chunk (the digested ket, as in the J engine)
+      for (int it = lt; it < npc * NU; it += TS) {
+        const int u = it / npc, pp = it - u * npc;
+        const double *SWp = prims + pp * REC + PS_N + G::NV1;
+        const double *DPp = DP + pp * NCP;
+        double h = 0.0;
+#pragma unroll 4
+        for (int qq = SH::jh_start[u]; qq < SH::jh_start[u + 1]; ++qq) {
+          const uint32_t t = SH::jh_t[qq];
+          h += double(t >> 16) * DPp[t & 0xffu] * SWp[(t >> 8) & 0xffu];
+        }
+        prims[pp * REC + E::HU + u] = h;
+      }
+      team_sync();
+      // Y_e = sum_u e!/(e-u)! H_u V_{e-u} per slot
+      for (int it = lt; it < npc * NY; it += TS) {
+        const int pp = it / NY, ef = it - pp * NY;
+        const double *R = prims + pp * REC;
+        double v = 0.0;
+#pragma unroll 4
+        for (int qq = TY::y_start[ef]; qq < TY::y_start[ef + 1]; ++qq) {
+          const uint32_t t = TY::y_t[qq];
+          v += double(t >> 16) * R[E::HU + ((t >> 8) & 0xffu)] * R[PS_N + (t & 0xffu)];
+        }
+        Yv[pp * NY + ef] = v;
+      }
+      team_sync();
+      // the twelve dot products per slot
+      for (int it = lt; it < npc * 12; it += TS) {
+        const int pp = it / 12, j = it - pp * 12, s = j / 3;
+        const int e0 = s == 0 ? E::lo(0) : s == 1 ? E::lo(1) : s == 2 ? E::lo(2) : E::lo(3);
+        const int e1 = s == 0 ? E::hi(0) : s == 1 ? E::hi(1) : s == 2 ? E::hi(2) : E::hi(3);
+        const double *o = OM + j * NY, *y = Yv + pp * NY;
+        double v = 0.0;
+        for (int e = e0; e < e1; ++e) v += o[e] * y[e];
+        Tv[it] = v;
+      }
+      team_sync();
+      if (lt < 3) {
+        for (int pp = 0; pp < npc; ++pp) {
+          const double *t = Tv + pp * 12;
+          const double dA = ZW[pp * 3] * t[lt] - t[6 + lt];
+          const double dB = ZW[pp * 3 + 1] * t[3 + lt] - t[9 + lt];
+          GA += dA;
+          GB += dB;
+          ACC[3 * int(ZW[pp * 3 + 2]) + lt] -= dA + dB;
+        }
+      }
+      team_sync();
+    }
+    if (tid < 3) {
+      ACC[3 * atA + tid] += GA;
+      ACC[3 * atB + tid] += GB;
+    }
+    team_sync();
+  }
+  double *part = g.partial + int64_t(blockIdx.x) * 3 * g.natom;
+  for (int x = tid; x < 3 * g.natom; x += TS) part[x] += ACC[x];
+}
+
+}  // namespace df3c

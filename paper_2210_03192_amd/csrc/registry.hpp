@@ -110,13 +110,12 @@ void fill_metric(MetricInfo (&t)[7]) {
 }
 
 template <int LP, int LA, int LB>
-hipError_t launch_grad(const GradArgs &a, int grid, int lds, hipStream_t s) {
-  using C = GradCfg<LP, LA, LB>;
-  auto kern = k_grad<LP, LA, LB, C::TS, C::PCH>;
+hipError_t launch_grade(const GradArgs &a, int grid, int lds, hipStream_t s) {
+  auto kern = k_grade<LP, LA, LB>;
   static const hipError_t attr = hipFuncSetAttribute(
       reinterpret_cast<const void *>(kern), hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
   if (attr != hipSuccess) return attr;
-  hipLaunchKernelGGL(kern, dim3(grid), dim3(C::BLK), lds, s, a);
+  hipLaunchKernelGGL(kern, dim3(grid), dim3(64), lds, s, a);
   return hipGetLastError();
 }
 
@@ -132,7 +131,6 @@ hipError_t launch_gradr(const GradArgs &a, int grid, int lds, hipStream_t s) {
 
 template <int LP, int LA, int LB>
 GradInfo grad_info() {
-  using C = GradCfg<LP, LA, LB>;
   GradInfo g;
   if constexpr (GReg<LP, LA, LB>::OK) {
     g.tpb = 1;
@@ -141,11 +139,11 @@ GradInfo grad_info() {
     g.wpb = 1;
     g.gfn = &launch_gradr<LP, LA, LB>;
   } else {
-    g.tpb = C::TPB;
-    g.team = C::TEAM;
-    g.ppw = C::TPB;
-    g.wpb = C::BLK / 64;
-    g.gfn = &launch_grad<LP, LA, LB>;
+    g.tpb = 1;
+    g.team = GEng<LP, LA, LB>::TEAM;
+    g.ppw = 1;
+    g.wpb = 1;
+    g.gfn = &launch_grade<LP, LA, LB>;
   }
   return g;
 }

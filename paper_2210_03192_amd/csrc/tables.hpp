@@ -168,7 +168,9 @@ struct alignas(16) VO {
 //   GenSolid<l>:        solid-harmonic transform, CSR rows m = -l..l
 //   GenHrr<LA, LB>:     n-q HRR terms
 //   GenV<L>:            VRR1 stage items (operand offsets)
+//   GenY<LP, EA, EB>:   per-primitive digested ket of the derivative engine
 template <int LP, int EA, int EB> struct GenTab;
+template <int LP, int EA, int EB> struct GenY;
 template <int l> struct GenSolid;
 template <int LA, int LB> struct GenHrr;
 template <int L> struct GenV;
