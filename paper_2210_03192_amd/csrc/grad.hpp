@@ -707,9 +707,16 @@ struct GEng {
   }
 };
 
-// omega^{s,x}_e (j = 3 s + x; e given by its flat index relative to level EA)
+// binomial coefficients C(n, k) for n <= 5 (row n at 6 n)
+static __device__ const double k_binom6[36] = {
+    1, 0, 0, 0, 0, 0, 1, 1, 0, 0, 0, 0, 1, 2, 1, 0, 0, 0,
+    1, 3, 3, 1, 0, 0, 1, 4, 6, 4, 1, 0, 1, 5, 10, 10, 5, 1};
+
+// omega^{s,x}_e (j = 3 s + x; e given by its flat index relative to level EA):
+// a gather over b and i <= b' (b' = b, b + 1_x or b - 1_x) with |i| = |e| - l_a'
 template <int LA, int LB, int EA>
 __device__ __forceinline__ double grad_omega(int j, int ef, const double *GT, const double *PW) {
+  static_assert(LB + 1 <= 5, "binomial table");
   int lev = EA;
   while (offT(lev + 1) - offT(EA) <= ef) ++lev;
   const C3 e = cart(lev, ef - (offT(lev) - offT(EA)));
@@ -718,26 +725,29 @@ __device__ __forceinline__ double grad_omega(int j, int ef, const double *GT, co
   const int k = lev - las;  // |i|
   if (k < 0) return 0.0;
   const int dbx = x == 0, dby = x == 1, dbz = x == 2;
+  const int sg = s == 1 ? 1 : s == 3 ? -1 : 0;   // b' = b + sg 1_x
+  const int sa = s == 0 ? -1 : s == 2 ? 1 : 0;   // a = e - i + sa 1_x
   double v = 0.0;
+#pragma unroll
   for (int bi = 0; bi < ncart(LB); ++bi) {
+    constexpr int NBc = ncart(LB);
     const C3 b = cart(LB, bi);
-    const int bx = b[0], by = b[1], bz = b[2];
-    const int bxs = x == 0 ? bx : x == 1 ? by : bz;
+    const int bxs = x == 0 ? b[0] : x == 1 ? b[1] : b[2];
     if (s == 3 && bxs == 0) continue;
-    const int sg = s == 1 ? 1 : s == 3 ? -1 : 0;
-    const int b0 = bx + sg * dbx, b1 = by + sg * dby, b2 = bz + sg * dbz;
-    if (k > b0 + b1 + b2) continue;
+    const int b0 = b[0] + sg * dbx, b1 = b[1] + sg * dby, b2 = b[2] + sg * dbz;
     const double cb = s == 3 ? double(bxs) : 1.0;
-    for (int ic = 0; ic < ncart(k); ++ic) {
-      const C3 i = cart(k, ic);
-      if (i[0] > b0 || i[1] > b1 || i[2] > b2) continue;
-      const int sa = s == 0 ? -1 : s == 2 ? 1 : 0;
-      const int a0 = e[0] - i[0] + sa * dbx, a1 = e[1] - i[1] + sa * dby, a2 = e[2] - i[2] + sa * dbz;
-      if (a0 < 0 || a1 < 0 || a2 < 0) continue;
-      const double ca = s == 2 ? double(x == 0 ? a0 : x == 1 ? a1 : a2) : 1.0;
-      const double bn = double(binom(b0, i[0]) * binom(b1, i[1]) * binom(b2, i[2]));
-      v += ca * cb * bn * GT[cidx(a0, a1, a2) * ncart(LB) + bi] * PW[b0 - i[0]] *
-           PW[(LB + 2) + b1 - i[1]] * PW[2 * (LB + 2) + b2 - i[2]];
+    for (int ix = 0; ix <= b0 && ix <= k; ++ix) {
+      const int a0 = e[0] - ix + sa * dbx;
+      if (a0 < 0) continue;
+      for (int iy = 0; iy <= b1 && ix + iy <= k; ++iy) {
+        const int iz = k - ix - iy;
+        const int a1 = e[1] - iy + sa * dby, a2 = e[2] - iz + sa * dbz;
+        if (iz > b2 || a1 < 0 || a2 < 0) continue;
+        const double ca = s == 2 ? double(x == 0 ? a0 : x == 1 ? a1 : a2) : 1.0;
+        v += ca * cb * k_binom6[6 * b0 + ix] * k_binom6[6 * b1 + iy] * k_binom6[6 * b2 + iz] *
+             GT[cidx(a0, a1, a2) * NBc + bi] * PW[b0 - ix] * PW[(LB + 2) + b1 - iy] *
+             PW[2 * (LB + 2) + b2 - iz];
+      }
     }
   }
   return v;

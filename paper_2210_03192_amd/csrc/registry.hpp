@@ -32,6 +32,7 @@ struct GradInfo {
   int team = 0;       // LDS doubles per team before the per-atom array
   int ppw = 0;        // shell pairs per workgroup and grid step
   int wpb = 0;        // wavefronts per workgroup
+  int min_aux = 1;    // fewest aux shells per work item worth the per-pair set-up
   hipError_t (*gfn)(const GradArgs &, int, int, hipStream_t) = nullptr;  // (args, grid, lds)
 };
 
@@ -143,6 +144,7 @@ GradInfo grad_info() {
     g.team = GEng<LP, LA, LB>::TEAM;
     g.ppw = 1;
     g.wpb = 1;
+    g.min_aux = 8;
     g.gfn = &launch_grade<LP, LA, LB>;
   }
   return g;

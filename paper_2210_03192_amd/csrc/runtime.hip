@@ -835,13 +835,14 @@ int grad_slots(int ncu) { return ncu * GRAD_GRID_PER_CU * GRAD_MAX_TPB; }
 
 // Aux-shell subsets per shell pair of a gradient class: a class of few pairs
 // (or few pairs per wavefront) is split into pairs x subsets work items until
-// about four waves per SIMD are available (at most 16 subsets, no more than
-// the aux shells).
+// about four waves per SIMD are available (at most 16 subsets, each with at
+// least the class's min_aux aux shells, since every item redoes the pair's
+// set-up).
 int grad_split(const GradInfo &gi, int64_t npair, int np, int ncu) {
   const int64_t target = int64_t(ncu) * 16;
   auto waves = [&](int k) { return (npair + gi.ppw - 1) / gi.ppw * k * gi.wpb; };
   int n = 1;
-  while (n < 16 && 2 * n <= np && waves(n) < target) n *= 2;
+  while (n < 16 && 2 * n * gi.min_aux <= np && waves(n) < target) n *= 2;
   return n;
 }
 }  // namespace
