@@ -51,7 +51,16 @@ struct JArgs {
   int32_t pure;
   int32_t nsub;             // register engine: lanes per shell pair (power of two,
                             // 1..16), which split the aux shells between them
+  const double *arec;       // aux-shell records, aligned with psh (see AREC)
 };
+
+// Aux-shell record, one per position of the sorted aux list, built once per
+// call: centre, primitive offset, contraction degree, atom (as doubles, exact)
+// and d' = T^T d_P, the Cartesian image of the shell's fitting coefficients
+// (d_P itself for a Cartesian aux basis), so that an engine's aux loop reads
+// one contiguous, aligned record instead of a chain of dependent loads.
+enum { AR_CX = 0, AR_CY, AR_CZ, AR_PRIM, AR_K, AR_ATOM, AR_DQ };
+constexpr int AREC = AR_DQ + 28;  // doubles per record (d' of l <= 6)
 
 // LDS layout of one team (in doubles).  Regions are reused once dead:
 //   PRIM [0, PCH*REC)             primitive records of the current chunk (loop only)
@@ -690,7 +699,6 @@ __device__ __forceinline__ void orient_pair(const ShellsDev &orb, int &sa, int &
 template <int LP, int LA, int LB>
 __device__ __forceinline__ void jr_pair(const JArgs &a, bool valid, int sa, int sb, int sub) {
   using R = JReg<LP, LA, LB>;
-  using SH = GenSolid<LP>;
   constexpr int L = R::L, NE = R::NE, NCP = ncart(LP), NA = ncart(LA), NB = ncart(LB);
   if (!valid) return;
   orient_pair<LA, LB>(a.orb, sa, sb);
@@ -715,29 +723,14 @@ __device__ __forceinline__ void jr_pair(const JArgs &a, bool valid, int sa, int 
   // the nsub lanes of the pair take every nsub-th aux shell
   const int nsub = a.nsub;
   for (int ip = sub; ip < a.np; ip += nsub) {
-    const int sP = a.psh[ip];
-    const int Kc = a.aux.nprim[sP];
-    const double *ec = a.aux.exps + a.aux.prim_off[sP], *cc = a.aux.coefs + a.aux.prim_off[sP];
-    const int icn = a.aux.atom[sP];
-    const double C[3] = {a.xyz[3 * icn], a.xyz[3 * icn + 1], a.xyz[3 * icn + 2]};
-    const double *dP = a.d + a.aux_off[sP];
-    // d' = T^T d (pure) or d (Cartesian)
+    const double *rc = a.arec + int64_t(ip) * AREC;
+    const double C[3] = {rc[AR_CX], rc[AR_CY], rc[AR_CZ]};
+    const int64_t po = int64_t(rc[AR_PRIM]);
+    const int Kc = int(rc[AR_K]);
+    const double *ec = a.aux.exps + po, *cc = a.aux.coefs + po;
     double dq[NCP];
-    if (a.pure) {
-      static_for<NCP>([&](auto cc_) {
-        constexpr int c = decltype(cc_)::value;
-        double v = 0.0;
-        static_for<npure(LP)>([&](auto mc) {
-          constexpr int m = decltype(mc)::value;
-          constexpr double t = SH::dense[m * NCP + c];
-          if constexpr (t != 0.0) v += t * dP[m];
-        });
-        dq[c] = v;
-      });
-    } else {
 #pragma unroll
-      for (int c = 0; c < NCP; ++c) dq[c] = dP[c];
-    }
+    for (int c = 0; c < NCP; ++c) dq[c] = rc[AR_DQ + c];
     for (int ia = 0; ia < Ka; ++ia)
       for (int ib = 0; ib < Kb; ++ib) {
         const double za = ea[ia], zb = eb[ib];

@@ -81,6 +81,7 @@ __global__ void __launch_bounds__(TS > 64 ? TS : 64)
         a.nao = sg.nao;
         a.ao_base = sg.ao_base;
         a.psh = q.aux_sorted + sg.psh;
+        a.arec = q.a.arec + int64_t(sg.psh) * AREC;
         np = sg.np;
         if (sg.same) {
           int i = int((sqrt(8.0 * double(r) + 1.0) - 1.0) * 0.5);

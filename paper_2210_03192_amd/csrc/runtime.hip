@@ -481,7 +481,64 @@ int make_plan(const df3c_shells *aux, const df3c_shells *orb, JPlan &p) {
 
 size_t jplan_bytes(int64_t norb, int64_t naux) {
   return align256(sizeof(int) * 8) + align256(sizeof(int32_t) * norb) + align256(sizeof(int32_t) * naux) +
-         align256(sizeof(int64_t) * (norb + 1)) + align256(sizeof(int64_t) * (naux + 1));
+         align256(sizeof(int64_t) * (norb + 1)) + align256(sizeof(int64_t) * (naux + 1)) +
+         align256(sizeof(double) * AREC * naux);
+}
+
+extern "C++" {
+// d' = T^T d_P of one aux shell of l = LP into its record
+template <int LP>
+__device__ void aux_dq(const double *dP, int pure, double *dq) {
+  constexpr int NCP = ncart(LP);
+  if (pure) {
+    for (int c = 0; c < NCP; ++c) {
+      double v = 0.0;
+      for (int m = 0; m < npure(LP); ++m) v += GenSolid<LP>::dense[m * NCP + c] * dP[m];
+      dq[c] = v;
+    }
+  } else {
+    for (int c = 0; c < NCP; ++c) dq[c] = dP[c];
+  }
+}
+
+// aux-shell records of the sorted aux list (d may be null: no d')
+__global__ void k_aux_records(const int32_t *sorted, int64_t n, const int32_t *lsh, ShellsDev aux,
+                              const double *xyz, const int64_t *aux_off, const double *d,
+                              int32_t pure, double *rec) {
+  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
+       i += int64_t(gridDim.x) * blockDim.x) {
+    const int s = sorted[i];
+    const int at = aux.atom[s];
+    double *r = rec + i * AREC;
+    r[AR_CX] = xyz[3 * at];
+    r[AR_CY] = xyz[3 * at + 1];
+    r[AR_CZ] = xyz[3 * at + 2];
+    r[AR_PRIM] = double(aux.prim_off[s]);
+    r[AR_K] = double(aux.nprim[s]);
+    r[AR_ATOM] = double(at);
+    if (!d) continue;
+    const double *dP = d + aux_off[s];
+    switch (lsh[s]) {
+      case 0: aux_dq<0>(dP, pure, r + AR_DQ); break;
+      case 1: aux_dq<1>(dP, pure, r + AR_DQ); break;
+      case 2: aux_dq<2>(dP, pure, r + AR_DQ); break;
+      case 3: aux_dq<3>(dP, pure, r + AR_DQ); break;
+      case 4: aux_dq<4>(dP, pure, r + AR_DQ); break;
+      case 5: aux_dq<5>(dP, pure, r + AR_DQ); break;
+      default: aux_dq<6>(dP, pure, r + AR_DQ); break;
+    }
+  }
+}
+}  // extern "C++"
+
+hipError_t launch_aux_records(const int32_t *sorted, int64_t n, const df3c_shells *aux,
+                              const double *xyz, const int64_t *aux_off, const double *d,
+                              double *rec, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  const int grid = int(std::min<int64_t>((n + 255) / 256, 1024));
+  hipLaunchKernelGGL(k_aux_records, dim3(grid), dim3(256), 0, s, sorted, n, aux->l,
+                     dev_shells(aux), xyz, aux_off, d, aux->pure, rec);
+  return hipGetLastError();
 }
 }  // namespace
 
@@ -514,6 +571,8 @@ int df3c_coulomb_J(const double *xyz, int32_t natom, const df3c_shells *aux,
   int64_t *ao_off = reinterpret_cast<int64_t *>(w);
   w += align256(sizeof(int64_t) * (orb->nshell + 1));
   int64_t *aux_off = reinterpret_cast<int64_t *>(w);
+  w += align256(sizeof(int64_t) * (aux->nshell + 1));
+  double *arec = reinterpret_cast<double *>(w);
   if (hipMemcpyAsync(orb_sorted, p.orb_sorted.data(), sizeof(int32_t) * orb->nshell,
                      hipMemcpyHostToDevice, s) != hipSuccess ||
       hipMemcpyAsync(aux_sorted, p.aux_sorted.data(), sizeof(int32_t) * aux->nshell,
@@ -534,6 +593,8 @@ int df3c_coulomb_J(const double *xyz, int32_t natom, const df3c_shells *aux,
   const int64_t nJ = p.nao * p.nao;
   hipLaunchKernelGGL(k_zero_f64, dim3(int(std::min<int64_t>((nJ + 255) / 256, 4096))), dim3(256),
                      0, s, J, nJ);
+  if (launch_aux_records(aux_sorted, aux->nshell, aux, xyz, aux_off, d, arec, s) != hipSuccess)
+    return DF3C_E_HIP;
   JArgs a{};
   a.boys = ds->boys;
   a.xyz = xyz;
@@ -549,6 +610,7 @@ int df3c_coulomb_J(const double *xyz, int32_t natom, const df3c_shells *aux,
     const int np = p.aux_start[lp + 1] - p.aux_start[lp];
     if (!np) continue;
     a.psh = aux_sorted + p.aux_start[lp];
+    a.arec = arec + int64_t(p.aux_start[lp]) * AREC;
     a.np = np;
     for (int la = 0; la <= DF3C_LMAX_ORB; ++la)
       for (int lb = 0; lb <= la; ++lb) {
@@ -974,7 +1036,7 @@ size_t bplan_bytes(int64_t norb, int64_t naux, int64_t nmol) {
   return align256(sizeof(int) * 8) + align256(sizeof(int32_t) * norb) +
          align256(sizeof(int32_t) * naux) + align256(sizeof(int64_t) * (norb + 1)) +
          align256(sizeof(int64_t) * (naux + 1)) + align256(sizeof(JSeg) * nmol * NCLS) +
-         align256(sizeof(unsigned long long) * NCLS);
+         align256(sizeof(unsigned long long) * NCLS) + align256(sizeof(double) * AREC * naux);
 }
 
 int make_bplan(const df3c_shells *aux, const df3c_shells *orb, int nmol, const int32_t *mo,
@@ -1146,6 +1208,8 @@ int df3c_coulomb_J_batched(const double *xyz, int32_t natom, const df3c_shells *
   JSeg *segd = reinterpret_cast<JSeg *>(w);
   w += align256(sizeof(JSeg) * nmol * NCLS);
   unsigned long long *ctr = reinterpret_cast<unsigned long long *>(w);
+  w += align256(sizeof(unsigned long long) * NCLS);
+  double *arec = reinterpret_cast<double *>(w);
   if ((!p.orb_sorted.empty() &&
        hipMemcpyAsync(orb_sorted, p.orb_sorted.data(), sizeof(int32_t) * p.orb_sorted.size(),
                       hipMemcpyHostToDevice, s) != hipSuccess) ||
@@ -1192,9 +1256,14 @@ int df3c_coulomb_J_batched(const double *xyz, int32_t natom, const df3c_shells *
     return reg_split(g_cls[lp][la][lb], p.cls_items[c], np_max, ds->ncu);
   };
 
+  base.arec = arec;
+
   auto enqueue = [&]() -> int {
     hipLaunchKernelGGL(k_zero_f64, dim3(int(std::min<int64_t>((p.jtotal + 255) / 256, 4096))),
                        dim3(256), 0, s, J, p.jtotal);
+    if (launch_aux_records(aux_sorted, int64_t(p.aux_sorted.size()), aux, xyz, aux_off, d, arec,
+                           s) != hipSuccess)
+      return DF3C_E_HIP;
     if (flags & DF3C_SCHED_PERSISTENT) {
       hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(256), 0, s, reinterpret_cast<int *>(ctr),
                          2 * NCLS, 0);
@@ -1233,6 +1302,7 @@ int df3c_coulomb_J_batched(const double *xyz, int32_t natom, const df3c_shells *
             a.nb = sg.nb;
             a.same = sg.same;
             a.psh = aux_sorted + sg.psh;
+            a.arec = arec + int64_t(sg.psh) * AREC;
             a.np = sg.np;
             a.J = J + sg.jbase;
             a.nao = sg.nao;
