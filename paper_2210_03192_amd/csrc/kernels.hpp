@@ -129,6 +129,50 @@ struct JReg {
   static constexpr bool OK = L <= 4 && COST <= 160;
 };
 
+template <class G>
+struct MTiles {
+  static constexpr int nr(int k) { return (ncart(k) + 15) / 16; }
+  static constexpr int nc(int k) { return (G::nek(k) + 15) / 16; }
+  static constexpr int count() {
+    int n = 0;
+    for (int k = 0; k <= G::LP; ++k)
+      if (G::nek(k) > 0) n += nr(k) * nc(k);
+    return n;
+  }
+  static constexpr int N = count();
+  static constexpr int field(int t, int which) {
+    for (int k = 0; k <= G::LP; ++k) {
+      if (G::nek(k) == 0) continue;
+      const int n = nr(k) * nc(k);
+      if (t < n) return which == 0 ? k : which == 1 ? 16 * (t / nc(k)) : 16 * (t % nc(k));
+      t -= n;
+    }
+    return -1;
+  }
+  static constexpr int moff(int k) {
+    int o = 0;
+    for (int q = 0; q < k; ++q) o += ncart(q) * G::nek(q);
+    return o;
+  }
+  static constexpr int NM = moff(G::LP + 1);
+};
+
+// LDS layout of one J-engine team (doubles):
+//   PRIM [0, PCH*REC)    records [PS_N][T][W][sW][H] of the current chunk
+//   DP   [.., +PCH*NCP)  d' of the aux shell of each primitive of the chunk
+//   MJ   [0, NM)         M after the aux loop (over the dead PRIM / DP)
+//   XD   [.., +NE)       X_e for the HRR
+template <int LP, int LA, int LB, int PCH>
+struct JELayout {
+  using G = Geo<LP, LA, LA + LB>;
+  static constexpr int HU = PS_N + G::NV1 + G::NSW;
+  static constexpr int REC = HU + G::NSW;
+  static constexpr int DP = PCH * REC;
+  static constexpr int MJ = 0;
+  static constexpr int XD = imax(DP + PCH * G::NCP, MTiles<G>::NM);
+  static constexpr int TOTAL = XD + G::NE;
+};
+
 template <int LP, int LA, int LB>
 struct Cfg {
   using G = Geo<LP, LA, LA + LB>;
@@ -149,7 +193,12 @@ struct Cfg {
   // engine with whole-wave teams (at least one wave per shell pair)
   static constexpr bool JREG = JReg<LP, LA, LB>::OK;
   static constexpr int TSJ = JREG ? 1 : TS >= 64 ? TS : 64;
-  static constexpr int PCHJ = JREG ? 1 : 4;
+  // J engine: 16 primitive triplets per chunk where the team's LDS stays
+  // within 48 kB, else 8, else 4
+  static constexpr int PCHJ = JREG ? 1
+                              : JELayout<LP, LA, LB, 16>::TOTAL * 8 <= 48 * 1024 ? 16
+                              : JELayout<LP, LA, LB, 8>::TOTAL * 8 <= 48 * 1024  ? 8
+                                                                                  : 4;
   static constexpr int BLKJ = TSJ > 64 ? TSJ : 64;
   static constexpr int WPEJ = JREG ? DF3C_MIN_WAVES_JREG : TSJ >= 128 ? DF3C_MIN_WAVES_BIG
                                                                     : DF3C_MIN_WAVES_WAVE;
@@ -879,54 +928,11 @@ __device__ __forceinline__ void jr_pair(const JArgs &a, bool valid, int sa, int 
 // tiles) and forms X_e = sum_u e!/(e-u)! M_{u,e-u} once; one HRR of X gives the
 // J block.  No per-triplet CVRR2 combination, ket transform or digestion remains.
 // ---------------------------------------------------------------------------
-template <class G>
-struct MTiles {
-  static constexpr int nr(int k) { return (ncart(k) + 15) / 16; }
-  static constexpr int nc(int k) { return (G::nek(k) + 15) / 16; }
-  static constexpr int count() {
-    int n = 0;
-    for (int k = 0; k <= G::LP; ++k)
-      if (G::nek(k) > 0) n += nr(k) * nc(k);
-    return n;
-  }
-  static constexpr int N = count();
-  static constexpr int field(int t, int which) {
-    for (int k = 0; k <= G::LP; ++k) {
-      if (G::nek(k) == 0) continue;
-      const int n = nr(k) * nc(k);
-      if (t < n) return which == 0 ? k : which == 1 ? 16 * (t / nc(k)) : 16 * (t % nc(k));
-      t -= n;
-    }
-    return -1;
-  }
-  static constexpr int moff(int k) {
-    int o = 0;
-    for (int q = 0; q < k; ++q) o += ncart(q) * G::nek(q);
-    return o;
-  }
-  static constexpr int NM = moff(G::LP + 1);
-};
-
-// LDS layout of one J-engine team (doubles):
-//   PRIM [0, PCH*REC)    records [PS_N][T][W][sW][H] of the current chunk
-//   DP   [.., +PCH*NCP)  d' of the aux shell of each primitive of the chunk
-//   MJ   [0, NM)         M after the aux loop (over the dead PRIM / DP)
-//   XD   [.., +NE)       X_e for the HRR
-template <int LP, int LA, int LB, int PCH>
-struct JELayout {
-  using G = Geo<LP, LA, LA + LB>;
-  static constexpr int HU = PS_N + G::NV1 + G::NSW;
-  static constexpr int REC = HU + G::NSW;
-  static constexpr int DP = PCH * REC;
-  static constexpr int MJ = 0;
-  static constexpr int XD = imax(DP + PCH * G::NCP, MTiles<G>::NM);
-  static constexpr int TOTAL = XD + G::NE;
-};
-
-// classes whose J runs on the engine: whole-wave teams with chunks of 4
+// classes whose J runs on the engine: whole-wave teams, chunks of 4, 8 or 16
+// primitive triplets (groups of 4 = the K extent of one MFMA)
 template <int LP, int LA, int LB, int TS, int PCH>
 constexpr bool use_jengine() {
-  return TS % 64 == 0 && PCH == 4;
+  return TS % 64 == 0 && PCH % 4 == 0 && PCH <= 16;
 }
 
 template <int LP, int LA, int LB, int TS, int PCH>
@@ -938,7 +944,7 @@ __device__ __forceinline__ void jeng_pair(const JArgs &a, double *S, int tid, bo
   using SH = GenSolid<LP>;
   using TB = GenTab<LP, G::EA, G::EB>;
   static_assert(TB::NM == MT::NM, "generated J-engine tables out of date");
-  static_assert(TS % 64 == 0 && PCH == 4, "the J engine runs whole-wave teams");
+  static_assert(use_jengine<LP, LA, LB, TS, PCH>(), "the J engine runs whole-wave teams");
   constexpr int REC = JE::REC;
   constexpr int NA = ncart(LA), NB = ncart(LB);
   constexpr int NWV = TS / 64;
@@ -1041,22 +1047,28 @@ __device__ __forceinline__ void jeng_pair(const JArgs &a, double *S, int tid, bo
       prims[pp * REC + JE::HU + u] = h;
     }
     team_sync();
-    // M += H V on the matrix cores; lane (pc, cl): primitive pc, row / column cl
+    // M += H V on the matrix cores, one MFMA per tile and group of 4
+    // primitives; lane (pc, cl): primitive 4 g + pc of group g, row / column cl
     const int wl = lt >> 6, pc = (lt & 63) >> 4, cl = lt & 15;
-    const double *Rl = prims + pc * REC + cl;
-    const bool pv = pc < npc;
-    static_for<NWV>([&](auto wc) {
-      constexpr int W = decltype(wc)::value;
-      if (wl == W) {
-        static_for<NTW>([&](auto jc) {
-          constexpr int j = decltype(jc)::value;
-          constexpr int t = j * NWV + W;
-          if constexpr (t < MT::N) {
-            constexpr int k = MT::field(t, 0), r0 = MT::field(t, 1), c0 = MT::field(t, 2);
-            constexpr int nr = ncart(k) - r0, nc = G::nek(k) - c0;
-            const double av = (pv && cl < nr) ? Rl[JE::HU + offT(k) + r0] : 0.0;
-            const double bv = (pv && cl < nc) ? Rl[PS_N + offT(G::emin(k)) + c0] : 0.0;
-            macc[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, macc[j], 0, 0, 0);
+    static_for<PCH / 4>([&](auto gc) {
+      constexpr int g4 = decltype(gc)::value;
+      if (4 * g4 < npc) {
+        const double *Rl = prims + (4 * g4 + pc) * REC + cl;
+        const bool pv = 4 * g4 + pc < npc;
+        static_for<NWV>([&](auto wc) {
+          constexpr int W = decltype(wc)::value;
+          if (wl == W) {
+            static_for<NTW>([&](auto jc) {
+              constexpr int j = decltype(jc)::value;
+              constexpr int t = j * NWV + W;
+              if constexpr (t < MT::N) {
+                constexpr int k = MT::field(t, 0), r0 = MT::field(t, 1), c0 = MT::field(t, 2);
+                constexpr int nr = ncart(k) - r0, nc = G::nek(k) - c0;
+                const double av = (pv && cl < nr) ? Rl[JE::HU + offT(k) + r0] : 0.0;
+                const double bv = (pv && cl < nc) ? Rl[PS_N + offT(G::emin(k)) + c0] : 0.0;
+                macc[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, macc[j], 0, 0, 0);
+              }
+            });
           }
         });
       }
