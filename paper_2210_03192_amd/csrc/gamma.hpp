@@ -8,10 +8,10 @@
 //   G_u = sum_{e >= u} w_e e!/(e-u)! [e-u 0|0]^(LP),
 //   y_c += sum_{u <= c} C(c,u) sW_{|u|}[c-u] G_u,      gamma_m = sum_c T_mc y_c.
 //
-// Work items write partial gammas that one reduction per class adds in a fixed
-// order (no atomics, bitwise reproducible): on the register engine an item is
-// (range of shell pairs, subset of the aux shells), on the per-triplet
-// pipeline (aux shell, chunk of consecutive shell pairs).
+// Work items (range of shell pairs, subset of the aux shells) write partial
+// gammas that one reduction per class adds in a fixed order (no atomics,
+// bitwise reproducible); the register engine serves the classes whose
+// intermediates fit a lane, the gamma engine the others.
 #pragma once
 #include "kernels.hpp"
 
@@ -29,16 +29,13 @@ struct GamArgs {
   const double *D;            // [nao][nao]
   int64_t nao, npair;
   int32_t pure;
-  int32_t nchunk;             // chunks of pairs per aux shell
-  int64_t chunk;              // pairs per chunk
-  // register engine: items (pair range r, aux subset s); subset s holds the
-  // aux shells s, s + nsplit, ... (at most nps of them), range r the pairs
+  // items (pair range r, aux subset s); subset s holds the aux shells s,
+  // s + nsplit, ... (at most nps of them), range r the pairs
   // [r prange, (r + 1) prange)
   int32_t nsplit, nps;
   int64_t prange;
   int64_t nrange;
-  double *partial;            // per-triplet pipeline: [np * nchunk][np_out];
-                              // register engine: [nrange][nsplit][nps][np_out]
+  double *partial;            // [nrange][nsplit][nps][np_out]
 };
 
 // pair q of the class -> (sa, sb)
@@ -285,109 +282,208 @@ __global__ void __launch_bounds__(64) k_gam_r(GamArgs g) {
 }
 
 // ---------------------------------------------------------------------------
-// Per-triplet pipeline (all other classes): one team per item; per pair the
-// block (P|ab) is formed in LDS (triplet_to_e0P + hrr_block) and contracted
-// with D~ by the lanes owning the ket components.
+// Gamma engine (classes beyond the register engine): one wavefront per item
+// (range of shell pairs, subset of the aux shells), the pairs of the range in
+// turn.  Per pair the HRR is transposed onto D~ once (w_e, lanes over e); the
+// pair's primitive triplets over the subset's aux shells are cut into chunks
+// that span shells, and per primitive
+//   G_u = sum_{e >= u} w_e e!/(e-u)! [e-u 0|0]^(LP),
+//   y_c = sum_{u <= c} C(c,u) sW_{|u|}[c-u] G_u,
+// which the lanes of the components c add to the accumulator of the
+// primitive's aux shell in primitive order.  The ket transform runs once per
+// item, on the accumulators.
 // ---------------------------------------------------------------------------
-template <int LP, int LA, int LB, int TS, int PCH>
-struct GamLayout {
-  static constexpr int DT = Layout<LP, LA, LB, PCH>::TOTAL;   // D~ of the current pair
-  static constexpr int TOTAL = (DT + ncart(LA) * ncart(LB)) | 1;
-  static constexpr int BYTES_WG = ((TS > 64 ? TS : 64) / TS) * TOTAL * 8;
-  static_assert(BYTES_WG <= 160 * 1024, "gamma layout does not fit the LDS of a CU");
+template <int LP, int LA, int LB>
+struct GamE {
+  using G = Geo<LP, LA, LA + LB>;
+  static constexpr int NA = ncart(LA), NB = ncart(LB), NCP = ncart(LP), NE = G::NE;
+  static constexpr int NU = offT(imin(LP, G::EB) + 1);
+  static constexpr int HU = PS_N + G::NV1 + G::NSW;   // record: scalars, VRR1, sW, G
+  static constexpr int REC = HU + G::NSW;
+  static constexpr int PCH = REC <= 200 ? 16 : 8;
+  static constexpr int SL = PCH * REC;                // aux-shell slot of each primitive
+  static constexpr int YC = SL + PCH;                 // y [PCH][NCP]
+  static constexpr int W = YC + PCH * NCP;            // w_e of the pair
+  static constexpr int DT = W + NE;                   // D~ of the pair [NA][NB]
+  static constexpr int PW = DT + NA * NB;             // AB powers [3][LB + 1]
+  static constexpr int TEAM = PW + 3 * (LB + 1);      // doubles before the accumulators
 };
 
-template <int LP, int LA, int LB, int TS, int PCH>
-__global__ void __launch_bounds__(TS > 64 ? TS : 64)
-    __attribute__((amdgpu_waves_per_eu(Cfg<LP, LA, LB>::WPE))) k_gam_p(GamArgs g) {
-  using G = Geo<LP, LA, LA + LB>;
-  using LY = Layout<LP, LA, LB, PCH>;
-  using GL = GamLayout<LP, LA, LB, TS, PCH>;
-  constexpr int BLK = TS > 64 ? TS : 64;
-  constexpr int TPB = BLK / TS;
-  constexpr int NA = ncart(LA), NB = ncart(LB);
-  constexpr bool MF = (TS % 64 == 0) && PCH % 4 == 0;
-  constexpr int NQ = MF ? 1 : (G::NPI + TS - 1) / TS;
-  constexpr int NOUT = imax(npure(LP), ncart(LP));
-  constexpr int NM = (NOUT + TS - 1) / TS;
-  extern __shared__ double smem[];
-  const int team = threadIdx.x / TS, tid = threadIdx.x % TS;
-  double *S = smem + team * GL::TOTAL;
-  double *DT = S + GL::DT;
-  const double *STG = S + LY::STG;
-  const int np_out = g.pure ? npure(LP) : ncart(LP);
-  int slot[NQ];
-  if constexpr (!MF) make_slots<LP, LA, LB, TS>(slot, tid);
-  const int64_t items = int64_t(g.np) * g.nchunk;
-
-  for (int64_t base = int64_t(blockIdx.x) * TPB; base < items; base += int64_t(gridDim.x) * TPB) {
-    const int64_t item = base + team;
-    const bool ivalid = item < items;
-    const int ip = ivalid ? int(item / g.nchunk) : 0;
-    const int64_t ch = ivalid ? item - int64_t(ip) * g.nchunk : 0;
-    const int sP = g.psh[ip];
-    const int64_t q0 = ch * g.chunk;
-    const int64_t q1 = ivalid ? (q0 + g.chunk < g.npair ? q0 + g.chunk : g.npair) : q0;
-    const int icn = g.aux.atom[sP];
-    const double Cr[3] = {g.xyz[3 * icn], g.xyz[3 * icn + 1], g.xyz[3 * icn + 2]};
-    const int64_t oc = g.aux.prim_off[sP];
-    double acc[NM];
+// w_e = sum_{a,b} D~_ab sum_{i <= b} [a + i = e] C(b,i) AB^{b-i} (e by its flat
+// index relative to level LA): the HRR of the class transposed onto D~
+template <int LA, int LB>
+__device__ __forceinline__ double gam_w(int ef, const double *DT, const double *PW) {
+  static_assert(LB <= 5, "binomial table");
+  int lev = LA;
+  while (offT(lev + 1) - offT(LA) <= ef) ++lev;
+  const C3 e = cart(lev, ef - (offT(lev) - offT(LA)));
+  const int k = lev - LA;  // |i|
+  double v = 0.0;
 #pragma unroll
-    for (int k = 0; k < NM; ++k) acc[k] = 0.0;
-    // the same number of steps for every team of the workgroup (barriers)
-    for (int64_t qi = 0; qi < g.chunk; ++qi) {
-      const int64_t q = q0 + qi;
-      const bool valid = q < q1;
-      int sa = 0, sb = 0;
-      if (valid) {
-        gam_pair(g, q, sa, sb);
-        orient_pair<LA, LB>(g.orb, sa, sb);
+  for (int bi = 0; bi < ncart(LB); ++bi) {
+    const C3 b = cart(LB, bi);
+    for (int ix = 0; ix <= b[0] && ix <= k; ++ix) {
+      const int a0 = e[0] - ix;
+      if (a0 < 0) continue;
+      for (int iy = 0; iy <= b[1] && ix + iy <= k; ++iy) {
+        const int iz = k - ix - iy;
+        const int a1 = e[1] - iy, a2 = e[2] - iz;
+        if (iz > b[2] || a1 < 0 || a2 < 0) continue;
+        v += k_binom6[6 * b[0] + ix] * k_binom6[6 * b[1] + iy] * k_binom6[6 * b[2] + iz] *
+             DT[cidx(a0, a1, a2) * ncart(LB) + bi] * PW[b[0] - ix] * PW[(LB + 1) + b[1] - iy] *
+             PW[2 * (LB + 1) + b[2] - iz];
       }
-      const int Ka = valid ? g.orb.nprim[sa] : 0, Kb = valid ? g.orb.nprim[sb] : 0;
-      const int Kc = valid ? g.aux.nprim[sP] : 0;
-      const int64_t oa = valid ? g.orb.prim_off[sa] : 0, ob = valid ? g.orb.prim_off[sb] : 0;
-      double Ar[3] = {0, 0, 0}, Br[3] = {0, 0, 0};
-      if (valid) {
+    }
+  }
+  return v;
+}
+
+template <int LP, int LA, int LB>
+__global__ void __launch_bounds__(64)
+    __attribute__((amdgpu_waves_per_eu(DF3C_MIN_WAVES_WAVE))) k_gam_e(GamArgs g) {
+  using E = GamE<LP, LA, LB>;
+  using G = typename E::G;
+  using SH = GenSolid<LP>;
+  using TB = GenTab<LP, LA, LA + LB>;
+  constexpr int TS = 64, PCH = E::PCH, REC = E::REC, NU = E::NU, NE = E::NE;
+  constexpr int NA = E::NA, NB = E::NB, NCP = E::NCP;
+  extern __shared__ double smem[];
+  double *prims = smem, *SLK = smem + E::SL, *Yc = smem + E::YC, *Wv = smem + E::W;
+  double *DT = smem + E::DT, *PW = smem + E::PW, *acc = smem + E::TEAM;  // acc [nps][NCP]
+  const int tid = threadIdx.x;
+  for (int64_t item = blockIdx.x; item < g.nrange * g.nsplit; item += gridDim.x) {
+    const int64_t r = item / g.nsplit;
+    const int sub = int(item - r * g.nsplit);
+    for (int x = tid; x < g.nps * NCP; x += TS) acc[x] = 0.0;
+    const int64_t qend = (r + 1) * g.prange < g.npair ? (r + 1) * g.prange : g.npair;
+    for (int64_t q = r * g.prange; q < qend; ++q) {
+      int sa, sb;
+      gam_pair(g, q, sa, sb);
+      orient_pair<LA, LB>(g.orb, sa, sb);
+      const int Ka = g.orb.nprim[sa], Kb = g.orb.nprim[sb];
+      const int64_t oa = g.orb.prim_off[sa], ob = g.orb.prim_off[sb];
+      double Ar[3], Br[3];
+      {
         const int ia = g.orb.atom[sa], ib = g.orb.atom[sb];
         for (int x = 0; x < 3; ++x) {
           Ar[x] = g.xyz[3 * ia + x];
           Br[x] = g.xyz[3 * ib + x];
         }
+      }
+      const double AB2 = (Ar[0] - Br[0]) * (Ar[0] - Br[0]) + (Ar[1] - Br[1]) * (Ar[1] - Br[1]) +
+                         (Ar[2] - Br[2]) * (Ar[2] - Br[2]);
+      {
         const int64_t ra = g.ao_off[sa], rb = g.ao_off[sb];
         for (int ab = tid; ab < NA * NB; ab += TS) {
-          const int ia2 = ab / NB, ib2 = ab - ia2 * NB;
-          double v = g.D[(ra + ia2) * g.nao + rb + ib2];
-          if (sa != sb) v += g.D[(rb + ib2) * g.nao + ra + ia2];
+          const int ia = ab / NB, ib = ab - ia * NB;
+          double v = g.D[(ra + ia) * g.nao + rb + ib];
+          if (sa != sb) v += g.D[(rb + ib) * g.nao + ra + ia];
           DT[ab] = v;
         }
-      }
-      const int npmax = TS >= 64 ? Ka * Kb * Kc : wave_max(Ka * Kb * Kc);
-      triplet_to_e0P<LP, LA, LB, TS, PCH>(g.boys, S, tid, slot, npmax, Ar, Br, Cr, Ka,
-                                          g.orb.exps + oa, g.orb.coefs + oa, Kb, g.orb.exps + ob,
-                                          g.orb.coefs + ob, Kc, g.aux.exps + oc,
-                                          g.aux.coefs + oc, g.pure);
-      hrr_block<LP, LA, LB, TS, PCH>(S, tid, Ar, Br, np_out, false);
-      team_sync();
-      if (valid) {
-#pragma unroll
-        for (int k = 0; k < NM; ++k) {
-          const int m = tid + k * TS;
-          if (m < np_out) {
-            double v = acc[k];
-            for (int ab = 0; ab < NA * NB; ++ab) v += DT[ab] * STG[m * NA * NB + ab];
-            acc[k] = v;
+        if (tid < 3) {
+          const double d = Ar[tid] - Br[tid];
+          double p = 1.0;
+          for (int n = 0; n < LB + 1; ++n) {
+            PW[tid * (LB + 1) + n] = p;
+            p *= d;
           }
         }
       }
       team_sync();
-    }
-    if (ivalid) {
+      for (int e = tid; e < NE; e += TS) Wv[e] = gam_w<LA, LB>(e, DT, PW);
+      team_sync();
+      const int Kab = Ka * Kb;
+      // the pair's primitive triplets over the subset's aux shells, in
+      // (aux shell, p) order, in chunks of PCH; the cursor is uniform
+      auto shell_prims = [&](int ip) { return ip < g.np ? Kab * g.aux.nprim[g.psh[ip]] : 0; };
+      int cip = sub, cp = 0, cK = shell_prims(sub);
+      while (cip < g.np && cK == 0) cK = shell_prims(cip += g.nsplit);
+      while (cip < g.np) {
+        int sl_ip[PCH], sl_p[PCH];
+        int npc = 0;
 #pragma unroll
-      for (int k = 0; k < NM; ++k) {
-        const int m = tid + k * TS;
-        if (m < np_out) g.partial[item * np_out + m] = acc[k];
+        for (int pp = 0; pp < PCH; ++pp) {
+          sl_ip[pp] = cip;
+          sl_p[pp] = cp;
+          if (cip < g.np) {
+            npc = pp + 1;
+            if (++cp == cK) {
+              cp = 0;
+              cK = shell_prims(cip += g.nsplit);
+              while (cip < g.np && cK == 0) cK = shell_prims(cip += g.nsplit);
+            }
+          }
+        }
+        int lt = tid;
+        __asm__ volatile("" : "+v"(lt));
+        if (lt < npc) {
+          int ip = sl_ip[0], p = sl_p[0];
+#pragma unroll
+          for (int qq = 1; qq < PCH; ++qq)
+            if (lt == qq) {
+              ip = sl_ip[qq];
+              p = sl_p[qq];
+            }
+          const int sP = g.psh[ip];
+          const int Kc = g.aux.nprim[sP];
+          const int64_t oc = g.aux.prim_off[sP];
+          const int atC = g.aux.atom[sP];
+          const double Cr[3] = {g.xyz[3 * atC], g.xyz[3 * atC + 1], g.xyz[3 * atC + 2]};
+          setup_prim<G, 0>(g.boys, prims + lt * REC, p, Kb, Kc, Ar, Br, Cr, AB2, g.orb.exps + oa,
+                           g.orb.coefs + oa, g.orb.exps + ob, g.orb.coefs + ob,
+                           g.aux.exps + oc, g.aux.coefs + oc);
+          SLK[lt] = double((ip - sub) / g.nsplit);  // the shell's place in the subset
+        }
+        team_sync();
+        vrr1<G, TS, PCH, REC>(prims, npc, lt);
+        // G_u per primitive
+        for (int it = lt; it < npc * NU; it += TS) {
+          const int pp = it / NU, u = it - pp * NU;
+          const double *R = prims + pp * REC;
+          double v = 0.0;
+#pragma unroll 4
+          for (int qq = TB::g_start[u]; qq < TB::g_start[u + 1]; ++qq) {
+            const uint32_t t = TB::g_t[qq];
+            v += double(t >> 16) * Wv[(t >> 8) & 0xffu] * R[PS_N + (t & 0xffu)];
+          }
+          prims[pp * REC + E::HU + u] = v;
+        }
+        team_sync();
+        // y_c per primitive
+        for (int it = lt; it < npc * NCP; it += TS) {
+          const int pp = it / NCP, c = it - pp * NCP;
+          const double *R = prims + pp * REC;
+          double v = 0.0;
+#pragma unroll 4
+          for (int qq = SH::jy_start[c]; qq < SH::jy_start[c + 1]; ++qq) {
+            const uint32_t t = SH::jy_t[qq];
+            const int u = int(t & 0xffu);
+            if (u < NU) v += double(t >> 16) * R[PS_N + G::NV1 + ((t >> 8) & 0xffu)] * R[E::HU + u];
+          }
+          Yc[it] = v;
+        }
+        team_sync();
+        // lanes of the components add the chunk to the shells' accumulators in order
+        if (lt < NCP)
+          for (int pp = 0; pp < npc; ++pp) acc[int(SLK[pp]) * NCP + lt] += Yc[pp * NCP + lt];
+        team_sync();
       }
     }
+    // ket transform of the accumulators: the item's partial
+    const int nout = g.pure ? npure(LP) : NCP;
+    double *out = g.partial + item * g.nps * nout;
+    for (int x = tid; x < g.nps * nout; x += TS) {
+      const int ks = x / nout, m = x - ks * nout;
+      double v;
+      if (g.pure) {
+        v = 0.0;
+        for (int c = 0; c < NCP; ++c) v += SH::dense[m * NCP + c] * acc[ks * NCP + c];
+      } else {
+        v = acc[ks * NCP + m];
+      }
+      out[x] = v;
+    }
+    team_sync();
   }
 }
 

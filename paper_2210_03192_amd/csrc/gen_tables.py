@@ -232,6 +232,45 @@ def jx_terms(g):
     return start, mi, co
 
 
+def gg_terms(g):
+    """Per u (flat index offT(|u|) + cidx(u), |u| <= min(LP, EB)): the terms
+    (e!/(e-u)!, target index of e relative to level EA, VRR1 index of e - u) of
+    G_u = sum_{e >= u} w_e e!/(e-u)! [e-u 0|0]^(LP) over the targets e of the
+    class (the adjoint digestion engine)."""
+    start, co, ei, vi = [], [], [], []
+    targets = [e for lev in range(g.EA, g.EB + 1) for e in carts(lev)]
+    for k in range(min(g.LP, g.EB) + 1):
+        for u in carts(k):
+            start.append(len(co))
+            for t, e in enumerate(targets):
+                if all(e[i] >= u[i] for i in range(3)):
+                    r = tuple(e[i] - u[i] for i in range(3))
+                    co.append(math.perm(e[0], u[0]) * math.perm(e[1], u[1]) * math.perm(e[2], u[2]))
+                    ei.append(t)
+                    vi.append(offT(sum(r)) + cidx(r))
+    start.append(len(co))
+    return start, co, ei, vi
+
+
+def jy_terms(LP):
+    """The terms of jh_terms regrouped per c: (u index, sW index, C(c, u)) of
+    y_c = sum_{u <= c} C(c,u) sW_{|u|}[c-u] G_u."""
+    hs, hc, hw, hb = jh_terms(LP)
+    per_c = [[] for _ in range(ncart(LP))]
+    for u in range(len(hs) - 1):
+        for q in range(hs[u], hs[u + 1]):
+            per_c[hc[q]].append((u, hw[q], hb[q]))
+    start, uu, ww, bb = [], [], [], []
+    for lst in per_c:
+        start.append(len(uu))
+        for u, w, b in lst:
+            uu.append(u)
+            ww.append(w)
+            bb.append(b)
+    start.append(len(uu))
+    return start, uu, ww, bb
+
+
 def gy_terms(LP, EA, EB):
     """Per target e (levels EA..EB, flat order): the terms (e!/(e-u)!, H_u
     index offT(|u|) + cidx(u), VRR1 index offT(|e-u|) + cidx(e-u)) of the
@@ -442,6 +481,11 @@ def write(outdir):
             # one word per term: coefficient << 16 | index into M
             assert max(jm, default=0) < 65536 and max(jc, default=0) < 65536
             s.append(arr("uint32_t", "jx_mc", [(cc << 16) | mm for mm, cc in zip(jm, jc)]))
+            gs, gc, ge, gv = gg_terms(g)
+            s.append(arr("int16_t", "g_start", gs))
+            # one word per term: coefficient << 16 | target index << 8 | VRR1 index
+            assert max(ge, default=0) < 256 and max(gv, default=0) < 256 and max(gc, default=0) < 65536
+            s.append(arr("uint32_t", "g_t", [(c << 16) | (e << 8) | v for c, e, v in zip(gc, ge, gv)]))
             s.append("};\n")
         for (lp, EA, EB) in grad_geometries():
             if lp != LP:
@@ -478,6 +522,12 @@ def write(outdir):
         assert max(hc, default=0) < 256 and max(hw, default=0) < 256 and max(hb, default=0) < 65536
         s.append(arr("uint32_t", "jh_t", [(bb << 16) | (ww << 8) | cc
                                           for cc, ww, bb in zip(hc, hw, hb)]))
+        ys, yu, yw, yb = jy_terms(l)
+        s.append(arr("int16_t", "jy_start", ys))
+        # one word per term: binomial << 16 | sW index << 8 | u
+        assert max(yu, default=0) < 256 and max(yw, default=0) < 256
+        s.append(arr("uint32_t", "jy_t", [(bb << 16) | (ww << 8) | uu
+                                          for uu, ww, bb in zip(yu, yw, yb)]))
         s.append("};\n")
     for la in range(LMAX_ORB + 1):
         for lb in range(LMAX_ORB + 1):

@@ -707,11 +707,6 @@ struct GEng {
   }
 };
 
-// binomial coefficients C(n, k) for n <= 5 (row n at 6 n)
-static __device__ const double k_binom6[36] = {
-    1, 0, 0, 0, 0, 0, 1, 1, 0, 0, 0, 0, 1, 2, 1, 0, 0, 0,
-    1, 3, 3, 1, 0, 0, 1, 4, 6, 4, 1, 0, 1, 5, 10, 10, 5, 1};
-
 // omega^{s,x}_e (j = 3 s + x; e given by its flat index relative to level EA):
 // a gather over b and i <= b' (b' = b, b + 1_x or b - 1_x) with |i| = |e| - l_a'
 template <int LA, int LB, int EA>

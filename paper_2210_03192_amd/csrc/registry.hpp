@@ -18,8 +18,6 @@ struct ClassInfo {
   hipError_t (*jfn)(const JArgs &, int, hipStream_t) = nullptr;
   hipError_t (*jq)(const JQArgs &, int, hipStream_t) = nullptr;
   hipError_t (*gam)(const GamArgs &, int, hipStream_t) = nullptr;
-  int gam_reg = 0;    // gamma on the register engine (one lane per item)
-  int gam_ipw = 0;    // gamma items per workgroup and grid step
 };
 
 struct MetricInfo {
@@ -79,12 +77,14 @@ hipError_t launch_gam(const GamArgs &a, int grid, hipStream_t s) {
     const int lds = a.nps * (a.pure ? 2 * LP + 1 : (LP + 1) * (LP + 2) / 2) * 8;
     hipLaunchKernelGGL(kr, dim3(grid), dim3(64), lds, s, a);
   } else {
-    constexpr int lds = GamLayout<LP, LA, LB, C::TS, C::PCH>::BYTES_WG;
-    auto kern = k_gam_p<LP, LA, LB, C::TS, C::PCH>;
+    using E = GamE<LP, LA, LB>;
+    auto kern = k_gam_e<LP, LA, LB>;
     static const hipError_t attr = hipFuncSetAttribute(
-        reinterpret_cast<const void *>(kern), hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+        reinterpret_cast<const void *>(kern), hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
     if (attr != hipSuccess) return attr;
-    hipLaunchKernelGGL(kern, dim3(grid), dim3(C::BLK), lds, s, a);
+    const int lds = (E::TEAM + a.nps * E::NCP) * 8;
+    if (lds > 160 * 1024) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(64), lds, s, a);
   }
   return hipGetLastError();
 }
@@ -163,8 +163,6 @@ ClassInfo class_info() {
   c.jfn = &launch_J<LP, LA, LB>;
   c.jq = &launch_Jq<LP, LA, LB>;
   c.gam = &launch_gam<LP, LA, LB>;
-  c.gam_reg = C::JREG ? 1 : 0;
-  c.gam_ipw = C::JREG ? 64 : C::BLK / C::TS;
   return c;
 }
 

@@ -709,22 +709,20 @@ int df3c_coulomb_metric(const double *xyz, int32_t natom, const df3c_shells *aux
 // ------------------------------------------------------------ adjoint gamma
 namespace {
 // gamma work items aimed at per class: 4 wavefronts of register items per CU
-int64_t gam_target(int ncu) { return int64_t(ncu) * 4 * 64; }
-
-// Items of the register gamma engine for a class of npair shell pairs and np
-// aux shells with nout functions each: nsplit aux subsets (about 8 aux shells
-// per subset, so that a pair's set-up serves several shells; at most 4096
-// LDS doubles per item) times nrange ranges of pairs, about four wavefronts
-// per SIMD in all.
+// Items of the gamma engines for a class of npair shell pairs and np aux
+// shells with nacc accumulated components each: nsplit aux subsets (about 8
+// aux shells per subset, so that a pair's set-up serves several shells; at
+// most 4096 LDS accumulator doubles per item) times nrange ranges of pairs,
+// about four wavefronts per SIMD in all.
 struct GamRegPlan {
   int32_t nsplit, nps;
   int64_t prange, nrange;
   size_t partial_doubles(int nout) const { return size_t(nrange) * nsplit * nps * nout; }
 };
-GamRegPlan gam_reg_plan(int64_t npair, int np, int nout, int ncu) {
+GamRegPlan gam_reg_plan(int64_t npair, int np, int nacc, int ncu) {
   GamRegPlan g;
   const int64_t target = int64_t(ncu) * 16;
-  const int lo = int((int64_t(np) * nout + 4095) / 4096);
+  const int lo = int((int64_t(np) * nacc + 4095) / 4096);
   g.nsplit = std::max(lo, std::min(std::max(1, np / 8), 64));
   g.nps = (np + g.nsplit - 1) / g.nsplit;
   const int64_t rounds = (npair + 63) / 64;
@@ -747,26 +745,14 @@ __global__ void k_gam_reduce_r(const double *partial, int32_t np, int32_t nsplit
   }
 }
 
-// gamma[aux function] += sum over the chunks of the class's partials, in order
-__global__ void k_gam_reduce(const double *partial, int32_t np, int32_t nchunk, int32_t nout,
-                             const int32_t *psh, const int64_t *aux_off, double *gamma) {
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < np * nout; i += gridDim.x * blockDim.x) {
-    const int ip = i / nout, m = i - ip * nout;
-    double v = 0.0;
-    for (int c = 0; c < nchunk; ++c) v += partial[(int64_t(ip) * nchunk + c) * nout + m];
-    gamma[aux_off[psh[ip]] + m] += v;
-  }
-}
 }  // namespace
 
 size_t df3c_coulomb_gamma_workspace(const df3c_shells *aux, const df3c_shells *orb) {
   if (!aux || !orb || !aux->l_host || !orb->l_host) return 0;
   DevState *ds = nullptr;
   if (init_device(&ds)) return 0;
-  // per-triplet pipeline: (aux shell, chunk) items; register engine: the plan
-  // of every class it runs
-  const size_t items = size_t(gam_target(ds->ncu)) + size_t(aux->nshell);
-  size_t part = items * size_t(2 * DF3C_LMAX_AUX + 1);
+  // the partials of the largest class plan
+  size_t part = 1;
   int64_t no[DF3C_LMAX_ORB + 1] = {}, na[DF3C_LMAX_AUX + 1] = {};
   for (int s = 0; s < orb->nshell; ++s)
     if (orb->l_host[s] >= 0 && orb->l_host[s] <= DF3C_LMAX_ORB) ++no[orb->l_host[s]];
@@ -775,10 +761,11 @@ size_t df3c_coulomb_gamma_workspace(const df3c_shells *aux, const df3c_shells *o
   for (int lp = 0; lp <= DF3C_LMAX_AUX; ++lp)
     for (int la = 0; la <= DF3C_LMAX_ORB; ++la)
       for (int lb = 0; lb <= la; ++lb) {
-        if (!na[lp] || !no[la] || !no[lb] || !g_cls[lp][la][lb].gam_reg) continue;
+        if (!na[lp] || !no[la] || !no[lb]) continue;
         const int64_t npair = la == lb ? no[la] * (no[la] + 1) / 2 : no[la] * no[lb];
         const int nout = aux->pure ? 2 * lp + 1 : (lp + 1) * (lp + 2) / 2;
-        part = std::max(part, gam_reg_plan(npair, int(na[lp]), nout, ds->ncu).partial_doubles(nout));
+        const int nacc = (lp + 1) * (lp + 2) / 2;
+        part = std::max(part, gam_reg_plan(npair, int(na[lp]), nacc, ds->ncu).partial_doubles(nout));
       }
   return jplan_bytes(orb->nshell, aux->nshell) + align256(sizeof(double) * part);
 }
@@ -856,34 +843,19 @@ int df3c_coulomb_gamma(const double *xyz, int32_t natom, const df3c_shells *aux,
         a.npair = (la == lb) ? int64_t(na) * (na + 1) / 2 : int64_t(na) * nb;
         const ClassInfo &ci = g_cls[lp][la][lb];
         const int c = (lp * NLA + la) * NLA + lb;
-        if (ci.gam_reg) {
-          const GamRegPlan gp = gam_reg_plan(a.npair, np, nout, ds->ncu);
-          a.nsplit = gp.nsplit;
-          a.nps = gp.nps;
-          a.prange = gp.prange;
-          a.nrange = gp.nrange;
-          const int grid = int(gp.nrange * gp.nsplit);
-          if (timed(DF3C_KERNEL_GAMMA, c, s, [&] { return ci.gam(a, grid, s); }) != hipSuccess)
-            return DF3C_E_HIP;
-          const int nred = np * nout;
-          hipLaunchKernelGGL(k_gam_reduce_r, dim3((nred + 255) / 256), dim3(256), 0, s, partial, np,
-                             gp.nsplit, gp.nps, gp.nrange, nout, a.psh, aux_off, gamma);
-          continue;
-        }
-        // items = (aux shell, chunk of pairs); about gam_target of them per class
-        const int64_t target = int64_t(ds->ncu) * 2 * ci.gam_ipw;
-        int64_t nchunk = std::min<int64_t>(a.npair, std::max<int64_t>(1, (target + np - 1) / np));
-        a.chunk = (a.npair + nchunk - 1) / nchunk;
-        nchunk = (a.npair + a.chunk - 1) / a.chunk;
-        a.nchunk = int32_t(nchunk);
-        const int64_t items = int64_t(np) * nchunk;
-        const int grid = int(std::max<int64_t>(
-            1, std::min<int64_t>((items + ci.gam_ipw - 1) / ci.gam_ipw, int64_t(ds->ncu) * 4)));
+        // items (range of pairs, subset of the aux shells) on the register
+        // engine or the gamma engine; partials added per class in order
+        const GamRegPlan gp = gam_reg_plan(a.npair, np, (lp + 1) * (lp + 2) / 2, ds->ncu);
+        a.nsplit = gp.nsplit;
+        a.nps = gp.nps;
+        a.prange = gp.prange;
+        a.nrange = gp.nrange;
+        const int grid = int(gp.nrange * gp.nsplit);
         if (timed(DF3C_KERNEL_GAMMA, c, s, [&] { return ci.gam(a, grid, s); }) != hipSuccess)
           return DF3C_E_HIP;
         const int nred = np * nout;
-        hipLaunchKernelGGL(k_gam_reduce, dim3((nred + 255) / 256), dim3(256), 0, s, partial, np,
-                           a.nchunk, nout, a.psh, aux_off, gamma);
+        hipLaunchKernelGGL(k_gam_reduce_r, dim3((nred + 255) / 256), dim3(256), 0, s, partial, np,
+                           gp.nsplit, gp.nps, gp.nrange, nout, a.psh, aux_off, gamma);
       }
   }
   return DF3C_OK;
