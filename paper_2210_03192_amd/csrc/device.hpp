@@ -59,6 +59,8 @@ template <int M0, int NM>
 __device__ __forceinline__ void boys(const double *__restrict__ tab, double T, double *F) {
   constexpr int MTOP = M0 + NM - 1;
   static_assert(MTOP <= BOYS_MTOP_MAX, "Boys order beyond the table");
+  // both branches need e^{-T}: one evaluation, outside the (divergent) branch
+  const double e = exp(-T);
   if (T < BOYS_TMAX) {
     const int i = min(max(int(T * (1.0 / BOYS_DT) + 0.5), 0), BOYS_NGRID - 1);
     const double md = double(i) * BOYS_DT - T;  // -(T - T_i)
@@ -66,13 +68,11 @@ __device__ __forceinline__ void boys(const double *__restrict__ tab, double T, d
     double f = row[BOYS_NTAY - 1];
 #pragma unroll
     for (int k = BOYS_NTAY - 2; k >= 0; --k) f = row[k] + f * md * (1.0 / double(k + 1));
-    const double e = exp(-T);
     F[NM - 1] = f;
 #pragma unroll
     for (int m = MTOP - 1; m >= M0; --m)
       F[m - M0] = (2.0 * T * F[m - M0 + 1] + e) * (1.0 / double(2 * m + 1));
   } else {
-    const double e = exp(-T);
     const double r2t = 0.5 / T;
     double f = 0.5 * sqrt(3.14159265358979323846 / T);
 #pragma unroll

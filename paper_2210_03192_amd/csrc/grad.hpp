@@ -6,17 +6,17 @@
 //   d/dB_x (ab|P) = (a b+1_x|P)^{2 zeta_b} - b_x (a b-1_x|P)
 //   d/dC_x (ab|P) = -(d/dA_x + d/dB_x)            (translational invariance)
 // where (..)^{2 zeta} is contracted with the extra primitive weight 2 zeta.
-// Each of the four shifted classes is evaluated by the forward pipeline
-// (Boys, 2-q VRR1, contracted CVRR2, ket transform), the ket is contracted with
-// d_P before the HRR (linear in the ket, so the result is unchanged), and the
-// single-component HRR gives the shifted blocks that are contracted with G.
+// Small classes run the register engine (one lane per shell pair, every
+// intermediate in registers, per aux shell the shifted HRR blocks contracted
+// with G~); the others run the gradient engine, which transposes the shifted
+// HRRs onto G~ once per pair and takes dot products per primitive triplet.
 // Integrals are recomputed, never stored.
 //
-// Owner computes: one team per orbital shell pair and subset of the aux shells
-// of l = LP.  Per-atom contributions are accumulated per team in LDS in a fixed
-// order and added to a per-(workgroup, team) partial array in global memory;
-// a final kernel sums the partials in a fixed order, so the gradient is
-// bitwise reproducible.
+// Owner computes: work items are (shell pairs, subset of the aux shells of
+// l = LP).  Per-atom contributions are accumulated per workgroup in LDS in a
+// fixed order and added to a per-workgroup partial array in global memory; a
+// final kernel sums the partials in a fixed order, so the gradient is bitwise
+// reproducible.
 #pragma once
 #include "kernels.hpp"
 
@@ -37,7 +37,7 @@ struct GradArgs {
   int32_t pure;
   int32_t natom;
   int32_t nsplit;           // aux shells of a pair split into nsplit interleaved subsets
-  double *partial;          // [gridDim.x * teams per block][natom][3], accumulated
+  double *partial;          // [gridDim.x][natom][3], accumulated
 };
 
 // Work items of the gradient kernels: blocks of tpb consecutive shell pairs
@@ -46,274 +46,6 @@ struct GradArgs {
 // uniform over the workgroup.  Block b -> subset b / nblk, pairs of block b % nblk.
 __device__ __forceinline__ int64_t grad_blocks(const GradArgs &g, int tpb) {
   return (g.npair + tpb - 1) / tpb * g.nsplit;
-}
-
-template <int LP, int LA, int LB, int PCH>
-struct GradLayout {
-  // sub-evaluations: 0 = A+ (LA+1, LB), 1 = B+ (LA, LB+1), 2 = A- (LA-1, LB), 3 = B- (LA, LB-1)
-  static constexpr int la(int s) { return s == 0 ? LA + 1 : s == 2 ? LA - 1 : LA; }
-  static constexpr int lb(int s) { return s == 1 ? LB + 1 : s == 3 ? LB - 1 : LB; }
-  static constexpr bool on(int s) { return la(s) >= 0 && lb(s) >= 0; }
-  static constexpr int ne(int s) { return on(s) ? offT(la(s) + lb(s) + 1) - offT(la(s)) : 0; }
-  static constexpr int nh(int s) { return on(s) ? ncart(la(s)) * ncart(lb(s)) : 0; }
-  template <int s>
-  static constexpr int scr() {
-    if constexpr (!on(s)) return 0;
-    else return Layout<LP, la(s), lb(s), PCH>::TOTAL;
-  }
-  static constexpr int SCR = imax(imax(scr<0>(), scr<1>()), imax(scr<2>(), scr<3>()));
-  static constexpr int XD(int s) {
-    int o = SCR;
-    for (int q = 0; q < s; ++q) o += ne(q);
-    return o;
-  }
-  static constexpr int H(int s) {
-    int o = XD(4);
-    for (int q = 0; q < s; ++q) o += nh(q);
-    return o;
-  }
-  static constexpr int RED = H(4);                 // 6 values per wave (4 waves max)
-  static constexpr int TEAM = RED + 24;            // doubles per team before the atom array
-};
-
-template <int LP, int LA, int LB>
-struct GradCfg {
-  // team size from the largest shifted class, at least 16 lanes (<= 4 teams per wave)
-  static constexpr int TS0 = imax(Cfg<LP, LA + 1, LB>::TS, Cfg<LP, LA, LB + 1>::TS);
-  static constexpr int TS = TS0 < 16 ? 16 : TS0;
-  static constexpr int PCH = 4;
-  static constexpr int BLK = TS > 64 ? TS : 64;
-  static constexpr int TPB = BLK / TS;
-  static constexpr int TEAM = GradLayout<LP, LA, LB, PCH>::TEAM;
-  static constexpr int WPE = TS >= 128 ? DF3C_MIN_WAVES_BIG : TS == 64 ? DF3C_MIN_WAVES_WAVE : 1;
-  // dynamic LDS for natom atoms
-  static constexpr int lds(int natom) { return TPB * (TEAM + 3 * natom) * 8; }
-};
-
-// sum over the lanes of a team (TS lanes, aligned); the total ends up in lane 0
-template <int TS>
-__device__ __forceinline__ double team_sum(double v, double *red, int tid, int slot) {
-  constexpr int W = TS < 64 ? TS : 64;
-#pragma unroll
-  for (int o = W / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  if constexpr (TS > 64) {
-    if ((tid & 63) == 0) red[(tid >> 6) * 6 + slot] = v;
-  }
-  return v;
-}
-
-template <int LP, int LA, int LB, int TS, int PCH, int s, int WM>
-__device__ __forceinline__ void grad_sub(const GradArgs &g, double *S, int tid, int npmax,
-                                         const double *Ar, const double *Br, const double *Cr,
-                                         int Ka, int64_t oa, int Kb, int64_t ob, int Kc,
-                                         int64_t oc, const double *dP, int np_out) {
-  using GL = GradLayout<LP, LA, LB, PCH>;
-  constexpr int la = GL::la(s), lb = GL::lb(s);
-  if constexpr (GL::on(s)) {
-    using LY = Layout<LP, la, lb, PCH>;
-    using G = Geo<LP, la, la + lb>;
-    triplet_to_e0P<LP, la, lb, TS, PCH, WM>(g.boys, S, tid, nullptr, npmax, Ar, Br, Cr, Ka,
-                                            g.orb.exps + oa, g.orb.coefs + oa, Kb,
-                                            g.orb.exps + ob, g.orb.coefs + ob, Kc,
-                                            g.aux.exps + oc, g.aux.coefs + oc, g.pure);
-    // contract the ket with d_P:  X_e = sum_m d_m (e0|m)
-    const double *EM = S + LY::EM;
-    double *XD = S + GL::XD(s);
-    for (int e = tid; e < G::NE; e += TS) {
-      double v = 0.0;
-      for (int m = 0; m < np_out; ++m) v += dP[m] * EM[m * G::NE + e];
-      XD[e] = v;
-    }
-    team_sync();
-  }
-}
-
-template <int LP, int LA, int LB, int TS, int PCH, int s>
-__device__ __forceinline__ void grad_hrr(double *S, int tid, const double *pwx, const double *pwy,
-                                         const double *pwz) {
-  using GL = GradLayout<LP, LA, LB, PCH>;
-  constexpr int la = GL::la(s), lb = GL::lb(s);
-  if constexpr (GL::on(s)) {
-    const double *XD = S + GL::XD(s);
-    double *H = S + GL::H(s);
-    for (int a = tid; a < ncart(la); a += TS) {
-      double o[ncart(lb)];
-      hrr_nq<la, lb>(XD, a, pwx, pwy, pwz, o);
-#pragma unroll
-      for (int b = 0; b < ncart(lb); ++b) H[a * ncart(lb) + b] = o[b];
-    }
-  }
-}
-
-template <int LP, int LA, int LB, int TS, int PCH>
-__global__ void __launch_bounds__(TS > 64 ? TS : 64)
-    __attribute__((amdgpu_waves_per_eu(GradCfg<LP, LA, LB>::WPE))) k_grad(GradArgs g) {
-  using GL = GradLayout<LP, LA, LB, PCH>;
-  constexpr int BLK = TS > 64 ? TS : 64;
-  constexpr int TPB = BLK / TS;
-  constexpr int NA = ncart(LA), NB = ncart(LB), NAB = NA * NB;
-  constexpr int NACC = (NAB + TS - 1) / TS;
-  constexpr int NBP = ncart(LB + 1), NBM = ncart(LB - 1), NAM = ncart(LA - 1);
-  extern __shared__ double smem[];
-  const int team = threadIdx.x / TS, tid = threadIdx.x % TS;
-  double *S = smem + team * (GL::TEAM + 3 * g.natom);
-  double *ACC = S + GL::TEAM;
-  double *RED = S + GL::RED;
-  const int np_out = g.pure ? npure(LP) : ncart(LP);
-  for (int x = tid; x < 3 * g.natom; x += TS) ACC[x] = 0.0;
-  team_sync();
-
-  const int64_t nblk = (g.npair + TPB - 1) / TPB;
-  for (int64_t blk = blockIdx.x; blk < grad_blocks(g, TPB); blk += gridDim.x) {
-    const int sub = int(blk / nblk);
-    const int64_t q = (blk - sub * nblk) * TPB + team;
-    const bool valid = q < g.npair;
-    int sa = 0, sb = 0;
-    if (valid) {
-      if (g.same) {
-        int i = int((sqrt(8.0 * double(q) + 1.0) - 1.0) * 0.5);
-        while (int64_t(i) * (i + 1) / 2 > q) --i;
-        while (int64_t(i + 1) * (i + 2) / 2 <= q) ++i;
-        const int j = int(q - int64_t(i) * (i + 1) / 2);
-        sa = g.ash[i];
-        sb = g.ash[j];
-      } else {
-        const int i = int(q / g.nb), j = int(q - int64_t(i) * g.nb);
-        sa = g.ash[i];
-        sb = g.bsh[j];
-      }
-    }
-    if (valid) orient_pair<LA, LB>(g.orb, sa, sb);
-    const int Ka = valid ? g.orb.nprim[sa] : 0, Kb = valid ? g.orb.nprim[sb] : 0;
-    const int64_t oa = valid ? g.orb.prim_off[sa] : 0, ob = valid ? g.orb.prim_off[sb] : 0;
-    const int atA = valid ? g.orb.atom[sa] : 0, atB = valid ? g.orb.atom[sb] : 0;
-    double Ar[3] = {0, 0, 0}, Br[3] = {0, 0, 0};
-    if (valid)
-      for (int x = 0; x < 3; ++x) {
-        Ar[x] = g.xyz[3 * atA + x];
-        Br[x] = g.xyz[3 * atB + x];
-      }
-    // G~_ab for this lane's block elements (both J blocks of an off-diagonal pair)
-    const int64_t ra = valid ? g.ao_off[sa] : 0, rb = valid ? g.ao_off[sb] : 0;
-    double gt[NACC];
-#pragma unroll
-    for (int k = 0; k < NACC; ++k) {
-      const int ab = tid + k * TS;
-      gt[k] = 0.0;
-      if (valid && ab < NAB) {
-        const int ia = ab / NB, ib = ab - ia * NB;
-        gt[k] = g.G[(ra + ia) * g.nao + rb + ib];
-        if (sa != sb) gt[k] += g.G[(rb + ib) * g.nao + ra + ia];
-      }
-    }
-    double pwx[LB + 2], pwy[LB + 2], pwz[LB + 2];
-    pwx[0] = pwy[0] = pwz[0] = 1.0;
-#pragma unroll
-    for (int k = 1; k <= LB + 1; ++k) {
-      pwx[k] = pwx[k - 1] * (Ar[0] - Br[0]);
-      pwy[k] = pwy[k - 1] * (Ar[1] - Br[1]);
-      pwz[k] = pwz[k - 1] * (Ar[2] - Br[2]);
-    }
-    double GA[3] = {0, 0, 0}, GB[3] = {0, 0, 0};
-    for (int ip = sub; ip < g.np; ip += g.nsplit) {
-      const int sP = g.psh[ip];
-      const int Kc = g.aux.nprim[sP];
-      const int npmax = TS >= 64 ? Ka * Kb * Kc : wave_max(Ka * Kb * Kc);
-      const int64_t oc = g.aux.prim_off[sP];
-      const int atC = g.aux.atom[sP];
-      const double Cr[3] = {g.xyz[3 * atC], g.xyz[3 * atC + 1], g.xyz[3 * atC + 2]};
-      const double *dP = g.d + g.aux_off[sP];
-      grad_sub<LP, LA, LB, TS, PCH, 0, 1>(g, S, tid, npmax, Ar, Br, Cr, Ka, oa, Kb, ob, Kc, oc, dP,
-                                          np_out);
-      grad_sub<LP, LA, LB, TS, PCH, 1, 2>(g, S, tid, npmax, Ar, Br, Cr, Ka, oa, Kb, ob, Kc, oc, dP,
-                                          np_out);
-      grad_sub<LP, LA, LB, TS, PCH, 2, 0>(g, S, tid, npmax, Ar, Br, Cr, Ka, oa, Kb, ob, Kc, oc, dP,
-                                          np_out);
-      grad_sub<LP, LA, LB, TS, PCH, 3, 0>(g, S, tid, npmax, Ar, Br, Cr, Ka, oa, Kb, ob, Kc, oc, dP,
-                                          np_out);
-      grad_hrr<LP, LA, LB, TS, PCH, 0>(S, tid, pwx, pwy, pwz);
-      grad_hrr<LP, LA, LB, TS, PCH, 1>(S, tid, pwx, pwy, pwz);
-      grad_hrr<LP, LA, LB, TS, PCH, 2>(S, tid, pwx, pwy, pwz);
-      grad_hrr<LP, LA, LB, TS, PCH, 3>(S, tid, pwx, pwy, pwz);
-      team_sync();
-      // contract the shifted blocks with G~
-      const double *H0 = S + GL::H(0), *H1 = S + GL::H(1), *H2 = S + GL::H(2), *H3 = S + GL::H(3);
-      double pA[3] = {0, 0, 0}, pB[3] = {0, 0, 0};
-#pragma unroll
-      for (int k = 0; k < NACC; ++k) {
-        const int ab = tid + k * TS;
-        if (ab < NAB) {
-          const int ia = ab / NB, ib = ab - ia * NB;
-          int a3[3] = {0, 0, 0}, b3[3] = {0, 0, 0};
-          static_for<NA>([&](auto c) {
-            constexpr C3 qq = cart(LA, decltype(c)::value);
-            if (ia == decltype(c)::value) a3[0] = qq[0], a3[1] = qq[1], a3[2] = qq[2];
-          });
-          static_for<NB>([&](auto c) {
-            constexpr C3 qq = cart(LB, decltype(c)::value);
-            if (ib == decltype(c)::value) b3[0] = qq[0], b3[1] = qq[1], b3[2] = qq[2];
-          });
-#pragma unroll
-          for (int x = 0; x < 3; ++x) {
-            int u[3] = {a3[0], a3[1], a3[2]};
-            u[x] += 1;
-            double vA = H0[cidx(u[0], u[1], u[2]) * NB + ib];
-            if constexpr (LA > 0)
-              if (a3[x] > 0) {
-                u[x] -= 2;
-                vA -= double(a3[x]) * H2[cidx(u[0], u[1], u[2]) * NB + ib];
-              }
-            int w[3] = {b3[0], b3[1], b3[2]};
-            w[x] += 1;
-            double vB = H1[ia * NBP + cidx(w[0], w[1], w[2])];
-            if constexpr (LB > 0)
-              if (b3[x] > 0) {
-                w[x] -= 2;
-                vB -= double(b3[x]) * H3[ia * NBM + cidx(w[0], w[1], w[2])];
-              }
-            pA[x] += gt[k] * vA;
-            pB[x] += gt[k] * vB;
-          }
-        }
-      }
-      (void)NAM;
-      double sA[3], sB[3];
-#pragma unroll
-      for (int x = 0; x < 3; ++x) {
-        sA[x] = team_sum<TS>(pA[x], RED, tid, x);
-        sB[x] = team_sum<TS>(pB[x], RED, tid, 3 + x);
-      }
-      if constexpr (TS > 64) {
-        team_sync();
-        if (tid == 0)
-          for (int x = 0; x < 3; ++x) {
-            sA[x] = RED[x];
-            sB[x] = RED[3 + x];
-            for (int w = 1; w < TS / 64; ++w) {
-              sA[x] += RED[w * 6 + x];
-              sB[x] += RED[w * 6 + 3 + x];
-            }
-          }
-      }
-      if (tid == 0 && valid) {
-        for (int x = 0; x < 3; ++x) {
-          GA[x] += sA[x];
-          GB[x] += sB[x];
-          ACC[3 * atC + x] -= sA[x] + sB[x];
-        }
-      }
-      team_sync();
-    }
-    if (tid == 0 && valid)
-      for (int x = 0; x < 3; ++x) {
-        ACC[3 * atA + x] += GA[x];
-        ACC[3 * atB + x] += GB[x];
-      }
-    team_sync();
-  }
-  // this team's partial
-  double *part = g.partial + (int64_t(blockIdx.x) * TPB + team) * 3 * g.natom;
-  for (int x = tid; x < 3 * g.natom; x += TS) part[x] += ACC[x];
 }
 
 // ---------------------------------------------------------------------------

@@ -864,7 +864,7 @@ int df3c_coulomb_gamma(const double *xyz, int32_t natom, const df3c_shells *aux,
 // ----------------------------------------------------------------- J gradient
 namespace {
 constexpr int GRAD_GRID_PER_CU = 16;    // workgroups per CU of every gradient launch
-constexpr int GRAD_MAX_TPB = 4;         // teams per workgroup of the gradient kernels
+constexpr int GRAD_MAX_TPB = 1;         // teams per workgroup of the gradient kernels
 int grad_slots(int ncu) { return ncu * GRAD_GRID_PER_CU * GRAD_MAX_TPB; }
 
 // Aux-shell subsets per shell pair of a gradient class: a class of few pairs
