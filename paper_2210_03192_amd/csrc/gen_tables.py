@@ -232,6 +232,31 @@ def jx_terms(g):
     return start, mi, co
 
 
+def combine_blocks(st, pi, w):
+    """The CVRR2 combination terms re-laid for whole wavefronts: targets with
+    terms, ordered by decreasing term count, in blocks of 64 (one per wave);
+    block b holds m_b = its largest term count and its terms interleaved,
+    term j of lane l at word boff[b] + 64 j + l (weight 0 past a target's own
+    terms), so every lane of a wave runs the same loop with coalesced loads."""
+    cnt = [st[t + 1] - st[t] for t in range(len(st) - 1)]
+    order = sorted((t for t in range(len(cnt)) if cnt[t] > 0), key=lambda t: (-cnt[t], t))
+    boff, bm, tg, il = [0], [], [], []
+    for b0 in range(0, len(order), 64):
+        ts = order[b0:b0 + 64]
+        m = cnt[ts[0]]
+        bm.append(m)
+        for j in range(m):
+            for l in range(64):
+                if l < len(ts) and j < cnt[ts[l]]:
+                    q = st[ts[l]] + j
+                    il.append((w[q] << 16) | pi[q])
+                else:
+                    il.append(0)
+        boff.append(len(il))
+        tg.extend(ts + [0xffff] * (64 - len(ts)))
+    return boff, bm, tg, il
+
+
 def gg_terms(g):
     """Per u (flat index offT(|u|) + cidx(u), |u| <= min(LP, EB)): the terms
     (e!/(e-u)!, target index of e relative to level EA, VRR1 index of e - u) of
@@ -475,6 +500,12 @@ def write(outdir):
             # one word per term: weight << 16 | prerequisite index
             assert max(pi, default=0) < 65536 and max(w, default=0) < 65536
             s.append(arr("uint32_t", "cb_pw", [(ww << 16) | pp for pp, ww in zip(pi, w)]))
+            boff, bm, tg, il = combine_blocks(st, pi, w)
+            s.append(f"  static constexpr int NCB = {len(bm)};\n")
+            s.append(arr("int32_t", "cb_boff", boff))
+            s.append(arr("int16_t", "cb_bm", bm))
+            s.append(arr("uint16_t", "cb_tg", tg))
+            s.append(arr("uint32_t", "cb_il", il))
             js, jm, jc = jx_terms(g)
             s.append(f"  static constexpr int NM = {jm_off(g, LP + 1)};\n")
             s.append(arr("int16_t", "jx_start", js))

@@ -468,17 +468,36 @@ __device__ __forceinline__ void triplet_to_e0P(const double *btab, double *S, in
   }
   team_sync();
   // ---- n-quantal CVRR2 in place on pi_0: (e0|c) += sum_{u != 0} w pi_{|u|}(e-u, c-u)
-  for (int t = tid; t < TB::NTGT; t += TS) {
-    const int q0 = TB::cb_start[t], q1 = TB::cb_start[t + 1];
-    if (q1 > q0) {
-      double a = PI[t];
-      // independent table loads, batched so their latencies overlap
+  // (reads only the blocks k >= 1, so the targets may be updated in any order)
+  if constexpr (MF) {
+    // whole waves take blocks of 64 targets of equal term count, terms
+    // interleaved across the lanes: uniform loops, coalesced table loads
+    const int wv2 = tid >> 6, ln = tid & 63;
+    for (int b = wv2; b < TB::NCB; b += NWV) {
+      const int t = TB::cb_tg[b * 64 + ln];
+      const int m = TB::cb_bm[b];
+      const uint32_t *w = TB::cb_il + TB::cb_boff[b] + ln;
+      double a = 0.0;
 #pragma unroll 8
-      for (int q = q0; q < q1; ++q) {
-        const uint32_t c = TB::cb_pw[q];
+      for (int j = 0; j < m; ++j) {
+        const uint32_t c = w[j * 64];
         a += double(c >> 16) * PI[c & 0xffffu];
       }
-      PI[t] = a;
+      if (t != 0xffff) PI[t] += a;
+    }
+  } else {
+    for (int t = tid; t < TB::NTGT; t += TS) {
+      const int q0 = TB::cb_start[t], q1 = TB::cb_start[t + 1];
+      if (q1 > q0) {
+        double a = PI[t];
+        // independent table loads, batched so their latencies overlap
+#pragma unroll 8
+        for (int q = q0; q < q1; ++q) {
+          const uint32_t c = TB::cb_pw[q];
+          a += double(c >> 16) * PI[c & 0xffffu];
+        }
+        PI[t] = a;
+      }
     }
   }
   team_sync();

@@ -106,3 +106,25 @@ def test_jengine_table_sizes():
                 xs, xm, xc = gt.jx_terms(geo)
                 # each M entry is used by exactly one target
                 assert sorted(xm) == list(range(gt.jm_off(geo, LP + 1)))
+
+
+def test_combine_blocks_hold_every_term_once():
+    """The wavefront layout of the CVRR2 combination (blocks of 64 targets,
+    terms interleaved, weight-0 padding) holds exactly the CSR terms."""
+    for c in [(6, 4, 8), (6, 3, 6), (4, 2, 4), (2, 1, 2), (0, 0, 0), (3, 3, 3)]:
+        g = gt.Geo(*c)
+        st, pi, w = gt.combine(g)
+        boff, bm, tg, il = gt.combine_blocks(st, pi, w)
+        got = {}
+        for b in range(len(bm)):
+            for l in range(64):
+                t = tg[64 * b + l]
+                terms = [il[boff[b] + 64 * j + l] for j in range(bm[b])]
+                if t == 0xffff:
+                    assert all(x == 0 for x in terms)
+                    continue
+                got[t] = sorted(x for x in terms if x >> 16)
+                assert len(got[t]) == st[t + 1] - st[t]
+        want = {t: sorted((w[q] << 16) | pi[q] for q in range(st[t], st[t + 1]))
+                for t in range(len(st) - 1) if st[t + 1] > st[t]}
+        assert got == want
