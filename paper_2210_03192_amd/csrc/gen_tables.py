@@ -501,7 +501,7 @@ def write(outdir):
             assert max(pi, default=0) < 65536 and max(w, default=0) < 65536
             s.append(arr("uint32_t", "cb_pw", [(ww << 16) | pp for pp, ww in zip(pi, w)]))
             boff, bm, tg, il = combine_blocks(st, pi, w)
-            s.append(f"  static constexpr int NCB = {len(bm)};\n")
+            s.append(f"  static constexpr int NCB = {len(bm)}, CBM = {max(bm, default=0)};\n")
             s.append(arr("int32_t", "cb_boff", boff))
             s.append(arr("int16_t", "cb_bm", bm))
             s.append(arr("uint16_t", "cb_tg", tg))

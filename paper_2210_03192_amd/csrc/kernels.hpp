@@ -471,18 +471,24 @@ __device__ __forceinline__ void triplet_to_e0P(const double *btab, double *S, in
   // (reads only the blocks k >= 1, so the targets may be updated in any order)
   if constexpr (MF) {
     // whole waves take blocks of 64 targets of equal term count, terms
-    // interleaved across the lanes: uniform loops, coalesced table loads
+    // interleaved across the lanes: uniform loops, coalesced table loads; all
+    // table words of a block are loaded first, then all pi operands, so each
+    // block waits for one table and one LDS latency
+    constexpr int MM = TB::CBM > 0 ? TB::CBM : 1;
     const int wv2 = tid >> 6, ln = tid & 63;
     for (int b = wv2; b < TB::NCB; b += NWV) {
       const int t = TB::cb_tg[b * 64 + ln];
       const int m = TB::cb_bm[b];
       const uint32_t *w = TB::cb_il + TB::cb_boff[b] + ln;
+      uint32_t cw[MM];
+#pragma unroll
+      for (int j = 0; j < MM; ++j) cw[j] = j < m ? w[j * 64] : 0u;
+      double pv[MM];
+#pragma unroll
+      for (int j = 0; j < MM; ++j) pv[j] = j < m ? PI[cw[j] & 0xffffu] : 0.0;
       double a = 0.0;
-#pragma unroll 8
-      for (int j = 0; j < m; ++j) {
-        const uint32_t c = w[j * 64];
-        a += double(c >> 16) * PI[c & 0xffffu];
-      }
+#pragma unroll
+      for (int j = 0; j < MM; ++j) a += double(cw[j] >> 16) * pv[j];
       if (t != 0xffff) PI[t] += a;
     }
   } else {
