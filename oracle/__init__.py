@@ -47,6 +47,8 @@ def _lib(precision="double"):
         lib.oracle_solid_transform.argtypes = [ctypes.c_int, P]
         lib.oracle_eval_batch.argtypes = [P, P, P, ctypes.c_int64, P, P, P, ctypes.c_int]
         lib.oracle_coulomb_J.argtypes = [P, P, P, P, P, ctypes.c_int]
+        lib.oracle_coulomb_J_masked.argtypes = [P, P, P, P, P, P, ctypes.c_int]
+        lib.oracle_screen_pairs.argtypes = [P, P, ctypes.c_double, P, P]
         lib.oracle_coulomb_gamma.argtypes = [P, P, P, P, P, ctypes.c_int]
         lib.oracle_coulomb_metric.argtypes = [P, P, P, ctypes.c_int]
         lib.oracle_coulomb_J_pairs.argtypes = [P, P, P, P, ctypes.c_int64, P, P, P,
@@ -135,6 +137,35 @@ def coulomb_J(xyz, aux, orb, d, nthreads=0, precision="double"):
     _check(_lib(precision).oracle_coulomb_J(_ptr(xyz), pa.ref, po.ref, _ptr(d), _ptr(J),
                                             int(nthreads)), "coulomb_J")
     return J
+
+
+def coulomb_J_masked(xyz, aux, orb, d, mask, nthreads=0, precision="double"):
+    """J over the orbital shell pairs with mask[a, b] != 0 (nshell x nshell,
+    symmetric); the other blocks are zero."""
+    xyz = np.ascontiguousarray(xyz, np.float64)
+    d = np.ascontiguousarray(d, np.float64)
+    mask = np.ascontiguousarray(mask, np.uint8)
+    assert mask.shape == (len(orb.l), len(orb.l))
+    nao = int(sum(ncart(int(l)) for l in orb.l))
+    J = np.zeros((nao, nao))
+    pa, po = _Pinned(aux), _Pinned(orb)
+    _check(_lib(precision).oracle_coulomb_J_masked(_ptr(xyz), pa.ref, po.ref, _ptr(d),
+                                                   _ptr(mask), _ptr(J), int(nthreads)),
+           "coulomb_J_masked")
+    return J
+
+
+def screen_pairs(xyz, orb, tau):
+    """(mask, S): S[a, b] = max_ij |c_ai c_bj| (pi/(z_ai+z_bj))^{3/2}
+    exp(-z_ai z_bj/(z_ai+z_bj) |A-B|^2), mask = S >= tau."""
+    xyz = np.ascontiguousarray(xyz, np.float64)
+    n = len(orb.l)
+    mask = np.zeros((n, n), np.uint8)
+    S = np.zeros((n, n))
+    po = _Pinned(orb)
+    _check(_lib().oracle_screen_pairs(_ptr(xyz), po.ref, float(tau), _ptr(mask), _ptr(S)),
+           "screen_pairs")
+    return mask, S
 
 
 def coulomb_gamma(xyz, aux, orb, D, nthreads=0, precision="double"):

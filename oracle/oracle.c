@@ -602,6 +602,73 @@ int oracle_coulomb_J(const double *xyz, const oracle_basis *aux, const oracle_ba
   return 0;
 }
 
+int oracle_coulomb_J_masked(const double *xyz, const oracle_basis *aux, const oracle_basis *orb,
+                            const double *d, const uint8_t *mask, double *J, int nthreads) {
+  if (check_basis(aux, LMAX_AUX - 1) || check_basis(orb, LMAX_ORB - 1) || orb->pure || !mask)
+    return -1;
+  set_threads(nthreads);
+  int64_t *aoff = (int64_t *)malloc(sizeof(int64_t) * (aux->nshell + 1));
+  int64_t *ooff = (int64_t *)malloc(sizeof(int64_t) * (orb->nshell + 1));
+  offsets(aux, aoff);
+  offsets(orb, ooff);
+  int64_t nao = ooff[orb->nshell];
+  int64_t npair = (int64_t)orb->nshell * (orb->nshell + 1) / 2;
+  for (int64_t x = 0; x < nao * nao; ++x) J[x] = 0.0;
+#pragma omp parallel
+  {
+    md_work *w = (md_work *)malloc(sizeof(md_work));
+    real *cart = (real *)malloc(sizeof(real) * BLK_MAX);
+    real *pure = (real *)malloc(sizeof(real) * BLK_MAX);
+    real Jblk[NC_ORB * NC_ORB];
+#pragma omp for schedule(dynamic, 1)
+    for (int64_t k = 0; k < npair; ++k) {
+      int sa = (int)((sqrt(8.0 * (double)k + 1) - 1) / 2);
+      while ((int64_t)sa * (sa + 1) / 2 > k) --sa;
+      while ((int64_t)(sa + 1) * (sa + 2) / 2 <= k) ++sa;
+      int sb = (int)(k - (int64_t)sa * (sa + 1) / 2);
+      if (!mask[(int64_t)sa * orb->nshell + sb]) continue;
+      J_block(xyz, aux, orb, d, aoff, sa, sb, Jblk, cart, pure, w);
+      int na = ncart(orb->l[sa]), nb = ncart(orb->l[sb]);
+      for (int i = 0; i < na; ++i)
+        for (int j = 0; j < nb; ++j) {
+          J[(ooff[sa] + i) * nao + ooff[sb] + j] = (double)Jblk[i * nb + j];
+          J[(ooff[sb] + j) * nao + ooff[sa] + i] = (double)Jblk[i * nb + j];
+        }
+    }
+    free(w);
+    free(cart);
+    free(pure);
+  }
+  free(aoff);
+  free(ooff);
+  return 0;
+}
+
+int oracle_screen_pairs(const double *xyz, const oracle_basis *orb, double tau, uint8_t *mask,
+                        double *S) {
+  if (check_basis(orb, LMAX_ORB - 1) || !mask) return -1;
+  const double pi = 3.14159265358979323846;
+  for (int a = 0; a < orb->nshell; ++a)
+    for (int b = 0; b <= a; ++b) {
+      const double *A = xyz + 3 * orb->atom[a], *B = xyz + 3 * orb->atom[b];
+      const double ab2 = (A[0] - B[0]) * (A[0] - B[0]) + (A[1] - B[1]) * (A[1] - B[1]) +
+                         (A[2] - B[2]) * (A[2] - B[2]);
+      double smax = 0.0;
+      for (int i = 0; i < orb->nprim[a]; ++i)
+        for (int j = 0; j < orb->nprim[b]; ++j) {
+          const double za = orb->exps[orb->prim_off[a] + i], zb = orb->exps[orb->prim_off[b] + j];
+          const double ca = orb->coefs[orb->prim_off[a] + i], cb = orb->coefs[orb->prim_off[b] + j];
+          const double g = za + zb;
+          const double v = fabs(ca * cb) * pow(pi / g, 1.5) * exp(-za * zb / g * ab2);
+          if (v > smax) smax = v;
+        }
+      const uint8_t keep = smax >= tau;
+      mask[(int64_t)a * orb->nshell + b] = mask[(int64_t)b * orb->nshell + a] = keep;
+      if (S) S[(int64_t)a * orb->nshell + b] = S[(int64_t)b * orb->nshell + a] = smax;
+    }
+  return 0;
+}
+
 int oracle_coulomb_J_pairs(const double *xyz, const oracle_basis *aux, const oracle_basis *orb,
                            const double *d, int64_t npair, const int32_t *pairs,
                            const int64_t *out_off, double *out, int nthreads) {

@@ -54,6 +54,21 @@ int oracle_coulomb_J(const double *xyz, const oracle_basis *aux,
                      const oracle_basis *orb, const double *d, double *J,
                      int nthreads);
 
+/* J restricted to the orbital shell pairs with mask[a * nshell + b] != 0
+ * (mask symmetric, nshell x nshell, host); the blocks of the other pairs are
+ * zero.  Same arithmetic as oracle_coulomb_J per kept pair. */
+int oracle_coulomb_J_masked(const double *xyz, const oracle_basis *aux,
+                            const oracle_basis *orb, const double *d,
+                            const uint8_t *mask, double *J, int nthreads);
+
+/* Screening of orbital shell pairs by the largest primitive overlap bound
+ *   S_ab = max_ij |c_ai c_bj| (pi / (z_ai + z_bj))^{3/2}
+ *          exp(-z_ai z_bj / (z_ai + z_bj) |A - B|^2):
+ * mask[a * nshell + b] = mask[b * nshell + a] = (S_ab >= tau); S is also
+ * returned (nshell x nshell, may be NULL). */
+int oracle_screen_pairs(const double *xyz, const oracle_basis *orb, double tau,
+                        uint8_t *mask, double *S);
+
 /* gamma[naux] = sum_{a,b} (P|ab) D_ab over all ordered orbital shell pairs;
  * D is nao x nao row-major (not assumed symmetric). */
 int oracle_coulomb_gamma(const double *xyz, const oracle_basis *aux,

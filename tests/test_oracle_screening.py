@@ -1,0 +1,75 @@
+"""Pins of the oracle's shell-pair screening and masked J (NEXT row f2).
+
+* the bound S_ab is recomputed from its definition with numpy (to 1e-12: the
+  exponent argument, up to ~1e3 for distant pairs, scales the rounding);
+* an all-ones mask gives J exactly; a random symmetric mask keeps exactly the
+  blocks of its pairs and zeroes the others;
+* screening a water dimer at tau = 1e-12 changes J by far less than the
+  neglected pairs' bound would allow to matter (|dJ| <= 1e-8 max|J|).
+"""
+import math
+
+import numpy as np
+
+import oracle
+from paper_2210_03192_amd import inputs
+
+
+def _bound(xyz, orb):
+    n = len(orb.l)
+    S = np.zeros((n, n))
+    for a in range(n):
+        for b in range(n):
+            A, B = xyz[orb.atom[a]], xyz[orb.atom[b]]
+            ab2 = float((A - B) @ (A - B))
+            best = 0.0
+            for i in range(orb.nprim[a]):
+                for j in range(orb.nprim[b]):
+                    za, zb = orb.exps[orb.prim_off[a] + i], orb.exps[orb.prim_off[b] + j]
+                    ca, cb = orb.coefs[orb.prim_off[a] + i], orb.coefs[orb.prim_off[b] + j]
+                    g = za + zb
+                    best = max(best, abs(ca * cb) * (math.pi / g) ** 1.5 * math.exp(-za * zb / g * ab2))
+            S[a, b] = best
+    return S
+
+
+def test_screen_bound_and_mask():
+    s = inputs.water_cluster(3, seed=inputs.SEED_BASE + 401)
+    tau = 1e-6
+    mask, S = oracle.screen_pairs(s.xyz, s.orb, tau)
+    ref = _bound(s.xyz, s.orb)
+    # exp of arguments up to ~1e3 carries |argument| x eps relative rounding
+    np.testing.assert_allclose(S, ref, rtol=1e-12, atol=0)
+    assert np.array_equal(mask, (ref >= tau).astype(np.uint8))
+    assert np.array_equal(mask, mask.T)
+    assert 0 < mask.sum() < mask.size
+
+
+def test_masked_J_blocks():
+    s = inputs.plain_dfj_system(seed=inputs.SEED_BASE + 402, natom=3)
+    d = inputs.fitting_coefficients(s.aux.nbf, 403)
+    J = oracle.coulomb_J(s.xyz, s.aux, s.orb, d)
+    n = len(s.orb.l)
+    np.testing.assert_array_equal(oracle.coulomb_J_masked(s.xyz, s.aux, s.orb, d,
+                                                          np.ones((n, n), np.uint8)), J)
+    rng = np.random.default_rng(404)
+    m = rng.integers(0, 2, (n, n)).astype(np.uint8)
+    m = np.maximum(m, m.T)
+    Jm = oracle.coulomb_J_masked(s.xyz, s.aux, s.orb, d, m)
+    off = s.orb.offsets()
+    for a in range(n):
+        for b in range(n):
+            blk = (slice(off[a], off[a + 1]), slice(off[b], off[b + 1]))
+            if m[a, b]:
+                np.testing.assert_array_equal(Jm[blk], J[blk])
+            else:
+                assert not Jm[blk].any()
+
+
+def test_screening_error_is_small():
+    s = inputs.water_cluster(2, seed=inputs.SEED_BASE + 405)
+    d = inputs.fitting_coefficients(s.aux.nbf, 406)
+    mask, S = oracle.screen_pairs(s.xyz, s.orb, 1e-12)
+    J = oracle.coulomb_J(s.xyz, s.aux, s.orb, d)
+    Jm = oracle.coulomb_J_masked(s.xyz, s.aux, s.orb, d, mask)
+    assert np.abs(Jm - J).max() <= 1e-8 * np.abs(J).max()
