@@ -192,6 +192,22 @@ def dfj_legs(args, df3c, inputs, torch, dev):
             Vm = torch.empty((s.aux.nbf, s.aux.nbf), dtype=torch.float64, device=dev)
             out["metric_ms_water_120atoms"] = _time_ms(
                 torch, lambda: df3c.coulomb_metric(xyz, aux, V=Vm), 3)
+            # screened DF-J (pairs kept by the primitive overlap bound >= 1e-12):
+            # the screening kernel and the masked J together
+            tau = 1e-12
+            mask = torch.empty((orb.nshell, orb.nshell), dtype=torch.uint8, device=dev)
+            Js = torch.empty_like(J)
+            wsm = torch.empty(df3c.coulomb_J_masked_workspace(aux, orb), dtype=torch.uint8,
+                              device=dev)
+
+            def screened():
+                df3c.screen_pairs(xyz, orb, tau, mask=mask)
+                df3c.coulomb_J_masked(xyz, aux, orb, d, mask, J=Js, ws=wsm)
+            out["dfj_ms_water_120atoms_screened"] = _time_ms(torch, screened, 3)
+            out["dfj_screened_tau"] = tau
+            out["dfj_screened_pair_fraction"] = float(mask.double().mean())
+            df3c.coulomb_J(xyz, aux, orb, d, J=J, ws=wsj)
+            out["dfj_screened_max_dev_rel"] = float((Js - J).abs().max() / J.abs().max())
     # J gradient, 60 atoms
     s = inputs.grad_60_system()
     d = torch.as_tensor(inputs.fitting_coefficients(s.aux.nbf, 5), device=dev)

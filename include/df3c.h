@@ -123,6 +123,33 @@ int df3c_coulomb_J(const double *xyz, int32_t natom, const df3c_shells *aux,
                    const df3c_shells *orb, const double *d, double *J, void *ws, size_t ws_bytes,
                    uint32_t flags, void *stream);
 
+/* Screening of orbital shell pairs.  The paper's DF-J timings use screening
+ * without stating its criterion (Section 4); here the largest primitive
+ * overlap bound of a pair,
+ *   S_ab = max_ij |c_ai c_bj| (pi / (z_ai + z_bj))^{3/2}
+ *          exp(-z_ai z_bj / (z_ai + z_bj) |A - B|^2),
+ * keeps the pair when S_ab >= tau.
+ *   orb   orbital basis (as for df3c_coulomb_J)
+ *   tau   threshold (>= 0)
+ *   mask  DEVICE [nshell][nshell] uint8 output, symmetric: 1 = pair kept
+ * Asynchronous on `stream`; DF3C_E_ARG for a bad basis or tau < 0. */
+int df3c_screen_pairs(const double *xyz, int32_t natom, const df3c_shells *orb, double tau,
+                      uint8_t *mask, void *stream);
+
+/* Bytes of workspace df3c_coulomb_J_masked needs. */
+size_t df3c_coulomb_J_masked_workspace(const df3c_shells *aux, const df3c_shells *orb);
+
+/* J_ab = sum_P (ab|P) d_P over the orbital shell pairs (a, b) with
+ * mask[a * nshell + b] != 0 (mask DEVICE, symmetric, e.g. from
+ * df3c_screen_pairs); the J blocks of the other pairs are zero.  The kept
+ * pairs of each (l_a, l_b) class are compacted on the device and run by the
+ * same kernels as df3c_coulomb_J, so an all-ones mask gives the same J
+ * bitwise.  Other arguments as for df3c_coulomb_J; ws of at least
+ * df3c_coulomb_J_masked_workspace bytes. */
+int df3c_coulomb_J_masked(const double *xyz, int32_t natom, const df3c_shells *aux,
+                          const df3c_shells *orb, const double *d, const uint8_t *mask,
+                          double *J, void *ws, size_t ws_bytes, uint32_t flags, void *stream);
+
 /* Bytes of workspace df3c_coulomb_J_grad needs (depends on the current device's
  * CU count). */
 size_t df3c_coulomb_J_grad_workspace(const df3c_shells *aux, const df3c_shells *orb,

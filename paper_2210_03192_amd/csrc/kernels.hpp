@@ -52,6 +52,8 @@ struct JArgs {
   int32_t nsub;             // register engine: lanes per shell pair (power of two,
                             // 1..16), which split the aux shells between them
   const double *arec;       // aux-shell records, aligned with psh (see AREC)
+  const int64_t *plist;     // optional: indices q of the class's pairs to run
+  const int64_t *pcount;    //   (device count of plist), null for all npair
 };
 
 // Aux-shell record, one per position of the sorted aux list, built once per
@@ -1199,9 +1201,11 @@ __global__ void __launch_bounds__(TS > 64 ? TS : 64)
   const int tid = threadIdx.x % TS;
   double *S = smem + (REG ? 0 : team * JL::TOTAL);
 
-  for (int64_t base = int64_t(blockIdx.x) * tpb; base < a.npair; base += int64_t(gridDim.x) * tpb) {
-    const int64_t q = base + team;
-    const bool valid = q < a.npair;
+  // all pairs of the class, or the compacted list of kept pairs
+  const int64_t nitem = a.plist ? *a.pcount : a.npair;
+  for (int64_t base = int64_t(blockIdx.x) * tpb; base < nitem; base += int64_t(gridDim.x) * tpb) {
+    const bool valid = base + team < nitem;
+    const int64_t q = valid && a.plist ? a.plist[base + team] : base + team;
     int sa = 0, sb = 0;
     if (valid) {
       if (a.same) {  // q -> (i >= j)

@@ -547,20 +547,74 @@ size_t df3c_coulomb_J_workspace(const df3c_shells *aux, const df3c_shells *orb) 
   return jplan_bytes(orb->nshell, aux->nshell);
 }
 
-int df3c_coulomb_J(const double *xyz, int32_t natom, const df3c_shells *aux,
-                   const df3c_shells *orb, const double *d, double *J, void *ws, size_t ws_bytes,
-                   uint32_t flags, void *stream) {
-  (void)flags;
-  if (!xyz || natom <= 0 || !shells_ok(aux) || !shells_ok(orb) || !d || !J) return DF3C_E_ARG;
-  if (orb->pure != 0 || (aux->pure != 0 && aux->pure != 1)) return DF3C_E_UNSUPPORTED;
-  if (!ws || ws_bytes < df3c_coulomb_J_workspace(aux, orb)) return DF3C_E_WORKSPACE;
+namespace {
+// shell-pair screening: S_ab = max_ij |c c'| (pi/(z+z'))^{3/2} exp(-z z'/(z+z') AB^2)
+__global__ void k_screen_pairs(const double *xyz, ShellsDev orb, int32_t n, double tau,
+                               uint8_t *mask) {
+  const int64_t total = int64_t(n) * n;
+  for (int64_t x = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; x < total;
+       x += int64_t(gridDim.x) * blockDim.x) {
+    const int sa = int(x / n), sb = int(x - int64_t(sa) * n);
+    const int ia = orb.atom[sa], ib = orb.atom[sb];
+    const double dx = xyz[3 * ia] - xyz[3 * ib], dy = xyz[3 * ia + 1] - xyz[3 * ib + 1],
+                 dz = xyz[3 * ia + 2] - xyz[3 * ib + 2];
+    const double ab2 = dx * dx + dy * dy + dz * dz;
+    const double *ea = orb.exps + orb.prim_off[sa], *ca = orb.coefs + orb.prim_off[sa];
+    const double *eb = orb.exps + orb.prim_off[sb], *cb = orb.coefs + orb.prim_off[sb];
+    double smax = 0.0;
+    for (int i = 0; i < orb.nprim[sa]; ++i)
+      for (int j = 0; j < orb.nprim[sb]; ++j) {
+        const double g = ea[i] + eb[j], t = 3.14159265358979323846 / g;
+        smax = fmax(smax, fabs(ca[i] * cb[j]) * t * sqrt(t) * exp(-ea[i] * eb[j] / g * ab2));
+      }
+    mask[x] = smax >= tau ? 1 : 0;
+  }
+}
+
+// indices q of the class's pairs (as the J kernels decode them) that the mask
+// keeps; the order of the list does not affect J (each pair owns its blocks)
+__global__ void k_pair_compact(const int32_t *ash, const int32_t *bsh, int32_t nb, int32_t same,
+                               int64_t npair, const uint8_t *mask, int32_t nshell,
+                               int64_t *plist, unsigned long long *count) {
+  for (int64_t q = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; q < npair;
+       q += int64_t(gridDim.x) * blockDim.x) {
+    int sa, sb;
+    if (same) {
+      int i = int((sqrt(8.0 * double(q) + 1.0) - 1.0) * 0.5);
+      while (int64_t(i) * (i + 1) / 2 > q) --i;
+      while (int64_t(i + 1) * (i + 2) / 2 <= q) ++i;
+      sa = ash[i];
+      sb = ash[int(q - int64_t(i) * (i + 1) / 2)];
+    } else {
+      const int i = int(q / nb);
+      sa = ash[i];
+      sb = bsh[int(q - int64_t(i) * nb)];
+    }
+    if (mask[int64_t(sa) * nshell + sb]) plist[atomicAdd(count, 1ull)] = q;
+  }
+}
+
+// shell pairs of all (l_a >= l_b) classes (the masked J's pair lists)
+int64_t total_class_pairs(const df3c_shells *orb) {
+  int64_t n[DF3C_LMAX_ORB + 1] = {};
+  for (int s = 0; s < orb->nshell; ++s)
+    if (orb->l_host[s] >= 0 && orb->l_host[s] <= DF3C_LMAX_ORB) ++n[orb->l_host[s]];
+  int64_t m = 1;
+  for (int la = 0; la <= DF3C_LMAX_ORB; ++la)
+    for (int lb = 0; lb <= la; ++lb) m += la == lb ? n[la] * (n[la] + 1) / 2 : n[la] * n[lb];
+  return m;
+}
+
+// DF-J over all pairs (mask null) or over the pairs the mask keeps
+int coulomb_J_run(const double *xyz, int32_t natom, const df3c_shells *aux,
+                  const df3c_shells *orb, const double *d, const uint8_t *mask, double *J,
+                  void *ws, hipStream_t s) {
   DevState *ds = nullptr;
   int rc = init_device(&ds);
   if (rc) return rc;
   JPlan p;
   rc = make_plan(aux, orb, p);
   if (rc) return rc;
-  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   char *w = static_cast<char *>(ws);
   int *err = reinterpret_cast<int *>(w);
   w += align256(sizeof(int) * 8);
@@ -573,6 +627,11 @@ int df3c_coulomb_J(const double *xyz, int32_t natom, const df3c_shells *aux,
   int64_t *aux_off = reinterpret_cast<int64_t *>(w);
   w += align256(sizeof(int64_t) * (aux->nshell + 1));
   double *arec = reinterpret_cast<double *>(w);
+  w += align256(sizeof(double) * AREC * aux->nshell);
+  // masked only: kept-pair counters and lists of the (l_a, l_b) classes
+  unsigned long long *pcount = reinterpret_cast<unsigned long long *>(w);
+  w += align256(sizeof(unsigned long long) * NLA * NLA);
+  int64_t *plist = reinterpret_cast<int64_t *>(w);
   if (hipMemcpyAsync(orb_sorted, p.orb_sorted.data(), sizeof(int32_t) * orb->nshell,
                      hipMemcpyHostToDevice, s) != hipSuccess ||
       hipMemcpyAsync(aux_sorted, p.aux_sorted.data(), sizeof(int32_t) * aux->nshell,
@@ -606,33 +665,117 @@ int df3c_coulomb_J(const double *xyz, int32_t natom, const df3c_shells *aux,
   a.J = J;
   a.nao = p.nao;
   a.pure = aux->pure;
-  for (int lp = 0; lp <= DF3C_LMAX_AUX; ++lp) {
+  auto launch = [&](int lp, int la, int lb) -> int {
     const int np = p.aux_start[lp + 1] - p.aux_start[lp];
-    if (!np) continue;
+    if (!np) return DF3C_OK;
     a.psh = aux_sorted + p.aux_start[lp];
     a.arec = arec + int64_t(p.aux_start[lp]) * AREC;
     a.np = np;
+    const ClassInfo &ci = g_cls[lp][la][lb];
+    const int c = (lp * NLA + la) * NLA + lb;
+    a.nsub = reg_split(ci, a.npair, a.np, ds->ncu);
+    if (timed(DF3C_KERNEL_J, c, s, [&] {
+          return ci.jfn(a, grid_for(a.npair, ci.tpwj / a.nsub, ds->ncu), s);
+        }) != hipSuccess)
+      return DF3C_E_HIP;
+    return DF3C_OK;
+  };
+  auto set_class = [&](int la, int lb) {
+    const int na = p.orb_start[la + 1] - p.orb_start[la];
+    const int nb = p.orb_start[lb + 1] - p.orb_start[lb];
+    a.ash = orb_sorted + p.orb_start[la];
+    a.bsh = orb_sorted + p.orb_start[lb];
+    a.na = na;
+    a.nb = nb;
+    a.same = (la == lb);
+    a.npair = (la == lb) ? int64_t(na) * (na + 1) / 2 : int64_t(na) * nb;
+    return na > 0 && nb > 0;
+  };
+  if (!mask) {
+    for (int lp = 0; lp <= DF3C_LMAX_AUX; ++lp)
+      for (int la = 0; la <= DF3C_LMAX_ORB; ++la)
+        for (int lb = 0; lb <= la; ++lb)
+          if (set_class(la, lb) && (rc = launch(lp, la, lb))) return rc;
+    return DF3C_OK;
+  }
+  // masked: the kept pairs of every (l_a, l_b) class are compacted into the
+  // class's list, the counts read back once (they size the launches), then
+  // every l_P class runs over the list (each J element still sums l_P in
+  // ascending order)
+  int64_t loff[NLA][NLA] = {};
+  {
+    int64_t o = 0;
+    hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, s, reinterpret_cast<int *>(pcount),
+                       2 * NLA * NLA, 0);
     for (int la = 0; la <= DF3C_LMAX_ORB; ++la)
       for (int lb = 0; lb <= la; ++lb) {
-        const int na = p.orb_start[la + 1] - p.orb_start[la];
-        const int nb = p.orb_start[lb + 1] - p.orb_start[lb];
-        if (!na || !nb) continue;
-        a.ash = orb_sorted + p.orb_start[la];
-        a.bsh = orb_sorted + p.orb_start[lb];
-        a.na = na;
-        a.nb = nb;
-        a.same = (la == lb);
-        a.npair = (la == lb) ? int64_t(na) * (na + 1) / 2 : int64_t(na) * nb;
-        const ClassInfo &ci = g_cls[lp][la][lb];
-        const int c = (lp * NLA + la) * NLA + lb;
-        a.nsub = reg_split(ci, a.npair, a.np, ds->ncu);
-        if (timed(DF3C_KERNEL_J, c, s, [&] {
-              return ci.jfn(a, grid_for(a.npair, ci.tpwj / a.nsub, ds->ncu), s);
-            }) != hipSuccess)
-          return DF3C_E_HIP;
+        loff[la][lb] = o;
+        if (!set_class(la, lb)) continue;
+        const int g = int(std::min<int64_t>((a.npair + 255) / 256, 4096));
+        hipLaunchKernelGGL(k_pair_compact, dim3(g), dim3(256), 0, s, a.ash, a.bsh, a.nb, a.same,
+                           a.npair, mask, orb->nshell, plist + o, pcount + la * NLA + lb);
+        if (hipGetLastError() != hipSuccess) return DF3C_E_HIP;
+        o += a.npair;
       }
   }
+  unsigned long long *kept = reinterpret_cast<unsigned long long *>(g_pinned);
+  if (hipMemcpyAsync(kept, pcount, sizeof(unsigned long long) * NLA * NLA, hipMemcpyDeviceToHost,
+                     s) != hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess)
+    return DF3C_E_HIP;
+  for (int la = 0; la <= DF3C_LMAX_ORB; ++la)
+    for (int lb = 0; lb <= la; ++lb) {
+      if (!set_class(la, lb)) continue;
+      a.plist = plist + loff[la][lb];
+      a.pcount = reinterpret_cast<const int64_t *>(pcount + la * NLA + lb);
+      a.npair = int64_t(kept[la * NLA + lb]);  // sizes the launch; the kernel reads *pcount
+      if (!a.npair) continue;
+      for (int lp = 0; lp <= DF3C_LMAX_AUX; ++lp)
+        if ((rc = launch(lp, la, lb))) return rc;
+    }
   return DF3C_OK;
+}
+}  // namespace
+
+int df3c_coulomb_J(const double *xyz, int32_t natom, const df3c_shells *aux,
+                   const df3c_shells *orb, const double *d, double *J, void *ws, size_t ws_bytes,
+                   uint32_t flags, void *stream) {
+  (void)flags;
+  if (!xyz || natom <= 0 || !shells_ok(aux) || !shells_ok(orb) || !d || !J) return DF3C_E_ARG;
+  if (orb->pure != 0 || (aux->pure != 0 && aux->pure != 1)) return DF3C_E_UNSUPPORTED;
+  if (!ws || ws_bytes < df3c_coulomb_J_workspace(aux, orb)) return DF3C_E_WORKSPACE;
+  return coulomb_J_run(xyz, natom, aux, orb, d, nullptr, J, ws, reinterpret_cast<hipStream_t>(stream));
+}
+
+int df3c_screen_pairs(const double *xyz, int32_t natom, const df3c_shells *orb, double tau,
+                      uint8_t *mask, void *stream) {
+  if (!xyz || natom <= 0 || !shells_ok(orb) || !mask || !(tau >= 0.0)) return DF3C_E_ARG;
+  DevState *ds = nullptr;
+  int rc = init_device(&ds);
+  if (rc) return rc;
+  if (orb->nshell == 0) return DF3C_OK;
+  const int64_t total = int64_t(orb->nshell) * orb->nshell;
+  const int g = int(std::min<int64_t>((total + 255) / 256, 4096));
+  hipLaunchKernelGGL(k_screen_pairs, dim3(g), dim3(256), 0, reinterpret_cast<hipStream_t>(stream),
+                     xyz, dev_shells(orb), orb->nshell, tau, mask);
+  return hipGetLastError() == hipSuccess ? DF3C_OK : DF3C_E_HIP;
+}
+
+size_t df3c_coulomb_J_masked_workspace(const df3c_shells *aux, const df3c_shells *orb) {
+  if (!aux || !orb || !orb->l_host) return 0;
+  return jplan_bytes(orb->nshell, aux->nshell) + align256(sizeof(unsigned long long) * NLA * NLA) +
+         align256(sizeof(int64_t) * size_t(total_class_pairs(orb)));
+}
+
+int df3c_coulomb_J_masked(const double *xyz, int32_t natom, const df3c_shells *aux,
+                          const df3c_shells *orb, const double *d, const uint8_t *mask,
+                          double *J, void *ws, size_t ws_bytes, uint32_t flags, void *stream) {
+  (void)flags;
+  if (!xyz || natom <= 0 || !shells_ok(aux) || !shells_ok(orb) || !d || !J || !mask)
+    return DF3C_E_ARG;
+  if (orb->pure != 0 || (aux->pure != 0 && aux->pure != 1)) return DF3C_E_UNSUPPORTED;
+  if (!ws || ws_bytes < df3c_coulomb_J_masked_workspace(aux, orb)) return DF3C_E_WORKSPACE;
+  return coulomb_J_run(xyz, natom, aux, orb, d, mask, J, ws, reinterpret_cast<hipStream_t>(stream));
 }
 
 

@@ -77,6 +77,10 @@ def lib():
         L.df3c_coulomb_J_workspace.restype = SZ
         L.df3c_coulomb_J_workspace.argtypes = [P, P]
         L.df3c_coulomb_J.argtypes = [P, I32, P, P, P, P, P, SZ, U32, P]
+        L.df3c_screen_pairs.argtypes = [P, I32, P, ctypes.c_double, P, P]
+        L.df3c_coulomb_J_masked_workspace.restype = SZ
+        L.df3c_coulomb_J_masked_workspace.argtypes = [P, P]
+        L.df3c_coulomb_J_masked.argtypes = [P, I32, P, P, P, P, P, P, SZ, U32, P]
         L.df3c_coulomb_J_grad_workspace.restype = SZ
         L.df3c_coulomb_J_grad_workspace.argtypes = [P, P, I32]
         L.df3c_coulomb_J_grad.argtypes = [P, I32, P, P, P, P, P, P, SZ, U32, P]
@@ -191,6 +195,42 @@ def coulomb_J(xyz: torch.Tensor, aux: DeviceBasis, orb: DeviceBasis, d: torch.Te
     _check(lib().df3c_coulomb_J(_ptr(xyz), int(xyz.shape[0]), ctypes.byref(sa), ctypes.byref(so),
                                 _ptr(d), _ptr(J), _ptr(ws), ws.numel(), flags, _stream(stream)),
            "df3c_coulomb_J")
+    return J
+
+
+def screen_pairs(xyz: torch.Tensor, orb: DeviceBasis, tau: float, mask: Optional[torch.Tensor] = None,
+                 stream=None) -> torch.Tensor:
+    """Shell-pair mask (nshell x nshell, uint8, symmetric): 1 where the largest
+    primitive overlap bound of the pair is >= tau."""
+    n = orb.nshell
+    if mask is None:
+        mask = torch.empty((n, n), dtype=torch.uint8, device=xyz.device)
+    so = orb.struct()
+    _check(lib().df3c_screen_pairs(_ptr(xyz), int(xyz.shape[0]), ctypes.byref(so), float(tau),
+                                   _ptr(mask), _stream(stream)), "df3c_screen_pairs")
+    return mask
+
+
+def coulomb_J_masked_workspace(aux: DeviceBasis, orb: DeviceBasis) -> int:
+    sa, so = aux.struct(), orb.struct()
+    return int(lib().df3c_coulomb_J_masked_workspace(ctypes.byref(sa), ctypes.byref(so)))
+
+
+def coulomb_J_masked(xyz: torch.Tensor, aux: DeviceBasis, orb: DeviceBasis, d: torch.Tensor,
+                     mask: torch.Tensor, J: Optional[torch.Tensor] = None,
+                     ws: Optional[torch.Tensor] = None, flags: int = 0, stream=None) -> torch.Tensor:
+    """J over the shell pairs the mask keeps (the other blocks zero)."""
+    nao = int(orb.offsets()[-1])
+    if J is None:
+        J = torch.empty((nao, nao), dtype=torch.float64, device=xyz.device)
+    need = coulomb_J_masked_workspace(aux, orb)
+    if ws is None or ws.numel() < need:
+        ws = torch.empty(max(need, 1), dtype=torch.uint8, device=xyz.device)
+    sa, so = aux.struct(), orb.struct()
+    _check(lib().df3c_coulomb_J_masked(_ptr(xyz), int(xyz.shape[0]), ctypes.byref(sa),
+                                       ctypes.byref(so), _ptr(d), _ptr(mask), _ptr(J), _ptr(ws),
+                                       ws.numel(), flags, _stream(stream)),
+           "df3c_coulomb_J_masked")
     return J
 
 
