@@ -309,35 +309,6 @@ struct GamE {
   static constexpr int TEAM = PW + 3 * (LB + 1);      // doubles before the accumulators
 };
 
-// w_e = sum_{a,b} D~_ab sum_{i <= b} [a + i = e] C(b,i) AB^{b-i} (e by its flat
-// index relative to level LA): the HRR of the class transposed onto D~
-template <int LA, int LB>
-__device__ __forceinline__ double gam_w(int ef, const double *DT, const double *PW) {
-  static_assert(LB <= 5, "binomial table");
-  int lev = LA;
-  while (offT(lev + 1) - offT(LA) <= ef) ++lev;
-  const C3 e = cart(lev, ef - (offT(lev) - offT(LA)));
-  const int k = lev - LA;  // |i|
-  double v = 0.0;
-#pragma unroll
-  for (int bi = 0; bi < ncart(LB); ++bi) {
-    const C3 b = cart(LB, bi);
-    for (int ix = 0; ix <= b[0] && ix <= k; ++ix) {
-      const int a0 = e[0] - ix;
-      if (a0 < 0) continue;
-      for (int iy = 0; iy <= b[1] && ix + iy <= k; ++iy) {
-        const int iz = k - ix - iy;
-        const int a1 = e[1] - iy, a2 = e[2] - iz;
-        if (iz > b[2] || a1 < 0 || a2 < 0) continue;
-        v += k_binom6[6 * b[0] + ix] * k_binom6[6 * b[1] + iy] * k_binom6[6 * b[2] + iz] *
-             DT[cidx(a0, a1, a2) * ncart(LB) + bi] * PW[b[0] - ix] * PW[(LB + 1) + b[1] - iy] *
-             PW[2 * (LB + 1) + b[2] - iz];
-      }
-    }
-  }
-  return v;
-}
-
 template <int LP, int LA, int LB>
 __global__ void __launch_bounds__(64)
     __attribute__((amdgpu_waves_per_eu(DF3C_MIN_WAVES_WAVE))) k_gam_e(GamArgs g) {
@@ -390,7 +361,17 @@ __global__ void __launch_bounds__(64)
         }
       }
       team_sync();
-      for (int e = tid; e < NE; e += TS) Wv[e] = gam_w<LA, LB>(e, DT, PW);
+      // w_e, the HRR transposed onto D~, from the generated terms
+      for (int e = tid; e < NE; e += TS) {
+        using TW = GenHrrT<LA, LB>;
+        double v = 0.0;
+        for (int q = TW::w_start[e]; q < TW::w_start[e + 1]; ++q) {
+          const uint32_t t = TW::w_t[q];
+          v += double(t >> 24) * DT[t & 0xfffu] * PW[(t >> 20) & 0xfu] *
+               PW[(LB + 1) + ((t >> 16) & 0xfu)] * PW[2 * (LB + 1) + ((t >> 12) & 0xfu)];
+        }
+        Wv[e] = v;
+      }
       team_sync();
       const int Kab = Ka * Kb;
       // the pair's primitive triplets over the subset's aux shells, in

@@ -319,6 +319,77 @@ def gy_terms(LP, EA, EB):
     return start, co, hu, vi
 
 
+def omega_terms(LA, LB):
+    """Per weight vector j = 3 s + x (shift s = A+, B+, A-, B-; direction x)
+    and target e (levels max(LA-1,0) .. LA+LB+1, flat order): the terms
+    (integer coefficient, AB exponents (px, py, pz), G~ index a NB + b) of
+      omega^{s,x}_e = sum_ab G~_ab sum_i [shifted a + i = e] C(b', i) AB^{b'-i}
+    (the HRRs of the four shifted blocks transposed onto G~; the coefficient
+    holds the binomials and the a_x or b_x factor of the lowered blocks)."""
+    EA, EB = max(LA - 1, 0), LA + LB + 1
+    es = [e for lev in range(EA, EB + 1) for e in carts(lev)]
+    NB = ncart(LB)
+    start, co, pw, ab = [], [], [], []
+    for j in range(12):
+        s, x = divmod(j, 3)
+        las = LA + 1 if s == 0 else LA - 1 if s == 2 else LA
+        for e in es:
+            start.append(len(co))
+            k = sum(e) - las
+            if k < 0:
+                continue
+            for bi, b in enumerate(carts(LB)):
+                bb = list(b)
+                cb = 1
+                if s == 1:
+                    bb[x] += 1
+                if s == 3:
+                    if b[x] == 0:
+                        continue
+                    cb = b[x]
+                    bb[x] -= 1
+                for i in carts(k):
+                    if any(i[t] > bb[t] for t in range(3)):
+                        continue
+                    a = [e[t] - i[t] for t in range(3)]
+                    if s == 0:
+                        a[x] -= 1
+                    if s == 2:
+                        a[x] += 1
+                    if min(a) < 0:
+                        continue
+                    ca = a[x] if s == 2 else 1
+                    co.append(ca * cb * math.prod(math.comb(bb[t], i[t]) for t in range(3)))
+                    pw.append(tuple(bb[t] - i[t] for t in range(3)))
+                    ab.append(cidx(tuple(a)) * NB + bi)
+    start.append(len(co))
+    return start, co, pw, ab
+
+
+def hrrt_terms(LA, LB):
+    """Per target e (levels LA .. LA+LB, flat order): the terms (C(b,i)
+    product, AB exponents b - i, D~ index a NB + b) of the HRR transposed onto
+    D~, w_e = sum_ab D~_ab sum_i [a + i = e] C(b,i) AB^{b-i} (gamma engine)."""
+    NB = ncart(LB)
+    start, co, pw, ab = [], [], [], []
+    for lev in range(LA, LA + LB + 1):
+        for e in carts(lev):
+            start.append(len(co))
+            k = lev - LA
+            for bi, b in enumerate(carts(LB)):
+                for i in carts(k):
+                    if any(i[t] > b[t] for t in range(3)):
+                        continue
+                    a = tuple(e[t] - i[t] for t in range(3))
+                    if min(a) < 0:
+                        continue
+                    co.append(math.prod(math.comb(b[t], i[t]) for t in range(3)))
+                    pw.append(tuple(b[t] - i[t] for t in range(3)))
+                    ab.append(cidx(a) * NB + bi)
+    start.append(len(co))
+    return start, co, pw, ab
+
+
 def grad_geometries():
     """(LP, EA, EB) = (L_P, max(l_a - 1, 0), l_a + l_b + 1) of the gradient
     classes (l_a >= l_b, up to the gradient's orbital limit)."""
@@ -569,6 +640,27 @@ def write(outdir):
             s.append(arr("int8_t", "hc_pow", hp))
             s.append(arr("int16_t", "hc_binom", hb))
             s.append(arr("int16_t", "e", e))
+            s.append("};\n")
+    for la in range(LMAX_GRAD_ORB + 1):
+        for lb in range(la + 1):
+            st, co, pw, ab = omega_terms(la, lb)
+            s.append(f"template <> struct GenOmega<{la}, {lb}> {{\n")
+            s.append(arr("int32_t", "o_start", st))
+            # one word per term: coefficient << 24 | px << 20 | py << 16 | pz << 12 | G~ index
+            assert max(co, default=0) < 256 and max(ab, default=0) < 4096
+            assert max((max(p) for p in pw), default=0) < 16
+            s.append(arr("uint32_t", "o_t", [(c << 24) | (p[0] << 20) | (p[1] << 16) | (p[2] << 12) | i
+                                             for c, p, i in zip(co, pw, ab)]))
+            s.append("};\n")
+    for la in range(LMAX_ORB + 1):
+        for lb in range(la + 1):
+            st, co, pw, ab = hrrt_terms(la, lb)
+            s.append(f"template <> struct GenHrrT<{la}, {lb}> {{\n")
+            s.append(arr("int32_t", "w_start", st))
+            # one word per term: coefficient << 24 | px << 20 | py << 16 | pz << 12 | D~ index
+            assert max(co, default=0) < 256 and max(ab, default=0) < 4096
+            s.append(arr("uint32_t", "w_t", [(c << 24) | (p[0] << 20) | (p[1] << 16) | (p[2] << 12) | i
+                                             for c, p, i in zip(co, pw, ab)]))
             s.append("};\n")
     for L in range(2 * LMAX_ORB + 2):
         items = vtab(L)

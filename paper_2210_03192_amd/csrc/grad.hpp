@@ -439,47 +439,6 @@ struct GEng {
   }
 };
 
-// omega^{s,x}_e (j = 3 s + x; e given by its flat index relative to level EA):
-// a gather over b and i <= b' (b' = b, b + 1_x or b - 1_x) with |i| = |e| - l_a'
-template <int LA, int LB, int EA>
-__device__ __forceinline__ double grad_omega(int j, int ef, const double *GT, const double *PW) {
-  static_assert(LB + 1 <= 5, "binomial table");
-  int lev = EA;
-  while (offT(lev + 1) - offT(EA) <= ef) ++lev;
-  const C3 e = cart(lev, ef - (offT(lev) - offT(EA)));
-  const int s = j / 3, x = j - 3 * s;
-  const int las = s == 0 ? LA + 1 : s == 2 ? LA - 1 : LA;
-  const int k = lev - las;  // |i|
-  if (k < 0) return 0.0;
-  const int dbx = x == 0, dby = x == 1, dbz = x == 2;
-  const int sg = s == 1 ? 1 : s == 3 ? -1 : 0;   // b' = b + sg 1_x
-  const int sa = s == 0 ? -1 : s == 2 ? 1 : 0;   // a = e - i + sa 1_x
-  double v = 0.0;
-#pragma unroll
-  for (int bi = 0; bi < ncart(LB); ++bi) {
-    constexpr int NBc = ncart(LB);
-    const C3 b = cart(LB, bi);
-    const int bxs = x == 0 ? b[0] : x == 1 ? b[1] : b[2];
-    if (s == 3 && bxs == 0) continue;
-    const int b0 = b[0] + sg * dbx, b1 = b[1] + sg * dby, b2 = b[2] + sg * dbz;
-    const double cb = s == 3 ? double(bxs) : 1.0;
-    for (int ix = 0; ix <= b0 && ix <= k; ++ix) {
-      const int a0 = e[0] - ix + sa * dbx;
-      if (a0 < 0) continue;
-      for (int iy = 0; iy <= b1 && ix + iy <= k; ++iy) {
-        const int iz = k - ix - iy;
-        const int a1 = e[1] - iy + sa * dby, a2 = e[2] - iz + sa * dbz;
-        if (iz > b2 || a1 < 0 || a2 < 0) continue;
-        const double ca = s == 2 ? double(x == 0 ? a0 : x == 1 ? a1 : a2) : 1.0;
-        v += ca * cb * k_binom6[6 * b0 + ix] * k_binom6[6 * b1 + iy] * k_binom6[6 * b2 + iz] *
-             GT[cidx(a0, a1, a2) * NBc + bi] * PW[b0 - ix] * PW[(LB + 2) + b1 - iy] *
-             PW[2 * (LB + 2) + b2 - iz];
-      }
-    }
-  }
-  return v;
-}
-
 template <int LP, int LA, int LB>
 __global__ void __launch_bounds__(64)
     __attribute__((amdgpu_waves_per_eu(DF3C_MIN_WAVES_WAVE))) k_grade(GradArgs g) {
@@ -545,8 +504,17 @@ __global__ void __launch_bounds__(64)
       }
     }
     team_sync();
-    for (int it = tid; it < 12 * NY; it += TS)
-      OM[it] = grad_omega<LA, LB, E::EA>(it / NY, it - (it / NY) * NY, GT, PW);
+    // omega from the generated terms: coefficient x G~_ab x AB^p per term
+    for (int it = tid; it < 12 * NY; it += TS) {
+      using TO = GenOmega<LA, LB>;
+      double v = 0.0;
+      for (int q = TO::o_start[it]; q < TO::o_start[it + 1]; ++q) {
+        const uint32_t t = TO::o_t[q];
+        v += double(t >> 24) * GT[t & 0xfffu] * PW[(t >> 20) & 0xfu] *
+             PW[(LB + 2) + ((t >> 16) & 0xfu)] * PW[2 * (LB + 2) + ((t >> 12) & 0xfu)];
+      }
+      OM[it] = v;
+    }
     team_sync();
 
     double GA = 0.0, GB = 0.0;  // lanes 0..2: direction x = tid

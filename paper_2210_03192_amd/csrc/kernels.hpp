@@ -724,11 +724,6 @@ __global__ void __launch_bounds__(TS > 64 ? TS : 64)
   }
 }
 
-// binomial coefficients C(n, k) for n <= 5 (row n at 6 n)
-static __device__ const double k_binom6[36] = {
-    1, 0, 0, 0, 0, 0, 1, 1, 0, 0, 0, 0, 1, 2, 1, 0, 0, 0,
-    1, 3, 3, 1, 0, 0, 1, 4, 6, 4, 1, 0, 1, 5, 10, 10, 5, 1};
-
 // ---------------------------------------------------------------------------
 // HRR orientation of a pair of equal l: the VRR1 quanta go to the shell with
 // the larger (max exponent x min exponent), for which the Gaussian product

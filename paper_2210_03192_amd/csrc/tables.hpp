@@ -171,6 +171,8 @@ struct alignas(16) VO {
 //   GenY<LP, EA, EB>:   per-primitive digested ket of the derivative engine
 template <int LP, int EA, int EB> struct GenTab;
 template <int LP, int EA, int EB> struct GenY;
+template <int LA, int LB> struct GenOmega;  // transposed shifted HRRs of the gradient engine
+template <int LA, int LB> struct GenHrrT;   // HRR transposed onto D~ (gamma engine)
 template <int l> struct GenSolid;
 template <int LA, int LB> struct GenHrr;
 template <int L> struct GenV;

@@ -86,3 +86,18 @@ def test_gamma_engine_table_shapes():
                 gs, gc, ge, gv = gt.gg_terms(geo)
                 assert len(gs) - 1 == gt.offT(min(LP, la + lb) + 1)
                 assert max(ge, default=0) < gt.offT(la + lb + 1) - gt.offT(la)
+
+
+@pytest.mark.parametrize("la,lb", [(0, 0), (2, 1), (3, 2), (3, 3), (4, 4), (4, 0)])
+def test_hrrt_term_table_matches_gather(la, lb):
+    """The generated terms of the HRR transposed onto D~ (GenHrrT) give w_e of
+    the gather above for a random D~ and AB."""
+    rng = np.random.default_rng(760 + 5 * la + lb)
+    Dt = rng.normal(size=(gt.ncart(la), gt.ncart(lb)))
+    AB = rng.uniform(-1.5, 1.5, 3)
+    ref = _w(la, lb, Dt, AB)
+    st, co, pw, ab = gt.hrrt_terms(la, lb)
+    flat = Dt.reshape(-1)
+    got = np.array([sum(co[q] * flat[ab[q]] * np.prod(AB ** np.array(pw[q]))
+                        for q in range(st[i], st[i + 1])) for i in range(len(st) - 1)])
+    np.testing.assert_allclose(got, ref, rtol=1e-12, atol=1e-14 * np.abs(ref).max())

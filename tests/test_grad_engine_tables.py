@@ -179,3 +179,18 @@ def test_grad_engine_y_table_terms():
                                         for z in range(e[2] + 1)] if sum(u) <= LP)
                 got = sorted(zip(yh[ys[ei]:ys[ei + 1]], yv[ys[ei]:ys[ei + 1]], yc[ys[ei]:ys[ei + 1]]))
                 assert got == want
+
+
+@pytest.mark.parametrize("la,lb", [(0, 0), (1, 0), (1, 1), (2, 1), (2, 2), (3, 1), (3, 2), (3, 3)])
+def test_omega_term_table_matches_gather(la, lb):
+    """The generated terms of the transposed shifted HRRs (GenOmega) give the
+    twelve weight vectors of the gather above for a random G~ and AB."""
+    rng = np.random.default_rng(960 + 5 * la + lb)
+    Gt = rng.normal(size=(gt.ncart(la), gt.ncart(lb)))
+    AB = rng.uniform(-1.5, 1.5, 3)
+    ref = _omegas(la, lb, Gt, AB)
+    st, co, pw, ab = gt.omega_terms(la, lb)
+    flat = Gt.reshape(-1)
+    got = np.array([sum(co[q] * flat[ab[q]] * np.prod(AB ** np.array(pw[q]))
+                        for q in range(st[i], st[i + 1])) for i in range(len(st) - 1)])
+    np.testing.assert_allclose(got, ref.reshape(-1), rtol=1e-12, atol=1e-14 * np.abs(ref).max())
