@@ -282,7 +282,7 @@ __global__ void __launch_bounds__(64) k_gam_r(GamArgs g) {
 }
 
 // ---------------------------------------------------------------------------
-// Gamma engine (classes beyond the register engine): one wavefront per item
+// Gamma engine (classes beyond the register engine): one workgroup per item
 // (range of shell pairs, subset of the aux shells), the pairs of the range in
 // turn.  Per pair the HRR is transposed onto D~ once (w_e, lanes over e); the
 // pair's primitive triplets over the subset's aux shells are cut into chunks
@@ -310,13 +310,13 @@ struct GamE {
 };
 
 template <int LP, int LA, int LB>
-__global__ void __launch_bounds__(64)
+__global__ void __launch_bounds__(ENG_TS)
     __attribute__((amdgpu_waves_per_eu(DF3C_MIN_WAVES_WAVE))) k_gam_e(GamArgs g) {
   using E = GamE<LP, LA, LB>;
   using G = typename E::G;
   using SH = GenSolid<LP>;
   using TB = GenTab<LP, LA, LA + LB>;
-  constexpr int TS = 64, PCH = E::PCH, REC = E::REC, NU = E::NU, NE = E::NE;
+  constexpr int TS = ENG_TS, PCH = E::PCH, REC = E::REC, NU = E::NU, NE = E::NE;
   constexpr int NA = E::NA, NB = E::NB, NCP = E::NCP;
   extern __shared__ double smem[];
   double *prims = smem, *SLK = smem + E::SL, *Yc = smem + E::YC, *Wv = smem + E::W;

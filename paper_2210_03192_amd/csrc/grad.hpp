@@ -391,7 +391,7 @@ __global__ void __launch_bounds__(64) k_gradr(GradArgs g) {
 namespace df3c {
 
 // ---------------------------------------------------------------------------
-// Gradient engine (classes beyond the register engine): one wavefront per
+// Gradient engine (classes beyond the register engine): one workgroup per
 // work item (shell pair, subset of the aux shells).  The HRRs of the four
 // shifted classes are transposed onto G~ once per pair, giving twelve weight
 // vectors over the targets e (shift s = A+, B+, A-, B-, direction x):
@@ -440,13 +440,13 @@ struct GEng {
 };
 
 template <int LP, int LA, int LB>
-__global__ void __launch_bounds__(64)
+__global__ void __launch_bounds__(ENG_TS)
     __attribute__((amdgpu_waves_per_eu(DF3C_MIN_WAVES_WAVE))) k_grade(GradArgs g) {
   using E = GEng<LP, LA, LB>;
   using G = typename E::G;
   using SH = GenSolid<LP>;
   using TY = GenY<LP, E::EA, E::EB>;
-  constexpr int TS = 64, PCH = E::PCH, REC = E::REC, NY = E::NY, NU = E::NU;
+  constexpr int TS = ENG_TS, PCH = E::PCH, REC = E::REC, NY = E::NY, NU = E::NU;
   constexpr int NA = E::NA, NB = E::NB, NCP = E::NCP;
   extern __shared__ double smem[];
   double *S = smem;

@@ -724,6 +724,10 @@ __global__ void __launch_bounds__(TS > 64 ? TS : 64)
   }
 }
 
+// lanes per work item of the gradient and gamma engines: four waves share one
+// item's LDS (the LDS per item, not the lanes, bounds the items per CU)
+constexpr int ENG_TS = 256;
+
 // ---------------------------------------------------------------------------
 // HRR orientation of a pair of equal l: the VRR1 quanta go to the shell with
 // the larger (max exponent x min exponent), for which the Gaussian product

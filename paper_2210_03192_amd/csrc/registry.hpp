@@ -84,7 +84,7 @@ hipError_t launch_gam(const GamArgs &a, int grid, hipStream_t s) {
     if (attr != hipSuccess) return attr;
     const int lds = (E::TEAM + a.nps * E::NCP) * 8;
     if (lds > 160 * 1024) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(kern, dim3(grid), dim3(64), lds, s, a);
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(ENG_TS), lds, s, a);
   }
   return hipGetLastError();
 }
@@ -116,7 +116,7 @@ hipError_t launch_grade(const GradArgs &a, int grid, int lds, hipStream_t s) {
   static const hipError_t attr = hipFuncSetAttribute(
       reinterpret_cast<const void *>(kern), hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
   if (attr != hipSuccess) return attr;
-  hipLaunchKernelGGL(kern, dim3(grid), dim3(64), lds, s, a);
+  hipLaunchKernelGGL(kern, dim3(grid), dim3(ENG_TS), lds, s, a);
   return hipGetLastError();
 }
 
@@ -143,7 +143,7 @@ GradInfo grad_info() {
     g.tpb = 1;
     g.team = GEng<LP, LA, LB>::TEAM;
     g.ppw = 1;
-    g.wpb = 1;
+    g.wpb = ENG_TS / 64;
     g.min_aux = 8;
     g.gfn = &launch_grade<LP, LA, LB>;
   }
