@@ -301,6 +301,9 @@ struct GamE {
   static constexpr int HU = PS_N + G::NV1 + G::NSW;   // record: scalars, VRR1, sW, G
   static constexpr int REC = HU + G::NSW;
   static constexpr int PCH = REC <= 200 ? 16 : 8;
+  // lanes per item: four waves where a primitive carries much work (measured
+  // on the water clusters), one wave for the (l_P <= 3, l_a l_b <= 3 2) classes
+  static constexpr int TS = (LP >= 4 || LB >= 3) ? ENG_TS : 64;
   static constexpr int SL = PCH * REC;                // aux-shell slot of each primitive
   static constexpr int YC = SL + PCH;                 // y [PCH][NCP]
   static constexpr int W = YC + PCH * NCP;            // w_e of the pair
@@ -310,13 +313,13 @@ struct GamE {
 };
 
 template <int LP, int LA, int LB>
-__global__ void __launch_bounds__(ENG_TS)
+__global__ void __launch_bounds__((GamE<LP, LA, LB>::TS))
     __attribute__((amdgpu_waves_per_eu(DF3C_MIN_WAVES_WAVE))) k_gam_e(GamArgs g) {
   using E = GamE<LP, LA, LB>;
   using G = typename E::G;
   using SH = GenSolid<LP>;
   using TB = GenTab<LP, LA, LA + LB>;
-  constexpr int TS = ENG_TS, PCH = E::PCH, REC = E::REC, NU = E::NU, NE = E::NE;
+  constexpr int TS = E::TS, PCH = E::PCH, REC = E::REC, NU = E::NU, NE = E::NE;
   constexpr int NA = E::NA, NB = E::NB, NCP = E::NCP;
   extern __shared__ double smem[];
   double *prims = smem, *SLK = smem + E::SL, *Yc = smem + E::YC, *Wv = smem + E::W;

@@ -84,7 +84,7 @@ hipError_t launch_gam(const GamArgs &a, int grid, hipStream_t s) {
     if (attr != hipSuccess) return attr;
     const int lds = (E::TEAM + a.nps * E::NCP) * 8;
     if (lds > 160 * 1024) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(kern, dim3(grid), dim3(ENG_TS), lds, s, a);
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(E::TS), lds, s, a);
   }
   return hipGetLastError();
 }
