@@ -1004,7 +1004,9 @@ __device__ __forceinline__ void jeng_pair(const JArgs &a, double *S, int tid, bo
   // order, are cut into chunks of PCH: M sums over aux shells as well, so a
   // chunk may mix shells and every chunk but the last is full.  The cursor
   // (cip, cp) is uniform over the team.
-  auto shell_prims = [&](int ip) { return (valid && ip < a.np) ? Kab * a.aux.nprim[a.psh[ip]] : 0; };
+  auto shell_prims = [&](int ip) {
+    return (valid && ip < a.np) ? Kab * int(a.arec[int64_t(ip) * AREC + AR_K]) : 0;
+  };
   int cip = 0, cp = 0, cK = shell_prims(0);
   while (cip < np_loop && cK == 0) cK = shell_prims(++cip);
   while (cip < np_loop) {
@@ -1026,23 +1028,14 @@ __device__ __forceinline__ void jeng_pair(const JArgs &a, double *S, int tid, bo
     }
     int lt = tid;
     __asm__ volatile("" : "+v"(lt));
-    // d' of the aux shell of every slot
+    // d' of the aux shell of every slot, from the shell's record
     for (int it = lt; it < npc * G::NCP; it += TS) {
       const int pp = it / G::NCP, c = it - pp * G::NCP;
       int ip = sl_ip[0];
 #pragma unroll
       for (int q = 1; q < PCH; ++q)
         if (pp == q) ip = sl_ip[q];
-      const double *dP = a.d + a.aux_off[a.psh[ip]];
-      double v;
-      if (a.pure) {
-        v = 0.0;
-#pragma unroll
-        for (int m = 0; m < G::NPURE; ++m) v += dP[m] * SH::dense[m * G::NCP + c];
-      } else {
-        v = dP[c];
-      }
-      DP[pp * G::NCP + c] = v;
+      DP[pp * G::NCP + c] = a.arec[int64_t(ip) * AREC + AR_DQ + c];
     }
     // one lane per slot: record setup (primitive of its own aux shell)
     if (lt < npc) {
@@ -1053,11 +1046,10 @@ __device__ __forceinline__ void jeng_pair(const JArgs &a, double *S, int tid, bo
           ip = sl_ip[q];
           p = sl_p[q];
         }
-      const int sP = a.psh[ip];
-      const int Kc = a.aux.nprim[sP];
-      const int64_t oc = a.aux.prim_off[sP];
-      const int ic = a.aux.atom[sP];
-      const double Cr[3] = {a.xyz[3 * ic], a.xyz[3 * ic + 1], a.xyz[3 * ic + 2]};
+      const double *rc = a.arec + int64_t(ip) * AREC;
+      const int Kc = int(rc[AR_K]);
+      const int64_t oc = int64_t(rc[AR_PRIM]);
+      const double Cr[3] = {rc[AR_CX], rc[AR_CY], rc[AR_CZ]};
       setup_prim<G, 0>(a.boys, prims + lt * REC, p, Kb, Kc, Ar, Br, Cr, AB2, a.orb.exps + oa,
                        a.orb.coefs + oa, a.orb.exps + ob, a.orb.coefs + ob, a.aux.exps + oc,
                        a.aux.coefs + oc);
