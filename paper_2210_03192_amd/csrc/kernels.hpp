@@ -114,6 +114,13 @@ struct Layout {
 
 // Small classes whose J runs on the register engine (jr_pair): VRR1 over all
 // m, the d-contracted ket and X fit the registers of one lane.
+// limits of the register J engine: l_a + l_b and the live doubles per lane
+#ifndef DF3C_JREG_LMAX
+#define DF3C_JREG_LMAX 6
+#endif
+#ifndef DF3C_JREG_COST
+#define DF3C_JREG_COST 300
+#endif
 template <int LP, int LA, int LB>
 struct JReg {
   static constexpr int L = LA + LB, EA = LA, EB = LA + LB;
@@ -128,7 +135,7 @@ struct JReg {
   }
   static constexpr int NVR = voff(L + 1);
   static constexpr int COST = ncart(LP) + NU + NE + NVR;
-  static constexpr bool OK = L <= 4 && COST <= 160;
+  static constexpr bool OK = L <= DF3C_JREG_LMAX && COST <= DF3C_JREG_COST;
 };
 
 template <class G>
