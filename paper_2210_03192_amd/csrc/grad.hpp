@@ -65,10 +65,10 @@ __device__ __forceinline__ int64_t grad_blocks(const GradArgs &g, int tpb) {
 // end, so the per-workgroup atom array is filled in a fixed order.
 // ---------------------------------------------------------------------------
 #ifndef DF3C_GREG_LMAX
-#define DF3C_GREG_LMAX 4
+#define DF3C_GREG_LMAX 5
 #endif
 #ifndef DF3C_GREG_COST
-#define DF3C_GREG_COST 170
+#define DF3C_GREG_COST 260
 #endif
 
 template <int LP, int LA, int LB>
