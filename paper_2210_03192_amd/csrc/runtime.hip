@@ -628,10 +628,14 @@ int coulomb_J_run(const double *xyz, int32_t natom, const df3c_shells *aux,
   w += align256(sizeof(int64_t) * (aux->nshell + 1));
   double *arec = reinterpret_cast<double *>(w);
   w += align256(sizeof(double) * AREC * aux->nshell);
-  // masked only: kept-pair counters and lists of the (l_a, l_b) classes
-  unsigned long long *pcount = reinterpret_cast<unsigned long long *>(w);
-  w += align256(sizeof(unsigned long long) * NLA * NLA);
-  int64_t *plist = reinterpret_cast<int64_t *>(w);
+  // masked only (its workspace is larger): kept-pair counters and lists of
+  // the (l_a, l_b) classes
+  unsigned long long *pcount = nullptr;
+  int64_t *plist = nullptr;
+  if (mask) {
+    pcount = reinterpret_cast<unsigned long long *>(w);
+    plist = reinterpret_cast<int64_t *>(w + align256(sizeof(unsigned long long) * NLA * NLA));
+  }
   if (hipMemcpyAsync(orb_sorted, p.orb_sorted.data(), sizeof(int32_t) * orb->nshell,
                      hipMemcpyHostToDevice, s) != hipSuccess ||
       hipMemcpyAsync(aux_sorted, p.aux_sorted.data(), sizeof(int32_t) * aux->nshell,
