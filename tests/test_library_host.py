@@ -62,3 +62,14 @@ def test_workspace_sizes(lib):
     a = lib.df3c_eval_batch_workspace(0)
     b = lib.df3c_eval_batch_workspace(100000)
     assert 0 < a < b
+
+
+def test_screening_entry_points_reject_bad_arguments(lib):
+    # null pointers, a null mask and a negative or NaN threshold are rejected
+    # before any HIP call
+    assert lib.df3c_screen_pairs(None, 1, None, ctypes.c_double(1e-12), None, None) == -1
+    assert lib.df3c_coulomb_J_masked(None, 1, None, None, None, None, None, None, 0, 0, None) == -1
+    buf = (ctypes.c_double * 3)()
+    assert lib.df3c_screen_pairs(buf, 1, None, ctypes.c_double(-1.0), buf, None) == -1
+    assert lib.df3c_screen_pairs(buf, 1, None, ctypes.c_double(float("nan")), buf, None) == -1
+    assert lib.df3c_coulomb_J_masked_workspace(None, None) == 0
