@@ -53,7 +53,7 @@ def _lib(precision="double"):
         lib.oracle_coulomb_metric.argtypes = [P, P, P, ctypes.c_int]
         lib.oracle_coulomb_J_pairs.argtypes = [P, P, P, P, ctypes.c_int64, P, P, P,
                                                ctypes.c_int]
-        lib.oracle_coulomb_J_grad.argtypes = [P, ctypes.c_int32, P, P, P, P, P, P,
+        lib.oracle_coulomb_J_grad.argtypes = [P, ctypes.c_int32, P, P, P, P, P, P, P,
                                               ctypes.c_int]
         _LIBS[name] = lib
     return _LIBS[name]
@@ -207,15 +207,22 @@ def coulomb_J_pairs(xyz, aux, orb, d, pairs, nthreads=0, precision="double"):
             for o, s, (a, b) in zip(off, sizes, pairs)]
 
 
-def coulomb_J_grad(xyz, aux, orb, d, G, atom_mask=None, nthreads=0, precision="double"):
+def coulomb_J_grad(xyz, aux, orb, d, G, atom_mask=None, pair_mask=None, nthreads=0,
+                   precision="double"):
+    """dL/dR for L = sum_ab G_ab J_ab; with pair_mask (nshell x nshell) J runs
+    over the kept shell pairs only."""
     xyz = np.ascontiguousarray(xyz, np.float64)
     natom = xyz.shape[0]
     d = np.ascontiguousarray(d, np.float64)
     G = np.ascontiguousarray(G, np.float64)
     grad = np.zeros((natom, 3))
     mask = None if atom_mask is None else np.ascontiguousarray(atom_mask, np.uint8)
+    pm = None if pair_mask is None else np.ascontiguousarray(pair_mask, np.uint8)
+    if pm is not None:
+        assert pm.shape == (len(orb.l), len(orb.l))
     pa, po = _Pinned(aux), _Pinned(orb)
     _check(_lib(precision).oracle_coulomb_J_grad(_ptr(xyz), natom, pa.ref, po.ref, _ptr(d),
                                                  _ptr(G), None if mask is None else _ptr(mask),
+                                                 None if pm is None else _ptr(pm),
                                                  _ptr(grad), int(nthreads)), "coulomb_J_grad")
     return grad

@@ -778,7 +778,8 @@ static void contracted_deriv(const shell_view *P, const shell_view *a, const she
 
 int oracle_coulomb_J_grad(const double *xyz, int32_t natom, const oracle_basis *aux,
                           const oracle_basis *orb, const double *d, const double *G,
-                          const uint8_t *atom_mask, double *grad, int nthreads) {
+                          const uint8_t *atom_mask, const uint8_t *pair_mask, double *grad,
+                          int nthreads) {
   if (check_basis(aux, LMAX_AUX - 2) || check_basis(orb, GRAD_LMAX_ORB) || orb->pure ||
       natom < 0)
     return -1;
@@ -803,6 +804,7 @@ int oracle_coulomb_J_grad(const double *xyz, int32_t natom, const oracle_basis *
 #pragma omp for schedule(dynamic, 1)
     for (int64_t k = 0; k < npair; ++k) {
       int sa = (int)(k / orb->nshell), sb = (int)(k % orb->nshell);
+      if (pair_mask && !pair_mask[k]) continue;
       shell_view a = view(xyz, orb, sa), b = view(xyz, orb, sb);
       if (a.atom < 0 || a.atom >= natom || b.atom < 0 || b.atom >= natom) {
         err = -1;

@@ -89,11 +89,14 @@ int oracle_coulomb_J_pairs(const double *xyz, const oracle_basis *aux,
 /* grad[natom][3] = dL/dR for L = sum_ab G_ab J_ab (d, G fixed).  Derivatives
  * with respect to all three centres are taken explicitly.  If atom_mask is not
  * NULL only triplets with a centre on a masked atom are visited, and only the
- * masked atoms' rows are meaningful. */
+ * masked atoms' rows are meaningful.  If pair_mask (nshell x nshell,
+ * symmetric) is not NULL, J and so L run over the kept orbital shell pairs
+ * only (the screened DF-J). */
 int oracle_coulomb_J_grad(const double *xyz, int32_t natom,
                           const oracle_basis *aux, const oracle_basis *orb,
                           const double *d, const double *G,
-                          const uint8_t *atom_mask, double *grad, int nthreads);
+                          const uint8_t *atom_mask, const uint8_t *pair_mask, double *grad,
+                          int nthreads);
 
 #ifdef __cplusplus
 }

@@ -73,3 +73,29 @@ def test_screening_error_is_small():
     J = oracle.coulomb_J(s.xyz, s.aux, s.orb, d)
     Jm = oracle.coulomb_J_masked(s.xyz, s.aux, s.orb, d, mask)
     assert np.abs(Jm - J).max() <= 1e-8 * np.abs(J).max()
+
+
+def test_masked_gradient_is_the_derivative_of_masked_J():
+    """The oracle's gradient over a pair mask is the derivative of
+    L = sum G_ab J_ab(masked): central differences of the masked J (h = 1e-4),
+    and an all-ones mask gives the full gradient."""
+    s = inputs.water_cluster(2, seed=inputs.SEED_BASE + 407)
+    d = inputs.fitting_coefficients(s.aux.nbf, 408)
+    G = inputs.symmetric_density(s.orb.nbf, 409)
+    mask, _ = oracle.screen_pairs(s.xyz, s.orb, 1e-3)
+    assert 0 < mask.sum() < mask.size
+    n = len(s.orb.l)
+    full = oracle.coulomb_J_grad(s.xyz, s.aux, s.orb, d, G)
+    # (the oracle's threaded reduction order varies, so equal to rounding)
+    np.testing.assert_allclose(
+        oracle.coulomb_J_grad(s.xyz, s.aux, s.orb, d, G, pair_mask=np.ones((n, n), np.uint8)), full,
+        rtol=1e-12, atol=1e-12 * np.abs(full).max())
+    g = oracle.coulomb_J_grad(s.xyz, s.aux, s.orb, d, G, pair_mask=mask)
+    h = 1e-4
+    for at, ax in ((0, 0), (1, 2), (4, 1)):
+        xp, xm = s.xyz.copy(), s.xyz.copy()
+        xp[at, ax] += h
+        xm[at, ax] -= h
+        fd = ((G * oracle.coulomb_J_masked(xp, s.aux, s.orb, d, mask)).sum() -
+              (G * oracle.coulomb_J_masked(xm, s.aux, s.orb, d, mask)).sum()) / (2 * h)
+        assert abs(g[at, ax] - fd) <= 1e-6 * max(1.0, abs(fd))
