@@ -170,6 +170,22 @@ int df3c_coulomb_J_grad(const double *xyz, int32_t natom, const df3c_shells *aux
                         const df3c_shells *orb, const double *d, const double *G, double *grad,
                         void *ws, size_t ws_bytes, uint32_t flags, void *stream);
 
+/* Bytes of workspace df3c_coulomb_J_grad_masked needs. */
+size_t df3c_coulomb_J_grad_masked_workspace(const df3c_shells *aux, const df3c_shells *orb,
+                                            int32_t natom);
+
+/* The gradient of L = sum_ab G_ab J_ab for the screened J of
+ * df3c_coulomb_J_masked: only the orbital shell pairs with
+ * mask[a * nshell + b] != 0 (DEVICE, symmetric) contribute.  The kept pairs of
+ * every class are compacted on the device (one readback of their counts sizes
+ * the launches); the result is bitwise reproducible.  Other arguments as for
+ * df3c_coulomb_J_grad; ws of at least df3c_coulomb_J_grad_masked_workspace
+ * bytes. */
+int df3c_coulomb_J_grad_masked(const double *xyz, int32_t natom, const df3c_shells *aux,
+                               const df3c_shells *orb, const double *d, const double *G,
+                               const uint8_t *mask, double *grad, void *ws, size_t ws_bytes,
+                               uint32_t flags, void *stream);
+
 /* Per-class schedule parameters of the persistent batched J (written by the
  * project's autotuner).  A table has DF3C_NCLASS entries indexed by
  * (l_P * 5 + l_a) * 5 + l_b with l_a >= l_b. */

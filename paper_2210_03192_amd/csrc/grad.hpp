@@ -38,14 +38,17 @@ struct GradArgs {
   int32_t natom;
   int32_t nsplit;           // aux shells of a pair split into nsplit interleaved subsets
   double *partial;          // [gridDim.x][natom][3], accumulated
+  const int64_t *plist;     // optional: indices q of the class's pairs to run
+  const int64_t *pcount;    //   (device count of plist), null for all npair
 };
 
 // Work items of the gradient kernels: blocks of tpb consecutive shell pairs
-// times nsplit subsets of the aux shells (subset k: aux shells k, k + nsplit,
-// ...); every team of a workgroup takes the same subset, so the aux loop is
-// uniform over the workgroup.  Block b -> subset b / nblk, pairs of block b % nblk.
-__device__ __forceinline__ int64_t grad_blocks(const GradArgs &g, int tpb) {
-  return (g.npair + tpb - 1) / tpb * g.nsplit;
+// (all pairs of the class, or the kept ones of a pair list) times nsplit
+// subsets of the aux shells (subset k: aux shells k, k + nsplit, ...); every
+// team of a workgroup takes the same subset, so the aux loop is uniform over
+// the workgroup.  Block b -> subset b / nblk, pairs of block b % nblk.
+__device__ __forceinline__ int64_t grad_items(const GradArgs &g) {
+  return g.plist ? *g.pcount : g.npair;
 }
 
 // ---------------------------------------------------------------------------
@@ -105,11 +108,13 @@ __global__ void __launch_bounds__(64) k_gradr(GradArgs g) {
   for (int x = lane; x < 3 * g.natom; x += 64) ACC[x] = 0.0;
   __syncthreads();
 
-  const int64_t nblk = (g.npair + 63) / 64;
-  for (int64_t blk = blockIdx.x; blk < grad_blocks(g, 64); blk += gridDim.x) {
+  const int64_t nitem = grad_items(g);
+  const int64_t nblk = (nitem + 63) / 64;
+  for (int64_t blk = blockIdx.x; blk < nblk * g.nsplit; blk += gridDim.x) {
     const int sub = int(blk / nblk);
-    const int64_t q = (blk - sub * nblk) * 64 + lane;
-    const bool valid = q < g.npair;
+    const int64_t qi = (blk - sub * nblk) * 64 + lane;
+    const bool valid = qi < nitem;
+    const int64_t q = valid && g.plist ? g.plist[qi] : qi;
     int sa = 0, sb = 0;
     if (valid) {
       if (g.same) {
@@ -457,10 +462,10 @@ __global__ void __launch_bounds__(ENG_TS)
   for (int x = tid; x < 3 * g.natom; x += TS) ACC[x] = 0.0;
   team_sync();
 
-  const int64_t nblk = g.npair;  // one pair per block
+  const int64_t nblk = grad_items(g);  // one pair per block
   for (int64_t blk = blockIdx.x; blk < nblk * g.nsplit; blk += gridDim.x) {
     const int sub = int(blk / nblk);
-    const int64_t q = blk - sub * nblk;
+    const int64_t q = g.plist ? g.plist[blk - sub * nblk] : blk - sub * nblk;
     int sa, sb;
     if (g.same) {
       int i = int((sqrt(8.0 * double(q) + 1.0) - 1.0) * 0.5);

@@ -571,13 +571,21 @@ __global__ void k_screen_pairs(const double *xyz, ShellsDev orb, int32_t n, doub
   }
 }
 
-// indices q of the class's pairs (as the J kernels decode them) that the mask
-// keeps; the order of the list does not affect J (each pair owns its blocks)
-__global__ void k_pair_compact(const int32_t *ash, const int32_t *bsh, int32_t nb, int32_t same,
-                               int64_t npair, const uint8_t *mask, int32_t nshell,
-                               int64_t *plist, unsigned long long *count) {
-  for (int64_t q = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; q < npair;
-       q += int64_t(gridDim.x) * blockDim.x) {
+// indices q of the class's pairs (as the kernels decode them) that the mask
+// keeps, in increasing q: one workgroup, thread t scans a contiguous range of
+// q, the ranges' counts are scanned in LDS, then every thread writes its kept
+// indices in order (deterministic; an all-ones mask gives q = 0, 1, ...)
+constexpr int COMPACT_TPB = 1024;
+__global__ void __launch_bounds__(COMPACT_TPB)
+    k_pair_compact(const int32_t *ash, const int32_t *bsh, int32_t nb, int32_t same, int64_t npair,
+                   const uint8_t *mask, int32_t nshell, int64_t *plist,
+                   unsigned long long *count) {
+  __shared__ int64_t cnt[COMPACT_TPB];
+  const int t = threadIdx.x;
+  const int64_t per = (npair + COMPACT_TPB - 1) / COMPACT_TPB;
+  const int64_t q0 = std::min<int64_t>(npair, int64_t(t) * per);
+  const int64_t q1 = std::min<int64_t>(npair, q0 + per);
+  auto kept = [&](int64_t q) {
     int sa, sb;
     if (same) {
       int i = int((sqrt(8.0 * double(q) + 1.0) - 1.0) * 0.5);
@@ -590,8 +598,25 @@ __global__ void k_pair_compact(const int32_t *ash, const int32_t *bsh, int32_t n
       sa = ash[i];
       sb = bsh[int(q - int64_t(i) * nb)];
     }
-    if (mask[int64_t(sa) * nshell + sb]) plist[atomicAdd(count, 1ull)] = q;
+    return mask[int64_t(sa) * nshell + sb] != 0;
+  };
+  int64_t c = 0;
+  for (int64_t q = q0; q < q1; ++q) c += kept(q) ? 1 : 0;
+  cnt[t] = c;
+  __syncthreads();
+  if (t == 0) {
+    int64_t run = 0;
+    for (int k = 0; k < COMPACT_TPB; ++k) {
+      const int64_t v = cnt[k];
+      cnt[k] = run;
+      run += v;
+    }
+    *count = (unsigned long long)run;
   }
+  __syncthreads();
+  int64_t o = cnt[t];
+  for (int64_t q = q0; q < q1; ++q)
+    if (kept(q)) plist[o++] = q;
 }
 
 // shell pairs of all (l_a >= l_b) classes (the masked J's pair lists)
@@ -715,9 +740,9 @@ int coulomb_J_run(const double *xyz, int32_t natom, const df3c_shells *aux,
       for (int lb = 0; lb <= la; ++lb) {
         loff[la][lb] = o;
         if (!set_class(la, lb)) continue;
-        const int g = int(std::min<int64_t>((a.npair + 255) / 256, 4096));
-        hipLaunchKernelGGL(k_pair_compact, dim3(g), dim3(256), 0, s, a.ash, a.bsh, a.nb, a.same,
-                           a.npair, mask, orb->nshell, plist + o, pcount + la * NLA + lb);
+        hipLaunchKernelGGL(k_pair_compact, dim3(1), dim3(COMPACT_TPB), 0, s, a.ash, a.bsh, a.nb,
+                           a.same, a.npair, mask, orb->nshell, plist + o,
+                           pcount + la * NLA + lb);
         if (hipGetLastError() != hipSuccess) return DF3C_E_HIP;
         o += a.npair;
       }
@@ -1040,26 +1065,26 @@ size_t df3c_coulomb_J_grad_workspace(const df3c_shells *aux, const df3c_shells *
          align256(sizeof(double) * size_t(grad_slots(ncu)) * 3 * size_t(natom));
 }
 
-int df3c_coulomb_J_grad(const double *xyz, int32_t natom, const df3c_shells *aux,
-                        const df3c_shells *orb, const double *d, const double *G, double *grad,
-                        void *ws, size_t ws_bytes, uint32_t flags, void *stream) {
-  (void)flags;
-  if (!xyz || natom <= 0 || !shells_ok(aux) || !shells_ok(orb) || !d || !G || !grad)
-    return DF3C_E_ARG;
-  if (orb->pure != 0 || (aux->pure != 0 && aux->pure != 1)) return DF3C_E_UNSUPPORTED;
+namespace {
+// the J gradient over all pairs (mask null) or over the pairs a mask keeps
+int grad_run(const double *xyz, int32_t natom, const df3c_shells *aux, const df3c_shells *orb,
+             const double *d, const double *G, const uint8_t *mask, double *grad, void *ws,
+             size_t ws_bytes, hipStream_t s) {
   DevState *ds = nullptr;
   int rc = init_device(&ds);
   if (rc) return rc;
   const int nslot = grad_slots(ds->ncu);
-  const size_t need = jplan_bytes(orb->nshell, aux->nshell) +
-                      align256(sizeof(double) * size_t(nslot) * 3 * size_t(natom));
+  const size_t base_need = jplan_bytes(orb->nshell, aux->nshell) +
+                           align256(sizeof(double) * size_t(nslot) * 3 * size_t(natom));
+  const size_t need = base_need + (mask ? align256(sizeof(unsigned long long) * NLA * NLA) +
+                                              align256(sizeof(int64_t) * size_t(total_class_pairs(orb)))
+                                        : 0);
   if (!ws || ws_bytes < need) return DF3C_E_WORKSPACE;
   JPlan p;
   rc = make_plan(aux, orb, p);
   if (rc) return rc;
   for (int l = DF3C_LMAX_GRAD_ORB + 1; l <= DF3C_LMAX_ORB; ++l)
     if (p.orb_start[l + 1] > p.orb_start[l]) return DF3C_E_UNSUPPORTED;
-  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   char *w = static_cast<char *>(ws);
   int *err = reinterpret_cast<int *>(w);
   w += align256(sizeof(int) * 8);
@@ -1072,6 +1097,14 @@ int df3c_coulomb_J_grad(const double *xyz, int32_t natom, const df3c_shells *aux
   int64_t *aux_off = reinterpret_cast<int64_t *>(w);
   w += align256(sizeof(int64_t) * (aux->nshell + 1));
   double *partial = reinterpret_cast<double *>(w);
+  // masked only: kept-pair counters and lists of the (l_a, l_b) classes
+  unsigned long long *pcount = nullptr;
+  int64_t *plist = nullptr;
+  if (mask) {
+    char *m = static_cast<char *>(ws) + base_need;
+    pcount = reinterpret_cast<unsigned long long *>(m);
+    plist = reinterpret_cast<int64_t *>(m + align256(sizeof(unsigned long long) * NLA * NLA));
+  }
   if (hipMemcpyAsync(orb_sorted, p.orb_sorted.data(), sizeof(int32_t) * orb->nshell,
                      hipMemcpyHostToDevice, s) != hipSuccess ||
       hipMemcpyAsync(aux_sorted, p.aux_sorted.data(), sizeof(int32_t) * aux->nshell,
@@ -1104,6 +1137,31 @@ int df3c_coulomb_J_grad(const double *xyz, int32_t natom, const df3c_shells *aux
   a.pure = aux->pure;
   a.natom = natom;
   a.partial = partial;
+  // masked: compact the kept pairs of every class, one readback of the counts
+  int64_t loff[NLA][NLA] = {};
+  unsigned long long *kept = reinterpret_cast<unsigned long long *>(g_pinned);
+  if (mask) {
+    int64_t o = 0;
+    hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, s, reinterpret_cast<int *>(pcount),
+                       2 * NLA * NLA, 0);
+    for (int la = 0; la <= DF3C_LMAX_GRAD_ORB; ++la)
+      for (int lb = 0; lb <= la; ++lb) {
+        loff[la][lb] = o;
+        const int na = p.orb_start[la + 1] - p.orb_start[la];
+        const int nb = p.orb_start[lb + 1] - p.orb_start[lb];
+        if (!na || !nb) continue;
+        const int64_t npair = (la == lb) ? int64_t(na) * (na + 1) / 2 : int64_t(na) * nb;
+        hipLaunchKernelGGL(k_pair_compact, dim3(1), dim3(COMPACT_TPB), 0, s, orb_sorted + p.orb_start[la],
+                           orb_sorted + p.orb_start[lb], nb, int(la == lb), npair, mask,
+                           orb->nshell, plist + o, pcount + la * NLA + lb);
+        if (hipGetLastError() != hipSuccess) return DF3C_E_HIP;
+        o += npair;
+      }
+    if (hipMemcpyAsync(kept, pcount, sizeof(unsigned long long) * NLA * NLA,
+                       hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+      return DF3C_E_HIP;
+  }
   const int grid_cap = ds->ncu * GRAD_GRID_PER_CU;
   for (int lp = 0; lp <= DF3C_LMAX_AUX; ++lp) {
     const int np = p.aux_start[lp + 1] - p.aux_start[lp];
@@ -1121,6 +1179,12 @@ int df3c_coulomb_J_grad(const double *xyz, int32_t natom, const df3c_shells *aux
         a.nb = nb;
         a.same = (la == lb);
         a.npair = (la == lb) ? int64_t(na) * (na + 1) / 2 : int64_t(na) * nb;
+        if (mask) {
+          a.plist = plist + loff[la][lb];
+          a.pcount = reinterpret_cast<const int64_t *>(pcount + la * NLA + lb);
+          a.npair = int64_t(kept[la * NLA + lb]);  // sizes the launch; kernels read *pcount
+          if (!a.npair) continue;
+        }
         const GradInfo &gi = g_grad[lp][la][lb];
         const int lds = gi.tpb * (gi.team + 3 * natom) * 8;
         if (lds > 160 * 1024) return DF3C_E_UNSUPPORTED;
@@ -1136,6 +1200,38 @@ int df3c_coulomb_J_grad(const double *xyz, int32_t natom, const df3c_shells *aux
   hipLaunchKernelGGL(k_reduce_partial, dim3((n + 255) / 256), dim3(256), 0, s, partial, nslot, n,
                      grad);
   return DF3C_OK;
+}
+}  // namespace
+
+int df3c_coulomb_J_grad(const double *xyz, int32_t natom, const df3c_shells *aux,
+                        const df3c_shells *orb, const double *d, const double *G, double *grad,
+                        void *ws, size_t ws_bytes, uint32_t flags, void *stream) {
+  (void)flags;
+  if (!xyz || natom <= 0 || !shells_ok(aux) || !shells_ok(orb) || !d || !G || !grad)
+    return DF3C_E_ARG;
+  if (orb->pure != 0 || (aux->pure != 0 && aux->pure != 1)) return DF3C_E_UNSUPPORTED;
+  return grad_run(xyz, natom, aux, orb, d, G, nullptr, grad, ws, ws_bytes,
+                  reinterpret_cast<hipStream_t>(stream));
+}
+
+size_t df3c_coulomb_J_grad_masked_workspace(const df3c_shells *aux, const df3c_shells *orb,
+                                            int32_t natom) {
+  if (!aux || !orb || !orb->l_host || natom < 0) return 0;
+  return df3c_coulomb_J_grad_workspace(aux, orb, natom) +
+         align256(sizeof(unsigned long long) * NLA * NLA) +
+         align256(sizeof(int64_t) * size_t(total_class_pairs(orb)));
+}
+
+int df3c_coulomb_J_grad_masked(const double *xyz, int32_t natom, const df3c_shells *aux,
+                               const df3c_shells *orb, const double *d, const double *G,
+                               const uint8_t *mask, double *grad, void *ws, size_t ws_bytes,
+                               uint32_t flags, void *stream) {
+  (void)flags;
+  if (!xyz || natom <= 0 || !shells_ok(aux) || !shells_ok(orb) || !d || !G || !grad || !mask)
+    return DF3C_E_ARG;
+  if (orb->pure != 0 || (aux->pure != 0 && aux->pure != 1)) return DF3C_E_UNSUPPORTED;
+  return grad_run(xyz, natom, aux, orb, d, G, mask, grad, ws, ws_bytes,
+                  reinterpret_cast<hipStream_t>(stream));
 }
 
 

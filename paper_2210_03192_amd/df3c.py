@@ -84,6 +84,9 @@ def lib():
         L.df3c_coulomb_J_grad_workspace.restype = SZ
         L.df3c_coulomb_J_grad_workspace.argtypes = [P, P, I32]
         L.df3c_coulomb_J_grad.argtypes = [P, I32, P, P, P, P, P, P, SZ, U32, P]
+        L.df3c_coulomb_J_grad_masked_workspace.restype = SZ
+        L.df3c_coulomb_J_grad_masked_workspace.argtypes = [P, P, I32]
+        L.df3c_coulomb_J_grad_masked.argtypes = [P, I32, P, P, P, P, P, P, P, SZ, U32, P]
         L.df3c_coulomb_J_batched_workspace.restype = SZ
         L.df3c_coulomb_J_batched_workspace.argtypes = [P, P, I32]
         L.df3c_coulomb_J_batched.argtypes = [P, I32, P, P, I32, P, P, P, P, P, P, SZ, U32, P]
@@ -233,6 +236,25 @@ def coulomb_J_masked(xyz: torch.Tensor, aux: DeviceBasis, orb: DeviceBasis, d: t
            "df3c_coulomb_J_masked")
     return J
 
+
+
+def coulomb_J_grad_masked(xyz: torch.Tensor, aux: DeviceBasis, orb: DeviceBasis, d: torch.Tensor,
+                          G: torch.Tensor, mask: torch.Tensor, grad: Optional[torch.Tensor] = None,
+                          ws: Optional[torch.Tensor] = None, flags: int = 0,
+                          stream=None) -> torch.Tensor:
+    """dL/dR [natom][3] of L = sum_ab G_ab J_ab over the shell pairs the mask keeps."""
+    natom = int(xyz.shape[0])
+    if grad is None:
+        grad = torch.empty((natom, 3), dtype=torch.float64, device=xyz.device)
+    sa, so = aux.struct(), orb.struct()
+    need = int(lib().df3c_coulomb_J_grad_masked_workspace(ctypes.byref(sa), ctypes.byref(so), natom))
+    if ws is None or ws.numel() < need:
+        ws = torch.empty(max(need, 1), dtype=torch.uint8, device=xyz.device)
+    _check(lib().df3c_coulomb_J_grad_masked(_ptr(xyz), natom, ctypes.byref(sa), ctypes.byref(so),
+                                            _ptr(d), _ptr(G), _ptr(mask), _ptr(grad), _ptr(ws),
+                                            ws.numel(), flags, _stream(stream)),
+           "df3c_coulomb_J_grad_masked")
+    return grad
 
 def coulomb_J_grad_workspace(aux: DeviceBasis, orb: DeviceBasis, natom: int) -> int:
     sa, so = aux.struct(), orb.struct()

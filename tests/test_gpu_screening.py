@@ -81,3 +81,23 @@ def test_screened_J_error_water120():
     J = df3c.coulomb_J(xyz, aux, orb, d)
     Js = df3c.coulomb_J_masked(xyz, aux, orb, d, mask)
     assert float((Js - J).abs().max()) <= 1e-7 * float(J.abs().max())
+
+
+def test_masked_gradient_vs_oracle():
+    """Gradient of the screened L over the oracle's mask against the oracle's
+    masked gradient (the gradient bar: 1e-10 relative in the max norm); an
+    all-ones mask gives the unscreened GPU gradient bitwise."""
+    s = inputs.water_cluster(3, seed=inputs.SEED_BASE + 440)
+    torch, df3c, xyz, aux, orb = _gpu(s)
+    mask, _ = oracle.screen_pairs(s.xyz, s.orb, 1e-4)
+    assert 0 < mask.sum() < mask.size
+    dn = inputs.fitting_coefficients(s.aux.nbf, 441)
+    Gn = inputs.symmetric_density(s.orb.nbf, 442)
+    d = torch.as_tensor(dn, device="cuda")
+    G = torch.as_tensor(Gn, device="cuda")
+    g = df3c.coulomb_J_grad_masked(xyz, aux, orb, d, G, torch.as_tensor(mask, device="cuda"))
+    ref = oracle.coulomb_J_grad(s.xyz, s.aux, s.orb, dn, Gn, pair_mask=mask)
+    assert np.abs(g.cpu().numpy() - ref).max() <= 1e-10 * np.abs(ref).max()
+    ones = torch.ones((orb.nshell, orb.nshell), dtype=torch.uint8, device="cuda")
+    assert torch.equal(df3c.coulomb_J_grad_masked(xyz, aux, orb, d, G, ones),
+                       df3c.coulomb_J_grad(xyz, aux, orb, d, G))
