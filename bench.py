@@ -222,6 +222,21 @@ def dfj_legs(args, df3c, inputs, torch, dev):
         out["dfj_ms_water_60atoms"] * 1e-3) / PEAK_FP64
     out["grad_model_frac_water_60atoms"] = system_model_flop(s.aux, s.orb, grad=True) / (
         out["grad_ms_water_60atoms"] * 1e-3) / PEAK_FP64
+    # screened J gradient (same criterion and threshold as the screened DF-J):
+    # the screening kernel and the masked gradient together
+    tau = 1e-12
+    mask = torch.empty((orb.nshell, orb.nshell), dtype=torch.uint8, device=dev)
+    gs = torch.empty((len(s.xyz), 3), dtype=torch.float64, device=dev)
+    wsg = torch.empty(df3c.coulomb_J_grad_masked_workspace(aux, orb, len(s.xyz)),
+                      dtype=torch.uint8, device=dev)
+
+    def screened_grad():
+        df3c.screen_pairs(xyz, orb, tau, mask=mask)
+        df3c.coulomb_J_grad_masked(xyz, aux, orb, d, G, mask, grad=gs, ws=wsg)
+    out["grad_ms_water_60atoms_screened"] = _time_ms(torch, screened_grad, 2)
+    out["grad_screened_pair_fraction"] = float(mask.double().mean())
+    g = df3c.coulomb_J_grad(xyz, aux, orb, d, G)
+    out["grad_screened_max_dev_rel"] = float((gs - g).abs().max() / g.abs().max())
     # batched uneven clusters
     if args.batched_nmol > 0:
         from paper_2210_03192_amd import autotune

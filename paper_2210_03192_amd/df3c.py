@@ -237,6 +237,11 @@ def coulomb_J_masked(xyz: torch.Tensor, aux: DeviceBasis, orb: DeviceBasis, d: t
     return J
 
 
+def coulomb_J_grad_masked_workspace(aux: DeviceBasis, orb: DeviceBasis, natom: int) -> int:
+    sa, so = aux.struct(), orb.struct()
+    return int(lib().df3c_coulomb_J_grad_masked_workspace(ctypes.byref(sa), ctypes.byref(so),
+                                                          int(natom)))
+
 
 def coulomb_J_grad_masked(xyz: torch.Tensor, aux: DeviceBasis, orb: DeviceBasis, d: torch.Tensor,
                           G: torch.Tensor, mask: torch.Tensor, grad: Optional[torch.Tensor] = None,
@@ -246,15 +251,17 @@ def coulomb_J_grad_masked(xyz: torch.Tensor, aux: DeviceBasis, orb: DeviceBasis,
     natom = int(xyz.shape[0])
     if grad is None:
         grad = torch.empty((natom, 3), dtype=torch.float64, device=xyz.device)
-    sa, so = aux.struct(), orb.struct()
-    need = int(lib().df3c_coulomb_J_grad_masked_workspace(ctypes.byref(sa), ctypes.byref(so), natom))
+    need = coulomb_J_grad_masked_workspace(aux, orb, natom)
     if ws is None or ws.numel() < need:
         ws = torch.empty(max(need, 1), dtype=torch.uint8, device=xyz.device)
+    G = G.contiguous()
+    sa, so = aux.struct(), orb.struct()
     _check(lib().df3c_coulomb_J_grad_masked(_ptr(xyz), natom, ctypes.byref(sa), ctypes.byref(so),
                                             _ptr(d), _ptr(G), _ptr(mask), _ptr(grad), _ptr(ws),
                                             ws.numel(), flags, _stream(stream)),
            "df3c_coulomb_J_grad_masked")
     return grad
+
 
 def coulomb_J_grad_workspace(aux: DeviceBasis, orb: DeviceBasis, natom: int) -> int:
     sa, so = aux.struct(), orb.struct()
