@@ -131,7 +131,7 @@ def eval_batch(xyz, aux, orb, trip, out_off=None, nthreads=0, precision="double"
 def coulomb_J(xyz, aux, orb, d, nthreads=0, precision="double"):
     xyz = np.ascontiguousarray(xyz, np.float64)
     d = np.ascontiguousarray(d, np.float64)
-    nao = int(sum(ncart(int(l)) for l in orb.l))
+    nao = int(sum(nfunc(int(l), orb.pure) for l in orb.l))
     J = np.zeros((nao, nao))
     pa, po = _Pinned(aux), _Pinned(orb)
     _check(_lib(precision).oracle_coulomb_J(_ptr(xyz), pa.ref, po.ref, _ptr(d), _ptr(J),

@@ -562,9 +562,29 @@ int oracle_coulomb_metric(const double *xyz, const oracle_basis *aux, double *V,
   return 0;
 }
 
+/* Bra transform of one Cartesian J block onto real solid harmonics on both
+ * orbital shells: out[i'][j'] = sum_ij T_la[i'][i] T_lb[j'][j] cart[i][j]
+ * (Section 2.5.1: the solid-harmonic transform is linear and acts on each
+ * shell's Cartesian index; the same T as for the ket). */
+static void bra_to_pure(int la, int lb, const real *cart, real *out) {
+  int na = ncart(la), nb = ncart(lb);
+  real Ta[(2 * LMAX_AUX + 1) * 45], Tb[(2 * LMAX_AUX + 1) * 45];
+  solid_transform_real(la, Ta);
+  solid_transform_real(lb, Tb);
+  for (int ip = 0; ip < 2 * la + 1; ++ip)
+    for (int jp = 0; jp < 2 * lb + 1; ++jp) {
+      real v = 0;
+      for (int i = 0; i < na; ++i)
+        for (int j = 0; j < nb; ++j) v += Ta[ip * na + i] * Tb[jp * nb + j] * cart[i * nb + j];
+      out[ip * (2 * lb + 1) + jp] = v;
+    }
+}
+
 int oracle_coulomb_J(const double *xyz, const oracle_basis *aux, const oracle_basis *orb,
                      const double *d, double *J, int nthreads) {
-  if (check_basis(aux, LMAX_AUX - 1) || check_basis(orb, LMAX_ORB - 1) || orb->pure) return -1;
+  if (check_basis(aux, LMAX_AUX - 1) || check_basis(orb, LMAX_ORB - 1) ||
+      (orb->pure != 0 && orb->pure != 1))
+    return -1;
   set_threads(nthreads);
   int64_t *aoff = (int64_t *)malloc(sizeof(int64_t) * (aux->nshell + 1));
   int64_t *ooff = (int64_t *)malloc(sizeof(int64_t) * (orb->nshell + 1));
@@ -577,7 +597,7 @@ int oracle_coulomb_J(const double *xyz, const oracle_basis *aux, const oracle_ba
     md_work *w = (md_work *)malloc(sizeof(md_work));
     real *cart = (real *)malloc(sizeof(real) * BLK_MAX);
     real *pure = (real *)malloc(sizeof(real) * BLK_MAX);
-    real Jblk[NC_ORB * NC_ORB];
+    real Jblk[NC_ORB * NC_ORB], Jp[NC_ORB * NC_ORB];
 #pragma omp for schedule(dynamic, 1)
     for (int64_t k = 0; k < npair; ++k) {
       /* k -> (sa >= sb) */
@@ -586,11 +606,16 @@ int oracle_coulomb_J(const double *xyz, const oracle_basis *aux, const oracle_ba
       while ((int64_t)(sa + 1) * (sa + 2) / 2 <= k) ++sa;
       int sb = (int)(k - (int64_t)sa * (sa + 1) / 2);
       J_block(xyz, aux, orb, d, aoff, sa, sb, Jblk, cart, pure, w);
-      int na = ncart(orb->l[sa]), nb = ncart(orb->l[sb]);
+      const real *out = Jblk;
+      if (orb->pure) {
+        bra_to_pure(orb->l[sa], orb->l[sb], Jblk, Jp);
+        out = Jp;
+      }
+      int na = nfunc(orb, orb->l[sa]), nb = nfunc(orb, orb->l[sb]);
       for (int i = 0; i < na; ++i)
         for (int j = 0; j < nb; ++j) {
-          J[(ooff[sa] + i) * nao + ooff[sb] + j] = (double)Jblk[i * nb + j];
-          J[(ooff[sb] + j) * nao + ooff[sa] + i] = (double)Jblk[i * nb + j];
+          J[(ooff[sa] + i) * nao + ooff[sb] + j] = (double)out[i * nb + j];
+          J[(ooff[sb] + j) * nao + ooff[sa] + i] = (double)out[i * nb + j];
         }
     }
     free(w);

@@ -49,7 +49,9 @@ int oracle_eval_batch(const double *xyz, const oracle_basis *aux,
                       const int32_t *trip, const int64_t *out_off, double *out,
                       int nthreads);
 
-/* J[nao][nao] = sum_P (ab|P) d_P over all shell pairs (both triangles). */
+/* J[nao][nao] = sum_P (ab|P) d_P over all shell pairs (both triangles).
+ * orb->pure = 1 takes the orbital shells as real solid harmonics: each
+ * Cartesian block is transformed on both sides (nao = sum 2l+1). */
 int oracle_coulomb_J(const double *xyz, const oracle_basis *aux,
                      const oracle_basis *orb, const double *d, double *J,
                      int nthreads);
