@@ -76,7 +76,8 @@ typedef struct {
   const double *exps;      /* DEVICE primitive exponents (> 0) */
   const double *coefs;     /* DEVICE contraction coefficients (normalised) */
   int32_t pure;            /* aux: 1 solid-harmonic (0 allowed only for l <= 1);
-                              orbital: must be 0 (Cartesian) */
+                              orbital: 0 Cartesian; 1 solid-harmonic, accepted by
+                              df3c_coulomb_J and df3c_coulomb_J_masked only */
   const int32_t *nprim_host; /* HOST [nshell] copy of nprim, or NULL.  Optional: when
                               given, the orbital shells of each l are processed in
                               order of decreasing contraction degree, so that the
@@ -115,10 +116,14 @@ int df3c_eval_batch(const double *xyz, int32_t natom, const df3c_shells *aux,
 size_t df3c_coulomb_J_workspace(const df3c_shells *aux, const df3c_shells *orb);
 
 /* J_ab = sum_P (ab|P) d_P over all orbital shell pairs (DF-J, Section 3).
- *   xyz, natom, aux, orb as for df3c_eval_batch
+ *   xyz, natom, aux, orb as for df3c_eval_batch, except that orb->pure = 1
+ *       is accepted: the orbital shells are then real solid harmonics (the
+ *       same transform as the ket's, Section 2.5.1, applied to both sides of
+ *       each Cartesian J block) and nao = sum over shells of 2l+1
  *   d   DEVICE [naux] fitting coefficients, aux function order
  *   J   DEVICE [nao][nao] output, overwritten, both triangles written
- *   ws  DEVICE workspace of at least df3c_coulomb_J_workspace bytes */
+ *   ws  DEVICE workspace of at least df3c_coulomb_J_workspace bytes (with
+ *       pure orbital shells it also holds the Cartesian J) */
 int df3c_coulomb_J(const double *xyz, int32_t natom, const df3c_shells *aux,
                    const df3c_shells *orb, const double *d, double *J, void *ws, size_t ws_bytes,
                    uint32_t flags, void *stream);

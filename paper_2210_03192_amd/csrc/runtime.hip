@@ -542,9 +542,23 @@ hipError_t launch_aux_records(const int32_t *sorted, int64_t n, const df3c_shell
 }
 }  // namespace
 
+namespace {
+// workspace of the solid-harmonic orbital transform (pure-row map, Cartesian J)
+size_t pure_bytes(const df3c_shells *orb) {
+  if (!orb->pure) return 0;
+  int64_t nc = 0, np = 0;
+  for (int s = 0; s < orb->nshell; ++s) {
+    const int l = orb->l_host[s];
+    nc += (l + 1) * (l + 2) / 2;
+    np += 2 * l + 1;
+  }
+  return align256(sizeof(int32_t) * np) + align256(sizeof(double) * nc * nc);
+}
+}  // namespace
+
 size_t df3c_coulomb_J_workspace(const df3c_shells *aux, const df3c_shells *orb) {
   if (!aux || !orb) return 0;
-  return jplan_bytes(orb->nshell, aux->nshell);
+  return jplan_bytes(orb->nshell, aux->nshell) + (orb->l_host ? pure_bytes(orb) : 0);
 }
 
 namespace {
@@ -630,10 +644,67 @@ int64_t total_class_pairs(const df3c_shells *orb) {
   return m;
 }
 
+// Solid-harmonic orbital shells: J is built over the Cartesian components
+// and each block is transformed on both sides afterwards (the solid-harmonic
+// transform is linear per shell, Section 2.5.1), from the sparse rows of the
+// same real solid-harmonic table as the ket.  Workspace past the J plan: the
+// pure-row map (shell << 4 | m) and the Cartesian J.
+extern "C++" {
+template <int L>
+__device__ inline void solid_row(int m, int &n, const int16_t *&col, const double *&val) {
+  const int b = GenSolid<L>::start[m];
+  n = GenSolid<L>::start[m + 1] - b;
+  col = GenSolid<L>::col + b;
+  val = GenSolid<L>::val + b;
+}
+
+__device__ inline void solid_row_l(int l, int m, int &n, const int16_t *&col, const double *&val) {
+  switch (l) {
+    case 0: solid_row<0>(m, n, col, val); break;
+    case 1: solid_row<1>(m, n, col, val); break;
+    case 2: solid_row<2>(m, n, col, val); break;
+    case 3: solid_row<3>(m, n, col, val); break;
+    default: solid_row<4>(m, n, col, val); break;
+  }
+}
+}  // extern "C++"
+
+// J[r][c] = sum_ij T_la[m_r][i] T_lb[m_c][j] Jc[cao[sa] + i][cao[sb] + j] for
+// the pure rows r, c (one thread per element of J, rows of J contiguous;
+// an element above the diagonal is evaluated as its mirror)
+__global__ void k_bra_pure(const double *Jc, int64_t nc, const int32_t *pmap,
+                           const int64_t *cao, const int32_t *lsh, double *J, int64_t np) {
+  const int64_t total = np * np;
+  for (int64_t x = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; x < total;
+       x += int64_t(gridDim.x) * blockDim.x) {
+    // both triangles from the same arithmetic (Jc is exactly symmetric)
+    int64_t r = x / np, c = x - r * np;
+    if (r < c) {
+      const int64_t t = r;
+      r = c;
+      c = t;
+    }
+    const int sa = pmap[r] >> 4, ma = pmap[r] & 15, sb = pmap[c] >> 4, mb = pmap[c] & 15;
+    int na, nb;
+    const int16_t *ca, *cb;
+    const double *va, *vb;
+    solid_row_l(lsh[sa], ma, na, ca, va);
+    solid_row_l(lsh[sb], mb, nb, cb, vb);
+    const double *row = Jc + cao[sa] * nc + cao[sb];
+    double v = 0.0;
+    for (int i = 0; i < na; ++i) {
+      double t = 0.0;
+      for (int j = 0; j < nb; ++j) t += vb[j] * row[int64_t(ca[i]) * nc + cb[j]];
+      v += va[i] * t;
+    }
+    J[x] = v;
+  }
+}
+
 // DF-J over all pairs (mask null) or over the pairs the mask keeps
 int coulomb_J_run(const double *xyz, int32_t natom, const df3c_shells *aux,
                   const df3c_shells *orb, const double *d, const uint8_t *mask, double *J,
-                  void *ws, hipStream_t s) {
+                  void *ws, size_t core, hipStream_t s) {
   DevState *ds = nullptr;
   int rc = init_device(&ds);
   if (rc) return rc;
@@ -678,6 +749,30 @@ int coulomb_J_run(const double *xyz, int32_t natom, const df3c_shells *aux,
   // the host vectors must outlive the asynchronous copies
   if (hipStreamSynchronize(s) != hipSuccess) return DF3C_E_HIP;
   if (g_pinned[0]) return DF3C_E_ARG;
+  // pure orbital shells: the engines fill the Cartesian J in the workspace
+  double *Jout = J;
+  int32_t *pmap = nullptr;
+  int64_t npure = 0;
+  if (orb->pure) {
+    std::vector<int32_t> pm;
+    for (int sh = 0; sh < orb->nshell; ++sh)
+      for (int m = 0; m < 2 * orb->l_host[sh] + 1; ++m) pm.push_back(sh << 4 | m);
+    npure = int64_t(pm.size());
+    pmap = reinterpret_cast<int32_t *>(static_cast<char *>(ws) + core);
+    J = reinterpret_cast<double *>(static_cast<char *>(ws) + core +
+                                   align256(sizeof(int32_t) * npure));
+    if (npure && (hipMemcpyAsync(pmap, pm.data(), sizeof(int32_t) * npure,
+                                 hipMemcpyHostToDevice, s) != hipSuccess ||
+                  hipStreamSynchronize(s) != hipSuccess))
+      return DF3C_E_HIP;
+  }
+  auto finish = [&]() -> int {
+    if (!orb->pure || !npure) return DF3C_OK;
+    const int64_t n2 = npure * npure;
+    hipLaunchKernelGGL(k_bra_pure, dim3(int(std::min<int64_t>((n2 + 255) / 256, 8192))),
+                       dim3(256), 0, s, J, p.nao, pmap, ao_off, orb->l, Jout, npure);
+    return hipGetLastError() == hipSuccess ? DF3C_OK : DF3C_E_HIP;
+  };
   const int64_t nJ = p.nao * p.nao;
   hipLaunchKernelGGL(k_zero_f64, dim3(int(std::min<int64_t>((nJ + 255) / 256, 4096))), dim3(256),
                      0, s, J, nJ);
@@ -725,7 +820,7 @@ int coulomb_J_run(const double *xyz, int32_t natom, const df3c_shells *aux,
       for (int la = 0; la <= DF3C_LMAX_ORB; ++la)
         for (int lb = 0; lb <= la; ++lb)
           if (set_class(la, lb) && (rc = launch(lp, la, lb))) return rc;
-    return DF3C_OK;
+    return finish();
   }
   // masked: the kept pairs of every (l_a, l_b) class are compacted into the
   // class's list, the counts read back once (they size the launches), then
@@ -762,7 +857,7 @@ int coulomb_J_run(const double *xyz, int32_t natom, const df3c_shells *aux,
       for (int lp = 0; lp <= DF3C_LMAX_AUX; ++lp)
         if ((rc = launch(lp, la, lb))) return rc;
     }
-  return DF3C_OK;
+  return finish();
 }
 }  // namespace
 
@@ -771,9 +866,11 @@ int df3c_coulomb_J(const double *xyz, int32_t natom, const df3c_shells *aux,
                    uint32_t flags, void *stream) {
   (void)flags;
   if (!xyz || natom <= 0 || !shells_ok(aux) || !shells_ok(orb) || !d || !J) return DF3C_E_ARG;
-  if (orb->pure != 0 || (aux->pure != 0 && aux->pure != 1)) return DF3C_E_UNSUPPORTED;
+  if ((orb->pure != 0 && orb->pure != 1) || (aux->pure != 0 && aux->pure != 1))
+    return DF3C_E_UNSUPPORTED;
   if (!ws || ws_bytes < df3c_coulomb_J_workspace(aux, orb)) return DF3C_E_WORKSPACE;
-  return coulomb_J_run(xyz, natom, aux, orb, d, nullptr, J, ws, reinterpret_cast<hipStream_t>(stream));
+  return coulomb_J_run(xyz, natom, aux, orb, d, nullptr, J, ws, jplan_bytes(orb->nshell, aux->nshell),
+                       reinterpret_cast<hipStream_t>(stream));
 }
 
 int df3c_screen_pairs(const double *xyz, int32_t natom, const df3c_shells *orb, double tau,
@@ -790,10 +887,16 @@ int df3c_screen_pairs(const double *xyz, int32_t natom, const df3c_shells *orb, 
   return hipGetLastError() == hipSuccess ? DF3C_OK : DF3C_E_HIP;
 }
 
-size_t df3c_coulomb_J_masked_workspace(const df3c_shells *aux, const df3c_shells *orb) {
-  if (!aux || !orb || !orb->l_host) return 0;
+namespace {
+size_t masked_core_bytes(const df3c_shells *aux, const df3c_shells *orb) {
   return jplan_bytes(orb->nshell, aux->nshell) + align256(sizeof(unsigned long long) * NLA * NLA) +
          align256(sizeof(int64_t) * size_t(total_class_pairs(orb)));
+}
+}  // namespace
+
+size_t df3c_coulomb_J_masked_workspace(const df3c_shells *aux, const df3c_shells *orb) {
+  if (!aux || !orb || !orb->l_host) return 0;
+  return masked_core_bytes(aux, orb) + pure_bytes(orb);
 }
 
 int df3c_coulomb_J_masked(const double *xyz, int32_t natom, const df3c_shells *aux,
@@ -802,9 +905,11 @@ int df3c_coulomb_J_masked(const double *xyz, int32_t natom, const df3c_shells *a
   (void)flags;
   if (!xyz || natom <= 0 || !shells_ok(aux) || !shells_ok(orb) || !d || !J || !mask)
     return DF3C_E_ARG;
-  if (orb->pure != 0 || (aux->pure != 0 && aux->pure != 1)) return DF3C_E_UNSUPPORTED;
+  if ((orb->pure != 0 && orb->pure != 1) || (aux->pure != 0 && aux->pure != 1))
+    return DF3C_E_UNSUPPORTED;
   if (!ws || ws_bytes < df3c_coulomb_J_masked_workspace(aux, orb)) return DF3C_E_WORKSPACE;
-  return coulomb_J_run(xyz, natom, aux, orb, d, mask, J, ws, reinterpret_cast<hipStream_t>(stream));
+  return coulomb_J_run(xyz, natom, aux, orb, d, mask, J, ws, masked_core_bytes(aux, orb),
+                       reinterpret_cast<hipStream_t>(stream));
 }
 
 

@@ -1,0 +1,119 @@
+"""DF-J over solid-harmonic orbital shells (NEXT row f4, first half): the
+library's J with orb.pure = 1 against the oracle's, which transforms each
+Cartesian block on both sides by its definition.
+
+* orbital s..g shells (contracted s and p), pure aux s..i, three atoms;
+* a water cluster (the element basis) with the orbital basis taken pure;
+* the masked J over pure orbital shells: the kept blocks are the oracle's
+  full-J blocks, the others zero.
+
+Bar: the Cartesian J's bar, max(1e-11 |x|, 1e-13) per element, carried
+through the linear transform: |x - x_ref| <= (|T_a| B_cart |T_b|^T)[r, c] with
+B_cart = max(1e-11 |J_cart|, 1e-13) from the oracle's Cartesian J and
+solid-harmonic tables.  A pure element sums up to (l+1)(l+2)/2 Cartesian
+elements per side with coefficients up to a few, and the combinations cancel
+(x^2 - y^2 and the like), so its error scales with those terms, not with the
+(possibly much smaller) result.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2210_03192_amd import inputs
+from paper_2210_03192_amd.inputs import Basis, System, _Builder, _logu, random_atoms
+from tests.test_gpu_parity import GpuSystem, _torch
+
+pytestmark = pytest.mark.gpu
+
+
+def _pure(b):
+    return Basis(b.l, b.nprim, b.prim_off, b.atom, b.exps, b.coefs, pure=1)
+
+
+def _system(seed):
+    rng = np.random.default_rng(seed)
+    xyz = random_atoms(rng, 3, 4.0, 1.5)
+    ob, ab = _Builder(1), _Builder(1)
+    for a in range(3):
+        for l, k in ((0, 3), (1, 2), (2, 1), (3, 1), (4, 1)):
+            ob.add(l, a, _logu(rng, 0.2, 20.0, k), rng.uniform(0.2, 1.0, k))
+        for l in range(7):
+            ab.add(l, a, _logu(rng, 0.1, 10.0, 1), [1.0])
+    return System(xyz, ob.build(), ab.build(), "pure-orbitals")
+
+
+def _cartesian(b):
+    return Basis(b.l, b.nprim, b.prim_off, b.atom, b.exps, b.coefs, pure=0)
+
+
+def _bound(xyz, aux, orb, d, mask=None):
+    """|T| max(1e-11 |J_cart|, 1e-13) |T|^T over the block-diagonal
+    solid-harmonic transform T."""
+    cart = _cartesian(orb)
+    Jc = oracle.coulomb_J(xyz, aux, cart, d)
+    B = np.maximum(1e-11 * np.abs(Jc), 1e-13)
+    op, oc = orb.offsets(), cart.offsets()
+    if mask is not None:
+        for a in range(orb.nshell):
+            for b in range(orb.nshell):
+                if not mask[a, b]:
+                    B[oc[a]:oc[a + 1], oc[b]:oc[b + 1]] = 1e-13
+    T = np.zeros((orb.nbf, cart.nbf))
+    for s, l in enumerate(orb.l):
+        T[op[s]:op[s + 1], oc[s]:oc[s + 1]] = oracle.solid_transform(int(l))
+    return np.abs(T) @ B @ np.abs(T).T
+
+
+def _assert_pure_parity(J, ref, bound, what):
+    err = np.abs(J - ref)
+    bad = err > bound
+    if bad.any():
+        i = np.unravel_index(int(np.argmax(err / bound)), err.shape)
+        raise AssertionError(f"{what}: {int(bad.sum())}/{err.size} elements outside the bar; "
+                             f"worst {i}: got {J[i]!r}, oracle {ref[i]!r}, |err| {err[i]:.3e}, "
+                             f"bar {bound[i]:.3e}")
+
+
+def _check(s, seed):
+    assert s.orb.pure == 1
+    d = inputs.fitting_coefficients(s.aux.nbf, seed)
+    print(f"pure-orbital J: {s.name} nao={s.orb.nbf} naux={s.aux.nbf}", flush=True)
+    J = GpuSystem(s.xyz, s.aux, s.orb).coulomb_J(d)
+    assert J.shape == (s.orb.nbf, s.orb.nbf)
+    ref = oracle.coulomb_J(s.xyz, s.aux, s.orb, d)
+    _assert_pure_parity(J, ref, _bound(s.xyz, s.aux, s.orb, d), "J (pure orbitals)")
+    assert np.array_equal(J, J.T)
+
+
+def test_J_pure_orbital_s_to_g():
+    _check(_system(inputs.SEED_BASE + 1201), inputs.SEED_BASE + 1202)
+
+
+def test_J_pure_orbital_water_cluster():
+    s = inputs.water_cluster(4, seed=inputs.SEED_BASE + 1203)
+    _check(System(s.xyz, _pure(s.orb), s.aux, "water4-pure"), inputs.SEED_BASE + 1204)
+
+
+def test_masked_J_pure_orbitals():
+    torch = _torch()
+    from paper_2210_03192_amd import df3c
+    s = inputs.water_cluster(4, seed=inputs.SEED_BASE + 1205)
+    orb = _pure(s.orb)
+    d = inputs.fitting_coefficients(s.aux.nbf, inputs.SEED_BASE + 1206)
+    mask, _ = oracle.screen_pairs(s.xyz, s.orb, 1e-4)
+    assert 0 < mask.sum() < mask.size
+    ref = oracle.coulomb_J(s.xyz, s.aux, orb, d)
+    off = orb.offsets()
+    for a in range(orb.nshell):
+        for b in range(orb.nshell):
+            if not mask[a, b]:
+                ref[off[a]:off[a + 1], off[b]:off[b + 1]] = 0.0
+    g = GpuSystem(s.xyz, s.aux, orb)
+    dd = torch.as_tensor(d, device="cuda")
+    m = torch.as_tensor(mask, device="cuda")
+    J = df3c.coulomb_J_masked(g.xyz, g.aux, g.orb, dd, m)
+    torch.cuda.synchronize()
+    J = J.cpu().numpy()
+    assert J.shape == ref.shape
+    _assert_pure_parity(J, ref, _bound(s.xyz, s.aux, orb, d, mask),
+                        "masked J (pure orbitals)")
