@@ -805,8 +805,8 @@ int oracle_coulomb_J_grad(const double *xyz, int32_t natom, const oracle_basis *
                           const oracle_basis *orb, const double *d, const double *G,
                           const uint8_t *atom_mask, const uint8_t *pair_mask, double *grad,
                           int nthreads) {
-  if (check_basis(aux, LMAX_AUX - 2) || check_basis(orb, GRAD_LMAX_ORB) || orb->pure ||
-      natom < 0)
+  if (check_basis(aux, LMAX_AUX - 2) || check_basis(orb, GRAD_LMAX_ORB) ||
+      (orb->pure != 0 && orb->pure != 1) || natom < 0)
     return -1;
   set_threads(nthreads);
   int64_t *aoff = (int64_t *)malloc(sizeof(int64_t) * (aux->nshell + 1));
@@ -824,7 +824,8 @@ int oracle_coulomb_J_grad(const double *xyz, int32_t natom, const oracle_basis *
     real *D = (real *)malloc(sizeof(real) * 9 * nblk_max);
     real *tmp = (real *)malloc(sizeof(real) * 6 * 55 * 36 * 36);
     real *pure = (real *)malloc(sizeof(real) * nblk_max);
-    real T[(2 * LMAX_AUX + 1) * 45];
+    real T[(2 * LMAX_AUX + 1) * 45], Ta[(2 * LMAX_AUX + 1) * 45], Tb[(2 * LMAX_AUX + 1) * 45];
+    real Gblk[NC_ORB * NC_ORB];
     real *g = (real *)calloc((size_t)natom * 3, sizeof(real));
 #pragma omp for schedule(dynamic, 1)
     for (int64_t k = 0; k < npair; ++k) {
@@ -836,6 +837,25 @@ int oracle_coulomb_J_grad(const double *xyz, int32_t natom, const oracle_basis *
         continue;
       }
       int na = ncart(a.l), nb = ncart(b.l), nab = na * nb;
+      /* weights of the Cartesian J block: G itself, or for solid-harmonic
+       * orbital shells (J_pure = T_a J_cart T_b^T) the pulled-back
+       * G_cart = T_a^T G_pure T_b */
+      if (orb->pure) {
+        solid_transform_real(a.l, Ta);
+        solid_transform_real(b.l, Tb);
+      }
+      for (int i = 0; i < na; ++i)
+        for (int j = 0; j < nb; ++j) {
+          if (!orb->pure) {
+            Gblk[i * nb + j] = G[(ooff[sa] + i) * nao + ooff[sb] + j];
+            continue;
+          }
+          real v = 0;
+          for (int ip = 0; ip < 2 * a.l + 1; ++ip)
+            for (int jp = 0; jp < 2 * b.l + 1; ++jp)
+              v += Ta[ip * na + i] * Tb[jp * nb + j] * G[(ooff[sa] + ip) * nao + ooff[sb] + jp];
+          Gblk[i * nb + j] = v;
+        }
       for (int sP = 0; sP < aux->nshell; ++sP) {
         shell_view P = view(xyz, aux, sP);
         if (P.atom < 0 || P.atom >= natom) {
@@ -862,8 +882,7 @@ int oracle_coulomb_J_grad(const double *xyz, int32_t natom, const oracle_basis *
                 } else {
                   v = blk[p * nab + x];
                 }
-                int i = x / nb, j = x % nb;
-                s += v * dp * G[(ooff[sa] + i) * nao + ooff[sb] + j];
+                s += v * dp * Gblk[x];
               }
             }
             g[atoms[cen] * 3 + ax] += s;

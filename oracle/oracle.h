@@ -93,7 +93,8 @@ int oracle_coulomb_J_pairs(const double *xyz, const oracle_basis *aux,
  * NULL only triplets with a centre on a masked atom are visited, and only the
  * masked atoms' rows are meaningful.  If pair_mask (nshell x nshell,
  * symmetric) is not NULL, J and so L run over the kept orbital shell pairs
- * only (the screened DF-J). */
+ * only (the screened DF-J).  With orb->pure = 1, G and J are over real
+ * solid-harmonic orbital functions (J as in oracle_coulomb_J). */
 int oracle_coulomb_J_grad(const double *xyz, int32_t natom,
                           const oracle_basis *aux, const oracle_basis *orb,
                           const double *d, const double *G,

@@ -68,3 +68,36 @@ def test_block_norms_invariant_under_rotation():
                 changed += 1
     assert changed > 0
 
+
+
+def test_gradient_is_the_derivative_of_pure_J():
+    """With solid-harmonic orbital shells, the gradient of L = sum G_ab J_ab
+    (G over the pure functions, non-symmetric) equals central differences
+    of the oracle's pure J (h = 1e-4) on d, f and g shells; an s/p basis gives
+    the Cartesian gradient of the permuted G."""
+    xyz, orb, aux = _system((0, 1, 2, 3, 4), 1108, natom=2)
+    po = _pure(orb)
+    d = inputs.fitting_coefficients(aux.nbf, 1109)
+    G = np.random.default_rng(1110).normal(size=(po.nbf, po.nbf))
+    g = oracle.coulomb_J_grad(xyz, aux, po, d, G)
+    h = 1e-4
+    for at in range(2):
+        for ax in range(3):
+            xp, xm = xyz.copy(), xyz.copy()
+            xp[at, ax] += h
+            xm[at, ax] -= h
+            fd = ((G * oracle.coulomb_J(xp, aux, po, d)).sum() -
+                  (G * oracle.coulomb_J(xm, aux, po, d)).sum()) / (2 * h)
+            assert abs(g[at, ax] - fd) <= 1e-6 * max(1.0, abs(fd)), (at, ax, g[at, ax], fd)
+
+    xyz, orb, aux = _system((0, 1, 1), 1111)
+    po = _pure(orb)
+    d = inputs.fitting_coefficients(aux.nbf, 1112)
+    G = np.random.default_rng(1113).normal(size=(po.nbf, po.nbf))
+    perm = []
+    for s, o in zip(orb.l, orb.offsets()[:-1]):
+        perm += [o] if s == 0 else [o + 1, o + 2, o]
+    Gc = np.zeros_like(G)
+    Gc[np.ix_(perm, perm)] = G
+    np.testing.assert_allclose(oracle.coulomb_J_grad(xyz, aux, po, d, G),
+                               oracle.coulomb_J_grad(xyz, aux, orb, d, Gc), rtol=1e-12, atol=1e-13)
