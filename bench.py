@@ -208,6 +208,16 @@ def dfj_legs(args, df3c, inputs, torch, dev):
             out["dfj_screened_pair_fraction"] = float(mask.double().mean())
             df3c.coulomb_J(xyz, aux, orb, d, J=J, ws=wsj)
             out["dfj_screened_max_dev_rel"] = float((Js - J).abs().max() / J.abs().max())
+            # solid-harmonic orbital shells: the same J plus the two-sided
+            # transform of every block (nao 2l+1 per shell)
+            sp = inputs.Basis(s.orb.l, s.orb.nprim, s.orb.prim_off, s.orb.atom, s.orb.exps,
+                              s.orb.coefs, pure=1)
+            orbp = df3c.DeviceBasis.from_basis(sp, dev)
+            Jp = torch.empty((sp.nbf, sp.nbf), dtype=torch.float64, device=dev)
+            wsp = torch.empty(df3c.coulomb_J_workspace(aux, orbp), dtype=torch.uint8, device=dev)
+            out["dfj_ms_water_120atoms_pure_orbitals"] = _time_ms(
+                torch, lambda: df3c.coulomb_J(xyz, aux, orbp, d, J=Jp, ws=wsp), 3)
+            out["dfj_pure_orbitals_nao"] = sp.nbf
     # J gradient, 60 atoms
     s = inputs.grad_60_system()
     d = torch.as_tensor(inputs.fitting_coefficients(s.aux.nbf, 5), device=dev)

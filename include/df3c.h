@@ -77,7 +77,8 @@ typedef struct {
   const double *coefs;     /* DEVICE contraction coefficients (normalised) */
   int32_t pure;            /* aux: 1 solid-harmonic (0 allowed only for l <= 1);
                               orbital: 0 Cartesian; 1 solid-harmonic, accepted by
-                              df3c_coulomb_J and df3c_coulomb_J_masked only */
+                              df3c_coulomb_J and df3c_coulomb_J_grad (and their
+                              masked forms) only */
   const int32_t *nprim_host; /* HOST [nshell] copy of nprim, or NULL.  Optional: when
                               given, the orbital shells of each l are processed in
                               order of decreasing contraction degree, so that the
@@ -165,7 +166,9 @@ size_t df3c_coulomb_J_grad_workspace(const df3c_shells *aux, const df3c_shells *
  * integrals come from raising and lowering the bra angular momentum,
  * d/dA (ab|P) = (a+1 b|P)^{2 zeta_a} - a (a-1 b|P) and likewise for B; the aux
  * centre follows from translational invariance.  Integrals are recomputed.
- *   xyz, natom, aux, orb, d as for df3c_coulomb_J
+ *   xyz, natom, aux, orb, d as for df3c_coulomb_J (with orb->pure = 1, G and J
+ *          are over the solid-harmonic functions; G is pulled back to the
+ *          Cartesian blocks, T_a^T G T_b, in the workspace first)
  *   G      DEVICE [nao][nao] = dL/dJ (need not be symmetric)
  *   grad   DEVICE [natom][3] output, overwritten
  * Orbital shells up to DF3C_LMAX_GRAD_ORB.  The result is bitwise reproducible

@@ -554,6 +554,14 @@ size_t pure_bytes(const df3c_shells *orb) {
   }
   return align256(sizeof(int32_t) * np) + align256(sizeof(double) * nc * nc);
 }
+// the gradient's: Cartesian-row map, pure shell offsets, the pulled-back G
+size_t grad_pure_bytes(const df3c_shells *orb) {
+  if (!orb->pure) return 0;
+  int64_t nc = 0;
+  for (int s = 0; s < orb->nshell; ++s) nc += (orb->l_host[s] + 1) * (orb->l_host[s] + 2) / 2;
+  return align256(sizeof(int32_t) * nc) + align256(sizeof(int64_t) * (orb->nshell + 1)) +
+         align256(sizeof(double) * nc * nc);
+}
 }  // namespace
 
 size_t df3c_coulomb_J_workspace(const df3c_shells *aux, const df3c_shells *orb) {
@@ -667,6 +675,17 @@ __device__ inline void solid_row_l(int l, int m, int &n, const int16_t *&col, co
     default: solid_row<4>(m, n, col, val); break;
   }
 }
+
+// dense [2l+1][ncart(l)] rows of the same table
+__device__ inline const double *solid_dense_l(int l) {
+  switch (l) {
+    case 0: return GenSolid<0>::dense;
+    case 1: return GenSolid<1>::dense;
+    case 2: return GenSolid<2>::dense;
+    case 3: return GenSolid<3>::dense;
+    default: return GenSolid<4>::dense;
+  }
+}
 }  // extern "C++"
 
 // J[r][c] = sum_ij T_la[m_r][i] T_lb[m_c][j] Jc[cao[sa] + i][cao[sb] + j] for
@@ -698,6 +717,33 @@ __global__ void k_bra_pure(const double *Jc, int64_t nc, const int32_t *pmap,
       v += va[i] * t;
     }
     J[x] = v;
+  }
+}
+
+// Gradient with solid-harmonic orbital shells: L = sum G_pure J_pure equals
+// sum G_cart J_cart with G_cart = T_a^T G_pure T_b per block, so G is pulled
+// back once and the Cartesian gradient engines run unchanged.
+//   Gc[r][c] = sum_mn T_la[m][i_r] T_lb[n][j_c] G[poff[sa] + m][poff[sb] + n]
+__global__ void k_bra_cart(const double *G, int64_t np, const int32_t *cmap,
+                           const int64_t *poff, const int32_t *lsh, double *Gc, int64_t nc) {
+  const int64_t total = nc * nc;
+  for (int64_t x = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; x < total;
+       x += int64_t(gridDim.x) * blockDim.x) {
+    const int64_t r = x / nc, c = x - r * nc;
+    const int sa = cmap[r] >> 4, ia = cmap[r] & 15, sb = cmap[c] >> 4, ib = cmap[c] & 15;
+    const int la = lsh[sa], lb = lsh[sb];
+    const int nca = (la + 1) * (la + 2) / 2, ncb = (lb + 1) * (lb + 2) / 2;
+    const double *Ta = solid_dense_l(la), *Tb = solid_dense_l(lb);
+    const double *row = G + poff[sa] * np + poff[sb];
+    double v = 0.0;
+    for (int m = 0; m < 2 * la + 1; ++m) {
+      const double ta = Ta[m * nca + ia];
+      if (ta == 0.0) continue;
+      double t = 0.0;
+      for (int n = 0; n < 2 * lb + 1; ++n) t += Tb[n * ncb + ib] * row[int64_t(m) * np + n];
+      v += ta * t;
+    }
+    Gc[x] = v;
   }
 }
 
@@ -1167,7 +1213,8 @@ size_t df3c_coulomb_J_grad_workspace(const df3c_shells *aux, const df3c_shells *
     if (hipGetDeviceProperties(&prop, dev) == hipSuccess) ncu = prop.multiProcessorCount;
   }
   return jplan_bytes(orb->nshell, aux->nshell) +
-         align256(sizeof(double) * size_t(grad_slots(ncu)) * 3 * size_t(natom));
+         align256(sizeof(double) * size_t(grad_slots(ncu)) * 3 * size_t(natom)) +
+         (orb->l_host ? grad_pure_bytes(orb) : 0);
 }
 
 namespace {
@@ -1181,10 +1228,10 @@ int grad_run(const double *xyz, int32_t natom, const df3c_shells *aux, const df3
   const int nslot = grad_slots(ds->ncu);
   const size_t base_need = jplan_bytes(orb->nshell, aux->nshell) +
                            align256(sizeof(double) * size_t(nslot) * 3 * size_t(natom));
-  const size_t need = base_need + (mask ? align256(sizeof(unsigned long long) * NLA * NLA) +
+  const size_t core = base_need + (mask ? align256(sizeof(unsigned long long) * NLA * NLA) +
                                               align256(sizeof(int64_t) * size_t(total_class_pairs(orb)))
                                         : 0);
-  if (!ws || ws_bytes < need) return DF3C_E_WORKSPACE;
+  if (!ws || ws_bytes < core + grad_pure_bytes(orb)) return DF3C_E_WORKSPACE;
   JPlan p;
   rc = make_plan(aux, orb, p);
   if (rc) return rc;
@@ -1229,6 +1276,36 @@ int grad_run(const double *xyz, int32_t natom, const df3c_shells *aux, const df3
   const int64_t npart = int64_t(nslot) * 3 * natom;
   hipLaunchKernelGGL(k_zero_f64, dim3(int(std::min<int64_t>((npart + 255) / 256, 4096))),
                      dim3(256), 0, s, partial, npart);
+  if (orb->pure) {
+    // solid-harmonic orbital shells: the engines take G_cart = T_a^T G T_b
+    std::vector<int32_t> cm;
+    std::vector<int64_t> po(orb->nshell + 1, 0);
+    for (int sh = 0; sh < orb->nshell; ++sh) {
+      const int l = orb->l_host[sh];
+      for (int c = 0; c < (l + 1) * (l + 2) / 2; ++c) cm.push_back(sh << 4 | c);
+      po[sh + 1] = po[sh] + 2 * l + 1;
+    }
+    const int64_t nc = int64_t(cm.size()), np = po[orb->nshell];
+    char *q = static_cast<char *>(ws) + core;
+    int32_t *cmap = reinterpret_cast<int32_t *>(q);
+    q += align256(sizeof(int32_t) * nc);
+    int64_t *poff = reinterpret_cast<int64_t *>(q);
+    q += align256(sizeof(int64_t) * (orb->nshell + 1));
+    double *Gc = reinterpret_cast<double *>(q);
+    if (nc && (hipMemcpyAsync(cmap, cm.data(), sizeof(int32_t) * nc, hipMemcpyHostToDevice,
+                              s) != hipSuccess ||
+               hipMemcpyAsync(poff, po.data(), sizeof(int64_t) * (orb->nshell + 1),
+                              hipMemcpyHostToDevice, s) != hipSuccess))
+      return DF3C_E_HIP;
+    if (nc) {
+      hipLaunchKernelGGL(k_bra_cart, dim3(int(std::min<int64_t>((nc * nc + 255) / 256, 8192))),
+                         dim3(256), 0, s, G, np, cmap, poff, orb->l, Gc, nc);
+      if (hipGetLastError() != hipSuccess) return DF3C_E_HIP;
+      // the host vectors must outlive the asynchronous copies
+      if (hipStreamSynchronize(s) != hipSuccess) return DF3C_E_HIP;
+    }
+    G = Gc;
+  }
   GradArgs a{};
   a.boys = ds->boys;
   a.xyz = xyz;
@@ -1314,7 +1391,8 @@ int df3c_coulomb_J_grad(const double *xyz, int32_t natom, const df3c_shells *aux
   (void)flags;
   if (!xyz || natom <= 0 || !shells_ok(aux) || !shells_ok(orb) || !d || !G || !grad)
     return DF3C_E_ARG;
-  if (orb->pure != 0 || (aux->pure != 0 && aux->pure != 1)) return DF3C_E_UNSUPPORTED;
+  if ((orb->pure != 0 && orb->pure != 1) || (aux->pure != 0 && aux->pure != 1))
+    return DF3C_E_UNSUPPORTED;
   return grad_run(xyz, natom, aux, orb, d, G, nullptr, grad, ws, ws_bytes,
                   reinterpret_cast<hipStream_t>(stream));
 }
@@ -1334,7 +1412,8 @@ int df3c_coulomb_J_grad_masked(const double *xyz, int32_t natom, const df3c_shel
   (void)flags;
   if (!xyz || natom <= 0 || !shells_ok(aux) || !shells_ok(orb) || !d || !G || !grad || !mask)
     return DF3C_E_ARG;
-  if (orb->pure != 0 || (aux->pure != 0 && aux->pure != 1)) return DF3C_E_UNSUPPORTED;
+  if ((orb->pure != 0 && orb->pure != 1) || (aux->pure != 0 && aux->pure != 1))
+    return DF3C_E_UNSUPPORTED;
   return grad_run(xyz, natom, aux, orb, d, G, mask, grad, ws, ws_bytes,
                   reinterpret_cast<hipStream_t>(stream));
 }
