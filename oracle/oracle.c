@@ -464,13 +464,33 @@ static void J_block(const double *xyz, const oracle_basis *aux, const oracle_bas
   }
 }
 
+/* Bra transform of one Cartesian block (of J, or of (P|ab) for one P) onto real solid harmonics on both
+ * orbital shells: out[i'][j'] = sum_ij T_la[i'][i] T_lb[j'][j] cart[i][j]
+ * (Section 2.5.1: the solid-harmonic transform is linear and acts on each
+ * shell's Cartesian index; the same T as for the ket). */
+static void bra_to_pure(int la, int lb, const real *cart, real *out) {
+  int na = ncart(la), nb = ncart(lb);
+  real Ta[(2 * LMAX_AUX + 1) * 45], Tb[(2 * LMAX_AUX + 1) * 45];
+  solid_transform_real(la, Ta);
+  solid_transform_real(lb, Tb);
+  for (int ip = 0; ip < 2 * la + 1; ++ip)
+    for (int jp = 0; jp < 2 * lb + 1; ++jp) {
+      real v = 0;
+      for (int i = 0; i < na; ++i)
+        for (int j = 0; j < nb; ++j) v += Ta[ip * na + i] * Tb[jp * nb + j] * cart[i * nb + j];
+      out[ip * (2 * lb + 1) + jp] = v;
+    }
+}
+
 /* gamma_P = sum_{a,b} (P|ab) D_ab over all ordered orbital shell pairs: the
  * definition written out (the contraction of the right-hand side of the fitting
  * equations, and dL/dd for L = sum_ab G_ab J_ab with D = G).  One loop
  * iteration owns one aux shell. */
 int oracle_coulomb_gamma(const double *xyz, const oracle_basis *aux, const oracle_basis *orb,
                          const double *D, double *gamma, int nthreads) {
-  if (check_basis(aux, LMAX_AUX - 1) || check_basis(orb, LMAX_ORB - 1) || orb->pure) return -1;
+  if (check_basis(aux, LMAX_AUX - 1) || check_basis(orb, LMAX_ORB - 1) ||
+      (orb->pure != 0 && orb->pure != 1))
+    return -1;
   set_threads(nthreads);
   int64_t *aoff = (int64_t *)malloc(sizeof(int64_t) * (aux->nshell + 1));
   int64_t *ooff = (int64_t *)malloc(sizeof(int64_t) * (orb->nshell + 1));
@@ -482,6 +502,7 @@ int oracle_coulomb_gamma(const double *xyz, const oracle_basis *aux, const oracl
     md_work *w = (md_work *)malloc(sizeof(md_work));
     real *cart = (real *)malloc(sizeof(real) * BLK_MAX);
     real *pure = (real *)malloc(sizeof(real) * BLK_MAX);
+    real blk[NC_ORB * NC_ORB], bp[NC_ORB * NC_ORB];
 #pragma omp for schedule(dynamic, 1)
     for (int sP = 0; sP < aux->nshell; ++sP) {
       shell_view P = view(xyz, aux, sP);
@@ -494,10 +515,23 @@ int oracle_coulomb_gamma(const double *xyz, const oracle_basis *aux, const oracl
           int na = ncart(a.l), nb = ncart(b.l), nab = na * nb;
           contracted_cart(&P, &a, &b, cart, w);
           ket_to_pure(P.l, aux->pure, nab, cart, pure);
-          for (int p = 0; p < np; ++p)
-            for (int i = 0; i < na; ++i)
-              for (int j = 0; j < nb; ++j)
-                acc[p] += pure[p * nab + i * nb + j] * D[(ooff[sa] + i) * nao + ooff[sb] + j];
+          if (!orb->pure) {
+            for (int p = 0; p < np; ++p)
+              for (int i = 0; i < na; ++i)
+                for (int j = 0; j < nb; ++j)
+                  acc[p] += pure[p * nab + i * nb + j] * D[(ooff[sa] + i) * nao + ooff[sb] + j];
+            continue;
+          }
+          /* solid-harmonic orbital shells: (P|a'b') = sum_ij T_a[a'][i]
+           * T_b[b'][j] (P|ij), contracted with D over the pure functions */
+          int npa = 2 * a.l + 1, npb = 2 * b.l + 1;
+          for (int p = 0; p < np; ++p) {
+            for (int x = 0; x < nab; ++x) blk[x] = pure[p * nab + x];
+            bra_to_pure(a.l, b.l, blk, bp);
+            for (int i = 0; i < npa; ++i)
+              for (int j = 0; j < npb; ++j)
+                acc[p] += bp[i * npb + j] * D[(ooff[sa] + i) * nao + ooff[sb] + j];
+          }
         }
       for (int p = 0; p < np; ++p) gamma[aoff[sP] + p] = (double)acc[p];
     }
@@ -560,24 +594,6 @@ int oracle_coulomb_metric(const double *xyz, const oracle_basis *aux, double *V,
   }
   free(aoff);
   return 0;
-}
-
-/* Bra transform of one Cartesian J block onto real solid harmonics on both
- * orbital shells: out[i'][j'] = sum_ij T_la[i'][i] T_lb[j'][j] cart[i][j]
- * (Section 2.5.1: the solid-harmonic transform is linear and acts on each
- * shell's Cartesian index; the same T as for the ket). */
-static void bra_to_pure(int la, int lb, const real *cart, real *out) {
-  int na = ncart(la), nb = ncart(lb);
-  real Ta[(2 * LMAX_AUX + 1) * 45], Tb[(2 * LMAX_AUX + 1) * 45];
-  solid_transform_real(la, Ta);
-  solid_transform_real(lb, Tb);
-  for (int ip = 0; ip < 2 * la + 1; ++ip)
-    for (int jp = 0; jp < 2 * lb + 1; ++jp) {
-      real v = 0;
-      for (int i = 0; i < na; ++i)
-        for (int j = 0; j < nb; ++j) v += Ta[ip * na + i] * Tb[jp * nb + j] * cart[i * nb + j];
-      out[ip * (2 * lb + 1) + jp] = v;
-    }
 }
 
 int oracle_coulomb_J(const double *xyz, const oracle_basis *aux, const oracle_basis *orb,

@@ -72,7 +72,8 @@ int oracle_screen_pairs(const double *xyz, const oracle_basis *orb, double tau,
                         uint8_t *mask, double *S);
 
 /* gamma[naux] = sum_{a,b} (P|ab) D_ab over all ordered orbital shell pairs;
- * D is nao x nao row-major (not assumed symmetric). */
+ * D is nao x nao row-major (not assumed symmetric).  With orb->pure = 1 the
+ * pairs run over real solid-harmonic orbital functions. */
 int oracle_coulomb_gamma(const double *xyz, const oracle_basis *aux,
                          const oracle_basis *orb, const double *D, double *gamma,
                          int nthreads);

@@ -101,3 +101,36 @@ def test_gradient_is_the_derivative_of_pure_J():
     Gc[np.ix_(perm, perm)] = G
     np.testing.assert_allclose(oracle.coulomb_J_grad(xyz, aux, po, d, G),
                                oracle.coulomb_J_grad(xyz, aux, orb, d, Gc), rtol=1e-12, atol=1e-13)
+
+
+def test_gamma_is_the_adjoint_of_pure_J():
+    """gamma_P = sum_ab (P|ab) D_ab over pure orbital functions satisfies
+    sum_P gamma_P(D) d_P = sum_ab D_ab J_ab(d) with the pure J (pinned
+    above), for a non-symmetric D and pure aux shells s..d; for s/p shells it
+    equals the Cartesian gamma of the permuted D."""
+    xyz, orb, aux = _system((0, 1, 2, 3), 1114, natom=2)
+    auxp = inputs._Builder(1)
+    rng = np.random.default_rng(1115)
+    for a in range(2):
+        for l in (0, 1, 2):
+            auxp.add(l, a, inputs._logu(rng, 0.1, 5.0, 1), [1.0])
+    aux = auxp.build()
+    po = _pure(orb)
+    d = inputs.fitting_coefficients(aux.nbf, 1116)
+    D = rng.normal(size=(po.nbf, po.nbf))
+    gam = oracle.coulomb_gamma(xyz, aux, po, D)
+    J = oracle.coulomb_J(xyz, aux, po, d)
+    lhs, rhs = float(gam @ d), float((D * J).sum())
+    # both sides sum the same products in different orders: rounding of the sum of |terms|
+    assert abs(lhs - rhs) <= 1e-12 * float((np.abs(D) * np.abs(J)).sum()), (lhs, rhs)
+
+    xyz, orb, aux = _system((0, 1, 1), 1117)
+    po = _pure(orb)
+    D = np.random.default_rng(1118).normal(size=(po.nbf, po.nbf))
+    perm = []
+    for s, o in zip(orb.l, orb.offsets()[:-1]):
+        perm += [o] if s == 0 else [o + 1, o + 2, o]
+    Dc = np.zeros_like(D)
+    Dc[np.ix_(perm, perm)] = D
+    np.testing.assert_allclose(oracle.coulomb_gamma(xyz, aux, po, D),
+                               oracle.coulomb_gamma(xyz, aux, orb, Dc), rtol=1e-13, atol=1e-14)
