@@ -77,8 +77,8 @@ typedef struct {
   const double *coefs;     /* DEVICE contraction coefficients (normalised) */
   int32_t pure;            /* aux: 1 solid-harmonic (0 allowed only for l <= 1);
                               orbital: 0 Cartesian; 1 solid-harmonic, accepted by
-                              df3c_coulomb_J and df3c_coulomb_J_grad (and their
-                              masked forms) only */
+                              df3c_coulomb_J, df3c_coulomb_J_grad (and their
+                              masked forms) and df3c_coulomb_gamma */
   const int32_t *nprim_host; /* HOST [nshell] copy of nprim, or NULL.  Optional: when
                               given, the orbital shells of each l are processed in
                               order of decreasing contraction degree, so that the
@@ -272,7 +272,9 @@ size_t df3c_coulomb_gamma_workspace(const df3c_shells *aux, const df3c_shells *o
  * function pairs -- the right-hand side of the density-fitting equations
  * (Section 3, the digestion of a 3-index batch) and dL/dd of L = sum G_ab J_ab
  * with D = G.
- *   D      DEVICE [nao][nao] row-major, any symmetry
+ *   D      DEVICE [nao][nao] row-major, any symmetry (over the solid-harmonic
+ *          functions when orb->pure = 1; pulled back to the Cartesian
+ *          blocks, T_a^T D T_b, in the workspace first)
  *   gamma  DEVICE output [naux] in aux-shell order, then component order
  *          (overwritten)
  * Work items are (aux shell, chunk of shell pairs); every item writes its own

@@ -554,8 +554,9 @@ size_t pure_bytes(const df3c_shells *orb) {
   }
   return align256(sizeof(int32_t) * np) + align256(sizeof(double) * nc * nc);
 }
-// the gradient's: Cartesian-row map, pure shell offsets, the pulled-back G
-size_t grad_pure_bytes(const df3c_shells *orb) {
+// pull-back of a matrix over pure orbital functions to the Cartesian blocks
+// (gradient G, gamma D): Cartesian-row map, pure shell offsets, the result
+size_t pullback_bytes(const df3c_shells *orb) {
   if (!orb->pure) return 0;
   int64_t nc = 0;
   for (int s = 0; s < orb->nshell; ++s) nc += (orb->l_host[s] + 1) * (orb->l_host[s] + 2) / 2;
@@ -745,6 +746,36 @@ __global__ void k_bra_cart(const double *G, int64_t np, const int32_t *cmap,
     }
     Gc[x] = v;
   }
+}
+
+// Gc = T_a^T G T_b per block into q (pullback_bytes(orb) bytes of workspace);
+// *out points at Gc on success.  Synchronises s (host vectors).
+int pull_back_cart(const df3c_shells *orb, const double *G, char *q, hipStream_t s,
+                   const double **out) {
+  std::vector<int32_t> cm;
+  std::vector<int64_t> po(orb->nshell + 1, 0);
+  for (int sh = 0; sh < orb->nshell; ++sh) {
+    const int l = orb->l_host[sh];
+    for (int c = 0; c < (l + 1) * (l + 2) / 2; ++c) cm.push_back(sh << 4 | c);
+    po[sh + 1] = po[sh] + 2 * l + 1;
+  }
+  const int64_t nc = int64_t(cm.size()), np = po[orb->nshell];
+  int32_t *cmap = reinterpret_cast<int32_t *>(q);
+  q += align256(sizeof(int32_t) * nc);
+  int64_t *poff = reinterpret_cast<int64_t *>(q);
+  q += align256(sizeof(int64_t) * (orb->nshell + 1));
+  double *Gc = reinterpret_cast<double *>(q);
+  *out = Gc;
+  if (!nc) return DF3C_OK;
+  if (hipMemcpyAsync(cmap, cm.data(), sizeof(int32_t) * nc, hipMemcpyHostToDevice, s) !=
+          hipSuccess ||
+      hipMemcpyAsync(poff, po.data(), sizeof(int64_t) * (orb->nshell + 1), hipMemcpyHostToDevice,
+                     s) != hipSuccess)
+    return DF3C_E_HIP;
+  hipLaunchKernelGGL(k_bra_cart, dim3(int(std::min<int64_t>((nc * nc + 255) / 256, 8192))),
+                     dim3(256), 0, s, G, np, cmap, poff, orb->l, Gc, nc);
+  if (hipGetLastError() != hipSuccess) return DF3C_E_HIP;
+  return hipStreamSynchronize(s) == hipSuccess ? DF3C_OK : DF3C_E_HIP;
 }
 
 // DF-J over all pairs (mask null) or over the pairs the mask keeps
@@ -1090,7 +1121,8 @@ size_t df3c_coulomb_gamma_workspace(const df3c_shells *aux, const df3c_shells *o
         const int nacc = (lp + 1) * (lp + 2) / 2;
         part = std::max(part, gam_reg_plan(npair, int(na[lp]), nacc, ds->ncu).partial_doubles(nout));
       }
-  return jplan_bytes(orb->nshell, aux->nshell) + align256(sizeof(double) * part);
+  return jplan_bytes(orb->nshell, aux->nshell) + align256(sizeof(double) * part) +
+         pullback_bytes(orb);
 }
 
 int df3c_coulomb_gamma(const double *xyz, int32_t natom, const df3c_shells *aux,
@@ -1098,8 +1130,10 @@ int df3c_coulomb_gamma(const double *xyz, int32_t natom, const df3c_shells *aux,
                        size_t ws_bytes, uint32_t flags, void *stream) {
   (void)flags;
   if (!xyz || natom <= 0 || !shells_ok(aux) || !shells_ok(orb) || !D || !gamma) return DF3C_E_ARG;
-  if (orb->pure != 0 || (aux->pure != 0 && aux->pure != 1)) return DF3C_E_UNSUPPORTED;
-  if (!ws || ws_bytes < df3c_coulomb_gamma_workspace(aux, orb)) return DF3C_E_WORKSPACE;
+  if ((orb->pure != 0 && orb->pure != 1) || (aux->pure != 0 && aux->pure != 1))
+    return DF3C_E_UNSUPPORTED;
+  const size_t need = df3c_coulomb_gamma_workspace(aux, orb);
+  if (!ws || ws_bytes < need) return DF3C_E_WORKSPACE;
   DevState *ds = nullptr;
   int rc = init_device(&ds);
   if (rc) return rc;
@@ -1137,6 +1171,12 @@ int df3c_coulomb_gamma(const double *xyz, int32_t natom, const df3c_shells *aux,
   if (g_pinned[0]) return DF3C_E_ARG;
   hipLaunchKernelGGL(k_zero_f64, dim3(int(std::min<int64_t>((p.naux + 255) / 256, 4096))),
                      dim3(256), 0, s, gamma, p.naux);
+  if (orb->pure) {
+    // solid-harmonic orbital shells: the engines contract with D_cart = T_a^T D T_b
+    // (the pull-back sits at the end of the workspace)
+    if ((rc = pull_back_cart(orb, D, static_cast<char *>(ws) + need - pullback_bytes(orb), s, &D)))
+      return rc;
+  }
   GamArgs a{};
   a.boys = ds->boys;
   a.xyz = xyz;
@@ -1214,7 +1254,7 @@ size_t df3c_coulomb_J_grad_workspace(const df3c_shells *aux, const df3c_shells *
   }
   return jplan_bytes(orb->nshell, aux->nshell) +
          align256(sizeof(double) * size_t(grad_slots(ncu)) * 3 * size_t(natom)) +
-         (orb->l_host ? grad_pure_bytes(orb) : 0);
+         (orb->l_host ? pullback_bytes(orb) : 0);
 }
 
 namespace {
@@ -1231,7 +1271,7 @@ int grad_run(const double *xyz, int32_t natom, const df3c_shells *aux, const df3
   const size_t core = base_need + (mask ? align256(sizeof(unsigned long long) * NLA * NLA) +
                                               align256(sizeof(int64_t) * size_t(total_class_pairs(orb)))
                                         : 0);
-  if (!ws || ws_bytes < core + grad_pure_bytes(orb)) return DF3C_E_WORKSPACE;
+  if (!ws || ws_bytes < core + pullback_bytes(orb)) return DF3C_E_WORKSPACE;
   JPlan p;
   rc = make_plan(aux, orb, p);
   if (rc) return rc;
@@ -1278,33 +1318,7 @@ int grad_run(const double *xyz, int32_t natom, const df3c_shells *aux, const df3
                      dim3(256), 0, s, partial, npart);
   if (orb->pure) {
     // solid-harmonic orbital shells: the engines take G_cart = T_a^T G T_b
-    std::vector<int32_t> cm;
-    std::vector<int64_t> po(orb->nshell + 1, 0);
-    for (int sh = 0; sh < orb->nshell; ++sh) {
-      const int l = orb->l_host[sh];
-      for (int c = 0; c < (l + 1) * (l + 2) / 2; ++c) cm.push_back(sh << 4 | c);
-      po[sh + 1] = po[sh] + 2 * l + 1;
-    }
-    const int64_t nc = int64_t(cm.size()), np = po[orb->nshell];
-    char *q = static_cast<char *>(ws) + core;
-    int32_t *cmap = reinterpret_cast<int32_t *>(q);
-    q += align256(sizeof(int32_t) * nc);
-    int64_t *poff = reinterpret_cast<int64_t *>(q);
-    q += align256(sizeof(int64_t) * (orb->nshell + 1));
-    double *Gc = reinterpret_cast<double *>(q);
-    if (nc && (hipMemcpyAsync(cmap, cm.data(), sizeof(int32_t) * nc, hipMemcpyHostToDevice,
-                              s) != hipSuccess ||
-               hipMemcpyAsync(poff, po.data(), sizeof(int64_t) * (orb->nshell + 1),
-                              hipMemcpyHostToDevice, s) != hipSuccess))
-      return DF3C_E_HIP;
-    if (nc) {
-      hipLaunchKernelGGL(k_bra_cart, dim3(int(std::min<int64_t>((nc * nc + 255) / 256, 8192))),
-                         dim3(256), 0, s, G, np, cmap, poff, orb->l, Gc, nc);
-      if (hipGetLastError() != hipSuccess) return DF3C_E_HIP;
-      // the host vectors must outlive the asynchronous copies
-      if (hipStreamSynchronize(s) != hipSuccess) return DF3C_E_HIP;
-    }
-    G = Gc;
+    if ((rc = pull_back_cart(orb, G, static_cast<char *>(ws) + core, s, &G))) return rc;
   }
   GradArgs a{};
   a.boys = ds->boys;

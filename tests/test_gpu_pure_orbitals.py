@@ -152,3 +152,41 @@ def test_gradient_pure_orbitals():
     got = got.cpu().numpy()
     assert np.abs(got - ref).max() <= 1e-10 * np.abs(ref).max(), np.abs(got - ref).max()
     assert np.array_equal(gm.cpu().numpy(), got)
+
+
+def _assert_gamma(g, s, D, what):
+    """The Cartesian gamma test's bar: max(1e-11 |ref|, 1e-13 max|ref|), with
+    elements outside it adjudicated by the long-double oracle."""
+    ref = oracle.coulomb_gamma(s.xyz, s.aux, s.orb, D)
+    atol = 1e-13 * np.abs(ref).max()
+
+    def bad(r):
+        return np.abs(g - r) > np.maximum(1e-11 * np.abs(r), atol)
+    if bad(ref).any():
+        ref_ld = oracle.coulomb_gamma(s.xyz, s.aux, s.orb, D, precision="long")
+        b = bad(ref_ld)
+        assert not b.any(), (what, int(b.sum()), np.abs(g - ref_ld).max())
+
+
+def test_gamma_and_autograd_pure_orbitals():
+    """gamma = (P|ab) D over pure orbital functions (D non-symmetric) against
+    the oracle, then the autograd of L = sum G J(xyz, d): dL/dd = gamma(G) and
+    dL/dxyz = the pure-orbital gradient, both against the oracle."""
+    torch = _torch()
+    from paper_2210_03192_amd import df3c
+    s = _grad_system(inputs.SEED_BASE + 1210)
+    print(f"pure-orbital gamma: nao={s.orb.nbf} naux={s.aux.nbf}", flush=True)
+    g = GpuSystem(s.xyz, s.aux, s.orb)
+    D = np.random.default_rng(inputs.SEED_BASE + 1211).normal(size=(s.orb.nbf, s.orb.nbf))
+    gam = df3c.coulomb_gamma(g.xyz, g.aux, g.orb, torch.as_tensor(D, device="cuda"))
+    _assert_gamma(gam.cpu().numpy(), s, D, "gamma (pure orbitals)")
+
+    dn = inputs.fitting_coefficients(s.aux.nbf, inputs.SEED_BASE + 1212)
+    Gn = np.random.default_rng(inputs.SEED_BASE + 1213).normal(size=(s.orb.nbf, s.orb.nbf))
+    d = torch.as_tensor(dn, device="cuda").requires_grad_(True)
+    x = g.xyz.clone().requires_grad_(True)
+    L = (torch.as_tensor(Gn, device="cuda") * df3c.J(x, d, g.aux, g.orb)).sum()
+    L.backward()
+    _assert_gamma(d.grad.cpu().numpy(), s, Gn, "dL/dd (pure orbitals)")
+    gref = oracle.coulomb_J_grad(s.xyz, s.aux, s.orb, dn, Gn)
+    assert np.abs(x.grad.cpu().numpy() - gref).max() <= 1e-10 * np.abs(gref).max()
