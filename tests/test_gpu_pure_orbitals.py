@@ -190,3 +190,19 @@ def test_gamma_and_autograd_pure_orbitals():
     _assert_gamma(d.grad.cpu().numpy(), s, Gn, "dL/dd (pure orbitals)")
     gref = oracle.coulomb_J_grad(s.xyz, s.aux, s.orb, dn, Gn)
     assert np.abs(x.grad.cpu().numpy() - gref).max() <= 1e-10 * np.abs(gref).max()
+
+
+@pytest.mark.parametrize("ls", [(0,), (1,), (2, 2)], ids=["one_s", "one_p", "two_d"])
+def test_J_pure_orbital_degenerate_bases(ls):
+    """The smallest bases: a lone s shell (nao 1), a lone p shell, two d
+    shells on one atom (no s or p orbital class at all)."""
+    rng = np.random.default_rng(inputs.SEED_BASE + 1214 + len(ls))
+    xyz = random_atoms(rng, 2, 3.0, 1.5)
+    ob, ab = _Builder(1), _Builder(1)
+    for l in ls:
+        ob.add(l, 0, _logu(rng, 0.3, 5.0, 2), rng.uniform(0.2, 1.0, 2))
+    for a in range(2):
+        for l in (0, 1, 2):
+            ab.add(l, a, _logu(rng, 0.1, 5.0, 1), [1.0])
+    _check(System(xyz, ob.build(), ab.build(), "pure-" + "".join(map(str, ls))),
+           inputs.SEED_BASE + 1218)

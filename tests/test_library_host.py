@@ -73,3 +73,33 @@ def test_screening_entry_points_reject_bad_arguments(lib):
     assert lib.df3c_screen_pairs(buf, 1, None, ctypes.c_double(-1.0), buf, None) == -1
     assert lib.df3c_screen_pairs(buf, 1, None, ctypes.c_double(float("nan")), buf, None) == -1
     assert lib.df3c_coulomb_J_masked_workspace(None, None) == 0
+
+
+def test_pure_orbital_options(lib):
+    # solid-harmonic orbital shells need workspace for the Cartesian J (or the
+    # pulled-back G) on top of the Cartesian sizes; pure flags other than 0
+    # and 1 are rejected before any HIP call
+    from paper_2210_03192_amd import df3c
+    lo = np.array([0, 1, 2, 3], np.int32)
+    la = np.array([0], np.int32)
+    buf = (ctypes.c_double * 8)()
+    p = ctypes.cast(buf, ctypes.c_void_p).value
+
+    def shells(l, pure):
+        return df3c._Shells(len(l), l.ctypes.data, p, p, p, p, p, p, pure, None)
+    aux = shells(la, 1)
+    cart, pure, bad = shells(lo, 0), shells(lo, 1), shells(lo, 2)
+    nc = 1 + 3 + 6 + 10
+    wc = lib.df3c_coulomb_J_workspace(ctypes.byref(aux), ctypes.byref(cart))
+    wp = lib.df3c_coulomb_J_workspace(ctypes.byref(aux), ctypes.byref(pure))
+    assert wp >= wc + 8 * nc * nc
+    wmc = lib.df3c_coulomb_J_masked_workspace(ctypes.byref(aux), ctypes.byref(cart))
+    wmp = lib.df3c_coulomb_J_masked_workspace(ctypes.byref(aux), ctypes.byref(pure))
+    assert wmp >= wmc + 8 * nc * nc
+    gc = lib.df3c_coulomb_J_grad_workspace(ctypes.byref(aux), ctypes.byref(cart), 1)
+    gp = lib.df3c_coulomb_J_grad_workspace(ctypes.byref(aux), ctypes.byref(pure), 1)
+    assert gp >= gc + 8 * nc * nc
+    assert lib.df3c_coulomb_J(buf, 1, ctypes.byref(aux), ctypes.byref(bad), buf, buf, buf,
+                              1 << 40, 0, None) == -2
+    assert lib.df3c_coulomb_J_grad(buf, 1, ctypes.byref(aux), ctypes.byref(bad), buf, buf, buf,
+                                   buf, 1 << 40, 0, None) == -2
