@@ -594,16 +594,30 @@ __global__ void k_screen_pairs(const double *xyz, ShellsDev orb, int32_t n, doub
   }
 }
 
-// indices q of the class's pairs (as the kernels decode them) that the mask
-// keeps, in increasing q: one workgroup, thread t scans a contiguous range of
-// q, the ranges' counts are scanned in LDS, then every thread writes its kept
-// indices in order (deterministic; an all-ones mask gives q = 0, 1, ...)
+// indices q of a class's pairs (as the kernels decode them) that the mask
+// keeps, in increasing q.  One workgroup per (l_a, l_b) class, all classes in
+// one launch: thread t scans a contiguous range of q, the ranges' counts are
+// scanned in LDS (log-step scan of integers), then every thread writes its
+// kept indices in order (deterministic; an all-ones mask gives q = 0, 1, ...)
 constexpr int COMPACT_TPB = 1024;
+constexpr int NCOMPACT = NLA * (NLA + 1) / 2;  // (l_a >= l_b) classes
+struct CompactJob {
+  const int32_t *ash, *bsh;
+  int32_t nb, same;
+  int64_t npair;
+  int64_t *plist;
+  unsigned long long *count;
+};
+struct CompactJobs {
+  CompactJob j[NCOMPACT];
+};
 __global__ void __launch_bounds__(COMPACT_TPB)
-    k_pair_compact(const int32_t *ash, const int32_t *bsh, int32_t nb, int32_t same, int64_t npair,
-                   const uint8_t *mask, int32_t nshell, int64_t *plist,
-                   unsigned long long *count) {
+    k_pair_compact(CompactJobs jobs, const uint8_t *mask, int32_t nshell) {
   __shared__ int64_t cnt[COMPACT_TPB];
+  const CompactJob &job = jobs.j[blockIdx.x];
+  const int32_t *ash = job.ash, *bsh = job.bsh;
+  const int32_t nb = job.nb, same = job.same;
+  const int64_t npair = job.npair;
   const int t = threadIdx.x;
   const int64_t per = (npair + COMPACT_TPB - 1) / COMPACT_TPB;
   const int64_t q0 = std::min<int64_t>(npair, int64_t(t) * per);
@@ -627,19 +641,16 @@ __global__ void __launch_bounds__(COMPACT_TPB)
   for (int64_t q = q0; q < q1; ++q) c += kept(q) ? 1 : 0;
   cnt[t] = c;
   __syncthreads();
-  if (t == 0) {
-    int64_t run = 0;
-    for (int k = 0; k < COMPACT_TPB; ++k) {
-      const int64_t v = cnt[k];
-      cnt[k] = run;
-      run += v;
-    }
-    *count = (unsigned long long)run;
+  for (int off = 1; off < COMPACT_TPB; off <<= 1) {  // inclusive scan
+    const int64_t v = t >= off ? cnt[t - off] : 0;
+    __syncthreads();
+    cnt[t] += v;
+    __syncthreads();
   }
-  __syncthreads();
-  int64_t o = cnt[t];
+  if (t == COMPACT_TPB - 1) *job.count = (unsigned long long)cnt[t];
+  int64_t o = cnt[t] - c;
   for (int64_t q = q0; q < q1; ++q)
-    if (kept(q)) plist[o++] = q;
+    if (kept(q)) job.plist[o++] = q;
 }
 
 // shell pairs of all (l_a >= l_b) classes (the masked J's pair lists)
@@ -908,16 +919,21 @@ int coulomb_J_run(const double *xyz, int32_t natom, const df3c_shells *aux,
     int64_t o = 0;
     hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, s, reinterpret_cast<int *>(pcount),
                        2 * NLA * NLA, 0);
+    CompactJobs jobs{};
+    int nj = 0;
     for (int la = 0; la <= DF3C_LMAX_ORB; ++la)
       for (int lb = 0; lb <= la; ++lb) {
         loff[la][lb] = o;
         if (!set_class(la, lb)) continue;
-        hipLaunchKernelGGL(k_pair_compact, dim3(1), dim3(COMPACT_TPB), 0, s, a.ash, a.bsh, a.nb,
-                           a.same, a.npair, mask, orb->nshell, plist + o,
-                           pcount + la * NLA + lb);
-        if (hipGetLastError() != hipSuccess) return DF3C_E_HIP;
+        jobs.j[nj++] = CompactJob{a.ash, a.bsh, a.nb, a.same, a.npair, plist + o,
+                                  pcount + la * NLA + lb};
         o += a.npair;
       }
+    if (nj) {
+      hipLaunchKernelGGL(k_pair_compact, dim3(nj), dim3(COMPACT_TPB), 0, s, jobs, mask,
+                         orb->nshell);
+      if (hipGetLastError() != hipSuccess) return DF3C_E_HIP;
+    }
   }
   unsigned long long *kept = reinterpret_cast<unsigned long long *>(g_pinned);
   if (hipMemcpyAsync(kept, pcount, sizeof(unsigned long long) * NLA * NLA, hipMemcpyDeviceToHost,
@@ -1340,6 +1356,8 @@ int grad_run(const double *xyz, int32_t natom, const df3c_shells *aux, const df3
     int64_t o = 0;
     hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, s, reinterpret_cast<int *>(pcount),
                        2 * NLA * NLA, 0);
+    CompactJobs jobs{};
+    int nj = 0;
     for (int la = 0; la <= DF3C_LMAX_GRAD_ORB; ++la)
       for (int lb = 0; lb <= la; ++lb) {
         loff[la][lb] = o;
@@ -1347,12 +1365,15 @@ int grad_run(const double *xyz, int32_t natom, const df3c_shells *aux, const df3
         const int nb = p.orb_start[lb + 1] - p.orb_start[lb];
         if (!na || !nb) continue;
         const int64_t npair = (la == lb) ? int64_t(na) * (na + 1) / 2 : int64_t(na) * nb;
-        hipLaunchKernelGGL(k_pair_compact, dim3(1), dim3(COMPACT_TPB), 0, s, orb_sorted + p.orb_start[la],
-                           orb_sorted + p.orb_start[lb], nb, int(la == lb), npair, mask,
-                           orb->nshell, plist + o, pcount + la * NLA + lb);
-        if (hipGetLastError() != hipSuccess) return DF3C_E_HIP;
+        jobs.j[nj++] = CompactJob{orb_sorted + p.orb_start[la], orb_sorted + p.orb_start[lb], nb,
+                                  int(la == lb), npair, plist + o, pcount + la * NLA + lb};
         o += npair;
       }
+    if (nj) {
+      hipLaunchKernelGGL(k_pair_compact, dim3(nj), dim3(COMPACT_TPB), 0, s, jobs, mask,
+                         orb->nshell);
+      if (hipGetLastError() != hipSuccess) return DF3C_E_HIP;
+    }
     if (hipMemcpyAsync(kept, pcount, sizeof(unsigned long long) * NLA * NLA,
                        hipMemcpyDeviceToHost, s) != hipSuccess ||
         hipStreamSynchronize(s) != hipSuccess)
