@@ -206,3 +206,32 @@ def test_J_pure_orbital_degenerate_bases(ls):
             ab.add(l, a, _logu(rng, 0.1, 5.0, 1), [1.0])
     _check(System(xyz, ob.build(), ab.build(), "pure-" + "".join(map(str, ls))),
            inputs.SEED_BASE + 1218)
+
+
+def test_J_pure_orbital_120_atoms_sampled_pairs():
+    """J over pure orbital shells of the 120-atom water cluster (the DF-J
+    benchmark workload, nao 2320, in the launch configuration the benchmark
+    times): 12 shell-pair blocks against the oracle's Cartesian blocks carried
+    through its solid-harmonic tables, with the Cartesian bar carried the same
+    way."""
+    s = inputs.dfj_120_system()
+    orb = _pure(s.orb)
+    d = inputs.fitting_coefficients(s.aux.nbf, inputs.SEED_BASE + 13)
+    print(f"pure-orbital J: 120 atoms nao={orb.nbf}", flush=True)
+    J = GpuSystem(s.xyz, s.aux, orb).coulomb_J(d)
+    assert np.array_equal(J, J.T)
+    n = orb.nshell
+    rng = np.random.default_rng(4)
+    pairs = np.stack([rng.integers(0, n, 12), rng.integers(0, n, 12)], 1)
+    pairs[0] = [0, 0]
+    pairs[1] = [n - 1, 0]
+    blocks = oracle.coulomb_J_pairs(s.xyz, s.aux, s.orb, d, pairs)
+    op = orb.offsets()
+    for (a, b), blk in zip(pairs, blocks):
+        Ta = oracle.solid_transform(int(orb.l[a]))
+        Tb = oracle.solid_transform(int(orb.l[b]))
+        ref = Ta @ blk @ Tb.T
+        bound = np.abs(Ta) @ np.maximum(1e-11 * np.abs(blk), 1e-13) @ np.abs(Tb).T
+        got = J[op[a]:op[a + 1], op[b]:op[b + 1]]
+        err = np.abs(got - ref)
+        assert (err <= bound).all(), (a, b, float(err.max()), float(bound.min()))
