@@ -247,6 +247,17 @@ def dfj_legs(args, df3c, inputs, torch, dev):
     out["grad_screened_pair_fraction"] = float(mask.double().mean())
     g = df3c.coulomb_J_grad(xyz, aux, orb, d, G)
     out["grad_screened_max_dev_rel"] = float((gs - g).abs().max() / g.abs().max())
+    # J gradient over solid-harmonic orbital shells (G over the pure functions,
+    # pulled back to the Cartesian blocks before the same engines)
+    sp = inputs.Basis(s.orb.l, s.orb.nprim, s.orb.prim_off, s.orb.atom, s.orb.exps, s.orb.coefs,
+                      pure=1)
+    orbp = df3c.DeviceBasis.from_basis(sp, dev)
+    Gp = torch.as_tensor(inputs.symmetric_density(sp.nbf, 6), device=dev)
+    wsp = torch.empty(df3c.coulomb_J_grad_workspace(aux, orbp, len(s.xyz)), dtype=torch.uint8,
+                      device=dev)
+    gp = torch.empty((len(s.xyz), 3), dtype=torch.float64, device=dev)
+    out["grad_ms_water_60atoms_pure_orbitals"] = _time_ms(
+        torch, lambda: df3c.coulomb_J_grad(xyz, aux, orbp, d, Gp, grad=gp, ws=wsp), 2)
     # batched uneven clusters
     if args.batched_nmol > 0:
         from paper_2210_03192_amd import autotune
