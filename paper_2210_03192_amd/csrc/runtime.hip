@@ -781,8 +781,10 @@ int pull_back_cart(const df3c_shells *orb, const double *G, char *q, hipStream_t
   if (hipMemcpyAsync(cmap, cm.data(), sizeof(int32_t) * nc, hipMemcpyHostToDevice, s) !=
           hipSuccess ||
       hipMemcpyAsync(poff, po.data(), sizeof(int64_t) * (orb->nshell + 1), hipMemcpyHostToDevice,
-                     s) != hipSuccess)
+                     s) != hipSuccess) {
+    (void)hipStreamSynchronize(s);  // a copy already queued still reads cm
     return DF3C_E_HIP;
+  }
   hipLaunchKernelGGL(k_bra_cart, dim3(int(std::min<int64_t>((nc * nc + 255) / 256, 8192))),
                      dim3(256), 0, s, G, np, cmap, poff, orb->l, Gc, nc);
   if (hipGetLastError() != hipSuccess) return DF3C_E_HIP;
