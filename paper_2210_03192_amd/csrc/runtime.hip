@@ -829,8 +829,10 @@ int coulomb_J_run(const double *xyz, int32_t natom, const df3c_shells *aux,
       hipMemcpyAsync(ao_off, p.ao_off.data(), sizeof(int64_t) * (orb->nshell + 1),
                      hipMemcpyHostToDevice, s) != hipSuccess ||
       hipMemcpyAsync(aux_off, p.aux_off.data(), sizeof(int64_t) * (aux->nshell + 1),
-                     hipMemcpyHostToDevice, s) != hipSuccess)
+                     hipMemcpyHostToDevice, s) != hipSuccess) {
+    (void)hipStreamSynchronize(s);  // copies already queued still read the plan
     return DF3C_E_HIP;
+  }
   hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, s, err, 1, 0);
   check_shells(aux, natom, err, s);
   check_shells(orb, natom, err, s);
@@ -1178,8 +1180,10 @@ int df3c_coulomb_gamma(const double *xyz, int32_t natom, const df3c_shells *aux,
       hipMemcpyAsync(ao_off, p.ao_off.data(), sizeof(int64_t) * (orb->nshell + 1),
                      hipMemcpyHostToDevice, s) != hipSuccess ||
       hipMemcpyAsync(aux_off, p.aux_off.data(), sizeof(int64_t) * (aux->nshell + 1),
-                     hipMemcpyHostToDevice, s) != hipSuccess)
+                     hipMemcpyHostToDevice, s) != hipSuccess) {
+    (void)hipStreamSynchronize(s);  // copies already queued still read the plan
     return DF3C_E_HIP;
+  }
   hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, s, err, 1, 0);
   check_shells(aux, natom, err, s);
   check_shells(orb, natom, err, s);
@@ -1322,8 +1326,10 @@ int grad_run(const double *xyz, int32_t natom, const df3c_shells *aux, const df3
       hipMemcpyAsync(ao_off, p.ao_off.data(), sizeof(int64_t) * (orb->nshell + 1),
                      hipMemcpyHostToDevice, s) != hipSuccess ||
       hipMemcpyAsync(aux_off, p.aux_off.data(), sizeof(int64_t) * (aux->nshell + 1),
-                     hipMemcpyHostToDevice, s) != hipSuccess)
+                     hipMemcpyHostToDevice, s) != hipSuccess) {
+    (void)hipStreamSynchronize(s);  // copies already queued still read the plan
     return DF3C_E_HIP;
+  }
   hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, s, err, 1, 0);
   check_shells(aux, natom, err, s);
   check_shells(orb, natom, err, s);
@@ -1657,8 +1663,10 @@ int df3c_coulomb_J_batched(const double *xyz, int32_t natom, const df3c_shells *
       hipMemcpyAsync(aux_off, p.aux_off.data(), sizeof(int64_t) * p.aux_off.size(),
                      hipMemcpyHostToDevice, s) != hipSuccess ||
       (!p.seg.empty() && hipMemcpyAsync(segd, p.seg.data(), sizeof(JSeg) * p.seg.size(),
-                                        hipMemcpyHostToDevice, s) != hipSuccess))
+                                        hipMemcpyHostToDevice, s) != hipSuccess)) {
+    (void)hipStreamSynchronize(s);  // copies already queued still read the plan
     return DF3C_E_HIP;
+  }
   hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, s, err, 1, 0);
   check_shells(aux, natom, err, s);
   check_shells(orb, natom, err, s);
