@@ -5,7 +5,8 @@ Cartesian block on both sides by its definition.
 * orbital s..g shells (contracted s and p), pure aux s..i, three atoms;
 * a water cluster (the element basis) with the orbital basis taken pure;
 * the masked J over pure orbital shells: the kept blocks are the oracle's
-  full-J blocks, the others zero.
+  full-J blocks, the others zero; an all-ones mask gives the unmasked pure J
+  bitwise.
 
 Bar: the Cartesian J's bar, max(1e-11 |x|, 1e-13) per element, carried
 through the linear transform: |x - x_ref| <= (|T_a| B_cart |T_b|^T)[r, c] with
@@ -112,6 +113,9 @@ def test_masked_J_pure_orbitals():
     dd = torch.as_tensor(d, device="cuda")
     m = torch.as_tensor(mask, device="cuda")
     J = df3c.coulomb_J_masked(g.xyz, g.aux, g.orb, dd, m)
+    ones = torch.ones_like(m)
+    assert torch.equal(df3c.coulomb_J_masked(g.xyz, g.aux, g.orb, dd, ones),
+                       df3c.coulomb_J(g.xyz, g.aux, g.orb, dd))
     torch.cuda.synchronize()
     J = J.cpu().numpy()
     assert J.shape == ref.shape
