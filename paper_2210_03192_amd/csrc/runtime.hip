@@ -763,6 +763,7 @@ __global__ void k_bra_cart(const double *G, int64_t np, const int32_t *cmap,
 // *out points at Gc on success.  Synchronises s (host vectors).
 int pull_back_cart(const df3c_shells *orb, const double *G, char *q, hipStream_t s,
                    const double **out) {
+  if (orb->nshell >= (1 << 27)) return DF3C_E_UNSUPPORTED;  // rows packed as shell << 4 | c
   std::vector<int32_t> cm;
   std::vector<int64_t> po(orb->nshell + 1, 0);
   for (int sh = 0; sh < orb->nshell; ++sh) {
@@ -846,6 +847,7 @@ int coulomb_J_run(const double *xyz, int32_t natom, const df3c_shells *aux,
   int32_t *pmap = nullptr;
   int64_t npure = 0;
   if (orb->pure) {
+    if (orb->nshell >= (1 << 27)) return DF3C_E_UNSUPPORTED;  // rows packed as shell << 4 | m
     std::vector<int32_t> pm;
     for (int sh = 0; sh < orb->nshell; ++sh)
       for (int m = 0; m < 2 * orb->l_host[sh] + 1; ++m) pm.push_back(sh << 4 | m);
