@@ -43,7 +43,7 @@ def main():
                 "# CPU oracle (explicit derivatives of all three centres, double precision).\n"
                 "# columns: atom  dL/dX  dL/dY  dL/dZ  (hartree/bohr)\n")
         for X, g in rows:
-            f.write(f"{X} {g[0]!r} {g[1]!r} {g[2]!r}\n")
+            f.write(f"{X} {float(g[0])!r} {float(g[1])!r} {float(g[2])!r}\n")
 
 
 if __name__ == "__main__":
