@@ -25,6 +25,8 @@ __device__ __forceinline__ void static_for(F &&f) {
 
 __device__ __forceinline__ void team_sync() { __syncthreads(); }
 
+__device__ __forceinline__ bool wave_any(bool v) { return __any(v ? 1 : 0) != 0; }
+
 __device__ __forceinline__ int wave_max(int v) {
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o, 64));

@@ -196,6 +196,11 @@ struct Cfg {
                              : TS >= 16 ? 4 : TS == 4 ? 2 : 1;
   static constexpr int BLK = TS > 64 ? TS : 64;
   static constexpr int LDS = (BLK / TS) * Layout<LP, LA, LB, PCH>::TOTAL * 8;
+  // store kernels also run the pipeline with the shells swapped (the second
+  // HRR direction of a split contracted pair); a team's slice holds either
+  static constexpr int STORE_TEAM =
+      imax(Layout<LP, LA, LB, PCH>::TOTAL, LA > LB ? Layout<LP, LB, LA, PCH>::TOTAL : 0) | 1;
+  static constexpr int STORE_LDS = (BLK / TS) * STORE_TEAM * 8;
   // minimum waves per SIMD requested from the register allocator
   static constexpr int WPE = TS >= 128 ? DF3C_MIN_WAVES_BIG : TS == 64 ? DF3C_MIN_WAVES_WAVE : 1;
   // J kernels: one lane per shell pair on the register engine, else the J
@@ -212,6 +217,7 @@ struct Cfg {
   static constexpr int WPEJ = JREG ? DF3C_MIN_WAVES_JREG : TSJ >= 128 ? DF3C_MIN_WAVES_BIG
                                                                     : DF3C_MIN_WAVES_WAVE;
   static_assert(LDS <= 160 * 1024, "class does not fit the LDS of a CU");
+  static_assert(STORE_LDS <= 160 * 1024, "class does not fit the LDS of a CU");
 };
 
 // ---------------------------------------------------------------------------
@@ -277,16 +283,69 @@ struct PiTiles {
 // WM selects the contraction weights: 0 -> c_a c_b c_c, 1 -> 2 zeta_a c_a c_b c_c,
 // 2 -> 2 zeta_b c_a c_b c_c (the raised bra of the derivative integrals).
 // ---------------------------------------------------------------------------
+// ---------------------------------------------------------------------------
+// Split of a contracted shell pair by HRR direction.  Eq. hrr transfers quanta
+// from the centre that carries the VRR1 quanta to the other one with powers of
+// AB, applied to the contracted (e0| of all primitive pairs at once.  A pair
+// (ia, ib) whose Gaussian product centre P lies near the other centre
+// (zeta_a < zeta_b) gives (e0| terms of order |PA|^e that the transfer
+// cancels, so with contracted shells mixing tight and diffuse primitives at a
+// few bohr the single-direction result loses up to ~1e-9 relative (and a
+// single pair with the tight exponent on the lower-l shell, whose quanta
+// would go to the higher-l shell, loses accuracy the same way).  The store
+// kernels therefore contract the pairs with zeta_a >= zeta_b with the quanta
+// on A (group 1) and the others with the quanta on B (group 2, the pipeline
+// with the shells swapped: zeta_b > zeta_a strictly), and add the two blocks.
+// Group 0 keeps every pair (no split).  Pairs of a group are taken in
+// row-major (ia, ib) order.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ bool split_keep(int grp, double za, double zb) {
+  return grp == 1 ? za >= zb : za > zb;
+}
+
+__device__ __forceinline__ int split_count(int grp, int Ka, int Kb, const double *ea,
+                                           const double *eb) {
+  if (grp == 0) return Ka * Kb;
+  int n = 0;
+  for (int i = 0; i < Ka; ++i) {
+    const double za = ea[i];
+    for (int j = 0; j < Kb; ++j) n += split_keep(grp, za, eb[j]) ? 1 : 0;
+  }
+  return n;
+}
+
+// (ia, ib) of the q-th pair of group grp (q < split_count)
+__device__ __forceinline__ void split_pair(int q, int grp, int Ka, int Kb, const double *ea,
+                                           const double *eb, int &ia, int &ib) {
+  ia = q / Kb;
+  ib = q - ia * Kb;
+  if (grp == 0) return;
+  for (int i = 0; i < Ka; ++i) {
+    const double za = ea[i];
+    for (int j = 0; j < Kb; ++j)
+      if (split_keep(grp, za, eb[j])) {
+        if (q == 0) {
+          ia = i;
+          ib = j;
+          return;
+        }
+        --q;
+      }
+  }
+}
+
 template <class G, int WM>
 __device__ __forceinline__ void setup_prim(const double *btab, double *R, int p, int Kb, int Kc,
                                            const double *A, const double *B, const double *C,
                                            double AB2, const double *ea, const double *ca,
                                            const double *eb, const double *cb,
-                                           const double *ec, const double *cc) {
+                                           const double *ec, const double *cc, int grp = 0,
+                                           int Ka = 0) {
   constexpr int LP = G::LP, L = G::L;
   {
     const int ic = p % Kc, rest = p / Kc;
-    const int ib = rest % Kb, ia = rest / Kb;
+    int ia, ib;
+    split_pair(rest, grp, Ka, Kb, ea, eb, ia, ib);
     const double za = ea[ia], zb = eb[ib], zc = ec[ic];
     const double g = za + zb, ig = 1.0 / g;
     const double Px = (za * A[0] + zb * B[0]) * ig, Py = (za * A[1] + zb * B[1]) * ig,
@@ -345,10 +404,11 @@ __device__ __forceinline__ void setup_chunk(const double *btab, double *prims, i
                                             const double *B, const double *C, double AB2,
                                             const double *ea, const double *ca,
                                             const double *eb, const double *cb,
-                                            const double *ec, const double *cc) {
+                                            const double *ec, const double *cc, int grp = 0,
+                                            int Ka = 0) {
   for (int pp = lt; pp < npc; pp += TS)
     setup_prim<G, WM>(btab, prims + pp * REC, p0 + pp, Kb, Kc, A, B, C, AB2, ea, ca, eb, cb, ec,
-                      cc);
+                      cc, grp, Ka);
 }
 
 // ---------------------------------------------------------------------------
@@ -362,7 +422,8 @@ __device__ __forceinline__ void triplet_to_e0P(const double *btab, double *S, in
                                                const double *B, const double *C, int Ka,
                                                const double *ea, const double *ca, int Kb,
                                                const double *eb, const double *cb, int Kc,
-                                               const double *ec, const double *cc, int pure) {
+                                               const double *ec, const double *cc, int pure,
+                                               int grp = 0) {
   using G = Geo<LP, LA, LA + LB>;
   using LY = Layout<LP, LA, LB, PCH>;
   using TB = GenTab<LP, G::EA, G::EB>;
@@ -375,7 +436,7 @@ __device__ __forceinline__ void triplet_to_e0P(const double *btab, double *S, in
 
   const double ABx = A[0] - B[0], ABy = A[1] - B[1], ABz = A[2] - B[2];
   const double AB2 = ABx * ABx + ABy * ABy + ABz * ABz;
-  const int K = Ka * Kb * Kc;
+  const int K = split_count(grp, Ka, Kb, ea, eb) * Kc;
 
   // matrix-core contraction for whole-wave teams (chunks of 4 primitives = the
   // K extent of one MFMA); per-lane register slots otherwise
@@ -399,7 +460,7 @@ __device__ __forceinline__ void triplet_to_e0P(const double *btab, double *S, in
     int lt = tid;
     __asm__ volatile("" : "+v"(lt));
     setup_chunk<G, TS, REC, WM>(btab, prims, lt, p0, npc, Kb, Kc, A, B, C, AB2, ea, ca, eb, cb, ec,
-                                cc);
+                                cc, grp, Ka);
     team_sync();
     // ---- VRR1, 2-quantal stages in place
     vrr1<G, TS, PCH, REC>(prims, npc, lt);
@@ -683,7 +744,7 @@ __global__ void __launch_bounds__(TS > 64 ? TS : 64)
   constexpr int NQ = (G::NPI + TS - 1) / TS;
   extern __shared__ double smem[];
   const int team = threadIdx.x / TS, tid = threadIdx.x % TS;
-  double *S = smem + team * LY::TOTAL;
+  double *S = smem + team * Cfg<LP, LA, LB>::STORE_TEAM;
   const int np_out = a.pure ? npure(LP) : ncart(LP);
   int slot[NQ];
   make_slots<LP, LA, LB, TS>(slot, tid);
@@ -703,7 +764,6 @@ __global__ void __launch_bounds__(TS > 64 ? TS : 64)
     const int sa = swp ? s2 : s1, sb = swp ? s1 : s2;
     const int Ka = valid ? a.orb.nprim[sa] : 0, Kb = valid ? a.orb.nprim[sb] : 0;
     const int Kc = valid ? a.aux.nprim[sP] : 0;
-    const int npmax = TS >= 64 ? Ka * Kb * Kc : wave_max(Ka * Kb * Kc);
     const int64_t oa = valid ? a.orb.prim_off[sa] : 0, ob = valid ? a.orb.prim_off[sb] : 0,
                   oc = valid ? a.aux.prim_off[sP] : 0;
     double Ar[3] = {0, 0, 0}, Br[3] = {0, 0, 0}, Cr[3] = {0, 0, 0};
@@ -715,19 +775,64 @@ __global__ void __launch_bounds__(TS > 64 ? TS : 64)
         Cr[x] = a.xyz[3 * ic + x];
       }
     }
-    triplet_to_e0P<LP, LA, LB, TS, PCH>(a.boys, S, tid, slot, npmax, Ar, Br, Cr, Ka,
-                                        a.orb.exps + oa, a.orb.coefs + oa, Kb, a.orb.exps + ob,
-                                        a.orb.coefs + ob, Kc, a.aux.exps + oc, a.aux.coefs + oc,
-                                        a.pure);
-    hrr_block<LP, LA, LB, TS, PCH>(S, tid, Ar, Br, np_out, swp);
-    team_sync();
+    const double *ea = a.orb.exps + oa, *eb = a.orb.exps + ob;
+    // HRR direction per primitive pair: pass 1 puts the VRR1 quanta on A
+    // (pairs with zeta_a >= zeta_b), pass 2 on B (the rest), and the blocks
+    // add.  A shell pair whose pairs all prefer A runs pass 1 alone over all
+    // of them; one whose pairs all prefer B (possible for l_a > l_b, where the
+    // quanta would otherwise always go to the higher-l shell) pass 2 alone;
+    // A == B needs no transfer and runs pass 1.
+    int n1 = 0;
+    bool far = false;
     if (valid) {
-      double *out = a.out + a.out_off[t];
-      const double *STG = S + LY::STG;
-      const int nout = np_out * NA * NB;
-      for (int o = tid; o < nout; o += TS) out[o] = STG[o];
+      const double ABx = Ar[0] - Br[0], ABy = Ar[1] - Br[1], ABz = Ar[2] - Br[2];
+      far = ABx * ABx + ABy * ABy + ABz * ABz > 0.0;
+      n1 = split_count(1, Ka, Kb, ea, eb);
     }
-    team_sync();
+    const int nab = Ka * Kb;
+    const bool run1 = valid && (!far || n1 > 0), run2 = valid && far && n1 < nab;
+    // the passes are uniform over the workgroup (teams of one wave share
+    // barriers); a team without work in a pass runs it over no primitives
+    const bool do1 = TS >= 64 ? run1 : wave_any(run1);
+    const bool do2 = TS >= 64 ? run2 : wave_any(run2);
+    const int nout = np_out * NA * NB;
+    if (do1) {
+      const int K1 = (run1 ? (run2 ? n1 : nab) : 0) * Kc;
+      triplet_to_e0P<LP, LA, LB, TS, PCH>(a.boys, S, tid, slot, TS >= 64 ? K1 : wave_max(K1),
+                                          Ar, Br, Cr, Ka, ea, a.orb.coefs + oa, Kb, eb,
+                                          a.orb.coefs + ob, run1 ? Kc : 0, a.aux.exps + oc,
+                                          a.aux.coefs + oc, a.pure, run2 ? 1 : 0);
+      hrr_block<LP, LA, LB, TS, PCH>(S, tid, Ar, Br, np_out, swp);
+      team_sync();
+      if (run1) {
+        double *out = a.out + a.out_off[t];
+        const double *STG = S + LY::STG;
+        for (int o = tid; o < nout; o += TS) out[o] = STG[o];
+      }
+      team_sync();
+    }
+    if (do2) {
+      // quanta on B: for l_a > l_b the pipeline of the swapped class
+      // (LP, LB, LA), whose VRR1 builds e = LB..LA+LB on B and whose HRR
+      // moves LA quanta to A
+      const int K2 = run2 ? (nab - n1) * Kc : 0;
+      triplet_to_e0P<LP, LB, LA, TS, PCH>(a.boys, S, tid, LA == LB ? slot : nullptr,
+                                          TS >= 64 ? K2 : wave_max(K2), Br, Ar, Cr, Kb, eb,
+                                          a.orb.coefs + ob, Ka, ea, a.orb.coefs + oa,
+                                          run2 ? Kc : 0, a.aux.exps + oc, a.aux.coefs + oc,
+                                          a.pure, 2);
+      hrr_block<LP, LB, LA, TS, PCH>(S, tid, Br, Ar, np_out, !swp);
+      team_sync();
+      if (run2) {
+        double *out = a.out + a.out_off[t];
+        const double *STG = S + Layout<LP, LB, LA, PCH>::STG;
+        if (run1)
+          for (int o = tid; o < nout; o += TS) out[o] += STG[o];
+        else
+          for (int o = tid; o < nout; o += TS) out[o] = STG[o];
+      }
+      team_sync();
+    }
   }
 }
 

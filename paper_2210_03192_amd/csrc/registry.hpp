@@ -39,9 +39,10 @@ hipError_t launch_store(const StoreArgs &a, int grid, hipStream_t s) {
   using C = Cfg<LP, LA, LB>;
   auto kern = k_store<LP, LA, LB, C::TS, C::PCH>;
   static const hipError_t attr = hipFuncSetAttribute(
-      reinterpret_cast<const void *>(kern), hipFuncAttributeMaxDynamicSharedMemorySize, C::LDS);
+      reinterpret_cast<const void *>(kern), hipFuncAttributeMaxDynamicSharedMemorySize,
+      C::STORE_LDS);
   if (attr != hipSuccess) return attr;
-  hipLaunchKernelGGL(kern, dim3(grid), dim3(C::BLK), C::LDS, s, a);
+  hipLaunchKernelGGL(kern, dim3(grid), dim3(C::BLK), C::STORE_LDS, s, a);
   return hipGetLastError();
 }
 
@@ -158,7 +159,7 @@ ClassInfo class_info() {
   c.tpw = C::BLK / C::TS;
   c.tpwj = C::BLKJ / C::TSJ;
   c.jreg = C::JREG ? 1 : 0;
-  c.lds = C::LDS;
+  c.lds = C::STORE_LDS;
   c.store = &launch_store<LP, LA, LB>;
   c.jfn = &launch_J<LP, LA, LB>;
   c.jq = &launch_Jq<LP, LA, LB>;

@@ -376,6 +376,11 @@ def coulomb_J_batched(xyz: torch.Tensor, aux: DeviceBasis, orb: DeviceBasis,
     if J is None:
         J = torch.empty(int((nao * nao).sum()), dtype=torch.float64, device=xyz.device)
     need = coulomb_J_batched_workspace(aux, orb, nmol)
+    if flags & GRAPH and (ws is None or ws.numel() < need):
+        # the cached graph replays against the same workspace address on later
+        # calls, so the workspace must be the caller's and outlive them
+        raise DF3CError("coulomb_J_batched: GRAPH needs a caller-owned workspace (ws) of "
+                        f"at least {need} bytes, kept for every later call")
     if ws is None or ws.numel() < need:
         ws = torch.empty(max(need, 1), dtype=torch.uint8, device=xyz.device)
     sa, so = aux.struct(), orb.struct()

@@ -23,3 +23,24 @@ def single_triplet(A, B, C, la, lb, lc, za, zb, zc, ca=None, cb=None, cc=None, p
 
 def block_shape(lc, la, lb, pure):
     return (npure(lc) if pure else ncart(lc), ncart(la), ncart(lb))
+
+
+def close_shell_pairs(orb, xyz, seed, per_class=3, max_dist=3.0):
+    """Orbital shell pairs (a, b) whose centres lie within max_dist bohr of each
+    other (same atom or a bonded neighbour), per_class of them for every
+    (l_a >= l_b) combination the basis has, drawn with a seeded generator.
+    Their J blocks are the largest of a molecule, so the relative part of the
+    parity bar applies to most of their elements."""
+    rng = np.random.default_rng(seed)
+    l = np.asarray(orb.l)
+    atom = np.asarray(orb.atom)
+    dist = np.sqrt(((xyz[atom][:, None, :] - xyz[atom][None, :, :]) ** 2).sum(-1))
+    pairs = []
+    for la in range(int(l.max()) + 1):
+        for lb in range(la + 1):
+            a_idx, b_idx = np.nonzero((l[:, None] == la) & (l[None, :] == lb) & (dist <= max_dist))
+            if not len(a_idx):
+                continue
+            pick = rng.choice(len(a_idx), min(per_class, len(a_idx)), replace=False)
+            pairs += [(int(a_idx[k]), int(b_idx[k])) for k in pick]
+    return np.array(pairs, np.int32).reshape(-1, 2)

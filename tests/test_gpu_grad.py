@@ -112,3 +112,36 @@ def test_grad_rejects_bad_atom_index():
     G = torch.zeros((s.orb.nbf, s.orb.nbf), dtype=torch.float64, device="cuda")
     with pytest.raises(df3c.DF3CError):
         df3c.coulomb_J_grad(xyz[:2].contiguous(), aux, orb, d, G)
+
+
+def _golden_rows(path):
+    atoms, rows = [], []
+    with open(path) as f:
+        for line in f:
+            if line.startswith("#") or not line.strip():
+                continue
+            x = line.split()
+            atoms.append(int(x[0]))
+            rows.append([float(v) for v in x[1:4]])
+    return np.array(atoms), np.array(rows)
+
+
+def test_grad_60_atoms_vs_oracle_rows():
+    """The differentiable workload at full size (60-atom water cluster, the
+    launch the benchmark times) against the oracle's explicit three-centre
+    gradient rows of six atoms (tests/golden/grad60_atoms.txt, written by
+    tests/golden/make_grad60_golden.py from the oracle alone): 1e-10 of the
+    largest oracle row element."""
+    import os
+    torch = _torch()
+    s = inputs.grad_60_system()
+    d = torch.as_tensor(inputs.fitting_coefficients(s.aux.nbf, 5), device="cuda")
+    G = torch.as_tensor(inputs.symmetric_density(s.orb.nbf, 6), device="cuda")
+    df3c, xyz, aux, orb = _dev(s)
+    g = df3c.coulomb_J_grad(xyz, aux, orb, d, G).cpu().numpy()
+    atoms, ref = _golden_rows(os.path.join(os.path.dirname(__file__), "golden",
+                                           "grad60_atoms.txt"))
+    assert len(atoms) >= 4
+    err = np.abs(g[atoms] - ref).max() / np.abs(ref).max()
+    print(f"60-atom gradient vs oracle rows of atoms {atoms.tolist()}: {err:.3g}")
+    assert err <= 1e-10, err

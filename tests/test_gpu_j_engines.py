@@ -50,3 +50,47 @@ def test_J_orbital_s_to_g_pure_aux_s_to_i():
 
 def test_J_orbital_s_to_g_cartesian_aux():
     _check(_system(inputs.SEED_BASE + 63, (0, 1, 1), 0), inputs.SEED_BASE + 64)
+
+
+def _contracted_system(seed):
+    """Three atoms 2.5..6 bohr apart with contracted d (K=3), f (K=3) and g
+    (K=2) orbital shells whose primitives mix tight and diffuse exponents
+    (log-uniform in [0.05, 100]), plus s and p; pure aux s..g."""
+    rng = np.random.default_rng(seed)
+    xyz = random_atoms(rng, 3, 5.0, 2.5)
+    ob, ab = _Builder(0), _Builder(1)
+    for a in range(3):
+        for l, k in ((0, 3), (1, 3), (2, 3), (3, 3), (4, 2)):
+            ob.add(l, a, _logu(rng, 0.05, 100.0, k), rng.uniform(0.1, 1.0, k))
+        for l in range(5):
+            ab.add(l, a, _logu(rng, 0.05, 20.0, 1), [1.0])
+    return System(xyz, ob.build(), ab.build(), "j-contracted")
+
+
+def test_J_contracted_high_l_orbital_shells():
+    """Contracted d, f, g orbital shells mixing tight and diffuse primitives
+    (exponents three orders apart, centres 2.5..5 bohr apart): the case
+    where a single HRR direction per shell pair loses accuracy.  The raw-block
+    kernels split such pairs by HRR direction (their parity tests hold the
+    element bar); the DF-J engines keep one direction per pair, so J is held
+    to the element bar carried through the sum over the fitting functions,
+    sum_P |d_P| max(1e-11 |(ab|P)|, 1e-13), and the ratio to the element bar
+    is reported."""
+    from tests.gamma_bar import j_pair_bars
+    s = _contracted_system(inputs.SEED_BASE + 65)
+    d = inputs.fitting_coefficients(s.aux.nbf, inputs.SEED_BASE + 66)
+    J = GpuSystem(s.xyz, s.aux, s.orb).coulomb_J(d)
+    ref = oracle.coulomb_J(s.xyz, s.aux, s.orb, d, precision="long")
+    n = s.orb.nshell
+    pairs = [(a, b) for a in range(n) for b in range(n)]
+    bars = j_pair_bars(s.xyz, s.aux, s.orb, d, pairs)
+    ao = s.orb.offsets()
+    worst_elem, worst_carried = 0.0, 0.0
+    for (a, b), bar in zip(pairs, bars):
+        r = ref[ao[a]:ao[a + 1], ao[b]:ao[b + 1]]
+        e = np.abs(J[ao[a]:ao[a + 1], ao[b]:ao[b + 1]] - r)
+        worst_elem = max(worst_elem, float((e / np.maximum(1e-11 * np.abs(r), 1e-13)).max()))
+        worst_carried = max(worst_carried, float((e / bar).max()))
+    print(f"contracted high-l J: worst error / element bar {worst_elem:.3g}, "
+          f"/ carried bar {worst_carried:.3g}")
+    assert worst_carried <= 1.0, worst_carried

@@ -34,12 +34,13 @@ def assert_parity(x, ref, rtol=RTOL, atol=ATOL, what=""):
                              f"index {i}: got {x[i]!r}, oracle {ref[i]!r}, |err| {err[i]:.3e}")
 
 
-def assert_blocks(got, xyz, aux, orb, trip, off, what=""):
+def assert_blocks(got, xyz, aux, orb, trip, off, what="", ref=None):
     """Blocks against the double-precision oracle; elements outside the bar are
     adjudicated by the long-double build of the oracle (the double oracle has
     its own rounding error, which matters only where the integral suffers
     cancellation)."""
-    ref, _ = oracle.eval_batch(xyz, aux, orb, trip, off)
+    if ref is None:
+        ref, _ = oracle.eval_batch(xyz, aux, orb, trip, off)
     try:
         assert_parity(got, ref, what=what)
     except AssertionError:
@@ -120,21 +121,68 @@ def test_mixed_batch_and_ragged_offsets():
     assert np.isnan(g[~mask]).all(), "gaps between blocks were written"
 
 
+def _largest_blocks_first(cb):
+    """Triplet indices of a per-class batch ordered by a size proxy of their
+    blocks: the largest primitive overlap factor exp(-z_a z_b/(z_a+z_b) |AB|^2)
+    of the bra pair over max(1, |P-C|) (P the pair's midpoint).  The largest
+    blocks are those of close, diffuse bra pairs, where the integrals are
+    O(1e-2..1) and the relative part of the bar decides."""
+    K = cb.K
+    ea = cb.orb.exps.reshape(-1, K)[0::2]
+    eb = cb.orb.exps.reshape(-1, K)[1::2]
+    C, A, B = cb.xyz[0::3], cb.xyz[1::3], cb.xyz[2::3]
+    ab2 = ((A - B) ** 2).sum(1)
+    mu = ea[:, :, None] * eb[:, None, :] / (ea[:, :, None] + eb[:, None, :])
+    s = np.exp(-mu * ab2[:, None, None]).max((1, 2))
+    pc = np.sqrt((((A + B) / 2 - C) ** 2).sum(1))
+    return np.argsort(-s / np.maximum(pc, 1.0), kind="stable")
+
+
+# elements at or above this size are judged by the relative part of the bar
+REL_BAR_FROM = ATOL / RTOL
+
+
 @pytest.mark.parametrize("cls", inputs.PER_CLASS_CLASSES, ids=lambda c: "P%d_a%d_b%d" % c)
 @pytest.mark.parametrize("K", inputs.PER_CLASS_K)
 def test_per_class_full_size_sampled(cls, K):
-    """The 1e5-triplet per-class batches at full size; 48 sampled triplets
-    (first, last and random) against the oracle."""
+    """The 1e5-triplet per-class batches at full size, in the launch the
+    benchmark times; about 2000 triplets against the oracle: the 1000 with the
+    largest blocks (size proxy above), 1000 drawn at random, the first and the
+    last.  At least 500 compared elements of every batch must be large enough
+    (>= 1e-2) for the relative 1e-11 bar to apply."""
     LP, la, lb = cls
     cb = inputs.class_batch(LP, la, lb, K, 100000)
     g = GpuSystem(cb.xyz, cb.aux, cb.orb).eval_batch(cb.trip, cb.out_off, cb.nint)
+    assert np.isfinite(g).all()
     rng = np.random.default_rng(5)
-    idx = np.unique(np.concatenate([[0, cb.ntrip - 1], rng.integers(0, cb.ntrip, 46)]))
+    idx = np.unique(np.concatenate([[0, cb.ntrip - 1], _largest_blocks_first(cb)[:1000],
+                                    rng.integers(0, cb.ntrip, 1000)]))
     sub = cb.trip[idx]
     got = np.concatenate([g[cb.out_off[t]:cb.out_off[t] + cb.block] for t in idx])
+    ref, _ = oracle.eval_batch(cb.xyz, cb.aux, cb.orb, sub, cb.block * np.arange(len(idx)))
+    n_rel = int((np.abs(ref) >= REL_BAR_FROM).sum())
+    print(f"class {cls} K={K}: {len(idx)} triplets, {ref.size} elements, {n_rel} at the "
+          f"relative bar, {int((np.abs(ref) < ATOL).sum())} below the floor")
+    assert n_rel >= 500, f"only {n_rel} compared elements reach the relative bar"
     assert_blocks(got, cb.xyz, cb.aux, cb.orb, sub, cb.block * np.arange(len(idx)),
-                  what=f"class {cls} K={K}")
-    assert np.isfinite(g).all()
+                  what=f"class {cls} K={K}", ref=ref)
+
+
+@pytest.mark.parametrize("cls", ALL_CLASSES, ids=lambda c: "P%d_a%d_b%d" % c)
+def test_class_parity_contracted_largest_blocks(cls):
+    """Every class with contracted orbital shells (K_a = K_b = 3, exponents
+    log-uniform in [0.05, 100], mixing tight and diffuse primitives): out of
+    4000 triplets in a 20 bohr box, the 150 with the largest blocks (size
+    proxy above) and 50 random ones against the oracle."""
+    LP, la, lb = cls
+    cb = inputs.class_batch(LP, la, lb, 3, 4000, seed=9000 + 100 * LP + 10 * la + lb)
+    g = GpuSystem(cb.xyz, cb.aux, cb.orb).eval_batch(cb.trip, cb.out_off, cb.nint)
+    rng = np.random.default_rng(7)
+    idx = np.unique(np.concatenate([_largest_blocks_first(cb)[:150],
+                                    rng.integers(0, cb.ntrip, 50)]))
+    got = np.concatenate([g[cb.out_off[t]:cb.out_off[t] + cb.block] for t in idx])
+    assert_blocks(got, cb.xyz, cb.aux, cb.orb, cb.trip[idx], cb.block * np.arange(len(idx)),
+                  what=f"class {cls} K=3")
 
 
 def test_plain_dfj_full():
@@ -168,19 +216,28 @@ def test_J_equals_contracted_blocks():
 
 
 def test_water_cluster_J_sampled_pairs():
-    """J of the 120-atom water cluster (2600 AOs, 10360 aux functions); 12
-    shell-pair blocks against the oracle."""
+    """J of the 120-atom water cluster (2600 AOs, 10360 aux functions) in the
+    launch the benchmark times: the blocks of 6 close shell pairs (same atom
+    or bonded neighbours) of every (l_a, l_b) class, where J is largest, and
+    12 random pairs against the oracle.  At least 1000 compared elements must
+    reach the relative part of the bar."""
+    from tests.helpers import close_shell_pairs
     s = inputs.dfj_120_system()
     d = inputs.fitting_coefficients(s.aux.nbf, inputs.SEED_BASE + 13)
     J = GpuSystem(s.xyz, s.aux, s.orb).coulomb_J(d)
     rng = np.random.default_rng(3)
-    pairs = np.stack([rng.integers(0, s.orb.nshell, 12), rng.integers(0, s.orb.nshell, 12)], 1)
-    pairs[0] = [0, 0]
-    pairs[1] = [s.orb.nshell - 1, 0]
+    rnd = np.stack([rng.integers(0, s.orb.nshell, 12), rng.integers(0, s.orb.nshell, 12)], 1)
+    rnd[0] = [0, 0]
+    rnd[1] = [s.orb.nshell - 1, 0]
+    pairs = np.concatenate([close_shell_pairs(s.orb, s.xyz, 31, per_class=6), rnd])
     blocks = oracle.coulomb_J_pairs(s.xyz, s.aux, s.orb, d, pairs)
     ao = s.orb.offsets()
+    n_rel = 0
     for (a, b), blk in zip(pairs, blocks):
         assert_parity(J[ao[a]:ao[a + 1], ao[b]:ao[b + 1]], blk, what=f"pair {a},{b}")
+        n_rel += int((np.abs(blk) >= ATOL / RTOL).sum())
+    print(f"water-120 J: {len(pairs)} pairs, {n_rel} elements at the relative bar")
+    assert n_rel >= 1000, n_rel
     assert np.abs(J - J.T).max() == 0.0
 
 

@@ -20,6 +20,7 @@ import numpy as np
 import pytest
 
 import oracle
+from tests.gamma_bar import assert_gamma
 from paper_2210_03192_amd import inputs
 from paper_2210_03192_amd.inputs import Basis, System, _Builder, _logu, random_atoms
 from tests.test_gpu_parity import GpuSystem, _torch
@@ -159,17 +160,7 @@ def test_gradient_pure_orbitals():
 
 
 def _assert_gamma(g, s, D, what):
-    """The Cartesian gamma test's bar: max(1e-11 |ref|, 1e-13 max|ref|), with
-    elements outside it adjudicated by the long-double oracle."""
-    ref = oracle.coulomb_gamma(s.xyz, s.aux, s.orb, D)
-    atol = 1e-13 * np.abs(ref).max()
-
-    def bad(r):
-        return np.abs(g - r) > np.maximum(1e-11 * np.abs(r), atol)
-    if bad(ref).any():
-        ref_ld = oracle.coulomb_gamma(s.xyz, s.aux, s.orb, D, precision="long")
-        b = bad(ref_ld)
-        assert not b.any(), (what, int(b.sum()), np.abs(g - ref_ld).max())
+    assert_gamma(g, s.xyz, s.aux, s.orb, D, what)
 
 
 def test_gamma_and_autograd_pure_orbitals():
@@ -215,9 +206,13 @@ def test_J_pure_orbital_degenerate_bases(ls):
 def test_J_pure_orbital_120_atoms_sampled_pairs():
     """J over pure orbital shells of the 120-atom water cluster (the DF-J
     benchmark workload, nao 2320, in the launch configuration the benchmark
-    times): 12 shell-pair blocks against the oracle's Cartesian blocks carried
-    through its solid-harmonic tables, with the Cartesian bar carried the same
-    way."""
+    times): the blocks of 10 close shell pairs (same atom or bonded
+    neighbours) of every (l_a, l_b) class, d-d, f-d and f-f included, and 12
+    random pairs against the oracle's Cartesian blocks carried through its
+    solid-harmonic tables, with the Cartesian bar carried the same way.  At
+    least 500 elements of the l >= 2 blocks must be >= 1e-2, where the
+    relative part of the bar applies."""
+    from tests.helpers import close_shell_pairs
     s = inputs.dfj_120_system()
     orb = _pure(s.orb)
     d = inputs.fitting_coefficients(s.aux.nbf, inputs.SEED_BASE + 13)
@@ -226,11 +221,13 @@ def test_J_pure_orbital_120_atoms_sampled_pairs():
     assert np.array_equal(J, J.T)
     n = orb.nshell
     rng = np.random.default_rng(4)
-    pairs = np.stack([rng.integers(0, n, 12), rng.integers(0, n, 12)], 1)
-    pairs[0] = [0, 0]
-    pairs[1] = [n - 1, 0]
+    rnd = np.stack([rng.integers(0, n, 12), rng.integers(0, n, 12)], 1)
+    rnd[0] = [0, 0]
+    rnd[1] = [n - 1, 0]
+    pairs = np.concatenate([close_shell_pairs(s.orb, s.xyz, 41, per_class=10), rnd])
     blocks = oracle.coulomb_J_pairs(s.xyz, s.aux, s.orb, d, pairs)
     op = orb.offsets()
+    n_rel_high_l = 0
     for (a, b), blk in zip(pairs, blocks):
         Ta = oracle.solid_transform(int(orb.l[a]))
         Tb = oracle.solid_transform(int(orb.l[b]))
@@ -239,3 +236,7 @@ def test_J_pure_orbital_120_atoms_sampled_pairs():
         got = J[op[a]:op[a + 1], op[b]:op[b + 1]]
         err = np.abs(got - ref)
         assert (err <= bound).all(), (a, b, float(err.max()), float(bound.min()))
+        if min(orb.l[a], orb.l[b]) >= 2:
+            n_rel_high_l += int((np.abs(ref) >= 1e-2).sum())
+    print(f"pure-orbital J: {len(pairs)} pairs, {n_rel_high_l} l>=2 elements >= 1e-2")
+    assert n_rel_high_l >= 500, n_rel_high_l
