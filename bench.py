@@ -179,6 +179,21 @@ def dfj_legs(args, df3c, inputs, torch, dev):
                                                                         ws=wsj), 3)
         mf = system_model_flop(s.aux, s.orb)
         out[f"dfj_model_frac_{name}"] = mf / (out[f"dfj_ms_{name}"] * 1e-3) / PEAK_FP64
+        if name == "plain_8atoms":
+            # asynchronous calls (plan built on the device, no readback) back to
+            # back, and the same call captured in a HIP graph and replayed
+            out["dfj_ms_plain_8atoms_async"] = _time_ms(
+                torch, lambda: df3c.coulomb_J(xyz, aux, orb, d, J=J, ws=wsj, flags=df3c.ASYNC), 50)
+            side = torch.cuda.Stream()
+            side.wait_stream(torch.cuda.current_stream())
+            with torch.cuda.stream(side):
+                df3c.coulomb_J(xyz, aux, orb, d, J=J, ws=wsj, flags=df3c.ASYNC, stream=side)
+            torch.cuda.current_stream().wait_stream(side)
+            graph = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(graph):
+                df3c.coulomb_J(xyz, aux, orb, d, J=J, ws=wsj, flags=df3c.ASYNC)
+            out["dfj_ms_plain_8atoms_graph"] = _time_ms(torch, graph.replay, 100)
+            df3c.check_workspace(wsj, "8-atom DF-J (graph)")
         if name == "water_120atoms":
             # the fitting legs: gamma = (P|ab) D and the metric (P|Q)
             D = torch.as_tensor(inputs.symmetric_density(s.orb.nbf, 2), device=dev)

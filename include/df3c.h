@@ -27,12 +27,21 @@
  * Memory: every pointer marked DEVICE must point to device memory of the
  * current HIP device; HOST pointers to host memory.  The caller owns every
  * buffer, including the workspace; the library never allocates device memory
- * in these entry points (it keeps one read-only Boys table per device, set up
- * by df3c_init).  All device work is enqueued on `stream`.
+ * (its read-only tables, the Boys table included, are part of its code
+ * object).  Calls that read counts or status words back take a small pinned
+ * host slot of their own from a pool (allocated on first use, a few hundred
+ * bytes each).  All device work is enqueued on `stream`.
  *
  * Errors: every function returns DF3C_OK (0) or a negative status; no C++
  * exception crosses the ABI.  After an error the outputs are unspecified.
- * Arguments are validated on the host before any device work is enqueued.
+ * Host-side arguments (pointers, sizes, l_host, flags) are checked before any
+ * device work is enqueued.  Device-side data (atom indices, contraction
+ * degrees, shell indices of triplets, l against l_host) is checked by the
+ * first kernels of a call, which set a status word at the start of the
+ * workspace; every later kernel of the call reads it and does nothing when
+ * it is set.  Without DF3C_ASYNC a call reads the word back at its end (one
+ * synchronisation of `stream`) and returns the status; with DF3C_ASYNC it
+ * returns after enqueueing and df3c_workspace_status reads the word later.
  */
 #ifndef DF3C_H
 #define DF3C_H
@@ -63,9 +72,20 @@ extern "C" {
 #define DF3C_GRAPH 2u            /* batched J: capture the launches in a HIP graph on the
                                     first call and replay it on calls with the same
                                     arguments */
+#define DF3C_ASYNC 4u            /* return right after enqueueing: no synchronisation of
+                                    `stream` and no host memory read after the call
+                                    returns, so the call may be captured into a HIP
+                                    graph; the status is left in the workspace
+                                    (df3c_workspace_status).  Accepted by
+                                    df3c_eval_batch, df3c_coulomb_J(_masked),
+                                    df3c_coulomb_J_grad(_masked), df3c_coulomb_gamma
+                                    and df3c_coulomb_J_batched */
 
 /* A basis: nshell shells.  l_host is a HOST array; the other arrays are DEVICE
- * arrays.  exps/coefs are indexed by prim_off[s] .. prim_off[s] + nprim[s]-1. */
+ * arrays.  exps/coefs are indexed by prim_off[s] .. prim_off[s] + nprim[s]-1.
+ * l_host is required whenever nshell > 0 (the launches are sized from it);
+ * the device plans compare its per-l counts with those of l (DF3C_E_ARG on a
+ * mismatch). */
 typedef struct {
   int32_t nshell;
   const int32_t *l_host;   /* HOST   [nshell] angular momentum */
@@ -79,18 +99,25 @@ typedef struct {
                               orbital: 0 Cartesian; 1 solid-harmonic, accepted by
                               df3c_coulomb_J, df3c_coulomb_J_grad (and their
                               masked forms) and df3c_coulomb_gamma */
-  const int32_t *nprim_host; /* HOST [nshell] copy of nprim, or NULL.  Optional: when
-                              given, the orbital shells of each l are processed in
-                              order of decreasing contraction degree, so that the
-                              shell pairs that share a wavefront have equal primitive
-                              loops; the results do not depend on it beyond rounding
-                              (the orientation of pairs of equally tight shells) */
+  const int32_t *nprim_host; /* HOST [nshell] copy of nprim, or NULL.  Optional, read
+                              by df3c_coulomb_J_batched only: when given, its host plan
+                              orders the orbital shells of each l by decreasing
+                              contraction degree, as the device plans of the
+                              single-molecule calls always do (from nprim), so that
+                              the shell pairs that share a wavefront have equal
+                              primitive loops; results do not depend on the order
+                              beyond rounding */
 } df3c_shells;
 
-/* Load-time set-up for the current device (Boys table upload).  Called
- * implicitly by the entry points; call it explicitly before capturing a HIP
- * graph.  Returns DF3C_E_HIP on failure. */
+/* Set-up for the current device (kernel registry, the device address of the
+ * code object's Boys table, CU count).  Called implicitly by the entry
+ * points; call it explicitly before capturing a HIP graph.  Returns
+ * DF3C_E_HIP on failure. */
 int df3c_init(void);
+
+/* Status of the last call that used workspace ws on `stream` (reads the
+ * status word back: synchronises `stream`).  For calls made with DF3C_ASYNC. */
+int df3c_workspace_status(const void *ws, void *stream);
 
 /* Bytes of workspace df3c_eval_batch needs for ntrip triplets. */
 size_t df3c_eval_batch_workspace(int64_t ntrip);
@@ -106,8 +133,11 @@ size_t df3c_eval_batch_workspace(int64_t ntrip);
  *   out      DEVICE output; block t is npure(l_P) x ncart(l_a) x ncart(l_b)
  *            (ncart(l_P) for a Cartesian aux basis) at out + out_off[t]
  *   ws       DEVICE workspace of at least df3c_eval_batch_workspace(ntrip) bytes
- * Shell indices in trip are checked on the device; the call synchronises
- * `stream` once to plan the per-class launches. */
+ * Shell indices in trip are checked on the device.  Without DF3C_ASYNC the
+ * call synchronises `stream` once to read the class counts, which size one
+ * launch per class present.  With DF3C_ASYNC nothing is read back: every
+ * class the bases allow is launched over the device counts (empty classes
+ * exit at once, about 0.3 ms of launches in all). */
 int df3c_eval_batch(const double *xyz, int32_t natom, const df3c_shells *aux,
                     const df3c_shells *orb,
                     int64_t ntrip, const int32_t *trip, const int64_t *out_off, double *out,
@@ -124,7 +154,11 @@ size_t df3c_coulomb_J_workspace(const df3c_shells *aux, const df3c_shells *orb);
  *   d   DEVICE [naux] fitting coefficients, aux function order
  *   J   DEVICE [nao][nao] output, overwritten, both triangles written
  *   ws  DEVICE workspace of at least df3c_coulomb_J_workspace bytes (with
- *       pure orbital shells it also holds the Cartesian J) */
+ *       pure orbital shells it also holds the Cartesian J)
+ *   flags  0 or DF3C_ASYNC
+ * The shell lists (grouped by l, orbital shells by decreasing contraction
+ * degree within l) and function offsets are built on the device, so with
+ * DF3C_ASYNC the call only enqueues kernels and can be captured. */
 int df3c_coulomb_J(const double *xyz, int32_t natom, const df3c_shells *aux,
                    const df3c_shells *orb, const double *d, double *J, void *ws, size_t ws_bytes,
                    uint32_t flags, void *stream);
@@ -150,8 +184,10 @@ size_t df3c_coulomb_J_masked_workspace(const df3c_shells *aux, const df3c_shells
  * df3c_screen_pairs); the J blocks of the other pairs are zero.  The kept
  * pairs of each (l_a, l_b) class are compacted on the device and run by the
  * same kernels as df3c_coulomb_J, so an all-ones mask gives the same J
- * bitwise.  Other arguments as for df3c_coulomb_J; ws of at least
- * df3c_coulomb_J_masked_workspace bytes. */
+ * bitwise.  Without DF3C_ASYNC the kept counts are read back once (one
+ * synchronisation) and size the launches; with it the launches are sized for
+ * every candidate pair and the kernels read the kept counts.  Other arguments
+ * as for df3c_coulomb_J; ws of at least df3c_coulomb_J_masked_workspace bytes. */
 int df3c_coulomb_J_masked(const double *xyz, int32_t natom, const df3c_shells *aux,
                           const df3c_shells *orb, const double *d, const uint8_t *mask,
                           double *J, void *ws, size_t ws_bytes, uint32_t flags, void *stream);
@@ -185,8 +221,8 @@ size_t df3c_coulomb_J_grad_masked_workspace(const df3c_shells *aux, const df3c_s
 /* The gradient of L = sum_ab G_ab J_ab for the screened J of
  * df3c_coulomb_J_masked: only the orbital shell pairs with
  * mask[a * nshell + b] != 0 (DEVICE, symmetric) contribute.  The kept pairs of
- * every class are compacted on the device (one readback of their counts sizes
- * the launches); the result is bitwise reproducible.  Other arguments as for
+ * every class are compacted on the device (launches sized as for
+ * df3c_coulomb_J_masked); the result is bitwise reproducible.  Other arguments as for
  * df3c_coulomb_J_grad; ws of at least df3c_coulomb_J_grad_masked_workspace
  * bytes. */
 int df3c_coulomb_J_grad_masked(const double *xyz, int32_t natom, const df3c_shells *aux,
@@ -219,10 +255,15 @@ size_t df3c_coulomb_J_batched_workspace(const df3c_shells *aux, const df3c_shell
  *                     sum_{m' < m} nao_m'^2 (both triangles)
  *   tune              HOST [DF3C_NCLASS] schedule parameters, or NULL for defaults
  *   flags             DF3C_SCHED_PER_CLASS or DF3C_SCHED_PERSISTENT, optionally
- *                     | DF3C_GRAPH.  With DF3C_GRAPH the workspace must be left
- *                     untouched between calls with the same arguments (the graph
- *                     reads the plan stored in it), and `stream` must not be the
- *                     legacy default stream (it cannot be captured).
+ *                     | DF3C_GRAPH and | DF3C_ASYNC.  The plan is built on the host
+ *                     and uploaded into ws on every call.  With DF3C_GRAPH the
+ *                     launches are captured on the first call and replayed on later
+ *                     calls with the same arguments (including ws); the cached graph
+ *                     owns its plan, and at most 8 graphs are kept (the oldest is
+ *                     destroyed, after a device synchronisation).  `stream` must not
+ *                     be the legacy default stream (it cannot be captured).  Without
+ *                     DF3C_GRAPH the call synchronises `stream` once (the plan's host
+ *                     memory ends with the call).
  * The persistent schedule runs one launch per class in which workgroups take
  * shell pairs of all molecules from an atomic counter until the queue is empty. */
 int df3c_coulomb_J_batched(const double *xyz, int32_t natom, const df3c_shells *aux,

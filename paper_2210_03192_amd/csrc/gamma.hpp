@@ -36,6 +36,7 @@ struct GamArgs {
   int64_t prange;
   int64_t nrange;
   double *partial;            // [nrange][nsplit][nps][np_out]
+  const int *err;             // device status word: nothing is done when it is non-zero
 };
 
 // pair q of the class -> (sa, sb)
@@ -71,6 +72,7 @@ __global__ void __launch_bounds__(64) k_gam_r(GamArgs g) {
   extern __shared__ double acc[];  // [nps][np_out]
   const int lane = threadIdx.x;
   const int nout = g.pure ? npure(LP) : NCP;
+  if (g.err && *g.err) return;
   for (int64_t item = blockIdx.x; item < g.nrange * g.nsplit; item += gridDim.x) {
     const int64_t r = item / g.nsplit;
     const int sub = int(item - r * g.nsplit);
@@ -325,6 +327,7 @@ __global__ void __launch_bounds__((GamE<LP, LA, LB>::TS))
   double *prims = smem, *SLK = smem + E::SL, *Yc = smem + E::YC, *Wv = smem + E::W;
   double *DT = smem + E::DT, *PW = smem + E::PW, *acc = smem + E::TEAM;  // acc [nps][NCP]
   const int tid = threadIdx.x;
+  if (g.err && *g.err) return;
   for (int64_t item = blockIdx.x; item < g.nrange * g.nsplit; item += gridDim.x) {
     const int64_t r = item / g.nsplit;
     const int sub = int(item - r * g.nsplit);

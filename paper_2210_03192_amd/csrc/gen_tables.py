@@ -674,5 +674,48 @@ def write(outdir):
     _write_if_changed(os.path.join(outdir, "tables_common.hpp"), "".join(s))
 
 
+# Boys table of device.hpp (kept in the library's code object): F_m(i DT) for
+# i = 0..NGRID-1 and m = 0..MTAB-1, row-major, from the series
+#   F_m(T) = exp(-T) sum_k (2T)^k / ((2m+1)(2m+3)...(2m+2k+1))
+# (all terms positive) in 40-digit decimal arithmetic, rounded once to double.
+BOYS_DT = Fraction(1, 8)
+BOYS_TMAX = 36
+BOYS_NGRID = int(BOYS_TMAX / BOYS_DT) + 1
+BOYS_MTAB = 17 + 10  # highest order used + Taylor terms
+
+
+def boys_table():
+    import decimal
+    ctx = decimal.Context(prec=40)
+    out = []
+    for i in range(BOYS_NGRID):
+        T = ctx.divide(decimal.Decimal(i * BOYS_DT.numerator), decimal.Decimal(BOYS_DT.denominator))
+        eT = ctx.exp(-T)
+        two_t = ctx.multiply(2, T)
+        for m in range(BOYS_MTAB):
+            term = ctx.divide(decimal.Decimal(1), decimal.Decimal(2 * m + 1))
+            tot = term
+            k = 1
+            while True:
+                term = ctx.divide(ctx.multiply(term, two_t), decimal.Decimal(2 * m + 2 * k + 1))
+                tot = ctx.add(tot, term)
+                if term < tot * decimal.Decimal("1e-36"):
+                    break
+                k += 1
+            out.append(float(ctx.multiply(eT, tot)))
+    return out
+
+
+def write_boys(outdir):
+    vals = boys_table()
+    lines = [f"// generated by gen_tables.py -- do not edit: F_m(i/8), i < {BOYS_NGRID}, "
+             f"m < {BOYS_MTAB}, row-major\n"]
+    for i in range(0, len(vals), 4):
+        lines.append(", ".join(repr(v) for v in vals[i:i + 4]) + ",\n")
+    _write_if_changed(os.path.join(outdir, "boys_table.inc"), "".join(lines))
+
+
 if __name__ == "__main__":
-    write(sys.argv[1] if len(sys.argv) > 1 else os.path.join(os.path.dirname(__file__), "gen"))
+    out = sys.argv[1] if len(sys.argv) > 1 else os.path.join(os.path.dirname(__file__), "gen")
+    write(out)
+    write_boys(out)

@@ -40,6 +40,7 @@ struct GradArgs {
   double *partial;          // [gridDim.x][natom][3], accumulated
   const int64_t *plist;     // optional: indices q of the class's pairs to run
   const int64_t *pcount;    //   (device count of plist), null for all npair
+  const int *err;           // device status word: nothing is done when it is non-zero
 };
 
 // Work items of the gradient kernels: blocks of tpb consecutive shell pairs
@@ -105,6 +106,7 @@ __global__ void __launch_bounds__(64) k_gradr(GradArgs g) {
   extern __shared__ double smem[];
   double *ACC = smem;  // [natom][3] of this workgroup
   const int lane = threadIdx.x;
+  if (g.err && *g.err) return;
   for (int x = lane; x < 3 * g.natom; x += 64) ACC[x] = 0.0;
   __syncthreads();
 
@@ -458,6 +460,7 @@ __global__ void __launch_bounds__(ENG_TS)
   double *ACC = S + E::TEAM;
   double *prims = S, *DP = S + E::DP, *ZW = S + E::ZW, *Yv = S + E::Y, *Tv = S + E::T;
   double *OM = S + E::OM, *GT = S + E::GT, *PW = S + E::PW;
+  if (g.err && *g.err) return;
   const int tid = threadIdx.x;
   for (int x = tid; x < 3 * g.natom; x += TS) ACC[x] = 0.0;
   team_sync();

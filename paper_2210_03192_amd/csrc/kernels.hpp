@@ -29,6 +29,9 @@ struct StoreArgs {
   const uint32_t *bucket;   // triplet ids of this class; bit 31: a and b swapped
   int64_t count;
   int32_t pure;             // ket solid-harmonic (1) or Cartesian (0, LP <= 1)
+  const int *err;           // device status word: nothing is done when it is non-zero
+  const int *dcount;        // optional device count and bucket offset of the class
+  const int *dstart;        //   (replace count and shift bucket; asynchronous calls)
 };
 
 struct JArgs {
@@ -54,6 +57,7 @@ struct JArgs {
   const double *arec;       // aux-shell records, aligned with psh (see AREC)
   const int64_t *plist;     // optional: indices q of the class's pairs to run
   const int64_t *pcount;    //   (device count of plist), null for all npair
+  const int *err;           // device status word: nothing is done when it is non-zero
 };
 
 // Aux-shell record, one per position of the sorted aux list, built once per
@@ -746,13 +750,16 @@ __global__ void __launch_bounds__(TS > 64 ? TS : 64)
   const int team = threadIdx.x / TS, tid = threadIdx.x % TS;
   double *S = smem + team * Cfg<LP, LA, LB>::STORE_TEAM;
   const int np_out = a.pure ? npure(LP) : ncart(LP);
+  if (a.err && *a.err) return;
+  const int64_t count = a.dcount ? int64_t(*a.dcount) : a.count;
+  const uint32_t *bucket = a.bucket + (a.dstart ? *a.dstart : 0);
   int slot[NQ];
   make_slots<LP, LA, LB, TS>(slot, tid);
 
-  for (int64_t base = int64_t(blockIdx.x) * TPB; base < a.count; base += int64_t(gridDim.x) * TPB) {
+  for (int64_t base = int64_t(blockIdx.x) * TPB; base < count; base += int64_t(gridDim.x) * TPB) {
     const int64_t item = base + team;
-    const bool valid = item < a.count;
-    uint32_t code = valid ? a.bucket[item] : 0u;
+    const bool valid = item < count;
+    uint32_t code = valid ? bucket[item] : 0u;
     const bool swp = (code >> 31) != 0;
     const int64_t t = int64_t(code & 0x7fffffffu);
     int sP = 0, s1 = 0, s2 = 0;
@@ -1303,6 +1310,7 @@ __global__ void __launch_bounds__(TS > 64 ? TS : 64)
   const int sub = REG ? int(threadIdx.x) / tpb : 0;
   const int tid = threadIdx.x % TS;
   double *S = smem + (REG ? 0 : team * JL::TOTAL);
+  if (a.err && *a.err) return;
 
   // all pairs of the class, or the compacted list of kept pairs
   const int64_t nitem = a.plist ? *a.pcount : a.npair;

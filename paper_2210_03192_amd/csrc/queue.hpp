@@ -62,6 +62,7 @@ __global__ void __launch_bounds__(TS > 64 ? TS : 64)
   const int sub = REG ? int(threadIdx.x) / tpb : 0;
   const int tid = threadIdx.x % TS;
   double *S = smem + (REG ? 0 : team * JL::TOTAL);
+  if (q.a.err && *q.a.err) return;
 
   for (;;) {
     if (threadIdx.x == 0) s_base = atomicAdd(q.counter, (unsigned long long)(tpb * q.chunk));

@@ -6,6 +6,7 @@
 #include <array>
 #include <cmath>
 #include <cstring>
+#include <memory>
 #include <mutex>
 #include <unordered_map>
 #include <vector>
@@ -21,7 +22,7 @@ constexpr int MAX_DEV = 64;
 
 struct DevState {
   bool ready = false;
-  double *boys = nullptr;
+  const double *boys = nullptr;  // the code object's Boys table on this device
   int ncu = 0;
 };
 DevState g_dev[MAX_DEV];
@@ -30,25 +31,76 @@ ClassInfo g_cls[NLP][NLA][NLA];
 GradInfo g_grad[NLP][NLG][NLG];
 MetricInfo g_metric[NLP][NLP];
 bool g_cls_ready = false;
-int *g_pinned = nullptr;  // host readback buffer
 
-// Boys table: F_m(i * DT) for m < BOYS_MTAB, by the series
-//   F_m(T) = exp(-T) sum_k (2T)^k / ((2m+1)(2m+3)...(2m+2k+1))
-// summed in long double (all terms positive, T <= 36).
-void boys_table_host(std::vector<double> &tab) {
-  tab.assign(size_t(BOYS_NGRID) * BOYS_MTAB, 0.0);
-  for (int i = 0; i < BOYS_NGRID; ++i) {
-    const long double T = (long double)i * BOYS_DT;
-    for (int m = 0; m < BOYS_MTAB; ++m) {
-      long double term = 1.0L / (2 * m + 1), sum = term;
-      for (int k = 1; k < 4000; ++k) {
-        term *= 2 * T / (2 * m + 2 * k + 1);
-        sum += term;
-        if (term < sum * 1e-24L) break;
+}  // namespace
+
+// Boys table of device.hpp, F_m(i * BOYS_DT) for m < BOYS_MTAB, row-major
+// (generated at build time from the all-positive series in 40-digit decimal
+// arithmetic): part of the library's code object, nothing is allocated.  It
+// is an ordinary (non-const, external) device variable: a const one has
+// internal linkage and, read by no device code of this unit, is left out of
+// the code object, where the runtime then cannot find it by name.
+__device__ double g_boys_table[BOYS_NGRID * BOYS_MTAB] = {
+#include "gen/boys_table.inc"
+};
+
+namespace {
+
+// Host readback slots (pinned, a few ints each): a call that reads counts or
+// status words back takes a slot of its own for the duration of the readback,
+// so concurrent calls on other streams or threads never share one.
+struct PinnedSlots {
+  std::mutex mu;
+  std::vector<int *> free_slots;
+};
+PinnedSlots g_slots;
+constexpr int SLOT_INTS = 256;  // the largest readback: the NCLS class counts
+static_assert(NCLS <= SLOT_INTS, "readback slot smaller than the class counts");
+
+struct Slot {
+  int *p = nullptr;
+  Slot() {
+    {
+      std::lock_guard<std::mutex> lk(g_slots.mu);
+      if (!g_slots.free_slots.empty()) {
+        p = g_slots.free_slots.back();
+        g_slots.free_slots.pop_back();
+        return;
       }
-      tab[size_t(i) * BOYS_MTAB + m] = (double)(expl(-T) * sum);
     }
+    if (hipHostMalloc((void **)&p, sizeof(int) * SLOT_INTS) != hipSuccess) p = nullptr;
   }
+  ~Slot() {
+    if (!p) return;
+    std::lock_guard<std::mutex> lk(g_slots.mu);
+    g_slots.free_slots.push_back(p);
+  }
+  Slot(const Slot &) = delete;
+  Slot &operator=(const Slot &) = delete;
+};
+
+// copy n bytes of device memory back through a slot of its own (synchronises s)
+hipError_t read_back(void *host, const void *dev, size_t n, hipStream_t s) {
+  Slot sl;
+  if (!sl.p || n > sizeof(int) * SLOT_INTS) return hipErrorOutOfMemory;
+  hipError_t e = hipMemcpyAsync(sl.p, dev, n, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e == hipSuccess) std::memcpy(host, sl.p, n);
+  return e;
+}
+
+// status of a call from its device word: without DF3C_ASYNC the call reads
+// it back (one synchronisation at the end); with it, the word stays in the
+// workspace for df3c_workspace_status
+int status_of(int word) {
+  if (word & ~2) return DF3C_E_ARG;  // bad index (1), descriptor (4), plan (8)
+  return word ? DF3C_E_UNSUPPORTED : DF3C_OK;  // l beyond the build (2)
+}
+int finish_call(uint32_t flags, const int *err, hipStream_t s) {
+  if (flags & DF3C_ASYNC) return DF3C_OK;
+  int word = 0;
+  if (read_back(&word, err, sizeof(int), s) != hipSuccess) return DF3C_E_HIP;
+  return status_of(word);
 }
 
 void register_all() {
@@ -85,17 +137,12 @@ int init_device(DevState **out) {
   register_all();
   DevState &s = g_dev[dev];
   if (!s.ready) {
-    std::vector<double> tab;
-    boys_table_host(tab);
-    if (hipMalloc(&s.boys, tab.size() * sizeof(double)) != hipSuccess) return DF3C_E_HIP;
-    if (hipMemcpy(s.boys, tab.data(), tab.size() * sizeof(double), hipMemcpyHostToDevice) !=
-        hipSuccess)
-      return DF3C_E_HIP;
+    void *p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(g_boys_table)) != hipSuccess || !p) return DF3C_E_HIP;
+    s.boys = static_cast<const double *>(p);
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return DF3C_E_HIP;
     s.ncu = prop.multiProcessorCount;
-    if (!g_pinned && hipHostMalloc((void **)&g_pinned, sizeof(int) * (NCLS + 8)) != hipSuccess)
-      return DF3C_E_HIP;
     s.ready = true;
   }
   *out = &s;
@@ -107,8 +154,9 @@ ShellsDev dev_shells(const df3c_shells *b) {
 }
 
 bool shells_ok(const df3c_shells *b) {
-  return b && b->nshell >= 0 && (b->nshell == 0 || (b->l && b->nprim && b->prim_off && b->atom &&
-                                                    b->exps && b->coefs));
+  return b && b->nshell >= 0 &&
+         (b->nshell == 0 || (b->l_host && b->l && b->nprim && b->prim_off && b->atom &&
+                             b->exps && b->coefs));
 }
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
@@ -183,7 +231,8 @@ void check_shells(const df3c_shells *b, int natom, int *err, hipStream_t s) {
 // class of every triplet; hist[NCLS] counts (aggregated per workgroup in LDS),
 // err[0] flags bad input
 __global__ void k_classify(const int32_t *trip, int64_t ntrip, const int32_t *laux, int32_t naux,
-                           const int32_t *lorb, int32_t norb, uint8_t *cls, int *hist, int *err) {
+                           const int32_t *lorb, int32_t norb, int32_t aux_pure, uint8_t *cls,
+                           int *hist, int *err) {
   __shared__ int h[NCLS];
   for (int i = threadIdx.x; i < NCLS; i += blockDim.x) h[i] = 0;
   __syncthreads();
@@ -197,7 +246,7 @@ __global__ void k_classify(const int32_t *trip, int64_t ntrip, const int32_t *la
     }
     const int lp = laux[P], la = lorb[a], lb = lorb[b];
     if (lp < 0 || lp > DF3C_LMAX_AUX || la < 0 || la > DF3C_LMAX_ORB || lb < 0 ||
-        lb > DF3C_LMAX_ORB) {
+        lb > DF3C_LMAX_ORB || (!aux_pure && lp > 1)) {
       atomicOr(err, 2);
       cls[t] = 255;
       continue;
@@ -212,12 +261,14 @@ __global__ void k_classify(const int32_t *trip, int64_t ntrip, const int32_t *la
     if (h[i]) atomicAdd(&hist[i], h[i]);
 }
 
-// exclusive scan of hist into cursor (one thread; NCLS is small)
-__global__ void k_scan(const int *hist, int *cursor) {
+// exclusive scan of hist into cursor (one thread; NCLS is small); start keeps
+// the class starts (the scatter advances cursor to the class ends)
+__global__ void k_scan(const int *hist, int *cursor, int *start) {
   if (threadIdx.x == 0 && blockIdx.x == 0) {
     int s = 0;
     for (int c = 0; c < NCLS; ++c) {
       cursor[c] = s;
+      if (start) start[c] = s;
       s += hist[c];
     }
   }
@@ -241,7 +292,8 @@ __device__ __forceinline__ double shell_tightness(const ShellsDev &b, int s) {
 }
 
 __global__ void k_scatter(const int32_t *trip, int64_t ntrip, const int32_t *lorb, ShellsDev orb,
-                          const uint8_t *cls, int *cursor, uint32_t *bucket) {
+                          const uint8_t *cls, int *cursor, uint32_t *bucket, const int *err) {
+  if (*err) return;
   // per round of blockDim.x triplets: rank inside the workgroup from LDS
   // atomics, one global reservation per class and workgroup
   __shared__ int h[NCLS], base[NCLS];
@@ -340,6 +392,14 @@ int64_t df3c_timing_read(int32_t *kind, int32_t *cls, float *ms, int64_t cap) {
   return rc ? rc : n;
 }
 
+int df3c_workspace_status(const void *ws, void *stream) {
+  if (!ws) return DF3C_E_ARG;
+  int word = 0;
+  if (read_back(&word, ws, sizeof(int), reinterpret_cast<hipStream_t>(stream)) != hipSuccess)
+    return DF3C_E_HIP;
+  return status_of(word);
+}
+
 const char *df3c_status_string(int status) {
   switch (status) {
     case DF3C_OK: return "ok";
@@ -353,7 +413,7 @@ const char *df3c_status_string(int status) {
 
 size_t df3c_eval_batch_workspace(int64_t ntrip) {
   if (ntrip < 0) ntrip = 0;
-  return align256(sizeof(int) * (2 * NCLS + 8)) + align256(size_t(ntrip)) +
+  return align256(sizeof(int) * 8) + align256(sizeof(int) * 3 * NCLS) + align256(size_t(ntrip)) +
          align256(sizeof(uint32_t) * size_t(ntrip));
 }
 
@@ -361,7 +421,7 @@ int df3c_eval_batch(const double *xyz, int32_t natom, const df3c_shells *aux,
                     const df3c_shells *orb, int64_t ntrip, const int32_t *trip,
                     const int64_t *out_off, double *out, void *ws, size_t ws_bytes, uint32_t flags,
                     void *stream) {
-  (void)flags;
+  if (flags & ~DF3C_ASYNC) return DF3C_E_ARG;
   if (ntrip < 0 || ntrip > 0x7fffffff) return DF3C_E_ARG;
   if (ntrip == 0) return DF3C_OK;
   if (!xyz || natom <= 0 || !shells_ok(aux) || !shells_ok(orb) || !trip || !out_off || !out)
@@ -373,36 +433,22 @@ int df3c_eval_batch(const double *xyz, int32_t natom, const df3c_shells *aux,
   if (rc) return rc;
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   char *w = static_cast<char *>(ws);
+  int *err = reinterpret_cast<int *>(w);
+  w += align256(sizeof(int) * 8);
   int *hist = reinterpret_cast<int *>(w);
-  int *cursor = hist + NCLS;
-  int *err = cursor + NCLS;
-  w += align256(sizeof(int) * (2 * NCLS + 8));
+  int *cursor = hist + NCLS, *start = hist + 2 * NCLS;
+  w += align256(sizeof(int) * 3 * NCLS);
   uint8_t *cls = reinterpret_cast<uint8_t *>(w);
   w += align256(size_t(ntrip));
   uint32_t *bucket = reinterpret_cast<uint32_t *>(w);
 
   const int g = int(std::min<int64_t>((ntrip + 255) / 256, 4096));
-  hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(256), 0, s, hist, 2 * NCLS + 8, 0);
+  hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(256), 0, s, err, 8, 0);
+  hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(256), 0, s, hist, 3 * NCLS, 0);
   check_shells(aux, natom, err, s);
   check_shells(orb, natom, err, s);
   hipLaunchKernelGGL(k_classify, dim3(g), dim3(256), 0, s, trip, ntrip, aux->l, aux->nshell,
-                     orb->l, orb->nshell, cls, hist, err);
-  if (hipMemcpyAsync(g_pinned, hist, sizeof(int) * NCLS, hipMemcpyDeviceToHost, s) != hipSuccess ||
-      hipMemcpyAsync(g_pinned + NCLS, err, sizeof(int), hipMemcpyDeviceToHost, s) != hipSuccess ||
-      hipStreamSynchronize(s) != hipSuccess)
-    return DF3C_E_HIP;
-  // nothing that dereferences shell data runs before the descriptors are checked
-  if (g_pinned[NCLS] & 5) return DF3C_E_ARG;
-  if (g_pinned[NCLS] & 2) return DF3C_E_UNSUPPORTED;
-  hipLaunchKernelGGL(k_scan, dim3(1), dim3(64), 0, s, hist, cursor);
-  hipLaunchKernelGGL(k_scatter, dim3(g), dim3(256), 0, s, trip, ntrip, orb->l, dev_shells(orb),
-                     cls, cursor, bucket);
-  int counts[NCLS];
-  std::memcpy(counts, g_pinned, sizeof(counts));
-  if (aux->pure == 0)
-    for (int c = 0; c < NCLS; ++c)
-      if (counts[c] && c / (NLA * NLA) > 1) return DF3C_E_UNSUPPORTED;
-
+                     orb->l, orb->nshell, aux->pure, cls, hist, err);
   StoreArgs a{};
   a.boys = ds->boys;
   a.xyz = xyz;
@@ -412,78 +458,285 @@ int df3c_eval_batch(const double *xyz, int32_t natom, const df3c_shells *aux,
   a.out_off = out_off;
   a.out = out;
   a.pure = aux->pure;
+  a.err = err;
+  if (flags & DF3C_ASYNC) {
+    // no readback: the scatter and every class kernel read the device status
+    // word and the class counts (k_scatter skips a failed batch), so every
+    // class the batch could hold is launched; the empty ones exit at once
+    hipLaunchKernelGGL(k_scan, dim3(1), dim3(64), 0, s, hist, cursor, start);
+    hipLaunchKernelGGL(k_scatter, dim3(g), dim3(256), 0, s, trip, ntrip, orb->l, dev_shells(orb),
+                       cls, cursor, bucket, err);
+    for (int lp = 0; lp <= (aux->pure ? DF3C_LMAX_AUX : 1); ++lp)
+      for (int la = 0; la <= DF3C_LMAX_ORB; ++la)
+        for (int lb = 0; lb <= la; ++lb) {
+          const int c = (lp * NLA + la) * NLA + lb;
+          const ClassInfo &ci = g_cls[lp][la][lb];
+          a.bucket = bucket;
+          a.dcount = hist + c;
+          a.dstart = start + c;
+          a.count = ntrip;
+          const int grid = std::min(grid_for(ntrip, ci.tpw, ds->ncu), 8 * ds->ncu);
+          if (timed(DF3C_KERNEL_STORE, c, s, [&] { return ci.store(a, grid, s); }) != hipSuccess)
+            return DF3C_E_HIP;
+        }
+    return DF3C_OK;
+  }
+  // one readback of the class counts and the status word sizes the launches;
+  // nothing that dereferences shell data runs before the descriptors are checked
+  int rb[NCLS + 8];
+  if (read_back(rb, hist, sizeof(int) * NCLS, s) != hipSuccess ||
+      read_back(rb + NCLS, err, sizeof(int), s) != hipSuccess)
+    return DF3C_E_HIP;
+  if (rb[NCLS] & 5) return DF3C_E_ARG;
+  if (rb[NCLS] & 2) return DF3C_E_UNSUPPORTED;
+  hipLaunchKernelGGL(k_scan, dim3(1), dim3(64), 0, s, hist, cursor, nullptr);
+  hipLaunchKernelGGL(k_scatter, dim3(g), dim3(256), 0, s, trip, ntrip, orb->l, dev_shells(orb),
+                     cls, cursor, bucket, err);
   int64_t off = 0;
   for (int c = 0; c < NCLS; ++c) {
-    if (!counts[c]) continue;
+    if (!rb[c]) continue;
     const int lp = c / (NLA * NLA), la = (c / NLA) % NLA, lb = c % NLA;
     const ClassInfo &ci = g_cls[lp][la][lb];
     a.bucket = bucket + off;
-    a.count = counts[c];
+    a.count = rb[c];
     if (timed(DF3C_KERNEL_STORE, c, s,
-              [&] { return ci.store(a, grid_for(counts[c], ci.tpw, ds->ncu), s); }) != hipSuccess)
+              [&] { return ci.store(a, grid_for(rb[c], ci.tpw, ds->ncu), s); }) != hipSuccess)
       return DF3C_E_HIP;
-    off += counts[c];
+    off += rb[c];
   }
   return DF3C_OK;
 }
 
 // ------------------------------------------------------------------- DF-J
 namespace {
-struct JPlan {
-  std::vector<int32_t> orb_sorted, aux_sorted;     // shells grouped by l
-  int32_t orb_start[DF3C_LMAX_ORB + 2] = {}, aux_start[DF3C_LMAX_AUX + 2] = {};
-  std::vector<int64_t> ao_off, aux_off;
-  int64_t nao = 0, naux = 0;
+// ------------------------------------------------------------ device plans
+// The shell lists of a single-molecule call are built on the device from the
+// shells' own l and nprim (no host-built plan is uploaded, so the calls that
+// use them are asynchronous and can be captured in a HIP graph).  One
+// workgroup of PLAN_TPB threads per basis:
+//   sorted[]  shells grouped by key, ascending, stable in shell order; the
+//             orbital key is l * 64 + 63 - min(nprim, 63) (decreasing
+//             contraction degree within l: the shell pairs that share a
+//             wavefront then run equal primitive loops), the aux key is l;
+//   off[]     function offset of every shell in shell order (off[n] = total):
+//             ncart(l) functions per orbital shell, npure or ncart per aux
+//             shell;
+//   pmap[]    optional (solid-harmonic orbital shells): pmap[po[s] + m] =
+//             s << 4 | m over the 2l+1 functions of each shell, po the pure
+//             offsets;
+//   cmap[]    optional: cmap[off[s] + i] = s << 4 | i over the Cartesian
+//             components, with the pure offsets in poff[];
+// and the number of shells of each l is compared with the host's count (the
+// launches are sized from l_host): a mismatch or an l beyond the build sets
+// bit 8 of *err.
+constexpr int PLAN_TPB = 1024;
+constexpr int PLAN_WAVES = PLAN_TPB / 64;
+constexpr int PLAN_NKEY = (DF3C_LMAX_AUX + 1) * 64;
+struct PlanCounts {
+  int32_t n[DF3C_LMAX_AUX + 1];
 };
 
-// Orbital shells of one l in order of decreasing contraction degree (stable):
-// the kernels give one lane or one team to a shell pair and loop over its
-// primitive pairs, so pairs that share a wavefront should have equal Ka Kb.
-void sort_by_contraction(const df3c_shells *orb, int32_t *first, int32_t *last) {
-  if (!orb->nprim_host) return;
-  std::stable_sort(first, last, [orb](int32_t x, int32_t y) {
-    return orb->nprim_host[x] > orb->nprim_host[y];
-  });
+__device__ __forceinline__ int plan_key(int l, int k, bool orb) {
+  return orb ? l * 64 + 63 - min(max(k, 1), 63) : l * 64;
 }
 
-int make_plan(const df3c_shells *aux, const df3c_shells *orb, JPlan &p) {
-  if (!aux->l_host || !orb->l_host) return DF3C_E_ARG;
-  std::vector<int32_t> cnt_o(DF3C_LMAX_ORB + 1, 0), cnt_a(DF3C_LMAX_AUX + 1, 0);
-  p.ao_off.assign(orb->nshell + 1, 0);
-  p.aux_off.assign(aux->nshell + 1, 0);
+__global__ void __launch_bounds__(PLAN_TPB)
+    k_plan_shells(const int32_t *l, const int32_t *nprim, int32_t n, int32_t lmax, int32_t orb,
+                  int32_t pure, PlanCounts hc, int32_t *sorted, int64_t *off, int32_t *pmap,
+                  int32_t *cmap, int64_t *poff, int *err) {
+  __shared__ int hist[PLAN_WAVES][PLAN_NKEY];  // per-wave counts, then running bases
+  __shared__ int kstart[PLAN_NKEY];
+  __shared__ int64_t wsum[PLAN_WAVES][2];
+  __shared__ int bad;
+  const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
+  for (int i = tid; i < PLAN_WAVES * PLAN_NKEY; i += PLAN_TPB) (&hist[0][0])[i] = 0;
+  if (tid == 0) bad = 0;
+  __syncthreads();
+  // each wave owns a contiguous slice of the shells
+  const int per = (n + PLAN_WAVES - 1) / PLAN_WAVES;
+  const int s0 = min(n, w * per), s1 = min(n, s0 + per);
+  auto keyof = [&](int s) {
+    const int ls = l[s];
+    if (ls < 0 || ls > lmax) {
+      bad = 1;
+      return 0;
+    }
+    return plan_key(ls, orb ? nprim[s] : 1, orb != 0);
+  };
+  for (int s = s0 + lane; s < s1; s += 64) atomicAdd(&hist[w][keyof(s)], 1);
+  __syncthreads();
+  // key totals -> exclusive key starts (log-step scan); per-wave bases
+  int tot = 0;
+  if (tid < PLAN_NKEY) {
+    for (int v = 0; v < PLAN_WAVES; ++v) {
+      const int c = hist[v][tid];
+      hist[v][tid] = tot;
+      tot += c;
+    }
+    kstart[tid] = tot;
+  }
+  __syncthreads();
+  for (int o = 1; o < PLAN_NKEY; o <<= 1) {
+    const int v = (tid < PLAN_NKEY && tid >= o) ? kstart[tid - o] : 0;
+    __syncthreads();
+    if (tid < PLAN_NKEY) kstart[tid] += v;
+    __syncthreads();
+  }
+  if (tid < PLAN_NKEY) kstart[tid] -= tot;  // inclusive -> exclusive
+  __syncthreads();
+  // shells per l against the host's counts
+  if (tid <= DF3C_LMAX_AUX) {
+    const int hi = tid == DF3C_LMAX_AUX ? 0 : kstart[(tid + 1) * 64];
+    const int cnt = (tid == DF3C_LMAX_AUX ? n : hi) - kstart[tid * 64];
+    const int want = tid <= lmax ? hc.n[tid] : 0;
+    if (cnt != want) bad = 1;
+  }
+  // stable scatter: every wave walks its slice in order, 64 shells at a time;
+  // the lanes of one key are ranked by a ballot
+  for (int c0 = s0; c0 < s1; c0 += 64) {
+    const int s = c0 + lane;
+    const bool act = s < s1;
+    const int k = act ? keyof(s) : -1;
+    unsigned long long rem = __ballot(act);
+    while (rem) {
+      const int lead = __ffsll(rem) - 1;
+      const int lk = __shfl(k, lead);
+      const unsigned long long m = __ballot(act && k == lk);
+      const int base = kstart[lk] + hist[w][lk];
+      if (act && k == lk) sorted[base + __popcll(m & ((1ull << lane) - 1))] = s;
+      if (lane == lead) hist[w][lk] += __popcll(m);
+      rem &= ~m;
+    }
+  }
+  // offsets in shell order: block-wide scans of the function counts (ncart or
+  // npure, and npure for the pure maps), tile by tile
+  int64_t carry0 = 0, carry1 = 0;
+  if (tid == 0) off[0] = 0;
+  if (tid == 0 && poff) poff[0] = 0;
+  for (int t0 = 0; t0 < n; t0 += PLAN_TPB) {
+    const int s = t0 + tid;
+    int ls = s < n ? l[s] : 0;
+    ls = min(max(ls, 0), lmax);
+    const int nc = (ls + 1) * (ls + 2) / 2, np = 2 * ls + 1;
+    int64_t v0 = s < n ? ((orb || !pure) ? nc : np) : 0, v1 = s < n ? np : 0;
+    // inclusive scan within the wave
+    for (int o = 1; o < 64; o <<= 1) {
+      const int64_t a0 = __shfl_up(v0, o), a1 = __shfl_up(v1, o);
+      if (lane >= o) {
+        v0 += a0;
+        v1 += a1;
+      }
+    }
+    if (lane == 63) {
+      wsum[w][0] = v0;
+      wsum[w][1] = v1;
+    }
+    __syncthreads();
+    int64_t b0 = carry0, b1 = carry1;
+    for (int v = 0; v < w; ++v) {
+      b0 += wsum[v][0];
+      b1 += wsum[v][1];
+    }
+    if (s < n) {
+      off[s + 1] = b0 + v0;
+      if (poff) poff[s + 1] = b1 + v1;
+      const int64_t f0 = b0 + v0 - ((orb || !pure) ? nc : np), f1 = b1 + v1 - np;
+      if (pmap)
+        for (int m = 0; m < np; ++m) pmap[f1 + m] = s << 4 | m;
+      if (cmap)
+        for (int i = 0; i < nc; ++i) cmap[f0 + i] = s << 4 | i;
+    }
+    for (int v = 0; v < PLAN_WAVES; ++v) {
+      carry0 += wsum[v][0];
+      carry1 += wsum[v][1];
+    }
+    __syncthreads();
+  }
+  if (tid == 0 && bad) atomicOr(err, 8);
+}
+
+extern "C++" {
+// Host half of a single-molecule plan, from l_host: the shells of every l
+// (the class ranges of the sorted lists the device plan fills), their counts
+// for the device's check, and the function totals.
+struct HostPlan {
+  int32_t orb_start[DF3C_LMAX_ORB + 2] = {}, aux_start[DF3C_LMAX_AUX + 2] = {};
+  PlanCounts co{}, ca{};
+  int64_t nao = 0, naux = 0, npure = 0;  // Cartesian AOs, aux functions, pure AOs
+};
+
+int host_plan(const df3c_shells *aux, const df3c_shells *orb, HostPlan &p) {
+  if ((orb->nshell && !orb->l_host) || (aux->nshell && !aux->l_host)) return DF3C_E_ARG;
   for (int s = 0; s < orb->nshell; ++s) {
     const int l = orb->l_host[s];
     if (l < 0 || l > DF3C_LMAX_ORB) return DF3C_E_UNSUPPORTED;
-    cnt_o[l]++;
-    p.ao_off[s + 1] = p.ao_off[s] + (l + 1) * (l + 2) / 2;
+    p.co.n[l]++;
+    p.nao += (l + 1) * (l + 2) / 2;
+    p.npure += 2 * l + 1;
   }
   for (int s = 0; s < aux->nshell; ++s) {
     const int l = aux->l_host[s];
     if (l < 0 || l > DF3C_LMAX_AUX) return DF3C_E_UNSUPPORTED;
     if (!aux->pure && l > 1) return DF3C_E_UNSUPPORTED;
-    cnt_a[l]++;
-    p.aux_off[s + 1] = p.aux_off[s] + (aux->pure ? 2 * l + 1 : (l + 1) * (l + 2) / 2);
+    p.ca.n[l]++;
+    p.naux += aux->pure ? 2 * l + 1 : (l + 1) * (l + 2) / 2;
   }
-  p.nao = p.ao_off[orb->nshell];
-  p.naux = p.aux_off[aux->nshell];
-  for (int l = 0; l <= DF3C_LMAX_ORB; ++l) p.orb_start[l + 1] = p.orb_start[l] + cnt_o[l];
-  for (int l = 0; l <= DF3C_LMAX_AUX; ++l) p.aux_start[l + 1] = p.aux_start[l] + cnt_a[l];
-  p.orb_sorted.resize(orb->nshell);
-  p.aux_sorted.resize(aux->nshell);
-  std::vector<int32_t> fo(p.orb_start, p.orb_start + DF3C_LMAX_ORB + 1),
-      fa(p.aux_start, p.aux_start + DF3C_LMAX_AUX + 1);
-  for (int s = 0; s < orb->nshell; ++s) p.orb_sorted[fo[orb->l_host[s]]++] = s;
-  for (int s = 0; s < aux->nshell; ++s) p.aux_sorted[fa[aux->l_host[s]]++] = s;
-  for (int l = 0; l <= DF3C_LMAX_ORB; ++l)
-    sort_by_contraction(orb, p.orb_sorted.data() + p.orb_start[l], p.orb_sorted.data() + p.orb_start[l + 1]);
+  for (int l = 0; l <= DF3C_LMAX_ORB; ++l) p.orb_start[l + 1] = p.orb_start[l] + p.co.n[l];
+  for (int l = 0; l <= DF3C_LMAX_AUX; ++l) p.aux_start[l + 1] = p.aux_start[l] + p.ca.n[l];
   return DF3C_OK;
 }
+
+// Device half, at the start of the workspace: status word, sorted shell
+// lists, function offsets, aux-shell records.
+struct DevPlan {
+  int *err = nullptr;
+  int32_t *orb_sorted = nullptr, *aux_sorted = nullptr;
+  int64_t *ao_off = nullptr, *aux_off = nullptr;
+  double *arec = nullptr;
+};
 
 size_t jplan_bytes(int64_t norb, int64_t naux) {
   return align256(sizeof(int) * 8) + align256(sizeof(int32_t) * norb) + align256(sizeof(int32_t) * naux) +
          align256(sizeof(int64_t) * (norb + 1)) + align256(sizeof(int64_t) * (naux + 1)) +
          align256(sizeof(double) * AREC * naux);
 }
+
+DevPlan carve_plan(void *ws, int64_t norb, int64_t naux) {
+  DevPlan d;
+  char *w = static_cast<char *>(ws);
+  d.err = reinterpret_cast<int *>(w);
+  w += align256(sizeof(int) * 8);
+  d.orb_sorted = reinterpret_cast<int32_t *>(w);
+  w += align256(sizeof(int32_t) * norb);
+  d.aux_sorted = reinterpret_cast<int32_t *>(w);
+  w += align256(sizeof(int32_t) * naux);
+  d.ao_off = reinterpret_cast<int64_t *>(w);
+  w += align256(sizeof(int64_t) * (norb + 1));
+  d.aux_off = reinterpret_cast<int64_t *>(w);
+  w += align256(sizeof(int64_t) * (naux + 1));
+  d.arec = reinterpret_cast<double *>(w);
+  return d;
+}
+
+// zero the status word, check both bases' descriptors, build both shell
+// lists (pmap / cmap + poff: optional maps of a solid-harmonic orbital basis)
+hipError_t launch_plan(const DevPlan &d, const HostPlan &hp, const df3c_shells *aux,
+                       const df3c_shells *orb, int natom, int32_t *pmap, int32_t *cmap,
+                       int64_t *poff, hipStream_t s) {
+  hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, s, d.err, 8, 0);
+  check_shells(aux, natom, d.err, s);
+  check_shells(orb, natom, d.err, s);
+  hipLaunchKernelGGL(k_plan_shells, dim3(1), dim3(PLAN_TPB), 0, s, orb->l, orb->nprim,
+                     orb->nshell, DF3C_LMAX_ORB, 1, 0, hp.co, d.orb_sorted, d.ao_off, pmap, cmap,
+                     poff, d.err);
+  hipLaunchKernelGGL(k_plan_shells, dim3(1), dim3(PLAN_TPB), 0, s, aux->l, aux->nprim,
+                     aux->nshell, DF3C_LMAX_AUX, 0, aux->pure, hp.ca, d.aux_sorted, d.aux_off,
+                     nullptr, nullptr, nullptr, d.err);
+  return hipGetLastError();
+}
+
+}  // extern "C++"
+
 
 extern "C++" {
 // d' = T^T d_P of one aux shell of l = LP into its record
@@ -504,7 +757,8 @@ __device__ void aux_dq(const double *dP, int pure, double *dq) {
 // aux-shell records of the sorted aux list (d may be null: no d')
 __global__ void k_aux_records(const int32_t *sorted, int64_t n, const int32_t *lsh, ShellsDev aux,
                               const double *xyz, const int64_t *aux_off, const double *d,
-                              int32_t pure, double *rec) {
+                              int32_t pure, double *rec, const int *err) {
+  if (err && *err) return;
   for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
        i += int64_t(gridDim.x) * blockDim.x) {
     const int s = sorted[i];
@@ -533,11 +787,11 @@ __global__ void k_aux_records(const int32_t *sorted, int64_t n, const int32_t *l
 
 hipError_t launch_aux_records(const int32_t *sorted, int64_t n, const df3c_shells *aux,
                               const double *xyz, const int64_t *aux_off, const double *d,
-                              double *rec, hipStream_t s) {
+                              double *rec, hipStream_t s, const int *err = nullptr) {
   if (n <= 0) return hipSuccess;
   const int grid = int(std::min<int64_t>((n + 255) / 256, 1024));
   hipLaunchKernelGGL(k_aux_records, dim3(grid), dim3(256), 0, s, sorted, n, aux->l,
-                     dev_shells(aux), xyz, aux_off, d, aux->pure, rec);
+                     dev_shells(aux), xyz, aux_off, d, aux->pure, rec, err);
   return hipGetLastError();
 }
 }  // namespace
@@ -548,7 +802,7 @@ size_t pure_bytes(const df3c_shells *orb) {
   if (!orb->pure) return 0;
   int64_t nc = 0, np = 0;
   for (int s = 0; s < orb->nshell; ++s) {
-    const int l = orb->l_host[s];
+    const int l = std::min(std::max(orb->l_host[s], 0), DF3C_LMAX_ORB);
     nc += (l + 1) * (l + 2) / 2;
     np += 2 * l + 1;
   }
@@ -559,15 +813,18 @@ size_t pure_bytes(const df3c_shells *orb) {
 size_t pullback_bytes(const df3c_shells *orb) {
   if (!orb->pure) return 0;
   int64_t nc = 0;
-  for (int s = 0; s < orb->nshell; ++s) nc += (orb->l_host[s] + 1) * (orb->l_host[s] + 2) / 2;
+  for (int s = 0; s < orb->nshell; ++s) {
+    const int l = std::min(std::max(orb->l_host[s], 0), DF3C_LMAX_ORB);
+    nc += (l + 1) * (l + 2) / 2;
+  }
   return align256(sizeof(int32_t) * nc) + align256(sizeof(int64_t) * (orb->nshell + 1)) +
          align256(sizeof(double) * nc * nc);
 }
 }  // namespace
 
 size_t df3c_coulomb_J_workspace(const df3c_shells *aux, const df3c_shells *orb) {
-  if (!aux || !orb) return 0;
-  return jplan_bytes(orb->nshell, aux->nshell) + (orb->l_host ? pure_bytes(orb) : 0);
+  if (!shells_ok(aux) || !shells_ok(orb)) return 0;
+  return jplan_bytes(orb->nshell, aux->nshell) + pure_bytes(orb);
 }
 
 namespace {
@@ -612,8 +869,9 @@ struct CompactJobs {
   CompactJob j[NCOMPACT];
 };
 __global__ void __launch_bounds__(COMPACT_TPB)
-    k_pair_compact(CompactJobs jobs, const uint8_t *mask, int32_t nshell) {
+    k_pair_compact(CompactJobs jobs, const uint8_t *mask, int32_t nshell, const int *err) {
   __shared__ int64_t cnt[COMPACT_TPB];
+  if (*err) return;
   const CompactJob &job = jobs.j[blockIdx.x];
   const int32_t *ash = job.ash, *bsh = job.bsh;
   const int32_t nb = job.nb, same = job.same;
@@ -704,7 +962,9 @@ __device__ inline const double *solid_dense_l(int l) {
 // the pure rows r, c (one thread per element of J, rows of J contiguous;
 // an element above the diagonal is evaluated as its mirror)
 __global__ void k_bra_pure(const double *Jc, int64_t nc, const int32_t *pmap,
-                           const int64_t *cao, const int32_t *lsh, double *J, int64_t np) {
+                           const int64_t *cao, const int32_t *lsh, double *J, int64_t np,
+                           const int *err) {
+  if (*err) return;
   const int64_t total = np * np;
   for (int64_t x = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; x < total;
        x += int64_t(gridDim.x) * blockDim.x) {
@@ -737,7 +997,9 @@ __global__ void k_bra_pure(const double *Jc, int64_t nc, const int32_t *pmap,
 // back once and the Cartesian gradient engines run unchanged.
 //   Gc[r][c] = sum_mn T_la[m][i_r] T_lb[n][j_c] G[poff[sa] + m][poff[sb] + n]
 __global__ void k_bra_cart(const double *G, int64_t np, const int32_t *cmap,
-                           const int64_t *poff, const int32_t *lsh, double *Gc, int64_t nc) {
+                           const int64_t *poff, const int32_t *lsh, double *Gc, int64_t nc,
+                           const int *err) {
+  if (*err) return;
   const int64_t total = nc * nc;
   for (int64_t x = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; x < total;
        x += int64_t(gridDim.x) * blockDim.x) {
@@ -759,135 +1021,91 @@ __global__ void k_bra_cart(const double *G, int64_t np, const int32_t *cmap,
   }
 }
 
-// Gc = T_a^T G T_b per block into q (pullback_bytes(orb) bytes of workspace);
-// *out points at Gc on success.  Synchronises s (host vectors).
-int pull_back_cart(const df3c_shells *orb, const double *G, char *q, hipStream_t s,
-                   const double **out) {
-  if (orb->nshell >= (1 << 27)) return DF3C_E_UNSUPPORTED;  // rows packed as shell << 4 | c
-  std::vector<int32_t> cm;
-  std::vector<int64_t> po(orb->nshell + 1, 0);
-  for (int sh = 0; sh < orb->nshell; ++sh) {
-    const int l = orb->l_host[sh];
-    for (int c = 0; c < (l + 1) * (l + 2) / 2; ++c) cm.push_back(sh << 4 | c);
-    po[sh + 1] = po[sh] + 2 * l + 1;
-  }
-  const int64_t nc = int64_t(cm.size()), np = po[orb->nshell];
-  int32_t *cmap = reinterpret_cast<int32_t *>(q);
+extern "C++" {
+// Pull-back workspace (pullback_bytes(orb) bytes at q): the Cartesian-row
+// map and pure shell offsets, which the device plan fills, and Gc.
+struct PullBack {
+  int32_t *cmap = nullptr;
+  int64_t *poff = nullptr;
+  double *Gc = nullptr;
+};
+PullBack carve_pullback(const df3c_shells *orb, char *q, int64_t nc) {
+  PullBack p;
+  p.cmap = reinterpret_cast<int32_t *>(q);
   q += align256(sizeof(int32_t) * nc);
-  int64_t *poff = reinterpret_cast<int64_t *>(q);
+  p.poff = reinterpret_cast<int64_t *>(q);
   q += align256(sizeof(int64_t) * (orb->nshell + 1));
-  double *Gc = reinterpret_cast<double *>(q);
-  *out = Gc;
-  if (!nc) return DF3C_OK;
-  if (hipMemcpyAsync(cmap, cm.data(), sizeof(int32_t) * nc, hipMemcpyHostToDevice, s) !=
-          hipSuccess ||
-      hipMemcpyAsync(poff, po.data(), sizeof(int64_t) * (orb->nshell + 1), hipMemcpyHostToDevice,
-                     s) != hipSuccess) {
-    (void)hipStreamSynchronize(s);  // a copy already queued still reads cm
-    return DF3C_E_HIP;
-  }
-  hipLaunchKernelGGL(k_bra_cart, dim3(int(std::min<int64_t>((nc * nc + 255) / 256, 8192))),
-                     dim3(256), 0, s, G, np, cmap, poff, orb->l, Gc, nc);
-  if (hipGetLastError() != hipSuccess) return DF3C_E_HIP;
-  return hipStreamSynchronize(s) == hipSuccess ? DF3C_OK : DF3C_E_HIP;
+  p.Gc = reinterpret_cast<double *>(q);
+  return p;
 }
+// Gc = T_a^T G T_b per block (asynchronous)
+hipError_t pull_back_cart(const df3c_shells *orb, const double *G, const PullBack &pb, int64_t nc,
+                          int64_t np, const int *err, hipStream_t s) {
+  if (!nc) return hipSuccess;
+  hipLaunchKernelGGL(k_bra_cart, dim3(int(std::min<int64_t>((nc * nc + 255) / 256, 8192))),
+                     dim3(256), 0, s, G, np, pb.cmap, pb.poff, orb->l, pb.Gc, nc, err);
+  return hipGetLastError();
+}
+}  // extern "C++"
 
-// DF-J over all pairs (mask null) or over the pairs the mask keeps
+// DF-J over all pairs (mask null) or over the pairs the mask keeps.  Every
+// step is enqueued on s: the plan is built on the device, the status word
+// guards every kernel that reads shell data, and no host memory is read
+// after the call returns (asynchronous, capturable).  `scratch` is the
+// workspace past the plan (masked pair lists, then the pure-orbital maps and
+// the Cartesian J).
 int coulomb_J_run(const double *xyz, int32_t natom, const df3c_shells *aux,
                   const df3c_shells *orb, const double *d, const uint8_t *mask, double *J,
-                  void *ws, size_t core, hipStream_t s) {
+                  void *ws, uint32_t flags, hipStream_t s) {
   DevState *ds = nullptr;
   int rc = init_device(&ds);
   if (rc) return rc;
-  JPlan p;
-  rc = make_plan(aux, orb, p);
-  if (rc) return rc;
-  char *w = static_cast<char *>(ws);
-  int *err = reinterpret_cast<int *>(w);
-  w += align256(sizeof(int) * 8);
-  int32_t *orb_sorted = reinterpret_cast<int32_t *>(w);
-  w += align256(sizeof(int32_t) * orb->nshell);
-  int32_t *aux_sorted = reinterpret_cast<int32_t *>(w);
-  w += align256(sizeof(int32_t) * aux->nshell);
-  int64_t *ao_off = reinterpret_cast<int64_t *>(w);
-  w += align256(sizeof(int64_t) * (orb->nshell + 1));
-  int64_t *aux_off = reinterpret_cast<int64_t *>(w);
-  w += align256(sizeof(int64_t) * (aux->nshell + 1));
-  double *arec = reinterpret_cast<double *>(w);
-  w += align256(sizeof(double) * AREC * aux->nshell);
-  // masked only (its workspace is larger): kept-pair counters and lists of
-  // the (l_a, l_b) classes
+  HostPlan p;
+  if ((rc = host_plan(aux, orb, p))) return rc;
+  if (orb->pure && orb->nshell >= (1 << 27)) return DF3C_E_UNSUPPORTED;  // rows packed shell << 4
+  const DevPlan dp = carve_plan(ws, orb->nshell, aux->nshell);
+  char *w = static_cast<char *>(ws) + jplan_bytes(orb->nshell, aux->nshell);
+  // masked only: kept-pair counters and lists of the (l_a, l_b) classes
   unsigned long long *pcount = nullptr;
   int64_t *plist = nullptr;
   if (mask) {
     pcount = reinterpret_cast<unsigned long long *>(w);
     plist = reinterpret_cast<int64_t *>(w + align256(sizeof(unsigned long long) * NLA * NLA));
+    w += align256(sizeof(unsigned long long) * NLA * NLA) +
+         align256(sizeof(int64_t) * size_t(total_class_pairs(orb)));
   }
-  if (hipMemcpyAsync(orb_sorted, p.orb_sorted.data(), sizeof(int32_t) * orb->nshell,
-                     hipMemcpyHostToDevice, s) != hipSuccess ||
-      hipMemcpyAsync(aux_sorted, p.aux_sorted.data(), sizeof(int32_t) * aux->nshell,
-                     hipMemcpyHostToDevice, s) != hipSuccess ||
-      hipMemcpyAsync(ao_off, p.ao_off.data(), sizeof(int64_t) * (orb->nshell + 1),
-                     hipMemcpyHostToDevice, s) != hipSuccess ||
-      hipMemcpyAsync(aux_off, p.aux_off.data(), sizeof(int64_t) * (aux->nshell + 1),
-                     hipMemcpyHostToDevice, s) != hipSuccess) {
-    (void)hipStreamSynchronize(s);  // copies already queued still read the plan
-    return DF3C_E_HIP;
-  }
-  hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, s, err, 1, 0);
-  check_shells(aux, natom, err, s);
-  check_shells(orb, natom, err, s);
-  if (hipMemcpyAsync(g_pinned, err, sizeof(int), hipMemcpyDeviceToHost, s) != hipSuccess)
-    return DF3C_E_HIP;
-  // the host vectors must outlive the asynchronous copies
-  if (hipStreamSynchronize(s) != hipSuccess) return DF3C_E_HIP;
-  if (g_pinned[0]) return DF3C_E_ARG;
   // pure orbital shells: the engines fill the Cartesian J in the workspace
   double *Jout = J;
   int32_t *pmap = nullptr;
-  int64_t npure = 0;
   if (orb->pure) {
-    if (orb->nshell >= (1 << 27)) return DF3C_E_UNSUPPORTED;  // rows packed as shell << 4 | m
-    std::vector<int32_t> pm;
-    for (int sh = 0; sh < orb->nshell; ++sh)
-      for (int m = 0; m < 2 * orb->l_host[sh] + 1; ++m) pm.push_back(sh << 4 | m);
-    npure = int64_t(pm.size());
-    pmap = reinterpret_cast<int32_t *>(static_cast<char *>(ws) + core);
-    J = reinterpret_cast<double *>(static_cast<char *>(ws) + core +
-                                   align256(sizeof(int32_t) * npure));
-    if (npure && (hipMemcpyAsync(pmap, pm.data(), sizeof(int32_t) * npure,
-                                 hipMemcpyHostToDevice, s) != hipSuccess ||
-                  hipStreamSynchronize(s) != hipSuccess))
-      return DF3C_E_HIP;
+    pmap = reinterpret_cast<int32_t *>(w);
+    J = reinterpret_cast<double *>(w + align256(sizeof(int32_t) * p.npure));
   }
-  auto finish = [&]() -> int {
-    if (!orb->pure || !npure) return DF3C_OK;
-    const int64_t n2 = npure * npure;
-    hipLaunchKernelGGL(k_bra_pure, dim3(int(std::min<int64_t>((n2 + 255) / 256, 8192))),
-                       dim3(256), 0, s, J, p.nao, pmap, ao_off, orb->l, Jout, npure);
-    return hipGetLastError() == hipSuccess ? DF3C_OK : DF3C_E_HIP;
-  };
+  if (launch_plan(dp, p, aux, orb, natom, pmap, nullptr, nullptr, s) != hipSuccess)
+    return DF3C_E_HIP;
   const int64_t nJ = p.nao * p.nao;
   hipLaunchKernelGGL(k_zero_f64, dim3(int(std::min<int64_t>((nJ + 255) / 256, 4096))), dim3(256),
                      0, s, J, nJ);
-  if (launch_aux_records(aux_sorted, aux->nshell, aux, xyz, aux_off, d, arec, s) != hipSuccess)
+  if (launch_aux_records(dp.aux_sorted, aux->nshell, aux, xyz, dp.aux_off, d, dp.arec, s,
+                         dp.err) != hipSuccess)
     return DF3C_E_HIP;
   JArgs a{};
   a.boys = ds->boys;
   a.xyz = xyz;
   a.aux = dev_shells(aux);
   a.orb = dev_shells(orb);
-  a.ao_off = ao_off;
-  a.aux_off = aux_off;
+  a.ao_off = dp.ao_off;
+  a.aux_off = dp.aux_off;
   a.d = d;
   a.J = J;
   a.nao = p.nao;
   a.pure = aux->pure;
+  a.err = dp.err;
   auto launch = [&](int lp, int la, int lb) -> int {
     const int np = p.aux_start[lp + 1] - p.aux_start[lp];
     if (!np) return DF3C_OK;
-    a.psh = aux_sorted + p.aux_start[lp];
-    a.arec = arec + int64_t(p.aux_start[lp]) * AREC;
+    a.psh = dp.aux_sorted + p.aux_start[lp];
+    a.arec = dp.arec + int64_t(p.aux_start[lp]) * AREC;
     a.np = np;
     const ClassInfo &ci = g_cls[lp][la][lb];
     const int c = (lp * NLA + la) * NLA + lb;
@@ -901,8 +1119,8 @@ int coulomb_J_run(const double *xyz, int32_t natom, const df3c_shells *aux,
   auto set_class = [&](int la, int lb) {
     const int na = p.orb_start[la + 1] - p.orb_start[la];
     const int nb = p.orb_start[lb + 1] - p.orb_start[lb];
-    a.ash = orb_sorted + p.orb_start[la];
-    a.bsh = orb_sorted + p.orb_start[lb];
+    a.ash = dp.orb_sorted + p.orb_start[la];
+    a.bsh = dp.orb_sorted + p.orb_start[lb];
     a.na = na;
     a.nb = nb;
     a.same = (la == lb);
@@ -914,14 +1132,12 @@ int coulomb_J_run(const double *xyz, int32_t natom, const df3c_shells *aux,
       for (int la = 0; la <= DF3C_LMAX_ORB; ++la)
         for (int lb = 0; lb <= la; ++lb)
           if (set_class(la, lb) && (rc = launch(lp, la, lb))) return rc;
-    return finish();
-  }
-  // masked: the kept pairs of every (l_a, l_b) class are compacted into the
-  // class's list, the counts read back once (they size the launches), then
-  // every l_P class runs over the list (each J element still sums l_P in
-  // ascending order)
-  int64_t loff[NLA][NLA] = {};
-  {
+  } else {
+    // masked: the kept pairs of every (l_a, l_b) class are compacted into the
+    // class's list on the device; every launch is sized for the whole class
+    // and the kernels read the kept count (each J element still sums l_P in
+    // ascending order)
+    int64_t loff[NLA][NLA] = {};
     int64_t o = 0;
     hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, s, reinterpret_cast<int *>(pcount),
                        2 * NLA * NLA, 0);
@@ -937,38 +1153,46 @@ int coulomb_J_run(const double *xyz, int32_t natom, const df3c_shells *aux,
       }
     if (nj) {
       hipLaunchKernelGGL(k_pair_compact, dim3(nj), dim3(COMPACT_TPB), 0, s, jobs, mask,
-                         orb->nshell);
+                         orb->nshell, dp.err);
       if (hipGetLastError() != hipSuccess) return DF3C_E_HIP;
     }
+    // without DF3C_ASYNC the kept counts are read back once and size the
+    // launches (lanes per pair and grid for the pairs that remain)
+    unsigned long long kept[NLA * NLA] = {};
+    const bool sized = !(flags & DF3C_ASYNC);
+    if (sized && read_back(kept, pcount, sizeof(kept), s) != hipSuccess) return DF3C_E_HIP;
+    for (int la = 0; la <= DF3C_LMAX_ORB; ++la)
+      for (int lb = 0; lb <= la; ++lb) {
+        if (!set_class(la, lb)) continue;
+        a.plist = plist + loff[la][lb];
+        a.pcount = reinterpret_cast<const int64_t *>(pcount + la * NLA + lb);
+        if (sized) {
+          a.npair = int64_t(kept[la * NLA + lb]);  // the kernels read *pcount
+          if (!a.npair) continue;
+        }
+        for (int lp = 0; lp <= DF3C_LMAX_AUX; ++lp)
+          if ((rc = launch(lp, la, lb))) return rc;
+      }
   }
-  unsigned long long *kept = reinterpret_cast<unsigned long long *>(g_pinned);
-  if (hipMemcpyAsync(kept, pcount, sizeof(unsigned long long) * NLA * NLA, hipMemcpyDeviceToHost,
-                     s) != hipSuccess ||
-      hipStreamSynchronize(s) != hipSuccess)
-    return DF3C_E_HIP;
-  for (int la = 0; la <= DF3C_LMAX_ORB; ++la)
-    for (int lb = 0; lb <= la; ++lb) {
-      if (!set_class(la, lb)) continue;
-      a.plist = plist + loff[la][lb];
-      a.pcount = reinterpret_cast<const int64_t *>(pcount + la * NLA + lb);
-      a.npair = int64_t(kept[la * NLA + lb]);  // sizes the launch; the kernel reads *pcount
-      if (!a.npair) continue;
-      for (int lp = 0; lp <= DF3C_LMAX_AUX; ++lp)
-        if ((rc = launch(lp, la, lb))) return rc;
-    }
-  return finish();
+  if (orb->pure && p.npure) {
+    const int64_t n2 = p.npure * p.npure;
+    hipLaunchKernelGGL(k_bra_pure, dim3(int(std::min<int64_t>((n2 + 255) / 256, 8192))),
+                       dim3(256), 0, s, J, p.nao, pmap, dp.ao_off, orb->l, Jout, p.npure, dp.err);
+    if (hipGetLastError() != hipSuccess) return DF3C_E_HIP;
+  }
+  return finish_call(flags, dp.err, s);
 }
 }  // namespace
 
 int df3c_coulomb_J(const double *xyz, int32_t natom, const df3c_shells *aux,
                    const df3c_shells *orb, const double *d, double *J, void *ws, size_t ws_bytes,
                    uint32_t flags, void *stream) {
-  (void)flags;
+  if (flags & ~DF3C_ASYNC) return DF3C_E_ARG;
   if (!xyz || natom <= 0 || !shells_ok(aux) || !shells_ok(orb) || !d || !J) return DF3C_E_ARG;
   if ((orb->pure != 0 && orb->pure != 1) || (aux->pure != 0 && aux->pure != 1))
     return DF3C_E_UNSUPPORTED;
   if (!ws || ws_bytes < df3c_coulomb_J_workspace(aux, orb)) return DF3C_E_WORKSPACE;
-  return coulomb_J_run(xyz, natom, aux, orb, d, nullptr, J, ws, jplan_bytes(orb->nshell, aux->nshell),
+  return coulomb_J_run(xyz, natom, aux, orb, d, nullptr, J, ws, flags,
                        reinterpret_cast<hipStream_t>(stream));
 }
 
@@ -994,20 +1218,20 @@ size_t masked_core_bytes(const df3c_shells *aux, const df3c_shells *orb) {
 }  // namespace
 
 size_t df3c_coulomb_J_masked_workspace(const df3c_shells *aux, const df3c_shells *orb) {
-  if (!aux || !orb || !orb->l_host) return 0;
+  if (!shells_ok(aux) || !shells_ok(orb)) return 0;
   return masked_core_bytes(aux, orb) + pure_bytes(orb);
 }
 
 int df3c_coulomb_J_masked(const double *xyz, int32_t natom, const df3c_shells *aux,
                           const df3c_shells *orb, const double *d, const uint8_t *mask,
                           double *J, void *ws, size_t ws_bytes, uint32_t flags, void *stream) {
-  (void)flags;
+  if (flags & ~DF3C_ASYNC) return DF3C_E_ARG;
   if (!xyz || natom <= 0 || !shells_ok(aux) || !shells_ok(orb) || !d || !J || !mask)
     return DF3C_E_ARG;
   if ((orb->pure != 0 && orb->pure != 1) || (aux->pure != 0 && aux->pure != 1))
     return DF3C_E_UNSUPPORTED;
   if (!ws || ws_bytes < df3c_coulomb_J_masked_workspace(aux, orb)) return DF3C_E_WORKSPACE;
-  return coulomb_J_run(xyz, natom, aux, orb, d, mask, J, ws, masked_core_bytes(aux, orb),
+  return coulomb_J_run(xyz, natom, aux, orb, d, mask, J, ws, flags,
                        reinterpret_cast<hipStream_t>(stream));
 }
 
@@ -1021,8 +1245,8 @@ size_t df3c_coulomb_metric_workspace(const df3c_shells *aux) {
 
 int df3c_coulomb_metric(const double *xyz, int32_t natom, const df3c_shells *aux, double *V,
                         void *ws, size_t ws_bytes, uint32_t flags, void *stream) {
-  (void)flags;
-  if (!xyz || natom <= 0 || !shells_ok(aux) || !V || !aux->l_host) return DF3C_E_ARG;
+  if (flags) return DF3C_E_ARG;
+  if (!xyz || natom <= 0 || !shells_ok(aux) || !V) return DF3C_E_ARG;
   if (aux->pure != 0 && aux->pure != 1) return DF3C_E_UNSUPPORTED;
   if (!ws || ws_bytes < df3c_coulomb_metric_workspace(aux)) return DF3C_E_WORKSPACE;
   DevState *ds = nullptr;
@@ -1050,14 +1274,16 @@ int df3c_coulomb_metric(const double *xyz, int32_t natom, const df3c_shells *aux
   if (hipMemcpyAsync(sorted_d, sorted.data(), sizeof(int32_t) * aux->nshell,
                      hipMemcpyHostToDevice, s) != hipSuccess ||
       hipMemcpyAsync(off_d, off.data(), sizeof(int64_t) * (aux->nshell + 1), hipMemcpyHostToDevice,
-                     s) != hipSuccess)
+                     s) != hipSuccess) {
+    (void)hipStreamSynchronize(s);  // a copy already queued still reads the host vectors
     return DF3C_E_HIP;
+  }
   hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, s, err, 1, 0);
   check_shells(aux, natom, err, s);
-  if (hipMemcpyAsync(g_pinned, err, sizeof(int), hipMemcpyDeviceToHost, s) != hipSuccess)
-    return DF3C_E_HIP;
-  if (hipStreamSynchronize(s) != hipSuccess) return DF3C_E_HIP;
-  if (g_pinned[0]) return DF3C_E_ARG;
+  // the readback also waits for the plan copies, whose host vectors end here
+  int word = 0;
+  if (read_back(&word, err, sizeof(int), s) != hipSuccess) return DF3C_E_HIP;
+  if (word) return DF3C_E_ARG;
   MetArgs a{};
   a.boys = ds->boys;
   a.xyz = xyz;
@@ -1111,7 +1337,8 @@ GamRegPlan gam_reg_plan(int64_t npair, int np, int nacc, int ncu) {
 // register engine: gamma[aux function] += sum over the pair ranges, in order
 __global__ void k_gam_reduce_r(const double *partial, int32_t np, int32_t nsplit, int32_t nps,
                                int64_t nrange, int32_t nout, const int32_t *psh,
-                               const int64_t *aux_off, double *gamma) {
+                               const int64_t *aux_off, double *gamma, const int *err) {
+  if (*err) return;
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < np * nout; i += gridDim.x * blockDim.x) {
     const int ip = i / nout, m = i - ip * nout;
     const int sub = ip % nsplit, k = ip / nsplit;
@@ -1124,7 +1351,7 @@ __global__ void k_gam_reduce_r(const double *partial, int32_t np, int32_t nsplit
 }  // namespace
 
 size_t df3c_coulomb_gamma_workspace(const df3c_shells *aux, const df3c_shells *orb) {
-  if (!aux || !orb || !aux->l_host || !orb->l_host) return 0;
+  if (!shells_ok(aux) || !shells_ok(orb)) return 0;
   DevState *ds = nullptr;
   if (init_device(&ds)) return 0;
   // the partials of the largest class plan
@@ -1150,7 +1377,7 @@ size_t df3c_coulomb_gamma_workspace(const df3c_shells *aux, const df3c_shells *o
 int df3c_coulomb_gamma(const double *xyz, int32_t natom, const df3c_shells *aux,
                        const df3c_shells *orb, const double *D, double *gamma, void *ws,
                        size_t ws_bytes, uint32_t flags, void *stream) {
-  (void)flags;
+  if (flags & ~DF3C_ASYNC) return DF3C_E_ARG;
   if (!xyz || natom <= 0 || !shells_ok(aux) || !shells_ok(orb) || !D || !gamma) return DF3C_E_ARG;
   if ((orb->pure != 0 && orb->pure != 1) || (aux->pure != 0 && aux->pure != 1))
     return DF3C_E_UNSUPPORTED;
@@ -1159,58 +1386,40 @@ int df3c_coulomb_gamma(const double *xyz, int32_t natom, const df3c_shells *aux,
   DevState *ds = nullptr;
   int rc = init_device(&ds);
   if (rc) return rc;
-  JPlan p;
-  rc = make_plan(aux, orb, p);
-  if (rc) return rc;
+  HostPlan p;
+  if ((rc = host_plan(aux, orb, p))) return rc;
+  if (orb->pure && orb->nshell >= (1 << 27)) return DF3C_E_UNSUPPORTED;  // rows packed shell << 4
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-  char *w = static_cast<char *>(ws);
-  int *err = reinterpret_cast<int *>(w);
-  w += align256(sizeof(int) * 8);
-  int32_t *orb_sorted = reinterpret_cast<int32_t *>(w);
-  w += align256(sizeof(int32_t) * orb->nshell);
-  int32_t *aux_sorted = reinterpret_cast<int32_t *>(w);
-  w += align256(sizeof(int32_t) * aux->nshell);
-  int64_t *ao_off = reinterpret_cast<int64_t *>(w);
-  w += align256(sizeof(int64_t) * (orb->nshell + 1));
-  int64_t *aux_off = reinterpret_cast<int64_t *>(w);
-  w += align256(sizeof(int64_t) * (aux->nshell + 1));
-  double *partial = reinterpret_cast<double *>(w);
-  if (hipMemcpyAsync(orb_sorted, p.orb_sorted.data(), sizeof(int32_t) * orb->nshell,
-                     hipMemcpyHostToDevice, s) != hipSuccess ||
-      hipMemcpyAsync(aux_sorted, p.aux_sorted.data(), sizeof(int32_t) * aux->nshell,
-                     hipMemcpyHostToDevice, s) != hipSuccess ||
-      hipMemcpyAsync(ao_off, p.ao_off.data(), sizeof(int64_t) * (orb->nshell + 1),
-                     hipMemcpyHostToDevice, s) != hipSuccess ||
-      hipMemcpyAsync(aux_off, p.aux_off.data(), sizeof(int64_t) * (aux->nshell + 1),
-                     hipMemcpyHostToDevice, s) != hipSuccess) {
-    (void)hipStreamSynchronize(s);  // copies already queued still read the plan
+  const DevPlan dp = carve_plan(ws, orb->nshell, aux->nshell);
+  int32_t *aux_sorted = dp.aux_sorted;
+  int64_t *aux_off = dp.aux_off;
+  double *partial = reinterpret_cast<double *>(static_cast<char *>(ws) +
+                                               jplan_bytes(orb->nshell, aux->nshell));
+  // solid-harmonic orbital shells: the engines contract with D_cart = T_a^T D T_b
+  // (the pull-back sits at the end of the workspace)
+  PullBack pb;
+  if (orb->pure)
+    pb = carve_pullback(orb, static_cast<char *>(ws) + need - pullback_bytes(orb), p.nao);
+  if (launch_plan(dp, p, aux, orb, natom, nullptr, orb->pure ? pb.cmap : nullptr,
+                  orb->pure ? pb.poff : nullptr, s) != hipSuccess)
     return DF3C_E_HIP;
-  }
-  hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, s, err, 1, 0);
-  check_shells(aux, natom, err, s);
-  check_shells(orb, natom, err, s);
-  if (hipMemcpyAsync(g_pinned, err, sizeof(int), hipMemcpyDeviceToHost, s) != hipSuccess)
-    return DF3C_E_HIP;
-  if (hipStreamSynchronize(s) != hipSuccess) return DF3C_E_HIP;
-  if (g_pinned[0]) return DF3C_E_ARG;
   hipLaunchKernelGGL(k_zero_f64, dim3(int(std::min<int64_t>((p.naux + 255) / 256, 4096))),
                      dim3(256), 0, s, gamma, p.naux);
   if (orb->pure) {
-    // solid-harmonic orbital shells: the engines contract with D_cart = T_a^T D T_b
-    // (the pull-back sits at the end of the workspace)
-    if ((rc = pull_back_cart(orb, D, static_cast<char *>(ws) + need - pullback_bytes(orb), s, &D)))
-      return rc;
+    if (pull_back_cart(orb, D, pb, p.nao, p.npure, dp.err, s) != hipSuccess) return DF3C_E_HIP;
+    D = pb.Gc;
   }
   GamArgs a{};
   a.boys = ds->boys;
   a.xyz = xyz;
   a.aux = dev_shells(aux);
   a.orb = dev_shells(orb);
-  a.ao_off = ao_off;
+  a.ao_off = dp.ao_off;
   a.D = D;
   a.nao = p.nao;
   a.pure = aux->pure;
   a.partial = partial;
+  a.err = dp.err;
   for (int lp = 0; lp <= DF3C_LMAX_AUX; ++lp) {
     const int np = p.aux_start[lp + 1] - p.aux_start[lp];
     if (!np) continue;
@@ -1222,8 +1431,8 @@ int df3c_coulomb_gamma(const double *xyz, int32_t natom, const df3c_shells *aux,
         const int na = p.orb_start[la + 1] - p.orb_start[la];
         const int nb = p.orb_start[lb + 1] - p.orb_start[lb];
         if (!na || !nb) continue;
-        a.ash = orb_sorted + p.orb_start[la];
-        a.bsh = orb_sorted + p.orb_start[lb];
+        a.ash = dp.orb_sorted + p.orb_start[la];
+        a.bsh = dp.orb_sorted + p.orb_start[lb];
         a.na = na;
         a.nb = nb;
         a.same = (la == lb);
@@ -1242,10 +1451,10 @@ int df3c_coulomb_gamma(const double *xyz, int32_t natom, const df3c_shells *aux,
           return DF3C_E_HIP;
         const int nred = np * nout;
         hipLaunchKernelGGL(k_gam_reduce_r, dim3((nred + 255) / 256), dim3(256), 0, s, partial, np,
-                           gp.nsplit, gp.nps, gp.nrange, nout, a.psh, aux_off, gamma);
+                           gp.nsplit, gp.nps, gp.nrange, nout, a.psh, aux_off, gamma, dp.err);
       }
   }
-  return DF3C_OK;
+  return finish_call(flags, dp.err, s);
 }
 
 // ----------------------------------------------------------------- J gradient
@@ -1270,7 +1479,7 @@ int grad_split(const GradInfo &gi, int64_t npair, int np, int ncu) {
 
 size_t df3c_coulomb_J_grad_workspace(const df3c_shells *aux, const df3c_shells *orb,
                                      int32_t natom) {
-  if (!aux || !orb || natom < 0) return 0;
+  if (!shells_ok(aux) || !shells_ok(orb) || natom < 0) return 0;
   int dev = 0, ncu = 256;
   if (hipGetDevice(&dev) == hipSuccess) {
     hipDeviceProp_t prop;
@@ -1278,14 +1487,15 @@ size_t df3c_coulomb_J_grad_workspace(const df3c_shells *aux, const df3c_shells *
   }
   return jplan_bytes(orb->nshell, aux->nshell) +
          align256(sizeof(double) * size_t(grad_slots(ncu)) * 3 * size_t(natom)) +
-         (orb->l_host ? pullback_bytes(orb) : 0);
+         pullback_bytes(orb);
 }
 
 namespace {
-// the J gradient over all pairs (mask null) or over the pairs a mask keeps
+// The J gradient over all pairs (mask null) or over the pairs a mask keeps;
+// asynchronous like coulomb_J_run (device plan, status word, device counts).
 int grad_run(const double *xyz, int32_t natom, const df3c_shells *aux, const df3c_shells *orb,
              const double *d, const double *G, const uint8_t *mask, double *grad, void *ws,
-             size_t ws_bytes, hipStream_t s) {
+             size_t ws_bytes, uint32_t flags, hipStream_t s) {
   DevState *ds = nullptr;
   int rc = init_device(&ds);
   if (rc) return rc;
@@ -1296,23 +1506,22 @@ int grad_run(const double *xyz, int32_t natom, const df3c_shells *aux, const df3
                                               align256(sizeof(int64_t) * size_t(total_class_pairs(orb)))
                                         : 0);
   if (!ws || ws_bytes < core + pullback_bytes(orb)) return DF3C_E_WORKSPACE;
-  JPlan p;
-  rc = make_plan(aux, orb, p);
-  if (rc) return rc;
+  HostPlan p;
+  if ((rc = host_plan(aux, orb, p))) return rc;
   for (int l = DF3C_LMAX_GRAD_ORB + 1; l <= DF3C_LMAX_ORB; ++l)
     if (p.orb_start[l + 1] > p.orb_start[l]) return DF3C_E_UNSUPPORTED;
-  char *w = static_cast<char *>(ws);
-  int *err = reinterpret_cast<int *>(w);
-  w += align256(sizeof(int) * 8);
-  int32_t *orb_sorted = reinterpret_cast<int32_t *>(w);
-  w += align256(sizeof(int32_t) * orb->nshell);
-  int32_t *aux_sorted = reinterpret_cast<int32_t *>(w);
-  w += align256(sizeof(int32_t) * aux->nshell);
-  int64_t *ao_off = reinterpret_cast<int64_t *>(w);
-  w += align256(sizeof(int64_t) * (orb->nshell + 1));
-  int64_t *aux_off = reinterpret_cast<int64_t *>(w);
-  w += align256(sizeof(int64_t) * (aux->nshell + 1));
-  double *partial = reinterpret_cast<double *>(w);
+  if (orb->pure && orb->nshell >= (1 << 27)) return DF3C_E_UNSUPPORTED;  // rows packed shell << 4
+  // the per-workgroup atom arrays must fit the LDS of every launched class
+  for (int lp = 0; lp <= DF3C_LMAX_AUX; ++lp)
+    for (int la = 0; la <= DF3C_LMAX_GRAD_ORB; ++la)
+      for (int lb = 0; lb <= la; ++lb) {
+        if (!p.ca.n[lp] || !p.co.n[la] || !p.co.n[lb]) continue;
+        const GradInfo &gi = g_grad[lp][la][lb];
+        if (gi.tpb * (gi.team + 3 * int64_t(natom)) * 8 > 160 * 1024) return DF3C_E_UNSUPPORTED;
+      }
+  const DevPlan dp = carve_plan(ws, orb->nshell, aux->nshell);
+  double *partial = reinterpret_cast<double *>(static_cast<char *>(ws) +
+                                               jplan_bytes(orb->nshell, aux->nshell));
   // masked only: kept-pair counters and lists of the (l_a, l_b) classes
   unsigned long long *pcount = nullptr;
   int64_t *plist = nullptr;
@@ -1321,47 +1530,36 @@ int grad_run(const double *xyz, int32_t natom, const df3c_shells *aux, const df3
     pcount = reinterpret_cast<unsigned long long *>(m);
     plist = reinterpret_cast<int64_t *>(m + align256(sizeof(unsigned long long) * NLA * NLA));
   }
-  if (hipMemcpyAsync(orb_sorted, p.orb_sorted.data(), sizeof(int32_t) * orb->nshell,
-                     hipMemcpyHostToDevice, s) != hipSuccess ||
-      hipMemcpyAsync(aux_sorted, p.aux_sorted.data(), sizeof(int32_t) * aux->nshell,
-                     hipMemcpyHostToDevice, s) != hipSuccess ||
-      hipMemcpyAsync(ao_off, p.ao_off.data(), sizeof(int64_t) * (orb->nshell + 1),
-                     hipMemcpyHostToDevice, s) != hipSuccess ||
-      hipMemcpyAsync(aux_off, p.aux_off.data(), sizeof(int64_t) * (aux->nshell + 1),
-                     hipMemcpyHostToDevice, s) != hipSuccess) {
-    (void)hipStreamSynchronize(s);  // copies already queued still read the plan
+  // solid-harmonic orbital shells: the engines take G_cart = T_a^T G T_b
+  PullBack pb;
+  if (orb->pure) pb = carve_pullback(orb, static_cast<char *>(ws) + core, p.nao);
+  if (launch_plan(dp, p, aux, orb, natom, nullptr, orb->pure ? pb.cmap : nullptr,
+                  orb->pure ? pb.poff : nullptr, s) != hipSuccess)
     return DF3C_E_HIP;
-  }
-  hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, s, err, 1, 0);
-  check_shells(aux, natom, err, s);
-  check_shells(orb, natom, err, s);
-  if (hipMemcpyAsync(g_pinned, err, sizeof(int), hipMemcpyDeviceToHost, s) != hipSuccess)
-    return DF3C_E_HIP;
-  if (hipStreamSynchronize(s) != hipSuccess) return DF3C_E_HIP;
-  if (g_pinned[0]) return DF3C_E_ARG;
   const int64_t npart = int64_t(nslot) * 3 * natom;
   hipLaunchKernelGGL(k_zero_f64, dim3(int(std::min<int64_t>((npart + 255) / 256, 4096))),
                      dim3(256), 0, s, partial, npart);
   if (orb->pure) {
-    // solid-harmonic orbital shells: the engines take G_cart = T_a^T G T_b
-    if ((rc = pull_back_cart(orb, G, static_cast<char *>(ws) + core, s, &G))) return rc;
+    if (pull_back_cart(orb, G, pb, p.nao, p.npure, dp.err, s) != hipSuccess) return DF3C_E_HIP;
+    G = pb.Gc;
   }
   GradArgs a{};
   a.boys = ds->boys;
   a.xyz = xyz;
   a.aux = dev_shells(aux);
   a.orb = dev_shells(orb);
-  a.ao_off = ao_off;
-  a.aux_off = aux_off;
+  a.ao_off = dp.ao_off;
+  a.aux_off = dp.aux_off;
   a.d = d;
   a.G = G;
   a.nao = p.nao;
   a.pure = aux->pure;
   a.natom = natom;
   a.partial = partial;
-  // masked: compact the kept pairs of every class, one readback of the counts
+  a.err = dp.err;
+  // masked: compact the kept pairs of every class on the device; launches
+  // are sized for the whole class and the kernels read the kept count
   int64_t loff[NLA][NLA] = {};
-  unsigned long long *kept = reinterpret_cast<unsigned long long *>(g_pinned);
   if (mask) {
     int64_t o = 0;
     hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, s, reinterpret_cast<int *>(pcount),
@@ -1375,33 +1573,33 @@ int grad_run(const double *xyz, int32_t natom, const df3c_shells *aux, const df3
         const int nb = p.orb_start[lb + 1] - p.orb_start[lb];
         if (!na || !nb) continue;
         const int64_t npair = (la == lb) ? int64_t(na) * (na + 1) / 2 : int64_t(na) * nb;
-        jobs.j[nj++] = CompactJob{orb_sorted + p.orb_start[la], orb_sorted + p.orb_start[lb], nb,
-                                  int(la == lb), npair, plist + o, pcount + la * NLA + lb};
+        jobs.j[nj++] = CompactJob{dp.orb_sorted + p.orb_start[la], dp.orb_sorted + p.orb_start[lb],
+                                  nb, int(la == lb), npair, plist + o, pcount + la * NLA + lb};
         o += npair;
       }
     if (nj) {
       hipLaunchKernelGGL(k_pair_compact, dim3(nj), dim3(COMPACT_TPB), 0, s, jobs, mask,
-                         orb->nshell);
+                         orb->nshell, dp.err);
       if (hipGetLastError() != hipSuccess) return DF3C_E_HIP;
     }
-    if (hipMemcpyAsync(kept, pcount, sizeof(unsigned long long) * NLA * NLA,
-                       hipMemcpyDeviceToHost, s) != hipSuccess ||
-        hipStreamSynchronize(s) != hipSuccess)
-      return DF3C_E_HIP;
   }
+  // without DF3C_ASYNC the kept counts are read back once and size the launches
+  unsigned long long kept[NLA * NLA] = {};
+  const bool sized = mask && !(flags & DF3C_ASYNC);
+  if (sized && read_back(kept, pcount, sizeof(kept), s) != hipSuccess) return DF3C_E_HIP;
   const int grid_cap = ds->ncu * GRAD_GRID_PER_CU;
   for (int lp = 0; lp <= DF3C_LMAX_AUX; ++lp) {
     const int np = p.aux_start[lp + 1] - p.aux_start[lp];
     if (!np) continue;
-    a.psh = aux_sorted + p.aux_start[lp];
+    a.psh = dp.aux_sorted + p.aux_start[lp];
     a.np = np;
     for (int la = 0; la <= DF3C_LMAX_GRAD_ORB; ++la)
       for (int lb = 0; lb <= la; ++lb) {
         const int na = p.orb_start[la + 1] - p.orb_start[la];
         const int nb = p.orb_start[lb + 1] - p.orb_start[lb];
         if (!na || !nb) continue;
-        a.ash = orb_sorted + p.orb_start[la];
-        a.bsh = orb_sorted + p.orb_start[lb];
+        a.ash = dp.orb_sorted + p.orb_start[la];
+        a.bsh = dp.orb_sorted + p.orb_start[lb];
         a.na = na;
         a.nb = nb;
         a.same = (la == lb);
@@ -1409,12 +1607,13 @@ int grad_run(const double *xyz, int32_t natom, const df3c_shells *aux, const df3
         if (mask) {
           a.plist = plist + loff[la][lb];
           a.pcount = reinterpret_cast<const int64_t *>(pcount + la * NLA + lb);
-          a.npair = int64_t(kept[la * NLA + lb]);  // sizes the launch; kernels read *pcount
-          if (!a.npair) continue;
+          if (sized) {
+            a.npair = int64_t(kept[la * NLA + lb]);  // the kernels read *pcount
+            if (!a.npair) continue;
+          }
         }
         const GradInfo &gi = g_grad[lp][la][lb];
         const int lds = gi.tpb * (gi.team + 3 * natom) * 8;
-        if (lds > 160 * 1024) return DF3C_E_UNSUPPORTED;
         a.nsplit = grad_split(gi, a.npair, np, ds->ncu);
         const int64_t blocks = (a.npair + gi.ppw - 1) / gi.ppw * a.nsplit;
         const int grid = int(std::max<int64_t>(1, std::min<int64_t>(blocks, grid_cap)));
@@ -1426,25 +1625,26 @@ int grad_run(const double *xyz, int32_t natom, const df3c_shells *aux, const df3
   const int n = 3 * natom;
   hipLaunchKernelGGL(k_reduce_partial, dim3((n + 255) / 256), dim3(256), 0, s, partial, nslot, n,
                      grad);
-  return DF3C_OK;
+  if (hipGetLastError() != hipSuccess) return DF3C_E_HIP;
+  return finish_call(flags, dp.err, s);
 }
 }  // namespace
 
 int df3c_coulomb_J_grad(const double *xyz, int32_t natom, const df3c_shells *aux,
                         const df3c_shells *orb, const double *d, const double *G, double *grad,
                         void *ws, size_t ws_bytes, uint32_t flags, void *stream) {
-  (void)flags;
+  if (flags & ~DF3C_ASYNC) return DF3C_E_ARG;
   if (!xyz || natom <= 0 || !shells_ok(aux) || !shells_ok(orb) || !d || !G || !grad)
     return DF3C_E_ARG;
   if ((orb->pure != 0 && orb->pure != 1) || (aux->pure != 0 && aux->pure != 1))
     return DF3C_E_UNSUPPORTED;
-  return grad_run(xyz, natom, aux, orb, d, G, nullptr, grad, ws, ws_bytes,
+  return grad_run(xyz, natom, aux, orb, d, G, nullptr, grad, ws, ws_bytes, flags,
                   reinterpret_cast<hipStream_t>(stream));
 }
 
 size_t df3c_coulomb_J_grad_masked_workspace(const df3c_shells *aux, const df3c_shells *orb,
                                             int32_t natom) {
-  if (!aux || !orb || !orb->l_host || natom < 0) return 0;
+  if (!shells_ok(aux) || !shells_ok(orb) || natom < 0) return 0;
   return df3c_coulomb_J_grad_workspace(aux, orb, natom) +
          align256(sizeof(unsigned long long) * NLA * NLA) +
          align256(sizeof(int64_t) * size_t(total_class_pairs(orb)));
@@ -1454,12 +1654,12 @@ int df3c_coulomb_J_grad_masked(const double *xyz, int32_t natom, const df3c_shel
                                const df3c_shells *orb, const double *d, const double *G,
                                const uint8_t *mask, double *grad, void *ws, size_t ws_bytes,
                                uint32_t flags, void *stream) {
-  (void)flags;
+  if (flags & ~DF3C_ASYNC) return DF3C_E_ARG;
   if (!xyz || natom <= 0 || !shells_ok(aux) || !shells_ok(orb) || !d || !G || !grad || !mask)
     return DF3C_E_ARG;
   if ((orb->pure != 0 && orb->pure != 1) || (aux->pure != 0 && aux->pure != 1))
     return DF3C_E_UNSUPPORTED;
-  return grad_run(xyz, natom, aux, orb, d, G, mask, grad, ws, ws_bytes,
+  return grad_run(xyz, natom, aux, orb, d, G, mask, grad, ws, ws_bytes, flags,
                   reinterpret_cast<hipStream_t>(stream));
 }
 
@@ -1481,6 +1681,17 @@ size_t bplan_bytes(int64_t norb, int64_t naux, int64_t nmol) {
          align256(sizeof(int32_t) * naux) + align256(sizeof(int64_t) * (norb + 1)) +
          align256(sizeof(int64_t) * (naux + 1)) + align256(sizeof(JSeg) * nmol * NCLS) +
          align256(sizeof(unsigned long long) * NCLS) + align256(sizeof(double) * AREC * naux);
+}
+
+// Orbital shells of one l in order of decreasing contraction degree (stable),
+// the order of the device plans: the kernels give one lane or one team to a
+// shell pair and loop over its primitive pairs, so pairs that share a
+// wavefront should have equal Ka Kb.
+void sort_by_contraction(const df3c_shells *orb, int32_t *first, int32_t *last) {
+  if (!orb->nprim_host) return;
+  std::stable_sort(first, last, [orb](int32_t x, int32_t y) {
+    return orb->nprim_host[x] > orb->nprim_host[y];
+  });
 }
 
 int make_bplan(const df3c_shells *aux, const df3c_shells *orb, int nmol, const int32_t *mo,
@@ -1570,10 +1781,19 @@ uint64_t fnv(uint64_t h, const void *data, size_t n) {
   return h;
 }
 
+// A cached executable graph owns the host plan its launches were captured
+// from: every call uploads that plan into the caller's workspace before the
+// replay (the copies read the entry's memory, which outlives them), so a
+// replay never depends on what the workspace held before.  At most
+// GRAPH_CACHE entries are kept; the oldest is destroyed first.
 struct GraphEntry {
   hipGraphExec_t exec = nullptr;
+  std::shared_ptr<BPlan> plan;
+  uint64_t stamp = 0;
 };
+constexpr size_t GRAPH_CACHE = 8;
 std::unordered_map<uint64_t, GraphEntry> g_graphs;
+uint64_t g_graph_clock = 0;
 std::mutex g_graph_mu;
 
 df3c_class_tune default_tune(int c) {
@@ -1600,7 +1820,7 @@ int df3c_coulomb_J_batched(const double *xyz, int32_t natom, const df3c_shells *
   if (!xyz || natom <= 0 || !shells_ok(aux) || !shells_ok(orb) || !d || !J || nmol <= 0)
     return DF3C_E_ARG;
   if (orb->pure != 0 || (aux->pure != 0 && aux->pure != 1)) return DF3C_E_UNSUPPORTED;
-  if (flags & ~(DF3C_SCHED_PERSISTENT | DF3C_GRAPH)) return DF3C_E_ARG;
+  if (flags & ~(DF3C_SCHED_PERSISTENT | DF3C_GRAPH | DF3C_ASYNC)) return DF3C_E_ARG;
   if (!ws || ws_bytes < bplan_bytes(orb->nshell, aux->nshell, nmol)) return DF3C_E_WORKSPACE;
   DevState *ds = nullptr;
   int rc = init_device(&ds);
@@ -1628,16 +1848,23 @@ int df3c_coulomb_J_batched(const double *xyz, int32_t natom, const df3c_shells *
   key = fnv(key, mol_orb, sizeof(int32_t) * (nmol + 1));
   key = fnv(key, mol_aux, sizeof(int32_t) * (nmol + 1));
   key = fnv(key, tt, sizeof(tt));
+  std::shared_ptr<BPlan> pp;
+  hipGraphExec_t hit = nullptr;
   if (flags & DF3C_GRAPH) {
     std::lock_guard<std::mutex> lk(g_graph_mu);
     auto it = g_graphs.find(key);
-    if (it != g_graphs.end())
-      return hipGraphLaunch(it->second.exec, s) == hipSuccess ? DF3C_OK : DF3C_E_HIP;
+    if (it != g_graphs.end()) {
+      hit = it->second.exec;
+      pp = it->second.plan;
+      it->second.stamp = ++g_graph_clock;
+    }
   }
-
-  BPlan p;
-  rc = make_bplan(aux, orb, nmol, mol_orb, mol_aux, p);
-  if (rc) return rc;
+  if (!pp) {
+    pp = std::make_shared<BPlan>();
+    rc = make_bplan(aux, orb, nmol, mol_orb, mol_aux, *pp);
+    if (rc) return rc;
+  }
+  const BPlan &p = *pp;
   char *w = static_cast<char *>(ws);
   int *err = reinterpret_cast<int *>(w);
   w += align256(sizeof(int) * 8);
@@ -1669,13 +1896,15 @@ int df3c_coulomb_J_batched(const double *xyz, int32_t natom, const df3c_shells *
     (void)hipStreamSynchronize(s);  // copies already queued still read the plan
     return DF3C_E_HIP;
   }
-  hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, s, err, 1, 0);
+  // the descriptors are checked on every call (the kernels read the status
+  // word and do nothing when it is set)
+  hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, s, err, 8, 0);
   check_shells(aux, natom, err, s);
   check_shells(orb, natom, err, s);
-  if (hipMemcpyAsync(g_pinned, err, sizeof(int), hipMemcpyDeviceToHost, s) != hipSuccess ||
-      hipStreamSynchronize(s) != hipSuccess)
-    return DF3C_E_HIP;
-  if (g_pinned[0]) return DF3C_E_ARG;
+  if (hit) {
+    if (hipGraphLaunch(hit, s) != hipSuccess) return DF3C_E_HIP;
+    return finish_call(flags, err, s);
+  }
 
   // class launch order
   std::vector<int> order;
@@ -1693,6 +1922,7 @@ int df3c_coulomb_J_batched(const double *xyz, int32_t natom, const df3c_shells *
   base.aux_off = aux_off;
   base.d = d;
   base.pure = aux->pure;
+  base.err = err;
   // lanes per pair of the register engine: one value per class from the
   // batch's totals, so that both schedules sum in the same order
   auto class_nsub = [&](int c) {
@@ -1708,7 +1938,7 @@ int df3c_coulomb_J_batched(const double *xyz, int32_t natom, const df3c_shells *
     hipLaunchKernelGGL(k_zero_f64, dim3(int(std::min<int64_t>((p.jtotal + 255) / 256, 4096))),
                        dim3(256), 0, s, J, p.jtotal);
     if (launch_aux_records(aux_sorted, int64_t(p.aux_sorted.size()), aux, xyz, aux_off, d, arec,
-                           s) != hipSuccess)
+                           s, err) != hipSuccess)
       return DF3C_E_HIP;
     if (flags & DF3C_SCHED_PERSISTENT) {
       hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(256), 0, s, reinterpret_cast<int *>(ctr),
@@ -1766,25 +1996,50 @@ int df3c_coulomb_J_batched(const double *xyz, int32_t natom, const df3c_shells *
     return DF3C_OK;
   };
 
-  if (!(flags & DF3C_GRAPH)) return enqueue();
+  // an error after the plan upload waits for its copies before the plan goes
+  auto fail = [&](int r) {
+    (void)hipStreamSynchronize(s);
+    return r;
+  };
+  if (!(flags & DF3C_GRAPH)) {
+    if ((rc = enqueue())) return fail(rc);
+    // the plan's host memory ends with this call: wait for its copies
+    if ((flags & DF3C_ASYNC) && hipStreamSynchronize(s) != hipSuccess) return DF3C_E_HIP;
+    return finish_call(flags, err, s);
+  }
   // first call with DF3C_GRAPH: run once eagerly (sets kernel attributes), then
-  // capture the same launches and keep the executable graph
-  rc = enqueue();
-  if (rc) return rc;
+  // capture the same launches and keep the executable graph with its plan
+  if ((rc = enqueue())) return fail(rc);
   hipGraph_t graph = nullptr;
-  if (hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) != hipSuccess) return DF3C_E_HIP;
+  if (hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) != hipSuccess)
+    return fail(DF3C_E_HIP);
   rc = enqueue();
   if (hipStreamEndCapture(s, &graph) != hipSuccess || rc) {
     if (graph) (void)hipGraphDestroy(graph);
-    return rc ? rc : DF3C_E_HIP;
+    return fail(rc ? rc : DF3C_E_HIP);
   }
   hipGraphExec_t exec = nullptr;
   const hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
   (void)hipGraphDestroy(graph);
-  if (ie != hipSuccess) return DF3C_E_HIP;
-  std::lock_guard<std::mutex> lk(g_graph_mu);
-  g_graphs[key].exec = exec;
-  return DF3C_OK;
+  if (ie != hipSuccess) return fail(DF3C_E_HIP);
+  {
+    std::lock_guard<std::mutex> lk(g_graph_mu);
+    if (g_graphs.size() >= GRAPH_CACHE) {
+      // the oldest entry's graph and plan may still be in use by work queued
+      // on any stream of the device: wait for the device first (rare)
+      auto old = g_graphs.begin();
+      for (auto it = g_graphs.begin(); it != g_graphs.end(); ++it)
+        if (it->second.stamp < old->second.stamp) old = it;
+      if (hipDeviceSynchronize() != hipSuccess) return DF3C_E_HIP;
+      (void)hipGraphExecDestroy(old->second.exec);
+      g_graphs.erase(old);
+    }
+    GraphEntry &e = g_graphs[key];
+    e.exec = exec;
+    e.plan = pp;
+    e.stamp = ++g_graph_clock;
+  }
+  return finish_call(flags, err, s);
 }
 
 }  // extern "C"

@@ -20,6 +20,7 @@ DF3C_OK = 0
 SCHED_PER_CLASS = 0
 SCHED_PERSISTENT = 1
 GRAPH = 2
+ASYNC = 4
 NCLASS = 175
 
 
@@ -68,6 +69,7 @@ def lib():
         L = ctypes.CDLL(LIB_PATH)
         P, I64, U32, SZ = ctypes.c_void_p, ctypes.c_int64, ctypes.c_uint32, ctypes.c_size_t
         L.df3c_init.argtypes = []
+        L.df3c_workspace_status.argtypes = [P, P]
         L.df3c_status_string.restype = ctypes.c_char_p
         L.df3c_status_string.argtypes = [ctypes.c_int]
         L.df3c_eval_batch_workspace.restype = SZ
@@ -157,6 +159,17 @@ class DeviceBasis:
 
 def init():
     _check(lib().df3c_init(), "df3c_init")
+
+
+def workspace_status(ws: torch.Tensor, stream=None) -> int:
+    """Status of the last call that used ws (synchronises the stream); for
+    calls made with ASYNC."""
+    return int(lib().df3c_workspace_status(_ptr(ws), _stream(stream)))
+
+
+def check_workspace(ws: torch.Tensor, what: str, stream=None) -> None:
+    """Raise DF3CError if the last call that used ws failed on the device."""
+    _check(workspace_status(ws, stream), what)
 
 
 def eval_batch_workspace(ntrip: int) -> int:

@@ -103,3 +103,42 @@ def test_pure_orbital_options(lib):
                               1 << 40, 0, None) == -2
     assert lib.df3c_coulomb_J_grad(buf, 1, ctypes.byref(aux), ctypes.byref(bad), buf, buf, buf,
                                    buf, 1 << 40, 0, None) == -2
+
+
+def test_null_l_host_rejected_before_device_work(lib):
+    # the plans are sized from l_host: a basis without it is rejected by every
+    # entry point (and its workspace query gives 0) before any HIP call
+    from paper_2210_03192_amd import df3c
+    la = np.array([0, 1], np.int32)
+    buf = (ctypes.c_double * 8)()
+    p = ctypes.cast(buf, ctypes.c_void_p).value
+    good = df3c._Shells(len(la), la.ctypes.data, p, p, p, p, p, p, 1, None)
+    nol = df3c._Shells(len(la), None, p, p, p, p, p, p, 0, None)
+    nol_pure = df3c._Shells(len(la), None, p, p, p, p, p, p, 1, None)
+    A, O, Op = ctypes.byref(good), ctypes.byref(nol), ctypes.byref(nol_pure)
+    big = 1 << 40
+    assert lib.df3c_coulomb_J(buf, 1, A, O, buf, buf, buf, big, 0, None) == -1
+    assert lib.df3c_coulomb_J_masked(buf, 1, A, O, buf, buf, buf, buf, big, 0, None) == -1
+    assert lib.df3c_coulomb_J_grad(buf, 1, A, Op, buf, buf, buf, buf, big, 0, None) == -1
+    assert lib.df3c_coulomb_J_grad_masked(buf, 1, A, O, buf, buf, buf, buf, buf, big, 0,
+                                          None) == -1
+    assert lib.df3c_coulomb_gamma(buf, 1, A, O, buf, buf, buf, big, 0, None) == -1
+    assert lib.df3c_coulomb_J_workspace(A, O) == 0
+    assert lib.df3c_coulomb_J_masked_workspace(A, O) == 0
+    assert lib.df3c_coulomb_J_grad_workspace(A, Op, 1) == 0
+    assert lib.df3c_coulomb_J_grad_masked_workspace(A, O, 1) == 0
+
+
+def test_unknown_flags_rejected(lib):
+    # flags beyond each entry point's set are rejected before any HIP call
+    from paper_2210_03192_amd import df3c
+    la = np.array([0], np.int32)
+    buf = (ctypes.c_double * 8)()
+    p = ctypes.cast(buf, ctypes.c_void_p).value
+    sh = df3c._Shells(1, la.ctypes.data, p, p, p, p, p, p, 1, None)
+    S = ctypes.byref(sh)
+    big = 1 << 40
+    assert lib.df3c_coulomb_J(buf, 1, S, S, buf, buf, buf, big, 8, None) == -1
+    assert lib.df3c_coulomb_J_grad(buf, 1, S, S, buf, buf, buf, buf, big, 1, None) == -1
+    assert lib.df3c_eval_batch(buf, 1, S, S, 1, buf, buf, buf, buf, big, 2, None) == -1
+    assert lib.df3c_workspace_status(None, None) == -1
