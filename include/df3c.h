@@ -163,6 +163,29 @@ int df3c_coulomb_J(const double *xyz, int32_t natom, const df3c_shells *aux,
                    const df3c_shells *orb, const double *d, double *J, void *ws, size_t ws_bytes,
                    uint32_t flags, void *stream);
 
+/* For callers that cannot allocate (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid allocation): DF-J as df3c_coulomb_J
+ * with DF3C_ASYNC, the workspace being the library's own device array of
+ * DF3C_NOALLOC_SCRATCH_BYTES (one per device, held until the process ends)
+ * instead of a caller's buffer.  The call makes no allocation of any kind
+ * (no hipMalloc/hipFree, no host allocation, no event: launch timing is
+ * off for it) and no synchronisation.
+ *   xyz, natom, aux, orb, d, J  as for df3c_coulomb_J
+ *   status  DEVICE int or NULL: receives the call's device-side status word
+ *           (0 = ok; nonzero: a device-side argument check failed and J is
+ *           unspecified) when the call's kernels have run
+ *   flags   must be 0
+ * Returns DF3C_E_WORKSPACE when df3c_coulomb_J_workspace(aux, orb) exceeds
+ * DF3C_NOALLOC_SCRATCH_BYTES (solid-harmonic orbital shells need the
+ * Cartesian J there too: about 1000 Cartesian AOs at most).  All calls on one
+ * device share its array: calls that overlap on a device (other streams or
+ * threads) race and give wrong results; each call rewrites every part of the
+ * array it reads. */
+#define DF3C_NOALLOC_SCRATCH_BYTES (8u << 20)
+int df3c_coulomb_J_noalloc(const double *xyz, int32_t natom, const df3c_shells *aux,
+                           const df3c_shells *orb, const double *d, double *J, int32_t *status,
+                           uint32_t flags, void *stream);
+
 /* Screening of orbital shell pairs.  The paper's DF-J timings use screening
  * without stating its criterion (Section 4); here the largest primitive
  * overlap bound of a pair,

@@ -23,6 +23,7 @@ constexpr int MAX_DEV = 64;
 struct DevState {
   bool ready = false;
   const double *boys = nullptr;  // the code object's Boys table on this device
+  char *scratch = nullptr;       // this device's copy of the no-allocation workspace
   int ncu = 0;
 };
 DevState g_dev[MAX_DEV];
@@ -43,6 +44,12 @@ bool g_cls_ready = false;
 __device__ double g_boys_table[BOYS_NGRID * BOYS_MTAB] = {
 #include "gen/boys_table.inc"
 };
+
+// Workspace of df3c_coulomb_J_noalloc: one copy per device, held until the
+// process ends.  In host code this name stands for the device array and is no
+// device address: init_device looks up each device's address once (with that
+// device current) and only that address is passed to kernels.
+static __device__ __align__(256) char scratch[DF3C_NOALLOC_SCRATCH_BYTES];
 
 namespace {
 
@@ -140,6 +147,9 @@ int init_device(DevState **out) {
     void *p = nullptr;
     if (hipGetSymbolAddress(&p, HIP_SYMBOL(g_boys_table)) != hipSuccess || !p) return DF3C_E_HIP;
     s.boys = static_cast<const double *>(p);
+    void *q = nullptr;
+    if (hipGetSymbolAddress(&q, HIP_SYMBOL(scratch)) != hipSuccess || !q) return DF3C_E_HIP;
+    s.scratch = static_cast<char *>(q);
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return DF3C_E_HIP;
     s.ncu = prop.multiProcessorCount;
@@ -173,10 +183,14 @@ bool g_timing = false;
 std::vector<TimedLaunch> g_tl;
 size_t g_tl_used = 0;
 
+// set while df3c_coulomb_J_noalloc runs on this thread: its launches are not
+// timed (the event records could create events and grow the record list)
+thread_local bool t_no_alloc = false;
+
 template <class F>
 hipError_t timed(int kind, int cls, hipStream_t s, F &&launch) {
   hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
-  if (!g_timing || hipStreamIsCapturing(s, &cap) != hipSuccess ||
+  if (!g_timing || t_no_alloc || hipStreamIsCapturing(s, &cap) != hipSuccess ||
       cap != hipStreamCaptureStatusNone)
     return launch();
   int dev = 0;
@@ -1194,6 +1208,33 @@ int df3c_coulomb_J(const double *xyz, int32_t natom, const df3c_shells *aux,
   if (!ws || ws_bytes < df3c_coulomb_J_workspace(aux, orb)) return DF3C_E_WORKSPACE;
   return coulomb_J_run(xyz, natom, aux, orb, d, nullptr, J, ws, flags,
                        reinterpret_cast<hipStream_t>(stream));
+}
+
+// status word of a call, copied to a caller's device int (one thread)
+__global__ void k_copy_status(const int *err, int *status) { *status = *err; }
+
+int df3c_coulomb_J_noalloc(const double *xyz, int32_t natom, const df3c_shells *aux,
+                           const df3c_shells *orb, const double *d, double *J, int32_t *status,
+                           uint32_t flags, void *stream) {
+  if (flags) return DF3C_E_ARG;
+  if (!xyz || natom <= 0 || !shells_ok(aux) || !shells_ok(orb) || !d || !J) return DF3C_E_ARG;
+  if ((orb->pure != 0 && orb->pure != 1) || (aux->pure != 0 && aux->pure != 1))
+    return DF3C_E_UNSUPPORTED;
+  if (df3c_coulomb_J_workspace(aux, orb) > DF3C_NOALLOC_SCRATCH_BYTES) return DF3C_E_WORKSPACE;
+  DevState *ds = nullptr;
+  int rc = init_device(&ds);
+  if (rc) return rc;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  t_no_alloc = true;
+  rc = coulomb_J_run(xyz, natom, aux, orb, d, nullptr, J, ds->scratch, DF3C_ASYNC, s);
+  t_no_alloc = false;
+  if (rc) return rc;
+  if (status) {
+    hipLaunchKernelGGL(k_copy_status, dim3(1), dim3(1), 0, s,
+                       reinterpret_cast<const int *>(ds->scratch), status);
+    if (hipGetLastError() != hipSuccess) return DF3C_E_HIP;
+  }
+  return DF3C_OK;
 }
 
 int df3c_screen_pairs(const double *xyz, int32_t natom, const df3c_shells *orb, double tau,
