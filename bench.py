@@ -207,6 +207,21 @@ def dfj_legs(args, df3c, inputs, torch, dev):
             Vm = torch.empty((s.aux.nbf, s.aux.nbf), dtype=torch.float64, device=dev)
             out["metric_ms_water_120atoms"] = _time_ms(
                 torch, lambda: df3c.coulomb_metric(xyz, aux, V=Vm), 3)
+            # the fitting solve d = V^-1 gamma (Cholesky of the n = 10360 metric,
+            # two triangular solves; the timed call includes restoring V, a
+            # 0.86 GB device copy)
+            V0 = Vm.clone()
+            dfit = torch.empty_like(gam)
+            wsf = torch.empty(df3c.lib().df3c_fit_solve_workspace(s.aux.nbf), dtype=torch.uint8,
+                              device=dev)
+
+            def fit():
+                Vm.copy_(V0)
+                df3c.fit_solve(Vm, gam, x=dfit, ws=wsf)
+            out["fit_solve_ms_water_120atoms"] = _time_ms(torch, fit, 2)
+            out["fit_solve_n_water_120atoms"] = s.aux.nbf
+            out["fit_solve_tflops_water_120atoms"] = (s.aux.nbf ** 3 / 3) / (
+                out["fit_solve_ms_water_120atoms"] * 1e-3) / 1e12
             # screened DF-J (pairs kept by the primitive overlap bound >= 1e-12):
             # the screening kernel and the masked J together
             tau = 1e-12

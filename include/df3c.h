@@ -58,6 +58,7 @@ extern "C" {
 #define DF3C_E_UNSUPPORTED (-2)  /* angular momentum or option beyond the build */
 #define DF3C_E_WORKSPACE (-3)    /* workspace missing or too small */
 #define DF3C_E_HIP (-4)          /* a HIP runtime call failed */
+#define DF3C_E_NUMERIC (-5)      /* matrix not positive definite in working precision */
 
 /* Limits of this build. */
 #define DF3C_LMAX_ORB 4  /* orbital shells: s..g */
@@ -161,6 +162,31 @@ size_t df3c_coulomb_J_workspace(const df3c_shells *aux, const df3c_shells *orb);
  * DF3C_ASYNC the call only enqueues kernels and can be captured. */
 int df3c_coulomb_J(const double *xyz, int32_t natom, const df3c_shells *aux,
                    const df3c_shells *orb, const double *d, double *J, void *ws, size_t ws_bytes,
+                   uint32_t flags, void *stream);
+
+/* Bytes of workspace df3c_fit_solve needs (a status word and a scalar). */
+size_t df3c_fit_solve_workspace(int64_t n);
+
+/* The density-fitting solve d = V^{-1} gamma (Introduction: the fitting
+ * equations of the DF-J method; Section 3's DF-J builder takes d as given):
+ * a blocked right-looking Cholesky factorisation V = L L^T in FP64 (64-wide
+ * block columns: diagonal block in LDS, panel by forward substitution per row,
+ * trailing update of the lower triangle in 64 x 64 tiles) and the two
+ * triangular solves.
+ *   V     DEVICE [n][n] row-major, symmetric positive definite (e.g. from
+ *         df3c_coulomb_metric); overwritten: L in its lower triangle and L^T
+ *         in its upper triangle (the diagonal is L's)
+ *   rhs   DEVICE [n] right-hand side (e.g. gamma from df3c_coulomb_gamma)
+ *   x     DEVICE [n] solution (may be rhs)
+ *   ws    DEVICE workspace of df3c_fit_solve_workspace(n) bytes
+ *   flags 0 or DF3C_ASYNC
+ * Conditioning policy: no regularisation; a pivot below DBL_EPSILON times
+ * the largest diagonal element of V (or a non-positive or NaN diagonal) stops
+ * the factorisation and the call returns DF3C_E_NUMERIC (with DF3C_ASYNC,
+ * df3c_workspace_status does).  A basis whose metric passes can still be
+ * ill-conditioned: the solution then carries a relative error of about
+ * cond(V) DBL_EPSILON. */
+int df3c_fit_solve(double *V, int64_t n, const double *rhs, double *x, void *ws, size_t ws_bytes,
                    uint32_t flags, void *stream);
 
 /* For callers that cannot allocate (code under HIP graph capture, tight

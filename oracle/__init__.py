@@ -226,3 +226,15 @@ def coulomb_J_grad(xyz, aux, orb, d, G, atom_mask=None, pair_mask=None, nthreads
                                                  None if pm is None else _ptr(pm),
                                                  _ptr(grad), int(nthreads)), "coulomb_J_grad")
     return grad
+
+
+def fit_coefficients(V, gamma):
+    """d = V^{-1} gamma, the solution of the density-fitting equations V d =
+    gamma (V symmetric positive definite), by its definition: the Cholesky
+    factor V = L L^T and the two triangular solves L y = gamma, L^T d = y
+    (numpy/scipy routines as the steps)."""
+    import scipy.linalg
+    V = np.asarray(V, np.float64)
+    L = np.linalg.cholesky(V)
+    y = scipy.linalg.solve_triangular(L, np.asarray(gamma, np.float64), lower=True)
+    return scipy.linalg.solve_triangular(L.T, y, lower=False)

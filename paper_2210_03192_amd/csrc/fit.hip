@@ -1,0 +1,292 @@
+// The density-fitting solve V d = gamma (the fitting equations whose
+// right-hand side is the adjoint digestion gamma = (P|ab) D and whose matrix is
+// the two-centre metric V = (P|Q)): a blocked right-looking Cholesky
+// factorisation V = L L^T in FP64 followed by the two triangular solves.
+//
+// V is row-major n x n and is overwritten: its lower triangle receives L and
+// its upper triangle L^T (so both solves read rows).  Steps per block column
+// k of width CB:
+//   k_chol_diag    factor the diagonal block in LDS (one workgroup);
+//   k_chol_panel   L21 = A21 L11^{-T}, one thread per row, L11 in LDS, and
+//                  the transposed copy into the upper triangle;
+//   k_chol_update  A22 -= L21 L21^T on the lower triangle, 64 x 64 output tiles
+//                  (256 threads, 4 x 4 outputs each, L21 rows staged in LDS).
+// A pivot below DBL_EPSILON x max_i V_ii (or NaN) stops the factorisation:
+// bit 16 of the status word, and every later kernel does nothing.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cfloat>
+#include <cstdint>
+
+#include "../../include/df3c.h"
+
+namespace df3c {
+namespace {
+
+constexpr int CB = 64;      // block column width
+constexpr int UT = 64;      // output tile of the trailing update
+constexpr int UK = 32;      // k extent staged in LDS per round of the update
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+__global__ void k_fit_init(int *err, double *dmax) {
+  if (threadIdx.x < 8) err[threadIdx.x] = 0;
+  if (threadIdx.x == 0) *dmax = 0.0;
+}
+
+// max_i V_ii (one workgroup, fixed reduction order); a non-positive or NaN
+// diagonal element fails at once
+__global__ void __launch_bounds__(256) k_diag_max(const double *V, int64_t n, double *dmax,
+                                                 int *err) {
+  __shared__ double m[256];
+  double v = 0.0;
+  bool bad = false;
+  for (int64_t i = threadIdx.x; i < n; i += 256) {
+    const double d = V[i * n + i];
+    if (!(d > 0.0)) bad = true;
+    v = fmax(v, d);
+  }
+  m[threadIdx.x] = v;
+  if (bad) atomicOr(err, 16);
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < o) m[threadIdx.x] = fmax(m[threadIdx.x], m[threadIdx.x + o]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *dmax = m[0];
+}
+
+// Cholesky of the nb x nb diagonal block at (k, k), in place (lower)
+__global__ void __launch_bounds__(256) k_chol_diag(double *V, int64_t n, int64_t k, int nb,
+                                                  const double *dmax, int *err) {
+  __shared__ double A[CB][CB + 1];
+  __shared__ int fail;
+  if (*err) return;
+  const int t = threadIdx.x;
+  for (int x = t; x < nb * nb; x += 256) {
+    const int i = x / nb, j = x - i * nb;
+    A[i][j] = j <= i ? V[(k + i) * n + k + j] : 0.0;
+  }
+  if (t == 0) fail = 0;
+  __syncthreads();
+  const double tol = DBL_EPSILON * *dmax;
+  for (int j = 0; j < nb; ++j) {
+    if (t == 0) {
+      const double p = A[j][j];
+      if (!(p > tol)) fail = 1;
+      A[j][j] = sqrt(fmax(p, tol));
+    }
+    __syncthreads();
+    const double piv = A[j][j];
+    for (int i = j + 1 + t; i < nb; i += 256) A[i][j] /= piv;
+    __syncthreads();
+    // rank-1 update of the rest of the block's lower triangle
+    const int m = nb - j - 1;
+    for (int x = t; x < m * m; x += 256) {
+      const int i = j + 1 + x / m, c = j + 1 + x % m;
+      if (c <= i) A[i][c] -= A[i][j] * A[c][j];
+    }
+    __syncthreads();
+  }
+  for (int x = t; x < nb * nb; x += 256) {
+    const int i = x / nb, j = x - i * nb;
+    if (j <= i) {
+      V[(k + i) * n + k + j] = A[i][j];
+      V[(k + j) * n + k + i] = A[i][j];  // L^T in the upper triangle
+    }
+  }
+  if (t == 0 && fail) atomicOr(err, 16);
+}
+
+// rows i >= k + nb: L21[i] = A21[i] L11^{-T} (forward substitution per row)
+__global__ void __launch_bounds__(256) k_chol_panel(double *V, int64_t n, int64_t k, int nb,
+                                                   const int *err) {
+  __shared__ double L[CB][CB + 1];
+  if (*err) return;
+  const int t = threadIdx.x;
+  for (int x = t; x < nb * nb; x += 256) {
+    const int i = x / nb, j = x - i * nb;
+    L[i][j] = j <= i ? V[(k + i) * n + k + j] : 0.0;
+  }
+  __syncthreads();
+  for (int64_t r = k + nb + int64_t(blockIdx.x) * 256 + t; r < n; r += int64_t(gridDim.x) * 256) {
+    double x[CB];
+    double *row = V + r * n + k;
+#pragma unroll
+    for (int j = 0; j < CB; ++j) x[j] = j < nb ? row[j] : 0.0;
+#pragma unroll
+    for (int j = 0; j < CB; ++j) {
+      if (j < nb) {
+        double v = x[j];
+#pragma unroll
+        for (int q = 0; q < j; ++q) v -= x[q] * L[j][q];
+        x[j] = v / L[j][j];
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < CB; ++j)
+      if (j < nb) {
+        row[j] = x[j];
+        V[(k + j) * n + r] = x[j];  // L^T in the upper triangle
+      }
+  }
+}
+
+// A22[i][j] -= sum_q L21[i][q] L21[j][q] for k + nb <= j <= i < n: tiles of
+// the lower triangle, one per workgroup (tile (ti, tj), tj <= ti, from the
+// workgroup index); 256 threads x 4 x 4 outputs; the rows of both tiles are
+// staged UK columns at a time
+__global__ void __launch_bounds__(256) k_chol_update(double *V, int64_t n, int64_t k, int nb,
+                                                    const int *err) {
+  __shared__ double Ri[UT][UK + 1], Rj[UT][UK + 1];
+  if (*err) return;
+  const int64_t b = blockIdx.x;
+  int64_t ti = int64_t((sqrt(8.0 * double(b) + 1.0) - 1.0) * 0.5);
+  while (ti * (ti + 1) / 2 > b) --ti;
+  while ((ti + 1) * (ti + 2) / 2 <= b) ++ti;
+  const int64_t tj = b - ti * (ti + 1) / 2;
+  const int64_t base = k + nb;
+  const int64_t i0 = base + ti * UT, j0 = base + tj * UT;
+  const int t = threadIdx.x, ty = t / 16, tx = t % 16;
+  double acc[4][4] = {};
+  for (int q0 = 0; q0 < nb; q0 += UK) {
+    for (int x = t; x < UT * UK; x += 256) {
+      const int r = x / UK, q = x % UK;
+      const int64_t gi = i0 + r, gj = j0 + r;
+      Ri[r][q] = (gi < n && q0 + q < nb) ? V[gi * n + k + q0 + q] : 0.0;
+      Rj[r][q] = (gj < n && q0 + q < nb) ? V[gj * n + k + q0 + q] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll 4
+    for (int q = 0; q < UK; ++q) {
+      double a[4], c[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        a[u] = Ri[ty + 16 * u][q];
+        c[u] = Rj[tx + 16 * u][q];
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) acc[u][v] += a[u] * c[v];
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int u = 0; u < 4; ++u)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int64_t gi = i0 + ty + 16 * u, gj = j0 + tx + 16 * v;
+      if (gi < n && gj <= gi) V[gi * n + gj] -= acc[u][v];
+    }
+}
+
+// One block of a triangular solve with the rows of V: lower (L y = b,
+// blocks in increasing order, columns 0..k-1 already solved) or upper
+// (L^T x = y, blocks in decreasing order, columns k+nb..n-1 already solved).
+// One workgroup: the block's residual r = b_k - sum over the solved columns
+// (4 lanes per row, fixed-order partial sums), then the nb x nb triangle in
+// order.
+__global__ void __launch_bounds__(256) k_trsv_block(const double *V, int64_t n, int64_t k,
+                                                   int nb, int upper, double *x, const int *err) {
+  __shared__ double part[CB][4];
+  __shared__ double r[CB];
+  __shared__ double D[CB][CB + 1];
+  if (*err) return;
+  const int t = threadIdx.x, row = t / 4, lane = t % 4;
+  for (int e = t; e < nb * nb; e += 256) {
+    const int i = e / nb, j = e - i * nb;
+    D[i][j] = V[(k + i) * n + k + j];
+  }
+  if (row < nb) {
+    const double *vr = V + (k + row) * n;
+    const int64_t c0 = upper ? k + nb : 0, c1 = upper ? n : k;
+    double s = 0.0;
+    for (int64_t c = c0 + lane; c < c1; c += 4) s += vr[c] * x[c];
+    part[row][lane] = s;
+  }
+  __syncthreads();
+  if (t < nb) r[t] = x[k + t] - ((part[t][0] + part[t][1]) + (part[t][2] + part[t][3]));
+  __syncthreads();
+  if (t == 0) {
+    if (!upper) {
+      for (int j = 0; j < nb; ++j) {
+        double v = r[j];
+        for (int q = 0; q < j; ++q) v -= D[j][q] * r[q];
+        r[j] = v / D[j][j];
+      }
+    } else {
+      for (int j = nb - 1; j >= 0; --j) {
+        double v = r[j];
+        for (int q = j + 1; q < nb; ++q) v -= D[j][q] * r[q];
+        r[j] = v / D[j][j];
+      }
+    }
+  }
+  __syncthreads();
+  if (t < nb) x[k + t] = r[t];
+}
+
+__global__ void k_copy_vec(const double *a, double *b, int64_t n, const int *err) {
+  if (*err) return;
+  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
+       i += int64_t(gridDim.x) * blockDim.x)
+    b[i] = a[i];
+}
+
+}  // namespace
+}  // namespace df3c
+
+using namespace df3c;
+
+extern "C" {
+
+size_t df3c_fit_solve_workspace(int64_t n) {
+  (void)n;
+  return align256(sizeof(int) * 8) + align256(sizeof(double));
+}
+
+int df3c_fit_solve(double *V, int64_t n, const double *rhs, double *x, void *ws, size_t ws_bytes,
+                   uint32_t flags, void *stream) {
+  if (flags & ~DF3C_ASYNC) return DF3C_E_ARG;
+  if (n < 0 || (n > 0 && (!V || !rhs || !x))) return DF3C_E_ARG;
+  if (n > (int64_t(1) << 31)) return DF3C_E_UNSUPPORTED;
+  if (!ws || ws_bytes < df3c_fit_solve_workspace(n)) return DF3C_E_WORKSPACE;
+  if (n == 0) return DF3C_OK;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  int *err = static_cast<int *>(ws);
+  double *dmax = reinterpret_cast<double *>(static_cast<char *>(ws) + align256(sizeof(int) * 8));
+  hipLaunchKernelGGL(k_fit_init, dim3(1), dim3(64), 0, s, err, dmax);
+  hipLaunchKernelGGL(k_diag_max, dim3(1), dim3(256), 0, s, V, n, dmax, err);
+  for (int64_t k = 0; k < n; k += CB) {
+    const int nb = int(std::min<int64_t>(CB, n - k));
+    hipLaunchKernelGGL(k_chol_diag, dim3(1), dim3(256), 0, s, V, n, k, nb, dmax, err);
+    const int64_t m = n - k - nb;
+    if (m <= 0) continue;
+    const int gp = int(std::min<int64_t>((m + 255) / 256, 1024));
+    hipLaunchKernelGGL(k_chol_panel, dim3(gp), dim3(256), 0, s, V, n, k, nb, err);
+    const int64_t T = (m + UT - 1) / UT;
+    hipLaunchKernelGGL(k_chol_update, dim3(unsigned(T * (T + 1) / 2)), dim3(256), 0, s, V, n, k,
+                       nb, err);
+  }
+  // x = rhs, then L y = x and L^T x = y in place
+  if (x != rhs)
+    hipLaunchKernelGGL(k_copy_vec, dim3(int(std::min<int64_t>((n + 255) / 256, 1024))), dim3(256),
+                       0, s, rhs, x, n, err);
+  for (int64_t k = 0; k < n; k += CB)
+    hipLaunchKernelGGL(k_trsv_block, dim3(1), dim3(256), 0, s, V, n, k,
+                       int(std::min<int64_t>(CB, n - k)), 0, x, err);
+  for (int64_t k = ((n - 1) / CB) * CB; k >= 0; k -= CB)
+    hipLaunchKernelGGL(k_trsv_block, dim3(1), dim3(256), 0, s, V, n, k,
+                       int(std::min<int64_t>(CB, n - k)), 1, x, err);
+  if (hipGetLastError() != hipSuccess) return DF3C_E_HIP;
+  if (flags & DF3C_ASYNC) return DF3C_OK;
+  int word = 0;
+  if (hipMemcpyAsync(&word, err, sizeof(int), hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess)
+    return DF3C_E_HIP;
+  return word ? DF3C_E_NUMERIC : DF3C_OK;
+}
+
+}  // extern "C"

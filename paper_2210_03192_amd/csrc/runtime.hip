@@ -100,7 +100,8 @@ hipError_t read_back(void *host, const void *dev, size_t n, hipStream_t s) {
 // it back (one synchronisation at the end); with it, the word stays in the
 // workspace for df3c_workspace_status
 int status_of(int word) {
-  if (word & ~2) return DF3C_E_ARG;  // bad index (1), descriptor (4), plan (8)
+  if (word & 16) return DF3C_E_NUMERIC;  // the fitting solve's pivot test
+  if (word & ~2) return DF3C_E_ARG;      // bad index (1), descriptor (4), plan (8)
   return word ? DF3C_E_UNSUPPORTED : DF3C_OK;  // l beyond the build (2)
 }
 int finish_call(uint32_t flags, const int *err, hipStream_t s) {
@@ -421,6 +422,7 @@ const char *df3c_status_string(int status) {
     case DF3C_E_UNSUPPORTED: return "unsupported angular momentum or option";
     case DF3C_E_WORKSPACE: return "workspace missing or too small";
     case DF3C_E_HIP: return "HIP runtime error";
+    case DF3C_E_NUMERIC: return "matrix not positive definite in working precision";
     default: return "unknown status";
   }
 }

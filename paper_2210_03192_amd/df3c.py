@@ -98,6 +98,9 @@ def lib():
         L.df3c_coulomb_gamma_workspace.restype = SZ
         L.df3c_coulomb_gamma_workspace.argtypes = [P, P]
         L.df3c_coulomb_gamma.argtypes = [P, I32, P, P, P, P, P, SZ, U32, P]
+        L.df3c_fit_solve_workspace.restype = SZ
+        L.df3c_fit_solve_workspace.argtypes = [I64]
+        L.df3c_fit_solve.argtypes = [P, I64, P, P, P, SZ, U32, P]
         L.df3c_timing_enable.argtypes = [I32]
         L.df3c_timing_read.restype = I64
         L.df3c_timing_read.argtypes = [P, P, P, I64]
@@ -337,6 +340,31 @@ def coulomb_gamma(xyz: torch.Tensor, aux: DeviceBasis, orb: DeviceBasis, D: torc
                                     ctypes.byref(so), _ptr(D), _ptr(gamma), _ptr(ws), ws.numel(),
                                     flags, _stream(stream)), "df3c_coulomb_gamma")
     return gamma
+
+
+def fit_solve(V: torch.Tensor, rhs: torch.Tensor, x: Optional[torch.Tensor] = None,
+              ws: Optional[torch.Tensor] = None, flags: int = 0, stream=None) -> torch.Tensor:
+    """x = V^{-1} rhs by the library's Cholesky (V is overwritten with L in its
+    lower and L^T in its upper triangle)."""
+    n = int(rhs.shape[0])
+    assert V.is_contiguous() and tuple(V.shape) == (n, n)
+    if x is None:
+        x = torch.empty(n, dtype=torch.float64, device=V.device)
+    need = int(lib().df3c_fit_solve_workspace(n))
+    if ws is None or ws.numel() < need:
+        ws = torch.empty(need, dtype=torch.uint8, device=V.device)
+    _check(lib().df3c_fit_solve(_ptr(V), n, _ptr(rhs), _ptr(x), _ptr(ws), ws.numel(), flags,
+                                _stream(stream)), "df3c_fit_solve")
+    return x
+
+
+def density_fit(xyz: torch.Tensor, aux: DeviceBasis, orb: DeviceBasis, D: torch.Tensor,
+                stream=None) -> torch.Tensor:
+    """d = V^{-1} gamma(D): the fitting coefficients of the density D (gamma =
+    (P|ab) D, V = (P|Q), Cholesky solve), every step in the library."""
+    gamma = coulomb_gamma(xyz, aux, orb, D, stream=stream)
+    V = coulomb_metric(xyz, aux, stream=stream)
+    return fit_solve(V, gamma, x=gamma, stream=stream)
 
 
 class CoulombJ(torch.autograd.Function):
