@@ -225,6 +225,27 @@ int df3c_coulomb_J_noalloc(const double *xyz, int32_t natom, const df3c_shells *
 int df3c_screen_pairs(const double *xyz, int32_t natom, const df3c_shells *orb, double tau,
                       uint8_t *mask, void *stream);
 
+/* Schwarz-type screening with an error guarantee (Section 4 screens the
+ * DF-J runs without stating how; this is the reading of this build).  Every
+ * shell and pair is bounded by positive s-type envelopes (a primitive
+ * component of l quanta by M_l(a) e^{-th a r^2}: th = 1, M_0 = 1 for l = 0;
+ * th = 1/2, M_l = (l / (a e))^{l/2} otherwise), so by the positivity and the
+ * Schwarz inequality of the Coulomb kernel |(ab|P_m)| <= Q_ab Q_P with
+ *   Q_ab = sum_ij |c_i c_j| M(a_i) M(b_j) e^{-mu_ij AB^2} (g|g)_ij^{1/2},
+ *   Q_P  = t_l sum_k |c_k| M(z_k) (g|g)_k^{1/2},
+ * (g|g) = 2 pi^{5/2} / (g^2 (2g)^{1/2}) at the envelope exponents, t_l the
+ * largest row 1-norm of the solid-harmonic table.  A pair is kept when
+ * Q_ab S_d >= tau, S_d = sum_P Q_P sum_m |d_Pm|: every element of a dropped
+ * pair's J block is below tau.
+ *   aux, orb, d  as for df3c_coulomb_J (d DEVICE [naux])
+ *   mask         DEVICE [nshell][nshell] uint8 output (exactly symmetric)
+ *   ws           DEVICE workspace of df3c_screen_pairs_schwarz_workspace() bytes
+ *   flags        0 or DF3C_ASYNC */
+size_t df3c_screen_pairs_schwarz_workspace(void);
+int df3c_screen_pairs_schwarz(const double *xyz, int32_t natom, const df3c_shells *aux,
+                              const df3c_shells *orb, const double *d, double tau, uint8_t *mask,
+                              void *ws, size_t ws_bytes, uint32_t flags, void *stream);
+
 /* Bytes of workspace df3c_coulomb_J_masked needs. */
 size_t df3c_coulomb_J_masked_workspace(const df3c_shells *aux, const df3c_shells *orb);
 

@@ -55,6 +55,8 @@ def _lib(precision="double"):
                                                ctypes.c_int]
         lib.oracle_coulomb_J_grad.argtypes = [P, ctypes.c_int32, P, P, P, P, P, P, P,
                                               ctypes.c_int]
+        lib.oracle_schwarz_bounds.argtypes = [P, P, P, P, P]
+        lib.oracle_screen_pairs_schwarz.argtypes = [P, P, P, P, ctypes.c_double, P, P]
         _LIBS[name] = lib
     return _LIBS[name]
 
@@ -238,3 +240,28 @@ def fit_coefficients(V, gamma):
     L = np.linalg.cholesky(V)
     y = scipy.linalg.solve_triangular(L, np.asarray(gamma, np.float64), lower=True)
     return scipy.linalg.solve_triangular(L.T, y, lower=False)
+
+
+def schwarz_bounds(xyz, aux, orb):
+    """(Qab [nshell x nshell], QP [naux shells]) with |(ab|P_m)| <= Qab QP."""
+    xyz = np.ascontiguousarray(xyz, np.float64)
+    n = len(orb.l)
+    Qab = np.zeros((n, n))
+    QP = np.zeros(len(aux.l))
+    pa, po = _Pinned(aux), _Pinned(orb)
+    _check(_lib().oracle_schwarz_bounds(_ptr(xyz), pa.ref, po.ref, _ptr(Qab), _ptr(QP)),
+           "schwarz_bounds")
+    return Qab, QP
+
+
+def screen_pairs_schwarz(xyz, aux, orb, d, tau):
+    """(mask, S_d): mask = Qab S_d >= tau, S_d = sum_P QP sum_m |d_Pm|."""
+    xyz = np.ascontiguousarray(xyz, np.float64)
+    d = np.ascontiguousarray(d, np.float64)
+    n = len(orb.l)
+    mask = np.zeros((n, n), np.uint8)
+    Sd = np.zeros(1)
+    pa, po = _Pinned(aux), _Pinned(orb)
+    _check(_lib().oracle_screen_pairs_schwarz(_ptr(xyz), pa.ref, po.ref, _ptr(d), float(tau),
+                                              _ptr(mask), _ptr(Sd)), "screen_pairs_schwarz")
+    return mask, float(Sd[0])

@@ -710,6 +710,99 @@ int oracle_screen_pairs(const double *xyz, const oracle_basis *orb, double tau, 
   return 0;
 }
 
+/* Schwarz-type bounds of the 3-center integrals (not in the paper; the
+ * screening reading of this build).  A primitive Cartesian component of l
+ * quanta satisfies |x^i y^j z^k| e^{-a r^2} <= r^l e^{-a r^2}
+ * <= M_l(a) e^{-theta a r^2}, with theta = 1, M_0 = 1 for l = 0 and
+ * theta = 1/2, M_l(a) = (l / (a e))^{l/2} (the maximum of r^l e^{-a r^2 / 2})
+ * for l > 0.  So |phi_a phi_b| is bounded pointwise by a positive sum of
+ * s-type Gaussians, |phi_P| likewise (times t_l = max_m sum_c |T_mc| for a
+ * solid-harmonic shell), and, the Coulomb kernel being positive and positive
+ * definite, |(ab|P_m)| <= (env_ab|env_P) <= Q_ab Q_P with
+ *   Q_ab = sum_ij |c_i c_j| M(a_i) M(b_j) e^{-mu_ij AB^2} sqrt((g|g)_ij),
+ * (g|g) = 2 pi^{5/2} / (gamma^2 sqrt(2 gamma)) the self-repulsion of
+ * e^{-gamma r^2}, gamma and mu from the envelope exponents theta a_i,
+ * theta b_j; Q_P = t_l sum_k |c_k| M(z_k) sqrt((g|g)) with gamma = theta z_k. */
+static double env_m(int l, double a) {
+  return l == 0 ? 1.0 : pow(l / (a * 2.718281828459045235360287), 0.5 * l);
+}
+static double env_theta(int l) { return l == 0 ? 1.0 : 0.5; }
+static double self_rep(double g) {
+  return sqrt(2.0 * 17.493418327624862 / (g * g * sqrt(2.0 * g)));  /* 2 pi^{5/2}: 34.98.. */
+}
+
+int oracle_schwarz_bounds(const double *xyz, const oracle_basis *aux, const oracle_basis *orb,
+                          double *Qab, double *QP) {
+  if (check_basis(aux, LMAX_AUX - 1) || check_basis(orb, LMAX_ORB - 1) || !Qab || !QP) return -1;
+  for (int a = 0; a < orb->nshell; ++a)
+    for (int b = 0; b <= a; ++b) {
+      const double *A = xyz + 3 * orb->atom[a], *B = xyz + 3 * orb->atom[b];
+      const double ab2 = (A[0] - B[0]) * (A[0] - B[0]) + (A[1] - B[1]) * (A[1] - B[1]) +
+                         (A[2] - B[2]) * (A[2] - B[2]);
+      const int la = orb->l[a], lb = orb->l[b];
+      double q = 0.0;
+      for (int i = 0; i < orb->nprim[a]; ++i)
+        for (int j = 0; j < orb->nprim[b]; ++j) {
+          const double za = orb->exps[orb->prim_off[a] + i], zb = orb->exps[orb->prim_off[b] + j];
+          const double ca = orb->coefs[orb->prim_off[a] + i], cb = orb->coefs[orb->prim_off[b] + j];
+          const double ea = env_theta(la) * za, eb = env_theta(lb) * zb, g = ea + eb;
+          q += fabs(ca * cb) * env_m(la, za) * env_m(lb, zb) * exp(-ea * eb / g * ab2) *
+               self_rep(g);
+        }
+      Qab[(int64_t)a * orb->nshell + b] = Qab[(int64_t)b * orb->nshell + a] = q;
+    }
+  for (int p = 0; p < aux->nshell; ++p) {
+    const int l = aux->l[p];
+    double t = 1.0;
+    if (aux->pure) {
+      double T[(2 * LMAX_AUX + 1) * 45];
+      oracle_solid_transform(l, T);
+      const int nc = (l + 1) * (l + 2) / 2;
+      t = 0.0;
+      for (int m = 0; m < 2 * l + 1; ++m) {
+        double r = 0.0;
+        for (int c = 0; c < nc; ++c) r += fabs(T[m * nc + c]);
+        if (r > t) t = r;
+      }
+    }
+    double q = 0.0;
+    for (int k = 0; k < aux->nprim[p]; ++k) {
+      const double z = aux->exps[aux->prim_off[p] + k], c = aux->coefs[aux->prim_off[p] + k];
+      q += fabs(c) * env_m(l, z) * self_rep(env_theta(l) * z);
+    }
+    QP[p] = t * q;
+  }
+  return 0;
+}
+
+/* mask[a][b] = (Q_ab S_d >= tau), S_d = sum_P Q_P sum_m |d_Pm|: the J blocks
+ * of the dropped pairs are bounded by tau element by element. */
+int oracle_screen_pairs_schwarz(const double *xyz, const oracle_basis *aux,
+                                const oracle_basis *orb, const double *d, double tau,
+                                uint8_t *mask, double *Sd) {
+  if (!mask || !d || !(tau >= 0.0)) return -1;
+  const int64_t n = orb->nshell;
+  double *Qab = (double *)malloc(sizeof(double) * (n * n > 0 ? n * n : 1));
+  double *QP = (double *)malloc(sizeof(double) * (aux->nshell > 0 ? aux->nshell : 1));
+  int rc = oracle_schwarz_bounds(xyz, aux, orb, Qab, QP);
+  if (!rc) {
+    double s = 0.0;
+    int64_t off = 0;
+    for (int p = 0; p < aux->nshell; ++p) {
+      const int l = aux->l[p], nf = aux->pure ? 2 * l + 1 : (l + 1) * (l + 2) / 2;
+      double a1 = 0.0;
+      for (int m = 0; m < nf; ++m) a1 += fabs(d[off + m]);
+      off += nf;
+      s += QP[p] * a1;
+    }
+    for (int64_t x = 0; x < n * n; ++x) mask[x] = Qab[x] * s >= tau;
+    if (Sd) *Sd = s;
+  }
+  free(Qab);
+  free(QP);
+  return rc;
+}
+
 int oracle_coulomb_J_pairs(const double *xyz, const oracle_basis *aux, const oracle_basis *orb,
                            const double *d, int64_t npair, const int32_t *pairs,
                            const int64_t *out_off, double *out, int nthreads) {

@@ -71,6 +71,17 @@ int oracle_coulomb_J_masked(const double *xyz, const oracle_basis *aux,
 int oracle_screen_pairs(const double *xyz, const oracle_basis *orb, double tau,
                         uint8_t *mask, double *S);
 
+/* Schwarz-type bounds |(ab|P_m)| <= Qab[a*nshell+b] QP[P] from positive
+ * s-type envelopes of the shells (see oracle.c). */
+int oracle_schwarz_bounds(const double *xyz, const oracle_basis *aux, const oracle_basis *orb,
+                          double *Qab, double *QP);
+
+/* mask[a*nshell+b] = (Qab S_d >= tau) with S_d = sum_P QP sum_m |d_Pm|
+ * (returned in *Sd if non-null): dropped J blocks are bounded by tau. */
+int oracle_screen_pairs_schwarz(const double *xyz, const oracle_basis *aux,
+                                const oracle_basis *orb, const double *d, double tau,
+                                uint8_t *mask, double *Sd);
+
 /* gamma[naux] = sum_{a,b} (P|ab) D_ab over all ordered orbital shell pairs;
  * D is nao x nao row-major (not assumed symmetric).  With orb->pure = 1 the
  * pairs run over real solid-harmonic orbital functions. */

@@ -1239,6 +1239,164 @@ int df3c_coulomb_J_noalloc(const double *xyz, int32_t natom, const df3c_shells *
   return DF3C_OK;
 }
 
+// ---------------------------------------------------------- Schwarz-type screening
+// |(ab|P_m)| <= Q_ab Q_P from positive s-type envelopes of the shells: a
+// primitive Cartesian component of l quanta is bounded by M_l(a) e^{-th a r^2}
+// (th = 1, M_0 = 1 for l = 0; th = 1/2, M_l = (l/(a e))^{l/2} otherwise),
+// and the Coulomb kernel is positive and positive definite, so
+//   Q_ab = sum_ij |c_i c_j| M(a_i) M(b_j) e^{-mu_ij AB^2} sqrt((g|g)_ij),
+//   Q_P  = t_l sum_k |c_k| M(z_k) sqrt((g|g)_k),
+// (g|g) = 2 pi^{5/2} / (g^2 sqrt(2 g)) for the envelope exponents, t_l the
+// largest row 1-norm of the solid-harmonic table (1 for a Cartesian shell).
+// A pair is kept when Q_ab S_d >= tau with S_d = sum_P Q_P sum_m |d_Pm|: the
+// J blocks of the dropped pairs are below tau element by element.
+}  // extern "C"
+namespace {
+__device__ __forceinline__ double env_m(int l, double a) {
+  return l == 0 ? 1.0 : pow(double(l) / (a * 2.718281828459045235360287), 0.5 * l);
+}
+__device__ __forceinline__ double env_theta(int l) { return l == 0 ? 1.0 : 0.5; }
+__device__ __forceinline__ double self_rep(double g) {
+  return sqrt(34.98683665524972497 / (g * g * sqrt(2.0 * g)));
+}
+template <int L>
+__device__ double solid_row_norm() {
+  double t = 0.0;
+  for (int m = 0; m < 2 * L + 1; ++m) {
+    double r = 0.0;
+    for (int q = GenSolid<L>::start[m]; q < GenSolid<L>::start[m + 1]; ++q)
+      r += fabs(GenSolid<L>::val[q]);
+    t = fmax(t, r);
+  }
+  return t;
+}
+__device__ double solid_row_norm_l(int l) {
+  switch (l) {
+    case 0: return solid_row_norm<0>();
+    case 1: return solid_row_norm<1>();
+    case 2: return solid_row_norm<2>();
+    case 3: return solid_row_norm<3>();
+    case 4: return solid_row_norm<4>();
+    case 5: return solid_row_norm<5>();
+    default: return solid_row_norm<6>();
+  }
+}
+
+// S_d = sum_P Q_P sum_m |d_Pm| over the aux shells in shell order (one
+// workgroup: tiles of PLAN_TPB shells, block scan of the function offsets,
+// per-thread partial sums, one fixed-order reduction)
+__global__ void __launch_bounds__(PLAN_TPB)
+    k_schwarz_fit_sum(const int32_t *l, ShellsDev aux, int32_t n, int32_t pure, const double *d,
+                      double *Sd, const int *err) {
+  __shared__ int64_t wsum[PLAN_WAVES];
+  __shared__ double part[PLAN_TPB];
+  if (*err) return;
+  const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
+  int64_t carry = 0;
+  double acc = 0.0;
+  for (int t0 = 0; t0 < n; t0 += PLAN_TPB) {
+    const int s = t0 + tid;
+    const int ls = s < n ? min(max(l[s], 0), DF3C_LMAX_AUX) : 0;
+    const int nf = s < n ? (pure ? 2 * ls + 1 : (ls + 1) * (ls + 2) / 2) : 0;
+    int64_t v = nf;
+    for (int o = 1; o < 64; o <<= 1) {
+      const int64_t a = __shfl_up(v, o);
+      if (lane >= o) v += a;
+    }
+    if (lane == 63) wsum[w] = v;
+    __syncthreads();
+    int64_t b = carry;
+    for (int q = 0; q < w; ++q) b += wsum[q];
+    if (s < n) {
+      const int64_t o0 = b + v - nf;
+      double a1 = 0.0;
+      for (int m = 0; m < nf; ++m) a1 += fabs(d[o0 + m]);
+      double q = 0.0;
+      const int64_t po = aux.prim_off[s];
+      for (int k = 0; k < aux.nprim[s]; ++k)
+        q += fabs(aux.coefs[po + k]) * env_m(ls, aux.exps[po + k]) *
+             self_rep(env_theta(ls) * aux.exps[po + k]);
+      acc += (pure ? solid_row_norm_l(ls) : 1.0) * q * a1;
+    }
+    for (int q = 0; q < PLAN_WAVES; ++q) carry += wsum[q];
+    __syncthreads();
+  }
+  part[tid] = acc;
+  __syncthreads();
+  for (int o = PLAN_TPB / 2; o > 0; o >>= 1) {
+    if (tid < o) part[tid] += part[tid + o];
+    __syncthreads();
+  }
+  if (tid == 0) *Sd = part[0];
+}
+
+__global__ void k_screen_schwarz(const double *xyz, ShellsDev orb, const int32_t *l, int32_t n,
+                                 double tau, const double *Sd, uint8_t *mask, const int *err) {
+  if (*err) return;
+  const double sd = *Sd;
+  const int64_t total = int64_t(n) * n;
+  for (int64_t x = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; x < total;
+       x += int64_t(gridDim.x) * blockDim.x) {
+    const int sa = int(x / n), sb = int(x - int64_t(sa) * n);
+    // the pair's bound from the lower-index shell first: the same arithmetic
+    // for (a, b) and (b, a), so the mask is exactly symmetric
+    const int s1 = sa >= sb ? sa : sb, s2 = sa >= sb ? sb : sa;
+    const int i1 = orb.atom[s1], i2 = orb.atom[s2];
+    const double dx = xyz[3 * i1] - xyz[3 * i2], dy = xyz[3 * i1 + 1] - xyz[3 * i2 + 1],
+                 dz = xyz[3 * i1 + 2] - xyz[3 * i2 + 2];
+    const double ab2 = dx * dx + dy * dy + dz * dz;
+    const int l1 = l[s1], l2 = l[s2];
+    const double *e1 = orb.exps + orb.prim_off[s1], *c1 = orb.coefs + orb.prim_off[s1];
+    const double *e2 = orb.exps + orb.prim_off[s2], *c2 = orb.coefs + orb.prim_off[s2];
+    double q = 0.0;
+    for (int i = 0; i < orb.nprim[s1]; ++i)
+      for (int j = 0; j < orb.nprim[s2]; ++j) {
+        const double ea = env_theta(l1) * e1[i], eb = env_theta(l2) * e2[j], g = ea + eb;
+        q += fabs(c1[i] * c2[j]) * env_m(l1, e1[i]) * env_m(l2, e2[j]) *
+             exp(-ea * eb / g * ab2) * self_rep(g);
+      }
+    mask[x] = q * sd >= tau ? 1 : 0;
+  }
+}
+
+}  // namespace
+extern "C" {
+
+size_t df3c_screen_pairs_schwarz_workspace(void) { return 512; }
+
+int df3c_screen_pairs_schwarz(const double *xyz, int32_t natom, const df3c_shells *aux,
+                              const df3c_shells *orb, const double *d, double tau, uint8_t *mask,
+                              void *ws, size_t ws_bytes, uint32_t flags, void *stream) {
+  if (flags & ~DF3C_ASYNC) return DF3C_E_ARG;
+  if (!xyz || natom <= 0 || !shells_ok(aux) || !shells_ok(orb) || !d || !mask || !(tau >= 0.0))
+    return DF3C_E_ARG;
+  if ((aux->pure != 0 && aux->pure != 1) || (orb->pure != 0 && orb->pure != 1))
+    return DF3C_E_UNSUPPORTED;
+  for (int i = 0; i < aux->nshell; ++i)
+    if (aux->l_host[i] < 0 || aux->l_host[i] > DF3C_LMAX_AUX) return DF3C_E_UNSUPPORTED;
+  for (int i = 0; i < orb->nshell; ++i)
+    if (orb->l_host[i] < 0 || orb->l_host[i] > DF3C_LMAX_ORB) return DF3C_E_UNSUPPORTED;
+  if (!ws || ws_bytes < df3c_screen_pairs_schwarz_workspace()) return DF3C_E_WORKSPACE;
+  DevState *ds = nullptr;
+  int rc = init_device(&ds);
+  if (rc) return rc;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  int *err = static_cast<int *>(ws);
+  double *Sd = reinterpret_cast<double *>(static_cast<char *>(ws) + 256);
+  hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, s, err, 8, 0);
+  check_shells(aux, natom, err, s);
+  check_shells(orb, natom, err, s);
+  hipLaunchKernelGGL(k_schwarz_fit_sum, dim3(1), dim3(PLAN_TPB), 0, s, aux->l, dev_shells(aux),
+                     aux->nshell, aux->pure, d, Sd, err);
+  const int64_t total = int64_t(orb->nshell) * orb->nshell;
+  if (total > 0)
+    hipLaunchKernelGGL(k_screen_schwarz, dim3(int(std::min<int64_t>((total + 255) / 256, 4096))),
+                       dim3(256), 0, s, xyz, dev_shells(orb), orb->l, orb->nshell, tau, Sd, mask,
+                       err);
+  if (hipGetLastError() != hipSuccess) return DF3C_E_HIP;
+  return finish_call(flags, err, s);
+}
+
 int df3c_screen_pairs(const double *xyz, int32_t natom, const df3c_shells *orb, double tau,
                       uint8_t *mask, void *stream) {
   if (!xyz || natom <= 0 || !shells_ok(orb) || !mask || !(tau >= 0.0)) return DF3C_E_ARG;

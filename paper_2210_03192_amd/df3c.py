@@ -80,6 +80,9 @@ def lib():
         L.df3c_coulomb_J_workspace.argtypes = [P, P]
         L.df3c_coulomb_J.argtypes = [P, I32, P, P, P, P, P, SZ, U32, P]
         L.df3c_screen_pairs.argtypes = [P, I32, P, ctypes.c_double, P, P]
+        L.df3c_screen_pairs_schwarz_workspace.restype = SZ
+        L.df3c_screen_pairs_schwarz_workspace.argtypes = []
+        L.df3c_screen_pairs_schwarz.argtypes = [P, I32, P, P, P, ctypes.c_double, P, P, SZ, U32, P]
         L.df3c_coulomb_J_masked_workspace.restype = SZ
         L.df3c_coulomb_J_masked_workspace.argtypes = [P, P]
         L.df3c_coulomb_J_masked.argtypes = [P, I32, P, P, P, P, P, P, SZ, U32, P]
@@ -227,6 +230,24 @@ def screen_pairs(xyz: torch.Tensor, orb: DeviceBasis, tau: float, mask: Optional
     so = orb.struct()
     _check(lib().df3c_screen_pairs(_ptr(xyz), int(xyz.shape[0]), ctypes.byref(so), float(tau),
                                    _ptr(mask), _stream(stream)), "df3c_screen_pairs")
+    return mask
+
+
+def screen_pairs_schwarz(xyz: torch.Tensor, aux: DeviceBasis, orb: DeviceBasis, d: torch.Tensor,
+                         tau: float, mask: Optional[torch.Tensor] = None, flags: int = 0,
+                         stream=None) -> torch.Tensor:
+    """Shell-pair mask with the Schwarz-type error guarantee: 1 where
+    Q_ab S_d >= tau (every element of a dropped pair's J block is below tau)."""
+    n = orb.nshell
+    if mask is None:
+        mask = torch.empty((n, n), dtype=torch.uint8, device=xyz.device)
+    ws = torch.empty(int(lib().df3c_screen_pairs_schwarz_workspace()), dtype=torch.uint8,
+                     device=xyz.device)
+    sa, so = aux.struct(), orb.struct()
+    _check(lib().df3c_screen_pairs_schwarz(_ptr(xyz), int(xyz.shape[0]), ctypes.byref(sa),
+                                           ctypes.byref(so), _ptr(d), float(tau), _ptr(mask),
+                                           _ptr(ws), ws.numel(), flags, _stream(stream)),
+           "df3c_screen_pairs_schwarz")
     return mask
 
 

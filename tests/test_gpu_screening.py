@@ -101,3 +101,50 @@ def test_masked_gradient_vs_oracle():
     ones = torch.ones((orb.nshell, orb.nshell), dtype=torch.uint8, device="cuda")
     assert torch.equal(df3c.coulomb_J_grad_masked(xyz, aux, orb, d, G, ones),
                        df3c.coulomb_J_grad(xyz, aux, orb, d, G))
+
+
+# ---------------------------------------------------------------- Schwarz-type
+@pytest.mark.parametrize("n_w,tau", [(3, 1e-6), (5, 1e-10)])
+def test_schwarz_mask_matches_oracle_and_masked_J(n_w, tau):
+    """The library's Schwarz-type mask equals the oracle's except for pairs
+    whose bound Q_ab S_d lies within 1e-9 (relative) of tau; J over the
+    oracle's mask matches the oracle's masked J at the element bar."""
+    s = inputs.water_cluster(n_w, seed=inputs.SEED_BASE + 430 + n_w)
+    torch, df3c, xyz, aux, orb = _gpu(s)
+    dn = inputs.fitting_coefficients(s.aux.nbf, 431 + n_w)
+    d = torch.as_tensor(dn, device="cuda")
+    m_gpu = df3c.screen_pairs_schwarz(xyz, aux, orb, d, tau).cpu().numpy()
+    m_ref, Sd = oracle.screen_pairs_schwarz(s.xyz, s.aux, s.orb, dn, tau)
+    Qab, _ = oracle.schwarz_bounds(s.xyz, s.aux, s.orb)
+    near = np.abs(Qab * Sd - tau) <= 1e-9 * tau
+    assert np.array_equal(m_gpu, m_gpu.T)
+    assert np.array_equal(m_gpu[~near], m_ref[~near])
+    assert 0 < m_ref.mean() < 1
+    J = df3c.coulomb_J_masked(xyz, aux, orb, d, torch.as_tensor(m_ref, device="cuda"))
+    ref = oracle.coulomb_J_masked(s.xyz, s.aux, s.orb, dn, m_ref)
+    assert_parity(J.cpu().numpy(), ref, what="Schwarz-masked J")
+
+
+def test_schwarz_screened_J_error_below_tau_120_atoms():
+    """120-atom water cluster: every element of a dropped pair's J block is
+    below tau (the guarantee of the criterion), checked on the library's full
+    J; the screened J equals the full J elsewhere to rounding."""
+    s = inputs.dfj_120_system()
+    torch, df3c, xyz, aux, orb = _gpu(s)
+    d = torch.as_tensor(inputs.fitting_coefficients(s.aux.nbf, 1), device="cuda")
+    J = df3c.coulomb_J(xyz, aux, orb, d)
+    for tau in (1e-10, 1e-12):
+        mask = df3c.screen_pairs_schwarz(xyz, aux, orb, d, tau)
+        Jm = df3c.coulomb_J_masked(xyz, aux, orb, d, mask)
+        ao = torch.as_tensor(s.orb.offsets(), device="cuda")
+        # AO-level mask
+        sh = torch.repeat_interleave(torch.arange(s.orb.nshell, device="cuda"),
+                                     (ao[1:] - ao[:-1]).long())
+        keep = mask[sh][:, sh].bool()
+        dropped = float(J[~keep].abs().max()) if (~keep).any() else 0.0
+        kept_dev = float((J - Jm)[keep].abs().max())
+        print(f"tau {tau:g}: kept {float(mask.double().mean()):.3f}, max dropped |J| "
+              f"{dropped:.3g}, kept deviation {kept_dev:.3g}")
+        assert dropped <= tau
+        assert kept_dev <= 1e-13 * float(J.abs().max())
+        assert float(Jm[~keep].abs().max()) == 0.0

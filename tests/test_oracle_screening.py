@@ -10,6 +10,7 @@
 import math
 
 import numpy as np
+import pytest
 
 import oracle
 from paper_2210_03192_amd import inputs
@@ -99,3 +100,68 @@ def test_masked_gradient_is_the_derivative_of_masked_J():
         fd = ((G * oracle.coulomb_J_masked(xp, s.aux, s.orb, d, mask)).sum() -
               (G * oracle.coulomb_J_masked(xm, s.aux, s.orb, d, mask)).sum()) / (2 * h)
         assert abs(g[at, ax] - fd) <= 1e-6 * max(1.0, abs(fd))
+
+
+# ---------------------------------------------------------------- Schwarz-type
+def _random_system(seed, natom=3, kmax=3):
+    from paper_2210_03192_amd.inputs import System, _Builder, _logu, random_atoms
+    rng = np.random.default_rng(seed)
+    xyz = random_atoms(rng, natom, 5.0, 1.2)
+    ob, ab = _Builder(0), _Builder(1)
+    for a in range(natom):
+        for l in range(5):
+            k = int(rng.integers(1, kmax + 1))
+            ob.add(l, a, _logu(rng, 0.05, 60.0, k), rng.uniform(0.1, 1.0, k))
+        for l in range(7):
+            ab.add(l, a, _logu(rng, 0.05, 20.0, 1), [1.0])
+    return System(xyz, ob.build(), ab.build(), "schwarz")
+
+
+@pytest.mark.parametrize("seed", [1, 2, 3])
+def test_schwarz_bound_holds_for_every_integral(seed):
+    """|(ab|P_m)| <= Q_ab Q_P for every triplet of a system with contracted
+    s..g orbital shells and pure s..i aux shells (brute force over the
+    oracle's McMurchie-Davidson integrals)."""
+    s = _random_system(seed)
+    Qab, QP = oracle.schwarz_bounds(s.xyz, s.aux, s.orb)
+    trip = np.array([(P, a, b) for P in range(s.aux.nshell) for a in range(s.orb.nshell)
+                     for b in range(s.orb.nshell)], np.int32)
+    out, off = oracle.eval_batch(s.xyz, s.aux, s.orb, trip)
+    worst = 0.0
+    for (P, a, b), o in zip(trip, off):
+        n = s.aux.nfunc(P) * s.orb.nfunc(a) * s.orb.nfunc(b)
+        m = np.abs(out[o:o + n]).max()
+        worst = max(worst, m / (Qab[a, b] * QP[P]))
+    assert worst <= 1.0 + 1e-12, worst
+
+
+def test_schwarz_bound_exact_for_one_centre_s_functions():
+    """For s functions the envelope is the function itself, so at one centre
+    Q_ab^2 = (ab|ab): with a = b one s primitive (exponent z, coefficient c)
+    and an aux s shell of exponent 2z and coefficient c^2 holding the pair's
+    product, (ab|P) = Q_ab^2; and Q_P^2 = (P|P) from the metric."""
+    from paper_2210_03192_amd.inputs import Basis
+    z, c = 0.7, 1.3
+    xyz = np.zeros((1, 3))
+    orb = Basis(np.array([0], np.int32), np.array([1], np.int32), np.array([0], np.int64),
+                np.array([0], np.int32), np.array([z]), np.array([c]), 0)
+    aux = Basis(np.array([0], np.int32), np.array([1], np.int32), np.array([0], np.int64),
+                np.array([0], np.int32), np.array([2 * z]), np.array([c * c]), 1)
+    Qab, QP = oracle.schwarz_bounds(xyz, aux, orb)
+    blk, _ = oracle.eval_batch(xyz, aux, orb, np.array([[0, 0, 0]], np.int32))
+    assert abs(blk[0] - Qab[0, 0] ** 2) <= 1e-14 * blk[0]
+    V = oracle.coulomb_metric(xyz, aux)
+    assert abs(V[0, 0] - QP[0] ** 2) <= 1e-14 * V[0, 0]
+
+
+def test_schwarz_mask_bounds_the_dropped_J_blocks():
+    """Every J block of a pair the Schwarz mask drops is below tau in every
+    element (the guarantee of the criterion), on a 4-water cluster."""
+    s = inputs.water_cluster(4, seed=inputs.SEED_BASE + 77)
+    d = inputs.fitting_coefficients(s.aux.nbf, 78)
+    tau = 1e-10
+    mask, Sd = oracle.screen_pairs_schwarz(s.xyz, s.aux, s.orb, d, tau)
+    assert 0 < mask.mean() < 1 and np.array_equal(mask, mask.T)
+    J = oracle.coulomb_J(s.xyz, s.aux, s.orb, d)
+    Jm = oracle.coulomb_J_masked(s.xyz, s.aux, s.orb, d, mask)
+    assert np.abs(J - Jm).max() <= tau
