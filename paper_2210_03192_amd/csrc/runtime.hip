@@ -20,11 +20,17 @@ namespace {
 constexpr int NCLS = NLP * NLA * NLA;  // class id = (LP * 5 + la) * 5 + lb
 constexpr int MAX_DEV = 64;
 
+constexpr int NBRANCH = 4;  // concurrent branches of the batched persistent schedule
 struct DevState {
   bool ready = false;
   const double *boys = nullptr;  // the code object's Boys table on this device
   char *scratch = nullptr;       // this device's copy of the no-allocation workspace
   int ncu = 0;
+  // side streams and fork/join events of the batched schedule's branches
+  // (created on first use, default priority)
+  bool branches = false;
+  hipStream_t side[NBRANCH - 1] = {};
+  hipEvent_t fork = nullptr, join[NBRANCH - 1] = {};
 };
 DevState g_dev[MAX_DEV];
 std::mutex g_mu;
@@ -2097,6 +2103,11 @@ int df3c_coulomb_J_batched(const double *xyz, int32_t natom, const df3c_shells *
     (void)hipStreamSynchronize(s);  // copies already queued still read the plan
     return DF3C_E_HIP;
   }
+  // an error after the plan upload waits for its copies before the plan goes
+  auto fail = [&](int r) {
+    (void)hipStreamSynchronize(s);
+    return r;
+  };
   // the descriptors are checked on every call (the kernels read the status
   // word and do nothing when it is set)
   hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, s, err, 8, 0);
@@ -2107,6 +2118,18 @@ int df3c_coulomb_J_batched(const double *xyz, int32_t natom, const df3c_shells *
     return finish_call(flags, err, s);
   }
 
+  if ((flags & DF3C_SCHED_PERSISTENT) && !ds->branches) {
+    std::lock_guard<std::mutex> lk(g_mu);
+    if (!ds->branches) {
+      for (int b = 0; b < NBRANCH - 1; ++b)
+        if (hipStreamCreateWithFlags(&ds->side[b], hipStreamNonBlocking) != hipSuccess ||
+            hipEventCreateWithFlags(&ds->join[b], hipEventDisableTiming) != hipSuccess)
+          return fail(DF3C_E_HIP);
+      if (hipEventCreateWithFlags(&ds->fork, hipEventDisableTiming) != hipSuccess)
+        return fail(DF3C_E_HIP);
+      ds->branches = true;
+    }
+  }
   // class launch order
   std::vector<int> order;
   for (int c = 0; c < NCLS; ++c)
@@ -2144,8 +2167,40 @@ int df3c_coulomb_J_batched(const double *xyz, int32_t natom, const df3c_shells *
     if (flags & DF3C_SCHED_PERSISTENT) {
       hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(256), 0, s, reinterpret_cast<int *>(ctr),
                          2 * NCLS, 0);
+      // Classes of different (l_a, l_b) write disjoint J blocks, so the
+      // (l_a, l_b) groups run on NBRANCH concurrent streams (forked from and
+      // joined back to s, also under capture: the graph gets parallel
+      // branches); inside a group the L_P classes keep the order of `order`,
+      // so every J element sums its classes in the same sequence as the
+      // per-class schedule (bitwise equal).  Groups go to branches longest
+      // first by a work model (items x functions of the class).
+      int branch_of[NLA * NLA];
+      {
+        double gcost[NLA * NLA] = {}, load[NBRANCH] = {};
+        for (int c : order) {
+          const int lp = c / (NLA * NLA), la = (c / NLA) % NLA, lb = c % NLA;
+          gcost[la * NLA + lb] += double(p.cls_items[c]) * (2 * lp + 1) * (la + 1) * (la + 2) *
+                                  (lb + 1) * (lb + 2);
+        }
+        int gid[NLA * NLA];
+        for (int g = 0; g < NLA * NLA; ++g) gid[g] = g;
+        std::stable_sort(gid, gid + NLA * NLA, [&](int x, int y) { return gcost[x] > gcost[y]; });
+        for (int k = 0; k < NLA * NLA; ++k) {
+          const int g = gid[k];
+          int bmin = 0;
+          for (int b = 1; b < NBRANCH; ++b)
+            if (load[b] < load[bmin]) bmin = b;
+          branch_of[g] = bmin;
+          load[bmin] += gcost[g];
+        }
+      }
+      if (hipEventRecord(ds->fork, s) != hipSuccess) return DF3C_E_HIP;
+      for (int b = 0; b < NBRANCH - 1; ++b)
+        if (hipStreamWaitEvent(ds->side[b], ds->fork, 0) != hipSuccess) return DF3C_E_HIP;
       for (int c : order) {
         const int lp = c / (NLA * NLA), la = (c / NLA) % NLA, lb = c % NLA;
+        const int br = branch_of[la * NLA + lb];
+        hipStream_t bs = br == 0 ? s : ds->side[br - 1];
         JQArgs q{};
         q.a = base;
         q.orb_sorted = orb_sorted;
@@ -2162,9 +2217,13 @@ int df3c_coulomb_J_batched(const double *xyz, int32_t natom, const df3c_shells *
         const int64_t need = (q.total + tpw * q.chunk - 1) / (tpw * q.chunk);
         const int grid = int(std::max<int64_t>(
             1, std::min<int64_t>(need, int64_t(ds->ncu) * tt[c].grid_per_cu)));
-        if (timed(DF3C_KERNEL_JQ, c, s, [&] { return ci.jq(q, grid, s); }) != hipSuccess)
+        if (timed(DF3C_KERNEL_JQ, c, bs, [&] { return ci.jq(q, grid, bs); }) != hipSuccess)
           return DF3C_E_HIP;
       }
+      for (int b = 0; b < NBRANCH - 1; ++b)
+        if (hipEventRecord(ds->join[b], ds->side[b]) != hipSuccess ||
+            hipStreamWaitEvent(s, ds->join[b], 0) != hipSuccess)
+          return DF3C_E_HIP;
     } else {
       for (int m = 0; m < nmol; ++m)
         for (int c : order) {
@@ -2197,11 +2256,6 @@ int df3c_coulomb_J_batched(const double *xyz, int32_t natom, const df3c_shells *
     return DF3C_OK;
   };
 
-  // an error after the plan upload waits for its copies before the plan goes
-  auto fail = [&](int r) {
-    (void)hipStreamSynchronize(s);
-    return r;
-  };
   if (!(flags & DF3C_GRAPH)) {
     if ((rc = enqueue())) return fail(rc);
     // the plan's host memory ends with this call: wait for its copies
