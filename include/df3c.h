@@ -63,7 +63,7 @@ extern "C" {
 /* Limits of this build. */
 #define DF3C_LMAX_ORB 4  /* orbital shells: s..g */
 #define DF3C_LMAX_AUX 6  /* auxiliary shells: s..i */
-#define DF3C_LMAX_GRAD_ORB 3  /* orbital shells in df3c_coulomb_J_grad: s..f */
+#define DF3C_LMAX_GRAD_ORB 4  /* orbital shells in df3c_coulomb_J_grad: s..g */
 #define DF3C_KMAX 64          /* primitives per shell */
 
 /* flags */
@@ -299,6 +299,31 @@ int df3c_coulomb_J_grad_masked(const double *xyz, int32_t natom, const df3c_shel
                                const df3c_shells *orb, const double *d, const double *G,
                                const uint8_t *mask, double *grad, void *ws, size_t ws_bytes,
                                uint32_t flags, void *stream);
+
+/* The J gradient for nmol independent molecules in one call (the batched form
+ * of df3c_coulomb_J_grad, matching df3c_coulomb_J_batched's layout).
+ *   mol_orb, mol_aux  HOST [nmol+1] shell ranges per molecule (as for
+ *                     df3c_coulomb_J_batched)
+ *   mol_atom          HOST [nmol+1]: molecule m owns atoms [mol_atom[m],
+ *                     mol_atom[m+1]) and its shells' atom indices must lie there
+ *                     (checked on the device); mol_atom[nmol] = natom
+ *   d                 DEVICE, the molecules' fitting coefficients in aux order
+ *   G                 DEVICE, molecule m's nao_m x nao_m dL/dJ at offset
+ *                     sum_{m' < m} nao_m'^2
+ *   grad              DEVICE [natom][3] output, overwritten
+ *   ws                DEVICE workspace of df3c_coulomb_J_grad_batched_workspace
+ *   flags             0 or DF3C_ASYNC
+ * The molecules run in turn on `stream` through the single-molecule gradient
+ * engines on their own atom ranges (each molecule's rows equal
+ * df3c_coulomb_J_grad of that molecule bitwise). */
+size_t df3c_coulomb_J_grad_batched_workspace(const df3c_shells *aux, const df3c_shells *orb,
+                                             int32_t nmol, const int32_t *mol_orb,
+                                             const int32_t *mol_aux, const int32_t *mol_atom);
+int df3c_coulomb_J_grad_batched(const double *xyz, int32_t natom, const df3c_shells *aux,
+                                const df3c_shells *orb, int32_t nmol, const int32_t *mol_orb,
+                                const int32_t *mol_aux, const int32_t *mol_atom, const double *d,
+                                const double *G, double *grad, void *ws, size_t ws_bytes,
+                                uint32_t flags, void *stream);
 
 /* Per-class schedule parameters of the persistent batched J (written by the
  * project's autotuner).  A table has DF3C_NCLASS entries indexed by

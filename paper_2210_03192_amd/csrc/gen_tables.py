@@ -27,7 +27,7 @@ from fractions import Fraction
 
 LMAX_AUX = 6
 LMAX_ORB = 4
-LMAX_GRAD_ORB = 3
+LMAX_GRAD_ORB = 4
 
 
 def ncart(l):

@@ -41,6 +41,8 @@ struct GradArgs {
   const int64_t *plist;     // optional: indices q of the class's pairs to run
   const int64_t *pcount;    //   (device count of plist), null for all npair
   const int *err;           // device status word: nothing is done when it is non-zero
+  int32_t atom_base;        // subtracted from the shells' atom indices (xyz, the
+                            // atom arrays and partials start at that atom)
 };
 
 // Work items of the gradient kernels: blocks of tpb consecutive shell pairs
@@ -138,7 +140,8 @@ __global__ void __launch_bounds__(64) k_gradr(GradArgs g) {
     const double *ca = g.orb.coefs + (valid ? g.orb.prim_off[sa] : 0);
     const double *eb = g.orb.exps + (valid ? g.orb.prim_off[sb] : 0);
     const double *cb = g.orb.coefs + (valid ? g.orb.prim_off[sb] : 0);
-    const int atA = valid ? g.orb.atom[sa] : 0, atB = valid ? g.orb.atom[sb] : 0;
+    const int atA = valid ? g.orb.atom[sa] - g.atom_base : 0,
+              atB = valid ? g.orb.atom[sb] - g.atom_base : 0;
     double A[3], B[3];
 #pragma unroll
     for (int x = 0; x < 3; ++x) {
@@ -178,7 +181,7 @@ __global__ void __launch_bounds__(64) k_gradr(GradArgs g) {
       const int Kc = g.aux.nprim[sP];
       const double *ec = g.aux.exps + g.aux.prim_off[sP];
       const double *cc = g.aux.coefs + g.aux.prim_off[sP];
-      const int atC = g.aux.atom[sP];
+      const int atC = g.aux.atom[sP] - g.atom_base;
       const double C[3] = {g.xyz[3 * atC], g.xyz[3 * atC + 1], g.xyz[3 * atC + 2]};
       const double *dP = g.d + g.aux_off[sP];
       double dq[NCP];
@@ -485,7 +488,7 @@ __global__ void __launch_bounds__(ENG_TS)
     orient_pair<LA, LB>(g.orb, sa, sb);
     const int Ka = g.orb.nprim[sa], Kb = g.orb.nprim[sb];
     const int64_t oa = g.orb.prim_off[sa], ob = g.orb.prim_off[sb];
-    const int atA = g.orb.atom[sa], atB = g.orb.atom[sb];
+    const int atA = g.orb.atom[sa] - g.atom_base, atB = g.orb.atom[sb] - g.atom_base;
     double Ar[3], Br[3];
     for (int x = 0; x < 3; ++x) {
       Ar[x] = g.xyz[3 * atA + x];
@@ -580,7 +583,7 @@ __global__ void __launch_bounds__(ENG_TS)
         const int sP = g.psh[ip];
         const int Kc = g.aux.nprim[sP];
         const int64_t oc = g.aux.prim_off[sP];
-        const int atC = g.aux.atom[sP];
+        const int atC = g.aux.atom[sP] - g.atom_base;
         const double Cr[3] = {g.xyz[3 * atC], g.xyz[3 * atC + 1], g.xyz[3 * atC + 2]};
         setup_prim<G, 0>(g.boys, prims + lt * REC, p, Kb, Kc, Ar, Br, Cr, AB2, g.orb.exps + oa,
                          g.orb.coefs + oa, g.orb.exps + ob, g.orb.coefs + ob, g.aux.exps + oc,

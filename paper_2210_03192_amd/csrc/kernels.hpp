@@ -338,6 +338,66 @@ __device__ __forceinline__ void split_pair(int q, int grp, int Ka, int Kb, const
   }
 }
 
+// Largest row 1-norm of the solid-harmonic table of l (a constant): a pure
+// function is bounded by it times r^l.
+template <int L>
+constexpr double solid_row_norm() {
+  double t = 0.0;
+  for (int m = 0; m < 2 * L + 1; ++m) {
+    double r = 0.0;
+    for (int q = GenSolid<L>::start[m]; q < GenSolid<L>::start[m + 1]; ++q)
+      r += GenSolid<L>::val[q] < 0 ? -GenSolid<L>::val[q] : GenSolid<L>::val[q];
+    t = r > t ? r : t;
+  }
+  return t;
+}
+
+// Positive s-type envelope of a primitive Cartesian component of l quanta:
+// r^l e^{-z r^2} <= env_m(l, z) e^{-env_theta(l) z r^2} (theta = 1 for l = 0,
+// else 1/2 with env_m = (l / (z e))^{l/2}); self-repulsion root of e^{-g r^2}.
+__device__ __forceinline__ double env_m(int l, double z) {
+  return l == 0 ? 1.0 : pow(double(l) / (z * 2.718281828459045235360287), 0.5 * l);
+}
+__device__ __forceinline__ double env_theta(int l) { return l == 0 ? 1.0 : 0.5; }
+__device__ __forceinline__ double env_self(double g) {
+  return sqrt(34.98683665524972497 / (g * g * sqrt(2.0 * g)));
+}
+
+// Bound on the rounding error a shell pair's group-2 primitive pairs
+// (zeta_a < zeta_b) would carry if their VRR1 quanta stayed on A: the HRR
+// adds sum_k C(LB,k) |AB|^{LB-k} [(LA+k) 0|P], whose terms are bounded by the
+// Schwarz-type envelope bounds (bra: l = LA+k on A, s on B; ket: the aux
+// shell), times the unit roundoff.  One wavefront's lanes take the primitive
+// pairs and sum by a butterfly, so every lane of every wave of a team gets the
+// same value (the decision is uniform over the team).
+template <int LP, int LA, int LB>
+__device__ double split_error_bound(int lane, int Ka, const double *ea, const double *ca, int Kb,
+                                    const double *eb, const double *cb, double AB2, int Kc,
+                                    const double *ec, const double *cc, int pure) {
+  const double R = sqrt(AB2);
+  double s = 0.0;
+  for (int q = lane; q < Ka * Kb; q += 64) {
+    const int i = q / Kb, j = q - i * Kb;
+    const double za = ea[i], zb = eb[j];
+    if (!(za < zb)) continue;
+    double b = 1.0, rp = 1.0;  // C(LB, k), R^{LB-k} built from the top
+    double t = 0.0;
+    for (int k = LB; k >= 0; --k) {
+      const double a1 = env_theta(LA + k) * za, g = a1 + zb;
+      t += b * rp * env_m(LA + k, za) * exp(-a1 * zb / g * AB2) * env_self(g);
+      b = b * double(k) / double(LB - k + 1);
+      rp *= R;
+    }
+    s += fabs(ca[i] * cb[j]) * t;
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+  double qp = 0.0;
+  for (int k = 0; k < Kc; ++k)
+    qp += fabs(cc[k]) * env_m(LP, ec[k]) * env_self(env_theta(LP) * ec[k]);
+  return 1.1102230246251565e-16 * s * qp * (pure ? solid_row_norm<LP>() : 1.0);
+}
+
 template <class G, int WM>
 __device__ __forceinline__ void setup_prim(const double *btab, double *R, int p, int Kb, int Kc,
                                            const double *A, const double *B, const double *C,
@@ -797,7 +857,25 @@ __global__ void __launch_bounds__(TS > 64 ? TS : 64)
       n1 = split_count(1, Ka, Kb, ea, eb);
     }
     const int nab = Ka * Kb;
-    const bool run1 = valid && (!far || n1 > 0), run2 = valid && far && n1 < nab;
+    bool run1 = valid && (!far || n1 > 0), run2 = valid && far && n1 < nab;
+    // a mixed pair whose group 2 is too weak to matter stays in one pass with
+    // the quanta on A: the bound on its HRR rounding lies below 1e-16 (a
+    // thousandth of the absolute floor of the element bar).  Whole-wave teams
+    // only (smaller teams share a wave, whose passes must agree).
+    if constexpr (TS >= 64) {
+      if (run1 && run2) {
+        int lane = tid & 63;
+        __asm__ volatile("" : "+v"(lane));
+        const double ABx = Ar[0] - Br[0], ABy = Ar[1] - Br[1], ABz = Ar[2] - Br[2];
+        const double bound = split_error_bound<LP, LA, LB>(
+            lane, Ka, ea, a.orb.coefs + oa, Kb, eb, a.orb.coefs + ob,
+            ABx * ABx + ABy * ABy + ABz * ABz, Kc, a.aux.exps + oc, a.aux.coefs + oc, a.pure);
+        if (bound < 1e-16) {
+          run2 = false;
+          n1 = nab;
+        }
+      }
+    }
     // the passes are uniform over the workgroup (teams of one wave share
     // barriers); a team without work in a pass runs it over no primitives
     const bool do1 = TS >= 64 ? run1 : wave_any(run1);

@@ -168,7 +168,7 @@ ClassInfo class_info() {
 }
 
 constexpr int NLP = 7, NLA = 5;  // LP <= 6, la, lb <= 4
-constexpr int NLG = 4;           // gradient: la, lb <= 3
+constexpr int NLG = 5;           // gradient: la, lb <= 4
 // filled by inst_lp<LP>.hip
 void register_metric_lp0(MetricInfo (&t)[7]);
 void register_metric_lp1(MetricInfo (&t)[7]);
@@ -228,5 +228,10 @@ void register_grad_lp6(GradInfo (&t)[NLG][NLG]);
     t[3][1] = grad_info<LPV, 3, 1>();                               \
     t[3][2] = grad_info<LPV, 3, 2>();                               \
     t[3][3] = grad_info<LPV, 3, 3>();                               \
+    t[4][0] = grad_info<LPV, 4, 0>();                               \
+    t[4][1] = grad_info<LPV, 4, 1>();                               \
+    t[4][2] = grad_info<LPV, 4, 2>();                               \
+    t[4][3] = grad_info<LPV, 4, 3>();                               \
+    t[4][4] = grad_info<LPV, 4, 4>();                               \
   }                                                                 \
   }

@@ -234,19 +234,20 @@ __global__ void k_zero_f64(double *p, int64_t n) {
 }
 
 // shell descriptors: contraction degree and centre index in range
+// (atom indices in [base, base + natom): a molecule's atoms within a batch)
 __global__ void k_check_shells(const int32_t *nprim, const int64_t *prim_off, const int32_t *atom,
-                               int32_t n, int32_t natom, int *err) {
+                               int32_t n, int32_t natom, int32_t base, int *err) {
   for (int s = blockIdx.x * blockDim.x + threadIdx.x; s < n; s += gridDim.x * blockDim.x)
-    if (nprim[s] < 1 || nprim[s] > DF3C_KMAX || prim_off[s] < 0 || atom[s] < 0 ||
-        atom[s] >= natom)
+    if (nprim[s] < 1 || nprim[s] > DF3C_KMAX || prim_off[s] < 0 || atom[s] < base ||
+        atom[s] - base >= natom)
       atomicOr(err, 4);
 }
 
-void check_shells(const df3c_shells *b, int natom, int *err, hipStream_t s) {
+void check_shells(const df3c_shells *b, int natom, int *err, hipStream_t s, int base = 0) {
   if (b->nshell <= 0) return;
   const int g = std::min((b->nshell + 255) / 256, 1024);
   hipLaunchKernelGGL(k_check_shells, dim3(g), dim3(256), 0, s, b->nprim, b->prim_off, b->atom,
-                     b->nshell, natom, err);
+                     b->nshell, natom, base, err);
 }
 
 // class of every triplet; hist[NCLS] counts (aggregated per workgroup in LDS),
@@ -744,10 +745,10 @@ DevPlan carve_plan(void *ws, int64_t norb, int64_t naux) {
 // lists (pmap / cmap + poff: optional maps of a solid-harmonic orbital basis)
 hipError_t launch_plan(const DevPlan &d, const HostPlan &hp, const df3c_shells *aux,
                        const df3c_shells *orb, int natom, int32_t *pmap, int32_t *cmap,
-                       int64_t *poff, hipStream_t s) {
+                       int64_t *poff, hipStream_t s, int atom_base = 0) {
   hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, s, d.err, 8, 0);
-  check_shells(aux, natom, d.err, s);
-  check_shells(orb, natom, d.err, s);
+  check_shells(aux, natom, d.err, s, atom_base);
+  check_shells(orb, natom, d.err, s, atom_base);
   hipLaunchKernelGGL(k_plan_shells, dim3(1), dim3(PLAN_TPB), 0, s, orb->l, orb->nprim,
                      orb->nshell, DF3C_LMAX_ORB, 1, 0, hp.co, d.orb_sorted, d.ao_off, pmap, cmap,
                      poff, d.err);
@@ -1702,7 +1703,7 @@ namespace {
 // asynchronous like coulomb_J_run (device plan, status word, device counts).
 int grad_run(const double *xyz, int32_t natom, const df3c_shells *aux, const df3c_shells *orb,
              const double *d, const double *G, const uint8_t *mask, double *grad, void *ws,
-             size_t ws_bytes, uint32_t flags, hipStream_t s) {
+             size_t ws_bytes, uint32_t flags, hipStream_t s, int32_t atom_base = 0) {
   DevState *ds = nullptr;
   int rc = init_device(&ds);
   if (rc) return rc;
@@ -1741,7 +1742,7 @@ int grad_run(const double *xyz, int32_t natom, const df3c_shells *aux, const df3
   PullBack pb;
   if (orb->pure) pb = carve_pullback(orb, static_cast<char *>(ws) + core, p.nao);
   if (launch_plan(dp, p, aux, orb, natom, nullptr, orb->pure ? pb.cmap : nullptr,
-                  orb->pure ? pb.poff : nullptr, s) != hipSuccess)
+                  orb->pure ? pb.poff : nullptr, s, atom_base) != hipSuccess)
     return DF3C_E_HIP;
   const int64_t npart = int64_t(nslot) * 3 * natom;
   hipLaunchKernelGGL(k_zero_f64, dim3(int(std::min<int64_t>((npart + 255) / 256, 4096))),
@@ -1764,6 +1765,7 @@ int grad_run(const double *xyz, int32_t natom, const df3c_shells *aux, const df3
   a.natom = natom;
   a.partial = partial;
   a.err = dp.err;
+  a.atom_base = atom_base;
   // masked: compact the kept pairs of every class on the device; launches
   // are sized for the whole class and the kernels read the kept count
   int64_t loff[NLA][NLA] = {};
@@ -1870,6 +1872,108 @@ int df3c_coulomb_J_grad_masked(const double *xyz, int32_t natom, const df3c_shel
                   reinterpret_cast<hipStream_t>(stream));
 }
 
+
+// ------------------------------------------------------- batched J gradient
+namespace {
+__global__ void k_or_status(const int *err, int *acc) {
+  if (threadIdx.x == 0 && *err) atomicOr(acc, *err);
+}
+
+// sub-basis of the shells [s0, s1) (prim_off and atom stay global)
+df3c_shells shell_range(const df3c_shells *b, int s0, int s1) {
+  df3c_shells r = *b;
+  r.nshell = s1 - s0;
+  r.l_host = b->l_host + s0;
+  r.l = b->l + s0;
+  r.nprim = b->nprim + s0;
+  r.prim_off = b->prim_off + s0;
+  r.atom = b->atom + s0;
+  r.nprim_host = b->nprim_host ? b->nprim_host + s0 : nullptr;
+  return r;
+}
+
+bool batch_ranges_ok(int nmol, const int32_t *r, int32_t total) {
+  if (!r || r[0] != 0 || r[nmol] != total) return false;
+  for (int m = 0; m < nmol; ++m)
+    if (r[m + 1] < r[m]) return false;
+  return true;
+}
+}  // namespace
+
+size_t df3c_coulomb_J_grad_batched_workspace(const df3c_shells *aux, const df3c_shells *orb,
+                                             int32_t nmol, const int32_t *mol_orb,
+                                             const int32_t *mol_aux, const int32_t *mol_atom) {
+  if (!shells_ok(aux) || !shells_ok(orb) || nmol <= 0 || !mol_orb || !mol_aux || !mol_atom)
+    return 0;
+  size_t w = 0;
+  for (int m = 0; m < nmol; ++m) {
+    const df3c_shells am = shell_range(aux, mol_aux[m], mol_aux[m + 1]);
+    const df3c_shells om = shell_range(orb, mol_orb[m], mol_orb[m + 1]);
+    w = std::max(w, df3c_coulomb_J_grad_workspace(&am, &om, mol_atom[m + 1] - mol_atom[m]));
+  }
+  return 256 + w;
+}
+
+int df3c_coulomb_J_grad_batched(const double *xyz, int32_t natom, const df3c_shells *aux,
+                                const df3c_shells *orb, int32_t nmol, const int32_t *mol_orb,
+                                const int32_t *mol_aux, const int32_t *mol_atom, const double *d,
+                                const double *G, double *grad, void *ws, size_t ws_bytes,
+                                uint32_t flags, void *stream) {
+  if (flags & ~DF3C_ASYNC) return DF3C_E_ARG;
+  if (!xyz || natom <= 0 || !shells_ok(aux) || !shells_ok(orb) || !d || !G || !grad || nmol <= 0)
+    return DF3C_E_ARG;
+  if ((orb->pure != 0 && orb->pure != 1) || (aux->pure != 0 && aux->pure != 1))
+    return DF3C_E_UNSUPPORTED;
+  if (!batch_ranges_ok(nmol, mol_orb, orb->nshell) || !batch_ranges_ok(nmol, mol_aux, aux->nshell) ||
+      !batch_ranges_ok(nmol, mol_atom, natom))
+    return DF3C_E_ARG;
+  for (int s = 0; s < orb->nshell; ++s)
+    if (orb->l_host[s] < 0 || orb->l_host[s] > DF3C_LMAX_ORB) return DF3C_E_UNSUPPORTED;
+  for (int s = 0; s < aux->nshell; ++s)
+    if (aux->l_host[s] < 0 || aux->l_host[s] > DF3C_LMAX_AUX) return DF3C_E_UNSUPPORTED;
+  const size_t need = df3c_coulomb_J_grad_batched_workspace(aux, orb, nmol, mol_orb, mol_aux,
+                                                            mol_atom);
+  if (!ws || ws_bytes < need) return DF3C_E_WORKSPACE;
+  DevState *ds = nullptr;
+  int rc = init_device(&ds);
+  if (rc) return rc;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  int *status = static_cast<int *>(ws);
+  char *mws = static_cast<char *>(ws) + 256;
+  hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, s, status, 8, 0);
+  // per molecule: its shells, fitting coefficients, G block (molecule m's
+  // nao_m x nao_m matrix at offset sum_{m' < m} nao_m'^2) and atoms; the
+  // gradient engines run on the molecule's own atom range
+  int64_t doff = 0, goff = 0;
+  for (int m = 0; m < nmol; ++m) {
+    const df3c_shells am = shell_range(aux, mol_aux[m], mol_aux[m + 1]);
+    const df3c_shells om = shell_range(orb, mol_orb[m], mol_orb[m + 1]);
+    int64_t naux_m = 0, nao_m = 0;
+    for (int q = 0; q < am.nshell; ++q) {
+      const int l = am.l_host[q];
+      naux_m += aux->pure ? 2 * l + 1 : (l + 1) * (l + 2) / 2;
+    }
+    for (int q = 0; q < om.nshell; ++q) {
+      const int l = om.l_host[q];
+      nao_m += orb->pure ? 2 * l + 1 : (l + 1) * (l + 2) / 2;
+    }
+    const int a0 = mol_atom[m], na = mol_atom[m + 1] - mol_atom[m];
+    if (na > 0) {
+      rc = grad_run(xyz + 3 * int64_t(a0), na, &am, &om, d + doff, G + goff, nullptr,
+                    grad + 3 * int64_t(a0), mws, ws_bytes - 256, DF3C_ASYNC, s, a0);
+      if (rc) {
+        (void)hipStreamSynchronize(s);
+        return rc;
+      }
+      hipLaunchKernelGGL(k_or_status, dim3(1), dim3(64), 0, s, reinterpret_cast<const int *>(mws),
+                         status);
+    }
+    doff += naux_m;
+    goff += nao_m * nao_m;
+  }
+  if (hipGetLastError() != hipSuccess) return DF3C_E_HIP;
+  return finish_call(flags, status, s);
+}
 
 // --------------------------------------------------------------- batched DF-J
 namespace {

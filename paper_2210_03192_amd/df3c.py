@@ -92,6 +92,10 @@ def lib():
         L.df3c_coulomb_J_grad_masked_workspace.restype = SZ
         L.df3c_coulomb_J_grad_masked_workspace.argtypes = [P, P, I32]
         L.df3c_coulomb_J_grad_masked.argtypes = [P, I32, P, P, P, P, P, P, P, SZ, U32, P]
+        L.df3c_coulomb_J_grad_batched_workspace.restype = SZ
+        L.df3c_coulomb_J_grad_batched_workspace.argtypes = [P, P, I32, P, P, P]
+        L.df3c_coulomb_J_grad_batched.argtypes = [P, I32, P, P, I32, P, P, P, P, P, P, P, SZ,
+                                                  U32, P]
         L.df3c_coulomb_J_batched_workspace.restype = SZ
         L.df3c_coulomb_J_batched_workspace.argtypes = [P, P, I32]
         L.df3c_coulomb_J_batched.argtypes = [P, I32, P, P, I32, P, P, P, P, P, P, SZ, U32, P]
@@ -475,3 +479,34 @@ def timing_read(cap: int = 65536):
     if n > cap:
         raise DF3CError(f"df3c_timing_read: {n} launches recorded, only {cap} could be read")
     return [(int(kind[i]), int(cls[i]), float(ms[i])) for i in range(n)]
+
+
+def coulomb_J_grad_batched(xyz: torch.Tensor, aux: DeviceBasis, orb: DeviceBasis,
+                           mol_orb: np.ndarray, mol_aux: np.ndarray, mol_atom: np.ndarray,
+                           d: torch.Tensor, G: torch.Tensor, grad: Optional[torch.Tensor] = None,
+                           ws: Optional[torch.Tensor] = None, flags: int = 0,
+                           stream=None) -> torch.Tensor:
+    """dL/dR [natom][3] of L = sum_m sum_ab G^m_ab J^m_ab over nmol molecules
+    (G: the molecules' nao_m x nao_m blocks back to back, as coulomb_J_batched
+    returns J)."""
+    mol_orb = np.ascontiguousarray(mol_orb, np.int32)
+    mol_aux = np.ascontiguousarray(mol_aux, np.int32)
+    mol_atom = np.ascontiguousarray(mol_atom, np.int32)
+    nmol = len(mol_orb) - 1
+    natom = int(xyz.shape[0])
+    if grad is None:
+        grad = torch.empty((natom, 3), dtype=torch.float64, device=xyz.device)
+    sa, so = aux.struct(), orb.struct()
+    need = int(lib().df3c_coulomb_J_grad_batched_workspace(
+        ctypes.byref(sa), ctypes.byref(so), nmol, mol_orb.ctypes.data, mol_aux.ctypes.data,
+        mol_atom.ctypes.data))
+    if need == 0:
+        raise DF3CError("df3c_coulomb_J_grad_batched_workspace: bad arguments")
+    if ws is None or ws.numel() < need:
+        ws = torch.empty(need, dtype=torch.uint8, device=xyz.device)
+    _check(lib().df3c_coulomb_J_grad_batched(_ptr(xyz), natom, ctypes.byref(sa), ctypes.byref(so),
+                                             nmol, mol_orb.ctypes.data, mol_aux.ctypes.data,
+                                             mol_atom.ctypes.data, _ptr(d), _ptr(G.contiguous()),
+                                             _ptr(grad), _ptr(ws), ws.numel(), flags,
+                                             _stream(stream)), "df3c_coulomb_J_grad_batched")
+    return grad

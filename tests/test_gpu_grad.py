@@ -145,3 +145,66 @@ def test_grad_60_atoms_vs_oracle_rows():
     err = np.abs(g[atoms] - ref).max() / np.abs(ref).max()
     print(f"60-atom gradient vs oracle rows of atoms {atoms.tolist()}: {err:.3g}")
     assert err <= 1e-10, err
+
+
+@pytest.mark.parametrize("which", ["s_to_g", "contracted_s_to_g"])
+def test_grad_g_orbital_shells_vs_oracle(which):
+    """Orbital shells up to g (the raised bra reaches h): the gradient against
+    the oracle's explicit three-centre gradient to 1e-10 of its max norm, and
+    zero net force."""
+    torch = _torch()
+    from tests.test_gpu_j_engines import _contracted_system, _system
+    if which == "s_to_g":
+        s = _system(inputs.SEED_BASE + 57, range(7), 1)
+    else:
+        s = _contracted_system(inputs.SEED_BASE + 58)
+    d = inputs.fitting_coefficients(s.aux.nbf, 59)
+    G = inputs.symmetric_density(s.orb.nbf, 60)
+    G[1, 4] -= 0.29  # not symmetric
+    ref = oracle.coulomb_J_grad(s.xyz, s.aux, s.orb, d, G)
+    df3c, xyz, aux, orb = _dev(s)
+    g = df3c.coulomb_J_grad(xyz, aux, orb, torch.as_tensor(d, device="cuda"),
+                            torch.as_tensor(G, device="cuda")).cpu().numpy()
+    err = _rel_inf(g, ref)
+    print(f"g-shell gradient ({which}): {err:.3g}")
+    assert err <= 1e-10, err
+    assert np.abs(g.sum(0)).max() <= 1e-10 * np.abs(g).max()
+
+
+def test_grad_batched_molecules():
+    """Four molecules of uneven size in one call: every molecule's gradient
+    rows equal its single-molecule gradient bitwise, the smallest two match the
+    oracle to 1e-10, and a shell whose atom lies outside its molecule's range
+    is rejected."""
+    torch = _torch()
+    from paper_2210_03192_amd import df3c
+    systems = [inputs.water_cluster(n, seed=inputs.SEED_BASE + 60 + n) for n in (3, 1, 5, 2)]
+    b = inputs.concat_systems(systems)
+    mol_atom = np.concatenate([[0], np.cumsum([len(s.xyz) for s in systems])]).astype(np.int32)
+    d = inputs.fitting_coefficients(b.aux.nbf, 61)
+    Gs = [inputs.symmetric_density(s.orb.nbf, 62 + k) for k, s in enumerate(systems)]
+    Gflat = np.concatenate([g.ravel() for g in Gs])
+    xyz = torch.as_tensor(b.xyz, device="cuda")
+    aux = df3c.DeviceBasis.from_basis(b.aux)
+    orb = df3c.DeviceBasis.from_basis(b.orb)
+    g = df3c.coulomb_J_grad_batched(xyz, aux, orb, b.mol_orb, b.mol_aux, mol_atom,
+                                    torch.as_tensor(d, device="cuda"),
+                                    torch.as_tensor(Gflat, device="cuda")).cpu().numpy()
+    po = b.aux.offsets()
+    for m, s in enumerate(systems):
+        dm = d[po[b.mol_aux[m]]:po[b.mol_aux[m + 1]]]
+        df, sx, sa, so = _dev(s)
+        single = df.coulomb_J_grad(sx, sa, so, torch.as_tensor(dm, device="cuda"),
+                                   torch.as_tensor(Gs[m], device="cuda")).cpu().numpy()
+        rows = g[mol_atom[m]:mol_atom[m + 1]]
+        assert np.array_equal(rows, single), m
+        if len(s.xyz) <= 6:
+            ref = oracle.coulomb_J_grad(s.xyz, s.aux, s.orb, dm, Gs[m])
+            assert _rel_inf(rows, ref) <= 1e-10, m
+    # molecule ranges that cut a molecule's shells off their atoms
+    bad = mol_atom.copy()
+    bad[1] -= 1
+    with pytest.raises(df3c.DF3CError):
+        df3c.coulomb_J_grad_batched(xyz, aux, orb, b.mol_orb, b.mol_aux, bad,
+                                    torch.as_tensor(d, device="cuda"),
+                                    torch.as_tensor(Gflat, device="cuda"))
