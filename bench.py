@@ -118,6 +118,12 @@ def parse():
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-dfj", action="store_true")
     p.add_argument("--batched-nmol", type=int, default=64)
+    p.add_argument("--dfj-only", default="",
+                   help="profiling runs: only these DF-J legs (comma list of j120, gamma120, "
+                        "grad60), no batched leg")
+    p.add_argument("--only", default="",
+                   help="profiling runs: only these per-class batches (comma list such as "
+                        "P6a4b4K6); the printed line then covers that subset (config.subset)")
     p.add_argument("--copy-calibration-mib", type=int, default=0,
                    help="first run a plain device copy of this many MiB three times "
                         "(the reference kernel for hardware byte counters)")
@@ -166,8 +172,12 @@ def dfj_legs(args, df3c, inputs, torch, dev):
     uneven water clusters (per-class launches vs the tuned persistent queue in a
     HIP graph), and the J gradient."""
     out = {}
+    legs = set(x for x in args.dfj_only.split(",") if x)
+    want = lambda leg: not legs or leg in legs  # noqa: E731
     for name, sysf in (("plain_8atoms", inputs.plain_dfj_system),
                        ("water_120atoms", inputs.dfj_120_system)):
+        if legs and not (name == "water_120atoms" and (legs & {"j120", "gamma120"})):
+            continue
         s = sysf()
         d = torch.as_tensor(inputs.fitting_coefficients(s.aux.nbf, 1), device=dev)
         xyz = torch.as_tensor(s.xyz, device=dev)
@@ -175,8 +185,15 @@ def dfj_legs(args, df3c, inputs, torch, dev):
         orb = df3c.DeviceBasis.from_basis(s.orb, dev)
         J = torch.empty((s.orb.nbf, s.orb.nbf), dtype=torch.float64, device=dev)
         wsj = torch.empty(df3c.coulomb_J_workspace(aux, orb), dtype=torch.uint8, device=dev)
-        out[f"dfj_ms_{name}"] = _time_ms(torch, lambda: df3c.coulomb_J(xyz, aux, orb, d, J=J,
-                                                                        ws=wsj), 3)
+        if want("j120"):
+            out[f"dfj_ms_{name}"] = _time_ms(torch, lambda: df3c.coulomb_J(xyz, aux, orb, d, J=J,
+                                                                            ws=wsj), 3)
+        if legs:
+            if "gamma120" in legs:
+                D = torch.as_tensor(inputs.symmetric_density(s.orb.nbf, 2), device=dev)
+                out["gamma_ms_water_120atoms"] = _time_ms(
+                    torch, lambda: df3c.coulomb_gamma(xyz, aux, orb, D), 2)
+            continue
         mf = system_model_flop(s.aux, s.orb)
         out[f"dfj_model_frac_{name}"] = mf / (out[f"dfj_ms_{name}"] * 1e-3) / PEAK_FP64
         if name == "plain_8atoms":
@@ -257,6 +274,8 @@ def dfj_legs(args, df3c, inputs, torch, dev):
             out["dfj_ms_water_120atoms_pure_orbitals"] = _time_ms(
                 torch, lambda: df3c.coulomb_J(xyz, aux, orbp, d, J=Jp, ws=wsp), 3)
             out["dfj_pure_orbitals_nao"] = sp.nbf
+    if legs and "grad60" not in legs:
+        return out
     # J gradient, 60 atoms
     s = inputs.grad_60_system()
     d = torch.as_tensor(inputs.fitting_coefficients(s.aux.nbf, 5), device=dev)
@@ -264,6 +283,10 @@ def dfj_legs(args, df3c, inputs, torch, dev):
     xyz = torch.as_tensor(s.xyz, device=dev)
     aux = df3c.DeviceBasis.from_basis(s.aux, dev)
     orb = df3c.DeviceBasis.from_basis(s.orb, dev)
+    if legs:
+        out["grad_ms_water_60atoms"] = _time_ms(
+            torch, lambda: df3c.coulomb_J_grad(xyz, aux, orb, d, G), 1)
+        return out
     out["dfj_ms_water_60atoms"] = _time_ms(torch, lambda: df3c.coulomb_J(xyz, aux, orb, d), 2)
     out["grad_ms_water_60atoms"] = _time_ms(
         torch, lambda: df3c.coulomb_J_grad(xyz, aux, orb, d, G), 1)
@@ -351,8 +374,11 @@ def main():
 
     batches, gpu = {}, {}
     maxout = 0
+    only = set(x for x in args.only.split(",") if x)
     for cls in inputs.PER_CLASS_CLASSES:
         for K in inputs.PER_CLASS_K:
+            if only and f"P{cls[0]}a{cls[1]}b{cls[2]}K{K}" not in only:
+                continue
             cb = inputs.class_batch(*cls, K, args.ntrip)
             batches[(cls, K)] = cb
             gpu[(cls, K)] = dict(
@@ -439,7 +465,8 @@ def main():
            "data": "synthetic",
            "config": {"workload": "per-class batches: 1e5 triplets x (L_P,l_a,l_b) in "
                                   "{(0,0,0),(2,1,1),(4,2,2),(6,3,3),(6,4,4)} x K_a=K_b in {1,3,6}",
-                      "ntrip_per_batch": args.ntrip, "integrals_per_step": nint},
+                      "ntrip_per_batch": args.ntrip, "integrals_per_step": nint,
+                      **({"subset": args.only} if args.only else {})},
            "roofline": roof, "per_class": per_class, **extra}
     if not args.no_cpu_baseline:
         rec["cpu_baseline"] = cpu_baseline(batches)
