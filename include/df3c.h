@@ -96,7 +96,8 @@ typedef struct {
   const int32_t *atom;     /* DEVICE [nshell] index of the shell's centre in xyz */
   const double *exps;      /* DEVICE primitive exponents (> 0) */
   const double *coefs;     /* DEVICE contraction coefficients (normalised) */
-  int32_t pure;            /* aux: 1 solid-harmonic (0 allowed only for l <= 1);
+  int32_t pure;            /* aux: 1 solid-harmonic; 0 Cartesian (every l in
+                              df3c_eval_batch, l <= 1 in the other calls);
                               orbital: 0 Cartesian; 1 solid-harmonic, accepted by
                               df3c_coulomb_J, df3c_coulomb_J_grad (and their
                               masked forms) and df3c_coulomb_gamma */
@@ -134,6 +135,11 @@ size_t df3c_eval_batch_workspace(int64_t ntrip);
  *   out      DEVICE output; block t is npure(l_P) x ncart(l_a) x ncart(l_b)
  *            (ncart(l_P) for a Cartesian aux basis) at out + out_off[t]
  *   ws       DEVICE workspace of at least df3c_eval_batch_workspace(ntrip) bytes
+ * A Cartesian aux shell of l >= 2 keeps the ket term that the paper's VRR2
+ * drops (Eq. vrr2 is exact for solid-harmonic kets only, Section 2.2): its
+ * block is the class-l block plus the lower-degree terms l - 2, l - 4, ...
+ * of the Cartesian-to-Hermite expansion, each from one more launch of class
+ * l - 2k with a modified Boys sequence, added in stream order.
  * Shell indices in trip are checked on the device.  Without DF3C_ASYNC the
  * call synchronises `stream` once to read the class counts, which size one
  * launch per class present.  With DF3C_ASYNC nothing is read back: every

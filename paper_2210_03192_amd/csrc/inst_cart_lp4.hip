@@ -1,0 +1,4 @@
+// Store kernels with a Cartesian ket for the classes with an auxiliary shell
+// of l = 4 (aux pure = 0; one translation unit per l).
+#include "registry.hpp"
+DF3C_REGISTER_CART_LP(4, register_cart_lp4)

@@ -28,10 +28,12 @@ struct StoreArgs {
   double *out;
   const uint32_t *bucket;   // triplet ids of this class; bit 31: a and b swapped
   int64_t count;
-  int32_t pure;             // ket solid-harmonic (1) or Cartesian (0, LP <= 1)
+  int32_t pure;             // ket solid-harmonic (1) or Cartesian (0)
   const int *err;           // device status word: nothing is done when it is non-zero
   const int *dcount;        // optional device count and bucket offset of the class
   const int *dstart;        //   (replace count and shift bucket; asynchronous calls)
+  int32_t cexp;             // Cartesian ket of l = LP + 2 cexp: this launch adds its
+                            //   degree-LP term (0: the plain block of the class)
 };
 
 struct JArgs {
@@ -74,13 +76,16 @@ constexpr int AREC = AR_DQ + 28;  // doubles per record (d' of l <= 6)
 //                                 the target (e0|c) ([c][e''])
 //   EM   (e0|P) [m][e'']          in the dead tail of pi, else after everything
 //   STG  output staging          at 0 (dead pi_0) when EM starts beyond it, else extra
-template <int LP, int LA, int LB, int PCH>
+template <int LP, int LA, int LB, int PCH, bool CART = false>
 struct Layout {
   using G = Geo<LP, LA, LA + LB>;
+  // ket rows of the transformed block: solid harmonics, or every Cartesian
+  // component for a Cartesian aux shell (CART)
+  static constexpr int NKET = CART ? G::NCP : G::NPURE;
   static constexpr int REC = PS_N + G::NV1 + G::NSW;
   static constexpr int NEC = G::NCP * G::NE;
-  static constexpr int NEM = G::NPURE * G::NE;
-  static constexpr int NOUT = G::NPURE * ncart(LA) * ncart(LB);
+  static constexpr int NEM = NKET * G::NE;
+  static constexpr int NOUT = NKET * ncart(LA) * ncart(LB);
   static constexpr int PI = 0;
   // the primitive records live only during the primitive loop, pi is written
   // to LDS only after it: the two share the start of the slice
@@ -205,6 +210,11 @@ struct Cfg {
   static constexpr int STORE_TEAM =
       imax(Layout<LP, LA, LB, PCH>::TOTAL, LA > LB ? Layout<LP, LB, LA, PCH>::TOTAL : 0) | 1;
   static constexpr int STORE_LDS = (BLK / TS) * STORE_TEAM * 8;
+  // the same for the Cartesian-ket instantiation (aux shells with pure = 0)
+  static constexpr int STORE_TEAM_C =
+      imax(Layout<LP, LA, LB, PCH, true>::TOTAL,
+           LA > LB ? Layout<LP, LB, LA, PCH, true>::TOTAL : 0) | 1;
+  static constexpr int STORE_LDS_C = (BLK / TS) * STORE_TEAM_C * 8;
   // minimum waves per SIMD requested from the register allocator
   static constexpr int WPE = TS >= 128 ? DF3C_MIN_WAVES_BIG : TS == 64 ? DF3C_MIN_WAVES_WAVE : 1;
   // J kernels: one lane per shell pair on the register engine, else the J
@@ -222,6 +232,7 @@ struct Cfg {
                                                                     : DF3C_MIN_WAVES_WAVE;
   static_assert(LDS <= 160 * 1024, "class does not fit the LDS of a CU");
   static_assert(STORE_LDS <= 160 * 1024, "class does not fit the LDS of a CU");
+  static_assert(STORE_LDS_C <= 160 * 1024, "class does not fit the LDS of a CU");
 };
 
 // ---------------------------------------------------------------------------
@@ -404,7 +415,7 @@ __device__ __forceinline__ void setup_prim(const double *btab, double *R, int p,
                                            double AB2, const double *ea, const double *ca,
                                            const double *eb, const double *cb,
                                            const double *ec, const double *cc, int grp = 0,
-                                           int Ka = 0) {
+                                           int Ka = 0, int cs = 0) {
   constexpr int LP = G::LP, L = G::L;
   {
     const int ic = p % Kc, rest = p / Kc;
@@ -424,7 +435,26 @@ __device__ __forceinline__ void setup_prim(const double *btab, double *R, int p,
     if constexpr (WM == 1) pre *= 2.0 * za;
     if constexpr (WM == 2) pre *= 2.0 * zb;
     double Fm[L + 1];
-    boys<LP, L + 1>(btab, T, Fm);
+    if (LP + L + 3 > BOYS_MTOP_MAX || cs == 0) {
+      boys<LP, L + 1>(btab, T, Fm);
+    } else if constexpr (LP + L + 3 <= BOYS_MTOP_MAX) {
+      // degree-LP term of a Cartesian ket of l = LP + 2 cs (cs <= 3): the
+      // Boys values become F'_m = (4 zc)^{-cs} sum_j C(cs, j) (-rho/zc)^j F_{m+j}
+      double Fx[L + 4];
+      boys<LP, L + 4>(btab, T, Fx);
+      const double q = -rho / zc;
+      double sc = 1.0;
+      for (int k = 0; k < cs; ++k) sc *= 0.25 / zc;
+#pragma unroll
+      for (int mm = 0; mm <= L; ++mm) {
+        double acc = Fx[mm], bq = 1.0;
+        for (int j = 1; j <= cs; ++j) {
+          bq *= q * double(cs - j + 1) / double(j);
+          acc += bq * Fx[mm + j];
+        }
+        Fm[mm] = sc * acc;
+      }
+    }
     R[PS_PAX] = Px - A[0];
     R[PS_PAY] = Py - A[1];
     R[PS_PAZ] = Pz - A[2];
@@ -469,10 +499,10 @@ __device__ __forceinline__ void setup_chunk(const double *btab, double *prims, i
                                             const double *ea, const double *ca,
                                             const double *eb, const double *cb,
                                             const double *ec, const double *cc, int grp = 0,
-                                            int Ka = 0) {
+                                            int Ka = 0, int cs = 0) {
   for (int pp = lt; pp < npc; pp += TS)
     setup_prim<G, WM>(btab, prims + pp * REC, p0 + pp, Kb, Kc, A, B, C, AB2, ea, ca, eb, cb, ec,
-                      cc, grp, Ka);
+                      cc, grp, Ka, cs);
 }
 
 // ---------------------------------------------------------------------------
@@ -480,16 +510,16 @@ __device__ __forceinline__ void setup_chunk(const double *btab, double *prims, i
 // ---------------------------------------------------------------------------
 // WM selects the contraction weights (see setup_chunk).  slot is the per-lane
 // prerequisite map of make_slots, or nullptr to decode it inline.
-template <int LP, int LA, int LB, int TS, int PCH, int WM = 0>
+template <int LP, int LA, int LB, int TS, int PCH, int WM = 0, bool CART = false>
 __device__ __forceinline__ void triplet_to_e0P(const double *btab, double *S, int tid,
                                                const int *slot, int npmax, const double *A,
                                                const double *B, const double *C, int Ka,
                                                const double *ea, const double *ca, int Kb,
                                                const double *eb, const double *cb, int Kc,
                                                const double *ec, const double *cc, int pure,
-                                               int grp = 0) {
+                                               int grp = 0, int cs = 0) {
   using G = Geo<LP, LA, LA + LB>;
-  using LY = Layout<LP, LA, LB, PCH>;
+  using LY = Layout<LP, LA, LB, PCH, CART>;
   using TB = GenTab<LP, G::EA, G::EB>;
   static_assert(TB::NPI == G::NPI && TB::NTGT == G::NE * G::NCP, "generated tables out of date");
   constexpr int L = G::L;
@@ -524,7 +554,7 @@ __device__ __forceinline__ void triplet_to_e0P(const double *btab, double *S, in
     int lt = tid;
     __asm__ volatile("" : "+v"(lt));
     setup_chunk<G, TS, REC, WM>(btab, prims, lt, p0, npc, Kb, Kc, A, B, C, AB2, ea, ca, eb, cb, ec,
-                                cc, grp, Ka);
+                                cc, grp, Ka, cs);
     team_sync();
     // ---- VRR1, 2-quantal stages in place
     vrr1<G, TS, PCH, REC>(prims, npc, lt);
@@ -752,11 +782,11 @@ __device__ __forceinline__ void hrr_nq(const double *EMm, int a, const double *p
 
 // HRR of the whole block into the staging area STG: [m][a][b] (or [m][b][a]
 // when the triplet's a and b were swapped to orient the transfer).
-template <int LP, int LA, int LB, int TS, int PCH>
+template <int LP, int LA, int LB, int TS, int PCH, bool CART = false>
 __device__ __forceinline__ void hrr_block(double *S, int tid, const double *A, const double *B,
                                           int np_out, bool swp) {
   using G = Geo<LP, LA, LA + LB>;
-  using LY = Layout<LP, LA, LB, PCH>;
+  using LY = Layout<LP, LA, LB, PCH, CART>;
   constexpr int NA = ncart(LA), NB = ncart(LB);
   const double *EM = S + LY::EM;
   double *STG = S + LY::STG;
@@ -795,20 +825,60 @@ __device__ __forceinline__ void make_slots(int *slot, int tid) {
 }
 
 // ---------------------------------------------------------------------------
+// Cartesian ket of l = LQ + 2 cs from the degree-LQ term of its expansion: a
+// Cartesian Gaussian x^c e^{-zc r^2} (per axis) is the sum over k of
+// c!/(k!(c-2k)!) (4 zc)^{-k} (2 zc)^{-(c-2k)} times the Hermite Gaussian of
+// order c - 2k, and a Hermite ket of order t is the sum over j of
+// t!/(j!(t-2j)!) (-rho/(4 zc^2))^j times the two-term VRR2 ket of order t - 2j
+// with the Boys orders raised by j.  Collected by the total lowering d = k + j
+// (Vandermonde over the axes), the part of degree LQ = l - 2 cs is
+//   (c|  +=  sum_{|d| = cs, 2d <= c} c! / ((c - 2d)! d!)  (c - 2d|',
+// where (t|' is the two-term ket of class LQ with the Boys sequence of
+// setup_prim (cs > 0).  The launch of class LQ adds this into the block of the
+// class LQ + 2 cs, rows [c][a b] from the staging rows [t][a b].
+// ---------------------------------------------------------------------------
+template <int LQ, int TS>
+__device__ __forceinline__ void store_cart_expand(double *out, const double *STG, int tid, int cs,
+                                                  int nab) {
+  constexpr double fact[11] = {1, 1, 2, 6, 24, 120, 720, 5040, 40320, 362880, 3628800};
+  const int l = LQ + 2 * cs;
+  const int nc = (l + 1) * (l + 2) / 2;
+  for (int o = tid; o < nc * nab; o += TS) {
+    const int c = o / nab, r = o - c * nab;
+    // Cartesian order: for i = 0..l, j = 0..i: (l - i, i - j, j)
+    int i = 0;
+    while ((i + 1) * (i + 2) / 2 <= c) ++i;
+    const int cz = c - i * (i + 1) / 2, cy = i - cz, cx = l - i;
+    double v = 0.0;
+    for (int dx = 0; dx <= cs && 2 * dx <= cx; ++dx)
+      for (int dy = 0; dx + dy <= cs && 2 * dy <= cy; ++dy) {
+        const int dz = cs - dx - dy;
+        if (2 * dz > cz) continue;
+        const int tx = cx - 2 * dx, ty = cy - 2 * dy, tz = cz - 2 * dz;
+        const int ti = (ty + tz) * (ty + tz + 1) / 2 + tz;
+        const double w = fact[cx] / (fact[tx] * fact[dx]) * fact[cy] / (fact[ty] * fact[dy]) *
+                         fact[cz] / (fact[tz] * fact[dz]);
+        v += w * STG[ti * nab + r];
+      }
+    out[o] += v;
+  }
+}
+
+// ---------------------------------------------------------------------------
 // store digestion: one triplet per team, blocks written to out + out_off[t]
 // ---------------------------------------------------------------------------
-template <int LP, int LA, int LB, int TS, int PCH>
+template <int LP, int LA, int LB, int TS, int PCH, bool CART = false>
 __global__ void __launch_bounds__(TS > 64 ? TS : 64)
     __attribute__((amdgpu_waves_per_eu(Cfg<LP, LA, LB>::WPE))) k_store(StoreArgs a) {
   using G = Geo<LP, LA, LA + LB>;
-  using LY = Layout<LP, LA, LB, PCH>;
+  using LY = Layout<LP, LA, LB, PCH, CART>;
   constexpr int BLK = TS > 64 ? TS : 64;
   constexpr int TPB = BLK / TS;
   constexpr int NA = ncart(LA), NB = ncart(LB);
   constexpr int NQ = (G::NPI + TS - 1) / TS;
   extern __shared__ double smem[];
   const int team = threadIdx.x / TS, tid = threadIdx.x % TS;
-  double *S = smem + team * Cfg<LP, LA, LB>::STORE_TEAM;
+  double *S = smem + team * (CART ? Cfg<LP, LA, LB>::STORE_TEAM_C : Cfg<LP, LA, LB>::STORE_TEAM);
   const int np_out = a.pure ? npure(LP) : ncart(LP);
   if (a.err && *a.err) return;
   const int64_t count = a.dcount ? int64_t(*a.dcount) : a.count;
@@ -863,7 +933,7 @@ __global__ void __launch_bounds__(TS > 64 ? TS : 64)
     // thousandth of the absolute floor of the element bar).  Whole-wave teams
     // only (smaller teams share a wave, whose passes must agree).
     if constexpr (TS >= 64) {
-      if (run1 && run2) {
+      if (run1 && run2 && a.cexp == 0) {
         int lane = tid & 63;
         __asm__ volatile("" : "+v"(lane));
         const double ABx = Ar[0] - Br[0], ABy = Ar[1] - Br[1], ABz = Ar[2] - Br[2];
@@ -883,16 +953,20 @@ __global__ void __launch_bounds__(TS > 64 ? TS : 64)
     const int nout = np_out * NA * NB;
     if (do1) {
       const int K1 = (run1 ? (run2 ? n1 : nab) : 0) * Kc;
-      triplet_to_e0P<LP, LA, LB, TS, PCH>(a.boys, S, tid, slot, TS >= 64 ? K1 : wave_max(K1),
+      triplet_to_e0P<LP, LA, LB, TS, PCH, 0, CART>(a.boys, S, tid, slot,
+                                                   TS >= 64 ? K1 : wave_max(K1),
                                           Ar, Br, Cr, Ka, ea, a.orb.coefs + oa, Kb, eb,
                                           a.orb.coefs + ob, run1 ? Kc : 0, a.aux.exps + oc,
-                                          a.aux.coefs + oc, a.pure, run2 ? 1 : 0);
-      hrr_block<LP, LA, LB, TS, PCH>(S, tid, Ar, Br, np_out, swp);
+                                          a.aux.coefs + oc, a.pure, run2 ? 1 : 0, a.cexp);
+      hrr_block<LP, LA, LB, TS, PCH, CART>(S, tid, Ar, Br, np_out, swp);
       team_sync();
       if (run1) {
         double *out = a.out + a.out_off[t];
         const double *STG = S + LY::STG;
-        for (int o = tid; o < nout; o += TS) out[o] = STG[o];
+        if (a.cexp)
+          store_cart_expand<LP, TS>(out, STG, tid, a.cexp, NA * NB);
+        else
+          for (int o = tid; o < nout; o += TS) out[o] = STG[o];
       }
       team_sync();
     }
@@ -901,17 +975,19 @@ __global__ void __launch_bounds__(TS > 64 ? TS : 64)
       // (LP, LB, LA), whose VRR1 builds e = LB..LA+LB on B and whose HRR
       // moves LA quanta to A
       const int K2 = run2 ? (nab - n1) * Kc : 0;
-      triplet_to_e0P<LP, LB, LA, TS, PCH>(a.boys, S, tid, LA == LB ? slot : nullptr,
+      triplet_to_e0P<LP, LB, LA, TS, PCH, 0, CART>(a.boys, S, tid, LA == LB ? slot : nullptr,
                                           TS >= 64 ? K2 : wave_max(K2), Br, Ar, Cr, Kb, eb,
                                           a.orb.coefs + ob, Ka, ea, a.orb.coefs + oa,
                                           run2 ? Kc : 0, a.aux.exps + oc, a.aux.coefs + oc,
-                                          a.pure, 2);
-      hrr_block<LP, LB, LA, TS, PCH>(S, tid, Br, Ar, np_out, !swp);
+                                          a.pure, 2, a.cexp);
+      hrr_block<LP, LB, LA, TS, PCH, CART>(S, tid, Br, Ar, np_out, !swp);
       team_sync();
       if (run2) {
         double *out = a.out + a.out_off[t];
-        const double *STG = S + Layout<LP, LB, LA, PCH>::STG;
-        if (run1)
+        const double *STG = S + Layout<LP, LB, LA, PCH, CART>::STG;
+        if (a.cexp)
+          store_cart_expand<LP, TS>(out, STG, tid, a.cexp, NA * NB);
+        else if (run1)
           for (int o = tid; o < nout; o += TS) out[o] += STG[o];
         else
           for (int o = tid; o < nout; o += TS) out[o] = STG[o];

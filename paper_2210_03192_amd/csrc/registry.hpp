@@ -15,6 +15,8 @@ struct ClassInfo {
   int jreg = 0;       // J on the register engine (one lane, or nsub lanes, per pair)
   int lds = 0;        // dynamic LDS bytes per workgroup
   hipError_t (*store)(const StoreArgs &, int, hipStream_t) = nullptr;
+  // Cartesian-ket instantiation (aux pure = 0; the same kernel for l <= 1)
+  hipError_t (*store_cart)(const StoreArgs &, int, hipStream_t) = nullptr;
   hipError_t (*jfn)(const JArgs &, int, hipStream_t) = nullptr;
   hipError_t (*jq)(const JQArgs &, int, hipStream_t) = nullptr;
   hipError_t (*gam)(const GamArgs &, int, hipStream_t) = nullptr;
@@ -43,6 +45,18 @@ hipError_t launch_store(const StoreArgs &a, int grid, hipStream_t s) {
       C::STORE_LDS);
   if (attr != hipSuccess) return attr;
   hipLaunchKernelGGL(kern, dim3(grid), dim3(C::BLK), C::STORE_LDS, s, a);
+  return hipGetLastError();
+}
+
+template <int LP, int LA, int LB>
+hipError_t launch_store_cart(const StoreArgs &a, int grid, hipStream_t s) {
+  using C = Cfg<LP, LA, LB>;
+  auto kern = k_store<LP, LA, LB, C::TS, C::PCH, true>;
+  static const hipError_t attr = hipFuncSetAttribute(
+      reinterpret_cast<const void *>(kern), hipFuncAttributeMaxDynamicSharedMemorySize,
+      C::STORE_LDS_C);
+  if (attr != hipSuccess) return attr;
+  hipLaunchKernelGGL(kern, dim3(grid), dim3(C::BLK), C::STORE_LDS_C, s, a);
   return hipGetLastError();
 }
 
@@ -161,6 +175,7 @@ ClassInfo class_info() {
   c.jreg = C::JREG ? 1 : 0;
   c.lds = C::STORE_LDS;
   c.store = &launch_store<LP, LA, LB>;
+  if constexpr (LP <= 1) c.store_cart = &launch_store<LP, LA, LB>;  // npure = ncart
   c.jfn = &launch_J<LP, LA, LB>;
   c.jq = &launch_Jq<LP, LA, LB>;
   c.gam = &launch_gam<LP, LA, LB>;
@@ -184,6 +199,11 @@ void register_lp3(ClassInfo (&t)[NLA][NLA]);
 void register_lp4(ClassInfo (&t)[NLA][NLA]);
 void register_lp5(ClassInfo (&t)[NLA][NLA]);
 void register_lp6(ClassInfo (&t)[NLA][NLA]);
+void register_cart_lp2(ClassInfo (&t)[NLA][NLA]);
+void register_cart_lp3(ClassInfo (&t)[NLA][NLA]);
+void register_cart_lp4(ClassInfo (&t)[NLA][NLA]);
+void register_cart_lp5(ClassInfo (&t)[NLA][NLA]);
+void register_cart_lp6(ClassInfo (&t)[NLA][NLA]);
 void register_grad_lp0(GradInfo (&t)[NLG][NLG]);
 void register_grad_lp1(GradInfo (&t)[NLG][NLG]);
 void register_grad_lp2(GradInfo (&t)[NLG][NLG]);
@@ -212,6 +232,27 @@ void register_grad_lp6(GradInfo (&t)[NLG][NLG]);
     t[4][2] = class_info<LPV, 4, 2>();                              \
     t[4][3] = class_info<LPV, 4, 3>();                              \
     t[4][4] = class_info<LPV, 4, 4>();                              \
+  }                                                                 \
+  }
+
+#define DF3C_REGISTER_CART_LP(LPV, FN)                              \
+  namespace df3c {                                                  \
+  void FN(ClassInfo (&t)[NLA][NLA]) {                               \
+    t[0][0].store_cart = &launch_store_cart<LPV, 0, 0>;             \
+    t[1][0].store_cart = &launch_store_cart<LPV, 1, 0>;             \
+    t[1][1].store_cart = &launch_store_cart<LPV, 1, 1>;             \
+    t[2][0].store_cart = &launch_store_cart<LPV, 2, 0>;             \
+    t[2][1].store_cart = &launch_store_cart<LPV, 2, 1>;             \
+    t[2][2].store_cart = &launch_store_cart<LPV, 2, 2>;             \
+    t[3][0].store_cart = &launch_store_cart<LPV, 3, 0>;             \
+    t[3][1].store_cart = &launch_store_cart<LPV, 3, 1>;             \
+    t[3][2].store_cart = &launch_store_cart<LPV, 3, 2>;             \
+    t[3][3].store_cart = &launch_store_cart<LPV, 3, 3>;             \
+    t[4][0].store_cart = &launch_store_cart<LPV, 4, 0>;             \
+    t[4][1].store_cart = &launch_store_cart<LPV, 4, 1>;             \
+    t[4][2].store_cart = &launch_store_cart<LPV, 4, 2>;             \
+    t[4][3].store_cart = &launch_store_cart<LPV, 4, 3>;             \
+    t[4][4].store_cart = &launch_store_cart<LPV, 4, 4>;             \
   }                                                                 \
   }
 

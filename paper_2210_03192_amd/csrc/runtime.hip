@@ -127,6 +127,11 @@ void register_all() {
   register_lp4(t[4]);
   register_lp5(t[5]);
   register_lp6(t[6]);
+  register_cart_lp2(t[2]);
+  register_cart_lp3(t[3]);
+  register_cart_lp4(t[4]);
+  register_cart_lp5(t[5]);
+  register_cart_lp6(t[6]);
   register_metric_lp0(g_metric[0]);
   register_metric_lp1(g_metric[1]);
   register_metric_lp2(g_metric[2]);
@@ -253,7 +258,7 @@ void check_shells(const df3c_shells *b, int natom, int *err, hipStream_t s, int 
 // class of every triplet; hist[NCLS] counts (aggregated per workgroup in LDS),
 // err[0] flags bad input
 __global__ void k_classify(const int32_t *trip, int64_t ntrip, const int32_t *laux, int32_t naux,
-                           const int32_t *lorb, int32_t norb, int32_t aux_pure, uint8_t *cls,
+                           const int32_t *lorb, int32_t norb, uint8_t *cls,
                            int *hist, int *err) {
   __shared__ int h[NCLS];
   for (int i = threadIdx.x; i < NCLS; i += blockDim.x) h[i] = 0;
@@ -268,7 +273,7 @@ __global__ void k_classify(const int32_t *trip, int64_t ntrip, const int32_t *la
     }
     const int lp = laux[P], la = lorb[a], lb = lorb[b];
     if (lp < 0 || lp > DF3C_LMAX_AUX || la < 0 || la > DF3C_LMAX_ORB || lb < 0 ||
-        lb > DF3C_LMAX_ORB || (!aux_pure && lp > 1)) {
+        lb > DF3C_LMAX_ORB) {
       atomicOr(err, 2);
       cls[t] = 255;
       continue;
@@ -471,7 +476,7 @@ int df3c_eval_batch(const double *xyz, int32_t natom, const df3c_shells *aux,
   check_shells(aux, natom, err, s);
   check_shells(orb, natom, err, s);
   hipLaunchKernelGGL(k_classify, dim3(g), dim3(256), 0, s, trip, ntrip, aux->l, aux->nshell,
-                     orb->l, orb->nshell, aux->pure, cls, hist, err);
+                     orb->l, orb->nshell, cls, hist, err);
   StoreArgs a{};
   a.boys = ds->boys;
   a.xyz = xyz;
@@ -489,18 +494,23 @@ int df3c_eval_batch(const double *xyz, int32_t natom, const df3c_shells *aux,
     hipLaunchKernelGGL(k_scan, dim3(1), dim3(64), 0, s, hist, cursor, start);
     hipLaunchKernelGGL(k_scatter, dim3(g), dim3(256), 0, s, trip, ntrip, orb->l, dev_shells(orb),
                        cls, cursor, bucket, err);
-    for (int lp = 0; lp <= (aux->pure ? DF3C_LMAX_AUX : 1); ++lp)
+    for (int lp = 0; lp <= DF3C_LMAX_AUX; ++lp)
       for (int la = 0; la <= DF3C_LMAX_ORB; ++la)
         for (int lb = 0; lb <= la; ++lb) {
           const int c = (lp * NLA + la) * NLA + lb;
-          const ClassInfo &ci = g_cls[lp][la][lb];
           a.bucket = bucket;
           a.dcount = hist + c;
           a.dstart = start + c;
           a.count = ntrip;
-          const int grid = std::min(grid_for(ntrip, ci.tpw, ds->ncu), 8 * ds->ncu);
-          if (timed(DF3C_KERNEL_STORE, c, s, [&] { return ci.store(a, grid, s); }) != hipSuccess)
-            return DF3C_E_HIP;
+          // a Cartesian aux shell of l >= 2 adds the terms of degree l - 2, l - 4, ...
+          for (int cs = 0; cs <= (aux->pure ? 0 : lp / 2); ++cs) {
+            const ClassInfo &ci = g_cls[lp - 2 * cs][la][lb];
+            a.cexp = cs;
+            const int grid = std::min(grid_for(ntrip, ci.tpw, ds->ncu), 8 * ds->ncu);
+            auto fn = aux->pure ? ci.store : ci.store_cart;
+            if (timed(DF3C_KERNEL_STORE, c, s, [&] { return fn(a, grid, s); }) != hipSuccess)
+              return DF3C_E_HIP;
+          }
         }
     return DF3C_OK;
   }
@@ -519,12 +529,18 @@ int df3c_eval_batch(const double *xyz, int32_t natom, const df3c_shells *aux,
   for (int c = 0; c < NCLS; ++c) {
     if (!rb[c]) continue;
     const int lp = c / (NLA * NLA), la = (c / NLA) % NLA, lb = c % NLA;
-    const ClassInfo &ci = g_cls[lp][la][lb];
     a.bucket = bucket + off;
     a.count = rb[c];
-    if (timed(DF3C_KERNEL_STORE, c, s,
-              [&] { return ci.store(a, grid_for(rb[c], ci.tpw, ds->ncu), s); }) != hipSuccess)
-      return DF3C_E_HIP;
+    // a Cartesian aux shell of l >= 2: the launches of classes l - 2, l - 4, ...
+    // add the lower-degree terms of its expansion into the same blocks
+    for (int cs = 0; cs <= (aux->pure ? 0 : lp / 2); ++cs) {
+      const ClassInfo &ci = g_cls[lp - 2 * cs][la][lb];
+      a.cexp = cs;
+      auto fn = aux->pure ? ci.store : ci.store_cart;
+      if (timed(DF3C_KERNEL_STORE, c, s,
+                [&] { return fn(a, grid_for(rb[c], ci.tpw, ds->ncu), s); }) != hipSuccess)
+        return DF3C_E_HIP;
+    }
     off += rb[c];
   }
   return DF3C_OK;
