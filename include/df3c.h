@@ -100,7 +100,7 @@ typedef struct {
                               df3c_eval_batch, l <= 1 in the other calls);
                               orbital: 0 Cartesian; 1 solid-harmonic, accepted by
                               df3c_coulomb_J, df3c_coulomb_J_grad (and their
-                              masked forms) and df3c_coulomb_gamma */
+                              masked and batched forms) and df3c_coulomb_gamma */
   const int32_t *nprim_host; /* HOST [nshell] copy of nprim, or NULL.  Optional, read
                               by df3c_coulomb_J_batched only: when given, its host plan
                               orders the orbital shells of each l by decreasing
@@ -342,9 +342,12 @@ typedef struct {
 } df3c_class_tune;
 #define DF3C_NCLASS 175
 
-/* Bytes of workspace df3c_coulomb_J_batched needs. */
+/* Bytes of workspace df3c_coulomb_J_batched needs.  mol_orb (HOST [nmol+1], as
+ * for df3c_coulomb_J_batched) is read only for solid-harmonic orbital shells
+ * (orb->pure = 1: the Cartesian J of every molecule is kept in the workspace)
+ * and may be NULL otherwise; 0 on bad arguments. */
 size_t df3c_coulomb_J_batched_workspace(const df3c_shells *aux, const df3c_shells *orb,
-                                        int32_t nmol);
+                                        int32_t nmol, const int32_t *mol_orb);
 
 /* DF-J for nmol independent molecules in one call: the batched form of
  * df3c_coulomb_J for uneven molecule sizes, L classes and contraction degrees.
@@ -353,7 +356,10 @@ size_t df3c_coulomb_J_batched_workspace(const df3c_shells *aux, const df3c_shell
  *                     [mol_aux[m], mol_aux[m+1]); mol_*[0] = 0, mol_*[nmol] = nshell
  *   d                 DEVICE, the molecules' fitting coefficients in aux order
  *   J                 DEVICE output, molecule m's nao_m x nao_m matrix at offset
- *                     sum_{m' < m} nao_m'^2 (both triangles)
+ *                     sum_{m' < m} nao_m'^2 (both triangles; nao_m counts 2l+1
+ *                     functions per shell for solid-harmonic orbital shells, whose
+ *                     Cartesian J is transformed on both sides per molecule, the
+ *                     transform captured with the other launches under DF3C_GRAPH)
  *   tune              HOST [DF3C_NCLASS] schedule parameters, or NULL for defaults
  *   flags             DF3C_SCHED_PER_CLASS or DF3C_SCHED_PERSISTENT, optionally
  *                     | DF3C_GRAPH and | DF3C_ASYNC.  The plan is built on the host

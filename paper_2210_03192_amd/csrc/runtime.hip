@@ -1993,6 +1993,12 @@ int df3c_coulomb_J_grad_batched(const double *xyz, int32_t natom, const df3c_she
 
 // --------------------------------------------------------------- batched DF-J
 namespace {
+// solid-harmonic orbital shells: per molecule, where its pure rows, its
+// Cartesian J (in the workspace) and its pure J (the caller's) lie
+struct PMol {
+  int64_t pbase, np, jpbase, jcbase, nc, ao_base;
+};
+
 struct BPlan {
   std::vector<int32_t> orb_sorted, aux_sorted;  // per molecule, grouped by l
   std::vector<int64_t> ao_off, aux_off;
@@ -2000,7 +2006,11 @@ struct BPlan {
   int32_t cls_seg0[NCLS + 1] = {};               // segment range of every class
   int64_t cls_items[NCLS] = {};
   std::vector<int64_t> jbase, nao_m, ao_base;
-  int64_t jtotal = 0;
+  int64_t jtotal = 0;                            // Cartesian J doubles of all molecules
+  // orb->pure = 1: pure rows (shell << 4 | m) of all molecules, per-molecule records
+  std::vector<int32_t> prow;
+  std::vector<PMol> pmol;
+  int64_t np_max = 0;
 };
 
 size_t bplan_bytes(int64_t norb, int64_t naux, int64_t nmol) {
@@ -2008,6 +2018,60 @@ size_t bplan_bytes(int64_t norb, int64_t naux, int64_t nmol) {
          align256(sizeof(int32_t) * naux) + align256(sizeof(int64_t) * (norb + 1)) +
          align256(sizeof(int64_t) * (naux + 1)) + align256(sizeof(JSeg) * nmol * NCLS) +
          align256(sizeof(unsigned long long) * NCLS) + align256(sizeof(double) * AREC * naux);
+}
+
+// extra workspace of solid-harmonic orbital shells: the Cartesian J of every
+// molecule, the pure row map and the per-molecule records
+size_t bplan_pure_bytes(const df3c_shells *orb, int32_t nmol, const int32_t *mol_orb) {
+  int64_t jc = 0, np = 0;
+  for (int m = 0; m < nmol; ++m) {
+    int64_t nc = 0;
+    for (int s = mol_orb[m]; s < mol_orb[m + 1]; ++s) {
+      const int l = orb->l_host[s];
+      nc += (l + 1) * (l + 2) / 2;
+      np += 2 * l + 1;
+    }
+    jc += nc * nc;
+  }
+  return align256(sizeof(double) * jc) + align256(sizeof(int32_t) * np) +
+         align256(sizeof(PMol) * nmol);
+}
+
+// J[m] pure = T_a Jc[m] T_b^T over the pure rows of molecule m (blockIdx.y
+// strides over molecules; an element above the diagonal is evaluated as its
+// mirror, as in k_bra_pure)
+__global__ void k_bra_pure_mol(const double *Jc, const PMol *pm, int32_t nmol,
+                               const int32_t *prow, const int64_t *ao_off, const int32_t *lsh,
+                               double *J, const int *err) {
+  if (*err) return;
+  for (int m = blockIdx.y; m < nmol; m += gridDim.y) {
+    const PMol q = pm[m];
+    const int64_t total = q.np * q.np;
+    for (int64_t x = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; x < total;
+         x += int64_t(gridDim.x) * blockDim.x) {
+      int64_t r = x / q.np, c = x - r * q.np;
+      if (r < c) {
+        const int64_t t = r;
+        r = c;
+        c = t;
+      }
+      const int sa = prow[q.pbase + r] >> 4, ma = prow[q.pbase + r] & 15;
+      const int sb = prow[q.pbase + c] >> 4, mb = prow[q.pbase + c] & 15;
+      int na, nb;
+      const int16_t *ca, *cb;
+      const double *va, *vb;
+      solid_row_l(lsh[sa], ma, na, ca, va);
+      solid_row_l(lsh[sb], mb, nb, cb, vb);
+      const double *row = Jc + q.jcbase + (ao_off[sa] - q.ao_base) * q.nc + (ao_off[sb] - q.ao_base);
+      double v = 0.0;
+      for (int i = 0; i < na; ++i) {
+        double t = 0.0;
+        for (int j = 0; j < nb; ++j) t += vb[j] * row[int64_t(ca[i]) * q.nc + cb[j]];
+        v += va[i] * t;
+      }
+      J[q.jpbase + x] = v;
+    }
+  }
 }
 
 // Orbital shells of one l in order of decreasing contraction degree (stable),
@@ -2069,6 +2133,27 @@ int make_bplan(const df3c_shells *aux, const df3c_shells *orb, int nmol, const i
     jb += p.nao_m[m] * p.nao_m[m];
   }
   p.jtotal = jb;
+  p.prow.clear();
+  p.pmol.clear();
+  p.np_max = 0;
+  if (orb->pure) {
+    if (orb->nshell >= (1 << 27)) return DF3C_E_UNSUPPORTED;  // rows packed shell << 4
+    int64_t jp = 0;
+    for (int m = 0; m < nmol; ++m) {
+      PMol q{};
+      q.pbase = int64_t(p.prow.size());
+      for (int s = mo[m]; s < mo[m + 1]; ++s)
+        for (int k = 0; k < 2 * orb->l_host[s] + 1; ++k) p.prow.push_back((s << 4) | k);
+      q.np = int64_t(p.prow.size()) - q.pbase;
+      q.jpbase = jp;
+      q.jcbase = p.jbase[m];
+      q.nc = p.nao_m[m];
+      q.ao_base = p.ao_base[m];
+      jp += q.np * q.np;
+      p.np_max = std::max(p.np_max, q.np);
+      p.pmol.push_back(q);
+    }
+  }
   p.seg.clear();
   for (int c = 0; c < NCLS; ++c) {
     p.cls_seg0[c] = int32_t(p.seg.size());
@@ -2134,8 +2219,12 @@ df3c_class_tune default_tune(int c) {
 }  // namespace
 
 size_t df3c_coulomb_J_batched_workspace(const df3c_shells *aux, const df3c_shells *orb,
-                                        int32_t nmol) {
+                                        int32_t nmol, const int32_t *mol_orb) {
   if (!aux || !orb || nmol <= 0) return 0;
+  if (orb->pure) {
+    if (!mol_orb || !orb->l_host || !batch_ranges_ok(nmol, mol_orb, orb->nshell)) return 0;
+    return bplan_bytes(orb->nshell, aux->nshell, nmol) + bplan_pure_bytes(orb, nmol, mol_orb);
+  }
   return bplan_bytes(orb->nshell, aux->nshell, nmol);
 }
 
@@ -2146,9 +2235,14 @@ int df3c_coulomb_J_batched(const double *xyz, int32_t natom, const df3c_shells *
                            uint32_t flags, void *stream) {
   if (!xyz || natom <= 0 || !shells_ok(aux) || !shells_ok(orb) || !d || !J || nmol <= 0)
     return DF3C_E_ARG;
-  if (orb->pure != 0 || (aux->pure != 0 && aux->pure != 1)) return DF3C_E_UNSUPPORTED;
+  if ((orb->pure != 0 && orb->pure != 1) || (aux->pure != 0 && aux->pure != 1))
+    return DF3C_E_UNSUPPORTED;
   if (flags & ~(DF3C_SCHED_PERSISTENT | DF3C_GRAPH | DF3C_ASYNC)) return DF3C_E_ARG;
-  if (!ws || ws_bytes < bplan_bytes(orb->nshell, aux->nshell, nmol)) return DF3C_E_WORKSPACE;
+  if (!mol_orb || !mol_aux || !batch_ranges_ok(nmol, mol_orb, orb->nshell) ||
+      !batch_ranges_ok(nmol, mol_aux, aux->nshell))
+    return DF3C_E_ARG;
+  if (!ws || ws_bytes < df3c_coulomb_J_batched_workspace(aux, orb, nmol, mol_orb))
+    return DF3C_E_WORKSPACE;
   DevState *ds = nullptr;
   int rc = init_device(&ds);
   if (rc) return rc;
@@ -2167,8 +2261,8 @@ int df3c_coulomb_J_batched(const double *xyz, int32_t natom, const df3c_shells *
                         orb->l, orb->nprim, orb->prim_off, orb->atom, orb->exps, orb->coefs,
                         d, J, ws};
   key = fnv(key, ptrs, sizeof(ptrs));
-  const int64_t scal[] = {natom, aux->nshell, orb->nshell, aux->pure, nmol, int64_t(ws_bytes),
-                          int64_t(flags), dev};
+  const int64_t scal[] = {natom, aux->nshell, orb->nshell, aux->pure, orb->pure, nmol,
+                          int64_t(ws_bytes), int64_t(flags), dev};
   key = fnv(key, scal, sizeof(scal));
   key = fnv(key, aux->l_host, sizeof(int32_t) * aux->nshell);
   key = fnv(key, orb->l_host, sizeof(int32_t) * orb->nshell);
@@ -2208,6 +2302,26 @@ int df3c_coulomb_J_batched(const double *xyz, int32_t natom, const df3c_shells *
   unsigned long long *ctr = reinterpret_cast<unsigned long long *>(w);
   w += align256(sizeof(unsigned long long) * NCLS);
   double *arec = reinterpret_cast<double *>(w);
+  w += align256(sizeof(double) * AREC * aux->nshell);
+  // solid-harmonic orbital shells: the engines write the Cartesian J here and
+  // one transform per molecule writes the caller's J
+  double *Jc = J;
+  int32_t *prow = nullptr;
+  PMol *pmol = nullptr;
+  if (orb->pure) {
+    Jc = reinterpret_cast<double *>(w);
+    w += align256(sizeof(double) * p.jtotal);
+    prow = reinterpret_cast<int32_t *>(w);
+    w += align256(sizeof(int32_t) * p.prow.size());
+    pmol = reinterpret_cast<PMol *>(w);
+    if ((!p.prow.empty() && hipMemcpyAsync(prow, p.prow.data(), sizeof(int32_t) * p.prow.size(),
+                                           hipMemcpyHostToDevice, s) != hipSuccess) ||
+        hipMemcpyAsync(pmol, p.pmol.data(), sizeof(PMol) * p.pmol.size(), hipMemcpyHostToDevice,
+                       s) != hipSuccess) {
+      (void)hipStreamSynchronize(s);
+      return DF3C_E_HIP;
+    }
+  }
   if ((!p.orb_sorted.empty() &&
        hipMemcpyAsync(orb_sorted, p.orb_sorted.data(), sizeof(int32_t) * p.orb_sorted.size(),
                       hipMemcpyHostToDevice, s) != hipSuccess) ||
@@ -2280,7 +2394,7 @@ int df3c_coulomb_J_batched(const double *xyz, int32_t natom, const df3c_shells *
 
   auto enqueue = [&]() -> int {
     hipLaunchKernelGGL(k_zero_f64, dim3(int(std::min<int64_t>((p.jtotal + 255) / 256, 4096))),
-                       dim3(256), 0, s, J, p.jtotal);
+                       dim3(256), 0, s, Jc, p.jtotal);
     if (launch_aux_records(aux_sorted, int64_t(p.aux_sorted.size()), aux, xyz, aux_off, d, arec,
                            s, err) != hipSuccess)
       return DF3C_E_HIP;
@@ -2325,7 +2439,7 @@ int df3c_coulomb_J_batched(const double *xyz, int32_t natom, const df3c_shells *
         q.a = base;
         q.orb_sorted = orb_sorted;
         q.aux_sorted = aux_sorted;
-        q.Jall = J;
+        q.Jall = Jc;
         q.seg = segd + p.cls_seg0[c];
         q.nseg = p.cls_seg0[c + 1] - p.cls_seg0[c];
         q.chunk = tt[c].chunk;
@@ -2360,7 +2474,7 @@ int df3c_coulomb_J_batched(const double *xyz, int32_t natom, const df3c_shells *
             a.psh = aux_sorted + sg.psh;
             a.arec = arec + int64_t(sg.psh) * AREC;
             a.np = sg.np;
-            a.J = J + sg.jbase;
+            a.J = Jc + sg.jbase;
             a.nao = sg.nao;
             a.ao_base = sg.ao_base;
             a.npair = sg.npair;
@@ -2372,6 +2486,12 @@ int df3c_coulomb_J_batched(const double *xyz, int32_t natom, const df3c_shells *
               return DF3C_E_HIP;
           }
         }
+    }
+    if (orb->pure && p.np_max > 0) {
+      const int gx = int(std::min<int64_t>((p.np_max * p.np_max + 255) / 256, 2048));
+      hipLaunchKernelGGL(k_bra_pure_mol, dim3(gx, std::min(nmol, 65535)), dim3(256), 0, s, Jc,
+                         pmol, nmol, prow, ao_off, orb->l, J, err);
+      if (hipGetLastError() != hipSuccess) return DF3C_E_HIP;
     }
     return DF3C_OK;
   };

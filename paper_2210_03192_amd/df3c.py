@@ -97,7 +97,7 @@ def lib():
         L.df3c_coulomb_J_grad_batched.argtypes = [P, I32, P, P, I32, P, P, P, P, P, P, P, SZ,
                                                   U32, P]
         L.df3c_coulomb_J_batched_workspace.restype = SZ
-        L.df3c_coulomb_J_batched_workspace.argtypes = [P, P, I32]
+        L.df3c_coulomb_J_batched_workspace.argtypes = [P, P, I32, P]
         L.df3c_coulomb_J_batched.argtypes = [P, I32, P, P, I32, P, P, P, P, P, P, SZ, U32, P]
         L.df3c_coulomb_metric_workspace.restype = SZ
         L.df3c_coulomb_metric_workspace.argtypes = [P]
@@ -422,10 +422,14 @@ def J(xyz: torch.Tensor, d: torch.Tensor, aux: DeviceBasis, orb: DeviceBasis) ->
     return CoulombJ.apply(xyz, d, aux, orb)
 
 
-def coulomb_J_batched_workspace(aux: DeviceBasis, orb: DeviceBasis, nmol: int) -> int:
+def coulomb_J_batched_workspace(aux: DeviceBasis, orb: DeviceBasis, nmol: int,
+                                mol_orb: Optional[np.ndarray] = None) -> int:
+    """mol_orb is needed for solid-harmonic orbital shells (orb.pure = 1)."""
     sa, so = aux.struct(), orb.struct()
+    mo = None if mol_orb is None else np.ascontiguousarray(mol_orb, np.int32)
     return int(lib().df3c_coulomb_J_batched_workspace(ctypes.byref(sa), ctypes.byref(so),
-                                                      int(nmol)))
+                                                      int(nmol),
+                                                      None if mo is None else mo.ctypes.data))
 
 
 def coulomb_J_batched(xyz: torch.Tensor, aux: DeviceBasis, orb: DeviceBasis,
@@ -441,7 +445,7 @@ def coulomb_J_batched(xyz: torch.Tensor, aux: DeviceBasis, orb: DeviceBasis,
     nao = off[mol_orb[1:]] - off[mol_orb[:-1]]
     if J is None:
         J = torch.empty(int((nao * nao).sum()), dtype=torch.float64, device=xyz.device)
-    need = coulomb_J_batched_workspace(aux, orb, nmol)
+    need = coulomb_J_batched_workspace(aux, orb, nmol, mol_orb)
     if flags & GRAPH and (ws is None or ws.numel() < need):
         # the cached graph replays against the same workspace address on later
         # calls, so the workspace must be the caller's and outlive them

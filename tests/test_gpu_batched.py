@@ -191,3 +191,59 @@ def test_batched_tune_table_and_errors():
     bad[-1] -= 1
     with pytest.raises(df3c.DF3CError):
         df3c.coulomb_J_batched(xyz, aux, orb, bad, b.mol_aux, dd)
+
+
+def test_batched_pure_orbital_shells():
+    """Solid-harmonic orbital shells in the batched call (the Cartesian J of
+    every cluster in the workspace, one transform per cluster): five water
+    clusters; persistent + graph (replayed) equals the per-class schedule
+    bitwise, each cluster's J equals the single-molecule pure J to rounding,
+    and the two smallest clusters' whole J matches the oracle's pure J at the
+    Cartesian element bar carried through the transform."""
+    import dataclasses
+    from paper_2210_03192_amd.inputs import Basis
+    torch = _torch()
+
+    def pure(bs):
+        return Basis(bs.l, bs.nprim, bs.prim_off, bs.atom, bs.exps, bs.coefs, pure=1)
+
+    systems = [dataclasses.replace(s, orb=pure(s.orb))
+               for s in (inputs.water_cluster(n, seed=600 + n) for n in (2, 6, 3, 11, 5))]
+    df3c, b, d, xyz, aux, orb, dd = _setup(systems, 34)
+    assert b.orb.pure == 1
+    stream = torch.cuda.Stream()
+    need = df3c.coulomb_J_batched_workspace(aux, orb, b.nmol, b.mol_orb)
+    assert need > df3c.coulomb_J_batched_workspace(
+        aux, df3c.DeviceBasis.from_basis(dataclasses.replace(b.orb, pure=0)), b.nmol)
+    ws = torch.empty(need, dtype=torch.uint8, device="cuda")
+    f = df3c.SCHED_PERSISTENT | df3c.GRAPH
+    with torch.cuda.stream(stream):
+        Jp = df3c.coulomb_J_batched(xyz, aux, orb, b.mol_orb, b.mol_aux, dd, flags=f, ws=ws,
+                                    stream=stream)
+        reps = [Jp.clone()]
+        for _ in range(2):  # graph replays, with eager work in between
+            Jp.fill_(np.nan)
+            df3c.coulomb_J_batched(xyz, aux, orb, b.mol_orb, b.mol_aux, dd, J=Jp, flags=f,
+                                   ws=ws, stream=stream)
+            stream.synchronize()
+            reps.append(Jp.clone())
+        Jc = df3c.coulomb_J_batched(xyz, aux, orb, b.mol_orb, b.mol_aux, dd,
+                                    flags=df3c.SCHED_PER_CLASS, ws=ws, stream=stream)
+    torch.cuda.synchronize()
+    for r in reps[1:]:
+        assert torch.equal(r, reps[0])
+    assert torch.equal(reps[0], Jc)
+    Js = _split(b, reps[0].cpu().numpy())
+    for m, s in enumerate(systems):
+        Jm = df3c.coulomb_J(torch.as_tensor(s.xyz, device="cuda"),
+                            df3c.DeviceBasis.from_basis(s.aux), df3c.DeviceBasis.from_basis(s.orb),
+                            torch.as_tensor(_mol_d(b, d, m), device="cuda")).cpu().numpy()
+        assert Js[m].shape == Jm.shape
+        assert np.abs(Js[m] - Jm).max() <= 1e-13 * max(1.0, np.abs(Jm).max())
+    # the pure J's bar: the Cartesian element bar carried through the transform
+    from tests.test_gpu_pure_orbitals import _assert_pure_parity, _bound
+    for m in (0, 2):
+        s, dm = systems[m], _mol_d(b, d, m)
+        ref = oracle.coulomb_J(s.xyz, s.aux, s.orb, dm)
+        _assert_pure_parity(Js[m], ref, _bound(s.xyz, s.aux, s.orb, dm),
+                            f"batched pure J, cluster {m}")

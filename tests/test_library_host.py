@@ -103,6 +103,19 @@ def test_pure_orbital_options(lib):
                               1 << 40, 0, None) == -2
     assert lib.df3c_coulomb_J_grad(buf, 1, ctypes.byref(aux), ctypes.byref(bad), buf, buf, buf,
                                    buf, 1 << 40, 0, None) == -2
+    # batched: pure orbital shells need the molecule ranges to size the
+    # Cartesian J of every molecule (two molecules of two shells each here)
+    mo = np.array([0, 2, 4], np.int32)
+    bc = lib.df3c_coulomb_J_batched_workspace(ctypes.byref(aux), ctypes.byref(cart), 2, None)
+    assert bc > 0
+    assert lib.df3c_coulomb_J_batched_workspace(ctypes.byref(aux), ctypes.byref(pure), 2,
+                                                None) == 0
+    bp = lib.df3c_coulomb_J_batched_workspace(ctypes.byref(aux), ctypes.byref(pure), 2,
+                                              mo.ctypes.data)
+    assert bp >= bc + 8 * ((1 + 3) ** 2 + (6 + 10) ** 2)
+    bad_mo = np.array([0, 3, 2], np.int32)
+    assert lib.df3c_coulomb_J_batched_workspace(ctypes.byref(aux), ctypes.byref(pure), 2,
+                                                bad_mo.ctypes.data) == 0
 
 
 def test_null_l_host_rejected_before_device_work(lib):
