@@ -329,6 +329,51 @@ __device__ __forceinline__ int split_count(int grp, int Ka, int Kb, const double
   return n;
 }
 
+// index of the k-th (0-based) set bit of m (k < popcount(m)), by halving
+__device__ __forceinline__ int nth_set_bit(uint64_t m, int k) {
+  int pos = 0;
+#pragma unroll
+  for (int s = 32; s > 0; s >>= 1) {
+    const uint64_t low = m & ((uint64_t(1) << s) - 1);
+    const int c = __popcll(low);
+    if (k >= c) {
+      k -= c;
+      m >>= s;
+      pos += s;
+    } else {
+      m = low;
+    }
+  }
+  return pos;
+}
+
+// split_pair for the lanes of one whole wavefront (every lane calls it): the
+// candidate pairs are flagged 64 at a time, a ballot and a prefix count rank
+// them, and a lane takes the pair ranked q; O(Ka Kb / 64) steps instead of a
+// serial scan per lane
+__device__ __forceinline__ void split_pair_wave(int lane, int q, int grp, int Ka, int Kb,
+                                                const double *ea, const double *eb, int &ia,
+                                                int &ib) {
+  const int n = Ka * Kb;
+  int base = 0;
+  for (int w0 = 0; w0 < n; w0 += 64) {
+    const int c = w0 + lane;
+    bool keep = false;
+    if (c < n) {
+      const int i = c / Kb;
+      keep = split_keep(grp, ea[i], eb[c - i * Kb]);
+    }
+    const uint64_t m = __ballot(keep);
+    const int cnt = __popcll(m);
+    if (q >= base && q < base + cnt) {
+      const int pos = w0 + nth_set_bit(m, q - base);
+      ia = pos / Kb;
+      ib = pos - ia * Kb;
+    }
+    base += cnt;
+  }
+}
+
 // (ia, ib) of the q-th pair of group grp (q < split_count)
 __device__ __forceinline__ void split_pair(int q, int grp, int Ka, int Kb, const double *ea,
                                            const double *eb, int &ia, int &ib) {
@@ -415,12 +460,13 @@ __device__ __forceinline__ void setup_prim(const double *btab, double *R, int p,
                                            double AB2, const double *ea, const double *ca,
                                            const double *eb, const double *cb,
                                            const double *ec, const double *cc, int grp = 0,
-                                           int Ka = 0, int cs = 0) {
+                                           int Ka = 0, int cs = 0, int ia_in = -1,
+                                           int ib_in = 0) {
   constexpr int LP = G::LP, L = G::L;
   {
     const int ic = p % Kc, rest = p / Kc;
-    int ia, ib;
-    split_pair(rest, grp, Ka, Kb, ea, eb, ia, ib);
+    int ia = ia_in, ib = ib_in;
+    if (ia_in < 0) split_pair(rest, grp, Ka, Kb, ea, eb, ia, ib);
     const double za = ea[ia], zb = eb[ib], zc = ec[ic];
     const double g = za + zb, ig = 1.0 / g;
     const double Px = (za * A[0] + zb * B[0]) * ig, Py = (za * A[1] + zb * B[1]) * ig,
@@ -500,9 +546,23 @@ __device__ __forceinline__ void setup_chunk(const double *btab, double *prims, i
                                             const double *eb, const double *cb,
                                             const double *ec, const double *cc, int grp = 0,
                                             int Ka = 0, int cs = 0) {
-  for (int pp = lt; pp < npc; pp += TS)
-    setup_prim<G, WM>(btab, prims + pp * REC, p0 + pp, Kb, Kc, A, B, C, AB2, ea, ca, eb, cb, ec,
-                      cc, grp, Ka, cs);
+  if constexpr (TS % 64 == 0 && REC > 0) {
+    // whole-wave teams: npc <= 64, the first wave sets the chunk up; with a
+    // split the pairs of the group are ranked by the whole wave
+    if (lt < 64) {
+      int ia = -1, ib = 0;
+      if (grp != 0)
+        split_pair_wave(lt, (p0 + lt) / imax(Kc, 1), grp, Ka, Kb, ea, eb, ia, ib);
+      if (lt < npc)
+        setup_prim<G, WM>(btab, prims + lt * REC, p0 + lt, Kb, Kc, A, B, C, AB2, ea, ca, eb, cb,
+                          ec, cc, grp, Ka, cs, grp != 0 ? ia : (p0 + lt) / Kc / Kb,
+                          grp != 0 ? ib : (p0 + lt) / Kc % Kb);
+    }
+  } else {
+    for (int pp = lt; pp < npc; pp += TS)
+      setup_prim<G, WM>(btab, prims + pp * REC, p0 + pp, Kb, Kc, A, B, C, AB2, ea, ca, eb, cb, ec,
+                        cc, grp, Ka, cs);
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -517,7 +577,7 @@ __device__ __forceinline__ void triplet_to_e0P(const double *btab, double *S, in
                                                const double *ea, const double *ca, int Kb,
                                                const double *eb, const double *cb, int Kc,
                                                const double *ec, const double *cc, int pure,
-                                               int grp = 0, int cs = 0) {
+                                               int grp = 0, int cs = 0, int nkept = -1) {
   using G = Geo<LP, LA, LA + LB>;
   using LY = Layout<LP, LA, LB, PCH, CART>;
   using TB = GenTab<LP, G::EA, G::EB>;
@@ -530,7 +590,8 @@ __device__ __forceinline__ void triplet_to_e0P(const double *btab, double *S, in
 
   const double ABx = A[0] - B[0], ABy = A[1] - B[1], ABz = A[2] - B[2];
   const double AB2 = ABx * ABx + ABy * ABy + ABz * ABz;
-  const int K = split_count(grp, Ka, Kb, ea, eb) * Kc;
+  // primitive triplets of the group (nkept: its pair count, when the caller has it)
+  const int K = (nkept >= 0 ? nkept : split_count(grp, Ka, Kb, ea, eb)) * Kc;
 
   // matrix-core contraction for whole-wave teams (chunks of 4 primitives = the
   // K extent of one MFMA); per-lane register slots otherwise
@@ -638,15 +699,35 @@ __device__ __forceinline__ void triplet_to_e0P(const double *btab, double *S, in
     // interleaved across the lanes: uniform loops, coalesced table loads; all
     // table words of a block are loaded first, then all pi operands, so each
     // block waits for one table and one LDS latency
+    // The table words of a wave's next block are requested before the
+    // current block's operands are read, so each block's table latency
+    // overlaps the previous block's work (one exposed latency per wave).
     constexpr int MM = TB::CBM > 0 ? TB::CBM : 1;
     const int wv2 = tid >> 6, ln = tid & 63;
-    for (int b = wv2; b < TB::NCB; b += NWV) {
-      const int t = TB::cb_tg[b * 64 + ln];
-      const int m = TB::cb_bm[b];
-      const uint32_t *w = TB::cb_il + TB::cb_boff[b] + ln;
-      uint32_t cw[MM];
+    uint32_t cw[MM];
+    int t = 0xffff;
+    if (wv2 < TB::NCB) {
+      const int m = TB::cb_bm[wv2];
+      const uint32_t *w = TB::cb_il + TB::cb_boff[wv2] + ln;
 #pragma unroll
       for (int j = 0; j < MM; ++j) cw[j] = j < m ? w[j * 64] : 0u;
+      t = TB::cb_tg[wv2 * 64 + ln];
+    }
+    for (int b = wv2; b < TB::NCB; b += NWV) {
+      const int bn = b + NWV;
+      uint32_t nw[MM];
+      int tn = 0xffff;
+      if (bn < TB::NCB) {
+        const int mn = TB::cb_bm[bn];
+        const uint32_t *w = TB::cb_il + TB::cb_boff[bn] + ln;
+#pragma unroll
+        for (int j = 0; j < MM; ++j) nw[j] = j < mn ? w[j * 64] : 0u;
+        tn = TB::cb_tg[bn * 64 + ln];
+      } else {
+#pragma unroll
+        for (int j = 0; j < MM; ++j) nw[j] = 0u;
+      }
+      const int m = TB::cb_bm[b];
       double pv[MM];
 #pragma unroll
       for (int j = 0; j < MM; ++j) pv[j] = j < m ? PI[cw[j] & 0xffffu] : 0.0;
@@ -654,6 +735,9 @@ __device__ __forceinline__ void triplet_to_e0P(const double *btab, double *S, in
 #pragma unroll
       for (int j = 0; j < MM; ++j) a += double(cw[j] >> 16) * pv[j];
       if (t != 0xffff) PI[t] += a;
+#pragma unroll
+      for (int j = 0; j < MM; ++j) cw[j] = nw[j];
+      t = tn;
     }
   } else {
     for (int t = tid; t < TB::NTGT; t += TS) {
@@ -880,6 +964,9 @@ __global__ void __launch_bounds__(TS > 64 ? TS : 64)
   const int team = threadIdx.x / TS, tid = threadIdx.x % TS;
   double *S = smem + team * (CART ? Cfg<LP, LA, LB>::STORE_TEAM_C : Cfg<LP, LA, LB>::STORE_TEAM);
   const int np_out = a.pure ? npure(LP) : ncart(LP);
+  // the lower-degree Cartesian terms run only in the Cartesian-ket kernels
+  // (a compile-time 0 elsewhere keeps their Boys branch out of the pure kernels)
+  const int cexp = CART ? a.cexp : 0;
   if (a.err && *a.err) return;
   const int64_t count = a.dcount ? int64_t(*a.dcount) : a.count;
   const uint32_t *bucket = a.bucket + (a.dstart ? *a.dstart : 0);
@@ -933,7 +1020,7 @@ __global__ void __launch_bounds__(TS > 64 ? TS : 64)
     // thousandth of the absolute floor of the element bar).  Whole-wave teams
     // only (smaller teams share a wave, whose passes must agree).
     if constexpr (TS >= 64) {
-      if (run1 && run2 && a.cexp == 0) {
+      if (run1 && run2 && cexp == 0) {
         int lane = tid & 63;
         __asm__ volatile("" : "+v"(lane));
         const double ABx = Ar[0] - Br[0], ABy = Ar[1] - Br[1], ABz = Ar[2] - Br[2];
@@ -957,14 +1044,15 @@ __global__ void __launch_bounds__(TS > 64 ? TS : 64)
                                                    TS >= 64 ? K1 : wave_max(K1),
                                           Ar, Br, Cr, Ka, ea, a.orb.coefs + oa, Kb, eb,
                                           a.orb.coefs + ob, run1 ? Kc : 0, a.aux.exps + oc,
-                                          a.aux.coefs + oc, a.pure, run2 ? 1 : 0, a.cexp);
+                                          a.aux.coefs + oc, a.pure, run2 ? 1 : 0, cexp,
+                                          run2 ? n1 : nab);
       hrr_block<LP, LA, LB, TS, PCH, CART>(S, tid, Ar, Br, np_out, swp);
       team_sync();
       if (run1) {
         double *out = a.out + a.out_off[t];
         const double *STG = S + LY::STG;
-        if (a.cexp)
-          store_cart_expand<LP, TS>(out, STG, tid, a.cexp, NA * NB);
+        if (cexp)
+          store_cart_expand<LP, TS>(out, STG, tid, cexp, NA * NB);
         else
           for (int o = tid; o < nout; o += TS) out[o] = STG[o];
       }
@@ -979,14 +1067,14 @@ __global__ void __launch_bounds__(TS > 64 ? TS : 64)
                                           TS >= 64 ? K2 : wave_max(K2), Br, Ar, Cr, Kb, eb,
                                           a.orb.coefs + ob, Ka, ea, a.orb.coefs + oa,
                                           run2 ? Kc : 0, a.aux.exps + oc, a.aux.coefs + oc,
-                                          a.pure, 2, a.cexp);
+                                          a.pure, 2, cexp, nab - n1);
       hrr_block<LP, LB, LA, TS, PCH, CART>(S, tid, Br, Ar, np_out, !swp);
       team_sync();
       if (run2) {
         double *out = a.out + a.out_off[t];
         const double *STG = S + Layout<LP, LB, LA, PCH, CART>::STG;
-        if (a.cexp)
-          store_cart_expand<LP, TS>(out, STG, tid, a.cexp, NA * NB);
+        if (cexp)
+          store_cart_expand<LP, TS>(out, STG, tid, cexp, NA * NB);
         else if (run1)
           for (int o = tid; o < nout; o += TS) out[o] += STG[o];
         else

@@ -175,7 +175,9 @@ ClassInfo class_info() {
   c.jreg = C::JREG ? 1 : 0;
   c.lds = C::STORE_LDS;
   c.store = &launch_store<LP, LA, LB>;
-  if constexpr (LP <= 1) c.store_cart = &launch_store<LP, LA, LB>;  // npure = ncart
+  // Cartesian-ket kernels of l <= 1 (the launches of the lower-degree terms
+  // of l = 2, 3 run here); those of l >= 2 are registered by inst_cart_lp*
+  if constexpr (LP <= 1) c.store_cart = &launch_store_cart<LP, LA, LB>;
   c.jfn = &launch_J<LP, LA, LB>;
   c.jq = &launch_Jq<LP, LA, LB>;
   c.gam = &launch_gam<LP, LA, LB>;
