@@ -92,8 +92,12 @@ enum { PS_PAX = 0, PS_PAY, PS_PAZ, PS_RPX, PS_RPY, PS_RPZ, PS_I2G, PS_RG, PS_N }
 // VRR1 over one chunk of primitives, 2-quantal stages in place (Section 2.5.3).
 // prim(pp) points at the record of primitive pp: [PS_N scalars][T region][W region].
 // On entry level 0 is stored (T[0] = m=LP, W[0..L-1] = m=LP+1..LP+L).
+// vt0 / vt1 (optional): the table's item records staged in LDS by the
+// kernel (words 0-3 and 4-5 of each 32-byte record), read there instead of
+// from global memory.
 template <class G, int TS, int PCH, int REC>
-__device__ __forceinline__ void vrr1(double *prims, int npc, int tid) {
+__device__ __forceinline__ void vrr1(double *prims, int npc, int tid, const uint4 *vt0 = nullptr,
+                                     const uint2 *vt1 = nullptr) {
   constexpr int L = G::L;
   using S = VStages<L>;
   static_for<S::nstage>([&](auto sc) {
@@ -117,8 +121,17 @@ __device__ __forceinline__ void vrr1(double *prims, int npc, int tid) {
         const double *P = prims + pp * REC;
         const double *T = P + PS_N;
         // the 32-byte item record in two 16-byte loads; all fields are >= 0
-        const uint4 *vp = reinterpret_cast<const uint4 *>(&V::ofs[IOFF + x]);
-        const uint4 w0 = vp[0], w1 = vp[1];
+        uint4 w0;
+        uint2 w1;
+        if (vt0) {
+          w0 = vt0[IOFF + x];
+          w1 = vt1[IOFF + x];
+        } else {
+          const uint4 *vp = reinterpret_cast<const uint4 *>(&V::ofs[IOFF + x]);
+          w0 = vp[0];
+          const uint4 t1 = vp[1];
+          w1 = make_uint2(t1.x, t1.y);
+        }
         const int u0 = w0.x & 0xffff, u1o = w0.x >> 16, u2 = w0.y & 0xffff, l0 = w0.y >> 16;
         const int l1o = w0.z & 0xffff, l2 = w0.z >> 16, y0 = w0.w & 0xffff, y1 = w0.w >> 16;
         const int od = w1.x & 0xffff, ax = w1.x >> 16, f1 = w1.y & 0xffff, f2 = w1.y >> 16;
@@ -145,6 +158,20 @@ __device__ __forceinline__ void vrr1(double *prims, int npc, int tid) {
       if (dst[q] >= 0) prims[dst[q]] = res[q];
     team_sync();
   });
+}
+
+// Stage the VRR1 item records of level L into LDS (all threads of the
+// workgroup; the caller synchronises): vt0[r] = words 0-3, vt1[r] = words 4-5.
+template <int L>
+__device__ __forceinline__ void stage_vrr1_table(uint4 *vt0, uint2 *vt1) {
+  using V = GenV<L>;
+  constexpr int N = VStages<L>::NITEMS;
+  for (int r = threadIdx.x; r < N; r += blockDim.x) {
+    const uint4 *vp = reinterpret_cast<const uint4 *>(&V::ofs[r]);
+    vt0[r] = vp[0];
+    const uint4 t1 = vp[1];
+    vt1[r] = make_uint2(t1.x, t1.y);
+  }
 }
 
 }  // namespace df3c

@@ -215,6 +215,11 @@ struct Cfg {
       imax(Layout<LP, LA, LB, PCH, true>::TOTAL,
            LA > LB ? Layout<LP, LB, LA, PCH, true>::TOTAL : 0) | 1;
   static constexpr int STORE_LDS_C = (BLK / TS) * STORE_TEAM_C * 8;
+  // the store kernels stage the VRR1 item records in LDS after the team
+  // slices (words 0-3 and 4-5 of each record, 16-byte aligned)
+  static constexpr int VT_BYTES = VStages<LA + LB>::NITEMS * 24;
+  static constexpr int STORE_LDS_V = ((BLK / TS) * STORE_TEAM * 8 + 15) / 16 * 16 + VT_BYTES;
+  static constexpr int STORE_LDS_CV = ((BLK / TS) * STORE_TEAM_C * 8 + 15) / 16 * 16 + VT_BYTES;
   // minimum waves per SIMD requested from the register allocator
   static constexpr int WPE = TS >= 128 ? DF3C_MIN_WAVES_BIG : TS == 64 ? DF3C_MIN_WAVES_WAVE : 1;
   // J kernels: one lane per shell pair on the register engine, else the J
@@ -233,6 +238,8 @@ struct Cfg {
   static_assert(LDS <= 160 * 1024, "class does not fit the LDS of a CU");
   static_assert(STORE_LDS <= 160 * 1024, "class does not fit the LDS of a CU");
   static_assert(STORE_LDS_C <= 160 * 1024, "class does not fit the LDS of a CU");
+  static_assert(STORE_LDS_V <= 160 * 1024 && STORE_LDS_CV <= 160 * 1024,
+                "class does not fit the LDS of a CU");
 };
 
 // ---------------------------------------------------------------------------
@@ -577,7 +584,9 @@ __device__ __forceinline__ void triplet_to_e0P(const double *btab, double *S, in
                                                const double *ea, const double *ca, int Kb,
                                                const double *eb, const double *cb, int Kc,
                                                const double *ec, const double *cc, int pure,
-                                               int grp = 0, int cs = 0, int nkept = -1) {
+                                               int grp = 0, int cs = 0, int nkept = -1,
+                                               const uint4 *vt0 = nullptr,
+                                               const uint2 *vt1 = nullptr) {
   using G = Geo<LP, LA, LA + LB>;
   using LY = Layout<LP, LA, LB, PCH, CART>;
   using TB = GenTab<LP, G::EA, G::EB>;
@@ -618,7 +627,7 @@ __device__ __forceinline__ void triplet_to_e0P(const double *btab, double *S, in
                                 cc, grp, Ka, cs);
     team_sync();
     // ---- VRR1, 2-quantal stages in place
-    vrr1<G, TS, PCH, REC>(prims, npc, lt);
+    vrr1<G, TS, PCH, REC>(prims, npc, lt, vt0, vt1);
     // ---- early contraction of the CVRR2 prerequisites
     if constexpr (MF) {
       // lane (pl, il): primitive pl of the chunk, row / column il of a tile
@@ -699,35 +708,15 @@ __device__ __forceinline__ void triplet_to_e0P(const double *btab, double *S, in
     // interleaved across the lanes: uniform loops, coalesced table loads; all
     // table words of a block are loaded first, then all pi operands, so each
     // block waits for one table and one LDS latency
-    // The table words of a wave's next block are requested before the
-    // current block's operands are read, so each block's table latency
-    // overlaps the previous block's work (one exposed latency per wave).
     constexpr int MM = TB::CBM > 0 ? TB::CBM : 1;
     const int wv2 = tid >> 6, ln = tid & 63;
-    uint32_t cw[MM];
-    int t = 0xffff;
-    if (wv2 < TB::NCB) {
-      const int m = TB::cb_bm[wv2];
-      const uint32_t *w = TB::cb_il + TB::cb_boff[wv2] + ln;
+    for (int b = wv2; b < TB::NCB; b += NWV) {
+      const int t = TB::cb_tg[b * 64 + ln];
+      const int m = TB::cb_bm[b];
+      const uint32_t *w = TB::cb_il + TB::cb_boff[b] + ln;
+      uint32_t cw[MM];
 #pragma unroll
       for (int j = 0; j < MM; ++j) cw[j] = j < m ? w[j * 64] : 0u;
-      t = TB::cb_tg[wv2 * 64 + ln];
-    }
-    for (int b = wv2; b < TB::NCB; b += NWV) {
-      const int bn = b + NWV;
-      uint32_t nw[MM];
-      int tn = 0xffff;
-      if (bn < TB::NCB) {
-        const int mn = TB::cb_bm[bn];
-        const uint32_t *w = TB::cb_il + TB::cb_boff[bn] + ln;
-#pragma unroll
-        for (int j = 0; j < MM; ++j) nw[j] = j < mn ? w[j * 64] : 0u;
-        tn = TB::cb_tg[bn * 64 + ln];
-      } else {
-#pragma unroll
-        for (int j = 0; j < MM; ++j) nw[j] = 0u;
-      }
-      const int m = TB::cb_bm[b];
       double pv[MM];
 #pragma unroll
       for (int j = 0; j < MM; ++j) pv[j] = j < m ? PI[cw[j] & 0xffffu] : 0.0;
@@ -735,9 +724,6 @@ __device__ __forceinline__ void triplet_to_e0P(const double *btab, double *S, in
 #pragma unroll
       for (int j = 0; j < MM; ++j) a += double(cw[j] >> 16) * pv[j];
       if (t != 0xffff) PI[t] += a;
-#pragma unroll
-      for (int j = 0; j < MM; ++j) cw[j] = nw[j];
-      t = tn;
     }
   } else {
     for (int t = tid; t < TB::NTGT; t += TS) {
@@ -968,6 +954,14 @@ __global__ void __launch_bounds__(TS > 64 ? TS : 64)
   // (a compile-time 0 elsewhere keeps their Boys branch out of the pure kernels)
   const int cexp = CART ? a.cexp : 0;
   if (a.err && *a.err) return;
+  // the VRR1 item records, staged once per workgroup after the team slices
+  constexpr int STEAM = CART ? Cfg<LP, LA, LB>::STORE_TEAM_C : Cfg<LP, LA, LB>::STORE_TEAM;
+  constexpr int VTO = (TPB * STEAM * 8 + 15) / 16 * 16;
+  constexpr int NVT = VStages<LA + LB>::NITEMS;
+  uint4 *vt0 = reinterpret_cast<uint4 *>(reinterpret_cast<char *>(smem) + VTO);
+  uint2 *vt1 = reinterpret_cast<uint2 *>(reinterpret_cast<char *>(smem) + VTO + NVT * 16);
+  stage_vrr1_table<LA + LB>(vt0, vt1);
+  __syncthreads();
   const int64_t count = a.dcount ? int64_t(*a.dcount) : a.count;
   const uint32_t *bucket = a.bucket + (a.dstart ? *a.dstart : 0);
   int slot[NQ];
@@ -1045,7 +1039,7 @@ __global__ void __launch_bounds__(TS > 64 ? TS : 64)
                                           Ar, Br, Cr, Ka, ea, a.orb.coefs + oa, Kb, eb,
                                           a.orb.coefs + ob, run1 ? Kc : 0, a.aux.exps + oc,
                                           a.aux.coefs + oc, a.pure, run2 ? 1 : 0, cexp,
-                                          run2 ? n1 : nab);
+                                          run2 ? n1 : nab, vt0, vt1);
       hrr_block<LP, LA, LB, TS, PCH, CART>(S, tid, Ar, Br, np_out, swp);
       team_sync();
       if (run1) {
@@ -1067,7 +1061,7 @@ __global__ void __launch_bounds__(TS > 64 ? TS : 64)
                                           TS >= 64 ? K2 : wave_max(K2), Br, Ar, Cr, Kb, eb,
                                           a.orb.coefs + ob, Ka, ea, a.orb.coefs + oa,
                                           run2 ? Kc : 0, a.aux.exps + oc, a.aux.coefs + oc,
-                                          a.pure, 2, cexp, nab - n1);
+                                          a.pure, 2, cexp, nab - n1, vt0, vt1);
       hrr_block<LP, LB, LA, TS, PCH, CART>(S, tid, Br, Ar, np_out, !swp);
       team_sync();
       if (run2) {

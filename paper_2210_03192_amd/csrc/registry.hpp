@@ -42,9 +42,9 @@ hipError_t launch_store(const StoreArgs &a, int grid, hipStream_t s) {
   auto kern = k_store<LP, LA, LB, C::TS, C::PCH>;
   static const hipError_t attr = hipFuncSetAttribute(
       reinterpret_cast<const void *>(kern), hipFuncAttributeMaxDynamicSharedMemorySize,
-      C::STORE_LDS);
+      C::STORE_LDS_V);
   if (attr != hipSuccess) return attr;
-  hipLaunchKernelGGL(kern, dim3(grid), dim3(C::BLK), C::STORE_LDS, s, a);
+  hipLaunchKernelGGL(kern, dim3(grid), dim3(C::BLK), C::STORE_LDS_V, s, a);
   return hipGetLastError();
 }
 
@@ -54,9 +54,9 @@ hipError_t launch_store_cart(const StoreArgs &a, int grid, hipStream_t s) {
   auto kern = k_store<LP, LA, LB, C::TS, C::PCH, true>;
   static const hipError_t attr = hipFuncSetAttribute(
       reinterpret_cast<const void *>(kern), hipFuncAttributeMaxDynamicSharedMemorySize,
-      C::STORE_LDS_C);
+      C::STORE_LDS_CV);
   if (attr != hipSuccess) return attr;
-  hipLaunchKernelGGL(kern, dim3(grid), dim3(C::BLK), C::STORE_LDS_C, s, a);
+  hipLaunchKernelGGL(kern, dim3(grid), dim3(C::BLK), C::STORE_LDS_CV, s, a);
   return hipGetLastError();
 }
 
@@ -173,7 +173,7 @@ ClassInfo class_info() {
   c.tpw = C::BLK / C::TS;
   c.tpwj = C::BLKJ / C::TSJ;
   c.jreg = C::JREG ? 1 : 0;
-  c.lds = C::STORE_LDS;
+  c.lds = C::STORE_LDS_V;
   c.store = &launch_store<LP, LA, LB>;
   // Cartesian-ket kernels of l <= 1 (the launches of the lower-degree terms
   // of l = 2, 3 run here); those of l >= 2 are registered by inst_cart_lp*
