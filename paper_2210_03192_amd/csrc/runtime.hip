@@ -38,6 +38,24 @@ ClassInfo g_cls[NLP][NLA][NLA];
 GradInfo g_grad[NLP][NLG][NLG];
 MetricInfo g_metric[NLP][NLP];
 bool g_cls_ready = false;
+// held while a call enqueues its fork / join of the branch streams (the
+// events are per device: another thread's record between a fork and its
+// waits would redirect them)
+std::mutex g_branch_mu;
+
+// side streams and fork / join events of the concurrent (l_a, l_b) branches
+int ensure_branches(DevState *ds) {
+  if (ds->branches) return DF3C_OK;
+  std::lock_guard<std::mutex> lk(g_mu);
+  if (ds->branches) return DF3C_OK;
+  for (int b = 0; b < NBRANCH - 1; ++b)
+    if (hipStreamCreateWithFlags(&ds->side[b], hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&ds->join[b], hipEventDisableTiming) != hipSuccess)
+      return DF3C_E_HIP;
+  if (hipEventCreateWithFlags(&ds->fork, hipEventDisableTiming) != hipSuccess) return DF3C_E_HIP;
+  ds->branches = true;
+  return DF3C_OK;
+}
 
 }  // namespace
 
@@ -1140,7 +1158,7 @@ int coulomb_J_run(const double *xyz, int32_t natom, const df3c_shells *aux,
   a.nao = p.nao;
   a.pure = aux->pure;
   a.err = dp.err;
-  auto launch = [&](int lp, int la, int lb) -> int {
+  auto launch = [&](int lp, int la, int lb, hipStream_t ls) -> int {
     const int np = p.aux_start[lp + 1] - p.aux_start[lp];
     if (!np) return DF3C_OK;
     a.psh = dp.aux_sorted + p.aux_start[lp];
@@ -1149,8 +1167,8 @@ int coulomb_J_run(const double *xyz, int32_t natom, const df3c_shells *aux,
     const ClassInfo &ci = g_cls[lp][la][lb];
     const int c = (lp * NLA + la) * NLA + lb;
     a.nsub = reg_split(ci, a.npair, a.np, ds->ncu);
-    if (timed(DF3C_KERNEL_J, c, s, [&] {
-          return ci.jfn(a, grid_for(a.npair, ci.tpwj / a.nsub, ds->ncu), s);
+    if (timed(DF3C_KERNEL_J, c, ls, [&] {
+          return ci.jfn(a, grid_for(a.npair, ci.tpwj / a.nsub, ds->ncu), ls);
         }) != hipSuccess)
       return DF3C_E_HIP;
     return DF3C_OK;
@@ -1167,10 +1185,50 @@ int coulomb_J_run(const double *xyz, int32_t natom, const df3c_shells *aux,
     return na > 0 && nb > 0;
   };
   if (!mask) {
-    for (int lp = 0; lp <= DF3C_LMAX_AUX; ++lp)
-      for (int la = 0; la <= DF3C_LMAX_ORB; ++la)
-        for (int lb = 0; lb <= la; ++lb)
-          if (set_class(la, lb) && (rc = launch(lp, la, lb))) return rc;
+    // Classes of different (l_a, l_b) write disjoint J blocks: the groups run
+    // on NBRANCH concurrent streams forked from and joined back to s (also
+    // under capture, as parallel graph branches); inside a group the L_P
+    // classes keep ascending order, so every J element sums its classes in
+    // the same sequence as on one stream.  Groups go to branches longest
+    // first by a work model (pairs x aux functions x Cartesian pair size).
+    if ((rc = ensure_branches(ds))) return rc;
+    std::lock_guard<std::mutex> lk(g_branch_mu);
+    double gcost[NLA * NLA] = {}, load[NBRANCH] = {};
+    int branch_of[NLA * NLA] = {};
+    for (int la = 0; la <= DF3C_LMAX_ORB; ++la)
+      for (int lb = 0; lb <= la; ++lb) {
+        if (!set_class(la, lb)) continue;
+        for (int lp = 0; lp <= DF3C_LMAX_AUX; ++lp)
+          gcost[la * NLA + lb] += double(a.npair) * double(p.aux_start[lp + 1] - p.aux_start[lp]) *
+                                  (2 * lp + 1) * (la + 1) * (la + 2) * (lb + 1) * (lb + 2);
+      }
+    int gid[NLA * NLA];
+    for (int g = 0; g < NLA * NLA; ++g) gid[g] = g;
+    std::stable_sort(gid, gid + NLA * NLA, [&](int x, int y) { return gcost[x] > gcost[y]; });
+    for (int k = 0; k < NLA * NLA; ++k) {
+      int bmin = 0;
+      for (int b = 1; b < NBRANCH; ++b)
+        if (load[b] < load[bmin]) bmin = b;
+      branch_of[gid[k]] = bmin;
+      load[bmin] += gcost[gid[k]];
+    }
+    if (hipEventRecord(ds->fork, s) != hipSuccess) return DF3C_E_HIP;
+    for (int b = 0; b < NBRANCH - 1; ++b)
+      if (hipStreamWaitEvent(ds->side[b], ds->fork, 0) != hipSuccess) return DF3C_E_HIP;
+    int brc = DF3C_OK;
+    for (int la = 0; la <= DF3C_LMAX_ORB && !brc; ++la)
+      for (int lb = 0; lb <= la && !brc; ++lb) {
+        if (!set_class(la, lb)) continue;
+        const int br = branch_of[la * NLA + lb];
+        hipStream_t bs = br == 0 ? s : ds->side[br - 1];
+        for (int lp = 0; lp <= DF3C_LMAX_AUX && !brc; ++lp) brc = launch(lp, la, lb, bs);
+      }
+    // join every branch back to s, also after a failed launch
+    for (int b = 0; b < NBRANCH - 1; ++b)
+      if (hipEventRecord(ds->join[b], ds->side[b]) != hipSuccess ||
+          hipStreamWaitEvent(s, ds->join[b], 0) != hipSuccess)
+        return DF3C_E_HIP;
+    if (brc) return brc;
   } else {
     // masked: the kept pairs of every (l_a, l_b) class are compacted into the
     // class's list on the device; every launch is sized for the whole class
@@ -1210,7 +1268,7 @@ int coulomb_J_run(const double *xyz, int32_t natom, const df3c_shells *aux,
           if (!a.npair) continue;
         }
         for (int lp = 0; lp <= DF3C_LMAX_AUX; ++lp)
-          if ((rc = launch(lp, la, lb))) return rc;
+          if ((rc = launch(lp, la, lb, s))) return rc;
       }
   }
   if (orb->pure && p.npure) {
@@ -2352,18 +2410,10 @@ int df3c_coulomb_J_batched(const double *xyz, int32_t natom, const df3c_shells *
     return finish_call(flags, err, s);
   }
 
-  if ((flags & DF3C_SCHED_PERSISTENT) && !ds->branches) {
-    std::lock_guard<std::mutex> lk(g_mu);
-    if (!ds->branches) {
-      for (int b = 0; b < NBRANCH - 1; ++b)
-        if (hipStreamCreateWithFlags(&ds->side[b], hipStreamNonBlocking) != hipSuccess ||
-            hipEventCreateWithFlags(&ds->join[b], hipEventDisableTiming) != hipSuccess)
-          return fail(DF3C_E_HIP);
-      if (hipEventCreateWithFlags(&ds->fork, hipEventDisableTiming) != hipSuccess)
-        return fail(DF3C_E_HIP);
-      ds->branches = true;
-    }
-  }
+  if ((flags & DF3C_SCHED_PERSISTENT) && ensure_branches(ds)) return fail(DF3C_E_HIP);
+  // the fork / join events are per device (see g_branch_mu)
+  std::unique_lock<std::mutex> branch_lock(g_branch_mu, std::defer_lock);
+  if (flags & DF3C_SCHED_PERSISTENT) branch_lock.lock();
   // class launch order
   std::vector<int> order;
   for (int c = 0; c < NCLS; ++c)
