@@ -1184,20 +1184,22 @@ int coulomb_J_run(const double *xyz, int32_t natom, const df3c_shells *aux,
     a.npair = (la == lb) ? int64_t(na) * (na + 1) / 2 : int64_t(na) * nb;
     return na > 0 && nb > 0;
   };
-  if (!mask) {
-    // Classes of different (l_a, l_b) write disjoint J blocks: the groups run
-    // on NBRANCH concurrent streams forked from and joined back to s (also
-    // under capture, as parallel graph branches); inside a group the L_P
-    // classes keep ascending order, so every J element sums its classes in
-    // the same sequence as on one stream.  Groups go to branches longest
-    // first by a work model (pairs x aux functions x Cartesian pair size).
-    if ((rc = ensure_branches(ds))) return rc;
+  // Classes of different (l_a, l_b) write disjoint J blocks: the groups run
+  // on NBRANCH concurrent streams forked from and joined back to s (also
+  // under capture, as parallel graph branches); inside a group the L_P
+  // classes keep ascending order, so every J element sums its classes in
+  // the same sequence as on one stream.  Groups go to branches longest
+  // first by a work model (pairs x aux functions x Cartesian pair size).
+  // prep(la, lb) sets the group's arguments up and tells whether it runs.
+  auto run_branches = [&](auto prep) -> int {
+    int e = ensure_branches(ds);
+    if (e) return e;
     std::lock_guard<std::mutex> lk(g_branch_mu);
     double gcost[NLA * NLA] = {}, load[NBRANCH] = {};
     int branch_of[NLA * NLA] = {};
     for (int la = 0; la <= DF3C_LMAX_ORB; ++la)
       for (int lb = 0; lb <= la; ++lb) {
-        if (!set_class(la, lb)) continue;
+        if (!prep(la, lb)) continue;
         for (int lp = 0; lp <= DF3C_LMAX_AUX; ++lp)
           gcost[la * NLA + lb] += double(a.npair) * double(p.aux_start[lp + 1] - p.aux_start[lp]) *
                                   (2 * lp + 1) * (la + 1) * (la + 2) * (lb + 1) * (lb + 2);
@@ -1212,13 +1214,13 @@ int coulomb_J_run(const double *xyz, int32_t natom, const df3c_shells *aux,
       branch_of[gid[k]] = bmin;
       load[bmin] += gcost[gid[k]];
     }
-    if (hipEventRecord(ds->fork, s) != hipSuccess) return DF3C_E_HIP;
+    if (hipEventRecord(ds->fork, s) != hipSuccess) return int(DF3C_E_HIP);
     for (int b = 0; b < NBRANCH - 1; ++b)
-      if (hipStreamWaitEvent(ds->side[b], ds->fork, 0) != hipSuccess) return DF3C_E_HIP;
+      if (hipStreamWaitEvent(ds->side[b], ds->fork, 0) != hipSuccess) return int(DF3C_E_HIP);
     int brc = DF3C_OK;
     for (int la = 0; la <= DF3C_LMAX_ORB && !brc; ++la)
       for (int lb = 0; lb <= la && !brc; ++lb) {
-        if (!set_class(la, lb)) continue;
+        if (!prep(la, lb)) continue;
         const int br = branch_of[la * NLA + lb];
         hipStream_t bs = br == 0 ? s : ds->side[br - 1];
         for (int lp = 0; lp <= DF3C_LMAX_AUX && !brc; ++lp) brc = launch(lp, la, lb, bs);
@@ -1227,8 +1229,11 @@ int coulomb_J_run(const double *xyz, int32_t natom, const df3c_shells *aux,
     for (int b = 0; b < NBRANCH - 1; ++b)
       if (hipEventRecord(ds->join[b], ds->side[b]) != hipSuccess ||
           hipStreamWaitEvent(s, ds->join[b], 0) != hipSuccess)
-        return DF3C_E_HIP;
-    if (brc) return brc;
+        return int(DF3C_E_HIP);
+    return brc;
+  };
+  if (!mask) {
+    if ((rc = run_branches(set_class))) return rc;
   } else {
     // masked: the kept pairs of every (l_a, l_b) class are compacted into the
     // class's list on the device; every launch is sized for the whole class
@@ -1258,18 +1263,14 @@ int coulomb_J_run(const double *xyz, int32_t natom, const df3c_shells *aux,
     unsigned long long kept[NLA * NLA] = {};
     const bool sized = !(flags & DF3C_ASYNC);
     if (sized && read_back(kept, pcount, sizeof(kept), s) != hipSuccess) return DF3C_E_HIP;
-    for (int la = 0; la <= DF3C_LMAX_ORB; ++la)
-      for (int lb = 0; lb <= la; ++lb) {
-        if (!set_class(la, lb)) continue;
-        a.plist = plist + loff[la][lb];
-        a.pcount = reinterpret_cast<const int64_t *>(pcount + la * NLA + lb);
-        if (sized) {
-          a.npair = int64_t(kept[la * NLA + lb]);  // the kernels read *pcount
-          if (!a.npair) continue;
-        }
-        for (int lp = 0; lp <= DF3C_LMAX_AUX; ++lp)
-          if ((rc = launch(lp, la, lb, s))) return rc;
-      }
+    auto prep = [&](int la, int lb) {
+      if (!set_class(la, lb)) return false;
+      a.plist = plist + loff[la][lb];
+      a.pcount = reinterpret_cast<const int64_t *>(pcount + la * NLA + lb);
+      if (sized) a.npair = int64_t(kept[la * NLA + lb]);  // the kernels read *pcount
+      return a.npair > 0;
+    };
+    if ((rc = run_branches(prep))) return rc;
   }
   if (orb->pure && p.npure) {
     const int64_t n2 = p.npure * p.npure;
@@ -1632,11 +1633,9 @@ __global__ void k_gam_reduce_r(const double *partial, int32_t np, int32_t nsplit
 
 }  // namespace
 
-size_t df3c_coulomb_gamma_workspace(const df3c_shells *aux, const df3c_shells *orb) {
-  if (!shells_ok(aux) || !shells_ok(orb)) return 0;
-  DevState *ds = nullptr;
-  if (init_device(&ds)) return 0;
-  // the partials of the largest class plan
+namespace {
+// bytes of one branch's partial buffer: the partials of the largest class plan
+size_t gamma_partial_bytes(const df3c_shells *aux, const df3c_shells *orb, int ncu) {
   size_t part = 1;
   int64_t no[DF3C_LMAX_ORB + 1] = {}, na[DF3C_LMAX_AUX + 1] = {};
   for (int s = 0; s < orb->nshell; ++s)
@@ -1650,9 +1649,18 @@ size_t df3c_coulomb_gamma_workspace(const df3c_shells *aux, const df3c_shells *o
         const int64_t npair = la == lb ? no[la] * (no[la] + 1) / 2 : no[la] * no[lb];
         const int nout = aux->pure ? 2 * lp + 1 : (lp + 1) * (lp + 2) / 2;
         const int nacc = (lp + 1) * (lp + 2) / 2;
-        part = std::max(part, gam_reg_plan(npair, int(na[lp]), nacc, ds->ncu).partial_doubles(nout));
+        part = std::max(part, gam_reg_plan(npair, int(na[lp]), nacc, ncu).partial_doubles(nout));
       }
-  return jplan_bytes(orb->nshell, aux->nshell) + align256(sizeof(double) * part) +
+  return align256(sizeof(double) * part);
+}
+}  // namespace
+
+size_t df3c_coulomb_gamma_workspace(const df3c_shells *aux, const df3c_shells *orb) {
+  if (!shells_ok(aux) || !shells_ok(orb)) return 0;
+  DevState *ds = nullptr;
+  if (init_device(&ds)) return 0;
+  // one partial buffer per concurrent branch
+  return jplan_bytes(orb->nshell, aux->nshell) + NBRANCH * gamma_partial_bytes(aux, orb, ds->ncu) +
          pullback_bytes(orb);
 }
 
@@ -1700,16 +1708,56 @@ int df3c_coulomb_gamma(const double *xyz, int32_t natom, const df3c_shells *aux,
   a.D = D;
   a.nao = p.nao;
   a.pure = aux->pure;
-  a.partial = partial;
   a.err = dp.err;
-  for (int lp = 0; lp <= DF3C_LMAX_AUX; ++lp) {
+  // The classes of one aux l write disjoint gamma entries from those of any
+  // other: the L_P groups run on NBRANCH concurrent streams forked from and
+  // joined back to s, each branch with its own partial buffer, and inside a
+  // group the (l_a, l_b) classes keep their order (gamma is bitwise the
+  // one-stream result).  Groups go to branches longest first by a work model.
+  const size_t part_stride = gamma_partial_bytes(aux, orb, ds->ncu);
+  if ((rc = ensure_branches(ds))) return rc;
+  std::lock_guard<std::mutex> branch_lock(g_branch_mu);
+  int branch_of[DF3C_LMAX_AUX + 1] = {};
+  {
+    double gcost[DF3C_LMAX_AUX + 1] = {}, load[NBRANCH] = {};
+    for (int lp = 0; lp <= DF3C_LMAX_AUX; ++lp)
+      for (int la = 0; la <= DF3C_LMAX_ORB; ++la)
+        for (int lb = 0; lb <= la; ++lb) {
+          const double na = p.orb_start[la + 1] - p.orb_start[la];
+          const double nb = p.orb_start[lb + 1] - p.orb_start[lb];
+          gcost[lp] += (la == lb ? na * (na + 1) / 2 : na * nb) *
+                       double(p.aux_start[lp + 1] - p.aux_start[lp]) * (2 * lp + 1) * (la + 1) *
+                       (la + 2) * (lb + 1) * (lb + 2);
+        }
+    int gid[DF3C_LMAX_AUX + 1];
+    for (int g = 0; g <= DF3C_LMAX_AUX; ++g) gid[g] = g;
+    std::stable_sort(gid, gid + DF3C_LMAX_AUX + 1,
+                     [&](int x, int y) { return gcost[x] > gcost[y]; });
+    for (int k = 0; k <= DF3C_LMAX_AUX; ++k) {
+      int bmin = 0;
+      for (int b = 1; b < NBRANCH; ++b)
+        if (load[b] < load[bmin]) bmin = b;
+      branch_of[gid[k]] = bmin;
+      load[bmin] += gcost[gid[k]];
+    }
+  }
+  if (hipEventRecord(ds->fork, s) != hipSuccess) return DF3C_E_HIP;
+  for (int b = 0; b < NBRANCH - 1; ++b)
+    if (hipStreamWaitEvent(ds->side[b], ds->fork, 0) != hipSuccess) return DF3C_E_HIP;
+  int brc = DF3C_OK;
+  for (int lp = 0; lp <= DF3C_LMAX_AUX && !brc; ++lp) {
     const int np = p.aux_start[lp + 1] - p.aux_start[lp];
     if (!np) continue;
     const int nout = aux->pure ? 2 * lp + 1 : (lp + 1) * (lp + 2) / 2;
+    const int br = branch_of[lp];
+    hipStream_t bs = br == 0 ? s : ds->side[br - 1];
+    double *bpartial = reinterpret_cast<double *>(reinterpret_cast<char *>(partial) +
+                                                  size_t(br) * part_stride);
+    a.partial = bpartial;
     a.psh = aux_sorted + p.aux_start[lp];
     a.np = np;
-    for (int la = 0; la <= DF3C_LMAX_ORB; ++la)
-      for (int lb = 0; lb <= la; ++lb) {
+    for (int la = 0; la <= DF3C_LMAX_ORB && !brc; ++la)
+      for (int lb = 0; lb <= la && !brc; ++lb) {
         const int na = p.orb_start[la + 1] - p.orb_start[la];
         const int nb = p.orb_start[lb + 1] - p.orb_start[lb];
         if (!na || !nb) continue;
@@ -1729,13 +1777,21 @@ int df3c_coulomb_gamma(const double *xyz, int32_t natom, const df3c_shells *aux,
         a.prange = gp.prange;
         a.nrange = gp.nrange;
         const int grid = int(gp.nrange * gp.nsplit);
-        if (timed(DF3C_KERNEL_GAMMA, c, s, [&] { return ci.gam(a, grid, s); }) != hipSuccess)
-          return DF3C_E_HIP;
+        if (timed(DF3C_KERNEL_GAMMA, c, bs, [&] { return ci.gam(a, grid, bs); }) != hipSuccess) {
+          brc = DF3C_E_HIP;
+          break;
+        }
         const int nred = np * nout;
-        hipLaunchKernelGGL(k_gam_reduce_r, dim3((nred + 255) / 256), dim3(256), 0, s, partial, np,
-                           gp.nsplit, gp.nps, gp.nrange, nout, a.psh, aux_off, gamma, dp.err);
+        hipLaunchKernelGGL(k_gam_reduce_r, dim3((nred + 255) / 256), dim3(256), 0, bs, bpartial,
+                           np, gp.nsplit, gp.nps, gp.nrange, nout, a.psh, aux_off, gamma, dp.err);
       }
   }
+  // join every branch back to s, also after a failed launch
+  for (int b = 0; b < NBRANCH - 1; ++b)
+    if (hipEventRecord(ds->join[b], ds->side[b]) != hipSuccess ||
+        hipStreamWaitEvent(s, ds->join[b], 0) != hipSuccess)
+      return DF3C_E_HIP;
+  if (brc) return brc;
   return finish_call(flags, dp.err, s);
 }
 
@@ -1870,41 +1926,84 @@ int grad_run(const double *xyz, int32_t natom, const df3c_shells *aux, const df3
   unsigned long long kept[NLA * NLA] = {};
   const bool sized = mask && !(flags & DF3C_ASYNC);
   if (sized && read_back(kept, pcount, sizeof(kept), s) != hipSuccess) return DF3C_E_HIP;
-  const int grid_cap = ds->ncu * GRAD_GRID_PER_CU;
-  for (int lp = 0; lp <= DF3C_LMAX_AUX; ++lp) {
+  // The (l_a, l_b) groups run on NBRANCH concurrent streams forked from and
+  // joined back to s; each branch owns a quarter of the partial slots (the
+  // workgroups of its launches add into those), and inside a branch the
+  // classes keep their order, so every slot sums the same contributions in
+  // the same sequence on every call and the final fixed-order reduction is
+  // reproducible bit for bit.
+  auto prep = [&](int la, int lb) {
+    const int na = p.orb_start[la + 1] - p.orb_start[la];
+    const int nb = p.orb_start[lb + 1] - p.orb_start[lb];
+    if (!na || !nb) return false;
+    a.ash = dp.orb_sorted + p.orb_start[la];
+    a.bsh = dp.orb_sorted + p.orb_start[lb];
+    a.na = na;
+    a.nb = nb;
+    a.same = (la == lb);
+    a.npair = (la == lb) ? int64_t(na) * (na + 1) / 2 : int64_t(na) * nb;
+    if (mask) {
+      a.plist = plist + loff[la][lb];
+      a.pcount = reinterpret_cast<const int64_t *>(pcount + la * NLA + lb);
+      if (sized) a.npair = int64_t(kept[la * NLA + lb]);  // the kernels read *pcount
+    }
+    return a.npair > 0;
+  };
+  if ((rc = ensure_branches(ds))) return rc;
+  std::lock_guard<std::mutex> branch_lock(g_branch_mu);
+  int branch_of[NLA * NLA] = {};
+  {
+    double gcost[NLA * NLA] = {}, load[NBRANCH] = {};
+    for (int la = 0; la <= DF3C_LMAX_GRAD_ORB; ++la)
+      for (int lb = 0; lb <= la; ++lb) {
+        if (!prep(la, lb)) continue;
+        for (int lp = 0; lp <= DF3C_LMAX_AUX; ++lp)
+          gcost[la * NLA + lb] += double(a.npair) * double(p.aux_start[lp + 1] - p.aux_start[lp]) *
+                                  (lp + 1) * (lp + 2) * (la + 1) * (la + 2) * (lb + 1) * (lb + 2);
+      }
+    int gid[NLA * NLA];
+    for (int g = 0; g < NLA * NLA; ++g) gid[g] = g;
+    std::stable_sort(gid, gid + NLA * NLA, [&](int x, int y) { return gcost[x] > gcost[y]; });
+    for (int k = 0; k < NLA * NLA; ++k) {
+      int bmin = 0;
+      for (int b = 1; b < NBRANCH; ++b)
+        if (load[b] < load[bmin]) bmin = b;
+      branch_of[gid[k]] = bmin;
+      load[bmin] += gcost[gid[k]];
+    }
+  }
+  const int slots_b = nslot / NBRANCH;
+  if (hipEventRecord(ds->fork, s) != hipSuccess) return DF3C_E_HIP;
+  for (int b = 0; b < NBRANCH - 1; ++b)
+    if (hipStreamWaitEvent(ds->side[b], ds->fork, 0) != hipSuccess) return DF3C_E_HIP;
+  int brc = DF3C_OK;
+  for (int lp = 0; lp <= DF3C_LMAX_AUX && !brc; ++lp) {
     const int np = p.aux_start[lp + 1] - p.aux_start[lp];
     if (!np) continue;
     a.psh = dp.aux_sorted + p.aux_start[lp];
     a.np = np;
-    for (int la = 0; la <= DF3C_LMAX_GRAD_ORB; ++la)
-      for (int lb = 0; lb <= la; ++lb) {
-        const int na = p.orb_start[la + 1] - p.orb_start[la];
-        const int nb = p.orb_start[lb + 1] - p.orb_start[lb];
-        if (!na || !nb) continue;
-        a.ash = dp.orb_sorted + p.orb_start[la];
-        a.bsh = dp.orb_sorted + p.orb_start[lb];
-        a.na = na;
-        a.nb = nb;
-        a.same = (la == lb);
-        a.npair = (la == lb) ? int64_t(na) * (na + 1) / 2 : int64_t(na) * nb;
-        if (mask) {
-          a.plist = plist + loff[la][lb];
-          a.pcount = reinterpret_cast<const int64_t *>(pcount + la * NLA + lb);
-          if (sized) {
-            a.npair = int64_t(kept[la * NLA + lb]);  // the kernels read *pcount
-            if (!a.npair) continue;
-          }
-        }
+    for (int la = 0; la <= DF3C_LMAX_GRAD_ORB && !brc; ++la)
+      for (int lb = 0; lb <= la && !brc; ++lb) {
+        if (!prep(la, lb)) continue;
+        const int br = branch_of[la * NLA + lb];
+        hipStream_t bs = br == 0 ? s : ds->side[br - 1];
+        a.partial = partial + int64_t(br) * slots_b * 3 * natom;
         const GradInfo &gi = g_grad[lp][la][lb];
         const int lds = gi.tpb * (gi.team + 3 * natom) * 8;
         a.nsplit = grad_split(gi, a.npair, np, ds->ncu);
         const int64_t blocks = (a.npair + gi.ppw - 1) / gi.ppw * a.nsplit;
-        const int grid = int(std::max<int64_t>(1, std::min<int64_t>(blocks, grid_cap)));
-        if (timed(DF3C_KERNEL_GRAD, (lp * NLA + la) * NLA + lb, s,
-                  [&] { return gi.gfn(a, grid, lds, s); }) != hipSuccess)
-          return DF3C_E_HIP;
+        const int grid = int(std::max<int64_t>(1, std::min<int64_t>(blocks, slots_b)));
+        if (timed(DF3C_KERNEL_GRAD, (lp * NLA + la) * NLA + lb, bs,
+                  [&] { return gi.gfn(a, grid, lds, bs); }) != hipSuccess)
+          brc = DF3C_E_HIP;
       }
   }
+  // join every branch back to s, also after a failed launch
+  for (int b = 0; b < NBRANCH - 1; ++b)
+    if (hipEventRecord(ds->join[b], ds->side[b]) != hipSuccess ||
+        hipStreamWaitEvent(s, ds->join[b], 0) != hipSuccess)
+      return DF3C_E_HIP;
+  if (brc) return brc;
   const int n = 3 * natom;
   hipLaunchKernelGGL(k_reduce_partial, dim3((n + 255) / 256), dim3(256), 0, s, partial, nslot, n,
                      grad);
