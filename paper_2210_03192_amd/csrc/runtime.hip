@@ -543,25 +543,63 @@ int df3c_eval_batch(const double *xyz, int32_t natom, const df3c_shells *aux,
   hipLaunchKernelGGL(k_scan, dim3(1), dim3(64), 0, s, hist, cursor, nullptr);
   hipLaunchKernelGGL(k_scatter, dim3(g), dim3(256), 0, s, trip, ntrip, orb->l, dev_shells(orb),
                      cls, cursor, bucket, err);
+  // The classes of a batch write disjoint blocks: a batch of several classes
+  // runs them on NBRANCH concurrent streams forked from and joined back to s
+  // (largest first by triplets x block size; the launches of one class, its
+  // Cartesian lower-degree terms included, stay in order on one branch).
+  int present = 0;
+  for (int c = 0; c < NCLS; ++c) present += rb[c] ? 1 : 0;
+  const bool branched = present > 1;
+  int branch_of[NCLS] = {};
+  std::unique_lock<std::mutex> branch_lock(g_branch_mu, std::defer_lock);
+  if (branched) {
+    if ((rc = ensure_branches(ds))) return rc;
+    branch_lock.lock();
+    double cost[NCLS] = {}, load[NBRANCH] = {};
+    int cid[NCLS];
+    for (int c = 0; c < NCLS; ++c) {
+      const int lp = c / (NLA * NLA), la = (c / NLA) % NLA, lb = c % NLA;
+      cost[c] = double(rb[c]) * (lp + 1) * (lp + 2) * (la + 1) * (la + 2) * (lb + 1) * (lb + 2);
+      cid[c] = c;
+    }
+    std::stable_sort(cid, cid + NCLS, [&](int x, int y) { return cost[x] > cost[y]; });
+    for (int k = 0; k < NCLS; ++k) {
+      int bmin = 0;
+      for (int b = 1; b < NBRANCH; ++b)
+        if (load[b] < load[bmin]) bmin = b;
+      branch_of[cid[k]] = bmin;
+      load[bmin] += cost[cid[k]];
+    }
+    if (hipEventRecord(ds->fork, s) != hipSuccess) return DF3C_E_HIP;
+    for (int b = 0; b < NBRANCH - 1; ++b)
+      if (hipStreamWaitEvent(ds->side[b], ds->fork, 0) != hipSuccess) return DF3C_E_HIP;
+  }
   int64_t off = 0;
-  for (int c = 0; c < NCLS; ++c) {
+  int brc = DF3C_OK;
+  for (int c = 0; c < NCLS && !brc; ++c) {
     if (!rb[c]) continue;
     const int lp = c / (NLA * NLA), la = (c / NLA) % NLA, lb = c % NLA;
+    hipStream_t bs = (!branched || branch_of[c] == 0) ? s : ds->side[branch_of[c] - 1];
     a.bucket = bucket + off;
     a.count = rb[c];
     // a Cartesian aux shell of l >= 2: the launches of classes l - 2, l - 4, ...
     // add the lower-degree terms of its expansion into the same blocks
-    for (int cs = 0; cs <= (aux->pure ? 0 : lp / 2); ++cs) {
+    for (int cs = 0; cs <= (aux->pure ? 0 : lp / 2) && !brc; ++cs) {
       const ClassInfo &ci = g_cls[lp - 2 * cs][la][lb];
       a.cexp = cs;
       auto fn = aux->pure ? ci.store : ci.store_cart;
-      if (timed(DF3C_KERNEL_STORE, c, s,
-                [&] { return fn(a, grid_for(rb[c], ci.tpw, ds->ncu), s); }) != hipSuccess)
-        return DF3C_E_HIP;
+      if (timed(DF3C_KERNEL_STORE, c, bs,
+                [&] { return fn(a, grid_for(rb[c], ci.tpw, ds->ncu), bs); }) != hipSuccess)
+        brc = DF3C_E_HIP;
     }
     off += rb[c];
   }
-  return DF3C_OK;
+  if (branched)
+    for (int b = 0; b < NBRANCH - 1; ++b)
+      if (hipEventRecord(ds->join[b], ds->side[b]) != hipSuccess ||
+          hipStreamWaitEvent(s, ds->join[b], 0) != hipSuccess)
+        return DF3C_E_HIP;
+  return brc;
 }
 
 // ------------------------------------------------------------------- DF-J
