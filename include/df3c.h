@@ -30,7 +30,15 @@
  * (its read-only tables, the Boys table included, are part of its code
  * object).  Calls that read counts or status words back take a small pinned
  * host slot of their own from a pool (allocated on first use, a few hundred
- * bytes each).  All device work is enqueued on `stream`.
+ * bytes each).  All device work is ordered on `stream`: the calls whose class
+ * groups write disjoint outputs (J, masked J, the gradient, gamma, a
+ * mixed-class eval_batch, the batched DF-J) fork them onto three internal side
+ * streams of the device (default priority, created on first use) and join
+ * them back to `stream` before returning, so a call's work still starts after
+ * `stream`'s earlier work and ends before its later work, also under graph
+ * capture (the branches become parallel graph branches).  The fork and join
+ * are enqueued under a per-device lock; calls from several host threads on one
+ * device share the side streams and serialise there.
  *
  * Errors: every function returns DF3C_OK (0) or a negative status; no C++
  * exception crosses the ABI.  After an error the outputs are unspecified.
