@@ -11,6 +11,9 @@
 //                  the transposed copy into the upper triangle;
 //   k_chol_update  A22 -= L21 L21^T on the lower triangle, 64 x 64 output tiles
 //                  (256 threads, 4 x 4 outputs each, L21 rows staged in LDS).
+// The solves run block by block: k_trsv_block solves a block's triangle (one
+// workgroup), k_trsv_update subtracts its contribution from every row still
+// to be solved (one wavefront per row).
 // A pivot below DBL_EPSILON x max_i V_ii (or NaN) stops the factorisation:
 // bit 16 of the status word, and every later kernel does nothing.
 #include <hip/hip_runtime.h>
@@ -183,31 +186,21 @@ __global__ void __launch_bounds__(256) k_chol_update(double *V, int64_t n, int64
 }
 
 // One block of a triangular solve with the rows of V: lower (L y = b,
-// blocks in increasing order, columns 0..k-1 already solved) or upper
-// (L^T x = y, blocks in decreasing order, columns k+nb..n-1 already solved).
-// One workgroup: the block's residual r = b_k - sum over the solved columns
-// (4 lanes per row, fixed-order partial sums), then the nb x nb triangle in
-// order.
+// blocks in increasing order) or upper (L^T x = y, blocks in decreasing
+// order).  The contributions of the solved blocks are already subtracted
+// (k_trsv_update after each block); one workgroup solves the nb x nb triangle
+// in order.
 __global__ void __launch_bounds__(256) k_trsv_block(const double *V, int64_t n, int64_t k,
                                                    int nb, int upper, double *x, const int *err) {
-  __shared__ double part[CB][4];
   __shared__ double r[CB];
   __shared__ double D[CB][CB + 1];
   if (*err) return;
-  const int t = threadIdx.x, row = t / 4, lane = t % 4;
+  const int t = threadIdx.x;
   for (int e = t; e < nb * nb; e += 256) {
     const int i = e / nb, j = e - i * nb;
     D[i][j] = V[(k + i) * n + k + j];
   }
-  if (row < nb) {
-    const double *vr = V + (k + row) * n;
-    const int64_t c0 = upper ? k + nb : 0, c1 = upper ? n : k;
-    double s = 0.0;
-    for (int64_t c = c0 + lane; c < c1; c += 4) s += vr[c] * x[c];
-    part[row][lane] = s;
-  }
-  __syncthreads();
-  if (t < nb) r[t] = x[k + t] - ((part[t][0] + part[t][1]) + (part[t][2] + part[t][3]));
+  if (t < nb) r[t] = x[k + t];
   __syncthreads();
   if (t == 0) {
     if (!upper) {
@@ -226,6 +219,28 @@ __global__ void __launch_bounds__(256) k_trsv_block(const double *V, int64_t n, 
   }
   __syncthreads();
   if (t < nb) x[k + t] = r[t];
+}
+
+// Right-looking update of the triangular solves after block k (width nb) is
+// solved: every row i still to be solved (lower: i >= k + nb; upper: i < k)
+// subtracts sum_q V[i][k + q] x[k + q].  One wavefront per row at a time (the
+// row's nb entries are contiguous, one per lane), summed by a fixed butterfly,
+// so every x_i receives the blocks' contributions in the same order on every
+// call.
+__global__ void __launch_bounds__(256) k_trsv_update(const double *V, int64_t n, int64_t k,
+                                                    int nb, int upper, double *x, const int *err) {
+  if (*err) return;
+  const int lane = threadIdx.x & 63;
+  const int64_t wave = (int64_t(blockIdx.x) * blockDim.x + threadIdx.x) >> 6;
+  const int64_t nwave = (int64_t(gridDim.x) * blockDim.x) >> 6;
+  const double xk = lane < nb ? x[k + lane] : 0.0;
+  const int64_t r0 = upper ? 0 : k + nb, r1 = upper ? k : n;
+  for (int64_t i = r0 + wave; i < r1; i += nwave) {
+    double v = lane < nb ? V[i * n + k + lane] * xk : 0.0;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    if (lane == 0) x[i] -= v;
+  }
 }
 
 __global__ void k_copy_vec(const double *a, double *b, int64_t n, const int *err) {
@@ -274,12 +289,24 @@ int df3c_fit_solve(double *V, int64_t n, const double *rhs, double *x, void *ws,
   if (x != rhs)
     hipLaunchKernelGGL(k_copy_vec, dim3(int(std::min<int64_t>((n + 255) / 256, 1024))), dim3(256),
                        0, s, rhs, x, n, err);
-  for (int64_t k = 0; k < n; k += CB)
-    hipLaunchKernelGGL(k_trsv_block, dim3(1), dim3(256), 0, s, V, n, k,
-                       int(std::min<int64_t>(CB, n - k)), 0, x, err);
-  for (int64_t k = ((n - 1) / CB) * CB; k >= 0; k -= CB)
-    hipLaunchKernelGGL(k_trsv_block, dim3(1), dim3(256), 0, s, V, n, k,
-                       int(std::min<int64_t>(CB, n - k)), 1, x, err);
+  // per block: solve its triangle, then update the rows still to be solved
+  auto upd_grid = [](int64_t rows) {
+    return int(std::max<int64_t>(1, std::min<int64_t>((rows + 3) / 4, 2048)));
+  };
+  for (int64_t k = 0; k < n; k += CB) {
+    const int nb = int(std::min<int64_t>(CB, n - k));
+    hipLaunchKernelGGL(k_trsv_block, dim3(1), dim3(256), 0, s, V, n, k, nb, 0, x, err);
+    if (k + nb < n)
+      hipLaunchKernelGGL(k_trsv_update, dim3(upd_grid(n - k - nb)), dim3(256), 0, s, V, n, k, nb,
+                         0, x, err);
+  }
+  for (int64_t k = ((n - 1) / CB) * CB; k >= 0; k -= CB) {
+    const int nb = int(std::min<int64_t>(CB, n - k));
+    hipLaunchKernelGGL(k_trsv_block, dim3(1), dim3(256), 0, s, V, n, k, nb, 1, x, err);
+    if (k > 0)
+      hipLaunchKernelGGL(k_trsv_update, dim3(upd_grid(k)), dim3(256), 0, s, V, n, k, nb, 1, x,
+                         err);
+  }
   if (hipGetLastError() != hipSuccess) return DF3C_E_HIP;
   if (flags & DF3C_ASYNC) return DF3C_OK;
   int word = 0;
