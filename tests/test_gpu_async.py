@@ -127,3 +127,46 @@ def test_device_checks_leave_status_in_workspace():
     # and the library still works after the failed calls
     J = df3c.coulomb_J(g.xyz, g.aux, g.orb, d).cpu().numpy()
     assert_parity(J, oracle.coulomb_J(s.xyz, s.aux, s.orb, d.cpu().numpy()), what="after errors")
+
+
+def test_concurrent_host_threads_match_serial_calls():
+    """Two host threads call DF-J, gamma and the gradient at the same time on
+    their own streams (the calls fork their class groups onto the device's
+    shared side streams under a lock): every result equals the one-thread
+    result bitwise."""
+    import threading
+    torch = _torch()
+    from paper_2210_03192_amd import df3c
+    s = inputs.water_cluster(4, seed=inputs.SEED_BASE + 330)
+    g = GpuSystem(s.xyz, s.aux, s.orb)
+    ds = [torch.as_tensor(inputs.fitting_coefficients(s.aux.nbf, 331 + k), device="cuda")
+          for k in range(2)]
+    G = torch.as_tensor(inputs.symmetric_density(s.orb.nbf, 333), device="cuda")
+
+    def calls(d, stream=None):
+        return (df3c.coulomb_J(g.xyz, g.aux, g.orb, d, stream=stream),
+                df3c.coulomb_gamma(g.xyz, g.aux, g.orb, G, stream=stream),
+                df3c.coulomb_J_grad(g.xyz, g.aux, g.orb, d, G, stream=stream))
+    ref = [calls(d) for d in ds]
+    torch.cuda.synchronize()
+    out, errs = [None, None], []
+
+    def worker(k):
+        try:
+            st = torch.cuda.Stream()
+            with torch.cuda.stream(st):
+                res = [calls(ds[k], stream=st) for _ in range(3)]
+            st.synchronize()
+            out[k] = res
+        except Exception as e:  # surfaced below
+            errs.append(e)
+    th = [threading.Thread(target=worker, args=(k,)) for k in range(2)]
+    for t in th:
+        t.start()
+    for t in th:
+        t.join()
+    assert not errs, errs
+    for k in range(2):
+        for res in out[k]:
+            for a, b in zip(res, ref[k]):
+                assert torch.equal(a, b)
