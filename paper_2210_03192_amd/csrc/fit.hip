@@ -60,13 +60,16 @@ __global__ void __launch_bounds__(256) k_diag_max(const double *V, int64_t n, do
   if (threadIdx.x == 0) *dmax = m[0];
 }
 
-// Cholesky of the nb x nb diagonal block at (k, k), in place (lower)
+// Cholesky of the nb x nb diagonal block at (k, k), in place (lower).  Per
+// column j: the pivot, the column scaled, then the rank-1 update of the
+// trailing triangle with a fixed 16 x 16 thread grid (thread (ty, tx) owns the
+// entries (i, c) with i = ty mod 16, c = tx mod 16), no index division.
 __global__ void __launch_bounds__(256) k_chol_diag(double *V, int64_t n, int64_t k, int nb,
                                                   const double *dmax, int *err) {
   __shared__ double A[CB][CB + 1];
   __shared__ int fail;
   if (*err) return;
-  const int t = threadIdx.x;
+  const int t = threadIdx.x, ty = t >> 4, tx = t & 15;
   for (int x = t; x < nb * nb; x += 256) {
     const int i = x / nb, j = x - i * nb;
     A[i][j] = j <= i ? V[(k + i) * n + k + j] : 0.0;
@@ -75,20 +78,21 @@ __global__ void __launch_bounds__(256) k_chol_diag(double *V, int64_t n, int64_t
   __syncthreads();
   const double tol = DBL_EPSILON * *dmax;
   for (int j = 0; j < nb; ++j) {
-    if (t == 0) {
-      const double p = A[j][j];
-      if (!(p > tol)) fail = 1;
-      A[j][j] = sqrt(fmax(p, tol));
-    }
+    // every thread takes the pivot itself (same value in every lane)
+    const double p = A[j][j];
+    const double piv = sqrt(fmax(p, tol));
+    const double rpiv = 1.0 / piv;
     __syncthreads();
-    const double piv = A[j][j];
-    for (int i = j + 1 + t; i < nb; i += 256) A[i][j] /= piv;
+    if (t == 0) {
+      if (!(p > tol)) fail = 1;
+      A[j][j] = piv;
+    }
+    if (t > j && t < nb) A[t][j] *= rpiv;
     __syncthreads();
     // rank-1 update of the rest of the block's lower triangle
-    const int m = nb - j - 1;
-    for (int x = t; x < m * m; x += 256) {
-      const int i = j + 1 + x / m, c = j + 1 + x % m;
-      if (c <= i) A[i][c] -= A[i][j] * A[c][j];
+    for (int i = j + 1 + ty; i < nb; i += 16) {
+      const double aij = A[i][j];
+      for (int c = j + 1 + tx; c <= i; c += 16) A[i][c] -= aij * A[c][j];
     }
     __syncthreads();
   }
@@ -202,22 +206,23 @@ __global__ void __launch_bounds__(256) k_trsv_block(const double *V, int64_t n, 
   }
   if (t < nb) r[t] = x[k + t];
   __syncthreads();
-  if (t == 0) {
-    if (!upper) {
-      for (int j = 0; j < nb; ++j) {
-        double v = r[j];
-        for (int q = 0; q < j; ++q) v -= D[j][q] * r[q];
-        r[j] = v / D[j][j];
-      }
-    } else {
-      for (int j = nb - 1; j >= 0; --j) {
-        double v = r[j];
-        for (int q = j + 1; q < nb; ++q) v -= D[j][q] * r[q];
-        r[j] = v / D[j][j];
-      }
+  // column by column: the solved entry, then every later row subtracts its
+  // share (lane i owns row i; the subtractions of row i come in column order)
+  if (!upper) {
+    for (int j = 0; j < nb; ++j) {
+      if (t == j) r[j] /= D[j][j];
+      __syncthreads();
+      if (t > j && t < nb) r[t] -= D[t][j] * r[j];
+      __syncthreads();
+    }
+  } else {
+    for (int j = nb - 1; j >= 0; --j) {
+      if (t == j) r[j] /= D[j][j];
+      __syncthreads();
+      if (t < j) r[t] -= D[t][j] * r[j];
+      __syncthreads();
     }
   }
-  __syncthreads();
   if (t < nb) x[k + t] = r[t];
 }
 
