@@ -21,6 +21,7 @@
 #include <algorithm>
 #include <cfloat>
 #include <cstdint>
+#include <mutex>
 
 #include "../../include/df3c.h"
 
@@ -143,16 +144,28 @@ __global__ void __launch_bounds__(256) k_chol_panel(double *V, int64_t n, int64_
 // A22[i][j] -= sum_q L21[i][q] L21[j][q] for k + nb <= j <= i < n: tiles of
 // the lower triangle, one per workgroup (tile (ti, tj), tj <= ti, from the
 // workgroup index); 256 threads x 4 x 4 outputs; the rows of both tiles are
-// staged UK columns at a time
+// staged UK columns at a time.  part 1: only the tiles of the first tile
+// column (tj = 0, the next block column: the look-ahead); part 2: the others
+// (tj >= 1); part 0: all.
 __global__ void __launch_bounds__(256) k_chol_update(double *V, int64_t n, int64_t k, int nb,
-                                                    const int *err) {
+                                                    int part, const int *err) {
   __shared__ double Ri[UT][UK + 1], Rj[UT][UK + 1];
   if (*err) return;
   const int64_t b = blockIdx.x;
-  int64_t ti = int64_t((sqrt(8.0 * double(b) + 1.0) - 1.0) * 0.5);
-  while (ti * (ti + 1) / 2 > b) --ti;
-  while ((ti + 1) * (ti + 2) / 2 <= b) ++ti;
-  const int64_t tj = b - ti * (ti + 1) / 2;
+  int64_t ti, tj;
+  if (part == 1) {
+    ti = b;
+    tj = 0;
+  } else {
+    ti = int64_t((sqrt(8.0 * double(b) + 1.0) - 1.0) * 0.5);
+    while (ti * (ti + 1) / 2 > b) --ti;
+    while ((ti + 1) * (ti + 2) / 2 <= b) ++ti;
+    tj = b - ti * (ti + 1) / 2;
+    if (part == 2) {  // the triangle of tiles below and right of the first tile column
+      ++ti;
+      ++tj;
+    }
+  }
   const int64_t base = k + nb;
   const int64_t i0 = base + ti * UT, j0 = base + tj * UT;
   const int t = threadIdx.x, ty = t / 16, tx = t % 16;
@@ -260,6 +273,35 @@ __global__ void k_copy_vec(const double *a, double *b, int64_t n, const int *err
 
 using namespace df3c;
 
+namespace {
+// the factorisation's look-ahead: a side stream (default priority) and two
+// events per device, created on first use; the enqueue of a factorisation
+// holds the lock (the events are shared)
+struct FitSide {
+  bool ready = false;
+  hipStream_t side = nullptr;
+  hipEvent_t panel = nullptr, rest = nullptr;
+};
+constexpr int FIT_MAX_DEV = 64;
+FitSide g_fit[FIT_MAX_DEV];
+std::mutex g_fit_mu;
+
+int fit_side(FitSide **out) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= FIT_MAX_DEV) return DF3C_E_HIP;
+  FitSide &f = g_fit[dev];
+  if (!f.ready) {
+    if (hipStreamCreateWithFlags(&f.side, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&f.panel, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&f.rest, hipEventDisableTiming) != hipSuccess)
+      return DF3C_E_HIP;
+    f.ready = true;
+  }
+  *out = &f;
+  return DF3C_OK;
+}
+}  // namespace
+
 extern "C" {
 
 size_t df3c_fit_solve_workspace(int64_t n) {
@@ -279,16 +321,42 @@ int df3c_fit_solve(double *V, int64_t n, const double *rhs, double *x, void *ws,
   double *dmax = reinterpret_cast<double *>(static_cast<char *>(ws) + align256(sizeof(int) * 8));
   hipLaunchKernelGGL(k_fit_init, dim3(1), dim3(64), 0, s, err, dmax);
   hipLaunchKernelGGL(k_diag_max, dim3(1), dim3(256), 0, s, V, n, dmax, err);
-  for (int64_t k = 0; k < n; k += CB) {
-    const int nb = int(std::min<int64_t>(CB, n - k));
-    hipLaunchKernelGGL(k_chol_diag, dim3(1), dim3(256), 0, s, V, n, k, nb, dmax, err);
-    const int64_t m = n - k - nb;
-    if (m <= 0) continue;
-    const int gp = int(std::min<int64_t>((m + 255) / 256, 1024));
-    hipLaunchKernelGGL(k_chol_panel, dim3(gp), dim3(256), 0, s, V, n, k, nb, err);
-    const int64_t T = (m + UT - 1) / UT;
-    hipLaunchKernelGGL(k_chol_update, dim3(unsigned(T * (T + 1) / 2)), dim3(256), 0, s, V, n, k,
-                       nb, err);
+  // Look-ahead: per block column k, the diagonal block, the panel and the
+  // update of the next block column run on `stream`, the update of the rest
+  // of the trailing matrix on a side stream, so the next diagonal block and
+  // panel overlap it.  The next-column update of step k waits for the
+  // rest-update of step k - 1 (both write that column); the rest-update of
+  // step k waits for the panel of step k.  Every element still receives its
+  // updates in step order.
+  FitSide *fs = nullptr;
+  if (int rc = fit_side(&fs)) return rc;
+  {
+    std::lock_guard<std::mutex> lk(g_fit_mu);
+    bool pending = false;  // a rest-update has been recorded on fs->rest
+    if (hipEventRecord(fs->rest, s) != hipSuccess) return DF3C_E_HIP;
+    pending = true;
+    for (int64_t k = 0; k < n; k += CB) {
+      const int nb = int(std::min<int64_t>(CB, n - k));
+      hipLaunchKernelGGL(k_chol_diag, dim3(1), dim3(256), 0, s, V, n, k, nb, dmax, err);
+      const int64_t m = n - k - nb;
+      if (m <= 0) continue;
+      const int gp = int(std::min<int64_t>((m + 255) / 256, 1024));
+      hipLaunchKernelGGL(k_chol_panel, dim3(gp), dim3(256), 0, s, V, n, k, nb, err);
+      if (hipEventRecord(fs->panel, s) != hipSuccess) return DF3C_E_HIP;
+      const int64_t T = (m + UT - 1) / UT;
+      // the next block column, after the previous rest-update
+      if (pending && hipStreamWaitEvent(s, fs->rest, 0) != hipSuccess) return DF3C_E_HIP;
+      hipLaunchKernelGGL(k_chol_update, dim3(unsigned(T)), dim3(256), 0, s, V, n, k, nb, 1, err);
+      // the rest, on the side stream after this panel
+      if (T > 1) {
+        if (hipStreamWaitEvent(fs->side, fs->panel, 0) != hipSuccess) return DF3C_E_HIP;
+        hipLaunchKernelGGL(k_chol_update, dim3(unsigned((T - 1) * T / 2)), dim3(256), 0,
+                           fs->side, V, n, k, nb, 2, err);
+        if (hipEventRecord(fs->rest, fs->side) != hipSuccess) return DF3C_E_HIP;
+        pending = true;
+      }
+    }
+    if (hipStreamWaitEvent(s, fs->rest, 0) != hipSuccess) return DF3C_E_HIP;
   }
   // x = rhs, then L y = x and L^T x = y in place
   if (x != rhs)
