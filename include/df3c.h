@@ -33,8 +33,9 @@
  * bytes each).  All device work is ordered on `stream`: the calls whose class
  * groups write disjoint outputs (J, masked J, the gradient, gamma, a
  * mixed-class eval_batch, the batched DF-J) fork them onto three internal side
- * streams of the device (default priority, created on first use) and join
- * them back to `stream` before returning, so a call's work still starts after
+ * streams of the device (default priority, created on first use), and
+ * df3c_fit_solve runs its trailing updates on a side stream of its own; all
+ * of them join back to `stream` before returning, so a call's work still starts after
  * `stream`'s earlier work and ends before its later work, also under graph
  * capture (the branches become parallel graph branches).  The fork and join
  * are enqueued under a per-device lock; calls from several host threads on one
