@@ -63,11 +63,13 @@ struct JArgs {
 };
 
 // Aux-shell record, one per position of the sorted aux list, built once per
-// call: centre, primitive offset, contraction degree, atom (as doubles, exact)
-// and d' = T^T d_P, the Cartesian image of the shell's fitting coefficients
-// (d_P itself for a Cartesian aux basis), so that an engine's aux loop reads
-// one contiguous, aligned record instead of a chain of dependent loads.
-enum { AR_CX = 0, AR_CY, AR_CZ, AR_PRIM, AR_K, AR_ATOM, AR_DQ };
+// call: centre, primitive offset, contraction degree, atom (as doubles, exact),
+// exponent and coefficient of the first primitive, and d' = T^T d_P, the
+// Cartesian image of the shell's fitting coefficients (d_P itself for a
+// Cartesian aux basis), so that an engine's aux loop reads one contiguous,
+// aligned record instead of a chain of dependent loads (and an uncontracted
+// shell needs no further load at all).
+enum { AR_CX = 0, AR_CY, AR_CZ, AR_PRIM, AR_K, AR_ATOM, AR_Z0, AR_C0, AR_DQ };
 constexpr int AREC = AR_DQ + 28;  // doubles per record (d' of l <= 6)
 
 // LDS layout of one team (in doubles).  Regions are reused once dead:
@@ -1155,32 +1157,38 @@ __device__ __forceinline__ void jr_pair(const JArgs &a, bool valid, int sa, int 
 #pragma unroll
   for (int e = 0; e < NE; ++e) X[e] = 0.0;
 
+  // primitive pairs outermost: 1/gamma, P and the pair's exponential are
+  // formed once per primitive pair, not once per (primitive pair, aux shell);
   // the nsub lanes of the pair take every nsub-th aux shell
   const int nsub = a.nsub;
-  for (int ip = sub; ip < a.np; ip += nsub) {
-    const double *rc = a.arec + int64_t(ip) * AREC;
-    const double C[3] = {rc[AR_CX], rc[AR_CY], rc[AR_CZ]};
-    const int64_t po = int64_t(rc[AR_PRIM]);
-    const int Kc = int(rc[AR_K]);
-    const double *ec = a.aux.exps + po, *cc = a.aux.coefs + po;
-    double dq[NCP];
+  for (int ia = 0; ia < Ka; ++ia)
+    for (int ib = 0; ib < Kb; ++ib) {
+      const double za = ea[ia], zb = eb[ib];
+      const double g = za + zb, ig = 1.0 / g;
+      const double P[3] = {(za * A[0] + zb * B[0]) * ig, (za * A[1] + zb * B[1]) * ig,
+                           (za * A[2] + zb * B[2]) * ig};
+      const double PA[3] = {P[0] - A[0], P[1] - A[1], P[2] - A[2]};
+      const double eab = exp(-za * zb * ig * AB2) * ca[ia] * cb[ib];
+      for (int ip = sub; ip < a.np; ip += nsub) {
+        const double *rc = a.arec + int64_t(ip) * AREC;
+        const double C[3] = {rc[AR_CX], rc[AR_CY], rc[AR_CZ]};
+        const int64_t po = int64_t(rc[AR_PRIM]);
+        const int Kc = int(rc[AR_K]);
+        const double *ec = a.aux.exps + po, *cc = a.aux.coefs + po;
+        double zc = rc[AR_Z0], ccv = rc[AR_C0];
+        double dq[NCP];
 #pragma unroll
-    for (int c = 0; c < NCP; ++c) dq[c] = rc[AR_DQ + c];
-    for (int ia = 0; ia < Ka; ++ia)
-      for (int ib = 0; ib < Kb; ++ib) {
-        const double za = ea[ia], zb = eb[ib];
-        const double g = za + zb, ig = 1.0 / g;
-        const double P[3] = {(za * A[0] + zb * B[0]) * ig, (za * A[1] + zb * B[1]) * ig,
-                             (za * A[2] + zb * B[2]) * ig};
-        const double PA[3] = {P[0] - A[0], P[1] - A[1], P[2] - A[2]};
-        const double eab = exp(-za * zb * ig * AB2) * ca[ia] * cb[ib];
+        for (int c = 0; c < NCP; ++c) dq[c] = rc[AR_DQ + c];
         for (int ic = 0; ic < Kc; ++ic) {
-          const double zc = ec[ic];
+          if (ic > 0) {
+            zc = ec[ic];
+            ccv = cc[ic];
+          }
           const double PC[3] = {P[0] - C[0], P[1] - C[1], P[2] - C[2]};
           const double gz = g + zc, rho = g * zc / gz, rg = rho * ig, i2g = 0.5 * ig;
           const double T = rho * (PC[0] * PC[0] + PC[1] * PC[1] + PC[2] * PC[2]);
           // 2 pi^{5/2} / ((g+zc)^{1/2} g zc) exp(-za zb/g AB^2) x contraction coefficients
-          const double pre = 34.98683665524972497 / (sqrt(gz) * g * zc) * eab * cc[ic];
+          const double pre = 34.98683665524972497 / (sqrt(gz) * g * zc) * eab * ccv;
           const double RP[3] = {rg * PC[0], rg * PC[1], rg * PC[2]};
           double Fm[L + 1];
           boys<LP, L + 1>(a.boys, T, Fm);

@@ -865,6 +865,9 @@ __global__ void k_aux_records(const int32_t *sorted, int64_t n, const int32_t *l
     r[AR_PRIM] = double(aux.prim_off[s]);
     r[AR_K] = double(aux.nprim[s]);
     r[AR_ATOM] = double(at);
+    const bool has = aux.nprim[s] > 0;
+    r[AR_Z0] = has ? aux.exps[aux.prim_off[s]] : 0.0;
+    r[AR_C0] = has ? aux.coefs[aux.prim_off[s]] : 0.0;
     if (!d) continue;
     const double *dP = d + aux_off[s];
     switch (lsh[s]) {
