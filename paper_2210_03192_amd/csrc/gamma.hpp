@@ -24,6 +24,7 @@ struct GamArgs {
   const int32_t *ash, *bsh;   // orbital shells of l = LA / LB (sorted)
   int32_t na, nb, same;
   const int32_t *psh;         // aux shells of l = LP
+  const double *arec;         // their aux-shell records (AREC), aligned with psh
   int32_t np;
   const int64_t *ao_off;      // AO offset of each orbital shell
   const double *D;            // [nao][nao]
@@ -38,6 +39,23 @@ struct GamArgs {
   double *partial;            // [nrange][nsplit][nps][np_out]
   const int *err;             // device status word: nothing is done when it is non-zero
 };
+
+// Register engine with the primitive pairs outermost (l_P <= 2): the per-lane
+// accumulators y of up to NPS aux shells live in LDS, YBYTES per wavefront.
+template <int LP>
+struct GamSwap {
+  static constexpr bool ON = LP <= 2;
+  static constexpr int YBYTES = 12 * 1024;
+  static constexpr int NPS = ON ? YBYTES / (ncart(LP) * 64 * 8) : 0;
+};
+inline int gam_nps_cap(int lp) {
+  switch (lp) {
+    case 0: return GamSwap<0>::NPS;
+    case 1: return GamSwap<1>::NPS;
+    case 2: return GamSwap<2>::NPS;
+    default: return 0;
+  }
+}
 
 // pair q of the class -> (sa, sb)
 __device__ __forceinline__ void gam_pair(const GamArgs &g, int64_t q, int &sa, int &sb) {
@@ -138,119 +156,105 @@ __global__ void __launch_bounds__(64) k_gam_r(GamArgs g) {
           });
         });
       }
-      for (int ks = 0, ip = sub; ip < g.np; ++ks, ip += g.nsplit) {  // uniform over the wave
-        const int sP = g.psh[ip];
-        const int Kc = g.aux.nprim[sP];
-        const double *ec = g.aux.exps + g.aux.prim_off[sP], *cc = g.aux.coefs + g.aux.prim_off[sP];
-        const int icn = g.aux.atom[sP];
-        const double C[3] = {g.xyz[3 * icn], g.xyz[3 * icn + 1], g.xyz[3 * icn + 2]};
-        double y[NCP];
+      // one primitive triplet into y: primitive pair (gg, ig, P, PA, eab), aux
+      // primitive (zc, cz) at C
+      auto triplet = [&](const double zc, const double cz, const double *C, const double gg,
+                         const double ig, const double *P, const double *PA,
+                         const double eab, double *y) {
+        const double PC[3] = {P[0] - C[0], P[1] - C[1], P[2] - C[2]};
+        const double gz = gg + zc, rho = gg * zc / gz, rg = rho * ig, i2g = 0.5 * ig;
+        const double T = rho * (PC[0] * PC[0] + PC[1] * PC[1] + PC[2] * PC[2]);
+        const double pre = 34.98683665524972497 / (sqrt(gz) * gg * zc) * eab * cz;
+        const double RP[3] = {rg * PC[0], rg * PC[1], rg * PC[2]};
+        double Fm[L + 1];
+        boys<LP, L + 1>(g.boys, T, Fm);
+        double vr[R::NVR];
 #pragma unroll
-        for (int c = 0; c < NCP; ++c) y[c] = 0.0;
-        for (int ia = 0; ia < Ka; ++ia)
-          for (int ib = 0; ib < Kb; ++ib) {
-            const double za = ea[ia], zb = eb[ib];
-            const double gg = za + zb, ig = 1.0 / gg;
-            const double P[3] = {(za * A[0] + zb * B[0]) * ig, (za * A[1] + zb * B[1]) * ig,
-                                 (za * A[2] + zb * B[2]) * ig};
-            const double PA[3] = {P[0] - A[0], P[1] - A[1], P[2] - A[2]};
-            const double eab = exp(-za * zb * ig * AB2) * ca[ia] * cb[ib];
-            for (int ic = 0; ic < Kc; ++ic) {
-              const double zc = ec[ic];
-              const double PC[3] = {P[0] - C[0], P[1] - C[1], P[2] - C[2]};
-              const double gz = gg + zc, rho = gg * zc / gz, rg = rho * ig, i2g = 0.5 * ig;
-              const double T = rho * (PC[0] * PC[0] + PC[1] * PC[1] + PC[2] * PC[2]);
-              const double pre = 34.98683665524972497 / (sqrt(gz) * gg * zc) * eab * cc[ic];
-              const double RP[3] = {rg * PC[0], rg * PC[1], rg * PC[2]};
-              double Fm[L + 1];
-              boys<LP, L + 1>(g.boys, T, Fm);
-              double vr[R::NVR];
-#pragma unroll
-              for (int m = 0; m <= L; ++m) vr[m] = pre * Fm[m];
-              static_for<L>([&](auto lc) {
-                constexpr int l = decltype(lc)::value + 1;
-                static_for<ncart(l)>([&](auto cc_) {
-                  constexpr int c = decltype(cc_)::value;
-                  constexpr C3 e = cart(l, c);
-                  constexpr int i = rdir(e);
-                  constexpr int c1 = cidx(e[0] - (i == 0), e[1] - (i == 1), e[2] - (i == 2));
-                  constexpr int o1 = R::voff(l - 1) + c1 * (L - l + 2);
-                  constexpr int o = R::voff(l) + c * (L - l + 1);
-                  static_for<L - l + 1>([&](auto mc) {
-                    constexpr int m = decltype(mc)::value;
-                    double v = PA[i] * vr[o1 + m] - RP[i] * vr[o1 + m + 1];
-                    if constexpr (e[i] >= 2) {
-                      constexpr int c2 = cidx(e[0] - 2 * (i == 0), e[1] - 2 * (i == 1),
-                                              e[2] - 2 * (i == 2));
-                      constexpr int o2 = R::voff(l - 2) + c2 * (L - l + 3);
-                      v += double(e[i] - 1) * i2g * (vr[o2 + m] - rg * vr[o2 + m + 1]);
-                    }
-                    vr[o + m] = v;
-                  });
-                });
-              });
-              // G_u = sum_{e >= u} w_e e!/(e-u)! V_{e-u}
-              double Gu[R::NU];
-#pragma unroll
-              for (int u = 0; u < R::NU; ++u) Gu[u] = 0.0;
-              static_for<L - LA + 1>([&](auto lc) {
-                constexpr int le = LA + decltype(lc)::value;
-                static_for<ncart(le)>([&](auto ec_) {
-                  constexpr int ce = decltype(ec_)::value;
-                  constexpr C3 e = cart(le, ce);
-                  const double we = w[offT(le) - offT(LA) + ce];
-                  static_for<e[0] + 1>([&](auto xc) {
-                    constexpr int ux = decltype(xc)::value;
-                    static_for<e[1] + 1>([&](auto yc) {
-                      constexpr int uy = decltype(yc)::value;
-                      static_for<e[2] + 1>([&](auto zc_) {
-                        constexpr int uz = decltype(zc_)::value;
-                        constexpr int k = ux + uy + uz;
-                        if constexpr (k <= LP) {
-                          constexpr int lr = le - k;
-                          constexpr int cr = cidx(e[0] - ux, e[1] - uy, e[2] - uz);
-                          constexpr double f = double(falling(e[0], ux) * falling(e[1], uy) *
-                                                      falling(e[2], uz));
-                          Gu[offT(k) + cidx(ux, uy, uz)] +=
-                              (f * we) * vr[R::voff(lr) + cr * (L - lr + 1)];
-                        }
-                      });
-                    });
-                  });
-                });
-              });
-              // y_c += sum_{u <= c} C(c,u) s^{|u|} W^{c-u} G_u
-              const double s = rho * ig * (0.5 / zc), rz = rho / zc;
-              double wx[LP + 1], wy[LP + 1], wz[LP + 1], sk[R::KU + 1];
-              wx[0] = wy[0] = wz[0] = sk[0] = 1.0;
-#pragma unroll
-              for (int k = 1; k <= LP; ++k) {
-                wx[k] = wx[k - 1] * (rz * PC[0]);
-                wy[k] = wy[k - 1] * (rz * PC[1]);
-                wz[k] = wz[k - 1] * (rz * PC[2]);
+        for (int m = 0; m <= L; ++m) vr[m] = pre * Fm[m];
+        static_for<L>([&](auto lc) {
+          constexpr int l = decltype(lc)::value + 1;
+          static_for<ncart(l)>([&](auto cc_) {
+            constexpr int c = decltype(cc_)::value;
+            constexpr C3 e = cart(l, c);
+            constexpr int i = rdir(e);
+            constexpr int c1 = cidx(e[0] - (i == 0), e[1] - (i == 1), e[2] - (i == 2));
+            constexpr int o1 = R::voff(l - 1) + c1 * (L - l + 2);
+            constexpr int o = R::voff(l) + c * (L - l + 1);
+            static_for<L - l + 1>([&](auto mc) {
+              constexpr int m = decltype(mc)::value;
+              double v = PA[i] * vr[o1 + m] - RP[i] * vr[o1 + m + 1];
+              if constexpr (e[i] >= 2) {
+                constexpr int c2 = cidx(e[0] - 2 * (i == 0), e[1] - 2 * (i == 1),
+                                        e[2] - 2 * (i == 2));
+                constexpr int o2 = R::voff(l - 2) + c2 * (L - l + 3);
+                v += double(e[i] - 1) * i2g * (vr[o2 + m] - rg * vr[o2 + m + 1]);
               }
+              vr[o + m] = v;
+            });
+          });
+        });
+        // G_u = sum_{e >= u} w_e e!/(e-u)! V_{e-u}
+        double Gu[R::NU];
 #pragma unroll
-              for (int k = 1; k <= R::KU; ++k) sk[k] = sk[k - 1] * s;
-              static_for<R::KU + 1>([&](auto kc) {
-                constexpr int k = decltype(kc)::value;
-                static_for<ncart(k)>([&](auto uc) {
-                  constexpr int ui = decltype(uc)::value;
-                  constexpr C3 u = cart(k, ui);
-                  const double gk = sk[k] * Gu[offT(k) + ui];
-                  static_for<NCP>([&](auto cc_) {
-                    constexpr int c = decltype(cc_)::value;
-                    constexpr C3 qq = cart(LP, c);
-                    if constexpr (qq[0] >= u[0] && qq[1] >= u[1] && qq[2] >= u[2]) {
-                      constexpr double bn =
-                          double(binom(qq[0], u[0]) * binom(qq[1], u[1]) * binom(qq[2], u[2]));
-                      y[c] += (bn * gk) * (wx[qq[0] - u[0]] * wy[qq[1] - u[1]] * wz[qq[2] - u[2]]);
-                    }
-                  });
+        for (int u = 0; u < R::NU; ++u) Gu[u] = 0.0;
+        static_for<L - LA + 1>([&](auto lc) {
+          constexpr int le = LA + decltype(lc)::value;
+          static_for<ncart(le)>([&](auto ec_) {
+            constexpr int ce = decltype(ec_)::value;
+            constexpr C3 e = cart(le, ce);
+            const double we = w[offT(le) - offT(LA) + ce];
+            static_for<e[0] + 1>([&](auto xc) {
+              constexpr int ux = decltype(xc)::value;
+              static_for<e[1] + 1>([&](auto yc) {
+                constexpr int uy = decltype(yc)::value;
+                static_for<e[2] + 1>([&](auto zc_) {
+                  constexpr int uz = decltype(zc_)::value;
+                  constexpr int k = ux + uy + uz;
+                  if constexpr (k <= LP) {
+                    constexpr int lr = le - k;
+                    constexpr int cr = cidx(e[0] - ux, e[1] - uy, e[2] - uz);
+                    constexpr double f = double(falling(e[0], ux) * falling(e[1], uy) *
+                                                falling(e[2], uz));
+                    Gu[offT(k) + cidx(ux, uy, uz)] +=
+                        (f * we) * vr[R::voff(lr) + cr * (L - lr + 1)];
+                  }
                 });
               });
-            }
-          }
-        // ket transform, sum over the wavefront's pairs, accumulate for the shell
+            });
+          });
+        });
+        // y_c += sum_{u <= c} C(c,u) s^{|u|} W^{c-u} G_u
+        const double s = rho * ig * (0.5 / zc), rz = rho / zc;
+        double wx[LP + 1], wy[LP + 1], wz[LP + 1], sk[R::KU + 1];
+        wx[0] = wy[0] = wz[0] = sk[0] = 1.0;
+#pragma unroll
+        for (int k = 1; k <= LP; ++k) {
+          wx[k] = wx[k - 1] * (rz * PC[0]);
+          wy[k] = wy[k - 1] * (rz * PC[1]);
+          wz[k] = wz[k - 1] * (rz * PC[2]);
+        }
+#pragma unroll
+        for (int k = 1; k <= R::KU; ++k) sk[k] = sk[k - 1] * s;
+        static_for<R::KU + 1>([&](auto kc) {
+          constexpr int k = decltype(kc)::value;
+          static_for<ncart(k)>([&](auto uc) {
+            constexpr int ui = decltype(uc)::value;
+            constexpr C3 u = cart(k, ui);
+            const double gk = sk[k] * Gu[offT(k) + ui];
+            static_for<NCP>([&](auto cc_) {
+              constexpr int c = decltype(cc_)::value;
+              constexpr C3 qq = cart(LP, c);
+              if constexpr (qq[0] >= u[0] && qq[1] >= u[1] && qq[2] >= u[2]) {
+                constexpr double bn =
+                    double(binom(qq[0], u[0]) * binom(qq[1], u[1]) * binom(qq[2], u[2]));
+                y[c] += (bn * gk) * (wx[qq[0] - u[0]] * wy[qq[1] - u[1]] * wz[qq[2] - u[2]]);
+              }
+            });
+          });
+        });
+      };
+      // ket transform of the shell ks, sum over the wavefront's pairs, accumulate
+      auto reduce_shell = [&](int ks, const double *y) {
         double o[NCP];
         if (g.pure) {
           static_for<npure(LP)>([&](auto mc) {
@@ -275,6 +279,71 @@ __global__ void __launch_bounds__(64) k_gam_r(GamArgs g) {
             for (int sh = 32; sh > 0; sh >>= 1) v += __shfl_xor(v, sh, 64);
             if (lane == 0) acc[ks * nout + m] += v;
           }
+        }
+      };
+      if constexpr (GamSwap<LP>::ON) {
+        // primitive pairs outermost, as in the J engine: 1/gamma, P and the pair
+        // exponential once per primitive pair for all the subset's aux shells;
+        // y of each shell accumulates per lane in LDS, over the primitive
+        // triplets in the same order as below
+        double *yb = acc + g.nps * nout;  // [nps][NCP][64]
+        const int nks = sub < g.np ? (g.np - sub + g.nsplit - 1) / g.nsplit : 0;
+        for (int x = 0; x < nks * NCP; ++x) yb[x * 64 + lane] = 0.0;
+        for (int ia = 0; ia < Ka; ++ia)
+          for (int ib = 0; ib < Kb; ++ib) {
+            const double za = ea[ia], zb = eb[ib];
+            const double gg = za + zb, ig = 1.0 / gg;
+            const double P[3] = {(za * A[0] + zb * B[0]) * ig, (za * A[1] + zb * B[1]) * ig,
+                                 (za * A[2] + zb * B[2]) * ig};
+            const double PA[3] = {P[0] - A[0], P[1] - A[1], P[2] - A[2]};
+            const double eab = exp(-za * zb * ig * AB2) * ca[ia] * cb[ib];
+            for (int ks = 0, ip = sub; ip < g.np; ++ks, ip += g.nsplit) {  // uniform
+              const double *rc = g.arec + int64_t(ip) * AREC;
+              const double C[3] = {rc[AR_CX], rc[AR_CY], rc[AR_CZ]};
+              const int Kc = int(rc[AR_K]);
+              const int64_t po = int64_t(rc[AR_PRIM]);
+              double y[NCP];
+#pragma unroll
+              for (int c = 0; c < NCP; ++c) y[c] = yb[(ks * NCP + c) * 64 + lane];
+              double zc = rc[AR_Z0], cz = rc[AR_C0];
+              for (int ic = 0; ic < Kc; ++ic) {
+                if (ic > 0) {
+                  zc = g.aux.exps[po + ic];
+                  cz = g.aux.coefs[po + ic];
+                }
+                triplet(zc, cz, C, gg, ig, P, PA, eab, y);
+              }
+#pragma unroll
+              for (int c = 0; c < NCP; ++c) yb[(ks * NCP + c) * 64 + lane] = y[c];
+            }
+          }
+        for (int ks = 0; ks < nks; ++ks) {
+          double y[NCP];
+#pragma unroll
+          for (int c = 0; c < NCP; ++c) y[c] = yb[(ks * NCP + c) * 64 + lane];
+          reduce_shell(ks, y);
+        }
+      } else {
+        for (int ks = 0, ip = sub; ip < g.np; ++ks, ip += g.nsplit) {  // uniform over the wave
+          const int sP = g.psh[ip];
+          const int Kc = g.aux.nprim[sP];
+          const double *ec = g.aux.exps + g.aux.prim_off[sP], *cc = g.aux.coefs + g.aux.prim_off[sP];
+          const int icn = g.aux.atom[sP];
+          const double C[3] = {g.xyz[3 * icn], g.xyz[3 * icn + 1], g.xyz[3 * icn + 2]};
+          double y[NCP];
+#pragma unroll
+          for (int c = 0; c < NCP; ++c) y[c] = 0.0;
+          for (int ia = 0; ia < Ka; ++ia)
+            for (int ib = 0; ib < Kb; ++ib) {
+              const double za = ea[ia], zb = eb[ib];
+              const double gg = za + zb, ig = 1.0 / gg;
+              const double P[3] = {(za * A[0] + zb * B[0]) * ig, (za * A[1] + zb * B[1]) * ig,
+                                   (za * A[2] + zb * B[2]) * ig};
+              const double PA[3] = {P[0] - A[0], P[1] - A[1], P[2] - A[2]};
+              const double eab = exp(-za * zb * ig * AB2) * ca[ia] * cb[ib];
+              for (int ic = 0; ic < Kc; ++ic) triplet(ec[ic], cc[ic], C, gg, ig, P, PA, eab, y);
+            }
+          reduce_shell(ks, y);
         }
       }
     }

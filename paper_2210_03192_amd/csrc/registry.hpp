@@ -89,7 +89,11 @@ hipError_t launch_gam(const GamArgs &a, int grid, hipStream_t s) {
   using C = Cfg<LP, LA, LB>;
   if constexpr (C::JREG) {
     auto kr = k_gam_r<LP, LA, LB>;
-    const int lds = a.nps * (a.pure ? 2 * LP + 1 : (LP + 1) * (LP + 2) / 2) * 8;
+    int lds = a.nps * (a.pure ? 2 * LP + 1 : (LP + 1) * (LP + 2) / 2) * 8;
+    if constexpr (GamSwap<LP>::ON) {
+      if (a.nps > GamSwap<LP>::NPS) return hipErrorInvalidValue;
+      lds += a.nps * ncart(LP) * 64 * 8;
+    }
     hipLaunchKernelGGL(kr, dim3(grid), dim3(64), lds, s, a);
   } else {
     using E = GamE<LP, LA, LB>;

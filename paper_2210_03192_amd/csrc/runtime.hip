@@ -1645,11 +1645,14 @@ struct GamRegPlan {
   int64_t prange, nrange;
   size_t partial_doubles(int nout) const { return size_t(nrange) * nsplit * nps * nout; }
 };
-GamRegPlan gam_reg_plan(int64_t npair, int np, int nacc, int ncu) {
+GamRegPlan gam_reg_plan(int64_t npair, int np, int nacc, int ncu, int npsmax) {
   GamRegPlan g;
   const int64_t target = int64_t(ncu) * 16;
   const int lo = int((int64_t(np) * nacc + 4095) / 4096);
   g.nsplit = std::max(lo, std::min(std::max(1, np / 8), 64));
+  // at most npsmax aux shells per subset (the LDS accumulators of the register
+  // engine with the primitive pairs outermost)
+  if (npsmax > 0) g.nsplit = std::max(g.nsplit, (np + npsmax - 1) / npsmax);
   g.nps = (np + g.nsplit - 1) / g.nsplit;
   const int64_t rounds = (npair + 63) / 64;
   const int64_t want = std::max<int64_t>(1, std::min<int64_t>(rounds, target / g.nsplit));
@@ -1690,7 +1693,8 @@ size_t gamma_partial_bytes(const df3c_shells *aux, const df3c_shells *orb, int n
         const int64_t npair = la == lb ? no[la] * (no[la] + 1) / 2 : no[la] * no[lb];
         const int nout = aux->pure ? 2 * lp + 1 : (lp + 1) * (lp + 2) / 2;
         const int nacc = (lp + 1) * (lp + 2) / 2;
-        part = std::max(part, gam_reg_plan(npair, int(na[lp]), nacc, ncu).partial_doubles(nout));
+        const GamRegPlan gp = gam_reg_plan(npair, int(na[lp]), nacc, ncu, gam_nps_cap(lp));
+        part = std::max(part, gp.partial_doubles(nout));
       }
   return align256(sizeof(double) * part);
 }
@@ -1733,6 +1737,10 @@ int df3c_coulomb_gamma(const double *xyz, int32_t natom, const df3c_shells *aux,
     pb = carve_pullback(orb, static_cast<char *>(ws) + need - pullback_bytes(orb), p.nao);
   if (launch_plan(dp, p, aux, orb, natom, nullptr, orb->pure ? pb.cmap : nullptr,
                   orb->pure ? pb.poff : nullptr, s) != hipSuccess)
+    return DF3C_E_HIP;
+  // aux-shell records (no d') for the register engine's aux loop
+  if (launch_aux_records(dp.aux_sorted, aux->nshell, aux, xyz, dp.aux_off, nullptr, dp.arec, s,
+                         dp.err) != hipSuccess)
     return DF3C_E_HIP;
   hipLaunchKernelGGL(k_zero_f64, dim3(int(std::min<int64_t>((p.naux + 255) / 256, 4096))),
                      dim3(256), 0, s, gamma, p.naux);
@@ -1796,6 +1804,7 @@ int df3c_coulomb_gamma(const double *xyz, int32_t natom, const df3c_shells *aux,
                                                   size_t(br) * part_stride);
     a.partial = bpartial;
     a.psh = aux_sorted + p.aux_start[lp];
+    a.arec = dp.arec + int64_t(p.aux_start[lp]) * AREC;
     a.np = np;
     for (int la = 0; la <= DF3C_LMAX_ORB && !brc; ++la)
       for (int lb = 0; lb <= la && !brc; ++lb) {
@@ -1812,7 +1821,8 @@ int df3c_coulomb_gamma(const double *xyz, int32_t natom, const df3c_shells *aux,
         const int c = (lp * NLA + la) * NLA + lb;
         // items (range of pairs, subset of the aux shells) on the register
         // engine or the gamma engine; partials added per class in order
-        const GamRegPlan gp = gam_reg_plan(a.npair, np, (lp + 1) * (lp + 2) / 2, ds->ncu);
+        const GamRegPlan gp =
+            gam_reg_plan(a.npair, np, (lp + 1) * (lp + 2) / 2, ds->ncu, gam_nps_cap(lp));
         a.nsplit = gp.nsplit;
         a.nps = gp.nps;
         a.prange = gp.prange;
