@@ -95,6 +95,41 @@ __global__ void __launch_bounds__(64) k_gam_r(GamArgs g) {
     const int64_t r = item / g.nsplit;
     const int sub = int(item - r * g.nsplit);
     for (int x = lane; x < g.nps * nout; x += 64) acc[x] = 0.0;
+    // ket transform of the shell ks, sum over the wavefront's pairs, accumulate
+    auto reduce_shell = [&](int ks, const double *y) {
+      double o[NCP];
+      if (g.pure) {
+        static_for<npure(LP)>([&](auto mc) {
+          constexpr int m = decltype(mc)::value;
+          double v = 0.0;
+          static_for<NCP>([&](auto cc_) {
+            constexpr int c = decltype(cc_)::value;
+            constexpr double t = SH::dense[m * NCP + c];
+            if constexpr (t != 0.0) v += t * y[c];
+          });
+          o[m] = v;
+        });
+      } else {
+#pragma unroll
+        for (int c = 0; c < NCP; ++c) o[c] = y[c];
+      }
+#pragma unroll
+      for (int m = 0; m < NCP; ++m) {
+        if (m < nout) {
+          double v = o[m];
+#pragma unroll
+          for (int sh = 32; sh > 0; sh >>= 1) v += __shfl_xor(v, sh, 64);
+          if (lane == 0) acc[ks * nout + m] += v;
+        }
+      }
+    };
+    // primitive pairs outermost (l_P <= 2): per-lane y of the nks aux shells of
+    // the subset in LDS, summed over all the item's pairs before one transform
+    // and one wavefront sum per shell
+    double *yb = acc + g.nps * nout;  // [nps][NCP][64]
+    const int nks = sub < g.np ? (g.np - sub + g.nsplit - 1) / g.nsplit : 0;
+    if constexpr (GamSwap<LP>::ON)
+      for (int x = 0; x < nks * NCP; ++x) yb[x * 64 + lane] = 0.0;
     const int64_t qend = (r + 1) * g.prange < g.npair ? (r + 1) * g.prange : g.npair;
     for (int64_t q0 = r * g.prange; q0 < qend; q0 += 64) {
       const int64_t q = q0 + lane;
@@ -253,42 +288,9 @@ __global__ void __launch_bounds__(64) k_gam_r(GamArgs g) {
           });
         });
       };
-      // ket transform of the shell ks, sum over the wavefront's pairs, accumulate
-      auto reduce_shell = [&](int ks, const double *y) {
-        double o[NCP];
-        if (g.pure) {
-          static_for<npure(LP)>([&](auto mc) {
-            constexpr int m = decltype(mc)::value;
-            double v = 0.0;
-            static_for<NCP>([&](auto cc_) {
-              constexpr int c = decltype(cc_)::value;
-              constexpr double t = SH::dense[m * NCP + c];
-              if constexpr (t != 0.0) v += t * y[c];
-            });
-            o[m] = v;
-          });
-        } else {
-#pragma unroll
-          for (int c = 0; c < NCP; ++c) o[c] = y[c];
-        }
-#pragma unroll
-        for (int m = 0; m < NCP; ++m) {
-          if (m < nout) {
-            double v = o[m];
-#pragma unroll
-            for (int sh = 32; sh > 0; sh >>= 1) v += __shfl_xor(v, sh, 64);
-            if (lane == 0) acc[ks * nout + m] += v;
-          }
-        }
-      };
       if constexpr (GamSwap<LP>::ON) {
-        // primitive pairs outermost, as in the J engine: 1/gamma, P and the pair
-        // exponential once per primitive pair for all the subset's aux shells;
-        // y of each shell accumulates per lane in LDS, over the primitive
-        // triplets in the same order as below
-        double *yb = acc + g.nps * nout;  // [nps][NCP][64]
-        const int nks = sub < g.np ? (g.np - sub + g.nsplit - 1) / g.nsplit : 0;
-        for (int x = 0; x < nks * NCP; ++x) yb[x * 64 + lane] = 0.0;
+        // as in the J engine: 1/gamma, P and the pair exponential once per
+        // primitive pair for all the subset's aux shells
         for (int ia = 0; ia < Ka; ++ia)
           for (int ib = 0; ib < Kb; ++ib) {
             const double za = ea[ia], zb = eb[ib];
@@ -317,12 +319,6 @@ __global__ void __launch_bounds__(64) k_gam_r(GamArgs g) {
               for (int c = 0; c < NCP; ++c) yb[(ks * NCP + c) * 64 + lane] = y[c];
             }
           }
-        for (int ks = 0; ks < nks; ++ks) {
-          double y[NCP];
-#pragma unroll
-          for (int c = 0; c < NCP; ++c) y[c] = yb[(ks * NCP + c) * 64 + lane];
-          reduce_shell(ks, y);
-        }
       } else {
         for (int ks = 0, ip = sub; ip < g.np; ++ks, ip += g.nsplit) {  // uniform over the wave
           const int sP = g.psh[ip];
@@ -347,6 +343,13 @@ __global__ void __launch_bounds__(64) k_gam_r(GamArgs g) {
         }
       }
     }
+    if constexpr (GamSwap<LP>::ON)
+      for (int ks = 0; ks < nks; ++ks) {
+        double y[NCP];
+#pragma unroll
+        for (int c = 0; c < NCP; ++c) y[c] = yb[(ks * NCP + c) * 64 + lane];
+        reduce_shell(ks, y);
+      }
     double *out = g.partial + item * g.nps * nout;
     for (int x = lane; x < g.nps * nout; x += 64) out[x] = acc[x];
   }
