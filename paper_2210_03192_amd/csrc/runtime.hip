@@ -1661,16 +1661,21 @@ GamRegPlan gam_reg_plan(int64_t npair, int np, int nacc, int ncu, int npsmax) {
   return g;
 }
 
-// register engine: gamma[aux function] += sum over the pair ranges, in order
+// register engine: gamma[aux function] += sum over the pair ranges, in order.
+// Threads follow the partials' own layout (f = (subset, shell of the subset,
+// component) within a range), so every range's reads are contiguous.
 __global__ void k_gam_reduce_r(const double *partial, int32_t np, int32_t nsplit, int32_t nps,
                                int64_t nrange, int32_t nout, const int32_t *psh,
                                const int64_t *aux_off, double *gamma, const int *err) {
   if (*err) return;
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < np * nout; i += gridDim.x * blockDim.x) {
-    const int ip = i / nout, m = i - ip * nout;
-    const int sub = ip % nsplit, k = ip / nsplit;
+  const int nf = nsplit * nps * nout;  // doubles of one range's partial
+  for (int f = blockIdx.x * blockDim.x + threadIdx.x; f < nf; f += gridDim.x * blockDim.x) {
+    const int t = f / nout, m = f - t * nout;
+    const int sub = t / nps, k = t - sub * nps;
+    const int ip = k * nsplit + sub;
+    if (ip >= np) continue;
     double v = 0.0;
-    for (int64_t r = 0; r < nrange; ++r) v += partial[((r * nsplit + sub) * nps + k) * nout + m];
+    for (int64_t r = 0; r < nrange; ++r) v += partial[r * nf + f];
     gamma[aux_off[psh[ip]] + m] += v;
   }
 }
@@ -1832,7 +1837,7 @@ int df3c_coulomb_gamma(const double *xyz, int32_t natom, const df3c_shells *aux,
           brc = DF3C_E_HIP;
           break;
         }
-        const int nred = np * nout;
+        const int nred = gp.nsplit * gp.nps * nout;
         hipLaunchKernelGGL(k_gam_reduce_r, dim3((nred + 255) / 256), dim3(256), 0, bs, bpartial,
                            np, gp.nsplit, gp.nps, gp.nrange, nout, a.psh, aux_off, gamma, dp.err);
       }
