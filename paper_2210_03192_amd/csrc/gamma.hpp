@@ -76,11 +76,14 @@ __device__ __forceinline__ void gam_pair(const GamArgs &g, int64_t q, int &sa, i
 // ---------------------------------------------------------------------------
 // Register engine (classes of the register J engine): one lane per shell pair.
 // A workgroup is one wavefront and one item (pair range, aux subset).  Per
-// round of 64 pairs each lane transposes the HRR onto its D~ once (w_e); per
-// aux shell of the subset it forms y over the pair's primitive triplets, the
-// ket transform, and the wavefront sums the 64 pairs by a fixed butterfly.
-// Lane 0 accumulates the sums per aux shell in LDS, and the item writes them
-// as its partial; a reduction adds the ranges in order.
+// round of 64 pairs each lane transposes the HRR onto its D~ once (w_e) and
+// forms y of every aux shell of the subset over the pair's primitive triplets.
+// l_P <= 2: primitive pairs outermost, y of each shell kept per lane in LDS
+// over all rounds of the item, then one ket transform and one fixed butterfly
+// over the wavefront per shell.  l_P >= 3: aux shells outermost, and each
+// round's y is transformed and summed over the wavefront at once.  Lane 0
+// accumulates the sums per aux shell in LDS, and the item writes them as its
+// partial; a reduction adds the ranges in order.
 // ---------------------------------------------------------------------------
 template <int LP, int LA, int LB>
 __global__ void __launch_bounds__(64) k_gam_r(GamArgs g) {
